@@ -1,0 +1,254 @@
+"""Seeded synthetic scenario-tree problems shaped like the paper's workloads.
+
+This module only draws data: trees, conditional probabilities, dynamics,
+costs, bounds, risk parameters and initial states.  It holds none of the
+method's arithmetic (no projections, no factorisations, no operator L), so
+both the FP64 oracle and the HIP path can take their inputs from it.
+
+A problem is a plain dict of NumPy arrays (the "problem description"):
+
+    parent   int32[n]      parent[0] = -1, nodes numbered stage by stage
+                           (breadth first), so children of a node are
+                           contiguous and every leaf sits at stage N
+    prob     float64[n]    conditional probability of a node given its
+                           parent (siblings sum to 1), prob[0] = 1
+    nx, nu   int           state / input sizes
+    A        float64[n,nx,nx]  x^i = A^i x^anc(i) + B^i u^anc(i) + c^i
+    B        float64[n,nx,nu]  (entry 0 unused)
+    c        float64[n,nx] or None
+    Q, R     float64[nx], float64[nu]   diagonal of the edge stage cost
+    QN       float64[nx]   diagonal of the leaf cost
+    x_lo, x_hi, u_lo, u_hi, xN_lo, xN_hi   box bounds
+    x_ball, xN_ball        Euclidean-ball radius on x (<= 0: none)
+    gamma    float64[n_nl] AV@R parameter per non-leaf node
+    x0       float64[nx]   initial state
+
+The problem formulation is the scenario-tree RAOCP of the paper's problem
+statement section (dynamics, constraints, quadratic costs, AV@R risk).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# trees
+# ----------------------------------------------------------------------------
+
+
+def tree_from_child_counts(counts_by_stage):
+    """Breadth-first parent array from per-node child counts.
+
+    ``counts_by_stage[t]`` lists the number of children of each node of stage
+    ``t`` in node order.  Returns (parent int32[n], stage int32[n]).
+    """
+    parent = [-1]
+    stage = [0]
+    frontier = [0]
+    for t, counts in enumerate(counts_by_stage):
+        if len(counts) != len(frontier):
+            raise ValueError("stage %d: %d counts for %d nodes" % (t, len(counts), len(frontier)))
+        nxt = []
+        for node, k in zip(frontier, counts):
+            if k < 1:
+                raise ValueError("every non-leaf node needs at least one child")
+            for _ in range(int(k)):
+                parent.append(node)
+                stage.append(t + 1)
+                nxt.append(len(parent) - 1)
+        frontier = nxt
+    return np.asarray(parent, dtype=np.int32), np.asarray(stage, dtype=np.int32)
+
+
+def tree_from_branching(branching):
+    """Uniform stage branching: ``branching[t]`` children for every node of stage t."""
+    counts = []
+    width = 1
+    for b in branching:
+        counts.append([int(b)] * width)
+        width *= int(b)
+    return tree_from_child_counts(counts)
+
+
+def children_lists(parent):
+    n = len(parent)
+    ch = [[] for _ in range(n)]
+    for j in range(1, n):
+        ch[int(parent[j])].append(j)
+    return ch
+
+
+def draw_cond_probs(parent, rng, kind):
+    """Conditional child probabilities, drawn stage-major (node order)."""
+    n = len(parent)
+    prob = np.zeros(n)
+    prob[0] = 1.0
+    for i, kids in enumerate(children_lists(parent)):
+        if not kids:
+            continue
+        k = len(kids)
+        if kind == "uniform" or k == 1:
+            p = np.full(k, 1.0 / k)
+        elif kind == "dirichlet":
+            p = rng.dirichlet(np.ones(k))
+            p = np.maximum(p, 1e-6)
+            p /= p.sum()
+        else:
+            raise ValueError(kind)
+        prob[kids] = p
+    return prob
+
+
+# ----------------------------------------------------------------------------
+# data
+# ----------------------------------------------------------------------------
+
+
+def _stable_gaussian(rng, nx, radius=0.95):
+    while True:
+        G = rng.standard_normal((nx, nx))
+        rho = np.max(np.abs(np.linalg.eigvals(G)))
+        if rho >= 1e-3:
+            return radius * G / rho
+
+
+def _guard_x0(x0, parent, A, x_hi, x_ball, xN_hi, xN_ball, n_nl, margin=0.9):
+    """Halve x0 until the zero-input rollout keeps a margin inside every box/ball.
+
+    This keeps the drawn instance strictly feasible (Slater), so the conic
+    problem has a solution.  Pure simulation of the dynamics, no solver.
+    """
+    n = len(parent)
+    for _ in range(80):
+        xs = np.zeros((n, x0.size))
+        xs[0] = x0
+        ok = True
+        for j in range(n):
+            if j > 0:
+                xs[j] = A[j] @ xs[int(parent[j])]
+            hi = x_hi if j < n_nl else xN_hi
+            ball = x_ball if j < n_nl else xN_ball
+            if np.any(np.abs(xs[j]) > margin * hi):
+                ok = False
+                break
+            if ball > 0 and np.linalg.norm(xs[j]) > margin * ball:
+                ok = False
+                break
+        if ok:
+            return x0
+        x0 = 0.5 * x0
+    raise RuntimeError("could not find a strictly feasible x0")
+
+
+def make_problem(parent, nx, nu, rng, *, prob_kind="uniform", gamma=0.95,
+                 x_box=5.0, u_box=1.0, x_ball=0.0, q=1.0, r=0.1, qn=1.0,
+                 affine=False, x0_range=2.0, name="custom"):
+    """Draw a full problem on the given tree (draw order: probabilities, then
+    A^i and B^i for i = 1..n-1, then x0, then the optional affine terms)."""
+    parent = np.asarray(parent, dtype=np.int32)
+    n = len(parent)
+    n_nl = int(np.sum(np.bincount(parent[1:], minlength=n) > 0))
+    prob = draw_cond_probs(parent, rng, prob_kind)
+    A = np.zeros((n, nx, nx))
+    B = np.zeros((n, nx, nu))
+    for j in range(1, n):
+        A[j] = _stable_gaussian(rng, nx)
+        B[j] = rng.standard_normal((nx, nu))
+    x0 = rng.uniform(-x0_range, x0_range, size=nx)
+    c = None
+    if affine:
+        c = np.zeros((n, nx))
+        c[1:] = 0.05 * rng.standard_normal((n - 1, nx))
+    x_hi = np.full(nx, float(x_box))
+    u_hi = np.full(nu, float(u_box))
+    x0 = _guard_x0(x0, parent, A, x_hi, x_ball, x_hi, x_ball, n_nl)
+    if np.isscalar(gamma):
+        gamma = np.full(n_nl, float(gamma))
+    return dict(
+        name=name, parent=parent, prob=prob, nx=int(nx), nu=int(nu), A=A, B=B, c=c,
+        Q=np.full(nx, float(q)), R=np.full(nu, float(r)), QN=np.full(nx, float(qn)),
+        x_lo=-x_hi.copy(), x_hi=x_hi.copy(), u_lo=-u_hi.copy(), u_hi=u_hi.copy(),
+        xN_lo=-x_hi.copy(), xN_hi=x_hi.copy(),
+        x_ball=float(x_ball), xN_ball=float(x_ball),
+        gamma=np.asarray(gamma, dtype=np.float64), x0=x0,
+    )
+
+
+def seeded_rng(config_id, instance_id=0):
+    return np.random.default_rng(np.random.SeedSequence([int(config_id), int(instance_id)]))
+
+
+# ----------------------------------------------------------------------------
+# the named workloads
+# ----------------------------------------------------------------------------
+
+CONFIGS = {
+    0: "tiny: N=3, binary (15 nodes), nx=2, nu=1, box, AV@R_0.95, FP64, eps 1e-6",
+    1: "medium: N=10, branching [3,3,3,1x7] (229 nodes), nx=20, nu=10, box+ball, AV@R_0.9, Dirichlet, FP64, eps 1e-6",
+    2: "large: N=15, branching [2x10,1x5] (7167 nodes), nx=50, nu=25, box+ball, AV@R_0.95, Dirichlet, mixed, eps 1e-4",
+    3: "batched: 256 uneven trees, nx 4..32, nu=nx/2, N 5..20, branching 2..4 for 2..5 stages",
+}
+
+
+def config_problem(config_id, instance_id=0):
+    """The single-tree workloads 0, 1, 2."""
+    rng = seeded_rng(config_id, instance_id)
+    if config_id == 0:
+        parent, _ = tree_from_branching([2, 2, 2])
+        return make_problem(parent, 2, 1, rng, prob_kind="uniform", gamma=0.95,
+                            name="cfg0_N3_b2_nx2_nu1")
+    if config_id == 1:
+        parent, _ = tree_from_branching([3, 3, 3] + [1] * 7)
+        return make_problem(parent, 20, 10, rng, prob_kind="dirichlet", gamma=0.9,
+                            x_ball=10.0, name="cfg1_N10_b333_nx20_nu10")
+    if config_id == 2:
+        parent, _ = tree_from_branching([2] * 10 + [1] * 5)
+        return make_problem(parent, 50, 25, rng, prob_kind="dirichlet", gamma=0.95,
+                            x_ball=10.0, name="cfg2_N15_b2x10_nx50_nu25")
+    raise ValueError("config %r is not a single-tree workload" % (config_id,))
+
+
+def batch_problem(k, seed=3):
+    """Problem k of the batched workload: nx ~ U{4..32}, nu = nx//2, N ~ U{5..20},
+    one branching factor b ~ U{2,3,4} for the first n_b ~ U{2..5} stages, then 1;
+    Dirichlet probabilities, box + ball, AV@R_0.9."""
+    rng = seeded_rng(seed, k)
+    nx = int(rng.integers(4, 33))
+    nu = max(1, nx // 2)
+    N = int(rng.integers(5, 21))
+    b = int(rng.integers(2, 5))
+    nb = min(int(rng.integers(2, 6)), N)
+    parent, _ = tree_from_branching([b] * nb + [1] * (N - nb))
+    return make_problem(parent, nx, nu, rng, prob_kind="dirichlet", gamma=0.9,
+                        x_ball=10.0, name="batch%d_nx%d_N%d_b%d^%d" % (k, nx, N, b, nb))
+
+
+def random_ragged_problem(seed, N=4, nx=3, nu=2, max_children=3, ball=True,
+                          affine=False, gamma=None):
+    """Irregular tree (each non-leaf has 1..max_children children), for tests."""
+    rng = np.random.default_rng(np.random.SeedSequence([977, int(seed)]))
+    counts = []
+    width = 1
+    for _ in range(N):
+        cs = [int(v) for v in rng.integers(1, max_children + 1, size=width)]
+        counts.append(cs)
+        width = sum(cs)
+    parent, _ = tree_from_child_counts(counts)
+    n = len(parent)
+    n_nl = n - width
+    if gamma is None:
+        gamma = rng.uniform(0.05, 1.0, size=n_nl)
+    return make_problem(parent, nx, nu, rng, prob_kind="dirichlet", gamma=gamma,
+                        x_ball=(6.0 if ball else 0.0), affine=affine,
+                        name="ragged%d" % seed)
+
+
+def problem_sizes(p):
+    """Counts used for reporting: nodes, non-leaf nodes, leaves, stages."""
+    parent = p["parent"]
+    n = len(parent)
+    n_ch = np.bincount(parent[1:], minlength=n)
+    n_nl = int(np.sum(n_ch > 0))
+    stage = np.zeros(n, dtype=np.int64)
+    for j in range(1, n):
+        stage[j] = stage[parent[j]] + 1
+    return dict(n=n, n_nl=n_nl, n_leaf=n - n_nl, N=int(stage.max()), max_children=int(n_ch.max()))
