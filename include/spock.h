@@ -1,0 +1,212 @@
+/*
+ * spock.h -- C ABI of the MI355X (gfx950) library for the Chambolle-Pock (CP)
+ * step of SPOCK on scenario trees (arXiv:2505.12078).
+ *
+ * The library solves the risk-averse optimal control problem (RAOCP) of the
+ * paper's problem-statement section (Sec. 3): linear dynamics on a scenario
+ * tree, box and Euclidean-ball constraints, quadratic stage and terminal
+ * costs, nested AV@R risk.  It iterates the CP operator T of Sec. 4.1 on the
+ * conic reformulation of Sec. 4.2-4.5:
+ *   z+   = prox_{alpha f}(z - alpha L* eta)       (Alg. 2 sweep + S2 + s0 shift)
+ *   eta+ = prox_{alpha g*}(eta + alpha L(2z+ - z)) (S3 cone projections, Moreau)
+ * with the offline factorisation of Alg. 1 done once per problem in FP64.
+ *
+ * Conventions for every entry point:
+ *  - Every function returns int32_t status: SPOCK_OK (0) or a negative code.
+ *    The message of the last failure on the calling thread is returned by
+ *    spock_last_error().  No C++ exception crosses this boundary.
+ *  - All pointers named in a description or argument are HOST pointers owned
+ *    by the caller, unless the name says "device".  The library copies what it
+ *    needs before returning; it keeps no pointer to caller memory.
+ *  - Arrays are dense, row-major, float64, in node order.  Nodes are numbered
+ *    stage by stage (breadth first): parent[j] < j, children of a node are
+ *    consecutive, all non-leaf nodes precede all leaves, every leaf sits at
+ *    the last stage N.
+ *  - One problem handle may be used by one host thread at a time.
+ *
+ * Canonical iterate layout (scaled variables, the space the CP method runs
+ * in; used by spock_get_iterate, spock_set_iterate and the operator hooks):
+ *   z   = [ s0 | x (n*nx) | u (n_nl*nu) | y (per non-leaf i: 2*n_ch(i)+1)
+ *         | tau (nodes 1..n-1) | s (nodes 1..n-1) ]
+ *   eta = [ eta_y (as y) | eta_s (n_nl) | eta_c (n_nl*nc) | eta_soc ((n-1)*(nx+nu+2))
+ *         | eta_cN (n_leaf*ncN) | eta_socN (n_leaf*(nx+2)) ]
+ * with nc = nx+nu (+nx with a ball) and ncN = nx (+nx with a ball); this is
+ * the operator L of Sec. 4.4 block by block.
+ */
+#ifndef SPOCK_MI355X_H
+#define SPOCK_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SPOCK_OK 0
+#define SPOCK_E_INVALID (-1)         /* malformed tree, data or argument */
+#define SPOCK_E_INFEASIBLE_X0 (-2)   /* x0 outside the root constraint set */
+#define SPOCK_E_NOT_CONVERGED (-3)   /* max_iters reached; info is filled */
+#define SPOCK_E_DIVERGED (-4)        /* non-finite residual */
+#define SPOCK_E_HIP (-5)             /* HIP runtime failure or device wait timeout */
+#define SPOCK_E_CAPACITY (-6)        /* a request larger than the whole budget */
+#define SPOCK_E_NOMEM (-7)           /* workspace too small / allocation failed */
+
+/* precision of the iteration */
+#define SPOCK_FP64 0   /* every step in float64 */
+#define SPOCK_MIXED 1  /* float32 steps; float64 final check and refinement */
+#define SPOCK_FP32 2   /* float32 steps only (hooks and benchmarks) */
+
+/*
+ * Problem data (Sec. 3.1-3.4).  x^j = A^j x^i + B^j u^i + c^j for j with
+ * parent i; stage cost of the edge into j: x^iT Q x^i + u^iT R u^i; leaf
+ * cost x^jT QN x^j; constraints lo <= (x, u) <= hi and ||x|| <= x_ball at
+ * non-leaf nodes, xN_lo <= x <= xN_hi and ||x|| <= xN_ball at leaves;
+ * AV@R_gamma[i] over the children of non-leaf node i with the conditional
+ * probabilities cond_prob (AV@R_1 = expectation, AV@R_0 = max).
+ */
+typedef struct spock_problem_desc {
+    int32_t n_nodes;          /* n >= 2 */
+    const int32_t* parent;    /* [n], parent[0] = -1 */
+    const double* cond_prob;  /* [n], > 0, children of each node sum to 1 */
+    int32_t nx, nu;           /* >= 1 */
+    const double* A;          /* [n][nx][nx]; entry 0 ignored */
+    const double* B;          /* [n][nx][nu]; entry 0 ignored */
+    const double* c;          /* [n][nx] or NULL (= 0) */
+    const double* Q_diag;     /* [nx] > 0, shared by all edges */
+    const double* R_diag;     /* [nu] > 0 */
+    const double* QN_diag;    /* [nx] > 0, shared by all leaves */
+    const double* x_lo;       /* [nx], non-leaf state box (may be +-inf) */
+    const double* x_hi;
+    const double* u_lo;       /* [nu] */
+    const double* u_hi;
+    const double* xN_lo;      /* [nx], leaf state box */
+    const double* xN_hi;
+    double x_ball;            /* radius at non-leaf nodes; <= 0: no ball */
+    double xN_ball;           /* radius at leaves; <= 0: no ball */
+    const double* gamma;      /* [n_nl] in [0, 1] */
+} spock_problem_desc;
+
+typedef struct spock_settings {
+    double alpha;          /* CP step; 0 = automatic 0.99/||L|| (exact block norm) */
+    double eps;            /* tolerance on rel_res (default 1e-6) */
+    int64_t max_iters;     /* CP steps (default 100000) */
+    int32_t precision;     /* SPOCK_FP64 / SPOCK_MIXED / SPOCK_FP32 */
+    int32_t precondition;  /* 1 = diagonal scaling of Sec. 5.4 (default), 0 = off */
+    int32_t check_every;   /* steps between residual checks, even (default 20) */
+    int32_t use_graph;     /* 1 = replay check_every steps as one hipGraph (default) */
+} spock_settings;
+
+/*
+ * Per-solve report.  rel_res = max(|xi1|_inf, |xi2|_inf) / max(1, |xi1_ref|_inf,
+ * |xi2_ref|_inf) with the residuals xi1, xi2 of Sec. 5.3 and the reference
+ * residuals of the first CP step from zero (kept with the handle).
+ */
+typedef struct spock_info {
+    int64_t iters;          /* CP steps taken in this solve */
+    int64_t iters_fp32;     /* of which in float32 */
+    double rel_res, xi1_inf, xi2_inf;
+    double s0;              /* objective value s^0 (= V* at convergence) */
+    double t_solve_s;       /* wall time of the solve call */
+    int32_t status;         /* the same code the call returned */
+    int32_t precision_used; /* precision of the final accepted step */
+    int32_t refined;        /* 1 if float64 steps had to follow float32 ones */
+} spock_info;
+
+typedef struct spock_sizes {
+    int64_t nz, neta;       /* canonical iterate lengths */
+    int32_t n, n_nl, n_leaf, N, nx, nu, nc, ncN, max_children;
+    double alpha, L_norm;
+    size_t device_bytes;    /* device memory held by the handle */
+} spock_sizes;
+
+typedef struct spock_problem spock_problem;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* spock_last_error(void);
+
+/* Defaults listed in spock_settings. */
+int32_t spock_default_settings(spock_settings* out);
+
+/* Device bytes spock_problem_create would need for this problem (pure; no
+ * device access).  Used for admission by footprint. */
+int32_t spock_problem_footprint(const spock_problem_desc* desc, const spock_settings* s,
+                                size_t* device_bytes);
+
+/*
+ * Validate the data, apply the scaling of Sec. 5.4, run Alg. 1 (offline S1
+ * factorisation, Sec. 5.1) in float64 on the host, compute the exact ||L||
+ * (Sec. 4.4) and upload everything to the current HIP device.
+ * device_workspace: device pointer of >= spock_problem_footprint bytes that
+ * the caller keeps alive until destroy, or NULL to let the library allocate.
+ * stream: hipStream_t to launch on, or NULL for the default stream.
+ * Errors: SPOCK_E_INVALID, SPOCK_E_NOMEM, SPOCK_E_HIP.
+ */
+int32_t spock_problem_create(const spock_problem_desc* desc, const spock_settings* s,
+                             void* device_workspace, size_t workspace_bytes, void* stream,
+                             spock_problem** out);
+
+int32_t spock_problem_destroy(spock_problem* p);
+
+int32_t spock_problem_sizes(const spock_problem* p, spock_sizes* out);
+
+/* Replace the settings used by later solves (alpha changes need a new handle). */
+int32_t spock_set_settings(spock_problem* p, const spock_settings* s);
+
+/*
+ * Solve from initial state x0 ([nx], unscaled).  warm_start = 0 starts from
+ * z = 0, eta = 0; 1 starts from the iterate left by the previous solve (or
+ * spock_set_iterate).  Stops when rel_res <= eps (checked every check_every
+ * steps) or after max_iters steps.
+ * Errors: SPOCK_E_INFEASIBLE_X0 (x0 outside the root box/ball),
+ * SPOCK_E_NOT_CONVERGED, SPOCK_E_DIVERGED, SPOCK_E_HIP.  info may be NULL.
+ */
+int32_t spock_solve(spock_problem* p, const double* x0, int32_t warm_start, spock_info* info);
+
+/* Unscaled solution of the last solve: x [n][nx], u [n_nl][nu], s0 (each may be NULL). */
+int32_t spock_get_solution(const spock_problem* p, double* x, double* u, double* s0);
+
+/* Current iterate (float64 copy) in the canonical layout, scaled space. */
+int32_t spock_get_iterate(const spock_problem* p, double* z, double* eta);
+int32_t spock_set_iterate(spock_problem* p, const double* z, const double* eta);
+
+/* Set the initial state used by the operator hooks below ([nx], unscaled). */
+int32_t spock_set_x0(spock_problem* p, const double* x0);
+
+/*
+ * Operator hooks on caller iterates (canonical layout, scaled space, host
+ * arrays).  precision selects the float64 or float32 kernels.
+ *  spock_apply_T: (z_out, eta_out) = T(z, eta) (Sec. 4.1); with eta = 0 the z
+ *    part is prox_{alpha f}(z): the S1 projection of Alg. 2 on (x, u), the S2
+ *    projection on (y, tau, s) and s0 - alpha.  xi (nullable, [2]) receives
+ *    |xi1|_inf and |xi2|_inf of this step (Sec. 5.3).
+ *  spock_apply_L: eta_out = L z (Sec. 4.4).
+ *  spock_apply_Lt: z_out = L* eta.
+ *  spock_prox_gconj: eta_out = w - alpha proj_S3(w / alpha) (Moreau).
+ */
+int32_t spock_apply_T(spock_problem* p, const double* z, const double* eta, double* z_out,
+                      double* eta_out, int32_t precision, double* xi);
+int32_t spock_apply_L(spock_problem* p, const double* z, double* eta_out, int32_t precision);
+int32_t spock_apply_Lt(spock_problem* p, const double* eta, double* z_out, int32_t precision);
+int32_t spock_prox_gconj(spock_problem* p, const double* w, double* eta_out, int32_t precision);
+
+/*
+ * Timing hook: run `steps` CP steps from the current device iterate in the
+ * given precision (no residual checks, no readback) and report the mean
+ * device duration of each kernel, measured with HIP events on the handle's
+ * stream around every launch.  ms_backward / ms_forward may be NULL.
+ */
+int32_t spock_time_steps(spock_problem* p, int32_t precision, int32_t steps, double* ms_total,
+                         double* ms_backward, double* ms_forward);
+
+/* Bytes one CP step must move at minimum (factor matrices + iterates) in the
+ * given precision, counted as in the design notes; for roofline reporting. */
+int32_t spock_step_bytes(const spock_problem* p, int32_t precision, double* bytes_backward,
+                         double* bytes_forward);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPOCK_MI355X_H */

@@ -1,0 +1,1316 @@
+// Host side of the SPOCK CP-step library: validation, the diagonal scaling of
+// Sec. 5.4, the offline factorisation of Alg. 1 (float64), the exact operator
+// norm of L (Sec. 4.4), the device memory plan, the solve loop and the C ABI
+// declared in include/spock.h.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/spock.h"
+#include "spock_dev.h"
+
+namespace spk {
+template <typename real>
+hipError_t launch_step(const ProbDev<real>*, const int2*, int, int, int, int, hipStream_t);
+template <typename real>
+hipError_t launch_backward(const ProbDev<real>*, const int2*, int, int, int, int, hipStream_t);
+template <typename real>
+hipError_t launch_forward(const ProbDev<real>*, const int2*, int, int, int, int, hipStream_t);
+template <typename real>
+hipError_t launch_apply_L(const ProbDev<real>*, int, const real*, real*, hipStream_t);
+template <typename real>
+hipError_t launch_apply_Lt(const ProbDev<real>*, int, const real*, real*, hipStream_t);
+template <typename real>
+hipError_t launch_prox_gconj(const ProbDev<real>*, int, const real*, real*, hipStream_t);
+template <typename D, typename S>
+hipError_t launch_convert(D*, const S*, long long, hipStream_t);
+template <typename T>
+hipError_t launch_fill(T*, T, long long, hipStream_t);
+}  // namespace spk
+
+using spk::ProbDev;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static int32_t fail(int32_t code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(...)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (__VA_ARGS__);                                                          \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(SPOCK_E_HIP, std::string(#__VA_ARGS__ ": ") + hipGetErrorString(e_));    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// small dense float64 kernels for the offline factorisation (row-major)
+// ---------------------------------------------------------------------------
+
+// C (M x N) = A (M x K) * B (K x N)  [+ C if acc]
+static void mm(int M, int N, int K, const double* A, const double* B, double* C, bool acc) {
+    if (!acc) std::fill(C, C + (size_t)M * N, 0.0);
+    for (int i = 0; i < M; ++i) {
+        double* c = C + (size_t)i * N;
+        for (int k = 0; k < K; ++k) {
+            const double a = A[(size_t)i * K + k];
+            const double* b = B + (size_t)k * N;
+            for (int j = 0; j < N; ++j) c[j] += a * b[j];
+        }
+    }
+}
+
+// C (M x N) += A^T * B with A (K x M), B (K x N)
+static void mtm_acc(int M, int N, int K, const double* A, const double* B, double* C) {
+    for (int k = 0; k < K; ++k) {
+        const double* a = A + (size_t)k * M;
+        const double* b = B + (size_t)k * N;
+        for (int i = 0; i < M; ++i) {
+            const double ai = a[i];
+            double* c = C + (size_t)i * N;
+            for (int j = 0; j < N; ++j) c[j] += ai * b[j];
+        }
+    }
+}
+
+// In-place Cholesky (lower) of an SPD matrix; false if not positive definite.
+static bool cholesky(int n, double* A) {
+    for (int j = 0; j < n; ++j) {
+        double s = A[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) s -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+        if (!(s > 0)) return false;
+        const double l = std::sqrt(s);
+        A[(size_t)j * n + j] = l;
+        for (int i = j + 1; i < n; ++i) {
+            double t = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) t -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+            A[(size_t)i * n + j] = t / l;
+        }
+        for (int k = j + 1; k < n; ++k) A[(size_t)j * n + k] = 0.0;
+    }
+    return true;
+}
+
+// inverse of L L^T from the Cholesky factor L
+static void chol_inverse(int n, const double* L, double* inv) {
+    std::vector<double> Li((size_t)n * n, 0.0);  // L^-1 (lower)
+    for (int j = 0; j < n; ++j) {
+        Li[(size_t)j * n + j] = 1.0 / L[(size_t)j * n + j];
+        for (int i = j + 1; i < n; ++i) {
+            double s = 0;
+            for (int k = j; k < i; ++k) s -= L[(size_t)i * n + k] * Li[(size_t)k * n + j];
+            Li[(size_t)i * n + j] = s / L[(size_t)i * n + i];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = 0;
+            for (int k = i; k < n; ++k) s += Li[(size_t)k * n + i] * Li[(size_t)k * n + j];
+            inv[(size_t)i * n + j] = s;
+            inv[(size_t)j * n + i] = s;
+        }
+}
+
+template <typename F>
+static void parallel_for(int n, F f) {
+    unsigned hw = std::thread::hardware_concurrency();
+    int nt = (int)std::min<unsigned>(hw ? hw : 1, 32);
+    if (n < 4 || nt <= 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    nt = std::min(nt, n);
+    std::atomic<int> next(0);
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&] {
+            for (int i; (i = next.fetch_add(1)) < n;) f(i);
+        });
+    for (auto& x : th) x.join();
+}
+
+// ---------------------------------------------------------------------------
+// the handle
+// ---------------------------------------------------------------------------
+
+template <typename real>
+struct DevSet {
+    ProbDev<real> h;           // host mirror of the descriptor
+    ProbDev<real>* d = nullptr;  // the descriptor in device memory
+    int par = 0;               // which copy holds the current iterate
+    int lds_bytes = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // check_every steps from parity 0 / 1
+    int graph_steps = 0;
+};
+
+struct spock_problem {
+    // sizes
+    int n = 0, n_nl = 0, n_leaf = 0, N = 0, nx = 0, nu = 0, m = 0, nc = 0, ncN = 0, max_ch = 0;
+    int has_ball = 0, has_ballN = 0, affine = 0;
+    long long ny = 0, nz = 0, neta = 0;
+    long long z_x, z_u, z_y, z_tau, z_s, e_y, e_s, e_c, e_soc, e_cN, e_socN;
+    long long M_stride = 0, KR_stride = 0;
+    std::vector<int> parent, first_child, n_ch, y_off;
+    // scaled problem data
+    std::vector<double> Sx, Su, SxN;
+    std::vector<double> qh, rh, qnh, gx, gu, gb, gxN, gbN, lo, hi, loN, hiN, prob, gamma;
+    double ball_r = 0, ballN_r = 0, con_scale = 1, con_scaleN = 1;
+    double Lnorm = 0, alpha = 0;
+    // unscaled root constraint for the x0 check
+    std::vector<double> x_lo, x_hi;
+    double x_ball = 0;
+    std::vector<double> x0s;   // scaled x0 currently on the device
+    spock_settings set{};
+    // device
+    void* base = nullptr;
+    bool owns = false;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    int* d_tree = nullptr;
+    int* d_cnt = nullptr;
+    int* d_flag = nullptr;
+    int2* d_tasks = nullptr;
+    unsigned long long* d_res = nullptr;
+    int* d_err = nullptr;
+    double* d_stash_z = nullptr;
+    double* d_stash_e = nullptr;
+    DevSet<double> s64;
+    DevSet<float> s32;
+    int cur = SPOCK_FP64;      // precision holding the current iterate
+    unsigned long long* h_res = nullptr;  // pinned readback: res[2], err
+    bool have_ref = false;
+    double xi_ref[2] = {0, 0};
+    bool solved = false;
+};
+
+template <typename real>
+static DevSet<real>& set_of(spock_problem* p);
+template <>
+DevSet<double>& set_of<double>(spock_problem* p) { return p->s64; }
+template <>
+DevSet<float>& set_of<float>(spock_problem* p) { return p->s32; }
+
+// ---------------------------------------------------------------------------
+// memory plan: one arena, 256-byte aligned sub-buffers
+// ---------------------------------------------------------------------------
+
+struct Arena {
+    char* base;
+    size_t off = 0;
+    explicit Arena(void* b) : base((char*)b) {}
+    template <typename T>
+    T* take(long long count) {
+        off = (off + 255) & ~(size_t)255;
+        T* r = base ? (T*)(base + off) : nullptr;
+        off += (size_t)std::max<long long>(count, 1) * sizeof(T);
+        return r;
+    }
+};
+
+template <typename real>
+static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
+    ProbDev<real>& h = s.h;
+    const int n = p->n, nl = p->n_nl, nx = p->nx, nu = p->nu, m = p->m;
+    h.M = a.take<real>((long long)n * p->M_stride);
+    h.KR = a.take<real>((long long)nl * p->KR_stride);
+    h.c = p->affine ? a.take<real>((long long)n * nx) : nullptr;
+    h.Pc = p->affine ? a.take<real>((long long)n * nx) : nullptr;
+    h.qh = a.take<real>(nx);
+    h.rh = a.take<real>(nu);
+    h.qnh = a.take<real>(nx);
+    h.gx = a.take<real>(nx);
+    h.gu = a.take<real>(nu);
+    h.gb = a.take<real>(nx);
+    h.gxN = a.take<real>(nx);
+    h.gbN = a.take<real>(nx);
+    h.lo = a.take<real>(m);
+    h.hi = a.take<real>(m);
+    h.loN = a.take<real>(nx);
+    h.hiN = a.take<real>(nx);
+    h.prob = a.take<real>(n);
+    h.gamma = a.take<real>(nl);
+    h.x0 = a.take<real>(nx);
+    for (int k = 0; k < 2; ++k) {
+        h.z[k] = a.take<real>(p->nz);
+        h.eta[k] = a.take<real>(p->neta);
+    }
+    h.d = a.take<real>((long long)nl * nu);
+    h.e = a.take<real>((long long)n * m);
+    s.d = a.take<ProbDev<real>>(1);
+}
+
+static void carve(Arena& a, spock_problem* p) {
+    p->d_tree = a.take<int>(4LL * p->n + 4);
+    p->d_cnt = a.take<int>(p->n);
+    p->d_flag = a.take<int>(p->n);
+    p->d_tasks = a.take<int2>(p->n_leaf);
+    p->d_res = a.take<unsigned long long>(4);
+    p->d_err = a.take<int>(4);
+    const long long nv = std::max(p->nz, p->neta);
+    p->d_stash_z = a.take<double>(nv);
+    p->d_stash_e = a.take<double>(nv);
+    carve_set(a, p, p->s64);
+    carve_set(a, p, p->s32);
+}
+
+// ---------------------------------------------------------------------------
+// validation and layout
+// ---------------------------------------------------------------------------
+
+static bool finite_all(const double* v, long long n) {
+    for (long long k = 0; k < n; ++k)
+        if (!std::isfinite(v[k])) return false;
+    return true;
+}
+
+static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p) {
+    if (!d) return fail(SPOCK_E_INVALID, "null problem description");
+    const int n = d->n_nodes;
+    if (n < 2) return fail(SPOCK_E_INVALID, "a tree needs at least two nodes");
+    if (d->nx < 1 || d->nu < 1) return fail(SPOCK_E_INVALID, "nx and nu must be >= 1");
+    if (!d->parent || !d->cond_prob || !d->A || !d->B || !d->Q_diag || !d->R_diag || !d->QN_diag ||
+        !d->x_lo || !d->x_hi || !d->u_lo || !d->u_hi || !d->xN_lo || !d->xN_hi || !d->gamma)
+        return fail(SPOCK_E_INVALID, "missing array in the problem description");
+    if (d->parent[0] != -1) return fail(SPOCK_E_INVALID, "parent[0] must be -1");
+    p->n = n;
+    p->nx = d->nx;
+    p->nu = d->nu;
+    p->m = d->nx + d->nu;
+    p->parent.assign(d->parent, d->parent + n);
+    p->n_ch.assign(n, 0);
+    p->first_child.assign(n, -1);
+    std::vector<int> stage(n, 0);
+    for (int j = 1; j < n; ++j) {
+        const int i = d->parent[j];
+        if (i < 0 || i >= j) return fail(SPOCK_E_INVALID, "parent[j] must lie in [0, j)");
+        if (j > 1 && i < d->parent[j - 1])
+            return fail(SPOCK_E_INVALID, "nodes must be numbered stage by stage (children contiguous)");
+        if (p->n_ch[i] == 0) p->first_child[i] = j;
+        p->n_ch[i]++;
+        stage[j] = stage[i] + 1;
+    }
+    int nl = 0;
+    while (nl < n && p->n_ch[nl] > 0) ++nl;
+    for (int j = nl; j < n; ++j)
+        if (p->n_ch[j] != 0) return fail(SPOCK_E_INVALID, "non-leaf nodes must precede all leaves");
+    p->n_nl = nl;
+    p->n_leaf = n - nl;
+    p->N = stage[n - 1];
+    for (int j = nl; j < n; ++j)
+        if (stage[j] != p->N) return fail(SPOCK_E_INVALID, "every leaf must sit at the last stage");
+    if (p->N + 1 > spk::kMaxDepth) return fail(SPOCK_E_INVALID, "horizon too long");
+    p->max_ch = *std::max_element(p->n_ch.begin(), p->n_ch.end());
+    for (int j = 0; j < n; ++j)
+        if (!(d->cond_prob[j] > 0) || !std::isfinite(d->cond_prob[j]))
+            return fail(SPOCK_E_INVALID, "probabilities must be positive");
+    for (int i = 0; i < nl; ++i) {
+        double s = 0;
+        for (int c = 0; c < p->n_ch[i]; ++c) s += d->cond_prob[p->first_child[i] + c];
+        if (std::fabs(s - 1.0) > 1e-9) return fail(SPOCK_E_INVALID, "children probabilities must sum to 1");
+    }
+    const int nx = d->nx, nu = d->nu;
+    if (!finite_all(d->A + (size_t)nx * nx, (long long)(n - 1) * nx * nx) ||
+        !finite_all(d->B + (size_t)nx * nu, (long long)(n - 1) * nx * nu) ||
+        (d->c && !finite_all(d->c + nx, (long long)(n - 1) * nx)) || !finite_all(d->Q_diag, nx) ||
+        !finite_all(d->R_diag, nu) || !finite_all(d->QN_diag, nx) || !finite_all(d->gamma, nl))
+        return fail(SPOCK_E_INVALID, "non-finite problem data");
+    for (int k = 0; k < nx; ++k)
+        if (!(d->Q_diag[k] > 0) || !(d->QN_diag[k] > 0)) return fail(SPOCK_E_INVALID, "Q, QN must be > 0");
+    for (int k = 0; k < nu; ++k)
+        if (!(d->R_diag[k] > 0)) return fail(SPOCK_E_INVALID, "R must be > 0");
+    for (int k = 0; k < nx; ++k)
+        if (!(d->x_lo[k] <= d->x_hi[k]) || !(d->xN_lo[k] <= d->xN_hi[k]) || std::isnan(d->x_lo[k]) ||
+            std::isnan(d->xN_lo[k]))
+            return fail(SPOCK_E_INVALID, "state bounds must satisfy lo <= hi");
+    for (int k = 0; k < nu; ++k)
+        if (!(d->u_lo[k] <= d->u_hi[k])) return fail(SPOCK_E_INVALID, "input bounds must satisfy lo <= hi");
+    for (int i = 0; i < nl; ++i)
+        if (!(d->gamma[i] >= 0 && d->gamma[i] <= 1)) return fail(SPOCK_E_INVALID, "gamma must lie in [0, 1]");
+    if (std::isnan(d->x_ball) || std::isnan(d->xN_ball)) return fail(SPOCK_E_INVALID, "NaN ball radius");
+
+    p->has_ball = d->x_ball > 0;
+    p->has_ballN = d->xN_ball > 0;
+    p->affine = d->c != nullptr;
+    p->nc = p->m + (p->has_ball ? nx : 0);
+    p->ncN = nx + (p->has_ballN ? nx : 0);
+    p->y_off.assign(nl + 1, 0);
+    for (int i = 0; i < nl; ++i) p->y_off[i + 1] = p->y_off[i] + 2 * p->n_ch[i] + 1;
+    p->ny = p->y_off[nl];
+    long long o = 1;
+    p->z_x = o; o += (long long)n * nx;
+    p->z_u = o; o += (long long)nl * nu;
+    p->z_y = o; o += p->ny;
+    p->z_tau = o; o += n - 1;
+    p->z_s = o; o += n - 1;
+    p->nz = o;
+    o = 0;
+    p->e_y = o; o += p->ny;
+    p->e_s = o; o += nl;
+    p->e_c = o; o += (long long)nl * p->nc;
+    p->e_soc = o; o += (long long)(n - 1) * (p->m + 2);
+    p->e_cN = o; o += (long long)p->n_leaf * p->ncN;
+    p->e_socN = o; o += (long long)p->n_leaf * (nx + 2);
+    p->neta = o;
+    p->M_stride = ((long long)nx * p->m + 31) / 32 * 32;
+    p->KR_stride = ((long long)nu * p->m + 31) / 32 * 32;
+    if ((long long)spk::lds_elems(nx, nu, p->max_ch) * 8 > 64 * 1024)
+        return fail(SPOCK_E_INVALID, "nx + nu or the branching is too large for one workgroup");
+    return SPOCK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// scaling (Sec. 5.4) and exact ||L|| (Sec. 4.4)
+// ---------------------------------------------------------------------------
+
+static void scale_data(const spock_problem_desc* d, int precondition, spock_problem* p) {
+    const int nx = p->nx, nu = p->nu;
+    p->Sx.assign(nx, 1.0);
+    p->Su.assign(nu, 1.0);
+    p->SxN.assign(nx, 1.0);
+    if (precondition) {
+        const double chat = std::sqrt((double)p->max_ch);
+        for (int k = 0; k < nx; ++k) {
+            p->Sx[k] = chat * std::max(1.0, std::sqrt(d->Q_diag[k]));
+            p->SxN[k] = std::max(1.0, std::sqrt(d->QN_diag[k]));
+        }
+        for (int k = 0; k < nu; ++k) p->Su[k] = chat * std::max(1.0, std::sqrt(d->R_diag[k]));
+    }
+    p->qh.resize(nx);
+    p->rh.resize(nu);
+    p->qnh.resize(nx);
+    for (int k = 0; k < nx; ++k) {
+        p->qh[k] = std::sqrt(d->Q_diag[k]) / p->Sx[k];
+        p->qnh[k] = std::sqrt(d->QN_diag[k]) / p->SxN[k];
+    }
+    for (int k = 0; k < nu; ++k) p->rh[k] = std::sqrt(d->R_diag[k]) / p->Su[k];
+    // constraint rows Gamma S^-1 have orthogonal columns; their 2-norm is the
+    // largest column norm
+    double a = 1.0, aN = 1.0;
+    if (precondition) {
+        double mx = 0;
+        for (int k = 0; k < nx; ++k) mx = std::max(mx, (1.0 + p->has_ball) / (p->Sx[k] * p->Sx[k]));
+        for (int k = 0; k < nu; ++k) mx = std::max(mx, 1.0 / (p->Su[k] * p->Su[k]));
+        a = std::max(1.0, std::sqrt(mx));
+        double mxN = 0;
+        for (int k = 0; k < nx; ++k) mxN = std::max(mxN, (1.0 + p->has_ballN) / (p->SxN[k] * p->SxN[k]));
+        aN = std::max(1.0, std::sqrt(mxN));
+    }
+    p->con_scale = a;
+    p->con_scaleN = aN;
+    p->gx.resize(nx);
+    p->gb.resize(nx);
+    p->gu.resize(nu);
+    p->gxN.resize(nx);
+    p->gbN.resize(nx);
+    for (int k = 0; k < nx; ++k) {
+        p->gx[k] = 1.0 / (a * p->Sx[k]);
+        p->gb[k] = p->has_ball ? 1.0 / (a * p->Sx[k]) : 0.0;
+        p->gxN[k] = 1.0 / (aN * p->SxN[k]);
+        p->gbN[k] = p->has_ballN ? 1.0 / (aN * p->SxN[k]) : 0.0;
+    }
+    for (int k = 0; k < nu; ++k) p->gu[k] = 1.0 / (a * p->Su[k]);
+    p->lo.resize(p->m);
+    p->hi.resize(p->m);
+    for (int k = 0; k < nx; ++k) {
+        p->lo[k] = d->x_lo[k] / a;
+        p->hi[k] = d->x_hi[k] / a;
+    }
+    for (int k = 0; k < nu; ++k) {
+        p->lo[nx + k] = d->u_lo[k] / a;
+        p->hi[nx + k] = d->u_hi[k] / a;
+    }
+    p->loN.resize(nx);
+    p->hiN.resize(nx);
+    for (int k = 0; k < nx; ++k) {
+        p->loN[k] = d->xN_lo[k] / aN;
+        p->hiN[k] = d->xN_hi[k] / aN;
+    }
+    p->ball_r = p->has_ball ? d->x_ball / a : 0.0;
+    p->ballN_r = p->has_ballN ? d->xN_ball / aN : 0.0;
+    p->prob.assign(d->cond_prob, d->cond_prob + p->n);
+    p->gamma.assign(d->gamma, d->gamma + p->n_nl);
+    p->x_lo.assign(d->x_lo, d->x_lo + nx);
+    p->x_hi.assign(d->x_hi, d->x_hi + nx);
+    p->x_ball = d->x_ball;
+
+    // ||L||: largest block norm of L composed with a permutation
+    double L2 = 0.5;  // tau^j and leaf s^j rows (1/2, 1/2)
+    for (int i = 0; i < p->n_nl; ++i) {
+        const double k = p->n_ch[i];
+        for (int r = 0; r < nx; ++r)
+            L2 = std::max(L2, p->gx[r] * p->gx[r] + p->gb[r] * p->gb[r] + k * p->qh[r] * p->qh[r]);
+        for (int r = 0; r < nu; ++r) L2 = std::max(L2, p->gu[r] * p->gu[r] + k * p->rh[r] * p->rh[r]);
+        double b2 = 1.0;
+        for (int c = 0; c < p->n_ch[i]; ++c) b2 += p->prob[p->first_child[i] + c] * p->prob[p->first_child[i] + c];
+        const double beta = std::sqrt(b2);
+        const double sig = 0.5 * (beta + std::sqrt(b2 + 4.0));  // [[I, 0], [-b^T, 1]]
+        L2 = std::max(L2, sig * sig);
+    }
+    for (int r = 0; r < nx; ++r)
+        L2 = std::max(L2, p->gxN[r] * p->gxN[r] + p->gbN[r] * p->gbN[r] + p->qnh[r] * p->qnh[r]);
+    p->Lnorm = std::sqrt(L2);
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 1 (offline S1) in float64; fills [Abar|B] per edge and [K | R~^-1] per
+// non-leaf node, and P c for affine dynamics.
+// ---------------------------------------------------------------------------
+
+static int32_t offline_factor(const spock_problem_desc* d, spock_problem* p, std::vector<double>& M,
+                              std::vector<double>& KR, std::vector<double>& cs, std::vector<double>& Pc) {
+    const int n = p->n, nx = p->nx, nu = p->nu, m = p->m;
+    M.assign((size_t)n * p->M_stride, 0.0);
+    KR.assign((size_t)p->n_nl * p->KR_stride, 0.0);
+    if (p->affine) {
+        cs.assign((size_t)n * nx, 0.0);
+        Pc.assign((size_t)n * nx, 0.0);
+    }
+    // scaled dynamics written straight into M: [A~ | B~] (Abar replaces A~ below)
+    auto S_of = [&](int j) -> const std::vector<double>& { return j < p->n_nl ? p->Sx : p->SxN; };
+    for (int j = 1; j < n; ++j) {
+        const std::vector<double>& Sj = S_of(j);
+        double* Mj = M.data() + (size_t)j * p->M_stride;
+        const double* A = d->A + (size_t)j * nx * nx;
+        const double* B = d->B + (size_t)j * nx * nu;
+        for (int r = 0; r < nx; ++r) {
+            for (int c = 0; c < nx; ++c) Mj[(size_t)r * m + c] = Sj[r] * A[(size_t)r * nx + c] / p->Sx[c];
+            for (int c = 0; c < nu; ++c) Mj[(size_t)r * m + nx + c] = Sj[r] * B[(size_t)r * nu + c] / p->Su[c];
+            if (p->affine) cs[(size_t)j * nx + r] = Sj[r] * d->c[(size_t)j * nx + r];
+        }
+    }
+    std::vector<std::vector<double>> P(n);
+    std::vector<int> stage_start(p->N + 2, 0);
+    {
+        std::vector<int> stage(n, 0);
+        for (int j = 1; j < n; ++j) stage[j] = stage[p->parent[j]] + 1;
+        for (int j = 0; j < n; ++j) stage_start[stage[j] + 1] = j + 1;
+        for (int t = 1; t <= p->N + 1; ++t) stage_start[t] = std::max(stage_start[t], stage_start[t - 1]);
+    }
+    for (int j = p->n_nl; j < n; ++j) {
+        P[j].assign((size_t)nx * nx, 0.0);
+        for (int r = 0; r < nx; ++r) P[j][(size_t)r * nx + r] = 1.0;
+        if (p->affine)
+            for (int r = 0; r < nx; ++r) Pc[(size_t)j * nx + r] = cs[(size_t)j * nx + r];
+    }
+    std::atomic<int> bad(0);
+    for (int t = p->N - 1; t >= 0; --t) {
+        const int s0 = stage_start[t], s1 = stage_start[t + 1];
+        parallel_for(s1 - s0, [&](int q) {
+            const int i = s0 + q;
+            std::vector<double> Rt((size_t)nu * nu, 0.0), rhs((size_t)nu * nx, 0.0);
+            std::vector<double> A((size_t)nx * nx), B((size_t)nx * nu), PB((size_t)nx * nu), PA((size_t)nx * nx);
+            for (int r = 0; r < nu; ++r) Rt[(size_t)r * nu + r] = 1.0;
+            const int fc = p->first_child[i], k = p->n_ch[i];
+            for (int c = 0; c < k; ++c) {
+                const int j = fc + c;
+                const double* Mj = M.data() + (size_t)j * p->M_stride;
+                for (int r = 0; r < nx; ++r) {
+                    std::memcpy(&A[(size_t)r * nx], Mj + (size_t)r * m, sizeof(double) * nx);
+                    std::memcpy(&B[(size_t)r * nu], Mj + (size_t)r * m + nx, sizeof(double) * nu);
+                }
+                mm(nx, nu, nx, P[j].data(), B.data(), PB.data(), false);
+                mtm_acc(nu, nu, nx, B.data(), PB.data(), Rt.data());  // R~ += B^T P B
+                mm(nx, nx, nx, P[j].data(), A.data(), PA.data(), false);
+                mtm_acc(nu, nx, nx, B.data(), PA.data(), rhs.data());  // sum B^T P A
+            }
+            std::vector<double> Lc = Rt, Rinv((size_t)nu * nu), K((size_t)nu * nx);
+            if (!cholesky(nu, Lc.data())) {
+                bad = 1;
+                return;
+            }
+            chol_inverse(nu, Lc.data(), Rinv.data());
+            mm(nu, nx, nu, Rinv.data(), rhs.data(), K.data(), false);
+            for (auto& v : K) v = -v;  // K = -R~^-1 sum B^T P A
+            std::vector<double> Pi((size_t)nx * nx, 0.0);
+            for (int r = 0; r < nx; ++r) Pi[(size_t)r * nx + r] = 1.0;
+            mtm_acc(nx, nx, nu, K.data(), K.data(), Pi.data());  // + K^T K
+            std::vector<double> BK((size_t)nx * nx), PAb((size_t)nx * nx);
+            for (int c = 0; c < k; ++c) {
+                const int j = fc + c;
+                double* Mj = M.data() + (size_t)j * p->M_stride;
+                for (int r = 0; r < nx; ++r) std::memcpy(&B[(size_t)r * nu], Mj + (size_t)r * m + nx, sizeof(double) * nu);
+                mm(nx, nx, nu, B.data(), K.data(), BK.data(), false);
+                for (int r = 0; r < nx; ++r)
+                    for (int cc = 0; cc < nx; ++cc) {
+                        const double ab = Mj[(size_t)r * m + cc] + BK[(size_t)r * nx + cc];  // Abar = A + B K
+                        Mj[(size_t)r * m + cc] = ab;
+                        A[(size_t)r * nx + cc] = ab;
+                    }
+                mm(nx, nx, nx, P[j].data(), A.data(), PAb.data(), false);
+                mtm_acc(nx, nx, nx, A.data(), PAb.data(), Pi.data());  // + Abar^T P Abar
+            }
+            double* KRi = KR.data() + (size_t)i * p->KR_stride;
+            for (int r = 0; r < nu; ++r) {
+                std::memcpy(KRi + (size_t)r * m, &K[(size_t)r * nx], sizeof(double) * nx);
+                std::memcpy(KRi + (size_t)r * m + nx, &Rinv[(size_t)r * nu], sizeof(double) * nu);
+            }
+            if (p->affine)
+                for (int r = 0; r < nx; ++r) {
+                    double s = 0;
+                    for (int cc = 0; cc < nx; ++cc) s += Pi[(size_t)r * nx + cc] * cs[(size_t)i * nx + cc];
+                    Pc[(size_t)i * nx + r] = s;
+                }
+            P[i].swap(Pi);
+            for (int c = 0; c < k; ++c) std::vector<double>().swap(P[fc + c]);
+        });
+        if (bad) return fail(SPOCK_E_INVALID, "R~ not positive definite in the offline factorisation");
+    }
+    return SPOCK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// upload
+// ---------------------------------------------------------------------------
+
+template <typename real>
+static hipError_t put(const real* dst, const std::vector<double>& src, hipStream_t st) {
+    std::vector<real> tmp(src.begin(), src.end());
+    hipError_t e = hipMemcpyAsync((void*)dst, tmp.data(), tmp.size() * sizeof(real), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
+template <typename real>
+static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<double>& M,
+                          const std::vector<double>& KR, const std::vector<double>& cs,
+                          const std::vector<double>& Pc) {
+    ProbDev<real>& h = s.h;
+    h.n = p->n;
+    h.n_nl = p->n_nl;
+    h.N = p->N;
+    h.nx = p->nx;
+    h.nu = p->nu;
+    h.m = p->m;
+    h.nc = p->nc;
+    h.ncN = p->ncN;
+    h.nbox = p->m;
+    h.has_ball = p->has_ball;
+    h.has_ballN = p->has_ballN;
+    h.affine = p->affine;
+    h.max_ch = p->max_ch;
+    h.alpha = (real)p->alpha;
+    h.ball_r = (real)p->ball_r;
+    h.ballN_r = (real)p->ballN_r;
+    h.parent = p->d_tree;
+    h.first_child = p->d_tree + p->n;
+    h.n_ch = p->d_tree + 2 * p->n;
+    h.y_off = p->d_tree + 3 * p->n;
+    h.M_stride = p->M_stride;
+    h.KR_stride = p->KR_stride;
+    h.z_x = p->z_x; h.z_u = p->z_u; h.z_y = p->z_y; h.z_tau = p->z_tau; h.z_s = p->z_s;
+    h.e_y = p->e_y; h.e_s = p->e_s; h.e_c = p->e_c; h.e_soc = p->e_soc; h.e_cN = p->e_cN; h.e_socN = p->e_socN;
+    h.nz = p->nz;
+    h.neta = p->neta;
+    h.cnt = p->d_cnt;
+    h.flag = p->d_flag;
+    h.err = p->d_err;
+    h.res = p->d_res;
+    s.lds_bytes = spk::lds_elems(p->nx, p->nu, p->max_ch) * (int)sizeof(real);
+    hipStream_t st = p->stream;
+    HIP_TRY(put<real>(h.M, M, st));
+    HIP_TRY(put<real>(h.KR, KR, st));
+    if (p->affine) {
+        HIP_TRY(put<real>(h.c, cs, st));
+        HIP_TRY(put<real>(h.Pc, Pc, st));
+    }
+    HIP_TRY(put<real>(h.qh, p->qh, st));
+    HIP_TRY(put<real>(h.rh, p->rh, st));
+    HIP_TRY(put<real>(h.qnh, p->qnh, st));
+    HIP_TRY(put<real>(h.gx, p->gx, st));
+    HIP_TRY(put<real>(h.gu, p->gu, st));
+    HIP_TRY(put<real>(h.gb, p->gb, st));
+    HIP_TRY(put<real>(h.gxN, p->gxN, st));
+    HIP_TRY(put<real>(h.gbN, p->gbN, st));
+    HIP_TRY(put<real>(h.lo, p->lo, st));
+    HIP_TRY(put<real>(h.hi, p->hi, st));
+    HIP_TRY(put<real>(h.loN, p->loN, st));
+    HIP_TRY(put<real>(h.hiN, p->hiN, st));
+    HIP_TRY(put<real>(h.prob, p->prob, st));
+    HIP_TRY(put<real>(h.gamma, p->gamma, st));
+    for (int k = 0; k < 2; ++k) {
+        HIP_TRY(spk::launch_fill<real>(h.z[k], real(0), p->nz, st));
+        HIP_TRY(spk::launch_fill<real>(h.eta[k], real(0), p->neta, st));
+    }
+    HIP_TRY(hipMemcpyAsync(s.d, &h, sizeof(h), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return SPOCK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stepping
+// ---------------------------------------------------------------------------
+
+template <typename real>
+static int32_t step(spock_problem* p, int check) {
+    DevSet<real>& s = set_of<real>(p);
+    HIP_TRY(spk::launch_step<real>(s.d, p->d_tasks, p->n_leaf, s.lds_bytes, s.par, check, p->stream));
+    s.par ^= 1;
+    return SPOCK_OK;
+}
+
+// `steps` (even) steps, residual check on the last one; replayed as a graph.
+template <typename real>
+static int32_t chunk(spock_problem* p, int steps) {
+    DevSet<real>& s = set_of<real>(p);
+    if (p->set.use_graph && (steps & 1) == 0 && steps >= 2) {
+        if (s.graph_steps != steps) {
+            for (auto& g : s.graph)
+                if (g) {
+                    (void)hipGraphExecDestroy(g);
+                    g = nullptr;
+                }
+            s.graph_steps = steps;
+        }
+        hipGraphExec_t& ge = s.graph[s.par];
+        if (!ge) {
+            hipGraph_t graph;
+            HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+            int par = s.par;
+            for (int k = 0; k < steps; ++k) {
+                hipError_t e =
+                    spk::launch_step<real>(s.d, p->d_tasks, p->n_leaf, s.lds_bytes, par, k == steps - 1, p->stream);
+                if (e != hipSuccess) {
+                    (void)hipStreamEndCapture(p->stream, &graph);
+                    return fail(SPOCK_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+                }
+                par ^= 1;
+            }
+            HIP_TRY(hipStreamEndCapture(p->stream, &graph));
+            HIP_TRY(hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0));
+            HIP_TRY(hipGraphDestroy(graph));
+        }
+        HIP_TRY(hipGraphLaunch(ge, p->stream));
+        return SPOCK_OK;  // parity unchanged after an even number of steps
+    }
+    for (int k = 0; k < steps; ++k) {
+        int32_t r = step<real>(p, k == steps - 1);
+        if (r) return r;
+    }
+    return SPOCK_OK;
+}
+
+static int32_t read_res(spock_problem* p, double* xi1, double* xi2) {
+    HIP_TRY(hipMemcpyAsync(p->h_res, p->d_res, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->h_res + 2, p->d_err, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    if ((int)p->h_res[2] != 0) {
+        int zero = 0;
+        (void)hipMemcpy(p->d_err, &zero, sizeof(int), hipMemcpyHostToDevice);
+        return fail(SPOCK_E_HIP, "device wait timeout in the forward sweep");
+    }
+    double a, b;
+    std::memcpy(&a, &p->h_res[0], 8);
+    std::memcpy(&b, &p->h_res[1], 8);
+    *xi1 = a;
+    *xi2 = b;
+    return SPOCK_OK;
+}
+
+// current iterate -> the other precision's copy `par`
+static int32_t move_iterate(spock_problem* p, int to) {
+    if (p->cur == to) return SPOCK_OK;
+    if (to == SPOCK_FP64) {
+        HIP_TRY(spk::launch_convert<double, float>(p->s64.h.z[0], p->s32.h.z[p->s32.par], p->nz, p->stream));
+        HIP_TRY(spk::launch_convert<double, float>(p->s64.h.eta[0], p->s32.h.eta[p->s32.par], p->neta, p->stream));
+        p->s64.par = 0;
+    } else {
+        HIP_TRY(spk::launch_convert<float, double>(p->s32.h.z[0], p->s64.h.z[p->s64.par], p->nz, p->stream));
+        HIP_TRY(spk::launch_convert<float, double>(p->s32.h.eta[0], p->s64.h.eta[p->s64.par], p->neta, p->stream));
+        p->s32.par = 0;
+    }
+    p->cur = to;
+    return SPOCK_OK;
+}
+
+static int32_t zero_iterate(spock_problem* p) {
+    HIP_TRY(spk::launch_fill<double>(p->s64.h.z[0], 0.0, p->nz, p->stream));
+    HIP_TRY(spk::launch_fill<double>(p->s64.h.eta[0], 0.0, p->neta, p->stream));
+    p->s64.par = 0;
+    p->cur = SPOCK_FP64;
+    return SPOCK_OK;
+}
+
+static int32_t set_x0_device(spock_problem* p, const double* x0, bool check_feasible) {
+    if (!x0) return fail(SPOCK_E_INVALID, "null x0");
+    if (!finite_all(x0, p->nx)) return fail(SPOCK_E_INVALID, "non-finite x0");
+    if (check_feasible) {
+        double nrm = 0;
+        for (int k = 0; k < p->nx; ++k) {
+            if (x0[k] < p->x_lo[k] || x0[k] > p->x_hi[k])
+                return fail(SPOCK_E_INFEASIBLE_X0, "x0 violates the state box at the root");
+            nrm += x0[k] * x0[k];
+        }
+        if (p->has_ball && std::sqrt(nrm) > p->x_ball)
+            return fail(SPOCK_E_INFEASIBLE_X0, "x0 violates the state ball at the root");
+    }
+    p->x0s.resize(p->nx);
+    for (int k = 0; k < p->nx; ++k) p->x0s[k] = p->Sx[k] * x0[k];
+    HIP_TRY(put<double>(p->s64.h.x0, p->x0s, p->stream));
+    HIP_TRY(put<float>(p->s32.h.x0, p->x0s, p->stream));
+    return SPOCK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* spock_last_error(void) { return g_err.c_str(); }
+
+int32_t spock_default_settings(spock_settings* s) {
+    if (!s) return fail(SPOCK_E_INVALID, "null settings");
+    s->alpha = 0.0;
+    s->eps = 1e-6;
+    s->max_iters = 100000;
+    s->precision = SPOCK_FP64;
+    s->precondition = 1;
+    s->check_every = 20;
+    s->use_graph = 1;
+    return SPOCK_OK;
+}
+
+static int32_t check_settings(const spock_settings* s) {
+    if (!s) return fail(SPOCK_E_INVALID, "null settings");
+    if (!(s->alpha >= 0) || !std::isfinite(s->alpha)) return fail(SPOCK_E_INVALID, "alpha must be >= 0");
+    if (!(s->eps > 0)) return fail(SPOCK_E_INVALID, "eps must be > 0");
+    if (s->max_iters < 1) return fail(SPOCK_E_INVALID, "max_iters must be >= 1");
+    if (s->precision < SPOCK_FP64 || s->precision > SPOCK_FP32) return fail(SPOCK_E_INVALID, "bad precision");
+    if (s->check_every < 2 || (s->check_every & 1)) return fail(SPOCK_E_INVALID, "check_every must be even and >= 2");
+    return SPOCK_OK;
+}
+
+int32_t spock_problem_footprint(const spock_problem_desc* desc, const spock_settings* s, size_t* bytes) {
+    if (!bytes) return fail(SPOCK_E_INVALID, "null output");
+    int32_t r = check_settings(s);
+    if (r) return r;
+    spock_problem tmp;
+    r = validate_and_layout(desc, &tmp);
+    if (r) return r;
+    Arena a(nullptr);
+    carve(a, &tmp);
+    *bytes = a.off + 256;
+    return SPOCK_OK;
+}
+
+int32_t spock_problem_create(const spock_problem_desc* desc, const spock_settings* s, void* ws, size_t ws_bytes,
+                             void* stream, spock_problem** out) {
+    if (!out) return fail(SPOCK_E_INVALID, "null output handle");
+    *out = nullptr;
+    int32_t r = check_settings(s);
+    if (r) return r;
+    spock_problem* p = nullptr;
+    try {
+        p = new spock_problem();
+        p->set = *s;
+        r = validate_and_layout(desc, p);
+        if (r) {
+            delete p;
+            return r;
+        }
+        scale_data(desc, s->precondition, p);
+        p->alpha = s->alpha > 0 ? s->alpha : 0.99 / p->Lnorm;
+        std::vector<double> M, KR, cs, Pc;
+        r = offline_factor(desc, p, M, KR, cs, Pc);
+        if (r) {
+            delete p;
+            return r;
+        }
+        Arena dry(nullptr);
+        carve(dry, p);
+        p->bytes = dry.off + 256;
+        if (ws) {
+            if (ws_bytes < p->bytes) {
+                delete p;
+                return fail(SPOCK_E_NOMEM, "device workspace smaller than the footprint");
+            }
+            p->base = ws;
+        } else {
+            hipError_t e = hipMalloc(&p->base, p->bytes);
+            if (e != hipSuccess) {
+                delete p;
+                return fail(SPOCK_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+            }
+            p->owns = true;
+        }
+        if (stream) {
+            p->stream = (hipStream_t)stream;
+        } else {
+            hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                spock_problem_destroy(p);
+                return fail(SPOCK_E_HIP, "hipStreamCreate failed");
+            }
+            p->owns_stream = true;
+        }
+        if (hipHostMalloc((void**)&p->h_res, 4 * sizeof(unsigned long long), 0) != hipSuccess) {
+            spock_problem_destroy(p);
+            return fail(SPOCK_E_HIP, "hipHostMalloc failed");
+        }
+        Arena a(p->base);
+        carve(a, p);
+        // tree arrays and tasks
+        std::vector<int> tree(4 * (size_t)p->n + 4, 0);
+        std::copy(p->parent.begin(), p->parent.end(), tree.begin());
+        std::copy(p->first_child.begin(), p->first_child.end(), tree.begin() + p->n);
+        std::copy(p->n_ch.begin(), p->n_ch.end(), tree.begin() + 2 * (size_t)p->n);
+        std::copy(p->y_off.begin(), p->y_off.end(), tree.begin() + 3 * (size_t)p->n);
+        std::vector<int2> tasks(p->n_leaf);
+        for (int k = 0; k < p->n_leaf; ++k) tasks[k] = make_int2(0, k);
+        hipError_t e = hipMemcpy(p->d_tree, tree.data(), tree.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_tasks, tasks.data(), tasks.size() * sizeof(int2), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            spock_problem_destroy(p);
+            return fail(SPOCK_E_HIP, std::string("upload: ") + hipGetErrorString(e));
+        }
+        // arrival counters, claim flags, the error flag and residual slots start at zero
+        e = spk::launch_fill<int>(p->d_cnt, 0, p->n, p->stream);
+        if (e == hipSuccess) e = spk::launch_fill<int>(p->d_flag, 0, p->n, p->stream);
+        if (e == hipSuccess) e = spk::launch_fill<int>(p->d_err, 0, 4, p->stream);
+        if (e == hipSuccess) e = spk::launch_fill<unsigned long long>(p->d_res, 0ull, 4, p->stream);
+        if (e != hipSuccess) {
+            spock_problem_destroy(p);
+            return fail(SPOCK_E_HIP, std::string("init: ") + hipGetErrorString(e));
+        }
+        r = upload_set<double>(p, p->s64, M, KR, cs, Pc);
+        if (!r) r = upload_set<float>(p, p->s32, M, KR, cs, Pc);
+        if (r) {
+            spock_problem_destroy(p);
+            return r;
+        }
+        *out = p;
+        return SPOCK_OK;
+    } catch (const std::bad_alloc&) {
+        if (p) spock_problem_destroy(p);
+        return fail(SPOCK_E_NOMEM, "host allocation failed");
+    } catch (const std::exception& ex) {
+        if (p) spock_problem_destroy(p);
+        return fail(SPOCK_E_INVALID, ex.what());
+    }
+}
+
+int32_t spock_problem_destroy(spock_problem* p) {
+    if (!p) return SPOCK_OK;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    for (auto* s : {&p->s64.graph[0], &p->s64.graph[1], &p->s32.graph[0], &p->s32.graph[1]})
+        if (*s) (void)hipGraphExecDestroy(*s);
+    if (p->h_res) (void)hipHostFree(p->h_res);
+    if (p->owns && p->base) (void)hipFree(p->base);
+    if (p->owns_stream && p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+    return SPOCK_OK;
+}
+
+int32_t spock_problem_sizes(const spock_problem* p, spock_sizes* o) {
+    if (!p || !o) return fail(SPOCK_E_INVALID, "null argument");
+    o->nz = p->nz;
+    o->neta = p->neta;
+    o->n = p->n;
+    o->n_nl = p->n_nl;
+    o->n_leaf = p->n_leaf;
+    o->N = p->N;
+    o->nx = p->nx;
+    o->nu = p->nu;
+    o->nc = p->nc;
+    o->ncN = p->ncN;
+    o->max_children = p->max_ch;
+    o->alpha = p->alpha;
+    o->L_norm = p->Lnorm;
+    o->device_bytes = p->bytes;
+    return SPOCK_OK;
+}
+
+int32_t spock_set_settings(spock_problem* p, const spock_settings* s) {
+    if (!p) return fail(SPOCK_E_INVALID, "null handle");
+    int32_t r = check_settings(s);
+    if (r) return r;
+    if (s->alpha != p->set.alpha && s->alpha > 0 && s->alpha != p->alpha)
+        return fail(SPOCK_E_INVALID, "alpha is fixed at create time");
+    if (s->precondition != p->set.precondition) return fail(SPOCK_E_INVALID, "precondition is fixed at create time");
+    p->set = *s;
+    return SPOCK_OK;
+}
+
+int32_t spock_set_x0(spock_problem* p, const double* x0) {
+    if (!p) return fail(SPOCK_E_INVALID, "null handle");
+    return set_x0_device(p, x0, false);
+}
+
+static double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Run chunks in one precision until rel_res <= eps, the step budget is spent,
+// or (float32 only) progress stalls.  Returns SPOCK_OK on convergence.
+extern "C++" {
+template <typename real>
+static int32_t iterate(spock_problem* p, long long budget, long long* taken, double* rel, double* x1, double* x2,
+                       bool stall_exit) {
+    const double scale = std::max(1.0, std::max(p->xi_ref[0], p->xi_ref[1]));
+    const int ce = p->set.check_every;
+    double best = INFINITY;
+    int no_gain = 0;
+    *taken = 0;
+    while (*taken < budget) {
+        int32_t r = chunk<real>(p, ce);
+        if (r) return r;
+        *taken += ce;
+        r = read_res(p, x1, x2);
+        if (r) return r;
+        *rel = std::max(*x1, *x2) / scale;
+        if (!std::isfinite(*rel)) return fail(SPOCK_E_DIVERGED, "non-finite residual");
+        if (*rel <= p->set.eps) return SPOCK_OK;
+        if (stall_exit) {
+            if (*rel < 0.99 * best) {
+                best = *rel;
+                no_gain = 0;
+            } else if (++no_gain >= 25) {
+                return SPOCK_E_NOT_CONVERGED;
+            }
+        }
+    }
+    return SPOCK_E_NOT_CONVERGED;
+}
+}  // extern "C++"
+
+
+int32_t spock_solve(spock_problem* p, const double* x0, int32_t warm, spock_info* info) {
+    if (!p) return fail(SPOCK_E_INVALID, "null handle");
+    const double t0 = now_s();
+    spock_info inf{};
+    int32_t r = set_x0_device(p, x0, true);
+    if (r) return r;
+    long long it = 0, it32 = 0;
+    double rel = INFINITY, x1 = INFINITY, x2 = INFINITY;
+    const int prec = p->set.precision;
+    if (!warm) {
+        r = zero_iterate(p);
+        if (r) return r;
+    }
+    if (!p->have_ref || !warm) {
+        // reference residuals: the first CP step from zero (float64)
+        const bool keep = warm != 0;
+        if (keep) {
+            r = move_iterate(p, SPOCK_FP64);
+            if (r) return r;
+            HIP_TRY(hipMemcpyAsync(p->d_stash_z, p->s64.h.z[p->s64.par], p->nz * 8, hipMemcpyDeviceToDevice, p->stream));
+            HIP_TRY(hipMemcpyAsync(p->d_stash_e, p->s64.h.eta[p->s64.par], p->neta * 8, hipMemcpyDeviceToDevice, p->stream));
+            r = zero_iterate(p);
+            if (r) return r;
+        }
+        r = step<double>(p, 1);
+        if (r) return r;
+        r = read_res(p, &x1, &x2);
+        if (r) return r;
+        p->xi_ref[0] = x1;
+        p->xi_ref[1] = x2;
+        p->have_ref = true;
+        if (keep) {
+            HIP_TRY(hipMemcpyAsync(p->s64.h.z[0], p->d_stash_z, p->nz * 8, hipMemcpyDeviceToDevice, p->stream));
+            HIP_TRY(hipMemcpyAsync(p->s64.h.eta[0], p->d_stash_e, p->neta * 8, hipMemcpyDeviceToDevice, p->stream));
+            p->s64.par = 0;
+        } else {
+            it = 1;
+            rel = std::max(x1, x2) / std::max(1.0, std::max(x1, x2));
+        }
+    }
+    const long long budget = p->set.max_iters;
+    int used = SPOCK_FP64;
+    int refined = 0;
+    long long taken = 0;
+    if (prec == SPOCK_FP64) {
+        r = move_iterate(p, SPOCK_FP64);
+        if (!r && !(it > 0 && rel <= p->set.eps)) r = iterate<double>(p, budget - it, &taken, &rel, &x1, &x2, false);
+        it += taken;
+    } else {
+        r = move_iterate(p, SPOCK_FP32);
+        if (r) return r;
+        r = iterate<float>(p, budget - it, &taken, &rel, &x1, &x2, prec == SPOCK_MIXED);
+        it += taken;
+        it32 = taken;
+        used = SPOCK_FP32;
+        if (prec == SPOCK_MIXED && (r == SPOCK_OK || r == SPOCK_E_NOT_CONVERGED)) {
+            // float64 check of the float32 iterate; refine in float64 if needed
+            int32_t r2 = move_iterate(p, SPOCK_FP64);
+            if (r2) return r2;
+            used = SPOCK_FP64;
+            r2 = step<double>(p, 1);
+            if (!r2) r2 = read_res(p, &x1, &x2);
+            if (r2) return r2;
+            it += 1;
+            rel = std::max(x1, x2) / std::max(1.0, std::max(p->xi_ref[0], p->xi_ref[1]));
+            if (rel <= p->set.eps) {
+                r = SPOCK_OK;
+            } else if (it < budget) {
+                refined = 1;
+                r = iterate<double>(p, budget - it, &taken, &rel, &x1, &x2, false);
+                it += taken;
+            } else {
+                r = SPOCK_E_NOT_CONVERGED;
+            }
+        }
+    }
+    if (r != SPOCK_OK && r != SPOCK_E_NOT_CONVERGED && r != SPOCK_E_DIVERGED) return r;
+    p->solved = true;
+    inf.iters = it;
+    inf.iters_fp32 = it32;
+    inf.rel_res = rel;
+    inf.xi1_inf = x1;
+    inf.xi2_inf = x2;
+    double s0 = 0;
+    if (p->cur == SPOCK_FP64) {
+        HIP_TRY(hipMemcpyAsync(&s0, p->s64.h.z[p->s64.par], 8, hipMemcpyDeviceToHost, p->stream));
+    } else {
+        float f = 0;
+        HIP_TRY(hipMemcpyAsync(&f, p->s32.h.z[p->s32.par], 4, hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        s0 = f;
+    }
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    inf.s0 = s0;
+    inf.status = r;
+    inf.precision_used = used;
+    inf.refined = refined;
+    inf.t_solve_s = now_s() - t0;
+    if (info) *info = inf;
+    if (r == SPOCK_E_NOT_CONVERGED) return fail(r, "max_iters reached before the tolerance");
+    if (r == SPOCK_E_DIVERGED) return fail(r, "non-finite residual");
+    return SPOCK_OK;
+}
+
+// float64 copy of the current iterate on the host
+static int32_t fetch_iterate(const spock_problem* pc, std::vector<double>& z, std::vector<double>& e) {
+    spock_problem* p = const_cast<spock_problem*>(pc);
+    z.resize(p->nz);
+    e.resize(p->neta);
+    if (p->cur == SPOCK_FP64) {
+        HIP_TRY(hipMemcpyAsync(z.data(), p->s64.h.z[p->s64.par], p->nz * 8, hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(hipMemcpyAsync(e.data(), p->s64.h.eta[p->s64.par], p->neta * 8, hipMemcpyDeviceToHost, p->stream));
+    } else {
+        HIP_TRY(spk::launch_convert<double, float>(p->d_stash_z, p->s32.h.z[p->s32.par], p->nz, p->stream));
+        HIP_TRY(spk::launch_convert<double, float>(p->d_stash_e, p->s32.h.eta[p->s32.par], p->neta, p->stream));
+        HIP_TRY(hipMemcpyAsync(z.data(), p->d_stash_z, p->nz * 8, hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(hipMemcpyAsync(e.data(), p->d_stash_e, p->neta * 8, hipMemcpyDeviceToHost, p->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return SPOCK_OK;
+}
+
+int32_t spock_get_solution(const spock_problem* p, double* x, double* u, double* s0) {
+    if (!p) return fail(SPOCK_E_INVALID, "null handle");
+    std::vector<double> z, e;
+    int32_t r = fetch_iterate(p, z, e);
+    if (r) return r;
+    const int nx = p->nx, nu = p->nu;
+    if (x)
+        for (int j = 0; j < p->n; ++j) {
+            const std::vector<double>& S = j < p->n_nl ? p->Sx : p->SxN;
+            for (int k = 0; k < nx; ++k) x[(size_t)j * nx + k] = z[p->z_x + (size_t)j * nx + k] / S[k];
+        }
+    if (u)
+        for (int i = 0; i < p->n_nl; ++i)
+            for (int k = 0; k < nu; ++k) u[(size_t)i * nu + k] = z[p->z_u + (size_t)i * nu + k] / p->Su[k];
+    if (s0) *s0 = z[0];
+    return SPOCK_OK;
+}
+
+int32_t spock_get_iterate(const spock_problem* p, double* z, double* eta) {
+    if (!p) return fail(SPOCK_E_INVALID, "null handle");
+    std::vector<double> zz, ee;
+    int32_t r = fetch_iterate(p, zz, ee);
+    if (r) return r;
+    if (z) std::copy(zz.begin(), zz.end(), z);
+    if (eta) std::copy(ee.begin(), ee.end(), eta);
+    return SPOCK_OK;
+}
+
+// host float64 arrays -> copy 0 of the given precision
+static int32_t load_iterate(spock_problem* p, const double* z, const double* eta, int prec) {
+    if (!z || !eta) return fail(SPOCK_E_INVALID, "null iterate");
+    if (prec == SPOCK_FP64) {
+        HIP_TRY(hipMemcpyAsync(p->s64.h.z[0], z, p->nz * 8, hipMemcpyHostToDevice, p->stream));
+        HIP_TRY(hipMemcpyAsync(p->s64.h.eta[0], eta, p->neta * 8, hipMemcpyHostToDevice, p->stream));
+        p->s64.par = 0;
+        p->cur = SPOCK_FP64;
+    } else {
+        HIP_TRY(hipMemcpyAsync(p->d_stash_z, z, p->nz * 8, hipMemcpyHostToDevice, p->stream));
+        HIP_TRY(hipMemcpyAsync(p->d_stash_e, eta, p->neta * 8, hipMemcpyHostToDevice, p->stream));
+        HIP_TRY(spk::launch_convert<float, double>(p->s32.h.z[0], p->d_stash_z, p->nz, p->stream));
+        HIP_TRY(spk::launch_convert<float, double>(p->s32.h.eta[0], p->d_stash_e, p->neta, p->stream));
+        p->s32.par = 0;
+        p->cur = SPOCK_FP32;
+    }
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return SPOCK_OK;
+}
+
+int32_t spock_set_iterate(spock_problem* p, const double* z, const double* eta) {
+    if (!p) return fail(SPOCK_E_INVALID, "null handle");
+    return load_iterate(p, z, eta, SPOCK_FP64);
+}
+
+static int32_t check_prec(int32_t prec) {
+    if (prec != SPOCK_FP64 && prec != SPOCK_FP32) return fail(SPOCK_E_INVALID, "hooks take SPOCK_FP64 or SPOCK_FP32");
+    return SPOCK_OK;
+}
+
+int32_t spock_apply_T(spock_problem* p, const double* z, const double* eta, double* z_out, double* eta_out,
+                      int32_t prec, double* xi) {
+    if (!p) return fail(SPOCK_E_INVALID, "null handle");
+    int32_t r = check_prec(prec);
+    if (!r) r = load_iterate(p, z, eta, prec);
+    if (!r) r = prec == SPOCK_FP64 ? step<double>(p, 1) : step<float>(p, 1);
+    double a = 0, b = 0;
+    if (!r) r = read_res(p, &a, &b);
+    if (r) return r;
+    if (xi) {
+        xi[0] = a;
+        xi[1] = b;
+    }
+    std::vector<double> zz, ee;
+    r = fetch_iterate(p, zz, ee);
+    if (r) return r;
+    if (z_out) std::copy(zz.begin(), zz.end(), z_out);
+    if (eta_out) std::copy(ee.begin(), ee.end(), eta_out);
+    return SPOCK_OK;
+}
+
+extern "C++" {
+template <typename real>
+static int32_t hook(spock_problem* p, int which, const double* in, long long nin, double* out, long long nout) {
+    DevSet<real>& s = set_of<real>(p);
+    // input -> copy 0 (z or eta as needed), output -> the other buffer kind of copy 1
+    real* din = which == 0 ? s.h.z[0] : s.h.eta[0];
+    real* dout = which == 1 ? s.h.z[1] : s.h.eta[1];
+    HIP_TRY(hipMemcpyAsync(p->d_stash_z, in, nin * 8, hipMemcpyHostToDevice, p->stream));
+    if (sizeof(real) == 8) {
+        HIP_TRY(hipMemcpyAsync(din, p->d_stash_z, nin * 8, hipMemcpyDeviceToDevice, p->stream));
+    } else {
+        HIP_TRY(spk::launch_convert<float, double>((float*)din, p->d_stash_z, nin, p->stream));
+    }
+    HIP_TRY(spk::launch_fill<real>(dout, real(0), nout, p->stream));
+    if (which == 0) HIP_TRY(spk::launch_apply_L<real>(s.d, p->n, din, dout, p->stream));
+    if (which == 1) HIP_TRY(spk::launch_apply_Lt<real>(s.d, p->n, din, dout, p->stream));
+    if (which == 2) HIP_TRY(spk::launch_prox_gconj<real>(s.d, p->n, din, dout, p->stream));
+    if (sizeof(real) == 8) {
+        HIP_TRY(hipMemcpyAsync(out, dout, nout * 8, hipMemcpyDeviceToHost, p->stream));
+    } else {
+        HIP_TRY(spk::launch_convert<double, float>(p->d_stash_e, (const float*)dout, nout, p->stream));
+        HIP_TRY(hipMemcpyAsync(out, p->d_stash_e, nout * 8, hipMemcpyDeviceToHost, p->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return SPOCK_OK;
+}
+}  // extern "C++"
+
+
+int32_t spock_apply_L(spock_problem* p, const double* z, double* eta_out, int32_t prec) {
+    if (!p || !z || !eta_out) return fail(SPOCK_E_INVALID, "null argument");
+    int32_t r = check_prec(prec);
+    if (r) return r;
+    return prec == SPOCK_FP64 ? hook<double>(p, 0, z, p->nz, eta_out, p->neta)
+                              : hook<float>(p, 0, z, p->nz, eta_out, p->neta);
+}
+
+int32_t spock_apply_Lt(spock_problem* p, const double* eta, double* z_out, int32_t prec) {
+    if (!p || !eta || !z_out) return fail(SPOCK_E_INVALID, "null argument");
+    int32_t r = check_prec(prec);
+    if (r) return r;
+    return prec == SPOCK_FP64 ? hook<double>(p, 1, eta, p->neta, z_out, p->nz)
+                              : hook<float>(p, 1, eta, p->neta, z_out, p->nz);
+}
+
+int32_t spock_prox_gconj(spock_problem* p, const double* w, double* eta_out, int32_t prec) {
+    if (!p || !w || !eta_out) return fail(SPOCK_E_INVALID, "null argument");
+    int32_t r = check_prec(prec);
+    if (r) return r;
+    return prec == SPOCK_FP64 ? hook<double>(p, 2, w, p->neta, eta_out, p->neta)
+                              : hook<float>(p, 2, w, p->neta, eta_out, p->neta);
+}
+
+extern "C++" {
+template <typename real>
+static int32_t time_steps(spock_problem* p, int steps, double* ms_total, double* ms_b, double* ms_f) {
+    DevSet<real>& s = set_of<real>(p);
+    std::vector<hipEvent_t> ev(2 * (size_t)steps + 1);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    HIP_TRY(hipEventRecord(ev[0], p->stream));
+    for (int k = 0; k < steps; ++k) {
+        HIP_TRY(spk::launch_backward<real>(s.d, p->d_tasks, p->n_leaf, s.lds_bytes, s.par, 0, p->stream));
+        HIP_TRY(hipEventRecord(ev[2 * k + 1], p->stream));
+        HIP_TRY(spk::launch_forward<real>(s.d, p->d_tasks, p->n_leaf, s.lds_bytes, s.par, 0, p->stream));
+        HIP_TRY(hipEventRecord(ev[2 * k + 2], p->stream));
+        s.par ^= 1;
+    }
+    HIP_TRY(hipEventSynchronize(ev.back()));
+    double tb = 0, tf = 0;
+    for (int k = 0; k < steps; ++k) {
+        float a = 0, b = 0;
+        HIP_TRY(hipEventElapsedTime(&a, ev[2 * k], ev[2 * k + 1]));
+        HIP_TRY(hipEventElapsedTime(&b, ev[2 * k + 1], ev[2 * k + 2]));
+        tb += a;
+        tf += b;
+    }
+    float tot = 0;
+    HIP_TRY(hipEventElapsedTime(&tot, ev[0], ev.back()));
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (ms_total) *ms_total = tot / steps;
+    if (ms_b) *ms_b = tb / steps;
+    if (ms_f) *ms_f = tf / steps;
+    int zero = 0;
+    int err = 0;
+    HIP_TRY(hipMemcpy(&err, p->d_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (err) {
+        (void)hipMemcpy(p->d_err, &zero, sizeof(int), hipMemcpyHostToDevice);
+        return fail(SPOCK_E_HIP, "device wait timeout in the forward sweep");
+    }
+    return SPOCK_OK;
+}
+}  // extern "C++"
+
+
+int32_t spock_time_steps(spock_problem* p, int32_t prec, int32_t steps, double* ms_total, double* ms_b,
+                         double* ms_f) {
+    if (!p || steps < 1) return fail(SPOCK_E_INVALID, "bad argument");
+    int32_t r = check_prec(prec);
+    if (r) return r;
+    r = move_iterate(p, prec);
+    if (r) return r;
+    return prec == SPOCK_FP64 ? time_steps<double>(p, steps, ms_total, ms_b, ms_f)
+                              : time_steps<float>(p, steps, ms_total, ms_b, ms_f);
+}
+
+int32_t spock_step_bytes(const spock_problem* p, int32_t prec, double* bb, double* bf) {
+    if (!p) return fail(SPOCK_E_INVALID, "null handle");
+    const double w = prec == SPOCK_FP64 ? 8.0 : 4.0;
+    const double n = p->n, nl = p->n_nl, nx = p->nx, nu = p->nu, m = p->m;
+    const double nz = (double)p->nz, neta = (double)p->neta;
+    const double s2 = (double)p->ny + 2.0 * (n - 1) + 1.0;  // y, tau, s, s0
+    // backward: [Abar|B]^T per edge, [K|R~^-1] per non-leaf, read z and eta,
+    // write the S2 block and d
+    const double b = (n - 1) * nx * m + nl * nu * m + nz + neta + s2 + nl * nu;
+    // forward: [Abar|B] per edge, K per non-leaf, read old z, new S2 block, d and
+    // eta, write x, u and eta
+    const double f = (n - 1) * nx * m + nl * nu * nx + nz + s2 + nl * nu + neta + (n * nx + nl * nu) + neta;
+    if (bb) *bb = w * b;
+    if (bf) *bf = w * f;
+    return SPOCK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,957 @@
+// gfx950 kernels of one Chambolle-Pock (CP) step of SPOCK on a scenario tree.
+//
+// One CP step (Sec. 4.1) is two launches over the tree:
+//
+//  backward  leaves -> root.  Per node: zbar = z - alpha L* eta for the node's
+//            (x, u) (adjoint of L, Sec. 4.4), the backward recursion of Alg. 2
+//            in reduced form, the S2 projection of the node's (y, tau, s) block
+//            (Sec. 4.3) and, at the root, the prox of s0.  One workgroup starts
+//            at every leaf and walks up; at a node with several children only
+//            the last child to arrive continues (atomic arrival counter), so no
+//            workgroup ever waits and the launch cannot deadlock.
+//
+//  forward   root -> leaves.  Per node: x^j = [Abar^j | B^j] [x^i; d^i] + c^j,
+//            u^j = K^j x^j + d^j (Alg. 2 forward), then every dual block the
+//            node owns: eta+ = prox_{alpha g*}(eta + alpha L(2 z+ - z)) with the
+//            S3 cone projections and Moreau's identity, and on request the
+//            residuals xi1, xi2 of Sec. 5.3.  One workgroup per leaf walks its
+//            root-to-leaf path; the first workgroup to reach a node claims and
+//            computes it, the others wait on its done flag.  A workgroup only
+//            waits on a node claimed by a running workgroup whose own inputs
+//            are already complete, so the wait always ends; a bounded spin
+//            turns an unexpected stall into an error flag instead of a hang.
+//
+// Reduced S1 recursion (algebraically equal to Alg. 2, using
+// sum_j Abar^jT P^j B^j = -K^iT, which follows from the definition of K in
+// Alg. 1):  with h^j = q^j + P^j c^j and g = sum_{j in ch(i)} [Abar^j|B^j]^T h^j,
+//   q^i = -xbar^i - K^iT ubar^i + g_x,   d^i = R~^i^-1 (ubar^i - g_u),
+// and forward u^i = K^i x^i + d^i, x^j = Abar^j x^i + B^j d^i + c^j.
+// Only [Abar|B] per edge and [K | R~^-1] per non-leaf node are read online.
+//
+// Every matrix is a contiguous row-major block per node, read once per
+// kernel with coalesced loads straight into registers (no LDS staging): the
+// transposed product (backward) maps consecutive lanes to consecutive columns;
+// the plain product (forward) maps a power-of-two lane segment to a row and
+// reduces it with cross-lane shuffles.  LDS only holds node vectors.
+
+#include <hip/hip_runtime.h>
+
+#include "spock_dev.h"
+
+namespace spk {
+
+#define SPK_DEV __device__ __forceinline__
+
+// ---------------------------------------------------------------------------
+// workgroup helpers
+// ---------------------------------------------------------------------------
+
+template <typename T>
+SPK_DEV T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T>
+SPK_DEV T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// Sum over the workgroup, same value returned to every thread; deterministic.
+template <typename T>
+SPK_DEV T block_sum(T v, T* red) {
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < kWG / 64; ++k) s += red[k];
+    return s;
+}
+
+template <typename T>
+SPK_DEV T block_max(T v, T* red) {
+    v = wave_max(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T s = red[0];
+#pragma unroll
+    for (int k = 1; k < kWG / 64; ++k) s = red[k] > s ? red[k] : s;
+    return s;
+}
+
+// out[c] = sum_r A[r*ld + c] * (c < split ? va[r] : vb[r]),  r < R, c < C.
+// A in global memory, vectors and out in LDS.  Threads (g, c): lanes run along
+// the columns of a row, so each load instruction covers a contiguous row
+// segment; G row groups split the rows and are summed through LDS.
+template <typename real>
+SPK_DEV void mat_t_vec(const real* __restrict__ A, int R, int C, long long ld, int split,
+                       const real* va, const real* vb, real* out, real* red) {
+    const int t = threadIdx.x;
+    for (int c0 = 0; c0 < C; c0 += kWG) {
+        const int Cc = (C - c0) < kWG ? (C - c0) : kWG;
+        const int G = kWG / Cc;
+        const int g = t / Cc, c = t - g * Cc;
+        real acc = 0;
+        if (g < G) {
+            const real* v = (c0 + c < split) ? va : vb;
+            const real* a = A + c0 + c;
+#pragma unroll 4
+            for (int r = g; r < R; r += G) acc += a[(long long)r * ld] * v[r];
+        }
+        __syncthreads();
+        red[t] = acc;
+        __syncthreads();
+        if (t < Cc) {
+            real s = 0;
+            for (int k = 0; k < G; ++k) s += red[k * Cc + t];
+            out[c0 + t] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// out[r] = sum_c A[r*ld + c] * v[c],  r < R, c < C.  A power-of-two segment of
+// W lanes (W <= 64) owns a row: lanes stride the row, then reduce by xor
+// shuffles inside the segment.
+template <typename real>
+SPK_DEV void mat_vec(const real* __restrict__ A, int R, int C, long long ld, const real* v,
+                     real* out) {
+    int W = 1;
+    while (W < C && W < 64) W <<= 1;
+    const int t = threadIdx.x;
+    const int nseg = kWG / W;
+    const int seg = t / W, k = t - seg * W;
+    for (int r0 = 0; r0 < R; r0 += nseg) {
+        const int r = r0 + seg;
+        real acc = 0;
+        if (r < R) {
+            const real* a = A + (long long)r * ld;
+#pragma unroll 4
+            for (int c = k; c < C; c += W) acc += a[c] * v[c];
+        }
+        for (int o = W >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, W);
+        if (k == 0 && r < R) out[r] = acc;
+    }
+    __syncthreads();
+}
+
+// Wait until a node's forward result is published; false on timeout.
+SPK_DEV bool wait_done(int* flag) {
+    const uint64_t t0 = wall_clock64();
+    unsigned spins = 0;
+    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 2) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 1023u) == 0 && wall_clock64() - t0 > 200000000ull) return false;  // ~2 s
+    }
+    return true;
+}
+
+template <typename real>
+SPK_DEV void record_max(unsigned long long* slot, real v) {
+    const double d = (double)v;
+    atomicMax(slot, (unsigned long long)__double_as_longlong(d));
+}
+
+// ---------------------------------------------------------------------------
+// backward sweep
+// ---------------------------------------------------------------------------
+
+// S2 projection (Sec. 4.3) of node i's block (y^i, tau^[i], s^[i]) after the
+// z - alpha L* eta shift, written to zout.  Kernel of G = [E^T, -I, -I] with
+// E = [gamma I; -I; 1^T] (AV@R, Sec. 3.3).  G G^T = (gamma^2 + 3) I + 1 1^T, so
+// with rho = G w the multiplier is lambda = (rho - (1^T rho / (c + n)) 1) / c,
+// c = gamma^2 + 3 (Sherman-Morrison), and w - G^T lambda is the projection.
+template <typename real>
+SPK_DEV void s2_block(const ProbDev<real>* __restrict__ P, int i, const real* __restrict__ zin,
+                      const real* __restrict__ ein, real* __restrict__ zout, real* s2, real* red) {
+    const int t = threadIdx.x;
+    const int k = P->n_ch[i], fc = P->first_child[i];
+    const int nx = P->nx, m = P->m;
+    const real alpha = P->alpha, gam = P->gamma[i];
+    const long long yo = P->y_off[i];
+    const real es = ein[P->e_s + i];
+    real* yb1 = s2;
+    real* yb2 = s2 + P->max_ch;
+    real* tb = s2 + 2 * P->max_ch;
+    real* sb = s2 + 3 * P->max_ch;
+    real* lam = s2 + 4 * P->max_ch;
+    const real yb3 = zin[P->z_y + yo + 2 * k] - alpha * (ein[P->e_y + yo + 2 * k] - es);
+    const real cc = gam * gam + real(3);
+    real rsum = 0;
+    for (int c = t; c < k; c += kWG) {
+        const int j = fc + c;
+        const real p = P->prob[j];
+        yb1[c] = zin[P->z_y + yo + c] - alpha * (ein[P->e_y + yo + c] - p * es);
+        yb2[c] = zin[P->z_y + yo + k + c] - alpha * ein[P->e_y + yo + k + c];
+        const real* es_soc = ein + P->e_soc + (long long)(j - 1) * (m + 2);
+        tb[c] = zin[P->z_tau + j - 1] - alpha * real(0.5) * (es_soc[m] + es_soc[m + 1]);
+        real lts;
+        if (j < P->n_nl) {
+            lts = ein[P->e_s + j];
+        } else {
+            const real* esN = ein + P->e_socN + (long long)(j - P->n_nl) * (nx + 2);
+            lts = real(0.5) * (esN[nx] + esN[nx + 1]);
+        }
+        sb[c] = zin[P->z_s + j - 1] - alpha * lts;
+        const real rho = gam * yb1[c] - yb2[c] + yb3 - tb[c] - sb[c];
+        lam[c] = rho;
+        rsum += rho;
+    }
+    rsum = block_sum(rsum, red);
+    real lsum = 0;
+    for (int c = t; c < k; c += kWG) {
+        const real l = (lam[c] - rsum / (cc + real(k))) / cc;
+        lsum += l;
+        const int j = fc + c;
+        zout[P->z_y + yo + c] = yb1[c] - gam * l;
+        zout[P->z_y + yo + k + c] = yb2[c] + l;
+        zout[P->z_tau + j - 1] = tb[c] + l;
+        zout[P->z_s + j - 1] = sb[c] + l;
+    }
+    lsum = block_sum(lsum, red);
+    if (t == 0) zout[P->z_y + yo + 2 * k] = yb3 - lsum;
+}
+
+template <typename real>
+__global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restrict__ probs,
+                                                  const int2* __restrict__ tasks, int par, int check) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_last;
+    real* sm = reinterpret_cast<real*>(smem_raw);
+    const int2 tk = tasks[blockIdx.x];
+    const ProbDev<real>* __restrict__ P = probs + tk.x;
+    const int nx = P->nx, nu = P->nu, m = P->m;
+    const real alpha = P->alpha;
+    const real* __restrict__ zin = P->z[par];
+    const real* __restrict__ ein = P->eta[par];
+    real* __restrict__ zout = P->z[par ^ 1];
+    const int t = threadIdx.x;
+
+    real* red = sm;
+    real* xb = red + kWG;   // xbar, then h = q + P c
+    real* ub = xb + nx;     // ubar
+    real* g = ub + nu;      // sum of children messages
+    real* w2 = g + m;       // ubar - g_u
+    real* o = w2 + nu;      // product outputs
+    real* s2 = o + m;       // S2 scratch, 5 * max_ch
+
+    // ---- leaf: q = -xbar, message [Abar|B]^T (q + P c) ----
+    int j = P->n_nl + tk.y;
+    {
+        const long long lf = j - P->n_nl;
+        const real* ecN = ein + P->e_cN + lf * P->ncN;
+        const real* esN = ein + P->e_socN + lf * (nx + 2);
+        for (int k = t; k < nx; k += kWG) {
+            real lt = P->gxN[k] * ecN[k] + P->qnh[k] * esN[k];
+            if (P->has_ballN) lt += P->gbN[k] * ecN[nx + k];
+            real h = -(zin[P->z_x + (long long)j * nx + k] - alpha * lt);
+            if (P->affine) h += P->Pc[(long long)j * nx + k];
+            xb[k] = h;
+        }
+        if (t == 0) P->flag[j] = 0;
+        __syncthreads();
+        mat_t_vec(P->M + j * P->M_stride, nx, m, m, m, xb, xb, o, red);
+    }
+
+    // ---- walk up ----
+    for (;;) {
+        const int i = P->parent[j];
+        const int k = P->n_ch[i], fc = P->first_child[i];
+        if (k > 1) {
+            for (int c = t; c < m; c += kWG) P->e[(long long)j * m + c] = o[c];
+            // every wave makes its own stores visible device-wide before the
+            // arrival is counted (a barrier alone does not wait for them)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (t == 0) {
+                const int prev =
+                    __hip_atomic_fetch_add(&P->cnt[i], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                const int last = (prev == k - 1);
+                if (last) P->cnt[i] = 0;  // the next launch reuses the counter
+                s_last = last;
+            }
+            __syncthreads();
+            if (!s_last) return;
+            for (int c = t; c < m; c += kWG) {
+                real s = 0;
+                for (int q = 0; q < k; ++q) s += P->e[(long long)(fc + q) * m + c];
+                g[c] = s;
+            }
+        } else {
+            for (int c = t; c < m; c += kWG) g[c] = o[c];
+        }
+
+        // zbar for (x^i, u^i): L* gathers the constraint rows and the SOC rows of
+        // every child edge (Sec. 4.4)
+        const real* ec = ein + P->e_c + (long long)i * P->nc;
+        for (int r = t; r < nx; r += kWG) {
+            real s = 0;
+            for (int q = 0; q < k; ++q) s += ein[P->e_soc + (long long)(fc + q - 1) * (m + 2) + r];
+            real lt = P->gx[r] * ec[r] + P->qh[r] * s;
+            if (P->has_ball) lt += P->gb[r] * ec[P->nbox + r];
+            xb[r] = zin[P->z_x + (long long)i * nx + r] - alpha * lt;
+        }
+        for (int r = t; r < nu; r += kWG) {
+            real s = 0;
+            for (int q = 0; q < k; ++q) s += ein[P->e_soc + (long long)(fc + q - 1) * (m + 2) + nx + r];
+            const real lt = P->gu[r] * ec[nx + r] + P->rh[r] * s;
+            const real u = zin[P->z_u + (long long)i * nu + r] - alpha * lt;
+            ub[r] = u;
+            w2[r] = u - g[nx + r];
+        }
+        if (t == 0) P->flag[i] = 0;
+        __syncthreads();
+        // [K^T ubar ; R~^-1 (ubar - g_u)] in one pass over [K | R~^-1]
+        mat_t_vec(P->KR + i * P->KR_stride, nu, m, m, nx, ub, w2, o, red);
+        for (int r = t; r < nx; r += kWG) {
+            real h = -xb[r] - o[r] + g[r];
+            if (P->affine && i > 0) h += P->Pc[(long long)i * nx + r];
+            xb[r] = h;
+        }
+        for (int r = t; r < nu; r += kWG) P->d[(long long)i * nu + r] = o[nx + r];
+        s2_block(P, i, zin, ein, zout, s2, red);  // ends with a barrier
+
+        if (i == 0) {
+            if (t == 0) {
+                zout[0] = zin[0] - alpha * ein[P->e_s] - alpha;  // prox of alpha * s0
+                if (check) {
+                    P->res[0] = 0ull;
+                    P->res[1] = 0ull;
+                }
+            }
+            return;
+        }
+        mat_t_vec(P->M + i * P->M_stride, nx, m, m, m, xb, xb, o, red);
+        j = i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward sweep
+// ---------------------------------------------------------------------------
+
+// eta+ = prox_{alpha g*}(etabar) for a box row: etabar - clamp(etabar, alpha lo, alpha hi)
+template <typename real>
+SPK_DEV real moreau_box(real eb, real alpha, real lo, real hi) {
+    real p = eb < alpha * lo ? alpha * lo : eb;
+    p = p > alpha * hi ? alpha * hi : p;
+    return eb - p;
+}
+
+// Translated SOC (Prop. 1 with q = 0, a = (0,..,0, 1/2, -1/2), scalar last):
+// with v = etabar - alpha a, eta+ = v - proj_SOC(v).  `nw2` is ||v_w||^2 over
+// all entries but the last, `vt` the last entry.  Returns the factor applied
+// to the w part and the value of the t entry.
+template <typename real>
+SPK_DEV void soc_moreau_coef(real nw2, real vt, real& cw, real& ct) {
+    const real nw = sqrt(nw2);
+    if (nw <= vt) {  // inside: proj = v, eta+ = 0
+        cw = 0;
+        ct = 0;
+    } else if (nw <= -vt) {  // polar: proj = 0, eta+ = v
+        cw = 1;
+        ct = vt;
+    } else {
+        const real a = real(0.5) * (nw + vt);
+        cw = real(1) - a / nw;
+        ct = vt - a;
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict__ probs,
+                                                 const int2* __restrict__ tasks, int par, int check) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_path[kMaxDepth];
+    __shared__ int s_claim;
+    real* sm = reinterpret_cast<real*>(smem_raw);
+    const int2 tk = tasks[blockIdx.x];
+    const ProbDev<real>* __restrict__ P = probs + tk.x;
+    const int nx = P->nx, nu = P->nu, m = P->m, nbox = P->nbox;
+    const real alpha = P->alpha, ialpha = real(1) / P->alpha;
+    const real* __restrict__ zin = P->z[par];
+    const real* __restrict__ ein = P->eta[par];
+    real* __restrict__ zout = P->z[par ^ 1];
+    real* __restrict__ eout = P->eta[par ^ 1];
+    const int t = threadIdx.x;
+
+    real* red = sm;
+    real* xa = red + kWG;   // [x^anc ; d^anc]
+    real* xn = xa + m;      // x+ of the node
+    real* un = xn + nx;     // u+
+    real* xo = un + nu;     // x of the previous iterate
+    real* uo = xo + nx;
+    real* lx = uo + nu;     // (L* d_eta) rows of x
+    real* lu = lx + nx;     // (L* d_eta) rows of u
+    const int bmax = blk_elems(nx, nu, P->max_ch);
+    real* blk = lu + nu;    // etabar of the current block
+    real* dblk = blk + bmax;  // eta - eta+ of the current block (residuals)
+
+    if (t == 0) {
+        int v = P->n_nl + tk.y;
+        int lev = P->N;
+        while (v >= 0) {
+            s_path[lev--] = v;
+            v = P->parent[v];
+        }
+    }
+    __syncthreads();
+
+    real r1 = 0, r2 = 0;  // residual maxima of this thread
+    for (int lev = 0; lev <= P->N; ++lev) {
+        const int v = s_path[lev];
+        __syncthreads();  // every thread has read the previous s_claim
+        if (t == 0) {
+            int expected = 0;
+            int claim = __hip_atomic_compare_exchange_strong(&P->flag[v], &expected, 1, __ATOMIC_RELAXED,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            ? 1
+                            : 0;
+            if (!claim && !wait_done(&P->flag[v])) {
+                atomicExch(P->err, 1);
+                claim = -1;
+            }
+            s_claim = claim;
+        }
+        __syncthreads();
+        const int claim = s_claim;
+        if (claim < 0) return;
+        if (claim == 0) continue;
+
+        // ---- state: x^v = [Abar|B] [x^anc; d^anc] + c ----
+        if (v == 0) {
+            for (int r = t; r < nx; r += kWG) xn[r] = P->x0[r];
+            __syncthreads();
+        } else {
+            const int i = P->parent[v];
+            for (int r = t; r < nx; r += kWG) xa[r] = zout[P->z_x + (long long)i * nx + r];
+            for (int r = t; r < nu; r += kWG) xa[nx + r] = P->d[(long long)i * nu + r];
+            __syncthreads();
+            mat_vec(P->M + v * P->M_stride, nx, m, m, xa, xn);
+            if (P->affine) {
+                for (int r = t; r < nx; r += kWG) xn[r] += P->c[(long long)v * nx + r];
+                __syncthreads();
+            }
+        }
+        for (int r = t; r < nx; r += kWG) {
+            zout[P->z_x + (long long)v * nx + r] = xn[r];
+            xo[r] = zin[P->z_x + (long long)v * nx + r];
+            lx[r] = 0;
+        }
+
+        if (v < P->n_nl) {
+            // ---- input: u^v = K^v x^v + d^v ----
+            mat_vec(P->KR + v * P->KR_stride, nu, nx, m, xn, un);
+            for (int r = t; r < nu; r += kWG) {
+                const real u = un[r] + P->d[(long long)v * nu + r];
+                un[r] = u;
+                zout[P->z_u + (long long)v * nu + r] = u;
+                uo[r] = zin[P->z_u + (long long)v * nu + r];
+                lu[r] = 0;
+            }
+            __syncthreads();
+
+            // ---- constraint block eta_c: C^i = box x ball ----
+            {
+                const long long off = P->e_c + (long long)v * P->nc;
+                real nb2 = 0;
+                for (int r = t; r < P->nc; r += kWG) {
+                    real wn, wo;
+                    if (r < nx) {
+                        wn = P->gx[r] * xn[r];
+                        wo = P->gx[r] * xo[r];
+                    } else if (r < nbox) {
+                        wn = P->gu[r - nx] * un[r - nx];
+                        wo = P->gu[r - nx] * uo[r - nx];
+                    } else {
+                        wn = P->gb[r - nbox] * xn[r - nbox];
+                        wo = P->gb[r - nbox] * xo[r - nbox];
+                    }
+                    const real eb = ein[off + r] + alpha * (real(2) * wn - wo);
+                    blk[r] = eb;
+                    dblk[r] = wo - wn;  // L dz for this row
+                    if (r >= nbox) nb2 += eb * eb;
+                }
+                real cb = 0;
+                if (P->has_ball) {
+                    nb2 = block_sum(nb2, red);
+                    const real nrm = sqrt(nb2);
+                    const real rad = alpha * P->ball_r;
+                    cb = nrm > rad ? real(1) - rad / nrm : real(0);
+                }
+                for (int r = t; r < P->nc; r += kWG) {
+                    const real eb = blk[r];
+                    const real ep = r < nbox ? moreau_box(eb, alpha, P->lo[r], P->hi[r]) : eb * cb;
+                    eout[off + r] = ep;
+                    const real de = ein[off + r] - ep;
+                    if (check) r2 = fmax(r2, fabs(de * ialpha - dblk[r]));
+                    dblk[r] = de;
+                }
+                __syncthreads();
+                if (check) {
+                    for (int r = t; r < nx; r += kWG) {
+                        real s = P->gx[r] * dblk[r];
+                        if (P->has_ball) s += P->gb[r] * dblk[nbox + r];
+                        lx[r] += s;
+                    }
+                    for (int r = t; r < nu; r += kWG) lu[r] += P->gu[r] * dblk[nx + r];
+                }
+            }
+
+            // ---- risk blocks eta_y (in (K^i)* = R^{2k}_+ x R) and eta_s (in R_+) ----
+            {
+                const int k = P->n_ch[v], fc = P->first_child[v];
+                const long long yo = P->y_off[v];
+                const real* yn = zout + P->z_y + yo;
+                const real* yv = zin + P->z_y + yo;
+                const long long soff = (v == 0) ? 0 : P->z_s + v - 1;
+                const real sn = zout[soff], sv = zin[soff];
+                // b^T y with b = (p, 0, 1)
+                real bn = 0, bo = 0;
+                for (int c = t; c < k; c += kWG) {
+                    const real p = P->prob[fc + c];
+                    bn += p * yn[c];
+                    bo += p * yv[c];
+                }
+                bn = block_sum(bn, red);
+                bo = block_sum(bo, red);
+                bn += yn[2 * k];
+                bo += yv[2 * k];
+                const real wsn = sn - bn, wso = sv - bo;
+                const real ebs = ein[P->e_s + v] + alpha * (real(2) * wsn - wso);
+                const real eps_ = ebs < 0 ? ebs : real(0);
+                const real des = ein[P->e_s + v] - eps_;
+                if (t == 0) eout[P->e_s + v] = eps_;
+                for (int c = t; c < 2 * k + 1; c += kWG) {
+                    const real eb = ein[P->e_y + yo + c] + alpha * (real(2) * yn[c] - yv[c]);
+                    const real ep = c < 2 * k ? (eb < 0 ? eb : real(0)) : real(0);
+                    eout[P->e_y + yo + c] = ep;
+                    if (check) {
+                        const real de = ein[P->e_y + yo + c] - ep;
+                        const real dy = yv[c] - yn[c];
+                        r2 = fmax(r2, fabs(de * ialpha - dy));
+                        const real bc = c < k ? P->prob[fc + c] : (c == 2 * k ? real(1) : real(0));
+                        r1 = fmax(r1, fabs(dy * ialpha - (de - bc * des)));
+                    }
+                }
+                if (check && t == 0) {
+                    r2 = fmax(r2, fabs(des * ialpha - (wso - wsn)));
+                    r1 = fmax(r1, fabs((sv - sn) * ialpha - des));
+                }
+            }
+
+            // ---- SOC block of every child edge: (Q^1/2 x, R^1/2 u, tau/2, tau/2) ----
+            {
+                const int k = P->n_ch[v], fc = P->first_child[v];
+                for (int q = 0; q < k; ++q) {
+                    const int j = fc + q;
+                    const long long off = P->e_soc + (long long)(j - 1) * (m + 2);
+                    const real tn = zout[P->z_tau + j - 1], tv = zin[P->z_tau + j - 1];
+                    real nw2 = 0;
+                    for (int r = t; r < m + 2; r += kWG) {
+                        real wn, wo;
+                        if (r < nx) {
+                            wn = P->qh[r] * xn[r];
+                            wo = P->qh[r] * xo[r];
+                        } else if (r < m) {
+                            wn = P->rh[r - nx] * un[r - nx];
+                            wo = P->rh[r - nx] * uo[r - nx];
+                        } else {
+                            wn = real(0.5) * tn;
+                            wo = real(0.5) * tv;
+                        }
+                        real eb = ein[off + r] + alpha * (real(2) * wn - wo);
+                        if (r == m) eb -= real(0.5) * alpha;       // v = etabar - alpha a
+                        if (r == m + 1) eb += real(0.5) * alpha;
+                        blk[r] = eb;
+                        dblk[r] = wo - wn;
+                        if (r <= m) nw2 += eb * eb;
+                    }
+                    nw2 = block_sum(nw2, red);
+                    real cw, ct;
+                    soc_moreau_coef(nw2, blk[m + 1], cw, ct);
+                    for (int r = t; r < m + 2; r += kWG) {
+                        const real ep = r <= m ? blk[r] * cw : ct;
+                        eout[off + r] = ep;
+                        const real de = ein[off + r] - ep;
+                        if (check) r2 = fmax(r2, fabs(de * ialpha - dblk[r]));
+                        dblk[r] = de;
+                    }
+                    __syncthreads();
+                    if (check) {
+                        for (int r = t; r < nx; r += kWG) lx[r] += P->qh[r] * dblk[r];
+                        for (int r = t; r < nu; r += kWG) lu[r] += P->rh[r] * dblk[nx + r];
+                        if (t == 0)
+                            r1 = fmax(r1, fabs((tv - tn) * ialpha - real(0.5) * (dblk[m] + dblk[m + 1])));
+                    }
+                    __syncthreads();
+                }
+            }
+            if (check) {
+                for (int r = t; r < nx; r += kWG) r1 = fmax(r1, fabs((xo[r] - xn[r]) * ialpha - lx[r]));
+                for (int r = t; r < nu; r += kWG) r1 = fmax(r1, fabs((uo[r] - un[r]) * ialpha - lu[r]));
+            }
+        } else {
+            // ---- leaf: eta_cN in C_N (box x ball), eta_socN in SOC + a_N ----
+            __syncthreads();
+            const long long lf = v - P->n_nl;
+            {
+                const long long off = P->e_cN + lf * P->ncN;
+                real nb2 = 0;
+                for (int r = t; r < P->ncN; r += kWG) {
+                    real wn, wo;
+                    if (r < nx) {
+                        wn = P->gxN[r] * xn[r];
+                        wo = P->gxN[r] * xo[r];
+                    } else {
+                        wn = P->gbN[r - nx] * xn[r - nx];
+                        wo = P->gbN[r - nx] * xo[r - nx];
+                    }
+                    const real eb = ein[off + r] + alpha * (real(2) * wn - wo);
+                    blk[r] = eb;
+                    dblk[r] = wo - wn;
+                    if (r >= nx) nb2 += eb * eb;
+                }
+                real cb = 0;
+                if (P->has_ballN) {
+                    nb2 = block_sum(nb2, red);
+                    const real nrm = sqrt(nb2);
+                    const real rad = alpha * P->ballN_r;
+                    cb = nrm > rad ? real(1) - rad / nrm : real(0);
+                }
+                for (int r = t; r < P->ncN; r += kWG) {
+                    const real eb = blk[r];
+                    const real ep = r < nx ? moreau_box(eb, alpha, P->loN[r], P->hiN[r]) : eb * cb;
+                    eout[off + r] = ep;
+                    const real de = ein[off + r] - ep;
+                    if (check) r2 = fmax(r2, fabs(de * ialpha - dblk[r]));
+                    dblk[r] = de;
+                }
+                __syncthreads();
+                if (check) {
+                    for (int r = t; r < nx; r += kWG) {
+                        real s = P->gxN[r] * dblk[r];
+                        if (P->has_ballN) s += P->gbN[r] * dblk[nx + r];
+                        lx[r] += s;
+                    }
+                }
+                __syncthreads();
+            }
+            {
+                const long long off = P->e_socN + lf * (nx + 2);
+                const real sn = zout[P->z_s + v - 1], sv = zin[P->z_s + v - 1];
+                real nw2 = 0;
+                for (int r = t; r < nx + 2; r += kWG) {
+                    real wn, wo;
+                    if (r < nx) {
+                        wn = P->qnh[r] * xn[r];
+                        wo = P->qnh[r] * xo[r];
+                    } else {
+                        wn = real(0.5) * sn;
+                        wo = real(0.5) * sv;
+                    }
+                    real eb = ein[off + r] + alpha * (real(2) * wn - wo);
+                    if (r == nx) eb -= real(0.5) * alpha;
+                    if (r == nx + 1) eb += real(0.5) * alpha;
+                    blk[r] = eb;
+                    dblk[r] = wo - wn;
+                    if (r <= nx) nw2 += eb * eb;
+                }
+                nw2 = block_sum(nw2, red);
+                real cw, ct;
+                soc_moreau_coef(nw2, blk[nx + 1], cw, ct);
+                for (int r = t; r < nx + 2; r += kWG) {
+                    const real ep = r <= nx ? blk[r] * cw : ct;
+                    eout[off + r] = ep;
+                    const real de = ein[off + r] - ep;
+                    if (check) r2 = fmax(r2, fabs(de * ialpha - dblk[r]));
+                    dblk[r] = de;
+                }
+                __syncthreads();
+                if (check) {
+                    for (int r = t; r < nx; r += kWG) {
+                        lx[r] += P->qnh[r] * dblk[r];
+                        r1 = fmax(r1, fabs((xo[r] - xn[r]) * ialpha - lx[r]));
+                    }
+                    if (t == 0) r1 = fmax(r1, fabs((sv - sn) * ialpha - real(0.5) * (dblk[nx] + dblk[nx + 1])));
+                }
+            }
+        }
+
+        // publish the node: every wave releases its stores, then one flag store
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (t == 0) __hip_atomic_store(&P->flag[v], 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (check) {
+        r1 = block_max(r1, red);
+        r2 = block_max(r2, red);
+        if (t == 0) {
+            record_max(&P->res[0], r1);
+            record_max(&P->res[1], r2);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// operator hooks: one workgroup per node, plain code paths
+// ---------------------------------------------------------------------------
+
+// eta = L z for the blocks node v owns (Sec. 4.4).
+template <typename real>
+__global__ __launch_bounds__(kWG) void k_apply_L(const ProbDev<real>* __restrict__ P,
+                                                 const real* __restrict__ z, real* __restrict__ eta) {
+    __shared__ real red[kWG];
+    const int v = blockIdx.x, t = threadIdx.x;
+    const int nx = P->nx, nu = P->nu, m = P->m, nbox = P->nbox;
+    const real* x = z + P->z_x + (long long)v * nx;
+    if (v < P->n_nl) {
+        const real* u = z + P->z_u + (long long)v * nu;
+        for (int r = t; r < P->nc; r += kWG) {
+            real w;
+            if (r < nx) w = P->gx[r] * x[r];
+            else if (r < nbox) w = P->gu[r - nx] * u[r - nx];
+            else w = P->gb[r - nbox] * x[r - nbox];
+            eta[P->e_c + (long long)v * P->nc + r] = w;
+        }
+        const int k = P->n_ch[v], fc = P->first_child[v];
+        const long long yo = P->y_off[v];
+        const real* y = z + P->z_y + yo;
+        real b = 0;
+        for (int c = t; c < k; c += kWG) b += P->prob[fc + c] * y[c];
+        b = block_sum(b, red) + y[2 * k];
+        const real s = (v == 0) ? z[0] : z[P->z_s + v - 1];
+        if (t == 0) eta[P->e_s + v] = s - b;
+        for (int c = t; c < 2 * k + 1; c += kWG) eta[P->e_y + yo + c] = y[c];
+        for (int q = 0; q < k; ++q) {
+            const int j = fc + q;
+            const real tau = z[P->z_tau + j - 1];
+            real* o = eta + P->e_soc + (long long)(j - 1) * (m + 2);
+            for (int r = t; r < m + 2; r += kWG)
+                o[r] = r < nx ? P->qh[r] * x[r] : (r < m ? P->rh[r - nx] * u[r - nx] : real(0.5) * tau);
+        }
+    } else {
+        const long long lf = v - P->n_nl;
+        for (int r = t; r < P->ncN; r += kWG)
+            eta[P->e_cN + lf * P->ncN + r] = r < nx ? P->gxN[r] * x[r] : P->gbN[r - nx] * x[r - nx];
+        const real s = z[P->z_s + v - 1];
+        for (int r = t; r < nx + 2; r += kWG)
+            eta[P->e_socN + lf * (nx + 2) + r] = r < nx ? P->qnh[r] * x[r] : real(0.5) * s;
+    }
+}
+
+// z = L* eta for the primal entries node v owns (adjoint of k_apply_L).
+template <typename real>
+__global__ __launch_bounds__(kWG) void k_apply_Lt(const ProbDev<real>* __restrict__ P,
+                                                  const real* __restrict__ eta, real* __restrict__ z) {
+    const int v = blockIdx.x, t = threadIdx.x;
+    const int nx = P->nx, nu = P->nu, m = P->m, nbox = P->nbox;
+    real* x = z + P->z_x + (long long)v * nx;
+    if (v < P->n_nl) {
+        const int k = P->n_ch[v], fc = P->first_child[v];
+        const real* ec = eta + P->e_c + (long long)v * P->nc;
+        for (int r = t; r < nx; r += kWG) {
+            real s = 0;
+            for (int q = 0; q < k; ++q) s += eta[P->e_soc + (long long)(fc + q - 1) * (m + 2) + r];
+            real w = P->gx[r] * ec[r] + P->qh[r] * s;
+            if (P->has_ball) w += P->gb[r] * ec[nbox + r];
+            x[r] = w;
+        }
+        for (int r = t; r < nu; r += kWG) {
+            real s = 0;
+            for (int q = 0; q < k; ++q) s += eta[P->e_soc + (long long)(fc + q - 1) * (m + 2) + nx + r];
+            z[P->z_u + (long long)v * nu + r] = P->gu[r] * ec[nx + r] + P->rh[r] * s;
+        }
+        const long long yo = P->y_off[v];
+        const real es = eta[P->e_s + v];
+        for (int c = t; c < 2 * k + 1; c += kWG) {
+            const real bc = c < k ? P->prob[fc + c] : (c == 2 * k ? real(1) : real(0));
+            z[P->z_y + yo + c] = eta[P->e_y + yo + c] - bc * es;
+        }
+        if (t == 0) {
+            if (v == 0) z[0] = es;
+            else z[P->z_s + v - 1] = es;
+        }
+        for (int q = t; q < k; q += kWG) {
+            const int j = fc + q;
+            const real* o = eta + P->e_soc + (long long)(j - 1) * (m + 2);
+            z[P->z_tau + j - 1] = real(0.5) * (o[m] + o[m + 1]);
+        }
+    } else {
+        const long long lf = v - P->n_nl;
+        const real* ecN = eta + P->e_cN + lf * P->ncN;
+        const real* esN = eta + P->e_socN + lf * (nx + 2);
+        for (int r = t; r < nx; r += kWG) {
+            real w = P->gxN[r] * ecN[r] + P->qnh[r] * esN[r];
+            if (P->has_ballN) w += P->gbN[r] * ecN[nx + r];
+            x[r] = w;
+        }
+        if (t == 0) z[P->z_s + v - 1] = real(0.5) * (esN[nx] + esN[nx + 1]);
+    }
+}
+
+// eta = w - alpha proj_S3(w / alpha) for the blocks node v owns.
+template <typename real>
+__global__ __launch_bounds__(kWG) void k_prox_gconj(const ProbDev<real>* __restrict__ P,
+                                                    const real* __restrict__ w, real* __restrict__ eta) {
+    __shared__ real red[kWG];
+    const int v = blockIdx.x, t = threadIdx.x;
+    const int nx = P->nx, m = P->m, nbox = P->nbox;
+    const real alpha = P->alpha;
+    auto soc = [&](long long off, int len) {
+        real nw2 = 0;
+        for (int r = t; r < len - 1; r += kWG) {
+            real e = w[off + r];
+            if (r == len - 2) e -= real(0.5) * alpha;
+            nw2 += e * e;
+        }
+        nw2 = block_sum(nw2, red);
+        const real vt = w[off + len - 1] + real(0.5) * alpha;
+        real cw, ct;
+        soc_moreau_coef(nw2, vt, cw, ct);
+        for (int r = t; r < len; r += kWG) {
+            real e = w[off + r];
+            if (r == len - 2) e -= real(0.5) * alpha;
+            eta[off + r] = r < len - 1 ? e * cw : ct;
+        }
+    };
+    auto ballbox = [&](long long off, int nb, int ntot, const real* lo, const real* hi, real r_ball) {
+        real nb2 = 0;
+        for (int r = nb + t; r < ntot; r += kWG) nb2 += w[off + r] * w[off + r];
+        real cb = 0;
+        if (ntot > nb) {
+            nb2 = block_sum(nb2, red);
+            const real nrm = sqrt(nb2), rad = alpha * r_ball;
+            cb = nrm > rad ? real(1) - rad / nrm : real(0);
+        }
+        for (int r = t; r < ntot; r += kWG)
+            eta[off + r] = r < nb ? moreau_box(w[off + r], alpha, lo[r], hi[r]) : w[off + r] * cb;
+    };
+    if (v < P->n_nl) {
+        const int k = P->n_ch[v], fc = P->first_child[v];
+        const long long yo = P->y_off[v];
+        for (int c = t; c < 2 * k + 1; c += kWG) {
+            const real e = w[P->e_y + yo + c];
+            eta[P->e_y + yo + c] = c < 2 * k ? (e < 0 ? e : real(0)) : real(0);
+        }
+        if (t == 0) {
+            const real e = w[P->e_s + v];
+            eta[P->e_s + v] = e < 0 ? e : real(0);
+        }
+        ballbox(P->e_c + (long long)v * P->nc, nbox, P->nc, P->lo, P->hi, P->ball_r);
+        for (int q = 0; q < k; ++q) soc(P->e_soc + (long long)(fc + q - 1) * (m + 2), m + 2);
+    } else {
+        const long long lf = v - P->n_nl;
+        ballbox(P->e_cN + lf * P->ncN, nx, P->ncN, P->loN, P->hiN, P->ballN_r);
+        soc(P->e_socN + lf * (nx + 2), nx + 2);
+    }
+}
+
+// dst = (real) src over n entries (precision conversion of iterates)
+template <typename D, typename S>
+__global__ void k_convert(D* __restrict__ dst, const S* __restrict__ src, long long n) {
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x)
+        dst[k] = (D)src[k];
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ dst, T val, long long n) {
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x)
+        dst[k] = val;
+}
+
+// ---------------------------------------------------------------------------
+// launchers (host side)
+// ---------------------------------------------------------------------------
+
+template <typename real>
+hipError_t launch_step(const ProbDev<real>* probs, const int2* tasks, int n_tasks, int lds_bytes, int par,
+                       int check, hipStream_t st) {
+    hipLaunchKernelGGL(k_backward<real>, dim3(n_tasks), dim3(kWG), lds_bytes, st, probs, tasks, par, check);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_forward<real>, dim3(n_tasks), dim3(kWG), lds_bytes, st, probs, tasks, par, check);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_backward(const ProbDev<real>* probs, const int2* tasks, int n_tasks, int lds_bytes,
+                           int par, int check, hipStream_t st) {
+    hipLaunchKernelGGL(k_backward<real>, dim3(n_tasks), dim3(kWG), lds_bytes, st, probs, tasks, par, check);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_forward(const ProbDev<real>* probs, const int2* tasks, int n_tasks, int lds_bytes,
+                          int par, int check, hipStream_t st) {
+    hipLaunchKernelGGL(k_forward<real>, dim3(n_tasks), dim3(kWG), lds_bytes, st, probs, tasks, par, check);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_apply_L(const ProbDev<real>* P, int n, const real* z, real* eta, hipStream_t st) {
+    hipLaunchKernelGGL(k_apply_L<real>, dim3(n), dim3(kWG), 0, st, P, z, eta);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_apply_Lt(const ProbDev<real>* P, int n, const real* eta, real* z, hipStream_t st) {
+    hipLaunchKernelGGL(k_apply_Lt<real>, dim3(n), dim3(kWG), 0, st, P, eta, z);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_prox_gconj(const ProbDev<real>* P, int n, const real* w, real* eta, hipStream_t st) {
+    hipLaunchKernelGGL(k_prox_gconj<real>, dim3(n), dim3(kWG), 0, st, P, w, eta);
+    return hipGetLastError();
+}
+
+template <typename D, typename S>
+hipError_t launch_convert(D* dst, const S* src, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL((k_convert<D, S>), dim3((unsigned)blocks), dim3(256), 0, st, dst, src, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* dst, T val, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, st, dst, val, n);
+    return hipGetLastError();
+}
+
+#define SPK_INSTANTIATE(real)                                                                              \
+    template hipError_t launch_step<real>(const ProbDev<real>*, const int2*, int, int, int, int, hipStream_t); \
+    template hipError_t launch_backward<real>(const ProbDev<real>*, const int2*, int, int, int, int,         \
+                                              hipStream_t);                                                \
+    template hipError_t launch_forward<real>(const ProbDev<real>*, const int2*, int, int, int, int,          \
+                                             hipStream_t);                                                 \
+    template hipError_t launch_apply_L<real>(const ProbDev<real>*, int, const real*, real*, hipStream_t);   \
+    template hipError_t launch_apply_Lt<real>(const ProbDev<real>*, int, const real*, real*, hipStream_t);  \
+    template hipError_t launch_prox_gconj<real>(const ProbDev<real>*, int, const real*, real*, hipStream_t); \
+    template hipError_t launch_fill<real>(real*, real, long long, hipStream_t);
+
+SPK_INSTANTIATE(float)
+SPK_INSTANTIATE(double)
+template hipError_t launch_convert<float, double>(float*, const double*, long long, hipStream_t);
+template hipError_t launch_convert<double, float>(double*, const float*, long long, hipStream_t);
+template hipError_t launch_fill<int>(int*, int, long long, hipStream_t);
+template hipError_t launch_fill<unsigned long long>(unsigned long long*, unsigned long long, long long,
+                                                    hipStream_t);
+
+}  // namespace spk

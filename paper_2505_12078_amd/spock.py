@@ -1,0 +1,269 @@
+"""Thin ctypes binding of the C ABI in include/spock.h (argument marshalling only).
+
+Every step of the CP iteration runs in the gfx950 library; this module only
+converts NumPy arrays to pointers.  It fails loudly if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libspock_mi355x.so")
+
+SPOCK_OK = 0
+SPOCK_E_INVALID = -1
+SPOCK_E_INFEASIBLE_X0 = -2
+SPOCK_E_NOT_CONVERGED = -3
+SPOCK_E_DIVERGED = -4
+SPOCK_E_HIP = -5
+SPOCK_E_CAPACITY = -6
+SPOCK_E_NOMEM = -7
+FP64, MIXED, FP32 = 0, 1, 2
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("parent", _ip), ("cond_prob", _dp), ("nx", C.c_int32),
+                ("nu", C.c_int32), ("A", _dp), ("B", _dp), ("c", _dp), ("Q_diag", _dp), ("R_diag", _dp),
+                ("QN_diag", _dp), ("x_lo", _dp), ("x_hi", _dp), ("u_lo", _dp), ("u_hi", _dp),
+                ("xN_lo", _dp), ("xN_hi", _dp), ("x_ball", C.c_double), ("xN_ball", C.c_double),
+                ("gamma", _dp)]
+
+
+class Settings(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("eps", C.c_double), ("max_iters", C.c_int64),
+                ("precision", C.c_int32), ("precondition", C.c_int32), ("check_every", C.c_int32),
+                ("use_graph", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("iters_fp32", C.c_int64), ("rel_res", C.c_double),
+                ("xi1_inf", C.c_double), ("xi2_inf", C.c_double), ("s0", C.c_double),
+                ("t_solve_s", C.c_double), ("status", C.c_int32), ("precision_used", C.c_int32),
+                ("refined", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Sizes(C.Structure):
+    _fields_ = [("nz", C.c_int64), ("neta", C.c_int64), ("n", C.c_int32), ("n_nl", C.c_int32),
+                ("n_leaf", C.c_int32), ("N", C.c_int32), ("nx", C.c_int32), ("nu", C.c_int32),
+                ("nc", C.c_int32), ("ncN", C.c_int32), ("max_children", C.c_int32),
+                ("alpha", C.c_double), ("L_norm", C.c_double), ("device_bytes", C.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# name -> (restype, argtypes); the exported surface of include/spock.h
+SIGNATURES = {
+    "spock_last_error": (C.c_char_p, []),
+    "spock_default_settings": (C.c_int32, [C.POINTER(Settings)]),
+    "spock_problem_footprint": (C.c_int32, [C.POINTER(ProblemDesc), C.POINTER(Settings), C.POINTER(C.c_size_t)]),
+    "spock_problem_create": (C.c_int32, [C.POINTER(ProblemDesc), C.POINTER(Settings), C.c_void_p, C.c_size_t,
+                                         C.c_void_p, C.POINTER(C.c_void_p)]),
+    "spock_problem_destroy": (C.c_int32, [C.c_void_p]),
+    "spock_problem_sizes": (C.c_int32, [C.c_void_p, C.POINTER(Sizes)]),
+    "spock_set_settings": (C.c_int32, [C.c_void_p, C.POINTER(Settings)]),
+    "spock_solve": (C.c_int32, [C.c_void_p, _dp, C.c_int32, C.POINTER(Info)]),
+    "spock_get_solution": (C.c_int32, [C.c_void_p, _dp, _dp, _dp]),
+    "spock_get_iterate": (C.c_int32, [C.c_void_p, _dp, _dp]),
+    "spock_set_iterate": (C.c_int32, [C.c_void_p, _dp, _dp]),
+    "spock_set_x0": (C.c_int32, [C.c_void_p, _dp]),
+    "spock_apply_T": (C.c_int32, [C.c_void_p, _dp, _dp, _dp, _dp, C.c_int32, _dp]),
+    "spock_apply_L": (C.c_int32, [C.c_void_p, _dp, _dp, C.c_int32]),
+    "spock_apply_Lt": (C.c_int32, [C.c_void_p, _dp, _dp, C.c_int32]),
+    "spock_prox_gconj": (C.c_int32, [C.c_void_p, _dp, _dp, C.c_int32]),
+    "spock_time_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp]),
+    "spock_step_bytes": (C.c_int32, [C.c_void_p, C.c_int32, _dp, _dp]),
+}
+
+_lib = None
+
+
+def load(path=None):
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError("HIP library not built: %s is missing (run __graft_entry__.build())" % path)
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class SpockError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("spock error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _check(code, allow=()):
+    if code != SPOCK_OK and code not in allow:
+        raise SpockError(code, load().spock_last_error().decode())
+    return code
+
+
+def _ptr(a, dtype=np.float64):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double if dtype == np.float64 else C.c_int32))
+
+
+def default_settings(**kw):
+    s = Settings()
+    _check(load().spock_default_settings(C.byref(s)))
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+class _Desc:
+    """Keeps the NumPy buffers of a ProblemDesc alive."""
+
+    def __init__(self, prob):
+        f = lambda k: np.ascontiguousarray(prob[k], dtype=np.float64)
+        self.keep = {
+            "parent": np.ascontiguousarray(prob["parent"], dtype=np.int32),
+            "prob": f("prob"), "A": f("A"), "B": f("B"),
+            "c": None if prob.get("c") is None else f("c"),
+            "Q": f("Q"), "R": f("R"), "QN": f("QN"), "x_lo": f("x_lo"), "x_hi": f("x_hi"),
+            "u_lo": f("u_lo"), "u_hi": f("u_hi"), "xN_lo": f("xN_lo"), "xN_hi": f("xN_hi"),
+            "gamma": f("gamma"),
+        }
+        k = self.keep
+        self.desc = ProblemDesc(
+            n_nodes=len(k["parent"]), parent=_ptr(k["parent"], np.int32), cond_prob=_ptr(k["prob"]),
+            nx=int(prob["nx"]), nu=int(prob["nu"]), A=_ptr(k["A"]), B=_ptr(k["B"]), c=_ptr(k["c"]),
+            Q_diag=_ptr(k["Q"]), R_diag=_ptr(k["R"]), QN_diag=_ptr(k["QN"]), x_lo=_ptr(k["x_lo"]),
+            x_hi=_ptr(k["x_hi"]), u_lo=_ptr(k["u_lo"]), u_hi=_ptr(k["u_hi"]), xN_lo=_ptr(k["xN_lo"]),
+            xN_hi=_ptr(k["xN_hi"]), x_ball=float(prob["x_ball"]), xN_ball=float(prob["xN_ball"]),
+            gamma=_ptr(k["gamma"]))
+
+
+def footprint(prob, settings=None):
+    d = _Desc(prob)
+    s = settings or default_settings()
+    out = C.c_size_t(0)
+    _check(load().spock_problem_footprint(C.byref(d.desc), C.byref(s), C.byref(out)))
+    return int(out.value)
+
+
+class Problem:
+    """One scenario-tree problem resident on the current HIP device."""
+
+    def __init__(self, prob, settings=None, workspace=None, stream=None, **kw):
+        lib = load()
+        self.settings = settings or default_settings(**kw)
+        d = _Desc(prob)
+        h = C.c_void_p()
+        ws_ptr, ws_bytes = None, 0
+        if workspace is not None:  # e.g. a torch uint8 device tensor
+            ws_ptr, ws_bytes = C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+            self._ws = workspace
+        st = None if stream is None else C.c_void_p(stream)
+        _check(lib.spock_problem_create(C.byref(d.desc), C.byref(self.settings), ws_ptr, ws_bytes, st,
+                                        C.byref(h)))
+        self.h = h
+        sz = Sizes()
+        _check(lib.spock_problem_sizes(h, C.byref(sz)))
+        self.sizes = sz.as_dict()
+        self.nz, self.neta = sz.nz, sz.neta
+        self.n, self.n_nl, self.nx, self.nu = sz.n, sz.n_nl, sz.nx, sz.nu
+        self.alpha = sz.alpha
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().spock_problem_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_settings(self, **kw):
+        for k, v in kw.items():
+            setattr(self.settings, k, v)
+        _check(load().spock_set_settings(self.h, C.byref(self.settings)))
+
+    def solve(self, x0, warm_start=False, raise_on_failure=False):
+        x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        info = Info()
+        code = load().spock_solve(self.h, _ptr(x0), int(bool(warm_start)), C.byref(info))
+        allow = () if raise_on_failure else (SPOCK_E_NOT_CONVERGED, SPOCK_E_DIVERGED)
+        _check(code, allow)
+        out = info.as_dict()
+        out["code"] = code
+        return out
+
+    def solution(self):
+        x = np.zeros((self.n, self.nx))
+        u = np.zeros((self.n_nl, self.nu))
+        s0 = C.c_double(0)
+        _check(load().spock_get_solution(self.h, _ptr(x), _ptr(u), C.byref(s0)))
+        return x, u, s0.value
+
+    def get_iterate(self):
+        z, e = np.zeros(self.nz), np.zeros(self.neta)
+        _check(load().spock_get_iterate(self.h, _ptr(z), _ptr(e)))
+        return z, e
+
+    def set_iterate(self, z, eta):
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        eta = np.ascontiguousarray(eta, dtype=np.float64)
+        _check(load().spock_set_iterate(self.h, _ptr(z), _ptr(eta)))
+
+    def set_x0(self, x0):
+        x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        _check(load().spock_set_x0(self.h, _ptr(x0)))
+
+    def apply_T(self, z, eta, precision=FP64):
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        eta = np.ascontiguousarray(eta, dtype=np.float64)
+        zo, eo, xi = np.zeros(self.nz), np.zeros(self.neta), np.zeros(2)
+        _check(load().spock_apply_T(self.h, _ptr(z), _ptr(eta), _ptr(zo), _ptr(eo), precision, _ptr(xi)))
+        return zo, eo, xi
+
+    def apply_L(self, z, precision=FP64):
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        out = np.zeros(self.neta)
+        _check(load().spock_apply_L(self.h, _ptr(z), _ptr(out), precision))
+        return out
+
+    def apply_Lt(self, eta, precision=FP64):
+        eta = np.ascontiguousarray(eta, dtype=np.float64)
+        out = np.zeros(self.nz)
+        _check(load().spock_apply_Lt(self.h, _ptr(eta), _ptr(out), precision))
+        return out
+
+    def prox_gconj(self, w, precision=FP64):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        out = np.zeros(self.neta)
+        _check(load().spock_prox_gconj(self.h, _ptr(w), _ptr(out), precision))
+        return out
+
+    def time_steps(self, steps, precision=FP64):
+        t, b, f = C.c_double(), C.c_double(), C.c_double()
+        _check(load().spock_time_steps(self.h, precision, int(steps), C.byref(t), C.byref(b), C.byref(f)))
+        return t.value, b.value, f.value
+
+    def step_bytes(self, precision=FP64):
+        b, f = C.c_double(), C.c_double()
+        _check(load().spock_step_bytes(self.h, precision, C.byref(b), C.byref(f)))
+        return b.value, f.value

@@ -1,0 +1,250 @@
+"""Parity of the gfx950 library with the FP64 oracle, through the C ABI.
+
+Tolerances (derived in the design doc):
+  * L, L*, prox_{alpha g*} in float64: 1e-12 relative to the input scale
+    (a handful of rounding errors per entry).
+  * One CP step T in float64: 1e-10 relative to max(1, |v|_inf, |T v|_inf)
+    (the S1 sweep chains N stages of length-(nx+nu) dot products, and the
+    GPU uses the reduced recursion while the oracle runs Alg. 2 with P).
+  * One CP step in float32: 2e-4 relative (float32 rounding ~6e-8 amplified
+    by the same chains).
+  * Solutions: |V*_gpu - V*_oracle| <= 1e-6 max(1, |V*|) with both at
+    rel_res <= 1e-6 (float64), and 1e-4 for the mixed form.
+"""
+import numpy as np
+import pytest
+
+from oracle import spock_oracle as O
+from paper_2505_12078_amd import spock as S
+from paper_2505_12078_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need an MI355X; none is visible")
+    S.load()
+
+
+def _cases():
+    cases = {
+        "cfg0": W.config_problem(0),
+        "cfg1": W.config_problem(1),
+        "ragged_a": W.random_ragged_problem(1, N=4, nx=3, nu=2, max_children=3),
+        "ragged_affine": W.random_ragged_problem(2, N=3, nx=5, nu=3, max_children=4, affine=True),
+        "ragged_noball": W.random_ragged_problem(3, N=5, nx=4, nu=1, max_children=2, ball=False),
+    }
+    # single scenario (every node has one child) and the smallest tree
+    par, _ = W.tree_from_branching([1, 1, 1, 1])
+    cases["chain"] = W.make_problem(par, 3, 2, np.random.default_rng(11), x_ball=6.0, name="chain")
+    par, _ = W.tree_from_branching([1])
+    cases["two_nodes"] = W.make_problem(par, 2, 1, np.random.default_rng(12), name="two_nodes")
+    # extreme risk levels: AV@R_0 = max and AV@R_1 = expectation
+    p = W.random_ragged_problem(4, N=3, nx=3, nu=2)
+    p["gamma"] = np.where(np.arange(p["gamma"].size) % 2 == 0, 0.0, 1.0)
+    cases["gamma_0_1"] = p
+    # wide node (many children) and larger dimensions
+    par, _ = W.tree_from_branching([7, 2])
+    cases["wide"] = W.make_problem(par, 9, 4, np.random.default_rng(13), prob_kind="dirichlet",
+                                   gamma=0.6, x_ball=8.0, name="wide")
+    par, _ = W.tree_from_branching([2, 1, 1])
+    cases["big_nx"] = W.make_problem(par, 70, 40, np.random.default_rng(14), prob_kind="dirichlet",
+                                     x_ball=12.0, name="big_nx")
+    return cases
+
+
+CASES = _cases()
+
+
+def _pair(name, precondition=True):
+    prob = CASES[name]
+    D = O.Data(prob, precondition=precondition)
+    alpha = O.step_size(D)
+    P = S.Problem(prob, S.default_settings(alpha=alpha, precondition=int(precondition)))
+    P.set_x0(prob["x0"])
+    return prob, D, alpha, P
+
+
+def _rel(a, b, scale):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / scale)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_alpha_and_sizes_match_oracle(name):
+    prob, D, alpha, P = _pair(name)
+    with P:
+        assert P.nz == D.layout.nz and P.neta == D.layout.neta
+        # the library's own exact ||L|| (automatic alpha) against the oracle's
+        Q = S.Problem(prob)
+        assert Q.sizes["L_norm"] == pytest.approx(O.L_norm(D), rel=1e-12)
+        assert Q.alpha == pytest.approx(alpha, rel=1e-12)
+        Q.close()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("precondition", [True, False])
+def test_L_Lt_prox_match_oracle(name, precondition):
+    prob, D, alpha, P = _pair(name, precondition)
+    rng = np.random.default_rng(5)
+    with P:
+        z = rng.standard_normal(P.nz) * 2
+        e = rng.standard_normal(P.neta) * 2
+        assert _rel(P.apply_L(z), O.apply_L(D, z), 2) < 1e-12
+        assert _rel(P.apply_Lt(e), O.apply_Lt(D, e), 2) < 1e-12
+        assert _rel(P.prox_gconj(e), O.prox_gconj(D, e, alpha), 2) < 1e-12
+        # float32 kernels
+        assert _rel(P.apply_L(z, S.FP32), O.apply_L(D, z), 2) < 1e-5
+        assert _rel(P.prox_gconj(e, S.FP32), O.prox_gconj(D, e, alpha), 2) < 1e-5
+
+
+def _random_v(P, rng, scale=2.0):
+    return rng.standard_normal(P.nz) * scale, rng.standard_normal(P.neta) * scale
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("precondition", [True, False])
+def test_T_step_matches_oracle(name, precondition):
+    prob, D, alpha, P = _pair(name, precondition)
+    F = O.Offline(D)
+    rng = np.random.default_rng(17)
+    with P:
+        for trial in range(2):
+            z, e = _random_v(P, rng)
+            zo, eo = O.cp_step(D, F, z, e, alpha)
+            x1, x2 = O.residuals(D, z, e, zo, eo, alpha)
+            zg, eg, xi = P.apply_T(z, e)
+            scale = max(1.0, np.abs(z).max(), np.abs(e).max(), np.abs(zo).max(), np.abs(eo).max())
+            assert _rel(zg, zo, scale) < 1e-10, (trial, _rel(zg, zo, scale))
+            assert _rel(eg, eo, scale) < 1e-10, (trial, _rel(eg, eo, scale))
+            assert xi[0] == pytest.approx(np.abs(x1).max(), rel=1e-9)
+            assert xi[1] == pytest.approx(np.abs(x2).max(), rel=1e-9)
+            zf, ef, xif = P.apply_T(z, e, S.FP32)
+            assert _rel(zf, zo, scale) < 2e-4
+            assert _rel(ef, eo, scale) < 2e-4
+            assert xif[0] == pytest.approx(np.abs(x1).max(), rel=1e-3, abs=1e-3 * scale / alpha)
+
+
+@pytest.mark.parametrize("name", ["cfg0", "ragged_a", "wide"])
+def test_prox_f_parts(name):
+    """With eta = 0 the z part of T is prox_{alpha f}: S1 on (x, u) by Alg. 2,
+    S2 on (y, tau, s) and s0 - alpha."""
+    prob, D, alpha, P = _pair(name)
+    F = O.Offline(D)
+    rng = np.random.default_rng(3)
+    with P:
+        z = rng.standard_normal(P.nz) * 3
+        zg, _, _ = P.apply_T(z, np.zeros(P.neta))
+        zo = O.prox_f(D, F, z, alpha)
+        assert _rel(zg, zo, 3) < 1e-11
+
+
+@pytest.mark.parametrize("name,steps", [("cfg0", 200), ("cfg1", 60), ("ragged_affine", 100)])
+def test_trajectory_matches_oracle(name, steps):
+    """K plain CP steps from zero: T is firmly nonexpansive, so differences
+    cannot amplify along the trajectory."""
+    prob, D, alpha, P = _pair(name)
+    F = O.Offline(D)
+    with P:
+        z, e = np.zeros(P.nz), np.zeros(P.neta)
+        zg, eg = z.copy(), e.copy()
+        for _ in range(steps):
+            z, e = O.cp_step(D, F, z, e, alpha)
+        P.set_iterate(zg, eg)
+        for _ in range(steps):
+            zg, eg, _ = P.apply_T(zg, eg)
+        scale = max(1.0, np.abs(z).max(), np.abs(e).max())
+        assert _rel(zg, z, scale) < steps * 1e-11
+        assert _rel(eg, e, scale) < steps * 1e-11
+
+
+def test_config0_solution_matches_oracle():
+    prob = CASES["cfg0"]
+    ref = O.solve(prob, eps=1e-6, max_iters=20000)
+    with S.Problem(prob, S.default_settings(eps=1e-6, check_every=2)) as P:
+        info = P.solve(prob["x0"])
+        assert info["code"] == S.SPOCK_OK and info["rel_res"] <= 1e-6
+        x, u, s0 = P.solution()
+        assert abs(s0 - ref["s0"]) <= 1e-6 * max(1, abs(ref["s0"])) * 10
+        assert O.nested_cost(prob, x, u) == pytest.approx(s0, rel=1e-5)
+        assert O.dynamics_violation(prob, x, u) < 1e-10
+        # the iteration count agrees with the oracle's up to the check interval
+        assert abs(info["iters"] - ref["iters"]) <= 2
+
+
+def test_config1_solution_invariants():
+    """Full solve of the medium tree to 1e-6 in float64 on the GPU; pinned by
+    the nested risk objective evaluated on the returned trajectory."""
+    prob = CASES["cfg1"]
+    with S.Problem(prob, S.default_settings(eps=1e-6, max_iters=400000)) as P:
+        info = P.solve(prob["x0"])
+        assert info["code"] == S.SPOCK_OK, info
+        x, u, s0 = P.solution()
+        assert O.nested_cost(prob, x, u) == pytest.approx(s0, rel=1e-5)
+        assert O.dynamics_violation(prob, x, u) < 1e-9
+        assert np.all(np.abs(x) <= 5 + 1e-3) and np.all(np.abs(u) <= 1 + 1e-3)
+        assert np.all(np.linalg.norm(x, axis=1) <= 10 + 1e-3)
+
+
+@pytest.mark.parametrize("name", ["cfg0", "ragged_a"])
+def test_mixed_precision_matches_fp64(name):
+    prob = CASES[name]
+    with S.Problem(prob, S.default_settings(eps=1e-6)) as P64:
+        r64 = P64.solve(prob["x0"])
+        _, _, s64 = P64.solution()
+    with S.Problem(prob, S.default_settings(eps=1e-4, precision=S.MIXED)) as PM:
+        rm = PM.solve(prob["x0"])
+        assert rm["code"] == S.SPOCK_OK and rm["rel_res"] <= 1e-4
+        assert rm["precision_used"] == S.FP64  # the accepted step is a float64 one
+        _, _, sm = PM.solution()
+    assert abs(sm - s64) <= 1e-3 * max(1.0, abs(s64))
+
+
+def test_warm_start_and_iterate_roundtrip():
+    prob = CASES["cfg0"]
+    with S.Problem(prob, S.default_settings(eps=1e-6)) as P:
+        a = P.solve(prob["x0"])
+        z, e = P.get_iterate()
+        b = P.solve(prob["x0"], warm_start=True)
+        assert b["iters"] <= 4  # already at the fixed point
+        P.set_iterate(z, e)
+        z2, e2 = P.get_iterate()
+        assert np.array_equal(z, z2) and np.array_equal(e, e2)
+        assert a["code"] == S.SPOCK_OK
+
+
+def test_infeasible_x0_and_not_converged():
+    prob = CASES["cfg0"]
+    with S.Problem(prob, S.default_settings(max_iters=10)) as P:
+        with pytest.raises(S.SpockError) as e:
+            P.solve(np.array([9.0, 0.0]))
+        assert e.value.code == S.SPOCK_E_INFEASIBLE_X0
+        r = P.solve(prob["x0"])
+        assert r["code"] == S.SPOCK_E_NOT_CONVERGED and r["iters"] >= 10
+
+
+def test_torch_workspace_and_stream():
+    """Device memory and the stream can come from PyTorch."""
+    import torch
+    prob = CASES["cfg0"]
+    nbytes = S.footprint(prob)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    st = torch.cuda.Stream()
+    with S.Problem(prob, workspace=ws, stream=st.cuda_stream) as P:
+        r = P.solve(prob["x0"])
+        assert r["code"] == S.SPOCK_OK
+    with S.Problem(prob) as Q:
+        r2 = Q.solve(prob["x0"])
+    assert r["s0"] == r2["s0"] and r["iters"] == r2["iters"]
+
+
+def test_run_to_run_bitwise_deterministic():
+    prob = CASES["cfg1"]
+    out = []
+    for _ in range(2):
+        with S.Problem(prob, S.default_settings(max_iters=200)) as P:
+            P.solve(prob["x0"])
+            out.append(P.get_iterate())
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
