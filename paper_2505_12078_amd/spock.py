@@ -93,6 +93,13 @@ def load(path=None):
     if _lib is not None and path is None:
         return _lib
     path = path or LIB_PATH
+    # PyTorch bundles its own HIP runtime under the same soname; loading it
+    # first makes this library bind to that one runtime instead of a second
+    # copy (two runtimes in one process cannot share the device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise RuntimeError("HIP library not built: %s is missing (run __graft_entry__.build())" % path)
     lib = C.CDLL(path)
@@ -177,6 +184,7 @@ class Problem:
         _check(lib.spock_problem_create(C.byref(d.desc), C.byref(self.settings), ws_ptr, ws_bytes, st,
                                         C.byref(h)))
         self.h = h
+        self._lib = lib
         sz = Sizes()
         _check(lib.spock_problem_sizes(h, C.byref(sz)))
         self.sizes = sz.as_dict()
@@ -186,7 +194,7 @@ class Problem:
 
     def close(self):
         if getattr(self, "h", None):
-            load().spock_problem_destroy(self.h)
+            self._lib.spock_problem_destroy(self.h)
             self.h = None
 
     __del__ = close
