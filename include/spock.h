@@ -200,6 +200,11 @@ int32_t spock_prox_gconj(spock_problem* p, const double* w, double* eta_out, int
 int32_t spock_time_steps(spock_problem* p, int32_t precision, int32_t steps, double* ms_total,
                          double* ms_backward, double* ms_forward);
 
+/* Launch `steps` CP steps from the current device iterate in the given
+ * precision (SPOCK_FP64 or SPOCK_FP32), without residual checks or readback;
+ * sync = 1 waits for them to finish.  For throughput measurement. */
+int32_t spock_run_steps(spock_problem* p, int32_t precision, int32_t steps, int32_t sync);
+
 /* Bytes one CP step must move at minimum (factor matrices + iterates) in the
  * given precision, counted as in the design notes; for roofline reporting. */
 int32_t spock_step_bytes(const spock_problem* p, int32_t precision, double* bytes_backward,

@@ -28,6 +28,8 @@ struct ProbDev {
     const int* first_child;
     const int* n_ch;
     const int* y_off;        // start of y^i inside the y block, per non-leaf node
+    const int* path;         // per leaf l: node at each stage 0..N on the root-to-leaf path
+    const int* top_owned;    // per leaf l: first stage whose path node has l as leftmost leaf
 
     // Offline factors (Alg. 1, reduced online form):
     //   M[j]  = [Abar^j | B^j]  (nx x m, row-major), node j >= 1
@@ -72,7 +74,7 @@ struct ProbDev {
     unsigned long long* res; // |xi1|_inf, |xi2|_inf as float64 bit patterns
 };
 
-// Elements of the per-block staging arrays of the forward sweep.
+// Elements of one wavefront's staging array for a dual block in the forward sweep.
 __host__ __device__ inline int blk_elems(int nx, int nu, int max_ch) {
     const int m = nx + nu;
     int b = 2 * nx + nu;
@@ -86,7 +88,7 @@ __host__ __device__ inline int blk_elems(int nx, int nu, int max_ch) {
 __host__ __device__ inline int lds_elems(int nx, int nu, int max_ch) {
     const int m = nx + nu;
     const int bwd = kWG + 2 * m + nx + 2 * nu + 5 * max_ch;
-    const int fwd = kWG + m + 3 * nx + 3 * nu + 2 * blk_elems(nx, nu, max_ch);
+    const int fwd = kWG + m + 6 * nx + 7 * nu + 8 * blk_elems(nx, nu, max_ch);
     return (bwd > fwd ? bwd : fwd) + 8;
 }
 

@@ -20,11 +20,11 @@
 
 namespace spk {
 template <typename real>
-hipError_t launch_step(const ProbDev<real>*, const int2*, int, int, int, int, hipStream_t);
+hipError_t launch_step(const ProbDev<real>*, const int2*, int*, int, int, int, int, hipStream_t);
 template <typename real>
-hipError_t launch_backward(const ProbDev<real>*, const int2*, int, int, int, int, hipStream_t);
+hipError_t launch_backward(const ProbDev<real>*, const int2*, int*, int, int, int, int, hipStream_t);
 template <typename real>
-hipError_t launch_forward(const ProbDev<real>*, const int2*, int, int, int, int, hipStream_t);
+hipError_t launch_forward(const ProbDev<real>*, const int2*, int*, int, int, int, int, hipStream_t);
 template <typename real>
 hipError_t launch_apply_L(const ProbDev<real>*, int, const real*, real*, hipStream_t);
 template <typename real>
@@ -184,6 +184,9 @@ struct spock_problem {
     int* d_tree = nullptr;
     int* d_cnt = nullptr;
     int* d_flag = nullptr;
+    int* d_path = nullptr;
+    int* d_top = nullptr;
+    int* d_ticket = nullptr;
     int2* d_tasks = nullptr;
     unsigned long long* d_res = nullptr;
     int* d_err = nullptr;
@@ -258,6 +261,9 @@ static void carve(Arena& a, spock_problem* p) {
     p->d_tree = a.take<int>(4LL * p->n + 4);
     p->d_cnt = a.take<int>(p->n);
     p->d_flag = a.take<int>(p->n);
+    p->d_path = a.take<int>((long long)p->n_leaf * (p->N + 1));
+    p->d_top = a.take<int>(p->n_leaf);
+    p->d_ticket = a.take<int>(4);
     p->d_tasks = a.take<int2>(p->n_leaf);
     p->d_res = a.take<unsigned long long>(4);
     p->d_err = a.take<int>(4);
@@ -371,6 +377,27 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     if ((long long)spk::lds_elems(nx, nu, p->max_ch) * 8 > 64 * 1024)
         return fail(SPOCK_E_INVALID, "nx + nu or the branching is too large for one workgroup");
     return SPOCK_OK;
+}
+
+// Root-to-leaf path of every leaf, and the first stage of that path whose node
+// has the leaf as its leftmost leaf: the forward task of a leaf computes the
+// path from that stage down, and only waits for the node just above it.
+static void leaf_paths(const spock_problem* p, std::vector<int>& path, std::vector<int>& top) {
+    const int n = p->n, N = p->N;
+    std::vector<int> leftmost(n);
+    for (int v = n - 1; v >= 0; --v) leftmost[v] = p->n_ch[v] ? leftmost[p->first_child[v]] : v;
+    path.assign((size_t)p->n_leaf * (N + 1), 0);
+    top.assign(p->n_leaf, 0);
+    for (int l = 0; l < p->n_leaf; ++l) {
+        int v = p->n_nl + l;
+        for (int lev = N; lev >= 0; --lev) {
+            path[(size_t)l * (N + 1) + lev] = v;
+            v = p->parent[v];
+        }
+        int L = 0;
+        while (leftmost[path[(size_t)l * (N + 1) + L]] != p->n_nl + l) ++L;
+        top[l] = L;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -618,6 +645,8 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     h.neta = p->neta;
     h.cnt = p->d_cnt;
     h.flag = p->d_flag;
+    h.path = p->d_path;
+    h.top_owned = p->d_top;
     h.err = p->d_err;
     h.res = p->d_res;
     s.lds_bytes = spk::lds_elems(p->nx, p->nu, p->max_ch) * (int)sizeof(real);
@@ -658,7 +687,8 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
 template <typename real>
 static int32_t step(spock_problem* p, int check) {
     DevSet<real>& s = set_of<real>(p);
-    HIP_TRY(spk::launch_step<real>(s.d, p->d_tasks, p->n_leaf, s.lds_bytes, s.par, check, p->stream));
+    HIP_TRY(spk::launch_step<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, s.par, check,
+                                   p->stream));
     s.par ^= 1;
     return SPOCK_OK;
 }
@@ -682,8 +712,8 @@ static int32_t chunk(spock_problem* p, int steps) {
             HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
             int par = s.par;
             for (int k = 0; k < steps; ++k) {
-                hipError_t e =
-                    spk::launch_step<real>(s.d, p->d_tasks, p->n_leaf, s.lds_bytes, par, k == steps - 1, p->stream);
+                hipError_t e = spk::launch_step<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, par,
+                                                      k == steps - 1, p->stream);
                 if (e != hipSuccess) {
                     (void)hipStreamEndCapture(p->stream, &graph);
                     return fail(SPOCK_E_HIP, std::string("capture: ") + hipGetErrorString(e));
@@ -872,9 +902,13 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
         std::copy(p->y_off.begin(), p->y_off.end(), tree.begin() + 3 * (size_t)p->n);
         std::vector<int2> tasks(p->n_leaf);
         for (int k = 0; k < p->n_leaf; ++k) tasks[k] = make_int2(0, k);
+        std::vector<int> path, top;
+        leaf_paths(p, path, top);
         hipError_t e = hipMemcpy(p->d_tree, tree.data(), tree.size() * sizeof(int), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(p->d_tasks, tasks.data(), tasks.size() * sizeof(int2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(p->d_path, path.data(), path.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(p->d_top, top.data(), top.size() * sizeof(int), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             spock_problem_destroy(p);
             return fail(SPOCK_E_HIP, std::string("upload: ") + hipGetErrorString(e));
@@ -883,6 +917,7 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
         e = spk::launch_fill<int>(p->d_cnt, 0, p->n, p->stream);
         if (e == hipSuccess) e = spk::launch_fill<int>(p->d_flag, 0, p->n, p->stream);
         if (e == hipSuccess) e = spk::launch_fill<int>(p->d_err, 0, 4, p->stream);
+        if (e == hipSuccess) e = spk::launch_fill<int>(p->d_ticket, 0, 4, p->stream);
         if (e == hipSuccess) e = spk::launch_fill<unsigned long long>(p->d_res, 0ull, 4, p->stream);
         if (e != hipSuccess) {
             spock_problem_destroy(p);
@@ -1252,9 +1287,11 @@ static int32_t time_steps(spock_problem* p, int steps, double* ms_total, double*
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     HIP_TRY(hipEventRecord(ev[0], p->stream));
     for (int k = 0; k < steps; ++k) {
-        HIP_TRY(spk::launch_backward<real>(s.d, p->d_tasks, p->n_leaf, s.lds_bytes, s.par, 0, p->stream));
+        HIP_TRY(spk::launch_backward<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, s.par, 0,
+                                           p->stream));
         HIP_TRY(hipEventRecord(ev[2 * k + 1], p->stream));
-        HIP_TRY(spk::launch_forward<real>(s.d, p->d_tasks, p->n_leaf, s.lds_bytes, s.par, 0, p->stream));
+        HIP_TRY(spk::launch_forward<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, s.par, 0,
+                                          p->stream));
         HIP_TRY(hipEventRecord(ev[2 * k + 2], p->stream));
         s.par ^= 1;
     }
@@ -1294,6 +1331,16 @@ int32_t spock_time_steps(spock_problem* p, int32_t prec, int32_t steps, double* 
     if (r) return r;
     return prec == SPOCK_FP64 ? time_steps<double>(p, steps, ms_total, ms_b, ms_f)
                               : time_steps<float>(p, steps, ms_total, ms_b, ms_f);
+}
+
+int32_t spock_run_steps(spock_problem* p, int32_t prec, int32_t steps, int32_t sync) {
+    if (!p || steps < 0) return fail(SPOCK_E_INVALID, "bad argument");
+    int32_t r = check_prec(prec);
+    if (!r) r = move_iterate(p, prec);
+    for (int k = 0; !r && k < steps; ++k) r = prec == SPOCK_FP64 ? step<double>(p, 0) : step<float>(p, 0);
+    if (r) return r;
+    if (sync) HIP_TRY(hipStreamSynchronize(p->stream));
+    return SPOCK_OK;
 }
 
 int32_t spock_step_bytes(const spock_problem* p, int32_t prec, double* bb, double* bf) {

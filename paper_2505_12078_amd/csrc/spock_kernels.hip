@@ -166,34 +166,29 @@ SPK_DEV void record_max(unsigned long long* slot, real v) {
 // ---------------------------------------------------------------------------
 
 // S2 projection (Sec. 4.3) of node i's block (y^i, tau^[i], s^[i]) after the
-// z - alpha L* eta shift, written to zout.  Kernel of G = [E^T, -I, -I] with
-// E = [gamma I; -I; 1^T] (AV@R, Sec. 3.3).  G G^T = (gamma^2 + 3) I + 1 1^T, so
-// with rho = G w the multiplier is lambda = (rho - (1^T rho / (c + n)) 1) / c,
-// c = gamma^2 + 3 (Sherman-Morrison), and w - G^T lambda is the projection.
+// z - alpha L* eta shift, written to zout; run by one wavefront.  Kernel of
+// G = [E^T, -I, -I] with E = [gamma I; -I; 1^T] (AV@R, Sec. 3.3).
+// G G^T = (gamma^2 + 3) I + 1 1^T, so with rho = G w the multiplier is
+// lambda = (rho - (1^T rho / (c + n)) 1) / c, c = gamma^2 + 3 (Sherman-Morrison),
+// and w - G^T lambda is the projection.
 template <typename real>
-SPK_DEV void s2_block(const ProbDev<real>* __restrict__ P, int i, const real* __restrict__ zin,
-                      const real* __restrict__ ein, real* __restrict__ zout, real* s2, real* red) {
-    const int t = threadIdx.x;
+SPK_DEV void s2_block_wave(const ProbDev<real>* __restrict__ P, int i, const real* __restrict__ zin,
+                           const real* __restrict__ ein, real* __restrict__ zout, real* lam) {
+    const int lane = threadIdx.x & 63;
     const int k = P->n_ch[i], fc = P->first_child[i];
     const int nx = P->nx, m = P->m;
     const real alpha = P->alpha, gam = P->gamma[i];
     const long long yo = P->y_off[i];
     const real es = ein[P->e_s + i];
-    real* yb1 = s2;
-    real* yb2 = s2 + P->max_ch;
-    real* tb = s2 + 2 * P->max_ch;
-    real* sb = s2 + 3 * P->max_ch;
-    real* lam = s2 + 4 * P->max_ch;
     const real yb3 = zin[P->z_y + yo + 2 * k] - alpha * (ein[P->e_y + yo + 2 * k] - es);
     const real cc = gam * gam + real(3);
     real rsum = 0;
-    for (int c = t; c < k; c += kWG) {
+    for (int c = lane; c < k; c += 64) {
         const int j = fc + c;
-        const real p = P->prob[j];
-        yb1[c] = zin[P->z_y + yo + c] - alpha * (ein[P->e_y + yo + c] - p * es);
-        yb2[c] = zin[P->z_y + yo + k + c] - alpha * ein[P->e_y + yo + k + c];
+        const real yb1 = zin[P->z_y + yo + c] - alpha * (ein[P->e_y + yo + c] - P->prob[j] * es);
+        const real yb2 = zin[P->z_y + yo + k + c] - alpha * ein[P->e_y + yo + k + c];
         const real* es_soc = ein + P->e_soc + (long long)(j - 1) * (m + 2);
-        tb[c] = zin[P->z_tau + j - 1] - alpha * real(0.5) * (es_soc[m] + es_soc[m + 1]);
+        const real tb = zin[P->z_tau + j - 1] - alpha * real(0.5) * (es_soc[m] + es_soc[m + 1]);
         real lts;
         if (j < P->n_nl) {
             lts = ein[P->e_s + j];
@@ -201,35 +196,42 @@ SPK_DEV void s2_block(const ProbDev<real>* __restrict__ P, int i, const real* __
             const real* esN = ein + P->e_socN + (long long)(j - P->n_nl) * (nx + 2);
             lts = real(0.5) * (esN[nx] + esN[nx + 1]);
         }
-        sb[c] = zin[P->z_s + j - 1] - alpha * lts;
-        const real rho = gam * yb1[c] - yb2[c] + yb3 - tb[c] - sb[c];
+        const real sb = zin[P->z_s + j - 1] - alpha * lts;
+        const real rho = gam * yb1 - yb2 + yb3 - tb - sb;
+        // keep the shifted values in the output slots; corrected below
+        zout[P->z_y + yo + c] = yb1;
+        zout[P->z_y + yo + k + c] = yb2;
+        zout[P->z_tau + j - 1] = tb;
+        zout[P->z_s + j - 1] = sb;
         lam[c] = rho;
         rsum += rho;
     }
-    rsum = block_sum(rsum, red);
+    rsum = wave_sum(rsum);
     real lsum = 0;
-    for (int c = t; c < k; c += kWG) {
+    for (int c = lane; c < k; c += 64) {
         const real l = (lam[c] - rsum / (cc + real(k))) / cc;
         lsum += l;
         const int j = fc + c;
-        zout[P->z_y + yo + c] = yb1[c] - gam * l;
-        zout[P->z_y + yo + k + c] = yb2[c] + l;
-        zout[P->z_tau + j - 1] = tb[c] + l;
-        zout[P->z_s + j - 1] = sb[c] + l;
+        zout[P->z_y + yo + c] -= gam * l;
+        zout[P->z_y + yo + k + c] += l;
+        zout[P->z_tau + j - 1] += l;
+        zout[P->z_s + j - 1] += l;
     }
-    lsum = block_sum(lsum, red);
-    if (t == 0) zout[P->z_y + yo + 2 * k] = yb3 - lsum;
+    lsum = wave_sum(lsum);
+    if (lane == 0) zout[P->z_y + yo + 2 * k] = yb3 - lsum;
 }
 
 template <typename real>
 __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restrict__ probs,
-                                                  const int2* __restrict__ tasks, int par, int check) {
+                                                  const int2* __restrict__ tasks, int* __restrict__ ticket,
+                                                  int par, int check) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_path[kMaxDepth];
     __shared__ int s_last;
     real* sm = reinterpret_cast<real*>(smem_raw);
     const int2 tk = tasks[blockIdx.x];
     const ProbDev<real>* __restrict__ P = probs + tk.x;
-    const int nx = P->nx, nu = P->nu, m = P->m;
+    const int nx = P->nx, nu = P->nu, m = P->m, N = P->N;
     const real alpha = P->alpha;
     const real* __restrict__ zin = P->z[par];
     const real* __restrict__ ein = P->eta[par];
@@ -242,10 +244,16 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
     real* g = ub + nu;      // sum of children messages
     real* w2 = g + m;       // ubar - g_u
     real* o = w2 + nu;      // product outputs
-    real* s2 = o + m;       // S2 scratch, 5 * max_ch
+    real* lam = o + m;      // S2 multipliers, max_ch
+
+    {
+        const int* path = P->path + (long long)tk.y * (N + 1);
+        for (int q = t; q <= N; q += kWG) s_path[q] = path[q];
+    }
+    __syncthreads();
 
     // ---- leaf: q = -xbar, message [Abar|B]^T (q + P c) ----
-    int j = P->n_nl + tk.y;
+    int j = s_path[N];
     {
         const long long lf = j - P->n_nl;
         const real* ecN = ein + P->e_cN + lf * P->ncN;
@@ -263,8 +271,8 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
     }
 
     // ---- walk up ----
-    for (;;) {
-        const int i = P->parent[j];
+    for (int lev = N - 1; lev >= 0; --lev) {
+        const int i = s_path[lev];
         const int k = P->n_ch[i], fc = P->first_child[i];
         if (k > 1) {
             for (int c = t; c < m; c += kWG) P->e[(long long)j * m + c] = o[c];
@@ -309,6 +317,7 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
             w2[r] = u - g[nx + r];
         }
         if (t == 0) P->flag[i] = 0;
+        if ((t >> 6) == (kWG / 64) - 1) s2_block_wave(P, i, zin, ein, zout, lam);
         __syncthreads();
         // [K^T ubar ; R~^-1 (ubar - g_u)] in one pass over [K | R~^-1]
         mat_t_vec(P->KR + i * P->KR_stride, nu, m, m, nx, ub, w2, o, red);
@@ -318,11 +327,10 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
             xb[r] = h;
         }
         for (int r = t; r < nu; r += kWG) P->d[(long long)i * nu + r] = o[nx + r];
-        s2_block(P, i, zin, ein, zout, s2, red);  // ends with a barrier
-
         if (i == 0) {
             if (t == 0) {
                 zout[0] = zin[0] - alpha * ein[P->e_s] - alpha;  // prox of alpha * s0
+                ticket[0] = 0;                                    // forward tickets restart
                 if (check) {
                     P->res[0] = 0ull;
                     P->res[1] = 0ull;
@@ -330,6 +338,7 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
             }
             return;
         }
+        __syncthreads();
         mat_t_vec(P->M + i * P->M_stride, nx, m, m, m, xb, xb, o, red);
         j = i;
     }
@@ -367,75 +376,322 @@ SPK_DEV void soc_moreau_coef(real nw2, real vt, real& cw, real& ct) {
     }
 }
 
+// Node vectors a forward step works on (LDS).
+template <typename real>
+struct FwdVecs {
+    const real* xn;  // x+ of the node
+    const real* un;  // u+
+    const real* xo;  // x of the previous iterate
+    const real* uo;
+    real* blk;       // this wavefront's staging: etabar
+    real* dblk;      //                            L dz, then eta - eta+
+    real* lxw;       // this wavefront's share of (L* d_eta) on x
+    real* luw;       //                                    on u
+};
+
+// eta_c of non-leaf node v: C^i = box x ball (one wavefront).
+template <typename real>
+SPK_DEV void fwd_block_c(const ProbDev<real>* __restrict__ P, int v, const real* __restrict__ ein,
+                         real* __restrict__ eout, const FwdVecs<real>& V, int check, real& r2) {
+    const int lane = threadIdx.x & 63;
+    const int nx = P->nx, nbox = P->nbox, nc = P->nc;
+    const real alpha = P->alpha, ialpha = real(1) / alpha;
+    const long long off = P->e_c + (long long)v * nc;
+    real nb2 = 0;
+    for (int r = lane; r < nc; r += 64) {
+        real wn, wo;
+        if (r < nx) {
+            wn = P->gx[r] * V.xn[r];
+            wo = P->gx[r] * V.xo[r];
+        } else if (r < nbox) {
+            wn = P->gu[r - nx] * V.un[r - nx];
+            wo = P->gu[r - nx] * V.uo[r - nx];
+        } else {
+            wn = P->gb[r - nbox] * V.xn[r - nbox];
+            wo = P->gb[r - nbox] * V.xo[r - nbox];
+        }
+        const real eb = ein[off + r] + alpha * (real(2) * wn - wo);
+        V.blk[r] = eb;
+        V.dblk[r] = wo - wn;
+        if (r >= nbox) nb2 += eb * eb;
+    }
+    real cb = 0;
+    if (P->has_ball) {
+        nb2 = wave_sum(nb2);
+        const real nrm = sqrt(nb2);
+        const real rad = alpha * P->ball_r;
+        cb = nrm > rad ? real(1) - rad / nrm : real(0);
+    }
+    for (int r = lane; r < nc; r += 64) {
+        const real eb = V.blk[r];
+        const real ep = r < nbox ? moreau_box(eb, alpha, P->lo[r], P->hi[r]) : eb * cb;
+        eout[off + r] = ep;
+        const real de = ein[off + r] - ep;
+        if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
+        V.dblk[r] = de;
+    }
+    if (check) {
+        __builtin_amdgcn_wave_barrier();
+        for (int r = lane; r < nx; r += 64) {
+            real s = P->gx[r] * V.dblk[r];
+            if (P->has_ball) s += P->gb[r] * V.dblk[nbox + r];
+            V.lxw[r] += s;
+        }
+        for (int r = lane; r < P->nu; r += 64) V.luw[r] += P->gu[r] * V.dblk[nx + r];
+    }
+}
+
+// eta_y in (K^i)* = R^{2k}_+ x R and eta_s in R_+ (one wavefront).
+template <typename real>
+SPK_DEV void fwd_block_risk(const ProbDev<real>* __restrict__ P, int v, const real* __restrict__ zin,
+                            const real* __restrict__ zout, const real* __restrict__ ein,
+                            real* __restrict__ eout, int check, real& r1, real& r2) {
+    const int lane = threadIdx.x & 63;
+    const real alpha = P->alpha, ialpha = real(1) / alpha;
+    const int k = P->n_ch[v], fc = P->first_child[v];
+    const long long yo = P->y_off[v];
+    const real* yn = zout + P->z_y + yo;
+    const real* yv = zin + P->z_y + yo;
+    const long long soff = (v == 0) ? 0 : P->z_s + v - 1;
+    const real sn = zout[soff], sv = zin[soff];
+    real bn = 0, bo = 0;  // b^T y with b = (p, 0, 1)
+    for (int c = lane; c < k; c += 64) {
+        const real p = P->prob[fc + c];
+        bn += p * yn[c];
+        bo += p * yv[c];
+    }
+    bn = wave_sum(bn) + yn[2 * k];
+    bo = wave_sum(bo) + yv[2 * k];
+    const real wsn = sn - bn, wso = sv - bo;
+    const real ebs = ein[P->e_s + v] + alpha * (real(2) * wsn - wso);
+    const real eps_ = ebs < 0 ? ebs : real(0);
+    const real des = ein[P->e_s + v] - eps_;
+    if (lane == 0) eout[P->e_s + v] = eps_;
+    for (int c = lane; c < 2 * k + 1; c += 64) {
+        const real eb = ein[P->e_y + yo + c] + alpha * (real(2) * yn[c] - yv[c]);
+        const real ep = c < 2 * k ? (eb < 0 ? eb : real(0)) : real(0);
+        eout[P->e_y + yo + c] = ep;
+        if (check) {
+            const real de = ein[P->e_y + yo + c] - ep;
+            const real dy = yv[c] - yn[c];
+            r2 = fmax(r2, fabs(de * ialpha - dy));
+            const real bc = c < k ? P->prob[fc + c] : (c == 2 * k ? real(1) : real(0));
+            r1 = fmax(r1, fabs(dy * ialpha - (de - bc * des)));
+        }
+    }
+    if (check && lane == 0) {
+        r2 = fmax(r2, fabs(des * ialpha - (wso - wsn)));
+        r1 = fmax(r1, fabs((sv - sn) * ialpha - des));
+    }
+}
+
+// SOC block of the edge into child j of non-leaf node v:
+// (Q^1/2 x^v, R^1/2 u^v, tau^j / 2, tau^j / 2) in SOC + a (one wavefront).
+template <typename real>
+SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, const real* __restrict__ zin,
+                           const real* __restrict__ zout, const real* __restrict__ ein,
+                           real* __restrict__ eout, const FwdVecs<real>& V, int check, real& r1, real& r2) {
+    const int lane = threadIdx.x & 63;
+    const int nx = P->nx, m = P->m;
+    const real alpha = P->alpha, ialpha = real(1) / alpha;
+    const long long off = P->e_soc + (long long)(j - 1) * (m + 2);
+    const real tn = zout[P->z_tau + j - 1], tv = zin[P->z_tau + j - 1];
+    real nw2 = 0;
+    for (int r = lane; r < m + 2; r += 64) {
+        real wn, wo;
+        if (r < nx) {
+            wn = P->qh[r] * V.xn[r];
+            wo = P->qh[r] * V.xo[r];
+        } else if (r < m) {
+            wn = P->rh[r - nx] * V.un[r - nx];
+            wo = P->rh[r - nx] * V.uo[r - nx];
+        } else {
+            wn = real(0.5) * tn;
+            wo = real(0.5) * tv;
+        }
+        real eb = ein[off + r] + alpha * (real(2) * wn - wo);
+        if (r == m) eb -= real(0.5) * alpha;  // v = etabar - alpha a
+        if (r == m + 1) eb += real(0.5) * alpha;
+        V.blk[r] = eb;
+        V.dblk[r] = wo - wn;
+        if (r <= m) nw2 += eb * eb;
+    }
+    nw2 = wave_sum(nw2);
+    __builtin_amdgcn_wave_barrier();
+    real cw, ct;
+    soc_moreau_coef(nw2, V.blk[m + 1], cw, ct);
+    for (int r = lane; r < m + 2; r += 64) {
+        const real ep = r <= m ? V.blk[r] * cw : ct;
+        eout[off + r] = ep;
+        const real de = ein[off + r] - ep;
+        if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
+        V.dblk[r] = de;
+    }
+    if (check) {
+        __builtin_amdgcn_wave_barrier();
+        for (int r = lane; r < nx; r += 64) V.lxw[r] += P->qh[r] * V.dblk[r];
+        for (int r = lane; r < P->nu; r += 64) V.luw[r] += P->rh[r] * V.dblk[nx + r];
+        if (lane == 0) r1 = fmax(r1, fabs((tv - tn) * ialpha - real(0.5) * (V.dblk[m] + V.dblk[m + 1])));
+    }
+}
+
+// eta_cN (box x ball) and eta_socN (Q_N^1/2 x, s/2, s/2) of leaf v (one wavefront each).
+template <typename real>
+SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int which, const real* __restrict__ zin,
+                            const real* __restrict__ zout, const real* __restrict__ ein,
+                            real* __restrict__ eout, const FwdVecs<real>& V, int check, real& r1, real& r2) {
+    const int lane = threadIdx.x & 63;
+    const int nx = P->nx;
+    const real alpha = P->alpha, ialpha = real(1) / alpha;
+    const long long lf = v - P->n_nl;
+    if (which == 0) {
+        const long long off = P->e_cN + lf * P->ncN;
+        real nb2 = 0;
+        for (int r = lane; r < P->ncN; r += 64) {
+            real wn, wo;
+            if (r < nx) {
+                wn = P->gxN[r] * V.xn[r];
+                wo = P->gxN[r] * V.xo[r];
+            } else {
+                wn = P->gbN[r - nx] * V.xn[r - nx];
+                wo = P->gbN[r - nx] * V.xo[r - nx];
+            }
+            const real eb = ein[off + r] + alpha * (real(2) * wn - wo);
+            V.blk[r] = eb;
+            V.dblk[r] = wo - wn;
+            if (r >= nx) nb2 += eb * eb;
+        }
+        real cb = 0;
+        if (P->has_ballN) {
+            nb2 = wave_sum(nb2);
+            const real nrm = sqrt(nb2);
+            const real rad = alpha * P->ballN_r;
+            cb = nrm > rad ? real(1) - rad / nrm : real(0);
+        }
+        for (int r = lane; r < P->ncN; r += 64) {
+            const real eb = V.blk[r];
+            const real ep = r < nx ? moreau_box(eb, alpha, P->loN[r], P->hiN[r]) : eb * cb;
+            eout[off + r] = ep;
+            const real de = ein[off + r] - ep;
+            if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
+            V.dblk[r] = de;
+        }
+        if (check) {
+            __builtin_amdgcn_wave_barrier();
+            for (int r = lane; r < nx; r += 64) {
+                real s = P->gxN[r] * V.dblk[r];
+                if (P->has_ballN) s += P->gbN[r] * V.dblk[nx + r];
+                V.lxw[r] += s;
+            }
+        }
+    } else {
+        const long long off = P->e_socN + lf * (nx + 2);
+        const real sn = zout[P->z_s + v - 1], sv = zin[P->z_s + v - 1];
+        real nw2 = 0;
+        for (int r = lane; r < nx + 2; r += 64) {
+            real wn, wo;
+            if (r < nx) {
+                wn = P->qnh[r] * V.xn[r];
+                wo = P->qnh[r] * V.xo[r];
+            } else {
+                wn = real(0.5) * sn;
+                wo = real(0.5) * sv;
+            }
+            real eb = ein[off + r] + alpha * (real(2) * wn - wo);
+            if (r == nx) eb -= real(0.5) * alpha;
+            if (r == nx + 1) eb += real(0.5) * alpha;
+            V.blk[r] = eb;
+            V.dblk[r] = wo - wn;
+            if (r <= nx) nw2 += eb * eb;
+        }
+        nw2 = wave_sum(nw2);
+        __builtin_amdgcn_wave_barrier();
+        real cw, ct;
+        soc_moreau_coef(nw2, V.blk[nx + 1], cw, ct);
+        for (int r = lane; r < nx + 2; r += 64) {
+            const real ep = r <= nx ? V.blk[r] * cw : ct;
+            eout[off + r] = ep;
+            const real de = ein[off + r] - ep;
+            if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
+            V.dblk[r] = de;
+        }
+        if (check) {
+            __builtin_amdgcn_wave_barrier();
+            for (int r = lane; r < nx; r += 64) V.lxw[r] += P->qnh[r] * V.dblk[r];
+            if (lane == 0) r1 = fmax(r1, fabs((sv - sn) * ialpha - real(0.5) * (V.dblk[nx] + V.dblk[nx + 1])));
+        }
+    }
+}
+
 template <typename real>
 __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict__ probs,
-                                                 const int2* __restrict__ tasks, int par, int check) {
+                                                 const int2* __restrict__ tasks, int* __restrict__ ticket,
+                                                 int par, int check) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int s_path[kMaxDepth];
-    __shared__ int s_claim;
+    __shared__ int s_task, s_ok;
     real* sm = reinterpret_cast<real*>(smem_raw);
-    const int2 tk = tasks[blockIdx.x];
+    const int t = threadIdx.x, w = t >> 6;
+    // Tickets hand out tasks in start order, so a workgroup only ever waits on
+    // a workgroup that started before it.
+    if (t == 0) s_task = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int2 tk = tasks[s_task];
     const ProbDev<real>* __restrict__ P = probs + tk.x;
-    const int nx = P->nx, nu = P->nu, m = P->m, nbox = P->nbox;
-    const real alpha = P->alpha, ialpha = real(1) / P->alpha;
+    const int nx = P->nx, nu = P->nu, m = P->m, N = P->N;
+    const real ialpha = real(1) / P->alpha;
     const real* __restrict__ zin = P->z[par];
     const real* __restrict__ ein = P->eta[par];
     real* __restrict__ zout = P->z[par ^ 1];
     real* __restrict__ eout = P->eta[par ^ 1];
-    const int t = threadIdx.x;
+    const int bmax = blk_elems(nx, nu, P->max_ch);
 
     real* red = sm;
-    real* xa = red + kWG;   // [x^anc ; d^anc]
-    real* xn = xa + m;      // x+ of the node
-    real* un = xn + nx;     // u+
-    real* xo = un + nu;     // x of the previous iterate
+    real* xa = red + kWG;  // [x^anc ; d^anc]
+    real* xn = xa + m;
+    real* un = xn + nx;
+    real* dv = un + nu;
+    real* xo = dv + nu;
     real* uo = xo + nx;
-    real* lx = uo + nu;     // (L* d_eta) rows of x
-    real* lu = lx + nx;     // (L* d_eta) rows of u
-    const int bmax = blk_elems(nx, nu, P->max_ch);
-    real* blk = lu + nu;    // etabar of the current block
-    real* dblk = blk + bmax;  // eta - eta+ of the current block (residuals)
+    real* lxw = uo + nu;   // 4 x nx
+    real* luw = lxw + 4 * nx;  // 4 x nu
+    real* blk = luw + 4 * nu;  // 4 x bmax
+    real* dblk = blk + 4 * bmax;
+    const FwdVecs<real> V{xn, un, xo, uo, blk + w * bmax, dblk + w * bmax, lxw + w * nx, luw + w * nu};
 
+    // this task computes the path nodes from stage L down to its leaf; the
+    // node above them belongs to the task of its leftmost leaf
+    const int L = P->top_owned[tk.y];
+    {
+        const int* path = P->path + (long long)tk.y * (N + 1);
+        for (int q = (L > 0 ? L - 1 : 0) + t; q <= N; q += kWG) s_path[q] = path[q];
+    }
+    __syncthreads();
     if (t == 0) {
-        int v = P->n_nl + tk.y;
-        int lev = P->N;
-        while (v >= 0) {
-            s_path[lev--] = v;
-            v = P->parent[v];
+        int ok = 1;
+        if (L > 0 && !wait_done(&P->flag[s_path[L - 1]])) {
+            atomicExch(P->err, 1);
+            ok = 0;
         }
+        s_ok = ok;
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    if (L > 0) {
+        const int pn = s_path[L - 1];
+        for (int r = t; r < nx; r += kWG) xa[r] = zout[P->z_x + (long long)pn * nx + r];
+        for (int r = t; r < nu; r += kWG) xa[nx + r] = P->d[(long long)pn * nu + r];
     }
     __syncthreads();
 
     real r1 = 0, r2 = 0;  // residual maxima of this thread
-    for (int lev = 0; lev <= P->N; ++lev) {
+    for (int lev = L; lev <= N; ++lev) {
         const int v = s_path[lev];
-        __syncthreads();  // every thread has read the previous s_claim
-        if (t == 0) {
-            int expected = 0;
-            int claim = __hip_atomic_compare_exchange_strong(&P->flag[v], &expected, 1, __ATOMIC_RELAXED,
-                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                            ? 1
-                            : 0;
-            if (!claim && !wait_done(&P->flag[v])) {
-                atomicExch(P->err, 1);
-                claim = -1;
-            }
-            s_claim = claim;
-        }
-        __syncthreads();
-        const int claim = s_claim;
-        if (claim < 0) return;
-        if (claim == 0) continue;
-
         // ---- state: x^v = [Abar|B] [x^anc; d^anc] + c ----
         if (v == 0) {
             for (int r = t; r < nx; r += kWG) xn[r] = P->x0[r];
             __syncthreads();
         } else {
-            const int i = P->parent[v];
-            for (int r = t; r < nx; r += kWG) xa[r] = zout[P->z_x + (long long)i * nx + r];
-            for (int r = t; r < nu; r += kWG) xa[nx + r] = P->d[(long long)i * nu + r];
-            __syncthreads();
             mat_vec(P->M + v * P->M_stride, nx, m, m, xa, xn);
             if (P->affine) {
                 for (int r = t; r < nx; r += kWG) xn[r] += P->c[(long long)v * nx + r];
@@ -445,252 +701,63 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
         for (int r = t; r < nx; r += kWG) {
             zout[P->z_x + (long long)v * nx + r] = xn[r];
             xo[r] = zin[P->z_x + (long long)v * nx + r];
-            lx[r] = 0;
         }
-
-        if (v < P->n_nl) {
+        const bool nonleaf = v < P->n_nl;
+        if (nonleaf) {
+            for (int r = t; r < nu; r += kWG) dv[r] = P->d[(long long)v * nu + r];
+            if (P->n_ch[v] > 1) {
+                // children owned by other tasks read x^v (and d^v): publish now
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __syncthreads();
+                if (t == 0) __hip_atomic_store(&P->flag[v], 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
             // ---- input: u^v = K^v x^v + d^v ----
             mat_vec(P->KR + v * P->KR_stride, nu, nx, m, xn, un);
             for (int r = t; r < nu; r += kWG) {
-                const real u = un[r] + P->d[(long long)v * nu + r];
+                const real u = un[r] + dv[r];
                 un[r] = u;
                 zout[P->z_u + (long long)v * nu + r] = u;
                 uo[r] = zin[P->z_u + (long long)v * nu + r];
-                lu[r] = 0;
-            }
-            __syncthreads();
-
-            // ---- constraint block eta_c: C^i = box x ball ----
-            {
-                const long long off = P->e_c + (long long)v * P->nc;
-                real nb2 = 0;
-                for (int r = t; r < P->nc; r += kWG) {
-                    real wn, wo;
-                    if (r < nx) {
-                        wn = P->gx[r] * xn[r];
-                        wo = P->gx[r] * xo[r];
-                    } else if (r < nbox) {
-                        wn = P->gu[r - nx] * un[r - nx];
-                        wo = P->gu[r - nx] * uo[r - nx];
-                    } else {
-                        wn = P->gb[r - nbox] * xn[r - nbox];
-                        wo = P->gb[r - nbox] * xo[r - nbox];
-                    }
-                    const real eb = ein[off + r] + alpha * (real(2) * wn - wo);
-                    blk[r] = eb;
-                    dblk[r] = wo - wn;  // L dz for this row
-                    if (r >= nbox) nb2 += eb * eb;
-                }
-                real cb = 0;
-                if (P->has_ball) {
-                    nb2 = block_sum(nb2, red);
-                    const real nrm = sqrt(nb2);
-                    const real rad = alpha * P->ball_r;
-                    cb = nrm > rad ? real(1) - rad / nrm : real(0);
-                }
-                for (int r = t; r < P->nc; r += kWG) {
-                    const real eb = blk[r];
-                    const real ep = r < nbox ? moreau_box(eb, alpha, P->lo[r], P->hi[r]) : eb * cb;
-                    eout[off + r] = ep;
-                    const real de = ein[off + r] - ep;
-                    if (check) r2 = fmax(r2, fabs(de * ialpha - dblk[r]));
-                    dblk[r] = de;
-                }
-                __syncthreads();
-                if (check) {
-                    for (int r = t; r < nx; r += kWG) {
-                        real s = P->gx[r] * dblk[r];
-                        if (P->has_ball) s += P->gb[r] * dblk[nbox + r];
-                        lx[r] += s;
-                    }
-                    for (int r = t; r < nu; r += kWG) lu[r] += P->gu[r] * dblk[nx + r];
-                }
-            }
-
-            // ---- risk blocks eta_y (in (K^i)* = R^{2k}_+ x R) and eta_s (in R_+) ----
-            {
-                const int k = P->n_ch[v], fc = P->first_child[v];
-                const long long yo = P->y_off[v];
-                const real* yn = zout + P->z_y + yo;
-                const real* yv = zin + P->z_y + yo;
-                const long long soff = (v == 0) ? 0 : P->z_s + v - 1;
-                const real sn = zout[soff], sv = zin[soff];
-                // b^T y with b = (p, 0, 1)
-                real bn = 0, bo = 0;
-                for (int c = t; c < k; c += kWG) {
-                    const real p = P->prob[fc + c];
-                    bn += p * yn[c];
-                    bo += p * yv[c];
-                }
-                bn = block_sum(bn, red);
-                bo = block_sum(bo, red);
-                bn += yn[2 * k];
-                bo += yv[2 * k];
-                const real wsn = sn - bn, wso = sv - bo;
-                const real ebs = ein[P->e_s + v] + alpha * (real(2) * wsn - wso);
-                const real eps_ = ebs < 0 ? ebs : real(0);
-                const real des = ein[P->e_s + v] - eps_;
-                if (t == 0) eout[P->e_s + v] = eps_;
-                for (int c = t; c < 2 * k + 1; c += kWG) {
-                    const real eb = ein[P->e_y + yo + c] + alpha * (real(2) * yn[c] - yv[c]);
-                    const real ep = c < 2 * k ? (eb < 0 ? eb : real(0)) : real(0);
-                    eout[P->e_y + yo + c] = ep;
-                    if (check) {
-                        const real de = ein[P->e_y + yo + c] - ep;
-                        const real dy = yv[c] - yn[c];
-                        r2 = fmax(r2, fabs(de * ialpha - dy));
-                        const real bc = c < k ? P->prob[fc + c] : (c == 2 * k ? real(1) : real(0));
-                        r1 = fmax(r1, fabs(dy * ialpha - (de - bc * des)));
-                    }
-                }
-                if (check && t == 0) {
-                    r2 = fmax(r2, fabs(des * ialpha - (wso - wsn)));
-                    r1 = fmax(r1, fabs((sv - sn) * ialpha - des));
-                }
-            }
-
-            // ---- SOC block of every child edge: (Q^1/2 x, R^1/2 u, tau/2, tau/2) ----
-            {
-                const int k = P->n_ch[v], fc = P->first_child[v];
-                for (int q = 0; q < k; ++q) {
-                    const int j = fc + q;
-                    const long long off = P->e_soc + (long long)(j - 1) * (m + 2);
-                    const real tn = zout[P->z_tau + j - 1], tv = zin[P->z_tau + j - 1];
-                    real nw2 = 0;
-                    for (int r = t; r < m + 2; r += kWG) {
-                        real wn, wo;
-                        if (r < nx) {
-                            wn = P->qh[r] * xn[r];
-                            wo = P->qh[r] * xo[r];
-                        } else if (r < m) {
-                            wn = P->rh[r - nx] * un[r - nx];
-                            wo = P->rh[r - nx] * uo[r - nx];
-                        } else {
-                            wn = real(0.5) * tn;
-                            wo = real(0.5) * tv;
-                        }
-                        real eb = ein[off + r] + alpha * (real(2) * wn - wo);
-                        if (r == m) eb -= real(0.5) * alpha;       // v = etabar - alpha a
-                        if (r == m + 1) eb += real(0.5) * alpha;
-                        blk[r] = eb;
-                        dblk[r] = wo - wn;
-                        if (r <= m) nw2 += eb * eb;
-                    }
-                    nw2 = block_sum(nw2, red);
-                    real cw, ct;
-                    soc_moreau_coef(nw2, blk[m + 1], cw, ct);
-                    for (int r = t; r < m + 2; r += kWG) {
-                        const real ep = r <= m ? blk[r] * cw : ct;
-                        eout[off + r] = ep;
-                        const real de = ein[off + r] - ep;
-                        if (check) r2 = fmax(r2, fabs(de * ialpha - dblk[r]));
-                        dblk[r] = de;
-                    }
-                    __syncthreads();
-                    if (check) {
-                        for (int r = t; r < nx; r += kWG) lx[r] += P->qh[r] * dblk[r];
-                        for (int r = t; r < nu; r += kWG) lu[r] += P->rh[r] * dblk[nx + r];
-                        if (t == 0)
-                            r1 = fmax(r1, fabs((tv - tn) * ialpha - real(0.5) * (dblk[m] + dblk[m + 1])));
-                    }
-                    __syncthreads();
-                }
-            }
-            if (check) {
-                for (int r = t; r < nx; r += kWG) r1 = fmax(r1, fabs((xo[r] - xn[r]) * ialpha - lx[r]));
-                for (int r = t; r < nu; r += kWG) r1 = fmax(r1, fabs((uo[r] - un[r]) * ialpha - lu[r]));
-            }
-        } else {
-            // ---- leaf: eta_cN in C_N (box x ball), eta_socN in SOC + a_N ----
-            __syncthreads();
-            const long long lf = v - P->n_nl;
-            {
-                const long long off = P->e_cN + lf * P->ncN;
-                real nb2 = 0;
-                for (int r = t; r < P->ncN; r += kWG) {
-                    real wn, wo;
-                    if (r < nx) {
-                        wn = P->gxN[r] * xn[r];
-                        wo = P->gxN[r] * xo[r];
-                    } else {
-                        wn = P->gbN[r - nx] * xn[r - nx];
-                        wo = P->gbN[r - nx] * xo[r - nx];
-                    }
-                    const real eb = ein[off + r] + alpha * (real(2) * wn - wo);
-                    blk[r] = eb;
-                    dblk[r] = wo - wn;
-                    if (r >= nx) nb2 += eb * eb;
-                }
-                real cb = 0;
-                if (P->has_ballN) {
-                    nb2 = block_sum(nb2, red);
-                    const real nrm = sqrt(nb2);
-                    const real rad = alpha * P->ballN_r;
-                    cb = nrm > rad ? real(1) - rad / nrm : real(0);
-                }
-                for (int r = t; r < P->ncN; r += kWG) {
-                    const real eb = blk[r];
-                    const real ep = r < nx ? moreau_box(eb, alpha, P->loN[r], P->hiN[r]) : eb * cb;
-                    eout[off + r] = ep;
-                    const real de = ein[off + r] - ep;
-                    if (check) r2 = fmax(r2, fabs(de * ialpha - dblk[r]));
-                    dblk[r] = de;
-                }
-                __syncthreads();
-                if (check) {
-                    for (int r = t; r < nx; r += kWG) {
-                        real s = P->gxN[r] * dblk[r];
-                        if (P->has_ballN) s += P->gbN[r] * dblk[nx + r];
-                        lx[r] += s;
-                    }
-                }
-                __syncthreads();
-            }
-            {
-                const long long off = P->e_socN + lf * (nx + 2);
-                const real sn = zout[P->z_s + v - 1], sv = zin[P->z_s + v - 1];
-                real nw2 = 0;
-                for (int r = t; r < nx + 2; r += kWG) {
-                    real wn, wo;
-                    if (r < nx) {
-                        wn = P->qnh[r] * xn[r];
-                        wo = P->qnh[r] * xo[r];
-                    } else {
-                        wn = real(0.5) * sn;
-                        wo = real(0.5) * sv;
-                    }
-                    real eb = ein[off + r] + alpha * (real(2) * wn - wo);
-                    if (r == nx) eb -= real(0.5) * alpha;
-                    if (r == nx + 1) eb += real(0.5) * alpha;
-                    blk[r] = eb;
-                    dblk[r] = wo - wn;
-                    if (r <= nx) nw2 += eb * eb;
-                }
-                nw2 = block_sum(nw2, red);
-                real cw, ct;
-                soc_moreau_coef(nw2, blk[nx + 1], cw, ct);
-                for (int r = t; r < nx + 2; r += kWG) {
-                    const real ep = r <= nx ? blk[r] * cw : ct;
-                    eout[off + r] = ep;
-                    const real de = ein[off + r] - ep;
-                    if (check) r2 = fmax(r2, fabs(de * ialpha - dblk[r]));
-                    dblk[r] = de;
-                }
-                __syncthreads();
-                if (check) {
-                    for (int r = t; r < nx; r += kWG) {
-                        lx[r] += P->qnh[r] * dblk[r];
-                        r1 = fmax(r1, fabs((xo[r] - xn[r]) * ialpha - lx[r]));
-                    }
-                    if (t == 0) r1 = fmax(r1, fabs((sv - sn) * ialpha - real(0.5) * (dblk[nx] + dblk[nx + 1])));
-                }
             }
         }
-
-        // publish the node: every wave releases its stores, then one flag store
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (check) {
+            for (int r = t & 63; r < nx; r += 64) V.lxw[r] = 0;
+            for (int r = t & 63; r < nu; r += 64) V.luw[r] = 0;
+        }
         __syncthreads();
-        if (t == 0) __hip_atomic_store(&P->flag[v], 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // ---- dual blocks, one wavefront each ----
+        if (nonleaf) {
+            const int k = P->n_ch[v], fc = P->first_child[v];
+            for (int b = w; b < k + 2; b += kWG / 64) {
+                if (b == 0) fwd_block_c(P, v, ein, eout, V, check, r2);
+                else if (b == 1) fwd_block_risk(P, v, zin, zout, ein, eout, check, r1, r2);
+                else fwd_block_soc(P, fc + b - 2, zin, zout, ein, eout, V, check, r1, r2);
+            }
+        } else if (w < 2) {
+            fwd_block_leaf(P, v, w, zin, zout, ein, eout, V, check, r1, r2);
+        }
+        if (check) {
+            __syncthreads();
+            for (int r = t; r < nx; r += kWG) {
+                real s = 0;
+                for (int q = 0; q < kWG / 64; ++q) s += lxw[q * nx + r];
+                r1 = fmax(r1, fabs((xo[r] - xn[r]) * ialpha - s));
+            }
+            if (nonleaf)
+                for (int r = t; r < nu; r += kWG) {
+                    real s = 0;
+                    for (int q = 0; q < kWG / 64; ++q) s += luw[q * nu + r];
+                    r1 = fmax(r1, fabs((uo[r] - un[r]) * ialpha - s));
+                }
+        }
+        // ---- next stage input [x^v ; d^v] ----
+        if (lev < N) {
+            __syncthreads();
+            for (int r = t; r < nx; r += kWG) xa[r] = xn[r];
+            for (int r = t; r < nu; r += kWG) xa[nx + r] = dv[r];
+            __syncthreads();
+        }
     }
     if (check) {
         r1 = block_max(r1, red);
@@ -876,27 +943,27 @@ __global__ void k_fill(T* __restrict__ dst, T val, long long n) {
 // ---------------------------------------------------------------------------
 
 template <typename real>
-hipError_t launch_step(const ProbDev<real>* probs, const int2* tasks, int n_tasks, int lds_bytes, int par,
-                       int check, hipStream_t st) {
-    hipLaunchKernelGGL(k_backward<real>, dim3(n_tasks), dim3(kWG), lds_bytes, st, probs, tasks, par, check);
-    hipError_t e = hipGetLastError();
+hipError_t launch_backward(const ProbDev<real>* probs, const int2* tasks, int* ticket, int n_tasks,
+                           int lds_bytes, int par, int check, hipStream_t st) {
+    hipLaunchKernelGGL(k_backward<real>, dim3(n_tasks), dim3(kWG), lds_bytes, st, probs, tasks, ticket, par,
+                       check);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_forward(const ProbDev<real>* probs, const int2* tasks, int* ticket, int n_tasks,
+                          int lds_bytes, int par, int check, hipStream_t st) {
+    hipLaunchKernelGGL(k_forward<real>, dim3(n_tasks), dim3(kWG), lds_bytes, st, probs, tasks, ticket, par,
+                       check);
+    return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_step(const ProbDev<real>* probs, const int2* tasks, int* ticket, int n_tasks, int lds_bytes,
+                       int par, int check, hipStream_t st) {
+    hipError_t e = launch_backward<real>(probs, tasks, ticket, n_tasks, lds_bytes, par, check, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_forward<real>, dim3(n_tasks), dim3(kWG), lds_bytes, st, probs, tasks, par, check);
-    return hipGetLastError();
-}
-
-template <typename real>
-hipError_t launch_backward(const ProbDev<real>* probs, const int2* tasks, int n_tasks, int lds_bytes,
-                           int par, int check, hipStream_t st) {
-    hipLaunchKernelGGL(k_backward<real>, dim3(n_tasks), dim3(kWG), lds_bytes, st, probs, tasks, par, check);
-    return hipGetLastError();
-}
-
-template <typename real>
-hipError_t launch_forward(const ProbDev<real>* probs, const int2* tasks, int n_tasks, int lds_bytes,
-                          int par, int check, hipStream_t st) {
-    hipLaunchKernelGGL(k_forward<real>, dim3(n_tasks), dim3(kWG), lds_bytes, st, probs, tasks, par, check);
-    return hipGetLastError();
+    return launch_forward<real>(probs, tasks, ticket, n_tasks, lds_bytes, par, check, st);
 }
 
 template <typename real>
@@ -936,10 +1003,11 @@ hipError_t launch_fill(T* dst, T val, long long n, hipStream_t st) {
 }
 
 #define SPK_INSTANTIATE(real)                                                                              \
-    template hipError_t launch_step<real>(const ProbDev<real>*, const int2*, int, int, int, int, hipStream_t); \
-    template hipError_t launch_backward<real>(const ProbDev<real>*, const int2*, int, int, int, int,         \
+    template hipError_t launch_step<real>(const ProbDev<real>*, const int2*, int*, int, int, int, int,      \
+                                          hipStream_t);                                                    \
+    template hipError_t launch_backward<real>(const ProbDev<real>*, const int2*, int*, int, int, int, int,  \
                                               hipStream_t);                                                \
-    template hipError_t launch_forward<real>(const ProbDev<real>*, const int2*, int, int, int, int,          \
+    template hipError_t launch_forward<real>(const ProbDev<real>*, const int2*, int*, int, int, int, int,   \
                                              hipStream_t);                                                 \
     template hipError_t launch_apply_L<real>(const ProbDev<real>*, int, const real*, real*, hipStream_t);   \
     template hipError_t launch_apply_Lt<real>(const ProbDev<real>*, int, const real*, real*, hipStream_t);  \

@@ -82,6 +82,7 @@ SIGNATURES = {
     "spock_prox_gconj": (C.c_int32, [C.c_void_p, _dp, _dp, C.c_int32]),
     "spock_time_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp]),
     "spock_step_bytes": (C.c_int32, [C.c_void_p, C.c_int32, _dp, _dp]),
+    "spock_run_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
 }
 
 _lib = None
@@ -270,6 +271,9 @@ class Problem:
         t, b, f = C.c_double(), C.c_double(), C.c_double()
         _check(load().spock_time_steps(self.h, precision, int(steps), C.byref(t), C.byref(b), C.byref(f)))
         return t.value, b.value, f.value
+
+    def run_steps(self, steps, precision=FP64, sync=True):
+        _check(load().spock_run_steps(self.h, precision, int(steps), int(bool(sync))))
 
     def step_bytes(self, precision=FP64):
         b, f = C.c_double(), C.c_double()
