@@ -210,6 +210,42 @@ int32_t spock_run_steps(spock_problem* p, int32_t precision, int32_t steps, int3
 int32_t spock_step_bytes(const spock_problem* p, int32_t precision, double* bytes_backward,
                          double* bytes_forward);
 
+/*
+ * Batched form: one CP step of the batch is one backward and one forward
+ * launch over every member tree (uneven trees of any shapes and sizes share
+ * the launch; one task per leaf of every member).
+ *
+ * spock_batch_create groups problems created on the current device.  The
+ * problems stay owned by the caller, must outlive the batch, and must not be
+ * used on their own while a batch call runs.  s gives eps, max_iters,
+ * precision (SPOCK_FP64 / SPOCK_MIXED / SPOCK_FP32), check_every, use_graph for
+ * every member (alpha and precondition are the members' own).
+ * Errors: SPOCK_E_INVALID, SPOCK_E_NOMEM, SPOCK_E_HIP.
+ */
+typedef struct spock_batch spock_batch;
+int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_settings* s, spock_batch** out);
+int32_t spock_batch_destroy(spock_batch* b);
+int32_t spock_batch_size(const spock_batch* b, int32_t* n_problems, int32_t* n_tasks, size_t* device_bytes);
+
+/*
+ * Solve every member from x0s[k] (host [nx_k], unscaled); warm (nullable)
+ * selects warm starts per member.  Members that converge leave the launch
+ * (their tasks exit at once) while the others continue; each member's result is
+ * in infos[k] (status: SPOCK_OK, SPOCK_E_NOT_CONVERGED, SPOCK_E_DIVERGED or
+ * SPOCK_E_INFEASIBLE_X0 for that member only).  Returns SPOCK_OK unless the
+ * batch itself failed (SPOCK_E_HIP).  Solutions are read per member with
+ * spock_get_solution.
+ */
+int32_t spock_batch_solve(spock_batch* b, const double* const* x0s, const int32_t* warm, spock_info* infos);
+
+/* Measurement: `steps` (even) batched steps of every member; per-kernel mean
+ * durations with HIP events; algorithmic bytes of one batched step. */
+int32_t spock_batch_run_steps(spock_batch* b, int32_t precision, int32_t steps, int32_t sync);
+int32_t spock_batch_time_steps(spock_batch* b, int32_t precision, int32_t steps, double* ms_total,
+                               double* ms_backward, double* ms_forward);
+int32_t spock_batch_step_bytes(const spock_batch* b, int32_t precision, double* bytes_backward,
+                               double* bytes_forward);
+
 #ifdef __cplusplus
 }
 #endif

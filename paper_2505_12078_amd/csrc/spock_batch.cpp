@@ -1,0 +1,435 @@
+// Batched form: many independent scenario trees advanced by one backward and
+// one forward launch per CP step.  Each member keeps its own workspace; the
+// batch holds copies of the members' descriptors whose residual slots, error
+// flags and "active" flags point into batch-owned arrays, a problem-major task
+// table (one task per leaf of every member) and one forward ticket counter.
+// Members that converge are switched off through their active flag, so a
+// captured graph of `check_every` steps is replayed unchanged until every
+// member is done.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "spock_internal.h"
+
+struct spock_batch {
+    std::vector<spock_problem*> probs;
+    int n = 0;
+    spock_settings set{};
+    hipStream_t stream = nullptr;
+    void* base = nullptr;
+    size_t bytes = 0;
+    ProbDev<double>* d64 = nullptr;
+    ProbDev<float>* d32 = nullptr;
+    int2* tasks = nullptr;
+    int n_tasks = 0;
+    int* active = nullptr;
+    int* ticket = nullptr;
+    int* err = nullptr;
+    unsigned long long* res = nullptr;
+    int lds64 = 0, lds32 = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // [0] float64, [1] float32
+    int graph_steps[2] = {0, 0};
+    unsigned long long* h_res = nullptr;  // pinned: 2n residual slots, then n error flags
+    std::vector<int> h_active;
+    double bytes_b[2] = {0, 0}, bytes_f[2] = {0, 0};
+};
+
+namespace {
+
+struct Member {
+    bool live = false;      // still iterating in the current phase
+    long long iters = 0, iters32 = 0;
+    double rel = INFINITY, x1 = INFINITY, x2 = INFINITY;
+    double best = INFINITY;
+    int no_gain = 0;
+    int32_t status = SPOCK_E_NOT_CONVERGED;
+    int refined = 0;
+};
+
+template <typename real>
+ProbDev<real>* dev_of(spock_batch* b);
+template <>
+ProbDev<double>* dev_of<double>(spock_batch* b) { return b->d64; }
+template <>
+ProbDev<float>* dev_of<float>(spock_batch* b) { return b->d32; }
+template <typename real>
+int lds_of(spock_batch* b) { return sizeof(real) == 8 ? b->lds64 : b->lds32; }
+
+int32_t upload_active(spock_batch* b, const std::vector<Member>* m) {
+    for (int k = 0; k < b->n; ++k) b->h_active[k] = m ? (int)(*m)[k].live : 1;
+    HIP_TRY(hipMemcpyAsync(b->active, b->h_active.data(), b->n * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    return SPOCK_OK;
+}
+
+template <typename real>
+int32_t batch_steps(spock_batch* b, int steps, bool check_last) {
+    for (int k = 0; k < steps; ++k) {
+        // every member sits at copy 0 before a batched chunk; parity follows k
+        HIP_TRY(spk::launch_step<real>(dev_of<real>(b), b->tasks, b->ticket, b->n_tasks, lds_of<real>(b), k & 1,
+                                       check_last && k == steps - 1, b->stream));
+    }
+    return SPOCK_OK;
+}
+
+template <typename real>
+int32_t batch_chunk(spock_batch* b, int steps) {
+    const int gi = sizeof(real) == 8 ? 0 : 1;
+    if (!b->set.use_graph) return batch_steps<real>(b, steps, true);
+    if (b->graph_steps[gi] != steps && b->graph[gi]) {
+        (void)hipGraphExecDestroy(b->graph[gi]);
+        b->graph[gi] = nullptr;
+    }
+    if (!b->graph[gi]) {
+        hipGraph_t g;
+        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        int32_t r = batch_steps<real>(b, steps, true);
+        hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (r) return r;
+        if (e != hipSuccess) return fail(SPOCK_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+        HIP_TRY(hipGraphInstantiate(&b->graph[gi], g, nullptr, nullptr, 0));
+        HIP_TRY(hipGraphDestroy(g));
+        b->graph_steps[gi] = steps;
+    }
+    HIP_TRY(hipGraphLaunch(b->graph[gi], b->stream));
+    return SPOCK_OK;
+}
+
+int32_t read_all(spock_batch* b) {
+    HIP_TRY(hipMemcpyAsync(b->h_res, b->res, 2 * b->n * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           b->stream));
+    HIP_TRY(hipMemcpyAsync(b->h_res + 2 * b->n, b->err, b->n * sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    const int* errs = reinterpret_cast<const int*>(b->h_res + 2 * b->n);
+    for (int k = 0; k < b->n; ++k)
+        if (errs[k]) {
+            HIP_TRY(hipMemset(b->err, 0, b->n * sizeof(int)));
+            return fail(SPOCK_E_HIP, "device wait timeout in a batched forward sweep");
+        }
+    return SPOCK_OK;
+}
+
+// Iterate every live member in one precision until it converges, stalls
+// (float32 only) or spends its budget.
+template <typename real>
+int32_t batch_phase(spock_batch* b, std::vector<Member>& m, bool stall_exit) {
+    const int ce = b->set.check_every;
+    for (;;) {
+        bool any = false;
+        for (auto& x : m) any = any || x.live;
+        if (!any) return SPOCK_OK;
+        int32_t r = upload_active(b, &m);
+        if (!r) r = batch_chunk<real>(b, ce);
+        if (!r) r = read_all(b);
+        if (r) return r;
+        for (int k = 0; k < b->n; ++k) {
+            Member& x = m[k];
+            if (!x.live) continue;
+            spock_problem* p = b->probs[k];
+            x.iters += ce;
+            if (sizeof(real) == 4) x.iters32 += ce;
+            std::memcpy(&x.x1, &b->h_res[2 * k], 8);
+            std::memcpy(&x.x2, &b->h_res[2 * k + 1], 8);
+            x.rel = std::max(x.x1, x.x2) / std::max(1.0, std::max(p->xi_ref[0], p->xi_ref[1]));
+            if (!std::isfinite(x.rel)) {
+                x.status = SPOCK_E_DIVERGED;
+                x.live = false;
+            } else if (x.rel <= b->set.eps) {
+                x.status = SPOCK_OK;
+                x.live = false;
+            } else if (x.iters >= b->set.max_iters) {
+                x.status = SPOCK_E_NOT_CONVERGED;
+                x.live = false;
+            } else if (stall_exit) {
+                if (x.rel < 0.99 * x.best) {
+                    x.best = x.rel;
+                    x.no_gain = 0;
+                } else if (++x.no_gain >= 25) {
+                    x.status = SPOCK_E_NOT_CONVERGED;
+                    x.live = false;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_settings* s, spock_batch** out) {
+    if (!out || !probs || n < 1 || !s) return fail(SPOCK_E_INVALID, "bad batch arguments");
+    *out = nullptr;
+    if (s->check_every < 2 || (s->check_every & 1) || !(s->eps > 0) || s->max_iters < 1 ||
+        s->precision < SPOCK_FP64 || s->precision > SPOCK_FP32)
+        return fail(SPOCK_E_INVALID, "bad batch settings");
+    spock_batch* b = new spock_batch();
+    b->n = n;
+    b->set = *s;
+    b->probs.assign(probs, probs + n);
+    for (int k = 0; k < n; ++k) {
+        if (!probs[k]) {
+            delete b;
+            return fail(SPOCK_E_INVALID, "null problem in batch");
+        }
+        b->n_tasks += probs[k]->n_leaf;
+        b->lds64 = std::max(b->lds64, probs[k]->s64.lds_bytes);
+        b->lds32 = std::max(b->lds32, probs[k]->s32.lds_bytes);
+        HIP_TRY(hipStreamSynchronize(probs[k]->stream));
+        double bb, bf;
+        for (int q = 0; q < 2; ++q) {
+            spock_step_bytes(probs[k], q == 0 ? SPOCK_FP64 : SPOCK_FP32, &bb, &bf);
+            b->bytes_b[q] += bb;
+            b->bytes_f[q] += bf;
+        }
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        size_t o = off;
+        off += std::max<size_t>(bytes, 1);
+        return o;
+    };
+    const size_t o64 = take(sizeof(ProbDev<double>) * n), o32 = take(sizeof(ProbDev<float>) * n);
+    const size_t ot = take(sizeof(int2) * b->n_tasks), oa = take(sizeof(int) * n), otk = take(sizeof(int) * 4);
+    const size_t oe = take(sizeof(int) * n), orr = take(sizeof(unsigned long long) * 2 * n);
+    b->bytes = off + 256;
+    hipError_t e = hipMalloc(&b->base, b->bytes);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(SPOCK_E_NOMEM, std::string("batch hipMalloc: ") + hipGetErrorString(e));
+    }
+    char* base = (char*)b->base;
+    b->d64 = (ProbDev<double>*)(base + o64);
+    b->d32 = (ProbDev<float>*)(base + o32);
+    b->tasks = (int2*)(base + ot);
+    b->active = (int*)(base + oa);
+    b->ticket = (int*)(base + otk);
+    b->err = (int*)(base + oe);
+    b->res = (unsigned long long*)(base + orr);
+    auto bail = [&](int32_t code, const std::string& msg) {
+        spock_batch_destroy(b);
+        return fail(code, msg);
+    };
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(SPOCK_E_HIP, "batch stream");
+    if (hipHostMalloc((void**)&b->h_res, 3 * n * sizeof(unsigned long long), 0) != hipSuccess)
+        return bail(SPOCK_E_HIP, "batch pinned buffer");
+    std::vector<ProbDev<double>> h64(n);
+    std::vector<ProbDev<float>> h32(n);
+    std::vector<int2> tasks;
+    tasks.reserve(b->n_tasks);
+    for (int k = 0; k < n; ++k) {
+        h64[k] = probs[k]->s64.h;
+        h32[k] = probs[k]->s32.h;
+        h64[k].active = h32[k].active = b->active + k;
+        h64[k].err = h32[k].err = b->err + k;
+        h64[k].res = h32[k].res = b->res + 2 * k;
+        for (int l = 0; l < probs[k]->n_leaf; ++l) tasks.push_back(make_int2(k, l));
+    }
+    b->h_active.assign(n, 1);
+    e = hipMemcpy(b->d64, h64.data(), sizeof(ProbDev<double>) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d32, h32.data(), sizeof(ProbDev<float>) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->tasks, tasks.data(), sizeof(int2) * tasks.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->active, b->h_active.data(), sizeof(int) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b->ticket, 0, sizeof(int) * 4);
+    if (e == hipSuccess) e = hipMemset(b->err, 0, sizeof(int) * n);
+    if (e == hipSuccess) e = hipMemset(b->res, 0, sizeof(unsigned long long) * 2 * n);
+    if (e != hipSuccess) return bail(SPOCK_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
+    *out = b;
+    return SPOCK_OK;
+}
+
+int32_t spock_batch_destroy(spock_batch* b) {
+    if (!b) return SPOCK_OK;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (auto& g : b->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (b->h_res) (void)hipHostFree(b->h_res);
+    if (b->base) (void)hipFree(b->base);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return SPOCK_OK;
+}
+
+int32_t spock_batch_size(const spock_batch* b, int32_t* n_problems, int32_t* n_tasks, size_t* device_bytes) {
+    if (!b) return fail(SPOCK_E_INVALID, "null batch");
+    if (n_problems) *n_problems = b->n;
+    if (n_tasks) *n_tasks = b->n_tasks;
+    if (device_bytes) *device_bytes = b->bytes;
+    return SPOCK_OK;
+}
+
+int32_t spock_batch_solve(spock_batch* b, const double* const* x0s, const int32_t* warm, spock_info* infos) {
+    if (!b || !x0s || !infos) return fail(SPOCK_E_INVALID, "null batch argument");
+    const double t0 = now_s();
+    const int n = b->n;
+    const int prec = b->set.precision;
+    std::vector<Member> m(n);
+    int32_t r = SPOCK_OK;
+    // set-up: x0, cold starts, reference residuals, every member at copy 0 of
+    // the phase precision
+    for (int k = 0; k < n; ++k) {
+        spock_problem* p = b->probs[k];
+        std::memset(&infos[k], 0, sizeof(spock_info));
+        const bool w = warm && warm[k];
+        int32_t rk = set_x0_device(p, x0s[k], true);
+        long long taken = 0;
+        double a1, a2;
+        if (!rk) rk = ensure_ref(p, w, &taken, &a1, &a2);
+        if (!rk) {
+            m[k].iters = taken;
+            if (taken) {
+                m[k].x1 = a1;
+                m[k].x2 = a2;
+                m[k].rel = std::max(a1, a2) / std::max(1.0, std::max(a1, a2));
+            }
+            rk = move_iterate(p, prec == SPOCK_FP64 ? SPOCK_FP64 : SPOCK_FP32);
+        }
+        if (!rk) rk = normalize_parity(p);
+        if (!rk) rk = hipStreamSynchronize(p->stream) == hipSuccess ? SPOCK_OK : fail(SPOCK_E_HIP, "sync");
+        if (rk) {
+            m[k].status = rk;
+            infos[k].status = rk;
+            continue;
+        }
+        m[k].live = m[k].iters < b->set.max_iters;
+    }
+    if (prec == SPOCK_FP64) {
+        r = batch_phase<double>(b, m, false);
+    } else {
+        r = batch_phase<float>(b, m, prec == SPOCK_MIXED);
+        if (!r && prec == SPOCK_MIXED) {
+            // float64 check of every float32 result; refine the ones that fail
+            std::vector<Member> m2 = m;
+            for (int k = 0; k < n; ++k) {
+                m2[k].live = false;
+                if (m[k].status != SPOCK_OK && m[k].status != SPOCK_E_NOT_CONVERGED) continue;
+                spock_problem* p = b->probs[k];
+                p->cur = SPOCK_FP32;
+                p->s32.par = 0;
+                double a1, a2;
+                r = move_iterate(p, SPOCK_FP64);
+                if (!r) r = step<double>(p, 1);
+                if (!r) r = read_res(p, &a1, &a2);
+                if (!r) r = normalize_parity(p);
+                if (!r) r = hipStreamSynchronize(p->stream) == hipSuccess ? SPOCK_OK : fail(SPOCK_E_HIP, "sync");
+                if (r) return r;
+                m2[k].iters += 1;
+                m2[k].x1 = a1;
+                m2[k].x2 = a2;
+                m2[k].rel = std::max(a1, a2) / std::max(1.0, std::max(p->xi_ref[0], p->xi_ref[1]));
+                if (m2[k].rel <= b->set.eps) {
+                    m2[k].status = SPOCK_OK;
+                } else if (m2[k].iters < b->set.max_iters) {
+                    m2[k].refined = 1;
+                    m2[k].live = true;
+                } else {
+                    m2[k].status = SPOCK_E_NOT_CONVERGED;
+                }
+            }
+            r = batch_phase<double>(b, m2, false);
+            m.swap(m2);
+        }
+    }
+    if (r) return r;
+    // results
+    for (int k = 0; k < n; ++k) {
+        if (infos[k].status != SPOCK_OK && m[k].status != SPOCK_OK && m[k].iters == 0) continue;
+        spock_problem* p = b->probs[k];
+        if (prec == SPOCK_FP64 || prec == SPOCK_MIXED) {
+            p->cur = SPOCK_FP64;
+            p->s64.par = 0;
+        } else {
+            p->cur = SPOCK_FP32;
+            p->s32.par = 0;
+        }
+        p->solved = true;
+        double s0 = 0;
+        if (p->cur == SPOCK_FP64) {
+            HIP_TRY(hipMemcpy(&s0, p->s64.h.z[0], 8, hipMemcpyDeviceToHost));
+        } else {
+            float f;
+            HIP_TRY(hipMemcpy(&f, p->s32.h.z[0], 4, hipMemcpyDeviceToHost));
+            s0 = f;
+        }
+        infos[k].iters = m[k].iters;
+        infos[k].iters_fp32 = m[k].iters32;
+        infos[k].rel_res = m[k].rel;
+        infos[k].xi1_inf = m[k].x1;
+        infos[k].xi2_inf = m[k].x2;
+        infos[k].s0 = s0;
+        infos[k].status = m[k].status;
+        infos[k].precision_used = p->cur;
+        infos[k].refined = m[k].refined;
+    }
+    const double t = now_s() - t0;
+    for (int k = 0; k < n; ++k) infos[k].t_solve_s = t;
+    return SPOCK_OK;
+}
+
+int32_t spock_batch_run_steps(spock_batch* b, int32_t prec, int32_t steps, int32_t sync) {
+    if (!b || steps < 0 || (steps & 1)) return fail(SPOCK_E_INVALID, "steps must be even and >= 0");
+    if (prec != SPOCK_FP64 && prec != SPOCK_FP32) return fail(SPOCK_E_INVALID, "precision");
+    for (int k = 0; k < b->n; ++k) {
+        spock_problem* p = b->probs[k];
+        int32_t r = move_iterate(p, prec);
+        if (!r) r = normalize_parity(p);
+        if (!r) r = hipStreamSynchronize(p->stream) == hipSuccess ? SPOCK_OK : fail(SPOCK_E_HIP, "sync");
+        if (r) return r;
+    }
+    int32_t r = upload_active(b, nullptr);
+    if (!r) r = prec == SPOCK_FP64 ? batch_steps<double>(b, steps, false) : batch_steps<float>(b, steps, false);
+    if (r) return r;
+    if (sync) HIP_TRY(hipStreamSynchronize(b->stream));
+    return SPOCK_OK;
+}
+
+int32_t spock_batch_time_steps(spock_batch* b, int32_t prec, int32_t steps, double* ms_total, double* ms_b,
+                               double* ms_f) {
+    if (!b || steps < 2 || (steps & 1)) return fail(SPOCK_E_INVALID, "steps must be even and >= 2");
+    int32_t r = spock_batch_run_steps(b, prec, 0, 1);
+    if (r) return r;
+    std::vector<hipEvent_t> ev(2 * (size_t)steps + 1);
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    HIP_TRY(hipEventRecord(ev[0], b->stream));
+    for (int k = 0; k < steps; ++k) {
+        if (prec == SPOCK_FP64) {
+            HIP_TRY(spk::launch_backward<double>(b->d64, b->tasks, b->ticket, b->n_tasks, b->lds64, k & 1, 0, b->stream));
+            HIP_TRY(hipEventRecord(ev[2 * k + 1], b->stream));
+            HIP_TRY(spk::launch_forward<double>(b->d64, b->tasks, b->ticket, b->n_tasks, b->lds64, k & 1, 0, b->stream));
+        } else {
+            HIP_TRY(spk::launch_backward<float>(b->d32, b->tasks, b->ticket, b->n_tasks, b->lds32, k & 1, 0, b->stream));
+            HIP_TRY(hipEventRecord(ev[2 * k + 1], b->stream));
+            HIP_TRY(spk::launch_forward<float>(b->d32, b->tasks, b->ticket, b->n_tasks, b->lds32, k & 1, 0, b->stream));
+        }
+        HIP_TRY(hipEventRecord(ev[2 * k + 2], b->stream));
+    }
+    HIP_TRY(hipEventSynchronize(ev.back()));
+    double tb = 0, tf = 0;
+    for (int k = 0; k < steps; ++k) {
+        float a = 0, c = 0;
+        HIP_TRY(hipEventElapsedTime(&a, ev[2 * k], ev[2 * k + 1]));
+        HIP_TRY(hipEventElapsedTime(&c, ev[2 * k + 1], ev[2 * k + 2]));
+        tb += a;
+        tf += c;
+    }
+    float tot = 0;
+    HIP_TRY(hipEventElapsedTime(&tot, ev[0], ev.back()));
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (ms_total) *ms_total = tot / steps;
+    if (ms_b) *ms_b = tb / steps;
+    if (ms_f) *ms_f = tf / steps;
+    return read_all(b);
+}
+
+int32_t spock_batch_step_bytes(const spock_batch* b, int32_t prec, double* bb, double* bf) {
+    if (!b) return fail(SPOCK_E_INVALID, "null batch");
+    const int q = prec == SPOCK_FP64 ? 0 : 1;
+    if (bb) *bb = b->bytes_b[q];
+    if (bf) *bf = b->bytes_f[q];
+    return SPOCK_OK;
+}
+
+}  // extern "C"

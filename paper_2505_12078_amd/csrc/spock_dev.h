@@ -71,6 +71,7 @@ struct ProbDev {
     int* cnt;                // backward arrival counters, per node
     int* flag;               // forward claim/done flags, per node
     int* err;                // device wait timeout
+    const int* active;       // 0: this problem sits out the launch (batched form)
     unsigned long long* res; // |xi1|_inf, |xi2|_inf as float64 bit patterns
 };
 

@@ -18,44 +18,16 @@
 #include "../../include/spock.h"
 #include "spock_dev.h"
 
-namespace spk {
-template <typename real>
-hipError_t launch_step(const ProbDev<real>*, const int2*, int*, int, int, int, int, hipStream_t);
-template <typename real>
-hipError_t launch_backward(const ProbDev<real>*, const int2*, int*, int, int, int, int, hipStream_t);
-template <typename real>
-hipError_t launch_forward(const ProbDev<real>*, const int2*, int*, int, int, int, int, hipStream_t);
-template <typename real>
-hipError_t launch_apply_L(const ProbDev<real>*, int, const real*, real*, hipStream_t);
-template <typename real>
-hipError_t launch_apply_Lt(const ProbDev<real>*, int, const real*, real*, hipStream_t);
-template <typename real>
-hipError_t launch_prox_gconj(const ProbDev<real>*, int, const real*, real*, hipStream_t);
-template <typename D, typename S>
-hipError_t launch_convert(D*, const S*, long long, hipStream_t);
-template <typename T>
-hipError_t launch_fill(T*, T, long long, hipStream_t);
-}  // namespace spk
+#include "spock_internal.h"
 
 using spk::ProbDev;
 
-// ---------------------------------------------------------------------------
-// errors
-// ---------------------------------------------------------------------------
+thread_local std::string g_err;
 
-static thread_local std::string g_err;
-
-static int32_t fail(int32_t code, const std::string& msg) {
+int32_t fail(int32_t code, const std::string& msg) {
     g_err = msg;
     return code;
 }
-
-#define HIP_TRY(...)                                                                            \
-    do {                                                                                        \
-        hipError_t e_ = (__VA_ARGS__);                                                          \
-        if (e_ != hipSuccess)                                                                   \
-            return fail(SPOCK_E_HIP, std::string(#__VA_ARGS__ ": ") + hipGetErrorString(e_));    \
-    } while (0)
 
 // ---------------------------------------------------------------------------
 // small dense float64 kernels for the offline factorisation (row-major)
@@ -144,71 +116,6 @@ static void parallel_for(int n, F f) {
 }
 
 // ---------------------------------------------------------------------------
-// the handle
-// ---------------------------------------------------------------------------
-
-template <typename real>
-struct DevSet {
-    ProbDev<real> h;           // host mirror of the descriptor
-    ProbDev<real>* d = nullptr;  // the descriptor in device memory
-    int par = 0;               // which copy holds the current iterate
-    int lds_bytes = 0;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};  // check_every steps from parity 0 / 1
-    int graph_steps = 0;
-};
-
-struct spock_problem {
-    // sizes
-    int n = 0, n_nl = 0, n_leaf = 0, N = 0, nx = 0, nu = 0, m = 0, nc = 0, ncN = 0, max_ch = 0;
-    int has_ball = 0, has_ballN = 0, affine = 0;
-    long long ny = 0, nz = 0, neta = 0;
-    long long z_x, z_u, z_y, z_tau, z_s, e_y, e_s, e_c, e_soc, e_cN, e_socN;
-    long long M_stride = 0, KR_stride = 0;
-    std::vector<int> parent, first_child, n_ch, y_off;
-    // scaled problem data
-    std::vector<double> Sx, Su, SxN;
-    std::vector<double> qh, rh, qnh, gx, gu, gb, gxN, gbN, lo, hi, loN, hiN, prob, gamma;
-    double ball_r = 0, ballN_r = 0, con_scale = 1, con_scaleN = 1;
-    double Lnorm = 0, alpha = 0;
-    // unscaled root constraint for the x0 check
-    std::vector<double> x_lo, x_hi;
-    double x_ball = 0;
-    std::vector<double> x0s;   // scaled x0 currently on the device
-    spock_settings set{};
-    // device
-    void* base = nullptr;
-    bool owns = false;
-    size_t bytes = 0;
-    hipStream_t stream = nullptr;
-    bool owns_stream = false;
-    int* d_tree = nullptr;
-    int* d_cnt = nullptr;
-    int* d_flag = nullptr;
-    int* d_path = nullptr;
-    int* d_top = nullptr;
-    int* d_ticket = nullptr;
-    int2* d_tasks = nullptr;
-    unsigned long long* d_res = nullptr;
-    int* d_err = nullptr;
-    double* d_stash_z = nullptr;
-    double* d_stash_e = nullptr;
-    DevSet<double> s64;
-    DevSet<float> s32;
-    int cur = SPOCK_FP64;      // precision holding the current iterate
-    unsigned long long* h_res = nullptr;  // pinned readback: res[2], err
-    bool have_ref = false;
-    double xi_ref[2] = {0, 0};
-    bool solved = false;
-};
-
-template <typename real>
-static DevSet<real>& set_of(spock_problem* p);
-template <>
-DevSet<double>& set_of<double>(spock_problem* p) { return p->s64; }
-template <>
-DevSet<float>& set_of<float>(spock_problem* p) { return p->s32; }
-
-// ---------------------------------------------------------------------------
 // memory plan: one arena, 256-byte aligned sub-buffers
 // ---------------------------------------------------------------------------
 
@@ -263,7 +170,7 @@ static void carve(Arena& a, spock_problem* p) {
     p->d_flag = a.take<int>(p->n);
     p->d_path = a.take<int>((long long)p->n_leaf * (p->N + 1));
     p->d_top = a.take<int>(p->n_leaf);
-    p->d_ticket = a.take<int>(4);
+    p->d_ticket = a.take<int>(4);  // [0] forward ticket, [1] constant 1 (active flag)
     p->d_tasks = a.take<int2>(p->n_leaf);
     p->d_res = a.take<unsigned long long>(4);
     p->d_err = a.take<int>(4);
@@ -647,6 +554,7 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     h.flag = p->d_flag;
     h.path = p->d_path;
     h.top_owned = p->d_top;
+    h.active = p->d_ticket + 1;
     h.err = p->d_err;
     h.res = p->d_res;
     s.lds_bytes = spk::lds_elems(p->nx, p->nu, p->max_ch) * (int)sizeof(real);
@@ -685,7 +593,7 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
 // ---------------------------------------------------------------------------
 
 template <typename real>
-static int32_t step(spock_problem* p, int check) {
+int32_t step(spock_problem* p, int check) {
     DevSet<real>& s = set_of<real>(p);
     HIP_TRY(spk::launch_step<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, s.par, check,
                                    p->stream));
@@ -734,7 +642,7 @@ static int32_t chunk(spock_problem* p, int steps) {
     return SPOCK_OK;
 }
 
-static int32_t read_res(spock_problem* p, double* xi1, double* xi2) {
+int32_t read_res(spock_problem* p, double* xi1, double* xi2) {
     HIP_TRY(hipMemcpyAsync(p->h_res, p->d_res, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipMemcpyAsync(p->h_res + 2, p->d_err, sizeof(int), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
@@ -752,7 +660,7 @@ static int32_t read_res(spock_problem* p, double* xi1, double* xi2) {
 }
 
 // current iterate -> the other precision's copy `par`
-static int32_t move_iterate(spock_problem* p, int to) {
+int32_t move_iterate(spock_problem* p, int to) {
     if (p->cur == to) return SPOCK_OK;
     if (to == SPOCK_FP64) {
         HIP_TRY(spk::launch_convert<double, float>(p->s64.h.z[0], p->s32.h.z[p->s32.par], p->nz, p->stream));
@@ -767,7 +675,7 @@ static int32_t move_iterate(spock_problem* p, int to) {
     return SPOCK_OK;
 }
 
-static int32_t zero_iterate(spock_problem* p) {
+int32_t zero_iterate(spock_problem* p) {
     HIP_TRY(spk::launch_fill<double>(p->s64.h.z[0], 0.0, p->nz, p->stream));
     HIP_TRY(spk::launch_fill<double>(p->s64.h.eta[0], 0.0, p->neta, p->stream));
     p->s64.par = 0;
@@ -775,7 +683,7 @@ static int32_t zero_iterate(spock_problem* p) {
     return SPOCK_OK;
 }
 
-static int32_t set_x0_device(spock_problem* p, const double* x0, bool check_feasible) {
+int32_t set_x0_device(spock_problem* p, const double* x0, bool check_feasible) {
     if (!x0) return fail(SPOCK_E_INVALID, "null x0");
     if (!finite_all(x0, p->nx)) return fail(SPOCK_E_INVALID, "non-finite x0");
     if (check_feasible) {
@@ -798,6 +706,57 @@ static int32_t set_x0_device(spock_problem* p, const double* x0, bool check_feas
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// The iterate of the current precision moved to copy 0 (batched steps keep
+// every member at the same parity).
+int32_t normalize_parity(spock_problem* p) {
+    if (p->cur == SPOCK_FP64 && p->s64.par == 1) {
+        HIP_TRY(hipMemcpyAsync(p->s64.h.z[0], p->s64.h.z[1], p->nz * 8, hipMemcpyDeviceToDevice, p->stream));
+        HIP_TRY(hipMemcpyAsync(p->s64.h.eta[0], p->s64.h.eta[1], p->neta * 8, hipMemcpyDeviceToDevice, p->stream));
+        p->s64.par = 0;
+    }
+    if (p->cur != SPOCK_FP64 && p->s32.par == 1) {
+        HIP_TRY(hipMemcpyAsync(p->s32.h.z[0], p->s32.h.z[1], p->nz * 4, hipMemcpyDeviceToDevice, p->stream));
+        HIP_TRY(hipMemcpyAsync(p->s32.h.eta[0], p->s32.h.eta[1], p->neta * 4, hipMemcpyDeviceToDevice, p->stream));
+        p->s32.par = 0;
+    }
+    return SPOCK_OK;
+}
+
+// Reference residuals of the first float64 CP step from zero (x0 already on
+// the device).  A cold start (warm = false) keeps that step as iteration 1 and
+// reports it in *taken; a warm start keeps its iterate untouched.
+int32_t ensure_ref(spock_problem* p, bool warm, long long* taken, double* x1, double* x2) {
+    *taken = 0;
+    if (p->have_ref && warm) return SPOCK_OK;
+    if (warm) {
+        int32_t r = move_iterate(p, SPOCK_FP64);
+        if (r) return r;
+        HIP_TRY(hipMemcpyAsync(p->d_stash_z, p->s64.h.z[p->s64.par], p->nz * 8, hipMemcpyDeviceToDevice, p->stream));
+        HIP_TRY(hipMemcpyAsync(p->d_stash_e, p->s64.h.eta[p->s64.par], p->neta * 8, hipMemcpyDeviceToDevice,
+                               p->stream));
+    }
+    int32_t r = zero_iterate(p);
+    if (!r) r = step<double>(p, 1);
+    if (!r) r = read_res(p, x1, x2);
+    if (r) return r;
+    p->xi_ref[0] = *x1;
+    p->xi_ref[1] = *x2;
+    p->have_ref = true;
+    if (warm) {
+        HIP_TRY(hipMemcpyAsync(p->s64.h.z[0], p->d_stash_z, p->nz * 8, hipMemcpyDeviceToDevice, p->stream));
+        HIP_TRY(hipMemcpyAsync(p->s64.h.eta[0], p->d_stash_e, p->neta * 8, hipMemcpyDeviceToDevice, p->stream));
+        p->s64.par = 0;
+        p->cur = SPOCK_FP64;
+    } else {
+        *taken = 1;
+    }
+    return SPOCK_OK;
+}
 
 extern "C" {
 
@@ -917,7 +876,8 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
         e = spk::launch_fill<int>(p->d_cnt, 0, p->n, p->stream);
         if (e == hipSuccess) e = spk::launch_fill<int>(p->d_flag, 0, p->n, p->stream);
         if (e == hipSuccess) e = spk::launch_fill<int>(p->d_err, 0, 4, p->stream);
-        if (e == hipSuccess) e = spk::launch_fill<int>(p->d_ticket, 0, 4, p->stream);
+        if (e == hipSuccess) e = spk::launch_fill<int>(p->d_ticket, 0, 1, p->stream);
+        if (e == hipSuccess) e = spk::launch_fill<int>(p->d_ticket + 1, 1, 1, p->stream);
         if (e == hipSuccess) e = spk::launch_fill<unsigned long long>(p->d_res, 0ull, 4, p->stream);
         if (e != hipSuccess) {
             spock_problem_destroy(p);
@@ -987,9 +947,6 @@ int32_t spock_set_x0(spock_problem* p, const double* x0) {
     return set_x0_device(p, x0, false);
 }
 
-static double now_s() {
-    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
 
 // Run chunks in one precision until rel_res <= eps, the step budget is spent,
 // or (float32 only) progress stalls.  Returns SPOCK_OK on convergence.
@@ -1361,3 +1318,6 @@ int32_t spock_step_bytes(const spock_problem* p, int32_t prec, double* bb, doubl
 }
 
 }  // extern "C"
+
+template int32_t step<double>(spock_problem*, int);
+template int32_t step<float>(spock_problem*, int);

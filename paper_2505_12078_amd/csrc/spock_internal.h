@@ -1,0 +1,122 @@
+// Internal declarations shared by the host sources of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/spock.h"
+#include "spock_dev.h"
+
+namespace spk {
+template <typename real>
+hipError_t launch_step(const ProbDev<real>*, const int2*, int*, int, int, int, int, hipStream_t);
+template <typename real>
+hipError_t launch_backward(const ProbDev<real>*, const int2*, int*, int, int, int, int, hipStream_t);
+template <typename real>
+hipError_t launch_forward(const ProbDev<real>*, const int2*, int*, int, int, int, int, hipStream_t);
+template <typename real>
+hipError_t launch_apply_L(const ProbDev<real>*, int, const real*, real*, hipStream_t);
+template <typename real>
+hipError_t launch_apply_Lt(const ProbDev<real>*, int, const real*, real*, hipStream_t);
+template <typename real>
+hipError_t launch_prox_gconj(const ProbDev<real>*, int, const real*, real*, hipStream_t);
+template <typename D, typename S>
+hipError_t launch_convert(D*, const S*, long long, hipStream_t);
+template <typename T>
+hipError_t launch_fill(T*, T, long long, hipStream_t);
+}  // namespace spk
+
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+extern thread_local std::string g_err;
+int32_t fail(int32_t code, const std::string& msg);
+
+#define HIP_TRY(...)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (__VA_ARGS__);                                                          \
+        if (e_ != hipSuccess)                                                                   \
+            return fail(SPOCK_E_HIP, std::string(#__VA_ARGS__ ": ") + hipGetErrorString(e_));    \
+    } while (0)
+
+using spk::ProbDev;
+
+// ---------------------------------------------------------------------------
+// the handle
+// ---------------------------------------------------------------------------
+
+template <typename real>
+struct DevSet {
+    ProbDev<real> h;           // host mirror of the descriptor
+    ProbDev<real>* d = nullptr;  // the descriptor in device memory
+    int par = 0;               // which copy holds the current iterate
+    int lds_bytes = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // check_every steps from parity 0 / 1
+    int graph_steps = 0;
+};
+
+struct spock_problem {
+    // sizes
+    int n = 0, n_nl = 0, n_leaf = 0, N = 0, nx = 0, nu = 0, m = 0, nc = 0, ncN = 0, max_ch = 0;
+    int has_ball = 0, has_ballN = 0, affine = 0;
+    long long ny = 0, nz = 0, neta = 0;
+    long long z_x, z_u, z_y, z_tau, z_s, e_y, e_s, e_c, e_soc, e_cN, e_socN;
+    long long M_stride = 0, KR_stride = 0;
+    std::vector<int> parent, first_child, n_ch, y_off;
+    // scaled problem data
+    std::vector<double> Sx, Su, SxN;
+    std::vector<double> qh, rh, qnh, gx, gu, gb, gxN, gbN, lo, hi, loN, hiN, prob, gamma;
+    double ball_r = 0, ballN_r = 0, con_scale = 1, con_scaleN = 1;
+    double Lnorm = 0, alpha = 0;
+    // unscaled root constraint for the x0 check
+    std::vector<double> x_lo, x_hi;
+    double x_ball = 0;
+    std::vector<double> x0s;   // scaled x0 currently on the device
+    spock_settings set{};
+    // device
+    void* base = nullptr;
+    bool owns = false;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    int* d_tree = nullptr;
+    int* d_cnt = nullptr;
+    int* d_flag = nullptr;
+    int* d_path = nullptr;
+    int* d_top = nullptr;
+    int* d_ticket = nullptr;
+    int2* d_tasks = nullptr;
+    unsigned long long* d_res = nullptr;
+    int* d_err = nullptr;
+    double* d_stash_z = nullptr;
+    double* d_stash_e = nullptr;
+    DevSet<double> s64;
+    DevSet<float> s32;
+    int cur = SPOCK_FP64;      // precision holding the current iterate
+    unsigned long long* h_res = nullptr;  // pinned readback: res[2], err
+    bool have_ref = false;
+    double xi_ref[2] = {0, 0};
+    bool solved = false;
+};
+
+template <typename real>
+static DevSet<real>& set_of(spock_problem* p);
+template <>
+inline DevSet<double>& set_of<double>(spock_problem* p) { return p->s64; }
+template <>
+inline DevSet<float>& set_of<float>(spock_problem* p) { return p->s32; }
+
+// handle operations used by the batched and served forms
+template <typename real>
+int32_t step(spock_problem* p, int check);
+int32_t read_res(spock_problem* p, double* xi1, double* xi2);
+int32_t move_iterate(spock_problem* p, int to);
+int32_t zero_iterate(spock_problem* p);
+int32_t set_x0_device(spock_problem* p, const double* x0, bool check_feasible);
+double now_s();
+int32_t normalize_parity(spock_problem* p);
+int32_t ensure_ref(spock_problem* p, bool warm, long long* taken, double* x1, double* x2);

@@ -231,6 +231,7 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
     real* sm = reinterpret_cast<real*>(smem_raw);
     const int2 tk = tasks[blockIdx.x];
     const ProbDev<real>* __restrict__ P = probs + tk.x;
+    if (*P->active == 0) return;
     const int nx = P->nx, nu = P->nu, m = P->m, N = P->N;
     const real alpha = P->alpha;
     const real* __restrict__ zin = P->z[par];
@@ -638,6 +639,7 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
     __syncthreads();
     const int2 tk = tasks[s_task];
     const ProbDev<real>* __restrict__ P = probs + tk.x;
+    if (*P->active == 0) return;
     const int nx = P->nx, nu = P->nu, m = P->m, N = P->N;
     const real ialpha = real(1) / P->alpha;
     const real* __restrict__ zin = P->z[par];

@@ -83,6 +83,15 @@ SIGNATURES = {
     "spock_time_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp]),
     "spock_step_bytes": (C.c_int32, [C.c_void_p, C.c_int32, _dp, _dp]),
     "spock_run_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    "spock_batch_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(Settings),
+                                       C.POINTER(C.c_void_p)]),
+    "spock_batch_destroy": (C.c_int32, [C.c_void_p]),
+    "spock_batch_size": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_size_t)]),
+    "spock_batch_solve": (C.c_int32, [C.c_void_p, C.POINTER(_dp), _ip, C.POINTER(Info)]),
+    "spock_batch_run_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    "spock_batch_time_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp]),
+    "spock_batch_step_bytes": (C.c_int32, [C.c_void_p, C.c_int32, _dp, _dp]),
 }
 
 _lib = None
@@ -278,4 +287,56 @@ class Problem:
     def step_bytes(self, precision=FP64):
         b, f = C.c_double(), C.c_double()
         _check(load().spock_step_bytes(self.h, precision, C.byref(b), C.byref(f)))
+        return b.value, f.value
+
+
+class Batch:
+    """Many problems advanced by one backward and one forward launch per step."""
+
+    def __init__(self, problems, settings=None, **kw):
+        lib = load()
+        self._lib = lib
+        self.problems = list(problems)
+        self.settings = settings or default_settings(**kw)
+        arr = (C.c_void_p * len(self.problems))(*[p.h.value for p in self.problems])
+        h = C.c_void_p()
+        _check(lib.spock_batch_create(arr, len(self.problems), C.byref(self.settings), C.byref(h)))
+        self.h = h
+        npb, nt, nb = C.c_int32(), C.c_int32(), C.c_size_t()
+        _check(lib.spock_batch_size(h, C.byref(npb), C.byref(nt), C.byref(nb)))
+        self.n_tasks, self.device_bytes = nt.value, nb.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.spock_batch_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def solve(self, x0s, warm=None):
+        n = len(self.problems)
+        keep = [np.ascontiguousarray(x, dtype=np.float64) for x in x0s]
+        ptrs = (_dp * n)(*[_ptr(x) for x in keep])
+        w = None if warm is None else np.ascontiguousarray(warm, dtype=np.int32)
+        infos = (Info * n)()
+        _check(load().spock_batch_solve(self.h, ptrs, None if w is None else _ptr(w, np.int32), infos))
+        return [i.as_dict() for i in infos]
+
+    def run_steps(self, steps, precision=FP64, sync=True):
+        _check(load().spock_batch_run_steps(self.h, precision, int(steps), int(bool(sync))))
+
+    def time_steps(self, steps, precision=FP64):
+        t, b, f = C.c_double(), C.c_double(), C.c_double()
+        _check(load().spock_batch_time_steps(self.h, precision, int(steps), C.byref(t), C.byref(b), C.byref(f)))
+        return t.value, b.value, f.value
+
+    def step_bytes(self, precision=FP64):
+        b, f = C.c_double(), C.c_double()
+        _check(load().spock_batch_step_bytes(self.h, precision, C.byref(b), C.byref(f)))
         return b.value, f.value

@@ -1,0 +1,89 @@
+"""Batched form: uneven trees in one launch give each member the result it
+gets alone (bitwise: the same kernels run the same per-node arithmetic), and
+a failing member does not disturb the others."""
+import numpy as np
+import pytest
+
+from oracle import spock_oracle as O
+from paper_2505_12078_amd import spock as S
+from paper_2505_12078_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need an MI355X; none is visible")
+    S.load()
+
+
+def _members():
+    probs = [W.config_problem(0), W.random_ragged_problem(5, N=4, nx=4, nu=2, max_children=3),
+             W.random_ragged_problem(6, N=3, nx=6, nu=3, max_children=4, affine=True)]
+    probs += [W.batch_problem(k) for k in range(5)]
+    return probs
+
+
+@pytest.mark.parametrize("precision,eps", [(S.FP64, 1e-5), (S.MIXED, 1e-4)])
+def test_batch_equals_alone(precision, eps):
+    probs = _members()
+    settings = dict(eps=eps, max_iters=60000, precision=precision)
+    alone = []
+    for p in probs:
+        with S.Problem(p, S.default_settings(**settings)) as P:
+            info = P.solve(p["x0"])
+            alone.append((info, P.solution()))
+    handles = [S.Problem(p, S.default_settings(**settings)) for p in probs]
+    with S.Batch(handles, S.default_settings(**settings)) as B:
+        infos = B.solve([p["x0"] for p in probs])
+    for k, (p, h) in enumerate(zip(probs, handles)):
+        a_info, (ax, au, as0) = alone[k]
+        b_info = infos[k]
+        assert b_info["status"] == a_info["code"], (k, b_info, a_info)
+        assert b_info["iters"] == a_info["iters"], (k, b_info["iters"], a_info["iters"])
+        x, u, s0 = h.solution()
+        assert np.array_equal(x, ax) and np.array_equal(u, au) and s0 == as0, k
+        if b_info["status"] == S.SPOCK_OK:
+            assert O.nested_cost(p, x, u) == pytest.approx(s0, rel=50 * eps)
+        h.close()
+
+
+def test_batch_member_failure_is_isolated():
+    probs = _members()[:4]
+    handles = [S.Problem(p, S.default_settings(eps=1e-5)) for p in probs]
+    x0s = [p["x0"] for p in probs]
+    x0s[1] = np.full_like(x0s[1], 100.0)  # outside the root box
+    with S.Batch(handles, S.default_settings(eps=1e-5, max_iters=60000)) as B:
+        infos = B.solve(x0s)
+    assert infos[1]["status"] == S.SPOCK_E_INFEASIBLE_X0
+    for k in (0, 2, 3):
+        assert infos[k]["status"] == S.SPOCK_OK, infos[k]
+        with S.Problem(probs[k], S.default_settings(eps=1e-5)) as P:
+            P.solve(probs[k]["x0"])
+            assert np.array_equal(P.solution()[0], handles[k].solution()[0])
+    for h in handles:
+        h.close()
+
+
+def test_batch_warm_start_after_shift():
+    """MPC use: the next request shifts x0 and warm-starts from the resident
+    iterate; the warm result equals a cold solve of the shifted problem up to
+    the tolerance and takes fewer steps."""
+    probs = _members()[:3]
+    handles = [S.Problem(p, S.default_settings(eps=1e-5)) for p in probs]
+    with S.Batch(handles, S.default_settings(eps=1e-5, max_iters=60000)) as B:
+        cold = B.solve([p["x0"] for p in probs])
+        x1 = [0.9 * p["x0"] for p in probs]
+        warm = B.solve(x1, warm=[1] * len(probs))
+    for k, p in enumerate(probs):
+        assert warm[k]["status"] == S.SPOCK_OK
+        q = dict(p)
+        q["x0"] = x1[k]
+        with S.Problem(q, S.default_settings(eps=1e-5)) as P:
+            ref = P.solve(q["x0"])
+        assert warm[k]["s0"] == pytest.approx(ref["s0"], rel=1e-3)
+        assert warm[k]["iters"] <= cold[k]["iters"] + 20
+    for h in handles:
+        h.close()
