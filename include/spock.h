@@ -246,6 +246,55 @@ int32_t spock_batch_time_steps(spock_batch* b, int32_t precision, int32_t steps,
 int32_t spock_batch_step_bytes(const spock_batch* b, int32_t precision, double* bytes_backward,
                                double* bytes_forward);
 
+/*
+ * Served form: continuous batching of MPC requests.
+ *
+ * A server owns a worker thread that drives the current HIP device.  Trees
+ * are registered once (the description is copied; its device footprint is
+ * computed without touching the device).  Requests (tree, x0) may be submitted
+ * from any thread at any time; a request starts as soon as its tree has no
+ * other request in flight and the tree is resident or fits in hbm_budget
+ * bytes (idle trees are evicted least recently used first).  A resident tree
+ * keeps its offline factors and its last iterate: its next request warm-starts
+ * from it.  All requests in flight advance together, one batched chunk of
+ * check_every CP steps per tick; requests that arrive in between join at the
+ * next tick.  Each request's result equals the result of the same sequence of
+ * spock_solve calls on that tree alone.
+ */
+typedef struct spock_server spock_server;
+
+typedef struct spock_result {
+    uint64_t req_id;
+    int64_t tree_id;
+    int32_t status;          /* SPOCK_OK, SPOCK_E_NOT_CONVERGED, SPOCK_E_DIVERGED, SPOCK_E_INFEASIBLE_X0 */
+    int32_t warm;            /* 1: started from the tree's resident iterate */
+    spock_info info;         /* iters, residuals, s0 (t_solve_s = admission to completion) */
+    double t_submit, t_admit, t_done;  /* spock_now() clock, seconds */
+} spock_result;
+
+typedef struct spock_server_stats {
+    uint64_t submitted, completed, created, evicted, ticks;
+    size_t resident_bytes, budget_bytes, pending, in_flight;
+} spock_server_stats;
+
+/* Errors: SPOCK_E_INVALID. */
+int32_t spock_server_create(size_t hbm_budget, const spock_settings* s, spock_server** out);
+/* SPOCK_E_CAPACITY if the tree alone exceeds the budget; SPOCK_E_INVALID for bad data. */
+int32_t spock_server_add_tree(spock_server* srv, const spock_problem_desc* desc, int64_t* tree_id);
+/* Thread-safe; x0 is copied ([nx] of the tree, unscaled). */
+int32_t spock_server_submit(spock_server* srv, int64_t tree_id, const double* x0, uint64_t req_id);
+/* Thread-safe, non-blocking: moves up to max finished results to out. */
+int32_t spock_server_poll(spock_server* srv, spock_result* out, int32_t max, int32_t* n_out);
+/* Block until nothing is pending or in flight (SPOCK_E_NOT_CONVERGED on timeout). */
+int32_t spock_server_wait_idle(spock_server* srv, double timeout_s);
+int32_t spock_server_get_stats(spock_server* srv, spock_server_stats* out);
+/* Unscaled solution of the tree's last request (tree idle and resident). */
+int32_t spock_server_solution(spock_server* srv, int64_t tree_id, double* x, double* u, double* s0);
+/* Stops the worker and frees every resident tree. */
+int32_t spock_server_destroy(spock_server* srv);
+/* The monotonic clock of the t_* fields. */
+double spock_now(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,40 +13,8 @@
 
 #include "spock_internal.h"
 
-struct spock_batch {
-    std::vector<spock_problem*> probs;
-    int n = 0;
-    spock_settings set{};
-    hipStream_t stream = nullptr;
-    void* base = nullptr;
-    size_t bytes = 0;
-    ProbDev<double>* d64 = nullptr;
-    ProbDev<float>* d32 = nullptr;
-    int2* tasks = nullptr;
-    int n_tasks = 0;
-    int* active = nullptr;
-    int* ticket = nullptr;
-    int* err = nullptr;
-    unsigned long long* res = nullptr;
-    int lds64 = 0, lds32 = 0;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};  // [0] float64, [1] float32
-    int graph_steps[2] = {0, 0};
-    unsigned long long* h_res = nullptr;  // pinned: 2n residual slots, then n error flags
-    std::vector<int> h_active;
-    double bytes_b[2] = {0, 0}, bytes_f[2] = {0, 0};
-};
-
 namespace {
 
-struct Member {
-    bool live = false;      // still iterating in the current phase
-    long long iters = 0, iters32 = 0;
-    double rel = INFINITY, x1 = INFINITY, x2 = INFINITY;
-    double best = INFINITY;
-    int no_gain = 0;
-    int32_t status = SPOCK_E_NOT_CONVERGED;
-    int refined = 0;
-};
 
 template <typename real>
 ProbDev<real>* dev_of(spock_batch* b);
@@ -110,15 +78,13 @@ int32_t read_all(spock_batch* b) {
     return SPOCK_OK;
 }
 
-// Iterate every live member in one precision until it converges, stalls
-// (float32 only) or spends its budget.
+}  // namespace
+
+// One chunk of check_every steps for the live members; updates their state.
 template <typename real>
-int32_t batch_phase(spock_batch* b, std::vector<Member>& m, bool stall_exit) {
+int32_t batch_tick(spock_batch* b, std::vector<Member>& m, bool stall_exit) {
     const int ce = b->set.check_every;
-    for (;;) {
-        bool any = false;
-        for (auto& x : m) any = any || x.live;
-        if (!any) return SPOCK_OK;
+    {
         int32_t r = upload_active(b, &m);
         if (!r) r = batch_chunk<real>(b, ce);
         if (!r) r = read_all(b);
@@ -152,9 +118,23 @@ int32_t batch_phase(spock_batch* b, std::vector<Member>& m, bool stall_exit) {
             }
         }
     }
+    return SPOCK_OK;
 }
+template int32_t batch_tick<double>(spock_batch*, std::vector<Member>&, bool);
+template int32_t batch_tick<float>(spock_batch*, std::vector<Member>&, bool);
 
-}  // namespace
+// Iterate every live member in one precision until it converges, stalls
+// (float32 only) or spends its budget.
+template <typename real>
+static int32_t batch_phase(spock_batch* b, std::vector<Member>& m, bool stall_exit) {
+    for (;;) {
+        bool any = false;
+        for (auto& x : m) any = any || x.live;
+        if (!any) return SPOCK_OK;
+        int32_t r = batch_tick<real>(b, m, stall_exit);
+        if (r) return r;
+    }
+}
 
 extern "C" {
 

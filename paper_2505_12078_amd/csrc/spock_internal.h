@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -120,3 +121,41 @@ int32_t set_x0_device(spock_problem* p, const double* x0, bool check_feasible);
 double now_s();
 int32_t normalize_parity(spock_problem* p);
 int32_t ensure_ref(spock_problem* p, bool warm, long long* taken, double* x1, double* x2);
+
+// Batched form (spock_batch.cpp).
+struct spock_batch {
+    std::vector<spock_problem*> probs;
+    int n = 0;
+    spock_settings set{};
+    hipStream_t stream = nullptr;
+    void* base = nullptr;
+    size_t bytes = 0;
+    ProbDev<double>* d64 = nullptr;
+    ProbDev<float>* d32 = nullptr;
+    int2* tasks = nullptr;
+    int n_tasks = 0;
+    int* active = nullptr;
+    int* ticket = nullptr;
+    int* err = nullptr;
+    unsigned long long* res = nullptr;
+    int lds64 = 0, lds32 = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // [0] float64, [1] float32
+    int graph_steps[2] = {0, 0};
+    unsigned long long* h_res = nullptr;  // pinned: 2n residual slots, then n error flags
+    std::vector<int> h_active;
+    double bytes_b[2] = {0, 0}, bytes_f[2] = {0, 0};
+};
+
+// State of one problem inside a batched iteration.
+struct Member {
+    bool live = false;  // iterating in the current phase
+    long long iters = 0, iters32 = 0;
+    double rel = INFINITY, x1 = INFINITY, x2 = INFINITY;
+    double best = INFINITY;
+    int no_gain = 0;
+    int32_t status = SPOCK_E_NOT_CONVERGED;
+    int refined = 0;
+};
+
+template <typename real>
+int32_t batch_tick(spock_batch* b, std::vector<Member>& m, bool stall_exit);

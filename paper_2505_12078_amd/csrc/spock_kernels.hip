@@ -144,6 +144,116 @@ SPK_DEV void mat_vec(const real* __restrict__ A, int R, int C, long long ld, con
     __syncthreads();
 }
 
+// Register-prefetched forms of the two products.  The loads of a node's
+// matrices do not depend on the sweep's vectors, so they are issued as soon as
+// the node is known and consumed after the vectors are ready: one memory
+// latency per node instead of one per batch of dependent loads.
+
+// Transposed product, thread (g, c) with G = kWG / C row groups (needs C <= kWG):
+// rows g + i G for i < RB live in registers, any further rows are read directly.
+template <typename real, int RB>
+struct TTile {
+    real a[RB];
+};
+
+template <typename real, int RB>
+SPK_DEV void t_load(TTile<real, RB>& T, const real* __restrict__ A, int R, int C, long long ld) {
+    const int t = threadIdx.x, G = kWG / C, g = t / C, c = t - g * C;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        const int r = g + i * G;
+        T.a[i] = (g < G && r < R) ? A[(long long)r * ld + c] : real(0);
+    }
+}
+
+// out[c] = sum_r A[r][c] (c < split ? va[r] : vb[r]) from a loaded tile.
+template <typename real, int RB>
+SPK_DEV void t_apply(const TTile<real, RB>& T, const real* __restrict__ A, int R, int C, long long ld, int split,
+                     const real* va, const real* vb, real* out, real* red) {
+    const int t = threadIdx.x, G = kWG / C, g = t / C, c = t - g * C;
+    real acc = 0;
+    if (g < G) {
+        const real* v = c < split ? va : vb;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int r = g + i * G;
+            if (r < R) acc += T.a[i] * v[r];
+        }
+        for (int r = g + RB * G; r < R; r += G) acc += A[(long long)r * ld + c] * v[r];
+    }
+    __syncthreads();
+    red[t] = acc;
+    __syncthreads();
+    if (t < C) {
+        real s = 0;
+        for (int k = 0; k < G; ++k) s += red[k * C + t];
+        out[t] = s;
+    }
+    __syncthreads();
+}
+
+// Plain product, a power-of-two segment of W lanes per row: rows seg + i nseg
+// for i < RB and columns k + j W for j < CB live in registers.
+template <typename real, int RB, int CB>
+struct PTile {
+    real a[RB][CB];
+};
+
+SPK_DEV int seg_width(int C) {
+    int W = 1;
+    while (W < C && W < 64) W <<= 1;
+    return W;
+}
+
+template <typename real, int RB, int CB>
+SPK_DEV void p_load(PTile<real, RB, CB>& T, const real* __restrict__ A, int R, int C, long long ld) {
+    const int W = seg_width(C), t = threadIdx.x, nseg = kWG / W, seg = t / W, k = t - seg * W;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        const int r = seg + i * nseg;
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+            const int c = k + j * W;
+            T.a[i][j] = (r < R && c < C) ? A[(long long)r * ld + c] : real(0);
+        }
+    }
+}
+
+template <typename real, int RB, int CB>
+SPK_DEV void p_apply(const PTile<real, RB, CB>& T, const real* __restrict__ A, int R, int C, long long ld,
+                     const real* v, real* out) {
+    const int W = seg_width(C), t = threadIdx.x, nseg = kWG / W, seg = t / W, k = t - seg * W;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        if (i * nseg >= R) break;  // uniform over the workgroup
+        const int r = seg + i * nseg;
+        real acc = 0;
+        if (r < R) {
+#pragma unroll
+            for (int j = 0; j < CB; ++j)
+                if (k + j * W < C) acc += T.a[i][j] * v[k + j * W];
+            for (int c = k + CB * W; c < C; c += W) acc += A[(long long)r * ld + c] * v[c];
+        }
+        for (int o = W >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, W);
+        if (k == 0 && r < R) out[r] = acc;
+    }
+    for (int r0 = RB * nseg; r0 < R; r0 += nseg) {
+        const int r = r0 + seg;
+        real acc = 0;
+        if (r < R)
+            for (int c = k; c < C; c += W) acc += A[(long long)r * ld + c] * v[c];
+        for (int o = W >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, W);
+        if (k == 0 && r < R) out[r] = acc;
+    }
+    __syncthreads();
+}
+
+// Register tile sizes (rows per thread kept in registers).
+constexpr int kRBM = 20;  // [Abar|B]^T in the backward sweep
+constexpr int kRBK = 12;  // [K|R~^-1]^T in the backward sweep
+constexpr int kRBP = 16;  // [Abar|B] rows in the forward sweep (two column chunks)
+constexpr int kRBQ = 8;   // K rows in the forward sweep
+
 // Wait until a node's forward result is published; false on timeout.
 SPK_DEV bool wait_done(int* flag) {
     const uint64_t t0 = wall_clock64();
@@ -253,9 +363,12 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
     }
     __syncthreads();
 
+    const bool tiles = m <= kWG;  // one column tile: register-prefetched products
     // ---- leaf: q = -xbar, message [Abar|B]^T (q + P c) ----
     int j = s_path[N];
     {
+        TTile<real, kRBM> TM;
+        if (tiles) t_load(TM, P->M + j * P->M_stride, nx, m, m);
         const long long lf = j - P->n_nl;
         const real* ecN = ein + P->e_cN + lf * P->ncN;
         const real* esN = ein + P->e_socN + lf * (nx + 2);
@@ -268,7 +381,8 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
         }
         if (t == 0) P->flag[j] = 0;
         __syncthreads();
-        mat_t_vec(P->M + j * P->M_stride, nx, m, m, m, xb, xb, o, red);
+        if (tiles) t_apply(TM, P->M + j * P->M_stride, nx, m, m, m, xb, xb, o, red);
+        else mat_t_vec(P->M + j * P->M_stride, nx, m, m, m, xb, xb, o, red);
     }
 
     // ---- walk up ----
@@ -299,6 +413,12 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
             for (int c = t; c < m; c += kWG) g[c] = o[c];
         }
 
+        TTile<real, kRBK> TK;
+        TTile<real, kRBM> TM;
+        if (tiles) {
+            t_load(TK, P->KR + i * P->KR_stride, nu, m, m);
+            if (i > 0) t_load(TM, P->M + i * P->M_stride, nx, m, m);
+        }
         // zbar for (x^i, u^i): L* gathers the constraint rows and the SOC rows of
         // every child edge (Sec. 4.4)
         const real* ec = ein + P->e_c + (long long)i * P->nc;
@@ -321,7 +441,8 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
         if ((t >> 6) == (kWG / 64) - 1) s2_block_wave(P, i, zin, ein, zout, lam);
         __syncthreads();
         // [K^T ubar ; R~^-1 (ubar - g_u)] in one pass over [K | R~^-1]
-        mat_t_vec(P->KR + i * P->KR_stride, nu, m, m, nx, ub, w2, o, red);
+        if (tiles) t_apply(TK, P->KR + i * P->KR_stride, nu, m, m, nx, ub, w2, o, red);
+        else mat_t_vec(P->KR + i * P->KR_stride, nu, m, m, nx, ub, w2, o, red);
         for (int r = t; r < nx; r += kWG) {
             real h = -xb[r] - o[r] + g[r];
             if (P->affine && i > 0) h += P->Pc[(long long)i * nx + r];
@@ -340,7 +461,8 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
             return;
         }
         __syncthreads();
-        mat_t_vec(P->M + i * P->M_stride, nx, m, m, m, xb, xb, o, red);
+        if (tiles) t_apply(TM, P->M + i * P->M_stride, nx, m, m, m, xb, xb, o, red);
+        else mat_t_vec(P->M + i * P->M_stride, nx, m, m, m, xb, xb, o, red);
         j = i;
     }
 }
@@ -689,12 +811,17 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
     real r1 = 0, r2 = 0;  // residual maxima of this thread
     for (int lev = L; lev <= N; ++lev) {
         const int v = s_path[lev];
+        const bool nonleaf = v < P->n_nl;
+        PTile<real, kRBP, 2> TM;
+        PTile<real, kRBQ, 1> TK;
+        if (v > 0) p_load(TM, P->M + v * P->M_stride, nx, m, m);
+        if (nonleaf) p_load(TK, P->KR + v * P->KR_stride, nu, nx, m);
         // ---- state: x^v = [Abar|B] [x^anc; d^anc] + c ----
         if (v == 0) {
             for (int r = t; r < nx; r += kWG) xn[r] = P->x0[r];
             __syncthreads();
         } else {
-            mat_vec(P->M + v * P->M_stride, nx, m, m, xa, xn);
+            p_apply(TM, P->M + v * P->M_stride, nx, m, m, xa, xn);
             if (P->affine) {
                 for (int r = t; r < nx; r += kWG) xn[r] += P->c[(long long)v * nx + r];
                 __syncthreads();
@@ -704,7 +831,6 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
             zout[P->z_x + (long long)v * nx + r] = xn[r];
             xo[r] = zin[P->z_x + (long long)v * nx + r];
         }
-        const bool nonleaf = v < P->n_nl;
         if (nonleaf) {
             for (int r = t; r < nu; r += kWG) dv[r] = P->d[(long long)v * nu + r];
             if (P->n_ch[v] > 1) {
@@ -715,7 +841,7 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
             }
             __syncthreads();
             // ---- input: u^v = K^v x^v + d^v ----
-            mat_vec(P->KR + v * P->KR_stride, nu, nx, m, xn, un);
+            p_apply(TK, P->KR + v * P->KR_stride, nu, nx, m, xn, un);
             for (int r = t; r < nu; r += kWG) {
                 const real u = un[r] + dv[r];
                 un[r] = u;

@@ -61,6 +61,25 @@ class Sizes(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Result(C.Structure):
+    _fields_ = [("req_id", C.c_uint64), ("tree_id", C.c_int64), ("status", C.c_int32), ("warm", C.c_int32),
+                ("info", Info), ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "info"}
+        d["info"] = self.info.as_dict()
+        return d
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("created", C.c_uint64),
+                ("evicted", C.c_uint64), ("ticks", C.c_uint64), ("resident_bytes", C.c_size_t),
+                ("budget_bytes", C.c_size_t), ("pending", C.c_size_t), ("in_flight", C.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # name -> (restype, argtypes); the exported surface of include/spock.h
 SIGNATURES = {
     "spock_last_error": (C.c_char_p, []),
@@ -92,6 +111,15 @@ SIGNATURES = {
     "spock_batch_run_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
     "spock_batch_time_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp]),
     "spock_batch_step_bytes": (C.c_int32, [C.c_void_p, C.c_int32, _dp, _dp]),
+    "spock_server_create": (C.c_int32, [C.c_size_t, C.POINTER(Settings), C.POINTER(C.c_void_p)]),
+    "spock_server_add_tree": (C.c_int32, [C.c_void_p, C.POINTER(ProblemDesc), C.POINTER(C.c_int64)]),
+    "spock_server_submit": (C.c_int32, [C.c_void_p, C.c_int64, _dp, C.c_uint64]),
+    "spock_server_poll": (C.c_int32, [C.c_void_p, C.POINTER(Result), C.c_int32, C.POINTER(C.c_int32)]),
+    "spock_server_wait_idle": (C.c_int32, [C.c_void_p, C.c_double]),
+    "spock_server_get_stats": (C.c_int32, [C.c_void_p, C.POINTER(ServerStats)]),
+    "spock_server_solution": (C.c_int32, [C.c_void_p, C.c_int64, _dp, _dp, _dp]),
+    "spock_server_destroy": (C.c_int32, [C.c_void_p]),
+    "spock_now": (C.c_double, []),
 }
 
 _lib = None
@@ -340,3 +368,65 @@ class Batch:
         b, f = C.c_double(), C.c_double()
         _check(load().spock_batch_step_bytes(self.h, precision, C.byref(b), C.byref(f)))
         return b.value, f.value
+
+
+class Server:
+    """Continuous-batching MPC server (worker thread inside the library)."""
+
+    def __init__(self, hbm_budget, settings=None, **kw):
+        lib = load()
+        self._lib = lib
+        self.settings = settings or default_settings(**kw)
+        h = C.c_void_p()
+        _check(lib.spock_server_create(int(hbm_budget), C.byref(self.settings), C.byref(h)))
+        self.h = h
+        self.shapes = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.spock_server_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def add_tree(self, prob):
+        d = _Desc(prob)
+        tid = C.c_int64()
+        _check(load().spock_server_add_tree(self.h, C.byref(d.desc), C.byref(tid)))
+        self.shapes[tid.value] = (len(prob["parent"]), int(prob["nx"]), int(prob["nu"]),
+                                  int(np.asarray(prob["gamma"]).size))
+        return tid.value
+
+    def submit(self, tree_id, x0, req_id):
+        x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        _check(load().spock_server_submit(self.h, int(tree_id), _ptr(x0), int(req_id)))
+
+    def poll(self, max_results=1024):
+        out = (Result * max_results)()
+        n = C.c_int32()
+        _check(load().spock_server_poll(self.h, out, max_results, C.byref(n)))
+        return [out[i].as_dict() for i in range(n.value)]
+
+    def wait_idle(self, timeout_s=600.0):
+        _check(load().spock_server_wait_idle(self.h, float(timeout_s)))
+
+    def stats(self):
+        st = ServerStats()
+        _check(load().spock_server_get_stats(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def solution(self, tree_id):
+        n, nx, nu, nl = self.shapes[tree_id]
+        x, u, s0 = np.zeros((n, nx)), np.zeros((nl, nu)), C.c_double()
+        _check(load().spock_server_solution(self.h, int(tree_id), _ptr(x), _ptr(u), C.byref(s0)))
+        return x, u, s0.value
+
+
+def now():
+    return load().spock_now()

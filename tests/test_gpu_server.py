@@ -1,0 +1,91 @@
+"""Served form: requests that arrive while others are on the GPU are
+admitted as budget allows and batched together; each result equals the
+result of the same request sequence solved alone."""
+import numpy as np
+import pytest
+
+from paper_2505_12078_amd import spock as S
+from paper_2505_12078_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need an MI355X; none is visible")
+    S.load()
+
+
+def _trees():
+    return [W.config_problem(0), W.random_ragged_problem(7, N=4, nx=4, nu=2, max_children=3),
+            W.batch_problem(11), W.batch_problem(12)]
+
+
+def _sequence(p, k):
+    """k MPC requests: x0 shrinking towards the origin (stays feasible)."""
+    return [p["x0"] * (0.9 ** i) for i in range(k)]
+
+
+@pytest.mark.parametrize("precision,eps", [(S.FP64, 1e-5), (S.MIXED, 1e-4)])
+def test_mix_equals_alone(precision, eps):
+    trees = _trees()
+    settings = S.default_settings(eps=eps, max_iters=80000, precision=precision)
+    with S.Server(hbm_budget=8 << 30, settings=settings) as srv:
+        ids = [srv.add_tree(p) for p in trees]
+        req = 0
+        for i in range(3):  # interleaved: every tree has a request queued behind its previous one
+            for tid, p in zip(ids, trees):
+                srv.submit(tid, _sequence(p, 3)[i], req)
+                req += 1
+        srv.wait_idle(600)
+        res = sorted(srv.poll(), key=lambda r: r["req_id"])
+        st = srv.stats()
+    assert len(res) == 12 and st["completed"] == 12 and st["evicted"] == 0
+    for t, p in enumerate(trees):
+        mine = [r for r in res if r["tree_id"] == ids[t]]
+        with S.Problem(p, S.default_settings(eps=eps, max_iters=80000, precision=precision)) as P:
+            for i, x0 in enumerate(_sequence(p, 3)):
+                a = P.solve(x0, warm_start=i > 0)
+                r = mine[i]
+                assert r["status"] == a["code"] == S.SPOCK_OK, (t, i, r, a)
+                assert r["warm"] == (1 if i > 0 else 0)
+                assert r["info"]["iters"] == a["iters"], (t, i)
+                assert r["info"]["s0"] == a["s0"], (t, i)
+                assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+
+
+def test_admission_by_footprint_and_eviction():
+    trees = _trees()
+    fps = [S.footprint(p) for p in trees]
+    budget = sum(sorted(fps)[-2:]) + 1  # any two trees fit, never all four
+    settings = S.default_settings(eps=1e-5, max_iters=80000)
+    with S.Server(hbm_budget=budget, settings=settings) as srv:
+        ids = [srv.add_tree(p) for p in trees]
+        for i in range(2):
+            for k, (tid, p) in enumerate(zip(ids, trees)):
+                srv.submit(tid, _sequence(p, 2)[i], 10 * i + k)
+        srv.wait_idle(600)
+        res = srv.poll()
+        st = srv.stats()
+    assert len(res) == 8 and all(r["status"] == S.SPOCK_OK for r in res)
+    assert st["evicted"] > 0 and st["resident_bytes"] <= budget
+    # a tree that does not fit at all is refused up front
+    with S.Server(hbm_budget=min(fps) // 2, settings=settings) as srv:
+        with pytest.raises(S.SpockError) as e:
+            srv.add_tree(trees[0])
+        assert e.value.code == S.SPOCK_E_CAPACITY
+
+
+def test_infeasible_request_reports_and_others_continue():
+    trees = _trees()[:2]
+    with S.Server(hbm_budget=1 << 30, settings=S.default_settings(eps=1e-5)) as srv:
+        ids = [srv.add_tree(p) for p in trees]
+        srv.submit(ids[0], np.full(trees[0]["nx"], 50.0), 1)
+        srv.submit(ids[1], trees[1]["x0"], 2)
+        srv.submit(ids[0], trees[0]["x0"], 3)
+        srv.wait_idle(600)
+        res = {r["req_id"]: r for r in srv.poll()}
+    assert res[1]["status"] == S.SPOCK_E_INFEASIBLE_X0
+    assert res[2]["status"] == S.SPOCK_OK and res[3]["status"] == S.SPOCK_OK
