@@ -61,6 +61,85 @@ def _cpu_baseline_only(steps):
                                 "one thread; offline factorisation not timed" % steps}))
 
 
+def serve_bench(S, W, duration_s=10.0, session_rate=20.0, req_per_session=10, gap_mean=0.5,
+                drain_s=40.0, budget=200 << 30, seed=4):
+    """Poisson sessions (rate session_rate/s), each one tree drawn uniformly from
+    {medium tree, large tree, a batched-workload tree} issuing req_per_session
+    requests with exponential gaps (mean gap_mean s); request k+1 shifts x0 by
+    N(0, 0.1) and re-applies the feasibility guard; warm starts from the
+    resident iterate; eps 1e-4, mixed precision.  Latency = submit -> result."""
+    import threading
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    pool = {"medium": [W.config_problem(1, i) for i in range(3)],
+            "large": [W.config_problem(2, 0)],
+            "batched": [W.batch_problem(k, seed=5) for k in range(12)]}
+    shapes = ["medium", "large", "batched"]
+    # schedule
+    sessions = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / session_rate)
+        if t > duration_s:
+            break
+        kind = shapes[int(rng.integers(3))]
+        prob = pool[kind][int(rng.integers(len(pool[kind])))]
+        times, x0s = [t], [prob["x0"]]
+        x = prob["x0"]
+        n_nl = prob["gamma"].size
+        for _ in range(req_per_session - 1):
+            times.append(times[-1] + rng.exponential(gap_mean))
+            x = W._guard_x0(x + rng.normal(0.0, np.sqrt(0.1), size=x.size), prob["parent"], prob["A"],
+                            prob["x_hi"], prob["x_ball"], prob["xN_hi"], prob["xN_ball"], n_nl)
+            x0s.append(x)
+        sessions.append((kind, prob, times, x0s))
+    settings = S.default_settings(eps=1e-4, precision=S.MIXED, max_iters=200000, check_every=20)
+    srv = S.Server(budget, settings)
+    ids = [srv.add_tree(sess[1]) for sess in sessions]
+    events = sorted((tm, si, k) for si, sess in enumerate(sessions) for k, tm in enumerate(sess[2]))
+    results = []
+    stop = threading.Event()
+
+    def poller():
+        while not stop.is_set():
+            results.extend(srv.poll())
+            time.sleep(0.01)
+        results.extend(srv.poll())
+
+    th = threading.Thread(target=poller)
+    th.start()
+    t0 = time.perf_counter()
+    for tm, si, k in events:
+        dt = tm - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        srv.submit(ids[si], sessions[si][3][k], si * 1000 + k)
+    t_end = time.perf_counter() + drain_s
+    while time.perf_counter() < t_end and len(results) < len(events):
+        time.sleep(0.05)
+    stop.set()
+    th.join()
+    st = srv.stats()
+    srv.close()
+    ok = [r for r in results if r["status"] == 0]
+    lat = np.array([r["t_done"] - r["t_submit"] for r in ok]) if ok else np.array([np.nan])
+    span = (max(r["t_done"] for r in results) - min(r["t_submit"] for r in results)) if results else float("nan")
+    by_kind = {}
+    for r in ok:
+        kind = sessions[r["req_id"] // 1000][0]
+        by_kind.setdefault(kind, []).append(r["t_done"] - r["t_submit"])
+    return {"offered_req_per_s": round(len(events) / duration_s, 2), "requests": len(events),
+            "completed_ok": len(ok), "completed": len(results),
+            "solves_per_s": round(len(ok) / span, 2) if results else 0.0,
+            "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+            "p50_by_shape_s": {k: round(float(np.percentile(v, 50)), 4) for k, v in by_kind.items()},
+            "warm_fraction": round(float(np.mean([r["warm"] for r in ok])), 3) if ok else 0.0,
+            "mean_iters": round(float(np.mean([r["info"]["iters"] for r in ok])), 1) if ok else 0.0,
+            "sessions": len(sessions), "duration_s": duration_s, "drain_s": drain_s,
+            "server": {k: int(v) for k, v in st.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +148,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tol", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="sessions per second (10 requests each)")
     ap.add_argument("--cpu-baseline-only", action="store_true")
     args = ap.parse_args()
     if args.cpu_baseline_only:
@@ -90,6 +172,7 @@ def main():
     P = S.Problem(prob, S.default_settings(eps=1e-4, precision=S.MIXED, check_every=20, max_iters=40000))
     t_setup = time.perf_counter() - t
     P.set_x0(prob["x0"])
+    nodes = P.n
     print("setup %.2fs, %s" % (t_setup, P.sizes), file=sys.stderr, flush=True)
 
     def rate(prec):
@@ -131,18 +214,22 @@ def main():
             print("time-to-tol %s: %s" % (name, tol[name]), file=sys.stderr, flush=True)
         tol["speedup_mixed_vs_fp64"] = round(tol["fp64"]["seconds"] / max(tol["mixed"]["seconds"], 1e-9), 3)
 
+    P.close()
+    serve = None
+    if not args.no_serve:
+        serve = serve_bench(S, W, duration_s=args.serve_seconds, session_rate=args.serve_rate)
+        print("serve: %s" % serve, file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC, "value": round(v32, 2), "unit": "CP iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1000.0 / v32, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD, "precision": "mixed: f32 steps on f32 copies of f64 factors, "
-                   "f64 final check and refinement", "nodes": P.n, "nx": P.nx, "nu": P.nu,
+                   "f64 final check and refinement", "nodes": nodes, "nx": 50, "nu": 25,
                    "setup_s": round(t_setup, 3)},
         "fp64": {"iters_per_s": round(v64, 2), "ms_per_step": round(1000.0 / v64, 4)},
-        "kernels": kt, "roofline": roofline, "time_to_tol": tol, "cpu_baseline": cpu,
+        "kernels": kt, "roofline": roofline, "time_to_tol": tol, "serve": serve, "cpu_baseline": cpu,
     }
-    P.close()
     print(json.dumps(out))
 
 

@@ -98,6 +98,12 @@ struct spock_server {
     bool stop = false;
     std::string error;
     spock_server_stats stats{};
+    // set-up thread: trees made resident off the worker's critical path
+    std::thread setup;
+    std::deque<int64_t> setup_jobs;              // trees to create (budget reserved)
+    std::deque<std::pair<int64_t, spock_problem*>> setup_done;  // created (or null on failure)
+    std::map<int64_t, SrvReq> waiting;           // admitted requests whose tree is being set up
+    size_t reserved = 0;                         // budget of trees being set up
     // worker-owned
     spock_batch* batch = nullptr;
     std::vector<int64_t> members;
@@ -157,14 +163,14 @@ void finish(spock_server* s, Flight& f, int32_t status, double t) {
 // Admit what fits; returns the requests to start (trees made resident by the caller).
 std::vector<SrvReq> admit(spock_server* s, std::vector<int64_t>& to_create, std::vector<int64_t>& to_evict) {
     std::vector<SrvReq> out;
-    size_t used = s->used;
+    size_t used = s->used + s->reserved;
     for (auto it = s->pending.begin(); it != s->pending.end();) {
         SrvTree& T = s->trees.at(it->tree);
         if (T.busy) {
             ++it;
             continue;
         }
-        if (!T.p && std::find(to_create.begin(), to_create.end(), T.id) == to_create.end()) {
+        if (!T.p) {
             if (used + T.footprint > s->budget) {
                 // evict idle resident trees, least recently used first
                 std::vector<SrvTree*> idle;
@@ -327,18 +333,50 @@ int32_t tick(spock_server* s) {
     return SPOCK_OK;
 }
 
+void setup_main(spock_server* s) {
+    (void)hipSetDevice(s->device);
+    for (;;) {
+        int64_t id;
+        spock_problem_desc d;
+        {
+            std::unique_lock<std::mutex> g(s->mu);
+            s->cv.wait(g, [&] { return s->stop || !s->setup_jobs.empty(); });
+            if (s->stop) return;
+            id = s->setup_jobs.front();
+            s->setup_jobs.pop_front();
+            d = s->trees.at(id).desc();
+        }
+        spock_problem* p = nullptr;
+        if (spock_problem_create(&d, &s->set, nullptr, 0, nullptr, &p) != SPOCK_OK) p = nullptr;
+        std::lock_guard<std::mutex> g(s->mu);
+        s->setup_done.emplace_back(id, p);
+        if (p) s->stats.created++;
+        s->cv.notify_all();
+    }
+}
+
 void worker_main(spock_server* s) {
     (void)hipSetDevice(s->device);
     for (;;) {
         std::vector<int64_t> to_create, to_evict;
         std::vector<SrvReq> start;
+        std::deque<std::pair<int64_t, spock_problem*>> ready;
         {
             std::unique_lock<std::mutex> g(s->mu);
             if (s->stop) break;
-            start = admit(s, to_create, to_evict);
-            if (start.empty() && s->flights.empty()) {
-                s->cv.wait_for(g, std::chrono::milliseconds(20));
-                continue;
+            std::vector<SrvReq> adm = admit(s, to_create, to_evict);
+            for (auto& rq : adm) {
+                if (std::find(to_create.begin(), to_create.end(), rq.tree) != to_create.end())
+                    s->waiting[rq.tree] = rq;  // starts when its tree is set up
+                else
+                    start.push_back(rq);
+            }
+            ready.swap(s->setup_done);
+            if (start.empty() && ready.empty() && s->flights.empty() && to_evict.empty()) {
+                if (to_create.empty()) {
+                    s->cv.wait_for(g, std::chrono::milliseconds(20));
+                    continue;
+                }
             }
         }
         int32_t r = SPOCK_OK;
@@ -353,15 +391,33 @@ void worker_main(spock_server* s) {
             T.busy = false;
             s->stats.evicted++;
         }
-        for (int64_t id : to_create) {
-            SrvTree& T = tree_ref(s, id);
-            spock_problem_desc d = T.desc();
-            r = spock_problem_create(&d, &s->set, nullptr, 0, nullptr, &T.p);
-            if (r) break;
+        if (!to_create.empty()) {
+            std::lock_guard<std::mutex> g(s->mu);
+            for (int64_t id : to_create) {
+                s->reserved += s->trees.at(id).footprint;
+                s->setup_jobs.push_back(id);
+            }
+            s->cv.notify_all();
+        }
+        for (auto& rd : ready) {
+            SrvTree& T = tree_ref(s, rd.first);
+            SrvReq rq;
+            {
+                std::lock_guard<std::mutex> g(s->mu);
+                s->reserved -= T.footprint;
+                rq = s->waiting.at(rd.first);
+                s->waiting.erase(rd.first);
+            }
+            if (!rd.second) {  // set-up failed: report and free the tree
+                Flight f;
+                f.req = rq;
+                finish(s, f, SPOCK_E_NOMEM, now_s());
+                continue;
+            }
+            T.p = rd.second;
             s->used += T.footprint;
             s->dirty = true;
-            std::lock_guard<std::mutex> g(s->mu);
-            s->stats.created++;
+            start.push_back(rq);
         }
         for (auto& rq : start) {
             if (r) break;
@@ -397,6 +453,7 @@ int32_t spock_server_create(size_t budget, const spock_settings* set, spock_serv
     s->set = *set;
     (void)hipGetDevice(&s->device);
     s->worker = std::thread(worker_main, s);
+    s->setup = std::thread(setup_main, s);
     *out = s;
     return SPOCK_OK;
 }
@@ -509,6 +566,9 @@ int32_t spock_server_destroy(spock_server* s) {
         s->cv.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
+    if (s->setup.joinable()) s->setup.join();
+    for (auto& rd : s->setup_done)
+        if (rd.second) spock_problem_destroy(rd.second);
     if (s->batch) spock_batch_destroy(s->batch);
     for (auto& kv : s->trees)
         if (kv.second.p) spock_problem_destroy(kv.second.p);
