@@ -140,6 +140,31 @@ def serve_bench(S, W, duration_s=10.0, session_rate=20.0, req_per_session=10, ga
             "server": {k: int(v) for k, v in st.items()}}
 
 
+def _profile_pass(steps):
+    """What a profiler should see: `steps` float32 and float64 CP steps of the
+    large tree (k_backward / k_forward) and one copy of 1 GiB (a plain kernel
+    of known traffic for scaling the memory counters)."""
+    import torch
+
+    from paper_2505_12078_amd import spock as S
+    from paper_2505_12078_amd import workloads as W
+    torch.cuda.set_device(0)
+    prob = W.config_problem(2)
+    P = S.Problem(prob, S.default_settings())
+    P.set_x0(prob["x0"])
+    for prec in (S.FP32, S.FP64):
+        P.run_steps(steps, prec)
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    bb32, bf32 = P.step_bytes(S.FP32)
+    bb64, bf64 = P.step_bytes(S.FP64)
+    print(json.dumps({"steps": steps, "copy_bytes": 1 << 30, "bytes_backward_f32": bb32, "bytes_forward_f32": bf32,
+                      "bytes_backward_f64": bb64, "bytes_forward_f64": bf64}))
+    P.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,9 +177,14 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="sessions per second (10 requests each)")
     ap.add_argument("--cpu-baseline-only", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: K steps per precision and a 1 GiB device copy")
     args = ap.parse_args()
     if args.cpu_baseline_only:
         _cpu_baseline_only(args.cpu_steps)
+        return
+    if args.profile:
+        _profile_pass(args.steps)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the CP step of one scenario tree runs on one MI355X "

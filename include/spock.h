@@ -205,6 +205,12 @@ int32_t spock_time_steps(spock_problem* p, int32_t precision, int32_t steps, dou
  * sync = 1 waits for them to finish.  For throughput measurement. */
 int32_t spock_run_steps(spock_problem* p, int32_t precision, int32_t steps, int32_t sync);
 
+/* Workgroup size (64, 128, 256 or 512 threads) of the sweep kernels of one
+ * precision; picked by the autotuner (default 256).  Results do not depend on
+ * it beyond rounding order. */
+int32_t spock_set_launch(spock_problem* p, int32_t precision, int32_t workgroup);
+int32_t spock_get_launch(const spock_problem* p, int32_t precision, int32_t* workgroup);
+
 /* Bytes one CP step must move at minimum (factor matrices + iterates) in the
  * given precision, counted as in the design notes; for roofline reporting. */
 int32_t spock_step_bytes(const spock_problem* p, int32_t precision, double* bytes_backward,
@@ -245,6 +251,8 @@ int32_t spock_batch_time_steps(spock_batch* b, int32_t precision, int32_t steps,
                                double* ms_backward, double* ms_forward);
 int32_t spock_batch_step_bytes(const spock_batch* b, int32_t precision, double* bytes_backward,
                                double* bytes_forward);
+/* Workgroup size of the batch's sweep kernels for one precision (autotuner). */
+int32_t spock_batch_set_launch(spock_batch* b, int32_t precision, int32_t workgroup);
 
 /*
  * Served form: continuous batching of MPC requests.

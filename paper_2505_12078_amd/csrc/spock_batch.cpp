@@ -24,6 +24,8 @@ template <>
 ProbDev<float>* dev_of<float>(spock_batch* b) { return b->d32; }
 template <typename real>
 int lds_of(spock_batch* b) { return sizeof(real) == 8 ? b->lds64 : b->lds32; }
+template <typename real>
+int wg_of(spock_batch* b) { return sizeof(real) == 8 ? b->wg64 : b->wg32; }
 
 int32_t upload_active(spock_batch* b, const std::vector<Member>* m) {
     for (int k = 0; k < b->n; ++k) b->h_active[k] = m ? (int)(*m)[k].live : 1;
@@ -36,7 +38,7 @@ int32_t batch_steps(spock_batch* b, int steps, bool check_last) {
     for (int k = 0; k < steps; ++k) {
         // every member sits at copy 0 before a batched chunk; parity follows k
         HIP_TRY(spk::launch_step<real>(dev_of<real>(b), b->tasks, b->ticket, b->n_tasks, lds_of<real>(b), k & 1,
-                                       check_last && k == steps - 1, b->stream));
+                                       check_last && k == steps - 1, wg_of<real>(b), b->stream));
     }
     return SPOCK_OK;
 }
@@ -154,8 +156,8 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
             return fail(SPOCK_E_INVALID, "null problem in batch");
         }
         b->n_tasks += probs[k]->n_leaf;
-        b->lds64 = std::max(b->lds64, probs[k]->s64.lds_bytes);
-        b->lds32 = std::max(b->lds32, probs[k]->s32.lds_bytes);
+        b->lds64 = std::max(b->lds64, sweep_lds_bytes(probs[k], b->wg64, 8));
+        b->lds32 = std::max(b->lds32, sweep_lds_bytes(probs[k], b->wg32, 4));
         HIP_TRY(hipStreamSynchronize(probs[k]->stream));
         double bb, bf;
         for (int q = 0; q < 2; ++q) {
@@ -376,13 +378,17 @@ int32_t spock_batch_time_steps(spock_batch* b, int32_t prec, int32_t steps, doub
     HIP_TRY(hipEventRecord(ev[0], b->stream));
     for (int k = 0; k < steps; ++k) {
         if (prec == SPOCK_FP64) {
-            HIP_TRY(spk::launch_backward<double>(b->d64, b->tasks, b->ticket, b->n_tasks, b->lds64, k & 1, 0, b->stream));
+            HIP_TRY(spk::launch_backward<double>(b->d64, b->tasks, b->ticket, b->n_tasks, b->lds64, k & 1, 0, b->wg64,
+                                                b->stream));
             HIP_TRY(hipEventRecord(ev[2 * k + 1], b->stream));
-            HIP_TRY(spk::launch_forward<double>(b->d64, b->tasks, b->ticket, b->n_tasks, b->lds64, k & 1, 0, b->stream));
+            HIP_TRY(spk::launch_forward<double>(b->d64, b->tasks, b->ticket, b->n_tasks, b->lds64, k & 1, 0, b->wg64,
+                                               b->stream));
         } else {
-            HIP_TRY(spk::launch_backward<float>(b->d32, b->tasks, b->ticket, b->n_tasks, b->lds32, k & 1, 0, b->stream));
+            HIP_TRY(spk::launch_backward<float>(b->d32, b->tasks, b->ticket, b->n_tasks, b->lds32, k & 1, 0, b->wg32,
+                                               b->stream));
             HIP_TRY(hipEventRecord(ev[2 * k + 1], b->stream));
-            HIP_TRY(spk::launch_forward<float>(b->d32, b->tasks, b->ticket, b->n_tasks, b->lds32, k & 1, 0, b->stream));
+            HIP_TRY(spk::launch_forward<float>(b->d32, b->tasks, b->ticket, b->n_tasks, b->lds32, k & 1, 0, b->wg32,
+                                              b->stream));
         }
         HIP_TRY(hipEventRecord(ev[2 * k + 2], b->stream));
     }
@@ -402,6 +408,30 @@ int32_t spock_batch_time_steps(spock_batch* b, int32_t prec, int32_t steps, doub
     if (ms_b) *ms_b = tb / steps;
     if (ms_f) *ms_f = tf / steps;
     return read_all(b);
+}
+
+int32_t spock_batch_set_launch(spock_batch* b, int32_t precision, int32_t workgroup) {
+    if (!b || !(workgroup == 64 || workgroup == 128 || workgroup == 256 || workgroup == 512))
+        return fail(SPOCK_E_INVALID, "workgroup must be 64, 128, 256 or 512");
+    const int bytes = precision == SPOCK_FP64 ? 8 : 4;
+    int lds = 0;
+    for (auto* p : b->probs) lds = std::max(lds, sweep_lds_bytes(p, workgroup, bytes));
+    if (lds > 64 * 1024) return fail(SPOCK_E_INVALID, "LDS too large");
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    const int gi = precision == SPOCK_FP64 ? 0 : 1;
+    if (b->graph[gi]) {
+        (void)hipGraphExecDestroy(b->graph[gi]);
+        b->graph[gi] = nullptr;
+        b->graph_steps[gi] = 0;
+    }
+    if (precision == SPOCK_FP64) {
+        b->wg64 = workgroup;
+        b->lds64 = lds;
+    } else {
+        b->wg32 = workgroup;
+        b->lds32 = lds;
+    }
+    return SPOCK_OK;
 }
 
 int32_t spock_batch_step_bytes(const spock_batch* b, int32_t prec, double* bb, double* bf) {

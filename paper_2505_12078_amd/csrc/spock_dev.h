@@ -7,8 +7,9 @@
 
 namespace spk {
 
-// Threads per workgroup for the sweep kernels: four wave64 wavefronts.
-constexpr int kWG = 256;
+// Threads per workgroup of the sweep kernels (a launch parameter: 64, 128,
+// 256 or 512, picked per problem or batch); the default is four wave64s.
+constexpr int kDefaultWG = 256;
 // Longest root-to-leaf path a forward task may walk (stages + 1).
 constexpr int kMaxDepth = 512;
 
@@ -86,10 +87,11 @@ __host__ __device__ inline int blk_elems(int nx, int nu, int max_ch) {
 
 // Number of `real` elements of dynamic LDS a sweep workgroup needs (the
 // larger of the backward and the forward partitions).
-__host__ __device__ inline int lds_elems(int nx, int nu, int max_ch) {
+__host__ __device__ inline int lds_elems(int nx, int nu, int max_ch, int wg) {
     const int m = nx + nu;
-    const int bwd = kWG + 2 * m + nx + 2 * nu + 5 * max_ch;
-    const int fwd = kWG + m + 6 * nx + 7 * nu + 8 * blk_elems(nx, nu, max_ch);
+    const int waves = wg / 64;
+    const int bwd = wg + 2 * m + nx + 2 * nu + 5 * max_ch;
+    const int fwd = wg + m + (2 + waves) * nx + (3 + waves) * nu + 2 * waves * blk_elems(nx, nu, max_ch);
     return (bwd > fwd ? bwd : fwd) + 8;
 }
 

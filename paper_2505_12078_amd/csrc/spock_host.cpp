@@ -281,7 +281,7 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     p->neta = o;
     p->M_stride = ((long long)nx * p->m + 31) / 32 * 32;
     p->KR_stride = ((long long)nu * p->m + 31) / 32 * 32;
-    if ((long long)spk::lds_elems(nx, nu, p->max_ch) * 8 > 64 * 1024)
+    if ((long long)spk::lds_elems(nx, nu, p->max_ch, spk::kDefaultWG) * 8 > 64 * 1024)
         return fail(SPOCK_E_INVALID, "nx + nu or the branching is too large for one workgroup");
     return SPOCK_OK;
 }
@@ -557,7 +557,7 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     h.active = p->d_ticket + 1;
     h.err = p->d_err;
     h.res = p->d_res;
-    s.lds_bytes = spk::lds_elems(p->nx, p->nu, p->max_ch) * (int)sizeof(real);
+    s.lds_bytes = sweep_lds_bytes(p, s.wg, (int)sizeof(real));
     hipStream_t st = p->stream;
     HIP_TRY(put<real>(h.M, M, st));
     HIP_TRY(put<real>(h.KR, KR, st));
@@ -595,7 +595,7 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
 template <typename real>
 int32_t step(spock_problem* p, int check) {
     DevSet<real>& s = set_of<real>(p);
-    HIP_TRY(spk::launch_step<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, s.par, check,
+    HIP_TRY(spk::launch_step<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, s.par, check, s.wg,
                                    p->stream));
     s.par ^= 1;
     return SPOCK_OK;
@@ -621,7 +621,7 @@ static int32_t chunk(spock_problem* p, int steps) {
             int par = s.par;
             for (int k = 0; k < steps; ++k) {
                 hipError_t e = spk::launch_step<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, par,
-                                                      k == steps - 1, p->stream);
+                                                      k == steps - 1, s.wg, p->stream);
                 if (e != hipSuccess) {
                     (void)hipStreamEndCapture(p->stream, &graph);
                     return fail(SPOCK_E_HIP, std::string("capture: ") + hipGetErrorString(e));
@@ -710,6 +710,12 @@ int32_t set_x0_device(spock_problem* p, const double* x0, bool check_feasible) {
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+int sweep_lds_bytes(const spock_problem* p, int wg, int real_bytes) {
+    return spk::lds_elems(p->nx, p->nu, p->max_ch, wg) * real_bytes;
+}
+
+static bool valid_wg(int wg) { return wg == 64 || wg == 128 || wg == 256 || wg == 512; }
 
 // The iterate of the current precision moved to copy 0 (batched steps keep
 // every member at the same parity).
@@ -1244,10 +1250,10 @@ static int32_t time_steps(spock_problem* p, int steps, double* ms_total, double*
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     HIP_TRY(hipEventRecord(ev[0], p->stream));
     for (int k = 0; k < steps; ++k) {
-        HIP_TRY(spk::launch_backward<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, s.par, 0,
+        HIP_TRY(spk::launch_backward<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, s.par, 0, s.wg,
                                            p->stream));
         HIP_TRY(hipEventRecord(ev[2 * k + 1], p->stream));
-        HIP_TRY(spk::launch_forward<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, s.par, 0,
+        HIP_TRY(spk::launch_forward<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, s.par, 0, s.wg,
                                           p->stream));
         HIP_TRY(hipEventRecord(ev[2 * k + 2], p->stream));
         s.par ^= 1;
@@ -1288,6 +1294,33 @@ int32_t spock_time_steps(spock_problem* p, int32_t prec, int32_t steps, double* 
     if (r) return r;
     return prec == SPOCK_FP64 ? time_steps<double>(p, steps, ms_total, ms_b, ms_f)
                               : time_steps<float>(p, steps, ms_total, ms_b, ms_f);
+}
+
+int32_t spock_set_launch(spock_problem* p, int32_t precision, int32_t workgroup) {
+    if (!p || !valid_wg(workgroup)) return fail(SPOCK_E_INVALID, "workgroup must be 64, 128, 256 or 512");
+    const int bytes = precision == SPOCK_FP64 ? 8 : 4;
+    if (sweep_lds_bytes(p, workgroup, bytes) > 64 * 1024) return fail(SPOCK_E_INVALID, "LDS too large");
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    auto apply = [&](auto& s) {
+        if (s.wg == workgroup) return;
+        s.wg = workgroup;
+        s.lds_bytes = sweep_lds_bytes(p, workgroup, bytes);
+        for (auto& g : s.graph)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+        s.graph_steps = 0;
+    };
+    if (precision == SPOCK_FP64) apply(p->s64);
+    else apply(p->s32);
+    return SPOCK_OK;
+}
+
+int32_t spock_get_launch(const spock_problem* p, int32_t precision, int32_t* workgroup) {
+    if (!p || !workgroup) return fail(SPOCK_E_INVALID, "null argument");
+    *workgroup = precision == SPOCK_FP64 ? p->s64.wg : p->s32.wg;
+    return SPOCK_OK;
 }
 
 int32_t spock_run_steps(spock_problem* p, int32_t prec, int32_t steps, int32_t sync) {

@@ -12,11 +12,11 @@
 
 namespace spk {
 template <typename real>
-hipError_t launch_step(const ProbDev<real>*, const int2*, int*, int, int, int, int, hipStream_t);
+hipError_t launch_step(const ProbDev<real>*, const int2*, int*, int, int, int, int, int, hipStream_t);
 template <typename real>
-hipError_t launch_backward(const ProbDev<real>*, const int2*, int*, int, int, int, int, hipStream_t);
+hipError_t launch_backward(const ProbDev<real>*, const int2*, int*, int, int, int, int, int, hipStream_t);
 template <typename real>
-hipError_t launch_forward(const ProbDev<real>*, const int2*, int*, int, int, int, int, hipStream_t);
+hipError_t launch_forward(const ProbDev<real>*, const int2*, int*, int, int, int, int, int, hipStream_t);
 template <typename real>
 hipError_t launch_apply_L(const ProbDev<real>*, int, const real*, real*, hipStream_t);
 template <typename real>
@@ -55,7 +55,8 @@ struct DevSet {
     ProbDev<real> h;           // host mirror of the descriptor
     ProbDev<real>* d = nullptr;  // the descriptor in device memory
     int par = 0;               // which copy holds the current iterate
-    int lds_bytes = 0;
+    int wg = spk::kDefaultWG;  // workgroup size of the sweep kernels
+    int lds_bytes = 0;         // dynamic LDS of a sweep workgroup at that size
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // check_every steps from parity 0 / 1
     int graph_steps = 0;
 };
@@ -139,6 +140,7 @@ struct spock_batch {
     int* err = nullptr;
     unsigned long long* res = nullptr;
     int lds64 = 0, lds32 = 0;
+    int wg64 = spk::kDefaultWG, wg32 = spk::kDefaultWG;
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // [0] float64, [1] float32
     int graph_steps[2] = {0, 0};
     unsigned long long* h_res = nullptr;  // pinned: 2n residual slots, then n error flags
@@ -159,3 +161,6 @@ struct Member {
 
 template <typename real>
 int32_t batch_tick(spock_batch* b, std::vector<Member>& m, bool stall_exit);
+
+// dynamic LDS bytes of a sweep workgroup of `wg` threads for this problem
+int sweep_lds_bytes(const spock_problem* p, int wg, int real_bytes);

@@ -40,6 +40,8 @@
 
 namespace spk {
 
+constexpr int kHookWG = 256;  // workgroup size of the per-node hook kernels
+
 #define SPK_DEV __device__ __forceinline__
 
 // ---------------------------------------------------------------------------
@@ -64,7 +66,7 @@ SPK_DEV T wave_max(T v) {
 }
 
 // Sum over the workgroup, same value returned to every thread; deterministic.
-template <typename T>
+template <int kWG, typename T>
 SPK_DEV T block_sum(T v, T* red) {
     v = wave_sum(v);
     __syncthreads();
@@ -76,7 +78,7 @@ SPK_DEV T block_sum(T v, T* red) {
     return s;
 }
 
-template <typename T>
+template <int kWG, typename T>
 SPK_DEV T block_max(T v, T* red) {
     v = wave_max(v);
     __syncthreads();
@@ -92,7 +94,7 @@ SPK_DEV T block_max(T v, T* red) {
 // A in global memory, vectors and out in LDS.  Threads (g, c): lanes run along
 // the columns of a row, so each load instruction covers a contiguous row
 // segment; G row groups split the rows and are summed through LDS.
-template <typename real>
+template <int kWG, typename real>
 SPK_DEV void mat_t_vec(const real* __restrict__ A, int R, int C, long long ld, int split,
                        const real* va, const real* vb, real* out, real* red) {
     const int t = threadIdx.x;
@@ -122,7 +124,7 @@ SPK_DEV void mat_t_vec(const real* __restrict__ A, int R, int C, long long ld, i
 // out[r] = sum_c A[r*ld + c] * v[c],  r < R, c < C.  A power-of-two segment of
 // W lanes (W <= 64) owns a row: lanes stride the row, then reduce by xor
 // shuffles inside the segment.
-template <typename real>
+template <int kWG, typename real>
 SPK_DEV void mat_vec(const real* __restrict__ A, int R, int C, long long ld, const real* v,
                      real* out) {
     int W = 1;
@@ -156,7 +158,7 @@ struct TTile {
     real a[RB];
 };
 
-template <typename real, int RB>
+template <int kWG, typename real, int RB>
 SPK_DEV void t_load(TTile<real, RB>& T, const real* __restrict__ A, int R, int C, long long ld) {
     const int t = threadIdx.x, G = kWG / C, g = t / C, c = t - g * C;
 #pragma unroll
@@ -167,7 +169,7 @@ SPK_DEV void t_load(TTile<real, RB>& T, const real* __restrict__ A, int R, int C
 }
 
 // out[c] = sum_r A[r][c] (c < split ? va[r] : vb[r]) from a loaded tile.
-template <typename real, int RB>
+template <int kWG, typename real, int RB>
 SPK_DEV void t_apply(const TTile<real, RB>& T, const real* __restrict__ A, int R, int C, long long ld, int split,
                      const real* va, const real* vb, real* out, real* red) {
     const int t = threadIdx.x, G = kWG / C, g = t / C, c = t - g * C;
@@ -205,7 +207,7 @@ SPK_DEV int seg_width(int C) {
     return W;
 }
 
-template <typename real, int RB, int CB>
+template <int kWG, typename real, int RB, int CB>
 SPK_DEV void p_load(PTile<real, RB, CB>& T, const real* __restrict__ A, int R, int C, long long ld) {
     const int W = seg_width(C), t = threadIdx.x, nseg = kWG / W, seg = t / W, k = t - seg * W;
 #pragma unroll
@@ -219,7 +221,7 @@ SPK_DEV void p_load(PTile<real, RB, CB>& T, const real* __restrict__ A, int R, i
     }
 }
 
-template <typename real, int RB, int CB>
+template <int kWG, typename real, int RB, int CB>
 SPK_DEV void p_apply(const PTile<real, RB, CB>& T, const real* __restrict__ A, int R, int C, long long ld,
                      const real* v, real* out) {
     const int W = seg_width(C), t = threadIdx.x, nseg = kWG / W, seg = t / W, k = t - seg * W;
@@ -331,7 +333,7 @@ SPK_DEV void s2_block_wave(const ProbDev<real>* __restrict__ P, int i, const rea
     if (lane == 0) zout[P->z_y + yo + 2 * k] = yb3 - lsum;
 }
 
-template <typename real>
+template <typename real, int kWG>
 __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restrict__ probs,
                                                   const int2* __restrict__ tasks, int* __restrict__ ticket,
                                                   int par, int check) {
@@ -368,7 +370,7 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
     int j = s_path[N];
     {
         TTile<real, kRBM> TM;
-        if (tiles) t_load(TM, P->M + j * P->M_stride, nx, m, m);
+        if (tiles) t_load<kWG>(TM, P->M + j * P->M_stride, nx, m, m);
         const long long lf = j - P->n_nl;
         const real* ecN = ein + P->e_cN + lf * P->ncN;
         const real* esN = ein + P->e_socN + lf * (nx + 2);
@@ -381,8 +383,8 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
         }
         if (t == 0) P->flag[j] = 0;
         __syncthreads();
-        if (tiles) t_apply(TM, P->M + j * P->M_stride, nx, m, m, m, xb, xb, o, red);
-        else mat_t_vec(P->M + j * P->M_stride, nx, m, m, m, xb, xb, o, red);
+        if (tiles) t_apply<kWG>(TM, P->M + j * P->M_stride, nx, m, m, m, xb, xb, o, red);
+        else mat_t_vec<kWG>(P->M + j * P->M_stride, nx, m, m, m, xb, xb, o, red);
     }
 
     // ---- walk up ----
@@ -416,8 +418,8 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
         TTile<real, kRBK> TK;
         TTile<real, kRBM> TM;
         if (tiles) {
-            t_load(TK, P->KR + i * P->KR_stride, nu, m, m);
-            if (i > 0) t_load(TM, P->M + i * P->M_stride, nx, m, m);
+            t_load<kWG>(TK, P->KR + i * P->KR_stride, nu, m, m);
+            if (i > 0) t_load<kWG>(TM, P->M + i * P->M_stride, nx, m, m);
         }
         // zbar for (x^i, u^i): L* gathers the constraint rows and the SOC rows of
         // every child edge (Sec. 4.4)
@@ -441,8 +443,8 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
         if ((t >> 6) == (kWG / 64) - 1) s2_block_wave(P, i, zin, ein, zout, lam);
         __syncthreads();
         // [K^T ubar ; R~^-1 (ubar - g_u)] in one pass over [K | R~^-1]
-        if (tiles) t_apply(TK, P->KR + i * P->KR_stride, nu, m, m, nx, ub, w2, o, red);
-        else mat_t_vec(P->KR + i * P->KR_stride, nu, m, m, nx, ub, w2, o, red);
+        if (tiles) t_apply<kWG>(TK, P->KR + i * P->KR_stride, nu, m, m, nx, ub, w2, o, red);
+        else mat_t_vec<kWG>(P->KR + i * P->KR_stride, nu, m, m, nx, ub, w2, o, red);
         for (int r = t; r < nx; r += kWG) {
             real h = -xb[r] - o[r] + g[r];
             if (P->affine && i > 0) h += P->Pc[(long long)i * nx + r];
@@ -461,8 +463,8 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
             return;
         }
         __syncthreads();
-        if (tiles) t_apply(TM, P->M + i * P->M_stride, nx, m, m, m, xb, xb, o, red);
-        else mat_t_vec(P->M + i * P->M_stride, nx, m, m, m, xb, xb, o, red);
+        if (tiles) t_apply<kWG>(TM, P->M + i * P->M_stride, nx, m, m, m, xb, xb, o, red);
+        else mat_t_vec<kWG>(P->M + i * P->M_stride, nx, m, m, m, xb, xb, o, red);
         j = i;
     }
 }
@@ -746,7 +748,7 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
     }
 }
 
-template <typename real>
+template <typename real, int kWG>
 __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict__ probs,
                                                  const int2* __restrict__ tasks, int* __restrict__ ticket,
                                                  int par, int check) {
@@ -777,10 +779,11 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
     real* dv = un + nu;
     real* xo = dv + nu;
     real* uo = xo + nx;
-    real* lxw = uo + nu;   // 4 x nx
-    real* luw = lxw + 4 * nx;  // 4 x nu
-    real* blk = luw + 4 * nu;  // 4 x bmax
-    real* dblk = blk + 4 * bmax;
+    constexpr int kWaves = kWG / 64;
+    real* lxw = uo + nu;             // kWaves x nx
+    real* luw = lxw + kWaves * nx;   // kWaves x nu
+    real* blk = luw + kWaves * nu;   // kWaves x bmax
+    real* dblk = blk + kWaves * bmax;
     const FwdVecs<real> V{xn, un, xo, uo, blk + w * bmax, dblk + w * bmax, lxw + w * nx, luw + w * nu};
 
     // this task computes the path nodes from stage L down to its leaf; the
@@ -814,14 +817,14 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
         const bool nonleaf = v < P->n_nl;
         PTile<real, kRBP, 2> TM;
         PTile<real, kRBQ, 1> TK;
-        if (v > 0) p_load(TM, P->M + v * P->M_stride, nx, m, m);
-        if (nonleaf) p_load(TK, P->KR + v * P->KR_stride, nu, nx, m);
+        if (v > 0) p_load<kWG>(TM, P->M + v * P->M_stride, nx, m, m);
+        if (nonleaf) p_load<kWG>(TK, P->KR + v * P->KR_stride, nu, nx, m);
         // ---- state: x^v = [Abar|B] [x^anc; d^anc] + c ----
         if (v == 0) {
             for (int r = t; r < nx; r += kWG) xn[r] = P->x0[r];
             __syncthreads();
         } else {
-            p_apply(TM, P->M + v * P->M_stride, nx, m, m, xa, xn);
+            p_apply<kWG>(TM, P->M + v * P->M_stride, nx, m, m, xa, xn);
             if (P->affine) {
                 for (int r = t; r < nx; r += kWG) xn[r] += P->c[(long long)v * nx + r];
                 __syncthreads();
@@ -841,7 +844,7 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
             }
             __syncthreads();
             // ---- input: u^v = K^v x^v + d^v ----
-            p_apply(TK, P->KR + v * P->KR_stride, nu, nx, m, xn, un);
+            p_apply<kWG>(TK, P->KR + v * P->KR_stride, nu, nx, m, xn, un);
             for (int r = t; r < nu; r += kWG) {
                 const real u = un[r] + dv[r];
                 un[r] = u;
@@ -888,8 +891,8 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
         }
     }
     if (check) {
-        r1 = block_max(r1, red);
-        r2 = block_max(r2, red);
+        r1 = block_max<kWG>(r1, red);
+        r2 = block_max<kWG>(r2, red);
         if (t == 0) {
             record_max(&P->res[0], r1);
             record_max(&P->res[1], r2);
@@ -903,15 +906,15 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
 
 // eta = L z for the blocks node v owns (Sec. 4.4).
 template <typename real>
-__global__ __launch_bounds__(kWG) void k_apply_L(const ProbDev<real>* __restrict__ P,
+__global__ __launch_bounds__(kHookWG) void k_apply_L(const ProbDev<real>* __restrict__ P,
                                                  const real* __restrict__ z, real* __restrict__ eta) {
-    __shared__ real red[kWG];
+    __shared__ real red[kHookWG];
     const int v = blockIdx.x, t = threadIdx.x;
     const int nx = P->nx, nu = P->nu, m = P->m, nbox = P->nbox;
     const real* x = z + P->z_x + (long long)v * nx;
     if (v < P->n_nl) {
         const real* u = z + P->z_u + (long long)v * nu;
-        for (int r = t; r < P->nc; r += kWG) {
+        for (int r = t; r < P->nc; r += kHookWG) {
             real w;
             if (r < nx) w = P->gx[r] * x[r];
             else if (r < nbox) w = P->gu[r - nx] * u[r - nx];
@@ -922,31 +925,31 @@ __global__ __launch_bounds__(kWG) void k_apply_L(const ProbDev<real>* __restrict
         const long long yo = P->y_off[v];
         const real* y = z + P->z_y + yo;
         real b = 0;
-        for (int c = t; c < k; c += kWG) b += P->prob[fc + c] * y[c];
-        b = block_sum(b, red) + y[2 * k];
+        for (int c = t; c < k; c += kHookWG) b += P->prob[fc + c] * y[c];
+        b = block_sum<kHookWG>(b, red) + y[2 * k];
         const real s = (v == 0) ? z[0] : z[P->z_s + v - 1];
         if (t == 0) eta[P->e_s + v] = s - b;
-        for (int c = t; c < 2 * k + 1; c += kWG) eta[P->e_y + yo + c] = y[c];
+        for (int c = t; c < 2 * k + 1; c += kHookWG) eta[P->e_y + yo + c] = y[c];
         for (int q = 0; q < k; ++q) {
             const int j = fc + q;
             const real tau = z[P->z_tau + j - 1];
             real* o = eta + P->e_soc + (long long)(j - 1) * (m + 2);
-            for (int r = t; r < m + 2; r += kWG)
+            for (int r = t; r < m + 2; r += kHookWG)
                 o[r] = r < nx ? P->qh[r] * x[r] : (r < m ? P->rh[r - nx] * u[r - nx] : real(0.5) * tau);
         }
     } else {
         const long long lf = v - P->n_nl;
-        for (int r = t; r < P->ncN; r += kWG)
+        for (int r = t; r < P->ncN; r += kHookWG)
             eta[P->e_cN + lf * P->ncN + r] = r < nx ? P->gxN[r] * x[r] : P->gbN[r - nx] * x[r - nx];
         const real s = z[P->z_s + v - 1];
-        for (int r = t; r < nx + 2; r += kWG)
+        for (int r = t; r < nx + 2; r += kHookWG)
             eta[P->e_socN + lf * (nx + 2) + r] = r < nx ? P->qnh[r] * x[r] : real(0.5) * s;
     }
 }
 
 // z = L* eta for the primal entries node v owns (adjoint of k_apply_L).
 template <typename real>
-__global__ __launch_bounds__(kWG) void k_apply_Lt(const ProbDev<real>* __restrict__ P,
+__global__ __launch_bounds__(kHookWG) void k_apply_Lt(const ProbDev<real>* __restrict__ P,
                                                   const real* __restrict__ eta, real* __restrict__ z) {
     const int v = blockIdx.x, t = threadIdx.x;
     const int nx = P->nx, nu = P->nu, m = P->m, nbox = P->nbox;
@@ -954,21 +957,21 @@ __global__ __launch_bounds__(kWG) void k_apply_Lt(const ProbDev<real>* __restric
     if (v < P->n_nl) {
         const int k = P->n_ch[v], fc = P->first_child[v];
         const real* ec = eta + P->e_c + (long long)v * P->nc;
-        for (int r = t; r < nx; r += kWG) {
+        for (int r = t; r < nx; r += kHookWG) {
             real s = 0;
             for (int q = 0; q < k; ++q) s += eta[P->e_soc + (long long)(fc + q - 1) * (m + 2) + r];
             real w = P->gx[r] * ec[r] + P->qh[r] * s;
             if (P->has_ball) w += P->gb[r] * ec[nbox + r];
             x[r] = w;
         }
-        for (int r = t; r < nu; r += kWG) {
+        for (int r = t; r < nu; r += kHookWG) {
             real s = 0;
             for (int q = 0; q < k; ++q) s += eta[P->e_soc + (long long)(fc + q - 1) * (m + 2) + nx + r];
             z[P->z_u + (long long)v * nu + r] = P->gu[r] * ec[nx + r] + P->rh[r] * s;
         }
         const long long yo = P->y_off[v];
         const real es = eta[P->e_s + v];
-        for (int c = t; c < 2 * k + 1; c += kWG) {
+        for (int c = t; c < 2 * k + 1; c += kHookWG) {
             const real bc = c < k ? P->prob[fc + c] : (c == 2 * k ? real(1) : real(0));
             z[P->z_y + yo + c] = eta[P->e_y + yo + c] - bc * es;
         }
@@ -976,7 +979,7 @@ __global__ __launch_bounds__(kWG) void k_apply_Lt(const ProbDev<real>* __restric
             if (v == 0) z[0] = es;
             else z[P->z_s + v - 1] = es;
         }
-        for (int q = t; q < k; q += kWG) {
+        for (int q = t; q < k; q += kHookWG) {
             const int j = fc + q;
             const real* o = eta + P->e_soc + (long long)(j - 1) * (m + 2);
             z[P->z_tau + j - 1] = real(0.5) * (o[m] + o[m + 1]);
@@ -985,7 +988,7 @@ __global__ __launch_bounds__(kWG) void k_apply_Lt(const ProbDev<real>* __restric
         const long long lf = v - P->n_nl;
         const real* ecN = eta + P->e_cN + lf * P->ncN;
         const real* esN = eta + P->e_socN + lf * (nx + 2);
-        for (int r = t; r < nx; r += kWG) {
+        for (int r = t; r < nx; r += kHookWG) {
             real w = P->gxN[r] * ecN[r] + P->qnh[r] * esN[r];
             if (P->has_ballN) w += P->gbN[r] * ecN[nx + r];
             x[r] = w;
@@ -996,24 +999,24 @@ __global__ __launch_bounds__(kWG) void k_apply_Lt(const ProbDev<real>* __restric
 
 // eta = w - alpha proj_S3(w / alpha) for the blocks node v owns.
 template <typename real>
-__global__ __launch_bounds__(kWG) void k_prox_gconj(const ProbDev<real>* __restrict__ P,
+__global__ __launch_bounds__(kHookWG) void k_prox_gconj(const ProbDev<real>* __restrict__ P,
                                                     const real* __restrict__ w, real* __restrict__ eta) {
-    __shared__ real red[kWG];
+    __shared__ real red[kHookWG];
     const int v = blockIdx.x, t = threadIdx.x;
     const int nx = P->nx, m = P->m, nbox = P->nbox;
     const real alpha = P->alpha;
     auto soc = [&](long long off, int len) {
         real nw2 = 0;
-        for (int r = t; r < len - 1; r += kWG) {
+        for (int r = t; r < len - 1; r += kHookWG) {
             real e = w[off + r];
             if (r == len - 2) e -= real(0.5) * alpha;
             nw2 += e * e;
         }
-        nw2 = block_sum(nw2, red);
+        nw2 = block_sum<kHookWG>(nw2, red);
         const real vt = w[off + len - 1] + real(0.5) * alpha;
         real cw, ct;
         soc_moreau_coef(nw2, vt, cw, ct);
-        for (int r = t; r < len; r += kWG) {
+        for (int r = t; r < len; r += kHookWG) {
             real e = w[off + r];
             if (r == len - 2) e -= real(0.5) * alpha;
             eta[off + r] = r < len - 1 ? e * cw : ct;
@@ -1021,20 +1024,20 @@ __global__ __launch_bounds__(kWG) void k_prox_gconj(const ProbDev<real>* __restr
     };
     auto ballbox = [&](long long off, int nb, int ntot, const real* lo, const real* hi, real r_ball) {
         real nb2 = 0;
-        for (int r = nb + t; r < ntot; r += kWG) nb2 += w[off + r] * w[off + r];
+        for (int r = nb + t; r < ntot; r += kHookWG) nb2 += w[off + r] * w[off + r];
         real cb = 0;
         if (ntot > nb) {
-            nb2 = block_sum(nb2, red);
+            nb2 = block_sum<kHookWG>(nb2, red);
             const real nrm = sqrt(nb2), rad = alpha * r_ball;
             cb = nrm > rad ? real(1) - rad / nrm : real(0);
         }
-        for (int r = t; r < ntot; r += kWG)
+        for (int r = t; r < ntot; r += kHookWG)
             eta[off + r] = r < nb ? moreau_box(w[off + r], alpha, lo[r], hi[r]) : w[off + r] * cb;
     };
     if (v < P->n_nl) {
         const int k = P->n_ch[v], fc = P->first_child[v];
         const long long yo = P->y_off[v];
-        for (int c = t; c < 2 * k + 1; c += kWG) {
+        for (int c = t; c < 2 * k + 1; c += kHookWG) {
             const real e = w[P->e_y + yo + c];
             eta[P->e_y + yo + c] = c < 2 * k ? (e < 0 ? e : real(0)) : real(0);
         }
@@ -1070,45 +1073,65 @@ __global__ void k_fill(T* __restrict__ dst, T val, long long n) {
 // launchers (host side)
 // ---------------------------------------------------------------------------
 
+template <typename real, int WG>
+static hipError_t launch_sweep(bool backward, const ProbDev<real>* probs, const int2* tasks, int* ticket,
+                               int n_tasks, int lds_bytes, int par, int check, hipStream_t st) {
+    if (backward)
+        hipLaunchKernelGGL((k_backward<real, WG>), dim3(n_tasks), dim3(WG), lds_bytes, st, probs, tasks, ticket,
+                           par, check);
+    else
+        hipLaunchKernelGGL((k_forward<real, WG>), dim3(n_tasks), dim3(WG), lds_bytes, st, probs, tasks, ticket,
+                           par, check);
+    return hipGetLastError();
+}
+
+template <typename real>
+static hipError_t launch_wg(bool backward, const ProbDev<real>* probs, const int2* tasks, int* ticket,
+                            int n_tasks, int lds_bytes, int par, int check, int wg, hipStream_t st) {
+    switch (wg) {
+        case 64: return launch_sweep<real, 64>(backward, probs, tasks, ticket, n_tasks, lds_bytes, par, check, st);
+        case 128: return launch_sweep<real, 128>(backward, probs, tasks, ticket, n_tasks, lds_bytes, par, check, st);
+        case 256: return launch_sweep<real, 256>(backward, probs, tasks, ticket, n_tasks, lds_bytes, par, check, st);
+        case 512: return launch_sweep<real, 512>(backward, probs, tasks, ticket, n_tasks, lds_bytes, par, check, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename real>
 hipError_t launch_backward(const ProbDev<real>* probs, const int2* tasks, int* ticket, int n_tasks,
-                           int lds_bytes, int par, int check, hipStream_t st) {
-    hipLaunchKernelGGL(k_backward<real>, dim3(n_tasks), dim3(kWG), lds_bytes, st, probs, tasks, ticket, par,
-                       check);
-    return hipGetLastError();
+                           int lds_bytes, int par, int check, int wg, hipStream_t st) {
+    return launch_wg<real>(true, probs, tasks, ticket, n_tasks, lds_bytes, par, check, wg, st);
 }
 
 template <typename real>
 hipError_t launch_forward(const ProbDev<real>* probs, const int2* tasks, int* ticket, int n_tasks,
-                          int lds_bytes, int par, int check, hipStream_t st) {
-    hipLaunchKernelGGL(k_forward<real>, dim3(n_tasks), dim3(kWG), lds_bytes, st, probs, tasks, ticket, par,
-                       check);
-    return hipGetLastError();
+                          int lds_bytes, int par, int check, int wg, hipStream_t st) {
+    return launch_wg<real>(false, probs, tasks, ticket, n_tasks, lds_bytes, par, check, wg, st);
 }
 
 template <typename real>
 hipError_t launch_step(const ProbDev<real>* probs, const int2* tasks, int* ticket, int n_tasks, int lds_bytes,
-                       int par, int check, hipStream_t st) {
-    hipError_t e = launch_backward<real>(probs, tasks, ticket, n_tasks, lds_bytes, par, check, st);
+                       int par, int check, int wg, hipStream_t st) {
+    hipError_t e = launch_backward<real>(probs, tasks, ticket, n_tasks, lds_bytes, par, check, wg, st);
     if (e != hipSuccess) return e;
-    return launch_forward<real>(probs, tasks, ticket, n_tasks, lds_bytes, par, check, st);
+    return launch_forward<real>(probs, tasks, ticket, n_tasks, lds_bytes, par, check, wg, st);
 }
 
 template <typename real>
 hipError_t launch_apply_L(const ProbDev<real>* P, int n, const real* z, real* eta, hipStream_t st) {
-    hipLaunchKernelGGL(k_apply_L<real>, dim3(n), dim3(kWG), 0, st, P, z, eta);
+    hipLaunchKernelGGL(k_apply_L<real>, dim3(n), dim3(kHookWG), 0, st, P, z, eta);
     return hipGetLastError();
 }
 
 template <typename real>
 hipError_t launch_apply_Lt(const ProbDev<real>* P, int n, const real* eta, real* z, hipStream_t st) {
-    hipLaunchKernelGGL(k_apply_Lt<real>, dim3(n), dim3(kWG), 0, st, P, eta, z);
+    hipLaunchKernelGGL(k_apply_Lt<real>, dim3(n), dim3(kHookWG), 0, st, P, eta, z);
     return hipGetLastError();
 }
 
 template <typename real>
 hipError_t launch_prox_gconj(const ProbDev<real>* P, int n, const real* w, real* eta, hipStream_t st) {
-    hipLaunchKernelGGL(k_prox_gconj<real>, dim3(n), dim3(kWG), 0, st, P, w, eta);
+    hipLaunchKernelGGL(k_prox_gconj<real>, dim3(n), dim3(kHookWG), 0, st, P, w, eta);
     return hipGetLastError();
 }
 
@@ -1131,12 +1154,12 @@ hipError_t launch_fill(T* dst, T val, long long n, hipStream_t st) {
 }
 
 #define SPK_INSTANTIATE(real)                                                                              \
-    template hipError_t launch_step<real>(const ProbDev<real>*, const int2*, int*, int, int, int, int,      \
+    template hipError_t launch_step<real>(const ProbDev<real>*, const int2*, int*, int, int, int, int, int,  \
                                           hipStream_t);                                                    \
-    template hipError_t launch_backward<real>(const ProbDev<real>*, const int2*, int*, int, int, int, int,  \
-                                              hipStream_t);                                                \
-    template hipError_t launch_forward<real>(const ProbDev<real>*, const int2*, int*, int, int, int, int,   \
-                                             hipStream_t);                                                 \
+    template hipError_t launch_backward<real>(const ProbDev<real>*, const int2*, int*, int, int, int, int, \
+                                              int, hipStream_t);                                           \
+    template hipError_t launch_forward<real>(const ProbDev<real>*, const int2*, int*, int, int, int, int,  \
+                                             int, hipStream_t);                                            \
     template hipError_t launch_apply_L<real>(const ProbDev<real>*, int, const real*, real*, hipStream_t);   \
     template hipError_t launch_apply_Lt<real>(const ProbDev<real>*, int, const real*, real*, hipStream_t);  \
     template hipError_t launch_prox_gconj<real>(const ProbDev<real>*, int, const real*, real*, hipStream_t); \

@@ -102,6 +102,9 @@ SIGNATURES = {
     "spock_time_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp]),
     "spock_step_bytes": (C.c_int32, [C.c_void_p, C.c_int32, _dp, _dp]),
     "spock_run_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    "spock_set_launch": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
+    "spock_get_launch": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "spock_batch_set_launch": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
     "spock_batch_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(Settings),
                                        C.POINTER(C.c_void_p)]),
     "spock_batch_destroy": (C.c_int32, [C.c_void_p]),
@@ -312,6 +315,14 @@ class Problem:
     def run_steps(self, steps, precision=FP64, sync=True):
         _check(load().spock_run_steps(self.h, precision, int(steps), int(bool(sync))))
 
+    def set_launch(self, workgroup, precision=FP64):
+        _check(load().spock_set_launch(self.h, precision, int(workgroup)))
+
+    def get_launch(self, precision=FP64):
+        v = C.c_int32()
+        _check(load().spock_get_launch(self.h, precision, C.byref(v)))
+        return v.value
+
     def step_bytes(self, precision=FP64):
         b, f = C.c_double(), C.c_double()
         _check(load().spock_step_bytes(self.h, precision, C.byref(b), C.byref(f)))
@@ -358,6 +369,9 @@ class Batch:
 
     def run_steps(self, steps, precision=FP64, sync=True):
         _check(load().spock_batch_run_steps(self.h, precision, int(steps), int(bool(sync))))
+
+    def set_launch(self, workgroup, precision=FP64):
+        _check(load().spock_batch_set_launch(self.h, precision, int(workgroup)))
 
     def time_steps(self, steps, precision=FP64):
         t, b, f = C.c_double(), C.c_double(), C.c_double()

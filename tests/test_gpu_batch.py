@@ -87,3 +87,37 @@ def test_batch_warm_start_after_shift():
         assert warm[k]["iters"] <= cold[k]["iters"] + 20
     for h in handles:
         h.close()
+
+
+@pytest.mark.parametrize("wg", [64, 128, 512])
+def test_workgroup_sizes_match_oracle(wg):
+    """Every launch size the autotuner may pick computes the same CP step."""
+    for p in (W.config_problem(1), W.batch_problem(3), W.random_ragged_problem(8, N=3, nx=5, nu=2)):
+        D = O.Data(p)
+        F = O.Offline(D)
+        a = O.step_size(D)
+        rng = np.random.default_rng(wg)
+        with S.Problem(p, S.default_settings(alpha=a)) as P:
+            P.set_x0(p["x0"])
+            P.set_launch(wg, S.FP64)
+            P.set_launch(wg, S.FP32)
+            z, e = rng.standard_normal(P.nz), rng.standard_normal(P.neta)
+            zo, eo = O.cp_step(D, F, z, e, a)
+            zg, eg, _ = P.apply_T(z, e)
+            sc = max(1.0, np.abs(zo).max(), np.abs(eo).max(), np.abs(z).max(), np.abs(e).max())
+            assert np.abs(zg - zo).max() / sc < 1e-10 and np.abs(eg - eo).max() / sc < 1e-10
+            zf, ef, _ = P.apply_T(z, e, S.FP32)
+            assert np.abs(zf - zo).max() / sc < 2e-4 and np.abs(ef - eo).max() / sc < 2e-4
+
+
+def test_autotuner_picks_a_candidate(tmp_path):
+    from paper_2505_12078_amd import tune
+    p = W.batch_problem(2)
+    with S.Problem(p) as P:
+        P.set_x0(p["x0"])
+        best, times = tune.tune_problem(P, S.FP32, steps=6, cache_path=str(tmp_path / "t.json"))
+        assert best in tune.CANDIDATES and best == min(times, key=times.get)
+        assert P.get_launch(S.FP32) == best
+        again, _ = tune.tune_problem(P, S.FP32, cache_path=str(tmp_path / "t.json"))
+        assert again == best
+        assert P.solve(p["x0"])["code"] == S.SPOCK_OK
