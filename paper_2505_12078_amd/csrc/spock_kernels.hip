@@ -865,8 +865,8 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
                 else if (b == 1) fwd_block_risk(P, v, zin, zout, ein, eout, check, r1, r2);
                 else fwd_block_soc(P, fc + b - 2, zin, zout, ein, eout, V, check, r1, r2);
             }
-        } else if (w < 2) {
-            fwd_block_leaf(P, v, w, zin, zout, ein, eout, V, check, r1, r2);
+        } else {
+            for (int b = w; b < 2; b += kWG / 64) fwd_block_leaf(P, v, b, zin, zout, ein, eout, V, check, r1, r2);
         }
         if (check) {
             __syncthreads();
