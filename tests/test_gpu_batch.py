@@ -120,4 +120,5 @@ def test_autotuner_picks_a_candidate(tmp_path):
         assert P.get_launch(S.FP32) == best
         again, _ = tune.tune_problem(P, S.FP32, cache_path=str(tmp_path / "t.json"))
         assert again == best
+        P.set_settings(eps=1e-4)
         assert P.solve(p["x0"])["code"] == S.SPOCK_OK
