@@ -85,13 +85,21 @@ __host__ __device__ inline int blk_elems(int nx, int nu, int max_ch) {
     return b;
 }
 
-// Number of `real` elements of dynamic LDS a sweep workgroup needs (the
-// larger of the backward and the forward partitions).
+// Elements of the LDS area that stages one node's vector inputs.
+__host__ __device__ inline int stage_elems(int nx, int nu, int nc, int max_ch) {
+    const int m = nx + nu;
+    return 3 * nx + 2 * nu + nc + max_ch * (2 * m + nx + 12) + 16;
+}
+
+// Number of `real` elements of dynamic LDS a sweep workgroup of `wg` threads
+// needs (the larger of the backward and the forward partitions).
 __host__ __device__ inline int lds_elems(int nx, int nu, int max_ch, int wg) {
     const int m = nx + nu;
+    const int nc = m + nx;  // the larger constraint block (with a ball)
     const int waves = wg / 64;
-    const int bwd = wg + 2 * m + nx + 2 * nu + 5 * max_ch;
-    const int fwd = wg + m + (2 + waves) * nx + (3 + waves) * nu + 2 * waves * blk_elems(nx, nu, max_ch);
+    const int common = wg + 10 * nx + 4 * nu + stage_elems(nx, nu, nc, max_ch);
+    const int bwd = common + 2 * m + nx + 2 * nu + max_ch;
+    const int fwd = common + m + nx + nu + waves * (nx + nu) + 2 * waves * blk_elems(nx, nu, max_ch);
     return (bwd > fwd ? bwd : fwd) + 8;
 }
 

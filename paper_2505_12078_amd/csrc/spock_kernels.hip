@@ -274,77 +274,137 @@ SPK_DEV void record_max(unsigned long long* slot, real v) {
 }
 
 // ---------------------------------------------------------------------------
-// backward sweep
+// node input staging
 // ---------------------------------------------------------------------------
 
-// S2 projection (Sec. 4.3) of node i's block (y^i, tau^[i], s^[i]) after the
-// z - alpha L* eta shift, written to zout; run by one wavefront.  Kernel of
-// G = [E^T, -I, -I] with E = [gamma I; -I; 1^T] (AV@R, Sec. 3.3).
-// G G^T = (gamma^2 + 3) I + 1 1^T, so with rho = G w the multiplier is
-// lambda = (rho - (1^T rho / (c + n)) 1) / c, c = gamma^2 + 3 (Sherman-Morrison),
-// and w - G^T lambda is the projection.
+// A node's vector inputs come from several arrays (z, eta, d, messages, ...).
+// They are gathered into LDS in one pass: thread 0 writes a table of
+// (source, length) segments, then every thread issues its share of the loads
+// back to back before storing any of them, so a node costs one memory round
+// trip for its vectors (issued together with its matrix tiles).
+constexpr int kMaxSeg = 16;
+constexpr int kGatherE = 4;  // loads in flight per thread per pass
+
 template <typename real>
-SPK_DEV void s2_block_wave(const ProbDev<real>* __restrict__ P, int i, const real* __restrict__ zin,
-                           const real* __restrict__ ein, real* __restrict__ zout, real* lam) {
-    const int lane = threadIdx.x & 63;
-    const int k = P->n_ch[i], fc = P->first_child[i];
-    const int nx = P->nx, m = P->m;
-    const real alpha = P->alpha, gam = P->gamma[i];
-    const long long yo = P->y_off[i];
-    const real es = ein[P->e_s + i];
-    const real yb3 = zin[P->z_y + yo + 2 * k] - alpha * (ein[P->e_y + yo + 2 * k] - es);
-    const real cc = gam * gam + real(3);
-    real rsum = 0;
-    for (int c = lane; c < k; c += 64) {
-        const int j = fc + c;
-        const real yb1 = zin[P->z_y + yo + c] - alpha * (ein[P->e_y + yo + c] - P->prob[j] * es);
-        const real yb2 = zin[P->z_y + yo + k + c] - alpha * ein[P->e_y + yo + k + c];
-        const real* es_soc = ein + P->e_soc + (long long)(j - 1) * (m + 2);
-        const real tb = zin[P->z_tau + j - 1] - alpha * real(0.5) * (es_soc[m] + es_soc[m + 1]);
-        real lts;
-        if (j < P->n_nl) {
-            lts = ein[P->e_s + j];
-        } else {
-            const real* esN = ein + P->e_socN + (long long)(j - P->n_nl) * (nx + 2);
-            lts = real(0.5) * (esN[nx] + esN[nx + 1]);
-        }
-        const real sb = zin[P->z_s + j - 1] - alpha * lts;
-        const real rho = gam * yb1 - yb2 + yb3 - tb - sb;
-        // keep the shifted values in the output slots; corrected below
-        zout[P->z_y + yo + c] = yb1;
-        zout[P->z_y + yo + k + c] = yb2;
-        zout[P->z_tau + j - 1] = tb;
-        zout[P->z_s + j - 1] = sb;
-        lam[c] = rho;
-        rsum += rho;
-    }
-    rsum = wave_sum(rsum);
-    real lsum = 0;
-    for (int c = lane; c < k; c += 64) {
-        const real l = (lam[c] - rsum / (cc + real(k))) / cc;
-        lsum += l;
-        const int j = fc + c;
-        zout[P->z_y + yo + c] -= gam * l;
-        zout[P->z_y + yo + k + c] += l;
-        zout[P->z_tau + j - 1] += l;
-        zout[P->z_s + j - 1] += l;
-    }
-    lsum = wave_sum(lsum);
-    if (lane == 0) zout[P->z_y + yo + 2 * k] = yb3 - lsum;
+struct SegTable {
+    const real* src[kMaxSeg];
+    int off[kMaxSeg + 1];
+    int n;
+};
+
+template <typename real>
+SPK_DEV void seg_reset(SegTable<real>& T) {
+    T.n = 0;
+    T.off[0] = 0;
 }
+
+template <typename real>
+SPK_DEV void seg_add(SegTable<real>& T, const real* src, int len) {
+    T.src[T.n] = src;
+    T.off[T.n + 1] = T.off[T.n] + len;
+    T.n++;
+}
+
+template <int kWG, typename real>
+SPK_DEV void seg_gather(const SegTable<real>& T, real* st) {
+    const int total = T.off[T.n];
+    for (int base = 0; base < total; base += kGatherE * kWG) {
+        real v[kGatherE];
+#pragma unroll
+        for (int j = 0; j < kGatherE; ++j) {
+            const int e = base + j * kWG + (int)threadIdx.x;
+            v[j] = 0;
+            if (e < total) {
+                int s = 0;
+                while (e >= T.off[s + 1]) ++s;
+                v[j] = T.src[s][e - T.off[s]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kGatherE; ++j) {
+            const int e = base + j * kWG + (int)threadIdx.x;
+            if (e < total) st[e] = v[j];
+        }
+    }
+}
+
+// Per-problem diagonal data staged once per workgroup.
+template <typename real>
+struct Consts {
+    const real *qh, *rh, *qnh, *gx, *gu, *gb, *gxN, *gbN, *lo, *hi, *loN, *hiN;
+};
+
+SPK_DEV int consts_elems(int nx, int nu) { return 10 * nx + 4 * nu; }
+
+template <typename real>
+SPK_DEV void consts_table(const ProbDev<real>* __restrict__ P, SegTable<real>& T) {
+    const int nx = P->nx, nu = P->nu, m = P->m;
+    seg_reset(T);
+    seg_add(T, P->qh, nx);
+    seg_add(T, P->rh, nu);
+    seg_add(T, P->qnh, nx);
+    seg_add(T, P->gx, nx);
+    seg_add(T, P->gu, nu);
+    seg_add(T, P->gb, nx);
+    seg_add(T, P->gxN, nx);
+    seg_add(T, P->gbN, nx);
+    seg_add(T, P->lo, m);
+    seg_add(T, P->hi, m);
+    seg_add(T, P->loN, nx);
+    seg_add(T, P->hiN, nx);
+}
+
+template <typename real>
+SPK_DEV Consts<real> consts_at(const real* c, int nx, int nu) {
+    const int m = nx + nu;
+    Consts<real> C;
+    C.qh = c;
+    C.rh = C.qh + nx;
+    C.qnh = C.rh + nu;
+    C.gx = C.qnh + nx;
+    C.gu = C.gx + nx;
+    C.gb = C.gu + nu;
+    C.gxN = C.gb + nx;
+    C.gbN = C.gxN + nx;
+    C.lo = C.gbN + nx;
+    C.hi = C.lo + m;
+    C.loN = C.hi + m;
+    C.hiN = C.loN + nx;
+    return C;
+}
+
+// Root-to-leaf path nodes, their child counts and first children (LDS).
+template <int kWG, typename real>
+SPK_DEV void load_path(const ProbDev<real>* __restrict__ P, int leaf, int from, int* s_node, int* s_nch,
+                       int* s_fc) {
+    const int N = P->N;
+    const int* path = P->path + (long long)leaf * (N + 1);
+    for (int q = from + (int)threadIdx.x; q <= N; q += kWG) {
+        const int v = path[q];
+        s_node[q] = v;
+        s_nch[q] = v < P->n_nl ? P->n_ch[v] : 0;
+        s_fc[q] = v < P->n_nl ? P->first_child[v] : 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward sweep
+// ---------------------------------------------------------------------------
 
 template <typename real, int kWG>
 __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restrict__ probs,
                                                   const int2* __restrict__ tasks, int* __restrict__ ticket,
                                                   int par, int check) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int s_path[kMaxDepth];
+    __shared__ int s_node[kMaxDepth], s_nch[kMaxDepth], s_fc[kMaxDepth];
+    __shared__ SegTable<real> s_seg;
     __shared__ int s_last;
     real* sm = reinterpret_cast<real*>(smem_raw);
     const int2 tk = tasks[blockIdx.x];
     const ProbDev<real>* __restrict__ P = probs + tk.x;
     if (*P->active == 0) return;
-    const int nx = P->nx, nu = P->nu, m = P->m, N = P->N;
+    const int nx = P->nx, nu = P->nu, m = P->m, N = P->N, nc = P->nc, ncN = P->ncN, nbox = P->nbox;
+    const int n_nl = P->n_nl;
     const real alpha = P->alpha;
     const real* __restrict__ zin = P->z[par];
     const real* __restrict__ ein = P->eta[par];
@@ -352,36 +412,51 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
     const int t = threadIdx.x;
 
     real* red = sm;
-    real* xb = red + kWG;   // xbar, then h = q + P c
-    real* ub = xb + nx;     // ubar
-    real* g = ub + nu;      // sum of children messages
-    real* w2 = g + m;       // ubar - g_u
-    real* o = w2 + nu;      // product outputs
-    real* lam = o + m;      // S2 multipliers, max_ch
+    real* cst = red + kWG;
+    real* st = cst + consts_elems(nx, nu);
+    real* xb = st + stage_elems(nx, nu, nc, P->max_ch);  // xbar, then h = q + P c
+    real* ub = xb + nx;                                  // ubar
+    real* g = ub + nu;                                   // sum of children messages
+    real* w2 = g + m;                                    // ubar - g_u
+    real* o = w2 + nu;                                   // product outputs
+    real* lam = o + m;                                   // S2 multipliers
 
-    {
-        const int* path = P->path + (long long)tk.y * (N + 1);
-        for (int q = t; q <= N; q += kWG) s_path[q] = path[q];
-    }
+    load_path<kWG>(P, tk.y, 0, s_node, s_nch, s_fc);
+    if (t == 0) consts_table(P, s_seg);
     __syncthreads();
-
+    seg_gather<kWG>(s_seg, cst);
+    const Consts<real> C = consts_at<real>(cst, nx, nu);
     const bool tiles = m <= kWG;  // one column tile: register-prefetched products
+
     // ---- leaf: q = -xbar, message [Abar|B]^T (q + P c) ----
-    int j = s_path[N];
+    int j = s_node[N];
     {
         TTile<real, kRBM> TM;
         if (tiles) t_load<kWG>(TM, P->M + j * P->M_stride, nx, m, m);
-        const long long lf = j - P->n_nl;
-        const real* ecN = ein + P->e_cN + lf * P->ncN;
-        const real* esN = ein + P->e_socN + lf * (nx + 2);
+        const long long lf = j - n_nl;
+        __syncthreads();  // constants gathered, table free
+        if (t == 0) {
+            seg_reset(s_seg);
+            seg_add(s_seg, zin + P->z_x + (long long)j * nx, nx);
+            seg_add(s_seg, ein + P->e_cN + lf * ncN, ncN);
+            seg_add(s_seg, ein + P->e_socN + lf * (nx + 2), nx + 2);
+            if (P->affine) seg_add(s_seg, P->Pc + (long long)j * nx, nx);
+            P->flag[j] = 0;
+        }
+        __syncthreads();
+        seg_gather<kWG>(s_seg, st);
+        __syncthreads();
+        const real* sx = st;
+        const real* sc = sx + nx;
+        const real* ss = sc + ncN;
+        const real* spc = ss + nx + 2;
         for (int k = t; k < nx; k += kWG) {
-            real lt = P->gxN[k] * ecN[k] + P->qnh[k] * esN[k];
-            if (P->has_ballN) lt += P->gbN[k] * ecN[nx + k];
-            real h = -(zin[P->z_x + (long long)j * nx + k] - alpha * lt);
-            if (P->affine) h += P->Pc[(long long)j * nx + k];
+            real lt = C.gxN[k] * sc[k] + C.qnh[k] * ss[k];
+            if (P->has_ballN) lt += C.gbN[k] * sc[nx + k];
+            real h = -(sx[k] - alpha * lt);
+            if (P->affine) h += spc[k];
             xb[k] = h;
         }
-        if (t == 0) P->flag[j] = 0;
         __syncthreads();
         if (tiles) t_apply<kWG>(TM, P->M + j * P->M_stride, nx, m, m, m, xb, xb, o, red);
         else mat_t_vec<kWG>(P->M + j * P->M_stride, nx, m, m, m, xb, xb, o, red);
@@ -389,8 +464,8 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
 
     // ---- walk up ----
     for (int lev = N - 1; lev >= 0; --lev) {
-        const int i = s_path[lev];
-        const int k = P->n_ch[i], fc = P->first_child[i];
+        const int i = s_node[lev];
+        const int k = s_nch[lev], fc = s_fc[lev];
         if (k > 1) {
             for (int c = t; c < m; c += kWG) P->e[(long long)j * m + c] = o[c];
             // every wave makes its own stores visible device-wide before the
@@ -406,55 +481,129 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
             }
             __syncthreads();
             if (!s_last) return;
-            for (int c = t; c < m; c += kWG) {
-                real s = 0;
-                for (int q = 0; q < k; ++q) s += P->e[(long long)(fc + q) * m + c];
-                g[c] = s;
-            }
-        } else {
-            for (int c = t; c < m; c += kWG) g[c] = o[c];
         }
-
         TTile<real, kRBK> TK;
         TTile<real, kRBM> TM;
         if (tiles) {
             t_load<kWG>(TK, P->KR + i * P->KR_stride, nu, m, m);
             if (i > 0) t_load<kWG>(TM, P->M + i * P->M_stride, nx, m, m);
         }
+        const bool leafkids = fc >= n_nl;
+        const int cs_len = leafkids ? k * (nx + 2) : k;
+        const long long yo = P->y_off[i];
+        // staged inputs of node i (offsets into st)
+        const int oX = 0, oU = oX + nx, oEC = oU + nu, oSOC = oEC + nc, oEY = oSOC + k * (m + 2);
+        const int oES = oEY + 2 * k + 1, oZY = oES + 1, oZT = oZY + 2 * k + 1, oZS = oZT + k, oCS = oZS + k;
+        const int oP = oCS + cs_len, oMSG = oP + k, oPC = oMSG + (k > 1 ? k * m : 0);
+        if (t == 0) {
+            seg_reset(s_seg);
+            seg_add(s_seg, zin + P->z_x + (long long)i * nx, nx);
+            seg_add(s_seg, zin + P->z_u + (long long)i * nu, nu);
+            seg_add(s_seg, ein + P->e_c + (long long)i * nc, nc);
+            seg_add(s_seg, ein + P->e_soc + (long long)(fc - 1) * (m + 2), k * (m + 2));
+            seg_add(s_seg, ein + P->e_y + yo, 2 * k + 1);
+            seg_add(s_seg, ein + P->e_s + i, 1);
+            seg_add(s_seg, zin + P->z_y + yo, 2 * k + 1);
+            seg_add(s_seg, zin + P->z_tau + fc - 1, k);
+            seg_add(s_seg, zin + P->z_s + fc - 1, k);
+            if (leafkids) seg_add(s_seg, ein + P->e_socN + (long long)(fc - n_nl) * (nx + 2), cs_len);
+            else seg_add(s_seg, ein + P->e_s + fc, k);
+            seg_add(s_seg, P->prob + fc, k);
+            if (k > 1) seg_add(s_seg, P->e + (long long)fc * m, k * m);
+            if (P->affine && i > 0) seg_add(s_seg, P->Pc + (long long)i * nx, nx);
+            P->flag[i] = 0;
+        }
+        __syncthreads();
+        seg_gather<kWG>(s_seg, st);
+        __syncthreads();
+
+        for (int c = t; c < m; c += kWG) {
+            if (k > 1) {
+                real s = 0;
+                for (int q = 0; q < k; ++q) s += st[oMSG + q * m + c];
+                g[c] = s;
+            } else {
+                g[c] = o[c];
+            }
+        }
         // zbar for (x^i, u^i): L* gathers the constraint rows and the SOC rows of
         // every child edge (Sec. 4.4)
-        const real* ec = ein + P->e_c + (long long)i * P->nc;
         for (int r = t; r < nx; r += kWG) {
             real s = 0;
-            for (int q = 0; q < k; ++q) s += ein[P->e_soc + (long long)(fc + q - 1) * (m + 2) + r];
-            real lt = P->gx[r] * ec[r] + P->qh[r] * s;
-            if (P->has_ball) lt += P->gb[r] * ec[P->nbox + r];
-            xb[r] = zin[P->z_x + (long long)i * nx + r] - alpha * lt;
+            for (int q = 0; q < k; ++q) s += st[oSOC + q * (m + 2) + r];
+            real lt = C.gx[r] * st[oEC + r] + C.qh[r] * s;
+            if (P->has_ball) lt += C.gb[r] * st[oEC + nbox + r];
+            xb[r] = st[oX + r] - alpha * lt;
         }
         for (int r = t; r < nu; r += kWG) {
-            real s = 0;
-            for (int q = 0; q < k; ++q) s += ein[P->e_soc + (long long)(fc + q - 1) * (m + 2) + nx + r];
-            const real lt = P->gu[r] * ec[nx + r] + P->rh[r] * s;
-            const real u = zin[P->z_u + (long long)i * nu + r] - alpha * lt;
+            real s = 0, gu = 0;
+            for (int q = 0; q < k; ++q) s += st[oSOC + q * (m + 2) + nx + r];
+            if (k > 1) {
+                for (int q = 0; q < k; ++q) gu += st[oMSG + q * m + nx + r];
+            } else {
+                gu = o[nx + r];
+            }
+            const real lt = C.gu[r] * st[oEC + nx + r] + C.rh[r] * s;
+            const real u = st[oU + r] - alpha * lt;
             ub[r] = u;
-            w2[r] = u - g[nx + r];
+            w2[r] = u - gu;
         }
-        if (t == 0) P->flag[i] = 0;
-        if ((t >> 6) == (kWG / 64) - 1) s2_block_wave(P, i, zin, ein, zout, lam);
+        // S2 projection (Sec. 4.3) of node i's block (y^i, tau^[i], s^[i]) after
+        // the z - alpha L* eta shift, on the last wavefront.  Kernel of
+        // G = [E^T, -I, -I] with E = [gamma I; -I; 1^T] (AV@R, Sec. 3.3);
+        // G G^T = (gamma^2 + 3) I + 1 1^T, so with rho = G w the multiplier is
+        // lambda = (rho - (1^T rho / (c + n)) 1) / c, c = gamma^2 + 3
+        // (Sherman-Morrison), and w - G^T lambda is the projection.
+        if ((t >> 6) == (kWG / 64) - 1) {
+            const int lane = t & 63;
+            const real gam = P->gamma[i], cc = gam * gam + real(3);
+            const real es = st[oES];
+            const real yb3 = st[oZY + 2 * k] - alpha * (st[oEY + 2 * k] - es);
+            auto shifted = [&](int c, real& yb1, real& yb2, real& tb, real& sb) {
+                yb1 = st[oZY + c] - alpha * (st[oEY + c] - st[oP + c] * es);
+                yb2 = st[oZY + k + c] - alpha * st[oEY + k + c];
+                tb = st[oZT + c] - alpha * real(0.5) * (st[oSOC + c * (m + 2) + m] + st[oSOC + c * (m + 2) + m + 1]);
+                const real lts = leafkids ? real(0.5) * (st[oCS + c * (nx + 2) + nx] + st[oCS + c * (nx + 2) + nx + 1])
+                                          : st[oCS + c];
+                sb = st[oZS + c] - alpha * lts;
+            };
+            real rsum = 0;
+            for (int c = lane; c < k; c += 64) {
+                real yb1, yb2, tb, sb;
+                shifted(c, yb1, yb2, tb, sb);
+                const real rho = gam * yb1 - yb2 + yb3 - tb - sb;
+                lam[c] = rho;
+                rsum += rho;
+            }
+            rsum = wave_sum(rsum);
+            real lsum = 0;
+            for (int c = lane; c < k; c += 64) {
+                real yb1, yb2, tb, sb;
+                shifted(c, yb1, yb2, tb, sb);
+                const real l = (lam[c] - rsum / (cc + real(k))) / cc;
+                lsum += l;
+                zout[P->z_y + yo + c] = yb1 - gam * l;
+                zout[P->z_y + yo + k + c] = yb2 + l;
+                zout[P->z_tau + fc + c - 1] = tb + l;
+                zout[P->z_s + fc + c - 1] = sb + l;
+            }
+            lsum = wave_sum(lsum);
+            if (lane == 0) zout[P->z_y + yo + 2 * k] = yb3 - lsum;
+        }
         __syncthreads();
         // [K^T ubar ; R~^-1 (ubar - g_u)] in one pass over [K | R~^-1]
         if (tiles) t_apply<kWG>(TK, P->KR + i * P->KR_stride, nu, m, m, nx, ub, w2, o, red);
         else mat_t_vec<kWG>(P->KR + i * P->KR_stride, nu, m, m, nx, ub, w2, o, red);
         for (int r = t; r < nx; r += kWG) {
             real h = -xb[r] - o[r] + g[r];
-            if (P->affine && i > 0) h += P->Pc[(long long)i * nx + r];
+            if (P->affine && i > 0) h += st[oPC + r];
             xb[r] = h;
         }
         for (int r = t; r < nu; r += kWG) P->d[(long long)i * nu + r] = o[nx + r];
         if (i == 0) {
             if (t == 0) {
-                zout[0] = zin[0] - alpha * ein[P->e_s] - alpha;  // prox of alpha * s0
-                ticket[0] = 0;                                    // forward tickets restart
+                zout[0] = zin[0] - alpha * st[oES] - alpha;  // prox of alpha * s0
+                ticket[0] = 0;                              // forward tickets restart
                 if (check) {
                     P->res[0] = 0ull;
                     P->res[1] = 0ull;
@@ -501,12 +650,13 @@ SPK_DEV void soc_moreau_coef(real nw2, real vt, real& cw, real& ct) {
     }
 }
 
-// Node vectors a forward step works on (LDS).
+// What the dual-block updates of one node read (LDS) and where they write.
 template <typename real>
-struct FwdVecs {
+struct FwdNode {
+    Consts<real> C;
     const real* xn;  // x+ of the node
     const real* un;  // u+
-    const real* xo;  // x of the previous iterate
+    const real* xo;  // x of the previous iterate (staged)
     const real* uo;
     real* blk;       // this wavefront's staging: etabar
     real* dblk;      //                            L dz, then eta - eta+
@@ -514,10 +664,10 @@ struct FwdVecs {
     real* luw;       //                                    on u
 };
 
-// eta_c of non-leaf node v: C^i = box x ball (one wavefront).
+// eta_c of non-leaf node v: C^i = box x ball (one wavefront).  ec: staged eta_c.
 template <typename real>
-SPK_DEV void fwd_block_c(const ProbDev<real>* __restrict__ P, int v, const real* __restrict__ ein,
-                         real* __restrict__ eout, const FwdVecs<real>& V, int check, real& r2) {
+SPK_DEV void fwd_block_c(const ProbDev<real>* __restrict__ P, int v, const real* ec, real* __restrict__ eout,
+                         const FwdNode<real>& V, int check, real& r2) {
     const int lane = threadIdx.x & 63;
     const int nx = P->nx, nbox = P->nbox, nc = P->nc;
     const real alpha = P->alpha, ialpha = real(1) / alpha;
@@ -526,16 +676,16 @@ SPK_DEV void fwd_block_c(const ProbDev<real>* __restrict__ P, int v, const real*
     for (int r = lane; r < nc; r += 64) {
         real wn, wo;
         if (r < nx) {
-            wn = P->gx[r] * V.xn[r];
-            wo = P->gx[r] * V.xo[r];
+            wn = V.C.gx[r] * V.xn[r];
+            wo = V.C.gx[r] * V.xo[r];
         } else if (r < nbox) {
-            wn = P->gu[r - nx] * V.un[r - nx];
-            wo = P->gu[r - nx] * V.uo[r - nx];
+            wn = V.C.gu[r - nx] * V.un[r - nx];
+            wo = V.C.gu[r - nx] * V.uo[r - nx];
         } else {
-            wn = P->gb[r - nbox] * V.xn[r - nbox];
-            wo = P->gb[r - nbox] * V.xo[r - nbox];
+            wn = V.C.gb[r - nbox] * V.xn[r - nbox];
+            wo = V.C.gb[r - nbox] * V.xo[r - nbox];
         }
-        const real eb = ein[off + r] + alpha * (real(2) * wn - wo);
+        const real eb = ec[r] + alpha * (real(2) * wn - wo);
         V.blk[r] = eb;
         V.dblk[r] = wo - wn;
         if (r >= nbox) nb2 += eb * eb;
@@ -549,58 +699,53 @@ SPK_DEV void fwd_block_c(const ProbDev<real>* __restrict__ P, int v, const real*
     }
     for (int r = lane; r < nc; r += 64) {
         const real eb = V.blk[r];
-        const real ep = r < nbox ? moreau_box(eb, alpha, P->lo[r], P->hi[r]) : eb * cb;
+        const real ep = r < nbox ? moreau_box(eb, alpha, V.C.lo[r], V.C.hi[r]) : eb * cb;
         eout[off + r] = ep;
-        const real de = ein[off + r] - ep;
+        const real de = ec[r] - ep;
         if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
         V.dblk[r] = de;
     }
     if (check) {
         __builtin_amdgcn_wave_barrier();
         for (int r = lane; r < nx; r += 64) {
-            real s = P->gx[r] * V.dblk[r];
-            if (P->has_ball) s += P->gb[r] * V.dblk[nbox + r];
+            real s = V.C.gx[r] * V.dblk[r];
+            if (P->has_ball) s += V.C.gb[r] * V.dblk[nbox + r];
             V.lxw[r] += s;
         }
-        for (int r = lane; r < P->nu; r += 64) V.luw[r] += P->gu[r] * V.dblk[nx + r];
+        for (int r = lane; r < P->nu; r += 64) V.luw[r] += V.C.gu[r] * V.dblk[nx + r];
     }
 }
 
-// eta_y in (K^i)* = R^{2k}_+ x R and eta_s in R_+ (one wavefront).
+// eta_y in (K^i)* = R^{2k}_+ x R and eta_s in R_+ (one wavefront), from staged
+// eta_y (ey), eta_s (es), new and old y (yn, yv) and s (sn, sv), probabilities p.
 template <typename real>
-SPK_DEV void fwd_block_risk(const ProbDev<real>* __restrict__ P, int v, const real* __restrict__ zin,
-                            const real* __restrict__ zout, const real* __restrict__ ein,
+SPK_DEV void fwd_block_risk(const ProbDev<real>* __restrict__ P, int v, int k, const real* ey, real es,
+                            const real* yn, const real* yv, real sn, real sv, const real* p,
                             real* __restrict__ eout, int check, real& r1, real& r2) {
     const int lane = threadIdx.x & 63;
     const real alpha = P->alpha, ialpha = real(1) / alpha;
-    const int k = P->n_ch[v], fc = P->first_child[v];
     const long long yo = P->y_off[v];
-    const real* yn = zout + P->z_y + yo;
-    const real* yv = zin + P->z_y + yo;
-    const long long soff = (v == 0) ? 0 : P->z_s + v - 1;
-    const real sn = zout[soff], sv = zin[soff];
     real bn = 0, bo = 0;  // b^T y with b = (p, 0, 1)
     for (int c = lane; c < k; c += 64) {
-        const real p = P->prob[fc + c];
-        bn += p * yn[c];
-        bo += p * yv[c];
+        bn += p[c] * yn[c];
+        bo += p[c] * yv[c];
     }
     bn = wave_sum(bn) + yn[2 * k];
     bo = wave_sum(bo) + yv[2 * k];
     const real wsn = sn - bn, wso = sv - bo;
-    const real ebs = ein[P->e_s + v] + alpha * (real(2) * wsn - wso);
+    const real ebs = es + alpha * (real(2) * wsn - wso);
     const real eps_ = ebs < 0 ? ebs : real(0);
-    const real des = ein[P->e_s + v] - eps_;
+    const real des = es - eps_;
     if (lane == 0) eout[P->e_s + v] = eps_;
     for (int c = lane; c < 2 * k + 1; c += 64) {
-        const real eb = ein[P->e_y + yo + c] + alpha * (real(2) * yn[c] - yv[c]);
+        const real eb = ey[c] + alpha * (real(2) * yn[c] - yv[c]);
         const real ep = c < 2 * k ? (eb < 0 ? eb : real(0)) : real(0);
         eout[P->e_y + yo + c] = ep;
         if (check) {
-            const real de = ein[P->e_y + yo + c] - ep;
+            const real de = ey[c] - ep;
             const real dy = yv[c] - yn[c];
             r2 = fmax(r2, fabs(de * ialpha - dy));
-            const real bc = c < k ? P->prob[fc + c] : (c == 2 * k ? real(1) : real(0));
+            const real bc = c < k ? p[c] : (c == 2 * k ? real(1) : real(0));
             r1 = fmax(r1, fabs(dy * ialpha - (de - bc * des)));
         }
     }
@@ -611,30 +756,29 @@ SPK_DEV void fwd_block_risk(const ProbDev<real>* __restrict__ P, int v, const re
 }
 
 // SOC block of the edge into child j of non-leaf node v:
-// (Q^1/2 x^v, R^1/2 u^v, tau^j / 2, tau^j / 2) in SOC + a (one wavefront).
+// (Q^1/2 x^v, R^1/2 u^v, tau^j / 2, tau^j / 2) in SOC + a (one wavefront);
+// es: staged eta_soc of that edge, tn / tv: new / old tau^j.
 template <typename real>
-SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, const real* __restrict__ zin,
-                           const real* __restrict__ zout, const real* __restrict__ ein,
-                           real* __restrict__ eout, const FwdVecs<real>& V, int check, real& r1, real& r2) {
+SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, const real* es, real tn, real tv,
+                           real* __restrict__ eout, const FwdNode<real>& V, int check, real& r1, real& r2) {
     const int lane = threadIdx.x & 63;
     const int nx = P->nx, m = P->m;
     const real alpha = P->alpha, ialpha = real(1) / alpha;
     const long long off = P->e_soc + (long long)(j - 1) * (m + 2);
-    const real tn = zout[P->z_tau + j - 1], tv = zin[P->z_tau + j - 1];
     real nw2 = 0;
     for (int r = lane; r < m + 2; r += 64) {
         real wn, wo;
         if (r < nx) {
-            wn = P->qh[r] * V.xn[r];
-            wo = P->qh[r] * V.xo[r];
+            wn = V.C.qh[r] * V.xn[r];
+            wo = V.C.qh[r] * V.xo[r];
         } else if (r < m) {
-            wn = P->rh[r - nx] * V.un[r - nx];
-            wo = P->rh[r - nx] * V.uo[r - nx];
+            wn = V.C.rh[r - nx] * V.un[r - nx];
+            wo = V.C.rh[r - nx] * V.uo[r - nx];
         } else {
             wn = real(0.5) * tn;
             wo = real(0.5) * tv;
         }
-        real eb = ein[off + r] + alpha * (real(2) * wn - wo);
+        real eb = es[r] + alpha * (real(2) * wn - wo);
         if (r == m) eb -= real(0.5) * alpha;  // v = etabar - alpha a
         if (r == m + 1) eb += real(0.5) * alpha;
         V.blk[r] = eb;
@@ -648,23 +792,24 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, const rea
     for (int r = lane; r < m + 2; r += 64) {
         const real ep = r <= m ? V.blk[r] * cw : ct;
         eout[off + r] = ep;
-        const real de = ein[off + r] - ep;
+        const real de = es[r] - ep;
         if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
         V.dblk[r] = de;
     }
     if (check) {
         __builtin_amdgcn_wave_barrier();
-        for (int r = lane; r < nx; r += 64) V.lxw[r] += P->qh[r] * V.dblk[r];
-        for (int r = lane; r < P->nu; r += 64) V.luw[r] += P->rh[r] * V.dblk[nx + r];
+        for (int r = lane; r < nx; r += 64) V.lxw[r] += V.C.qh[r] * V.dblk[r];
+        for (int r = lane; r < P->nu; r += 64) V.luw[r] += V.C.rh[r] * V.dblk[nx + r];
         if (lane == 0) r1 = fmax(r1, fabs((tv - tn) * ialpha - real(0.5) * (V.dblk[m] + V.dblk[m + 1])));
     }
 }
 
-// eta_cN (box x ball) and eta_socN (Q_N^1/2 x, s/2, s/2) of leaf v (one wavefront each).
+// Leaf v: eta_cN (box x ball) for which = 0, eta_socN (Q_N^1/2 x, s/2, s/2) for
+// which = 1 (one wavefront each); ec / es: the staged blocks.
 template <typename real>
-SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int which, const real* __restrict__ zin,
-                            const real* __restrict__ zout, const real* __restrict__ ein,
-                            real* __restrict__ eout, const FwdVecs<real>& V, int check, real& r1, real& r2) {
+SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int which, const real* ec,
+                            const real* es, real sn, real sv, real* __restrict__ eout, const FwdNode<real>& V,
+                            int check, real& r1, real& r2) {
     const int lane = threadIdx.x & 63;
     const int nx = P->nx;
     const real alpha = P->alpha, ialpha = real(1) / alpha;
@@ -675,13 +820,13 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
         for (int r = lane; r < P->ncN; r += 64) {
             real wn, wo;
             if (r < nx) {
-                wn = P->gxN[r] * V.xn[r];
-                wo = P->gxN[r] * V.xo[r];
+                wn = V.C.gxN[r] * V.xn[r];
+                wo = V.C.gxN[r] * V.xo[r];
             } else {
-                wn = P->gbN[r - nx] * V.xn[r - nx];
-                wo = P->gbN[r - nx] * V.xo[r - nx];
+                wn = V.C.gbN[r - nx] * V.xn[r - nx];
+                wo = V.C.gbN[r - nx] * V.xo[r - nx];
             }
-            const real eb = ein[off + r] + alpha * (real(2) * wn - wo);
+            const real eb = ec[r] + alpha * (real(2) * wn - wo);
             V.blk[r] = eb;
             V.dblk[r] = wo - wn;
             if (r >= nx) nb2 += eb * eb;
@@ -695,34 +840,33 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
         }
         for (int r = lane; r < P->ncN; r += 64) {
             const real eb = V.blk[r];
-            const real ep = r < nx ? moreau_box(eb, alpha, P->loN[r], P->hiN[r]) : eb * cb;
+            const real ep = r < nx ? moreau_box(eb, alpha, V.C.loN[r], V.C.hiN[r]) : eb * cb;
             eout[off + r] = ep;
-            const real de = ein[off + r] - ep;
+            const real de = ec[r] - ep;
             if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
             V.dblk[r] = de;
         }
         if (check) {
             __builtin_amdgcn_wave_barrier();
             for (int r = lane; r < nx; r += 64) {
-                real s = P->gxN[r] * V.dblk[r];
-                if (P->has_ballN) s += P->gbN[r] * V.dblk[nx + r];
+                real s = V.C.gxN[r] * V.dblk[r];
+                if (P->has_ballN) s += V.C.gbN[r] * V.dblk[nx + r];
                 V.lxw[r] += s;
             }
         }
     } else {
         const long long off = P->e_socN + lf * (nx + 2);
-        const real sn = zout[P->z_s + v - 1], sv = zin[P->z_s + v - 1];
         real nw2 = 0;
         for (int r = lane; r < nx + 2; r += 64) {
             real wn, wo;
             if (r < nx) {
-                wn = P->qnh[r] * V.xn[r];
-                wo = P->qnh[r] * V.xo[r];
+                wn = V.C.qnh[r] * V.xn[r];
+                wo = V.C.qnh[r] * V.xo[r];
             } else {
                 wn = real(0.5) * sn;
                 wo = real(0.5) * sv;
             }
-            real eb = ein[off + r] + alpha * (real(2) * wn - wo);
+            real eb = es[r] + alpha * (real(2) * wn - wo);
             if (r == nx) eb -= real(0.5) * alpha;
             if (r == nx + 1) eb += real(0.5) * alpha;
             V.blk[r] = eb;
@@ -736,13 +880,13 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
         for (int r = lane; r < nx + 2; r += 64) {
             const real ep = r <= nx ? V.blk[r] * cw : ct;
             eout[off + r] = ep;
-            const real de = ein[off + r] - ep;
+            const real de = es[r] - ep;
             if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
             V.dblk[r] = de;
         }
         if (check) {
             __builtin_amdgcn_wave_barrier();
-            for (int r = lane; r < nx; r += 64) V.lxw[r] += P->qnh[r] * V.dblk[r];
+            for (int r = lane; r < nx; r += 64) V.lxw[r] += V.C.qnh[r] * V.dblk[r];
             if (lane == 0) r1 = fmax(r1, fabs((sv - sn) * ialpha - real(0.5) * (V.dblk[nx] + V.dblk[nx + 1])));
         }
     }
@@ -753,7 +897,8 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
                                                  const int2* __restrict__ tasks, int* __restrict__ ticket,
                                                  int par, int check) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int s_path[kMaxDepth];
+    __shared__ int s_node[kMaxDepth], s_nch[kMaxDepth], s_fc[kMaxDepth];
+    __shared__ SegTable<real> s_seg;
     __shared__ int s_task, s_ok;
     real* sm = reinterpret_cast<real*>(smem_raw);
     const int t = threadIdx.x, w = t >> 6;
@@ -764,39 +909,38 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
     const int2 tk = tasks[s_task];
     const ProbDev<real>* __restrict__ P = probs + tk.x;
     if (*P->active == 0) return;
-    const int nx = P->nx, nu = P->nu, m = P->m, N = P->N;
+    const int nx = P->nx, nu = P->nu, m = P->m, N = P->N, nc = P->nc, ncN = P->ncN;
+    const int n_nl = P->n_nl;
     const real ialpha = real(1) / P->alpha;
     const real* __restrict__ zin = P->z[par];
     const real* __restrict__ ein = P->eta[par];
     real* __restrict__ zout = P->z[par ^ 1];
     real* __restrict__ eout = P->eta[par ^ 1];
     const int bmax = blk_elems(nx, nu, P->max_ch);
+    constexpr int kWaves = kWG / 64;
 
     real* red = sm;
-    real* xa = red + kWG;  // [x^anc ; d^anc]
+    real* cst = red + kWG;
+    real* st = cst + consts_elems(nx, nu);
+    real* xa = st + stage_elems(nx, nu, nc, P->max_ch);  // [x^anc ; d^anc]
     real* xn = xa + m;
     real* un = xn + nx;
-    real* dv = un + nu;
-    real* xo = dv + nu;
-    real* uo = xo + nx;
-    constexpr int kWaves = kWG / 64;
-    real* lxw = uo + nu;             // kWaves x nx
+    real* lxw = un + nu;             // kWaves x nx
     real* luw = lxw + kWaves * nx;   // kWaves x nu
     real* blk = luw + kWaves * nu;   // kWaves x bmax
     real* dblk = blk + kWaves * bmax;
-    const FwdVecs<real> V{xn, un, xo, uo, blk + w * bmax, dblk + w * bmax, lxw + w * nx, luw + w * nu};
 
     // this task computes the path nodes from stage L down to its leaf; the
     // node above them belongs to the task of its leftmost leaf
     const int L = P->top_owned[tk.y];
-    {
-        const int* path = P->path + (long long)tk.y * (N + 1);
-        for (int q = (L > 0 ? L - 1 : 0) + t; q <= N; q += kWG) s_path[q] = path[q];
-    }
+    load_path<kWG>(P, tk.y, L > 0 ? L - 1 : 0, s_node, s_nch, s_fc);
+    if (t == 0) consts_table(P, s_seg);
     __syncthreads();
+    seg_gather<kWG>(s_seg, cst);
+    const Consts<real> C = consts_at<real>(cst, nx, nu);
     if (t == 0) {
         int ok = 1;
-        if (L > 0 && !wait_done(&P->flag[s_path[L - 1]])) {
+        if (L > 0 && !wait_done(&P->flag[s_node[L - 1]])) {
             atomicExch(P->err, 1);
             ok = 0;
         }
@@ -805,20 +949,63 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
     __syncthreads();
     if (!s_ok) return;
     if (L > 0) {
-        const int pn = s_path[L - 1];
+        const int pn = s_node[L - 1];
         for (int r = t; r < nx; r += kWG) xa[r] = zout[P->z_x + (long long)pn * nx + r];
         for (int r = t; r < nu; r += kWG) xa[nx + r] = P->d[(long long)pn * nu + r];
     }
-    __syncthreads();
 
     real r1 = 0, r2 = 0;  // residual maxima of this thread
     for (int lev = L; lev <= N; ++lev) {
-        const int v = s_path[lev];
-        const bool nonleaf = v < P->n_nl;
+        const int v = s_node[lev];
+        const int k = s_nch[lev], fc = s_fc[lev];
+        const bool nonleaf = v < n_nl;
         PTile<real, kRBP, 2> TM;
         PTile<real, kRBQ, 1> TK;
         if (v > 0) p_load<kWG>(TM, P->M + v * P->M_stride, nx, m, m);
         if (nonleaf) p_load<kWG>(TK, P->KR + v * P->KR_stride, nu, nx, m);
+        // staged inputs of node v (offsets into st)
+        const long long yo = nonleaf ? P->y_off[v] : 0;
+        const long long soff = (v == 0) ? 0 : P->z_s + v - 1;
+        int oD = 0, oXO = 0, oUO = 0, oEC = 0, oSOC = 0, oEY = 0, oES = 0, oYN = 0, oYO = 0, oSN = 0, oSO = 0;
+        int oTN = 0, oTO = 0, oP = 0, oC = 0, oECN = 0, oSOCN = 0;
+        if (nonleaf) {
+            oD = 0; oXO = oD + nu; oUO = oXO + nx; oEC = oUO + nu; oSOC = oEC + nc; oEY = oSOC + k * (m + 2);
+            oES = oEY + 2 * k + 1; oYN = oES + 1; oYO = oYN + 2 * k + 1; oSN = oYO + 2 * k + 1; oSO = oSN + 1;
+            oTN = oSO + 1; oTO = oTN + k; oP = oTO + k; oC = oP + k;
+        } else {
+            oXO = 0; oECN = oXO + nx; oSOCN = oECN + ncN; oSN = oSOCN + nx + 2; oSO = oSN + 1; oC = oSO + 1;
+        }
+        __syncthreads();  // previous stage data consumed, table free
+        if (t == 0) {
+            seg_reset(s_seg);
+            if (nonleaf) {
+                seg_add(s_seg, P->d + (long long)v * nu, nu);
+                seg_add(s_seg, zin + P->z_x + (long long)v * nx, nx);
+                seg_add(s_seg, zin + P->z_u + (long long)v * nu, nu);
+                seg_add(s_seg, ein + P->e_c + (long long)v * nc, nc);
+                seg_add(s_seg, ein + P->e_soc + (long long)(fc - 1) * (m + 2), k * (m + 2));
+                seg_add(s_seg, ein + P->e_y + yo, 2 * k + 1);
+                seg_add(s_seg, ein + P->e_s + v, 1);
+                seg_add(s_seg, zout + P->z_y + yo, 2 * k + 1);
+                seg_add(s_seg, zin + P->z_y + yo, 2 * k + 1);
+                seg_add(s_seg, zout + soff, 1);
+                seg_add(s_seg, zin + soff, 1);
+                seg_add(s_seg, zout + P->z_tau + fc - 1, k);
+                seg_add(s_seg, zin + P->z_tau + fc - 1, k);
+                seg_add(s_seg, P->prob + fc, k);
+            } else {
+                seg_add(s_seg, zin + P->z_x + (long long)v * nx, nx);
+                seg_add(s_seg, ein + P->e_cN + (long long)(v - n_nl) * ncN, ncN);
+                seg_add(s_seg, ein + P->e_socN + (long long)(v - n_nl) * (nx + 2), nx + 2);
+                seg_add(s_seg, zout + soff, 1);
+                seg_add(s_seg, zin + soff, 1);
+            }
+            if (P->affine && v > 0) seg_add(s_seg, P->c + (long long)v * nx, nx);
+        }
+        __syncthreads();
+        seg_gather<kWG>(s_seg, st);
+        __syncthreads();
+
         // ---- state: x^v = [Abar|B] [x^anc; d^anc] + c ----
         if (v == 0) {
             for (int r = t; r < nx; r += kWG) xn[r] = P->x0[r];
@@ -826,68 +1013,70 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
         } else {
             p_apply<kWG>(TM, P->M + v * P->M_stride, nx, m, m, xa, xn);
             if (P->affine) {
-                for (int r = t; r < nx; r += kWG) xn[r] += P->c[(long long)v * nx + r];
+                for (int r = t; r < nx; r += kWG) xn[r] += st[oC + r];
                 __syncthreads();
             }
         }
-        for (int r = t; r < nx; r += kWG) {
-            zout[P->z_x + (long long)v * nx + r] = xn[r];
-            xo[r] = zin[P->z_x + (long long)v * nx + r];
+        for (int r = t; r < nx; r += kWG) zout[P->z_x + (long long)v * nx + r] = xn[r];
+        if (nonleaf && k > 1) {
+            // children owned by other tasks read x^v (and d^v): publish now
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (t == 0) __hip_atomic_store(&P->flag[v], 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (nonleaf) {
-            for (int r = t; r < nu; r += kWG) dv[r] = P->d[(long long)v * nu + r];
-            if (P->n_ch[v] > 1) {
-                // children owned by other tasks read x^v (and d^v): publish now
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __syncthreads();
-                if (t == 0) __hip_atomic_store(&P->flag[v], 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            __syncthreads();
             // ---- input: u^v = K^v x^v + d^v ----
             p_apply<kWG>(TK, P->KR + v * P->KR_stride, nu, nx, m, xn, un);
             for (int r = t; r < nu; r += kWG) {
-                const real u = un[r] + dv[r];
+                const real u = un[r] + st[oD + r];
                 un[r] = u;
                 zout[P->z_u + (long long)v * nu + r] = u;
-                uo[r] = zin[P->z_u + (long long)v * nu + r];
             }
         }
         if (check) {
-            for (int r = t & 63; r < nx; r += 64) V.lxw[r] = 0;
-            for (int r = t & 63; r < nu; r += 64) V.luw[r] = 0;
+            for (int r = t & 63; r < nx; r += 64) lxw[w * nx + r] = 0;
+            for (int r = t & 63; r < nu; r += 64) luw[w * nu + r] = 0;
         }
         __syncthreads();
         // ---- dual blocks, one wavefront each ----
+        const FwdNode<real> V{C, xn, un, st + oXO, st + oUO, blk + w * bmax, dblk + w * bmax,
+                              lxw + w * nx, luw + w * nu};
         if (nonleaf) {
-            const int k = P->n_ch[v], fc = P->first_child[v];
-            for (int b = w; b < k + 2; b += kWG / 64) {
-                if (b == 0) fwd_block_c(P, v, ein, eout, V, check, r2);
-                else if (b == 1) fwd_block_risk(P, v, zin, zout, ein, eout, check, r1, r2);
-                else fwd_block_soc(P, fc + b - 2, zin, zout, ein, eout, V, check, r1, r2);
+            for (int b = w; b < k + 2; b += kWaves) {
+                if (b == 0) {
+                    fwd_block_c(P, v, st + oEC, eout, V, check, r2);
+                } else if (b == 1) {
+                    fwd_block_risk(P, v, k, st + oEY, st[oES], st + oYN, st + oYO, st[oSN], st[oSO], st + oP,
+                                   eout, check, r1, r2);
+                } else {
+                    const int q = b - 2;
+                    fwd_block_soc(P, fc + q, st + oSOC + q * (m + 2), st[oTN + q], st[oTO + q], eout, V, check,
+                                  r1, r2);
+                }
             }
         } else {
-            for (int b = w; b < 2; b += kWG / 64) fwd_block_leaf(P, v, b, zin, zout, ein, eout, V, check, r1, r2);
+            for (int b = w; b < 2; b += kWaves)
+                fwd_block_leaf(P, v, b, st + oECN, st + oSOCN, st[oSN], st[oSO], eout, V, check, r1, r2);
         }
         if (check) {
             __syncthreads();
             for (int r = t; r < nx; r += kWG) {
                 real s = 0;
-                for (int q = 0; q < kWG / 64; ++q) s += lxw[q * nx + r];
-                r1 = fmax(r1, fabs((xo[r] - xn[r]) * ialpha - s));
+                for (int q = 0; q < kWaves; ++q) s += lxw[q * nx + r];
+                r1 = fmax(r1, fabs((st[oXO + r] - xn[r]) * ialpha - s));
             }
             if (nonleaf)
                 for (int r = t; r < nu; r += kWG) {
                     real s = 0;
-                    for (int q = 0; q < kWG / 64; ++q) s += luw[q * nu + r];
-                    r1 = fmax(r1, fabs((uo[r] - un[r]) * ialpha - s));
+                    for (int q = 0; q < kWaves; ++q) s += luw[q * nu + r];
+                    r1 = fmax(r1, fabs((st[oUO + r] - un[r]) * ialpha - s));
                 }
         }
         // ---- next stage input [x^v ; d^v] ----
         if (lev < N) {
             __syncthreads();
             for (int r = t; r < nx; r += kWG) xa[r] = xn[r];
-            for (int r = t; r < nu; r += kWG) xa[nx + r] = dv[r];
-            __syncthreads();
+            for (int r = t; r < nu; r += kWG) xa[nx + r] = st[oD + r];
         }
     }
     if (check) {
