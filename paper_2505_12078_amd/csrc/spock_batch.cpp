@@ -110,10 +110,11 @@ int32_t batch_tick(spock_batch* b, std::vector<Member>& m, bool stall_exit) {
                 x.status = SPOCK_E_NOT_CONVERGED;
                 x.live = false;
             } else if (stall_exit) {
+                ++x.checks;
                 if (x.rel < 0.99 * x.best) {
                     x.best = x.rel;
                     x.no_gain = 0;
-                } else if (++x.no_gain >= 25) {
+                } else if (++x.no_gain >= std::max(50, x.checks / 2)) {
                     x.status = SPOCK_E_NOT_CONVERGED;
                     x.live = false;
                 }

@@ -154,7 +154,7 @@ struct Member {
     long long iters = 0, iters32 = 0;
     double rel = INFINITY, x1 = INFINITY, x2 = INFINITY;
     double best = INFINITY;
-    int no_gain = 0;
+    int no_gain = 0, checks = 0;
     int32_t status = SPOCK_E_NOT_CONVERGED;
     int refined = 0;
 };

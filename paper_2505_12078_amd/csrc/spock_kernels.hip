@@ -307,7 +307,11 @@ SPK_DEV void seg_add(SegTable<real>& T, const real* src, int len) {
 
 template <int kWG, typename real>
 SPK_DEV void seg_gather(const SegTable<real>& T, real* st) {
-    const int total = T.off[T.n];
+    const int nseg = T.n;
+    const int total = T.off[nseg];
+    int off[kMaxSeg + 1];  // segment ends in registers: no dependent LDS reads per element
+#pragma unroll
+    for (int q = 0; q <= kMaxSeg; ++q) off[q] = q <= nseg ? T.off[q] : total;
     for (int base = 0; base < total; base += kGatherE * kWG) {
         real v[kGatherE];
 #pragma unroll
@@ -316,7 +320,8 @@ SPK_DEV void seg_gather(const SegTable<real>& T, real* st) {
             v[j] = 0;
             if (e < total) {
                 int s = 0;
-                while (e >= T.off[s + 1]) ++s;
+#pragma unroll
+                for (int q = 1; q <= kMaxSeg; ++q) s += e >= off[q];
                 v[j] = T.src[s][e - T.off[s]];
             }
         }
