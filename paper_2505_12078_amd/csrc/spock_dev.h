@@ -76,19 +76,23 @@ struct ProbDev {
     unsigned long long* res; // |xi1|_inf, |xi2|_inf as float64 bit patterns
 };
 
+// Children whose per-child inputs are staged in LDS; a wider node reads them
+// from global memory directly (same contiguous layout).
+constexpr int kStageKids = 16;
+
 // Elements of one wavefront's staging array for a dual block in the forward sweep.
-__host__ __device__ inline int blk_elems(int nx, int nu, int max_ch) {
+__host__ __device__ inline int blk_elems(int nx, int nu, int /*max_ch*/) {
     const int m = nx + nu;
     int b = 2 * nx + nu;
     if (m + 2 > b) b = m + 2;
-    if (2 * max_ch + 1 > b) b = 2 * max_ch + 1;
     return b;
 }
 
 // Elements of the LDS area that stages one node's vector inputs.
 __host__ __device__ inline int stage_elems(int nx, int nu, int nc, int max_ch) {
     const int m = nx + nu;
-    return 3 * nx + 2 * nu + nc + max_ch * (2 * m + nx + 12) + 16;
+    const int kc = max_ch < kStageKids ? max_ch : kStageKids;
+    return 3 * nx + 2 * nu + nc + kc * (2 * m + nx + 12) + 16;
 }
 
 // Number of `real` elements of dynamic LDS a sweep workgroup of `wg` threads

@@ -494,38 +494,55 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
             if (i > 0) t_load<kWG>(TM, P->M + i * P->M_stride, nx, m, m);
         }
         const bool leafkids = fc >= n_nl;
-        const int cs_len = leafkids ? k * (nx + 2) : k;
+        const bool sk = k <= kStageKids;  // per-child inputs staged, else read in place
+        const int kk = sk ? k : 0;
+        const int cs_len = leafkids ? kk * (nx + 2) : kk;
         const long long yo = P->y_off[i];
         // staged inputs of node i (offsets into st)
-        const int oX = 0, oU = oX + nx, oEC = oU + nu, oSOC = oEC + nc, oEY = oSOC + k * (m + 2);
-        const int oES = oEY + 2 * k + 1, oZY = oES + 1, oZT = oZY + 2 * k + 1, oZS = oZT + k, oCS = oZS + k;
-        const int oP = oCS + cs_len, oMSG = oP + k, oPC = oMSG + (k > 1 ? k * m : 0);
+        const int oX = 0, oU = oX + nx, oEC = oU + nu, oSOC = oEC + nc, oEY = oSOC + kk * (m + 2);
+        const int oES = oEY + (sk ? 2 * k + 1 : 0), oZY = oES + 1, oZT = oZY + (sk ? 2 * k + 1 : 0);
+        const int oZS = oZT + kk, oCS = oZS + kk, oP = oCS + cs_len, oMSG = oP + kk;
+        const int oPC = oMSG + (k > 1 ? kk * m : 0);
+        const real* g_soc = ein + P->e_soc + (long long)(fc - 1) * (m + 2);
+        const real* g_cs = leafkids ? ein + P->e_socN + (long long)(fc - n_nl) * (nx + 2) : ein + P->e_s + fc;
         if (t == 0) {
             seg_reset(s_seg);
             seg_add(s_seg, zin + P->z_x + (long long)i * nx, nx);
             seg_add(s_seg, zin + P->z_u + (long long)i * nu, nu);
             seg_add(s_seg, ein + P->e_c + (long long)i * nc, nc);
-            seg_add(s_seg, ein + P->e_soc + (long long)(fc - 1) * (m + 2), k * (m + 2));
-            seg_add(s_seg, ein + P->e_y + yo, 2 * k + 1);
+            if (sk) {
+                seg_add(s_seg, g_soc, k * (m + 2));
+                seg_add(s_seg, ein + P->e_y + yo, 2 * k + 1);
+            }
             seg_add(s_seg, ein + P->e_s + i, 1);
-            seg_add(s_seg, zin + P->z_y + yo, 2 * k + 1);
-            seg_add(s_seg, zin + P->z_tau + fc - 1, k);
-            seg_add(s_seg, zin + P->z_s + fc - 1, k);
-            if (leafkids) seg_add(s_seg, ein + P->e_socN + (long long)(fc - n_nl) * (nx + 2), cs_len);
-            else seg_add(s_seg, ein + P->e_s + fc, k);
-            seg_add(s_seg, P->prob + fc, k);
-            if (k > 1) seg_add(s_seg, P->e + (long long)fc * m, k * m);
+            if (sk) {
+                seg_add(s_seg, zin + P->z_y + yo, 2 * k + 1);
+                seg_add(s_seg, zin + P->z_tau + fc - 1, k);
+                seg_add(s_seg, zin + P->z_s + fc - 1, k);
+                seg_add(s_seg, g_cs, cs_len);
+                seg_add(s_seg, P->prob + fc, k);
+                if (k > 1) seg_add(s_seg, P->e + (long long)fc * m, k * m);
+            }
             if (P->affine && i > 0) seg_add(s_seg, P->Pc + (long long)i * nx, nx);
             P->flag[i] = 0;
         }
         __syncthreads();
         seg_gather<kWG>(s_seg, st);
         __syncthreads();
+        // per-child inputs: staged copies or the arrays themselves
+        const real* soc = sk ? st + oSOC : g_soc;
+        const real* ey = sk ? st + oEY : ein + P->e_y + yo;
+        const real* zy = sk ? st + oZY : zin + P->z_y + yo;
+        const real* zt = sk ? st + oZT : zin + P->z_tau + fc - 1;
+        const real* zs = sk ? st + oZS : zin + P->z_s + fc - 1;
+        const real* cs = sk ? st + oCS : g_cs;
+        const real* pr = sk ? st + oP : P->prob + fc;
+        const real* msg = sk ? st + oMSG : P->e + (long long)fc * m;
 
         for (int c = t; c < m; c += kWG) {
             if (k > 1) {
                 real s = 0;
-                for (int q = 0; q < k; ++q) s += st[oMSG + q * m + c];
+                for (int q = 0; q < k; ++q) s += msg[q * m + c];
                 g[c] = s;
             } else {
                 g[c] = o[c];
@@ -535,16 +552,16 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
         // every child edge (Sec. 4.4)
         for (int r = t; r < nx; r += kWG) {
             real s = 0;
-            for (int q = 0; q < k; ++q) s += st[oSOC + q * (m + 2) + r];
+            for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + r];
             real lt = C.gx[r] * st[oEC + r] + C.qh[r] * s;
             if (P->has_ball) lt += C.gb[r] * st[oEC + nbox + r];
             xb[r] = st[oX + r] - alpha * lt;
         }
         for (int r = t; r < nu; r += kWG) {
             real s = 0, gu = 0;
-            for (int q = 0; q < k; ++q) s += st[oSOC + q * (m + 2) + nx + r];
+            for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + nx + r];
             if (k > 1) {
-                for (int q = 0; q < k; ++q) gu += st[oMSG + q * m + nx + r];
+                for (int q = 0; q < k; ++q) gu += msg[q * m + nx + r];
             } else {
                 gu = o[nx + r];
             }
@@ -563,14 +580,13 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
             const int lane = t & 63;
             const real gam = P->gamma[i], cc = gam * gam + real(3);
             const real es = st[oES];
-            const real yb3 = st[oZY + 2 * k] - alpha * (st[oEY + 2 * k] - es);
+            const real yb3 = zy[2 * k] - alpha * (ey[2 * k] - es);
             auto shifted = [&](int c, real& yb1, real& yb2, real& tb, real& sb) {
-                yb1 = st[oZY + c] - alpha * (st[oEY + c] - st[oP + c] * es);
-                yb2 = st[oZY + k + c] - alpha * st[oEY + k + c];
-                tb = st[oZT + c] - alpha * real(0.5) * (st[oSOC + c * (m + 2) + m] + st[oSOC + c * (m + 2) + m + 1]);
-                const real lts = leafkids ? real(0.5) * (st[oCS + c * (nx + 2) + nx] + st[oCS + c * (nx + 2) + nx + 1])
-                                          : st[oCS + c];
-                sb = st[oZS + c] - alpha * lts;
+                yb1 = zy[c] - alpha * (ey[c] - pr[c] * es);
+                yb2 = zy[k + c] - alpha * ey[k + c];
+                tb = zt[c] - alpha * real(0.5) * (soc[c * (m + 2) + m] + soc[c * (m + 2) + m + 1]);
+                const real lts = leafkids ? real(0.5) * (cs[c * (nx + 2) + nx] + cs[c * (nx + 2) + nx + 1]) : cs[c];
+                sb = zs[c] - alpha * lts;
             };
             real rsum = 0;
             for (int c = lane; c < k; c += 64) {
@@ -971,12 +987,14 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
         // staged inputs of node v (offsets into st)
         const long long yo = nonleaf ? P->y_off[v] : 0;
         const long long soff = (v == 0) ? 0 : P->z_s + v - 1;
+        const bool sk = k <= kStageKids;  // per-child inputs staged, else read in place
+        const int kk = sk ? k : 0, ky = sk ? 2 * k + 1 : 0;
         int oD = 0, oXO = 0, oUO = 0, oEC = 0, oSOC = 0, oEY = 0, oES = 0, oYN = 0, oYO = 0, oSN = 0, oSO = 0;
         int oTN = 0, oTO = 0, oP = 0, oC = 0, oECN = 0, oSOCN = 0;
         if (nonleaf) {
-            oD = 0; oXO = oD + nu; oUO = oXO + nx; oEC = oUO + nu; oSOC = oEC + nc; oEY = oSOC + k * (m + 2);
-            oES = oEY + 2 * k + 1; oYN = oES + 1; oYO = oYN + 2 * k + 1; oSN = oYO + 2 * k + 1; oSO = oSN + 1;
-            oTN = oSO + 1; oTO = oTN + k; oP = oTO + k; oC = oP + k;
+            oD = 0; oXO = oD + nu; oUO = oXO + nx; oEC = oUO + nu; oSOC = oEC + nc; oEY = oSOC + kk * (m + 2);
+            oES = oEY + ky; oYN = oES + 1; oYO = oYN + ky; oSN = oYO + ky; oSO = oSN + 1;
+            oTN = oSO + 1; oTO = oTN + kk; oP = oTO + kk; oC = oP + kk;
         } else {
             oXO = 0; oECN = oXO + nx; oSOCN = oECN + ncN; oSN = oSOCN + nx + 2; oSO = oSN + 1; oC = oSO + 1;
         }
@@ -988,16 +1006,22 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
                 seg_add(s_seg, zin + P->z_x + (long long)v * nx, nx);
                 seg_add(s_seg, zin + P->z_u + (long long)v * nu, nu);
                 seg_add(s_seg, ein + P->e_c + (long long)v * nc, nc);
-                seg_add(s_seg, ein + P->e_soc + (long long)(fc - 1) * (m + 2), k * (m + 2));
-                seg_add(s_seg, ein + P->e_y + yo, 2 * k + 1);
+                if (sk) {
+                    seg_add(s_seg, ein + P->e_soc + (long long)(fc - 1) * (m + 2), k * (m + 2));
+                    seg_add(s_seg, ein + P->e_y + yo, 2 * k + 1);
+                }
                 seg_add(s_seg, ein + P->e_s + v, 1);
-                seg_add(s_seg, zout + P->z_y + yo, 2 * k + 1);
-                seg_add(s_seg, zin + P->z_y + yo, 2 * k + 1);
+                if (sk) {
+                    seg_add(s_seg, zout + P->z_y + yo, 2 * k + 1);
+                    seg_add(s_seg, zin + P->z_y + yo, 2 * k + 1);
+                }
                 seg_add(s_seg, zout + soff, 1);
                 seg_add(s_seg, zin + soff, 1);
-                seg_add(s_seg, zout + P->z_tau + fc - 1, k);
-                seg_add(s_seg, zin + P->z_tau + fc - 1, k);
-                seg_add(s_seg, P->prob + fc, k);
+                if (sk) {
+                    seg_add(s_seg, zout + P->z_tau + fc - 1, k);
+                    seg_add(s_seg, zin + P->z_tau + fc - 1, k);
+                    seg_add(s_seg, P->prob + fc, k);
+                }
             } else {
                 seg_add(s_seg, zin + P->z_x + (long long)v * nx, nx);
                 seg_add(s_seg, ein + P->e_cN + (long long)(v - n_nl) * ncN, ncN);
@@ -1047,16 +1071,22 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
         const FwdNode<real> V{C, xn, un, st + oXO, st + oUO, blk + w * bmax, dblk + w * bmax,
                               lxw + w * nx, luw + w * nu};
         if (nonleaf) {
+            // per-child inputs: staged copies or the arrays themselves
+            const real* soc = sk ? st + oSOC : ein + P->e_soc + (long long)(fc - 1) * (m + 2);
+            const real* ey = sk ? st + oEY : ein + P->e_y + yo;
+            const real* yn = sk ? st + oYN : zout + P->z_y + yo;
+            const real* yv = sk ? st + oYO : zin + P->z_y + yo;
+            const real* tn = sk ? st + oTN : zout + P->z_tau + fc - 1;
+            const real* tv = sk ? st + oTO : zin + P->z_tau + fc - 1;
+            const real* pr = sk ? st + oP : P->prob + fc;
             for (int b = w; b < k + 2; b += kWaves) {
                 if (b == 0) {
                     fwd_block_c(P, v, st + oEC, eout, V, check, r2);
                 } else if (b == 1) {
-                    fwd_block_risk(P, v, k, st + oEY, st[oES], st + oYN, st + oYO, st[oSN], st[oSO], st + oP,
-                                   eout, check, r1, r2);
+                    fwd_block_risk(P, v, k, ey, st[oES], yn, yv, st[oSN], st[oSO], pr, eout, check, r1, r2);
                 } else {
                     const int q = b - 2;
-                    fwd_block_soc(P, fc + q, st + oSOC + q * (m + 2), st[oTN + q], st[oTO + q], eout, V, check,
-                                  r1, r2);
+                    fwd_block_soc(P, fc + q, soc + q * (m + 2), tn[q], tv[q], eout, V, check, r1, r2);
                 }
             }
         } else {

@@ -50,6 +50,10 @@ def _cases():
     par, _ = W.tree_from_branching([7, 2])
     cases["wide"] = W.make_problem(par, 9, 4, np.random.default_rng(13), prob_kind="dirichlet",
                                    gamma=0.6, x_ball=8.0, name="wide")
+    # wider than the staged-children limit: per-child inputs read in place
+    par, _ = W.tree_from_branching([24, 2])
+    cases["very_wide"] = W.make_problem(par, 4, 2, np.random.default_rng(15), prob_kind="dirichlet",
+                                        gamma=0.7, x_ball=7.0, name="very_wide")
     par, _ = W.tree_from_branching([2, 1, 1])
     cases["big_nx"] = W.make_problem(par, 70, 40, np.random.default_rng(14), prob_kind="dirichlet",
                                      x_ball=12.0, name="big_nx")
