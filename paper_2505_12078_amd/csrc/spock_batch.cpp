@@ -52,6 +52,7 @@ int32_t batch_chunk(spock_batch* b, int steps) {
         b->graph[gi] = nullptr;
     }
     if (!b->graph[gi]) {
+        std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
         hipGraph_t g;
         HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         int32_t r = batch_steps<real>(b, steps, true);
@@ -178,6 +179,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
     const size_t ot = take(sizeof(int2) * b->n_tasks), oa = take(sizeof(int) * n), otk = take(sizeof(int) * 4);
     const size_t oe = take(sizeof(int) * n), orr = take(sizeof(unsigned long long) * 2 * n);
     b->bytes = off + 256;
+    std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
     hipError_t e = hipMalloc(&b->base, b->bytes);
     if (e != hipSuccess) {
         delete b;
@@ -226,6 +228,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
 
 int32_t spock_batch_destroy(spock_batch* b) {
     if (!b) return SPOCK_OK;
+    std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     for (auto& g : b->graph)
         if (g) (void)hipGraphExecDestroy(g);

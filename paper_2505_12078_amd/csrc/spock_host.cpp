@@ -24,6 +24,11 @@ using spk::ProbDev;
 
 thread_local std::string g_err;
 
+std::recursive_mutex& hip_setup_mutex() {
+    static std::recursive_mutex mu;
+    return mu;
+}
+
 int32_t fail(int32_t code, const std::string& msg) {
     g_err = msg;
     return code;
@@ -616,6 +621,7 @@ static int32_t chunk(spock_problem* p, int steps) {
         }
         hipGraphExec_t& ge = s.graph[s.par];
         if (!ge) {
+            std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
             hipGraph_t graph;
             HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
             int par = s.par;
@@ -829,6 +835,7 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
         Arena dry(nullptr);
         carve(dry, p);
         p->bytes = dry.off + 256;
+        std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
         if (ws) {
             if (ws_bytes < p->bytes) {
                 delete p;
@@ -908,6 +915,7 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
 
 int32_t spock_problem_destroy(spock_problem* p) {
     if (!p) return SPOCK_OK;
+    std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     for (auto* s : {&p->s64.graph[0], &p->s64.graph[1], &p->s32.graph[0], &p->s32.graph[1]})
         if (*s) (void)hipGraphExecDestroy(*s);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,12 @@ hipError_t launch_fill(T*, T, long long, hipStream_t);
 // ---------------------------------------------------------------------------
 
 extern thread_local std::string g_err;
+
+// Held while a stream is being captured into a graph and while device memory,
+// streams and uploads of a problem or a batch are set up or torn down.  The
+// runtime invalidates a capture in progress when another thread makes such
+// calls at the same time (the server sets up trees on its own thread).
+std::recursive_mutex& hip_setup_mutex();
 int32_t fail(int32_t code, const std::string& msg);
 
 #define HIP_TRY(...)                                                                            \

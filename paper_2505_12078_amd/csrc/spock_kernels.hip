@@ -256,11 +256,35 @@ constexpr int kRBK = 12;  // [K|R~^-1]^T in the backward sweep
 constexpr int kRBP = 16;  // [Abar|B] rows in the forward sweep (two column chunks)
 constexpr int kRBQ = 8;   // K rows in the forward sweep
 
+// Exchange between workgroups of one launch.  A value that another workgroup
+// reads while the launch runs is stored and loaded at device scope: the store
+// is written through to the level of the memory hierarchy that all XCDs share,
+// and the load skips the XCD-private caches.  Before the barrier that precedes
+// the counter or flag update, every wavefront drains its vector memory counter,
+// so its device-scope stores are complete.  Release/acquire fences would do the
+// same job, but at device scope they write back or invalidate the whole L2 of
+// the XCD, and that costs tens of microseconds per node when many workgroups
+// have stores in flight.
+template <typename real>
+SPK_DEV void st_dev(real* p, real v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename real>
+SPK_DEV real ld_dev(const real* p) {
+    return __hip_atomic_load(const_cast<real*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Every store this wavefront issued has completed (s_waitcnt vmcnt(0)); the
+// workgroup fence keeps the compiler from sinking stores below it.
+SPK_DEV void drain_stores() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+}
+
 // Wait until a node's forward result is published; false on timeout.
 SPK_DEV bool wait_done(int* flag) {
     const uint64_t t0 = wall_clock64();
     unsigned spins = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 2) {
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 2) {
         __builtin_amdgcn_s_sleep(1);
         if ((++spins & 1023u) == 0 && wall_clock64() - t0 > 200000000ull) return false;  // ~2 s
     }
@@ -306,7 +330,7 @@ SPK_DEV void seg_add(SegTable<real>& T, const real* src, int len) {
 }
 
 template <int kWG, typename real>
-SPK_DEV void seg_gather(const SegTable<real>& T, real* st) {
+SPK_DEV void seg_gather(const SegTable<real>& T, real* st, bool dev = false) {
     const int nseg = T.n;
     const int total = T.off[nseg];
     int off[kMaxSeg + 1];  // segment ends in registers: no dependent LDS reads per element
@@ -322,7 +346,8 @@ SPK_DEV void seg_gather(const SegTable<real>& T, real* st) {
                 int s = 0;
 #pragma unroll
                 for (int q = 1; q <= kMaxSeg; ++q) s += e >= off[q];
-                v[j] = T.src[s][e - T.off[s]];
+                const real* src = T.src[s] + (e - T.off[s]);
+                v[j] = dev ? ld_dev(src) : *src;
             }
         }
 #pragma unroll
@@ -472,14 +497,14 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
         const int i = s_node[lev];
         const int k = s_nch[lev], fc = s_fc[lev];
         if (k > 1) {
-            for (int c = t; c < m; c += kWG) P->e[(long long)j * m + c] = o[c];
-            // every wave makes its own stores visible device-wide before the
-            // arrival is counted (a barrier alone does not wait for them)
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            for (int c = t; c < m; c += kWG) st_dev(P->e + (long long)j * m + c, o[c]);
+            // every wave completes its own message stores before the arrival
+            // is counted (a barrier alone does not wait for them)
+            drain_stores();
             __syncthreads();
             if (t == 0) {
                 const int prev =
-                    __hip_atomic_fetch_add(&P->cnt[i], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_add(&P->cnt[i], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const int last = (prev == k - 1);
                 if (last) P->cnt[i] = 0;  // the next launch reuses the counter
                 s_last = last;
@@ -527,7 +552,7 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
             P->flag[i] = 0;
         }
         __syncthreads();
-        seg_gather<kWG>(s_seg, st);
+        seg_gather<kWG>(s_seg, st, k > 1);  // messages: device scope
         __syncthreads();
         // per-child inputs: staged copies or the arrays themselves
         const real* soc = sk ? st + oSOC : g_soc;
@@ -542,7 +567,11 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
         for (int c = t; c < m; c += kWG) {
             if (k > 1) {
                 real s = 0;
-                for (int q = 0; q < k; ++q) s += msg[q * m + c];
+                if (sk) {
+                    for (int q = 0; q < k; ++q) s += msg[q * m + c];
+                } else {
+                    for (int q = 0; q < k; ++q) s += ld_dev(msg + q * m + c);
+                }
                 g[c] = s;
             } else {
                 g[c] = o[c];
@@ -561,7 +590,11 @@ __global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restric
             real s = 0, gu = 0;
             for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + nx + r];
             if (k > 1) {
-                for (int q = 0; q < k; ++q) gu += msg[q * m + nx + r];
+                if (sk) {
+                    for (int q = 0; q < k; ++q) gu += msg[q * m + nx + r];
+                } else {
+                    for (int q = 0; q < k; ++q) gu += ld_dev(msg + q * m + nx + r);
+                }
             } else {
                 gu = o[nx + r];
             }
@@ -971,7 +1004,7 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
     if (!s_ok) return;
     if (L > 0) {
         const int pn = s_node[L - 1];
-        for (int r = t; r < nx; r += kWG) xa[r] = zout[P->z_x + (long long)pn * nx + r];
+        for (int r = t; r < nx; r += kWG) xa[r] = ld_dev(zout + P->z_x + (long long)pn * nx + r);
         for (int r = t; r < nu; r += kWG) xa[nx + r] = P->d[(long long)pn * nu + r];
     }
 
@@ -1046,12 +1079,14 @@ __global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict
                 __syncthreads();
             }
         }
-        for (int r = t; r < nx; r += kWG) zout[P->z_x + (long long)v * nx + r] = xn[r];
         if (nonleaf && k > 1) {
             // children owned by other tasks read x^v (and d^v): publish now
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            for (int r = t; r < nx; r += kWG) st_dev(zout + P->z_x + (long long)v * nx + r, xn[r]);
+            drain_stores();
             __syncthreads();
-            if (t == 0) __hip_atomic_store(&P->flag[v], 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == 0) st_dev(P->flag + v, 2);
+        } else {
+            for (int r = t; r < nx; r += kWG) zout[P->z_x + (long long)v * nx + r] = xn[r];
         }
         if (nonleaf) {
             // ---- input: u^v = K^v x^v + d^v ----
