@@ -193,33 +193,46 @@ int32_t spock_prox_gconj(spock_problem* p, const double* w, double* eta_out, int
 
 /*
  * Timing hook: run `steps` CP steps from the current device iterate in the
- * given precision (no residual checks, no readback) and report the mean
- * device duration of each kernel, measured with HIP events on the handle's
- * stream around every launch.  ms_backward / ms_forward may be NULL.
+ * given precision (no residual checks, no readback) and report mean device
+ * durations measured with HIP events on the handle's stream around every
+ * launch.  A step is four launches: prep (node-parallel: z - alpha L* eta, the
+ * S2 projection and the children-independent part of Alg. 2's backward
+ * recursion, Sec. 4.1-4.4), bsweep (leaves -> root: the dependent part of the
+ * backward recursion), fsweep (root -> leaves: x^j = Abar^j x^i + B^j d^i + c^j)
+ * and dual (node-parallel: u = K x + d and prox_{alpha g*} with the S3
+ * projections, Sec. 4.1, 5.3).  spock_time_steps reports ms_backward =
+ * prep + bsweep and ms_forward = fsweep + dual (each nullable);
+ * spock_time_kernels fills ms_kernels[4] in launch order.
  */
 int32_t spock_time_steps(spock_problem* p, int32_t precision, int32_t steps, double* ms_total,
                          double* ms_backward, double* ms_forward);
+int32_t spock_time_kernels(spock_problem* p, int32_t precision, int32_t steps, double* ms_total,
+                           double* ms_kernels);
 
 /* Launch `steps` CP steps from the current device iterate in the given
  * precision (SPOCK_FP64 or SPOCK_FP32), without residual checks or readback;
  * sync = 1 waits for them to finish.  For throughput measurement. */
 int32_t spock_run_steps(spock_problem* p, int32_t precision, int32_t steps, int32_t sync);
 
-/* Workgroup size (64, 128, 256 or 512 threads) of the sweep kernels of one
- * precision; picked by the autotuner (default 256).  Results do not depend on
- * it beyond rounding order. */
+/* Workgroup size (64, 128, 256 or 512 threads, i.e. 1-8 nodes per workgroup)
+ * of the node-parallel kernels of one precision; picked by the autotuner
+ * (default 256; lowered automatically when the LDS of a larger workgroup would
+ * exceed 64 KiB).  Results do not depend on it. */
 int32_t spock_set_launch(spock_problem* p, int32_t precision, int32_t workgroup);
 int32_t spock_get_launch(const spock_problem* p, int32_t precision, int32_t* workgroup);
 
-/* Bytes one CP step must move at minimum (factor matrices + iterates) in the
- * given precision, counted as in the design notes; for roofline reporting. */
+/* Bytes one CP step must move at minimum (every factor matrix and iterate
+ * entry a launch reads or writes, once) in the given precision; for roofline
+ * reporting.  spock_step_bytes: prep + bsweep and fsweep + dual;
+ * spock_kernel_bytes: bytes[4] per launch, in launch order. */
 int32_t spock_step_bytes(const spock_problem* p, int32_t precision, double* bytes_backward,
                          double* bytes_forward);
+int32_t spock_kernel_bytes(const spock_problem* p, int32_t precision, double* bytes);
 
 /*
- * Batched form: one CP step of the batch is one backward and one forward
- * launch over every member tree (uneven trees of any shapes and sizes share
- * the launch; one task per leaf of every member).
+ * Batched form: one CP step of the batch is the same four launches over every
+ * member tree (uneven trees of any shapes and sizes share each launch; one
+ * sweep wavefront per leaf and one node wavefront per node of every member).
  *
  * spock_batch_create groups problems created on the current device.  The
  * problems stay owned by the caller, must outlive the batch, and must not be
@@ -244,14 +257,18 @@ int32_t spock_batch_size(const spock_batch* b, int32_t* n_problems, int32_t* n_t
  */
 int32_t spock_batch_solve(spock_batch* b, const double* const* x0s, const int32_t* warm, spock_info* infos);
 
-/* Measurement: `steps` (even) batched steps of every member; per-kernel mean
- * durations with HIP events; algorithmic bytes of one batched step. */
+/* Measurement: `steps` (even) batched steps of every member; mean durations
+ * with HIP events (backward = prep + bsweep, forward = fsweep + dual, or the
+ * four launches in ms_kernels[4]); algorithmic bytes of one batched step. */
 int32_t spock_batch_run_steps(spock_batch* b, int32_t precision, int32_t steps, int32_t sync);
 int32_t spock_batch_time_steps(spock_batch* b, int32_t precision, int32_t steps, double* ms_total,
                                double* ms_backward, double* ms_forward);
+int32_t spock_batch_time_kernels(spock_batch* b, int32_t precision, int32_t steps, double* ms_total,
+                                 double* ms_kernels);
 int32_t spock_batch_step_bytes(const spock_batch* b, int32_t precision, double* bytes_backward,
                                double* bytes_forward);
-/* Workgroup size of the batch's sweep kernels for one precision (autotuner). */
+int32_t spock_batch_kernel_bytes(const spock_batch* b, int32_t precision, double* bytes);
+/* Workgroup size of the batch's node-parallel kernels for one precision (autotuner). */
 int32_t spock_batch_set_launch(spock_batch* b, int32_t precision, int32_t workgroup);
 
 /*

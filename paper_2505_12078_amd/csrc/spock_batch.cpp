@@ -1,8 +1,9 @@
-// Batched form: many independent scenario trees advanced by one backward and
-// one forward launch per CP step.  Each member keeps its own workspace; the
+// Batched form: many independent scenario trees advanced by the same four
+// launches per CP step as one tree.  Each member keeps its own workspace; the
 // batch holds copies of the members' descriptors whose residual slots, error
-// flags and "active" flags point into batch-owned arrays, a problem-major task
-// table (one task per leaf of every member) and one forward ticket counter.
+// flags and "active" flags point into batch-owned arrays, two problem-major
+// task tables (one sweep task per leaf and one node task per node of every
+// member) and one forward ticket counter.
 // Members that converge are switched off through their active flag, so a
 // captured graph of `check_every` steps is replayed unchanged until every
 // member is done.
@@ -23,9 +24,32 @@ ProbDev<double>* dev_of<double>(spock_batch* b) { return b->d64; }
 template <>
 ProbDev<float>* dev_of<float>(spock_batch* b) { return b->d32; }
 template <typename real>
-int lds_of(spock_batch* b) { return sizeof(real) == 8 ? b->lds64 : b->lds32; }
+spk::LaunchCfg& cfg_of(spock_batch* b) { return sizeof(real) == 8 ? b->cfg64 : b->cfg32; }
+
+// The batch's launch configuration: LDS sizes and tile classes large enough
+// for every member, the node workgroup lowered until its LDS fits 64 KiB.
 template <typename real>
-int wg_of(spock_batch* b) { return sizeof(real) == 8 ? b->wg64 : b->wg32; }
+spk::LaunchCfg batch_cfg(const spock_batch* b, int node_wg) {
+    spk::LaunchCfg c{};
+    int cst = 0;
+    for (auto* p : b->probs) {
+        const spk::LaunchCfg m = make_cfg<real>(p, 64);
+        c.wave_elems = std::max(c.wave_elems, m.wave_elems);
+        c.sweep_lds = std::max(c.sweep_lds, m.sweep_lds);
+        for (int q = 0; q < 4; ++q) c.cls[q] = std::max(c.cls[q], m.cls[q]);
+        cst = std::max(cst, spk::consts_elems(p->nx, p->nu));
+    }
+    auto lds = [&](int wg) { return (cst + (wg / 64) * c.wave_elems) * (int)sizeof(real); };
+    while (node_wg > 64 && lds(node_wg) > 64 * 1024) node_wg /= 2;
+    c.leaf_tasks = b->tasks;
+    c.n_leaf_tasks = b->n_tasks;
+    c.node_tasks = b->ntasks;
+    c.n_node_tasks = b->n_ntasks;
+    c.ticket = b->ticket;
+    c.node_wg = node_wg;
+    c.node_lds = lds(node_wg);
+    return c;
+}
 
 int32_t upload_active(spock_batch* b, const std::vector<Member>* m) {
     for (int k = 0; k < b->n; ++k) b->h_active[k] = m ? (int)(*m)[k].live : 1;
@@ -37,8 +61,8 @@ template <typename real>
 int32_t batch_steps(spock_batch* b, int steps, bool check_last) {
     for (int k = 0; k < steps; ++k) {
         // every member sits at copy 0 before a batched chunk; parity follows k
-        HIP_TRY(spk::launch_step<real>(dev_of<real>(b), b->tasks, b->ticket, b->n_tasks, lds_of<real>(b), k & 1,
-                                       check_last && k == steps - 1, wg_of<real>(b), b->stream));
+        HIP_TRY(spk::launch_step<real>(dev_of<real>(b), cfg_of<real>(b), k & 1, check_last && k == steps - 1,
+                                       b->stream));
     }
     return SPOCK_OK;
 }
@@ -158,14 +182,12 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
             return fail(SPOCK_E_INVALID, "null problem in batch");
         }
         b->n_tasks += probs[k]->n_leaf;
-        b->lds64 = std::max(b->lds64, sweep_lds_bytes(probs[k], b->wg64, 8));
-        b->lds32 = std::max(b->lds32, sweep_lds_bytes(probs[k], b->wg32, 4));
+        b->n_ntasks += probs[k]->n_ntasks;
         HIP_TRY(hipStreamSynchronize(probs[k]->stream));
-        double bb, bf;
         for (int q = 0; q < 2; ++q) {
-            spock_step_bytes(probs[k], q == 0 ? SPOCK_FP64 : SPOCK_FP32, &bb, &bf);
-            b->bytes_b[q] += bb;
-            b->bytes_f[q] += bf;
+            double kb[4];
+            step_bytes_of(probs[k], q == 0 ? 8 : 4, kb);
+            for (int ph = 0; ph < 4; ++ph) b->bytes_k[q][ph] += kb[ph];
         }
     }
     size_t off = 0;
@@ -177,6 +199,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
     };
     const size_t o64 = take(sizeof(ProbDev<double>) * n), o32 = take(sizeof(ProbDev<float>) * n);
     const size_t ot = take(sizeof(int2) * b->n_tasks), oa = take(sizeof(int) * n), otk = take(sizeof(int) * 4);
+    const size_t ont = take(sizeof(int2) * b->n_ntasks);
     const size_t oe = take(sizeof(int) * n), orr = take(sizeof(unsigned long long) * 2 * n);
     b->bytes = off + 256;
     std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
@@ -189,6 +212,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
     b->d64 = (ProbDev<double>*)(base + o64);
     b->d32 = (ProbDev<float>*)(base + o32);
     b->tasks = (int2*)(base + ot);
+    b->ntasks = (int2*)(base + ont);
     b->active = (int*)(base + oa);
     b->ticket = (int*)(base + otk);
     b->err = (int*)(base + oe);
@@ -203,8 +227,9 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
         return bail(SPOCK_E_HIP, "batch pinned buffer");
     std::vector<ProbDev<double>> h64(n);
     std::vector<ProbDev<float>> h32(n);
-    std::vector<int2> tasks;
+    std::vector<int2> tasks, ntasks;
     tasks.reserve(b->n_tasks);
+    ntasks.reserve(b->n_ntasks);
     for (int k = 0; k < n; ++k) {
         h64[k] = probs[k]->s64.h;
         h32[k] = probs[k]->s32.h;
@@ -212,11 +237,16 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
         h64[k].err = h32[k].err = b->err + k;
         h64[k].res = h32[k].res = b->res + 2 * k;
         for (int l = 0; l < probs[k]->n_leaf; ++l) tasks.push_back(make_int2(k, l));
+        for (int v = 0; v < probs[k]->n_ntasks; ++v) ntasks.push_back(make_int2(k, v < probs[k]->n ? v : -1));
     }
+    b->cfg64 = batch_cfg<double>(b, spk::kDefaultWG);
+    b->cfg32 = batch_cfg<float>(b, spk::kDefaultWG);
     b->h_active.assign(n, 1);
     e = hipMemcpy(b->d64, h64.data(), sizeof(ProbDev<double>) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d32, h32.data(), sizeof(ProbDev<float>) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->tasks, tasks.data(), sizeof(int2) * tasks.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->ntasks, ntasks.data(), sizeof(int2) * ntasks.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->active, b->h_active.data(), sizeof(int) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(b->ticket, 0, sizeof(int) * 4);
     if (e == hipSuccess) e = hipMemset(b->err, 0, sizeof(int) * n);
@@ -372,55 +402,50 @@ int32_t spock_batch_run_steps(spock_batch* b, int32_t prec, int32_t steps, int32
     return SPOCK_OK;
 }
 
-int32_t spock_batch_time_steps(spock_batch* b, int32_t prec, int32_t steps, double* ms_total, double* ms_b,
-                               double* ms_f) {
-    if (!b || steps < 2 || (steps & 1)) return fail(SPOCK_E_INVALID, "steps must be even and >= 2");
+int32_t spock_batch_time_kernels(spock_batch* b, int32_t prec, int32_t steps, double* ms_total, double* ms_k) {
+    if (!b || steps < 2 || (steps & 1) || !ms_k) return fail(SPOCK_E_INVALID, "steps must be even and >= 2");
     int32_t r = spock_batch_run_steps(b, prec, 0, 1);
     if (r) return r;
-    std::vector<hipEvent_t> ev(2 * (size_t)steps + 1);
+    std::vector<hipEvent_t> ev(4 * (size_t)steps + 1);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     HIP_TRY(hipEventRecord(ev[0], b->stream));
-    for (int k = 0; k < steps; ++k) {
-        if (prec == SPOCK_FP64) {
-            HIP_TRY(spk::launch_backward<double>(b->d64, b->tasks, b->ticket, b->n_tasks, b->lds64, k & 1, 0, b->wg64,
-                                                b->stream));
-            HIP_TRY(hipEventRecord(ev[2 * k + 1], b->stream));
-            HIP_TRY(spk::launch_forward<double>(b->d64, b->tasks, b->ticket, b->n_tasks, b->lds64, k & 1, 0, b->wg64,
-                                               b->stream));
-        } else {
-            HIP_TRY(spk::launch_backward<float>(b->d32, b->tasks, b->ticket, b->n_tasks, b->lds32, k & 1, 0, b->wg32,
-                                               b->stream));
-            HIP_TRY(hipEventRecord(ev[2 * k + 1], b->stream));
-            HIP_TRY(spk::launch_forward<float>(b->d32, b->tasks, b->ticket, b->n_tasks, b->lds32, k & 1, 0, b->wg32,
-                                              b->stream));
+    for (int k = 0; k < steps; ++k)
+        for (int ph = 0; ph < 4; ++ph) {
+            if (prec == SPOCK_FP64) HIP_TRY(spk::launch_phase<double>(b->d64, b->cfg64, ph, k & 1, 0, b->stream));
+            else HIP_TRY(spk::launch_phase<float>(b->d32, b->cfg32, ph, k & 1, 0, b->stream));
+            HIP_TRY(hipEventRecord(ev[4 * k + ph + 1], b->stream));
         }
-        HIP_TRY(hipEventRecord(ev[2 * k + 2], b->stream));
-    }
     HIP_TRY(hipEventSynchronize(ev.back()));
-    double tb = 0, tf = 0;
-    for (int k = 0; k < steps; ++k) {
-        float a = 0, c = 0;
-        HIP_TRY(hipEventElapsedTime(&a, ev[2 * k], ev[2 * k + 1]));
-        HIP_TRY(hipEventElapsedTime(&c, ev[2 * k + 1], ev[2 * k + 2]));
-        tb += a;
-        tf += c;
-    }
+    double t[4] = {0, 0, 0, 0};
+    for (int k = 0; k < steps; ++k)
+        for (int ph = 0; ph < 4; ++ph) {
+            float a = 0;
+            HIP_TRY(hipEventElapsedTime(&a, ev[4 * k + ph], ev[4 * k + ph + 1]));
+            t[ph] += a;
+        }
     float tot = 0;
     HIP_TRY(hipEventElapsedTime(&tot, ev[0], ev.back()));
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (ms_total) *ms_total = tot / steps;
-    if (ms_b) *ms_b = tb / steps;
-    if (ms_f) *ms_f = tf / steps;
+    for (int ph = 0; ph < 4; ++ph) ms_k[ph] = t[ph] / steps;
     return read_all(b);
+}
+
+int32_t spock_batch_time_steps(spock_batch* b, int32_t prec, int32_t steps, double* ms_total, double* ms_b,
+                               double* ms_f) {
+    double k[4];
+    int32_t r = spock_batch_time_kernels(b, prec, steps, ms_total, k);
+    if (r) return r;
+    if (ms_b) *ms_b = k[0] + k[1];
+    if (ms_f) *ms_f = k[2] + k[3];
+    return SPOCK_OK;
 }
 
 int32_t spock_batch_set_launch(spock_batch* b, int32_t precision, int32_t workgroup) {
     if (!b || !(workgroup == 64 || workgroup == 128 || workgroup == 256 || workgroup == 512))
         return fail(SPOCK_E_INVALID, "workgroup must be 64, 128, 256 or 512");
-    const int bytes = precision == SPOCK_FP64 ? 8 : 4;
-    int lds = 0;
-    for (auto* p : b->probs) lds = std::max(lds, sweep_lds_bytes(p, workgroup, bytes));
-    if (lds > 64 * 1024) return fail(SPOCK_E_INVALID, "LDS too large");
+    const spk::LaunchCfg c = precision == SPOCK_FP64 ? batch_cfg<double>(b, workgroup) : batch_cfg<float>(b, workgroup);
+    if (c.node_wg != workgroup) return fail(SPOCK_E_INVALID, "LDS too large");
     HIP_TRY(hipStreamSynchronize(b->stream));
     const int gi = precision == SPOCK_FP64 ? 0 : 1;
     if (b->graph[gi]) {
@@ -428,21 +453,23 @@ int32_t spock_batch_set_launch(spock_batch* b, int32_t precision, int32_t workgr
         b->graph[gi] = nullptr;
         b->graph_steps[gi] = 0;
     }
-    if (precision == SPOCK_FP64) {
-        b->wg64 = workgroup;
-        b->lds64 = lds;
-    } else {
-        b->wg32 = workgroup;
-        b->lds32 = lds;
-    }
+    if (precision == SPOCK_FP64) b->cfg64 = c;
+    else b->cfg32 = c;
     return SPOCK_OK;
 }
 
 int32_t spock_batch_step_bytes(const spock_batch* b, int32_t prec, double* bb, double* bf) {
     if (!b) return fail(SPOCK_E_INVALID, "null batch");
     const int q = prec == SPOCK_FP64 ? 0 : 1;
-    if (bb) *bb = b->bytes_b[q];
-    if (bf) *bf = b->bytes_f[q];
+    if (bb) *bb = b->bytes_k[q][0] + b->bytes_k[q][1];
+    if (bf) *bf = b->bytes_k[q][2] + b->bytes_k[q][3];
+    return SPOCK_OK;
+}
+
+int32_t spock_batch_kernel_bytes(const spock_batch* b, int32_t prec, double* bytes) {
+    if (!b || !bytes) return fail(SPOCK_E_INVALID, "null argument");
+    const int q = prec == SPOCK_FP64 ? 0 : 1;
+    for (int ph = 0; ph < 4; ++ph) bytes[ph] = b->bytes_k[q][ph];
     return SPOCK_OK;
 }
 

@@ -7,10 +7,11 @@
 
 namespace spk {
 
-// Threads per workgroup of the sweep kernels (a launch parameter: 64, 128,
-// 256 or 512, picked per problem or batch); the default is four wave64s.
+// Threads per workgroup of the node-parallel kernels (a launch parameter: 64,
+// 128, 256 or 512, i.e. one to eight nodes per workgroup, one wavefront each).
 constexpr int kDefaultWG = 256;
-// Longest root-to-leaf path a forward task may walk (stages + 1).
+constexpr int kMaxNodeWaves = 8;
+// Longest root-to-leaf path (stages + 1).
 constexpr int kMaxDepth = 512;
 
 // One problem in one precision.  Every pointer is a device address inside the
@@ -25,6 +26,7 @@ struct ProbDev {
     real alpha, ball_r, ballN_r;
 
     // tree (breadth-first numbering, children contiguous)
+    const int4* node;        // per node: first child, number of children, y offset, parent
     const int* parent;
     const int* first_child;
     const int* n_ch;
@@ -32,13 +34,23 @@ struct ProbDev {
     const int* path;         // per leaf l: node at each stage 0..N on the root-to-leaf path
     const int* top_owned;    // per leaf l: first stage whose path node has l as leftmost leaf
 
-    // Offline factors (Alg. 1, reduced online form):
-    //   M[j]  = [Abar^j | B^j]  (nx x m, row-major), node j >= 1
-    //   KR[i] = [K^i | R~^i^-1] (nu x m, row-major), non-leaf node i
-    const real* M;
-    long long M_stride;
-    const real* KR;
-    long long KR_stride;
+    // Offline factors (Alg. 1, reduced online form), each packed in the lane
+    // order of the product that reads it (tile_pack):
+    //   T1[i]  = K^i              read as (K^i)^T ubar          prep, non-leaf i
+    //   T2M[j] = [Abar^j | B^j]   read as [Abar|B]^T h          bsweep, node j >= 1
+    //   T2R[i] = R~^i^-1          (symmetric)                   bsweep, non-leaf i
+    //   T3[j]  = [Abar^j | B^j]^T read as [Abar|B] [x; d]       fsweep, node j >= 1
+    //   T4[i]  = (K^i)^T          read as K^i x                 dual, non-leaf i
+    const real* T1;
+    long long T1_stride;
+    const real* T2M;
+    long long T2M_stride;
+    const real* T2R;
+    long long T2R_stride;
+    const real* T3;
+    long long T3_stride;
+    const real* T4;
+    long long T4_stride;
     const real* c;           // affine term c^j (nx per node) or null
     const real* Pc;          // P^j c^j (nx per node) or null
 
@@ -69,6 +81,8 @@ struct ProbDev {
     // scratch
     real* d;                 // d^i of Alg. 2, nu per non-leaf node
     real* e;                 // backward message [Abar|B]^T h of node j, m per node
+    real* h0;                // -xbar - K^T ubar (+ P c): h of node j before its children's messages, nx
+    real* ub;                // ubar of non-leaf node i, nu
     int* cnt;                // backward arrival counters, per node
     int* flag;               // forward claim/done flags, per node
     int* err;                // device wait timeout
@@ -79,32 +93,110 @@ struct ProbDev {
 // Children whose per-child inputs are staged in LDS; a wider node reads them
 // from global memory directly (same contiguous layout).
 constexpr int kStageKids = 16;
+// LDS scratch of one wavefront for cross-lane partial sums.
+constexpr int kRed = 128;
+// Vector entries per lane the forward sweep keeps in registers (nx, nu <= 64 kVecPL).
+constexpr int kVecPL = 4;
 
-// Elements of one wavefront's staging array for a dual block in the forward sweep.
-__host__ __device__ inline int blk_elems(int nx, int nu, int /*max_ch*/) {
-    const int m = nx + nu;
-    int b = 2 * nx + nu;
-    if (m + 2 > b) b = m + 2;
-    return b;
+__host__ __device__ inline int imax(int a, int b) { return a > b ? a : b; }
+__host__ __device__ inline int round4(int a) { return (a + 3) & ~3; }
+
+// Per-problem diagonal data staged once per node workgroup.
+__host__ __device__ inline int consts_elems(int nx, int nu) { return round4(10 * nx + 4 * nu); }
+
+// Largest dual block of a node (constraint block with a ball, an SOC block).
+__host__ __device__ inline int blk_elems(int nx, int nu, int nc, int ncN) {
+    return imax(imax(nc, nx + nu + 2), imax(ncN, nx + 2));
 }
 
-// Elements of the LDS area that stages one node's vector inputs.
-__host__ __device__ inline int stage_elems(int nx, int nu, int nc, int max_ch) {
+// Staged vector inputs of one node in the prep and dual kernels.
+__host__ __device__ inline int node_stage_elems(int nx, int nu, int nc, int ncN, int max_ch) {
     const int m = nx + nu;
-    const int kc = max_ch < kStageKids ? max_ch : kStageKids;
-    return 3 * nx + 2 * nu + nc + kc * (2 * m + nx + 12) + 16;
+    const int kk = max_ch < kStageKids ? max_ch : kStageKids;
+    const int prep = 2 * nx + nu + nc + kk * (m + 2) + 2 * (2 * kk + 1) + 1 + 3 * kk + kk * (nx + 2);
+    const int dual = 2 * nx + 2 * nu + nc + kk * (m + 2) + 3 * (2 * kk + 1) + 3 + 3 * kk;
+    const int leaf = 3 * nx + ncN + 4;
+    return imax(imax(prep, dual), leaf);
 }
 
-// Number of `real` elements of dynamic LDS a sweep workgroup of `wg` threads
-// needs (the larger of the backward and the forward partitions).
-__host__ __device__ inline int lds_elems(int nx, int nu, int max_ch, int wg) {
+// LDS elements of one wavefront of the prep / dual kernels:
+//   prep: red | xbar (nx) | ubar (nu) | K^T ubar (nx) | stage
+//   dual: red | u (nu) | L* d_eta on x (nx) and u (nu) | blk | dblk | stage
+__host__ __device__ inline int node_head_elems(int nx, int nu, int nc, int ncN) {
+    return round4(imax(2 * round4(nx) + round4(nu), 2 * nu + nx + 2 * blk_elems(nx, nu, nc, ncN)));
+}
+__host__ __device__ inline int node_wave_elems(int nx, int nu, int nc, int ncN, int max_ch) {
+    return round4(kRed + node_head_elems(nx, nu, nc, ncN) + node_stage_elems(nx, nu, nc, ncN, max_ch));
+}
+
+// LDS bytes of the sweep kernels (one wavefront per workgroup): path node ids,
+// child counts and first children (ints), then red | h / a | g / x | w | d.
+// Every vector region holds at least kVecPad entries: the products read the
+// full register class of v (zero past the vector's length).
+constexpr int kVecPad = 80;
+__host__ __device__ inline int sweep_vec(int n) { return round4(imax(n, kVecPad)); }
+__host__ __device__ inline int sweep_int_bytes(int N) { return ((3 * (N + 1) * 4) + 15) & ~15; }
+__host__ __device__ inline int sweep_elems(int nx, int nu) {
     const int m = nx + nu;
-    const int nc = m + nx;  // the larger constraint block (with a ball)
-    const int waves = wg / 64;
-    const int common = wg + 10 * nx + 4 * nu + stage_elems(nx, nu, nc, max_ch);
-    const int bwd = common + 2 * m + nx + 2 * nu + max_ch;
-    const int fwd = common + m + nx + nu + waves * (nx + nu) + 2 * waves * blk_elems(nx, nu, max_ch);
-    return (bwd > fwd ? bwd : fwd) + 8;
+    return kRed + 2 * sweep_vec(m) + 2 * sweep_vec(nu);
+}
+
+// What one launch of a CP step needs besides the problem descriptors.
+struct LaunchCfg {
+    const int2* leaf_tasks;  // (problem, leaf) per sweep wavefront
+    int n_leaf_tasks;
+    const int2* node_tasks;  // (problem, node or -1) per node wavefront, kMaxNodeWaves-padded per problem
+    int n_node_tasks;
+    int* ticket;             // forward-sweep ticket counter
+    int node_wg;             // threads per node workgroup (64, 128, 256, 512)
+    int node_lds;            // dynamic LDS bytes of a node workgroup
+    int wave_elems;          // LDS elements of one node wavefront
+    int sweep_lds;           // dynamic LDS bytes of a sweep wavefront
+    int cls[4];              // register tile class of prep, bsweep, fsweep, dual
+};
+
+// Packed tiles of the column-lane products out[o] = sum_k A[k][o] v[k]
+// (K rows, O <= 128 columns).  Block 1 holds columns 0..min(O,64)-1 with
+// G1 = 64 / min(O,64) row groups, block 2 the columns from 64 on with
+// G2 = 64 / (O - 64).  Lane l = g W + c of a block holds rows g, g + G, ... of
+// column c; rows per lane are padded to the 16-byte vector width V, and the
+// element of (row slot i, lane l) sits at ((i / V) * 64 + l) * V + i % V.
+template <typename real>
+__host__ __device__ constexpr int tile_vec() { return 16 / (int)sizeof(real); }
+__host__ __device__ inline int tile_rows(int K, int G, int V) { return ((K + G - 1) / G + V - 1) / V * V; }
+__host__ __device__ inline long long tile_elems(int K, int O, int V) {
+    if (O < 1) return 0;
+    const int W1 = O < 64 ? O : 64, G1 = 64 / W1;
+    long long e = (long long)tile_rows(K, G1, V) * 64;
+    if (O > 64) {
+        const int W2 = O - 64, G2 = 64 / W2;
+        e += (long long)tile_rows(K, G2, V) * 64;
+    }
+    return e;
+}
+
+// Zero rows (of 64 lanes x V) after every packed tile array: a wavefront
+// loads the full rows of its register class from every tile, so reads run up
+// to (80 + 20) rows past the start of the last tile.
+constexpr int kTilePadRows = 128;
+template <typename real>
+__host__ __device__ constexpr long long tile_pad_elems() { return (long long)kTilePadRows * 64 * tile_vec<real>(); }
+
+// Register tile classes of the column-lane products (rows per lane); a
+// product that does not fit its class runs from global memory instead.
+constexpr int kTileClasses[4] = {16, 32, 64, 80};
+
+// Register rows a column-lane product needs: block 1 rows, and block 2 rows
+// times 4 (block 2 has a quarter of the class).
+__host__ __device__ inline int col_need(int K, int O, int V) {
+    if (O > 128 || O < 1) return 1 << 20;
+    const int W1 = O < 64 ? O : 64, G1 = 64 / W1;
+    int need = tile_rows(K, G1, V);
+    if (O > 64) {
+        const int W2 = O - 64, G2 = 64 / W2;
+        need = imax(need, 4 * tile_rows(K, G2, V));
+    }
+    return need;
 }
 
 }  // namespace spk

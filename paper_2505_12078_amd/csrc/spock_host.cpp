@@ -141,8 +141,18 @@ template <typename real>
 static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
     ProbDev<real>& h = s.h;
     const int n = p->n, nl = p->n_nl, nx = p->nx, nu = p->nu, m = p->m;
-    h.M = a.take<real>((long long)n * p->M_stride);
-    h.KR = a.take<real>((long long)nl * p->KR_stride);
+    constexpr int V = spk::tile_vec<real>();
+    h.T1_stride = spk::tile_elems(nu, nx, V);
+    h.T2M_stride = spk::tile_elems(nx, m, V);
+    h.T2R_stride = spk::tile_elems(nu, nu, V);
+    h.T3_stride = spk::tile_elems(m, nx, V);
+    h.T4_stride = spk::tile_elems(nx, nu, V);
+    const long long pad = spk::tile_pad_elems<real>();
+    h.T1 = a.take<real>((long long)nl * h.T1_stride + pad);
+    h.T2M = a.take<real>((long long)n * h.T2M_stride + pad);
+    h.T2R = a.take<real>((long long)nl * h.T2R_stride + pad);
+    h.T3 = a.take<real>((long long)n * h.T3_stride + pad);
+    h.T4 = a.take<real>((long long)nl * h.T4_stride + pad);
     h.c = p->affine ? a.take<real>((long long)n * nx) : nullptr;
     h.Pc = p->affine ? a.take<real>((long long)n * nx) : nullptr;
     h.qh = a.take<real>(nx);
@@ -166,6 +176,8 @@ static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
     }
     h.d = a.take<real>((long long)nl * nu);
     h.e = a.take<real>((long long)n * m);
+    h.h0 = a.take<real>((long long)n * nx);
+    h.ub = a.take<real>((long long)nl * nu);
     s.d = a.take<ProbDev<real>>(1);
 }
 
@@ -177,6 +189,9 @@ static void carve(Arena& a, spock_problem* p) {
     p->d_top = a.take<int>(p->n_leaf);
     p->d_ticket = a.take<int>(4);  // [0] forward ticket, [1] constant 1 (active flag)
     p->d_tasks = a.take<int2>(p->n_leaf);
+    p->d_node = a.take<int4>(p->n);
+    p->n_ntasks = (p->n + spk::kMaxNodeWaves - 1) / spk::kMaxNodeWaves * spk::kMaxNodeWaves;
+    p->d_ntasks = a.take<int2>(p->n_ntasks);
     p->d_res = a.take<unsigned long long>(4);
     p->d_err = a.take<int>(4);
     const long long nv = std::max(p->nz, p->neta);
@@ -286,8 +301,11 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     p->neta = o;
     p->M_stride = ((long long)nx * p->m + 31) / 32 * 32;
     p->KR_stride = ((long long)nu * p->m + 31) / 32 * 32;
-    if ((long long)spk::lds_elems(nx, nu, p->max_ch, spk::kDefaultWG) * 8 > 64 * 1024)
-        return fail(SPOCK_E_INVALID, "nx + nu or the branching is too large for one workgroup");
+    if (nx > 64 * spk::kVecPL || nu > 64 * spk::kVecPL)
+        return fail(SPOCK_E_INVALID, "nx and nu must not exceed 256");
+    if (node_lds_bytes(p, 64, 8) > 64 * 1024 ||
+        spk::sweep_int_bytes(p->N) + spk::sweep_elems(nx, nu) * 8 > 64 * 1024)
+        return fail(SPOCK_E_INVALID, "nx + nu or the branching is too large for one wavefront's LDS");
     return SPOCK_OK;
 }
 
@@ -524,6 +542,76 @@ static hipError_t put(const real* dst, const std::vector<double>& src, hipStream
     return hipStreamSynchronize(st);
 }
 
+// Pack A (K x O, A(k, o) given by `at`) in the lane order of the column-lane
+// product out[o] = sum_k A(k, o) v[k] (layout of tile_elems in spock_dev.h).
+template <typename real, typename F>
+static void tile_pack(real* out, int K, int O, F at) {
+    constexpr int V = spk::tile_vec<real>();
+    auto block = [&](real* dst, int W, int col0) {
+        const int G = 64 / W, rows = spk::tile_rows(K, G, V);
+        for (int i = 0; i < rows; ++i)
+            for (int l = 0; l < 64; ++l) {
+                const int g = l / W, c = l - g * W, k = g + i * G;
+                const double val = (g < G && k < K) ? at(k, col0 + c) : 0.0;
+                dst[((size_t)(i / V) * 64 + l) * V + i % V] = (real)val;
+            }
+        return (size_t)rows * 64;
+    };
+    const int W1 = O < 64 ? O : 64;
+    const size_t e1 = block(out, W1, 0);
+    if (O > 64) block(out + e1, O - 64, 64);
+}
+
+// The five packed tile arrays of one precision from the float64 factors.
+template <typename real>
+static hipError_t put_tiles(const spock_problem* p, const ProbDev<real>& h, const std::vector<double>& M,
+                            const std::vector<double>& KR, hipStream_t st) {
+    const int n = p->n, nl = p->n_nl, nx = p->nx, nu = p->nu, m = p->m;
+    // each array is followed by zero padding (see kTilePadRows)
+    auto upload = [&](const real* dst, long long count, long long stride, auto fill) -> hipError_t {
+        std::vector<real> buf((size_t)(count * stride + spk::tile_pad_elems<real>()), real(0));
+        parallel_for((int)count, [&](int v) { fill(buf.data() + (size_t)v * stride, v); });
+        hipError_t e = hipMemcpyAsync((void*)dst, buf.data(), buf.size() * sizeof(real), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(st);
+    };
+    auto Mj = [&](int j) { return M.data() + (size_t)j * p->M_stride; };
+    auto KRi = [&](int i) { return KR.data() + (size_t)i * p->KR_stride; };
+    hipError_t e;
+    // prep: (K^i)^T ubar, A(k, o) = K[k][o], k < nu, o < nx
+    e = upload(h.T1, nl, h.T1_stride, [&](real* t, int i) {
+        const double* a = KRi(i);
+        tile_pack<real>(t, nu, nx, [&](int k, int o) { return a[(size_t)k * m + o]; });
+    });
+    if (e != hipSuccess) return e;
+    // bsweep: [Abar|B]^T h, A(k, o) = M[k][o], k < nx, o < m
+    e = upload(h.T2M, n, h.T2M_stride, [&](real* t, int j) {
+        if (j == 0) return;
+        const double* a = Mj(j);
+        tile_pack<real>(t, nx, m, [&](int k, int o) { return a[(size_t)k * m + o]; });
+    });
+    if (e != hipSuccess) return e;
+    // bsweep: R~^-1 w with R~^-1 made exactly symmetric
+    e = upload(h.T2R, nl, h.T2R_stride, [&](real* t, int i) {
+        const double* a = KRi(i) + nx;
+        tile_pack<real>(t, nu, nu,
+                        [&](int k, int o) { return 0.5 * (a[(size_t)k * m + o] + a[(size_t)o * m + k]); });
+    });
+    if (e != hipSuccess) return e;
+    // fsweep: [Abar|B] a, A(k, o) = M[o][k], k < m, o < nx
+    e = upload(h.T3, n, h.T3_stride, [&](real* t, int j) {
+        if (j == 0) return;
+        const double* a = Mj(j);
+        tile_pack<real>(t, m, nx, [&](int k, int o) { return a[(size_t)o * m + k]; });
+    });
+    if (e != hipSuccess) return e;
+    // dual: K^i x, A(k, o) = K[o][k], k < nx, o < nu
+    return upload(h.T4, nl, h.T4_stride, [&](real* t, int i) {
+        const double* a = KRi(i);
+        tile_pack<real>(t, nx, nu, [&](int k, int o) { return a[(size_t)o * m + k]; });
+    });
+}
+
 template <typename real>
 static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<double>& M,
                           const std::vector<double>& KR, const std::vector<double>& cs,
@@ -549,8 +637,7 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     h.first_child = p->d_tree + p->n;
     h.n_ch = p->d_tree + 2 * p->n;
     h.y_off = p->d_tree + 3 * p->n;
-    h.M_stride = p->M_stride;
-    h.KR_stride = p->KR_stride;
+    h.node = p->d_node;
     h.z_x = p->z_x; h.z_u = p->z_u; h.z_y = p->z_y; h.z_tau = p->z_tau; h.z_s = p->z_s;
     h.e_y = p->e_y; h.e_s = p->e_s; h.e_c = p->e_c; h.e_soc = p->e_soc; h.e_cN = p->e_cN; h.e_socN = p->e_socN;
     h.nz = p->nz;
@@ -562,10 +649,9 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     h.active = p->d_ticket + 1;
     h.err = p->d_err;
     h.res = p->d_res;
-    s.lds_bytes = sweep_lds_bytes(p, s.wg, (int)sizeof(real));
+    s.cfg = make_cfg<real>(p, s.cfg.node_wg > 0 ? s.cfg.node_wg : spk::kDefaultWG);
     hipStream_t st = p->stream;
-    HIP_TRY(put<real>(h.M, M, st));
-    HIP_TRY(put<real>(h.KR, KR, st));
+    HIP_TRY(put_tiles<real>(p, h, M, KR, st));
     if (p->affine) {
         HIP_TRY(put<real>(h.c, cs, st));
         HIP_TRY(put<real>(h.Pc, Pc, st));
@@ -600,8 +686,7 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
 template <typename real>
 int32_t step(spock_problem* p, int check) {
     DevSet<real>& s = set_of<real>(p);
-    HIP_TRY(spk::launch_step<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, s.par, check, s.wg,
-                                   p->stream));
+    HIP_TRY(spk::launch_step<real>(s.d, s.cfg, s.par, check, p->stream));
     s.par ^= 1;
     return SPOCK_OK;
 }
@@ -626,8 +711,7 @@ static int32_t chunk(spock_problem* p, int steps) {
             HIP_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
             int par = s.par;
             for (int k = 0; k < steps; ++k) {
-                hipError_t e = spk::launch_step<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, par,
-                                                      k == steps - 1, s.wg, p->stream);
+                hipError_t e = spk::launch_step<real>(s.d, s.cfg, par, k == steps - 1, p->stream);
                 if (e != hipSuccess) {
                     (void)hipStreamEndCapture(p->stream, &graph);
                     return fail(SPOCK_E_HIP, std::string("capture: ") + hipGetErrorString(e));
@@ -717,8 +801,57 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-int sweep_lds_bytes(const spock_problem* p, int wg, int real_bytes) {
-    return spk::lds_elems(p->nx, p->nu, p->max_ch, wg) * real_bytes;
+int node_lds_bytes(const spock_problem* p, int node_wg, int real_bytes) {
+    const int waves = node_wg / 64;
+    return (spk::consts_elems(p->nx, p->nu) + waves * spk::node_wave_elems(p->nx, p->nu, p->nc, p->ncN, p->max_ch)) *
+           real_bytes;
+}
+
+int tile_class(int need) {
+    for (int c : spk::kTileClasses)
+        if (need <= c) return c;
+    return spk::kTileClasses[3];
+}
+
+template <typename real>
+spk::LaunchCfg make_cfg(const spock_problem* p, int node_wg) {
+    constexpr int V = spk::tile_vec<real>();
+    const int nx = p->nx, nu = p->nu, m = p->m;
+    // the largest node workgroup (up to node_wg) whose LDS fits 64 KiB
+    while (node_wg > 64 && node_lds_bytes(p, node_wg, (int)sizeof(real)) > 64 * 1024) node_wg /= 2;
+    spk::LaunchCfg c{};
+    c.leaf_tasks = p->d_tasks;
+    c.n_leaf_tasks = p->n_leaf;
+    c.node_tasks = p->d_ntasks;
+    c.n_node_tasks = p->n_ntasks;
+    c.ticket = p->d_ticket;
+    c.node_wg = node_wg;
+    c.node_lds = node_lds_bytes(p, node_wg, (int)sizeof(real));
+    c.wave_elems = spk::node_wave_elems(nx, nu, p->nc, p->ncN, p->max_ch);
+    c.sweep_lds = spk::sweep_int_bytes(p->N) + spk::sweep_elems(nx, nu) * (int)sizeof(real);
+    c.cls[0] = tile_class(spk::col_need(nu, nx, V));
+    c.cls[1] = tile_class(spk::col_need(nx, m, V));
+    c.cls[2] = tile_class(spk::col_need(m, nx, V));
+    c.cls[3] = tile_class(spk::col_need(nx, nu, V));
+    return c;
+}
+template spk::LaunchCfg make_cfg<double>(const spock_problem*, int);
+template spk::LaunchCfg make_cfg<float>(const spock_problem*, int);
+
+void step_bytes_of(const spock_problem* p, int w, double out[4]) {
+    const double n = p->n, nl = p->n_nl, nlf = p->n_leaf, nx = p->nx, nu = p->nu, m = p->m;
+    const double nc = p->nc, ncN = p->ncN, ny = (double)p->ny, edges = n - 1;
+    const double aff = p->affine ? 1.0 : 0.0;
+    // prep: K per non-leaf; z (x, u, y, tau, s), eta (c, soc, y, s, leaf blocks), probabilities, P c
+    // in; y, tau, s, h0, ubar out
+    out[0] = w * (nl * nu * nx + n * nx + nl * nu + 2 * ny + 2 * edges + nl * nc + edges * (m + 2) + nl +
+                  nlf * (ncN + nx + 2) + edges + aff * n * nx + ny + 2 * edges + n * nx + nl * nu);
+    // bsweep: [Abar|B] per edge, R~^-1 per non-leaf; h0, ubar, messages in; messages, d out
+    out[1] = w * (edges * nx * m + nl * nu * nu + n * nx + nl * nu + 2 * edges * m + nl * nu);
+    // fsweep: [Abar|B] per edge; d, c in; x out
+    out[2] = w * (edges * m * nx + nl * nu + aff * n * nx + n * nx);
+    // dual: K per non-leaf; z old and new, d, eta in; u, eta out
+    out[3] = w * (nl * nx * nu + 2 * ((double)p->nz) + nl * nu + 2 * ((double)p->neta) + nl * nu);
 }
 
 static bool valid_wg(int wg) { return wg == 64 || wg == 128 || wg == 256 || wg == 512; }
@@ -876,7 +1009,16 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
         for (int k = 0; k < p->n_leaf; ++k) tasks[k] = make_int2(0, k);
         std::vector<int> path, top;
         leaf_paths(p, path, top);
+        std::vector<int4> node(p->n);
+        for (int v = 0; v < p->n; ++v)
+            node[v] = make_int4(p->n_ch[v] ? p->first_child[v] : 0, p->n_ch[v], v < p->n_nl ? p->y_off[v] : 0,
+                                p->parent[v]);
+        std::vector<int2> ntasks(p->n_ntasks, make_int2(0, -1));
+        for (int v = 0; v < p->n; ++v) ntasks[v] = make_int2(0, v);
         hipError_t e = hipMemcpy(p->d_tree, tree.data(), tree.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(p->d_node, node.data(), node.size() * sizeof(int4), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_ntasks, ntasks.data(), ntasks.size() * sizeof(int2), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(p->d_tasks, tasks.data(), tasks.size() * sizeof(int2), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(p->d_path, path.data(), path.size() * sizeof(int), hipMemcpyHostToDevice);
@@ -1256,35 +1398,31 @@ int32_t spock_prox_gconj(spock_problem* p, const double* w, double* eta_out, int
 
 extern "C++" {
 template <typename real>
-static int32_t time_steps(spock_problem* p, int steps, double* ms_total, double* ms_b, double* ms_f) {
+static int32_t time_steps(spock_problem* p, int steps, double* ms_total, double ms_k[4]) {
     DevSet<real>& s = set_of<real>(p);
-    std::vector<hipEvent_t> ev(2 * (size_t)steps + 1);
+    std::vector<hipEvent_t> ev(4 * (size_t)steps + 1);
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     HIP_TRY(hipEventRecord(ev[0], p->stream));
     for (int k = 0; k < steps; ++k) {
-        HIP_TRY(spk::launch_backward<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, s.par, 0, s.wg,
-                                           p->stream));
-        HIP_TRY(hipEventRecord(ev[2 * k + 1], p->stream));
-        HIP_TRY(spk::launch_forward<real>(s.d, p->d_tasks, p->d_ticket, p->n_leaf, s.lds_bytes, s.par, 0, s.wg,
-                                          p->stream));
-        HIP_TRY(hipEventRecord(ev[2 * k + 2], p->stream));
+        for (int ph = 0; ph < 4; ++ph) {
+            HIP_TRY(spk::launch_phase<real>(s.d, s.cfg, ph, s.par, 0, p->stream));
+            HIP_TRY(hipEventRecord(ev[4 * k + ph + 1], p->stream));
+        }
         s.par ^= 1;
     }
     HIP_TRY(hipEventSynchronize(ev.back()));
-    double tb = 0, tf = 0;
-    for (int k = 0; k < steps; ++k) {
-        float a = 0, b = 0;
-        HIP_TRY(hipEventElapsedTime(&a, ev[2 * k], ev[2 * k + 1]));
-        HIP_TRY(hipEventElapsedTime(&b, ev[2 * k + 1], ev[2 * k + 2]));
-        tb += a;
-        tf += b;
-    }
+    double t[4] = {0, 0, 0, 0};
+    for (int k = 0; k < steps; ++k)
+        for (int ph = 0; ph < 4; ++ph) {
+            float a = 0;
+            HIP_TRY(hipEventElapsedTime(&a, ev[4 * k + ph], ev[4 * k + ph + 1]));
+            t[ph] += a;
+        }
     float tot = 0;
     HIP_TRY(hipEventElapsedTime(&tot, ev[0], ev.back()));
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (ms_total) *ms_total = tot / steps;
-    if (ms_b) *ms_b = tb / steps;
-    if (ms_f) *ms_f = tf / steps;
+    for (int ph = 0; ph < 4; ++ph) ms_k[ph] = t[ph] / steps;
     int zero = 0;
     int err = 0;
     HIP_TRY(hipMemcpy(&err, p->d_err, sizeof(int), hipMemcpyDeviceToHost));
@@ -1304,19 +1442,32 @@ int32_t spock_time_steps(spock_problem* p, int32_t prec, int32_t steps, double* 
     if (r) return r;
     r = move_iterate(p, prec);
     if (r) return r;
-    return prec == SPOCK_FP64 ? time_steps<double>(p, steps, ms_total, ms_b, ms_f)
-                              : time_steps<float>(p, steps, ms_total, ms_b, ms_f);
+    double k[4];
+    r = prec == SPOCK_FP64 ? time_steps<double>(p, steps, ms_total, k) : time_steps<float>(p, steps, ms_total, k);
+    if (r) return r;
+    if (ms_b) *ms_b = k[0] + k[1];
+    if (ms_f) *ms_f = k[2] + k[3];
+    return SPOCK_OK;
+}
+
+int32_t spock_time_kernels(spock_problem* p, int32_t prec, int32_t steps, double* ms_total, double* ms_kernels) {
+    if (!p || steps < 1 || !ms_kernels) return fail(SPOCK_E_INVALID, "bad argument");
+    int32_t r = check_prec(prec);
+    if (r) return r;
+    r = move_iterate(p, prec);
+    if (r) return r;
+    return prec == SPOCK_FP64 ? time_steps<double>(p, steps, ms_total, ms_kernels)
+                              : time_steps<float>(p, steps, ms_total, ms_kernels);
 }
 
 int32_t spock_set_launch(spock_problem* p, int32_t precision, int32_t workgroup) {
     if (!p || !valid_wg(workgroup)) return fail(SPOCK_E_INVALID, "workgroup must be 64, 128, 256 or 512");
     const int bytes = precision == SPOCK_FP64 ? 8 : 4;
-    if (sweep_lds_bytes(p, workgroup, bytes) > 64 * 1024) return fail(SPOCK_E_INVALID, "LDS too large");
+    if (node_lds_bytes(p, workgroup, bytes) > 64 * 1024) return fail(SPOCK_E_INVALID, "LDS too large");
     HIP_TRY(hipStreamSynchronize(p->stream));
-    auto apply = [&](auto& s) {
-        if (s.wg == workgroup) return;
-        s.wg = workgroup;
-        s.lds_bytes = sweep_lds_bytes(p, workgroup, bytes);
+    auto apply = [&](auto& s, auto cfg) {
+        if (s.cfg.node_wg == workgroup) return;
+        s.cfg = cfg;
         for (auto& g : s.graph)
             if (g) {
                 (void)hipGraphExecDestroy(g);
@@ -1324,14 +1475,14 @@ int32_t spock_set_launch(spock_problem* p, int32_t precision, int32_t workgroup)
             }
         s.graph_steps = 0;
     };
-    if (precision == SPOCK_FP64) apply(p->s64);
-    else apply(p->s32);
+    if (precision == SPOCK_FP64) apply(p->s64, make_cfg<double>(p, workgroup));
+    else apply(p->s32, make_cfg<float>(p, workgroup));
     return SPOCK_OK;
 }
 
 int32_t spock_get_launch(const spock_problem* p, int32_t precision, int32_t* workgroup) {
     if (!p || !workgroup) return fail(SPOCK_E_INVALID, "null argument");
-    *workgroup = precision == SPOCK_FP64 ? p->s64.wg : p->s32.wg;
+    *workgroup = precision == SPOCK_FP64 ? p->s64.cfg.node_wg : p->s32.cfg.node_wg;
     return SPOCK_OK;
 }
 
@@ -1347,18 +1498,16 @@ int32_t spock_run_steps(spock_problem* p, int32_t prec, int32_t steps, int32_t s
 
 int32_t spock_step_bytes(const spock_problem* p, int32_t prec, double* bb, double* bf) {
     if (!p) return fail(SPOCK_E_INVALID, "null handle");
-    const double w = prec == SPOCK_FP64 ? 8.0 : 4.0;
-    const double n = p->n, nl = p->n_nl, nx = p->nx, nu = p->nu, m = p->m;
-    const double nz = (double)p->nz, neta = (double)p->neta;
-    const double s2 = (double)p->ny + 2.0 * (n - 1) + 1.0;  // y, tau, s, s0
-    // backward: [Abar|B]^T per edge, [K|R~^-1] per non-leaf, read z and eta,
-    // write the S2 block and d
-    const double b = (n - 1) * nx * m + nl * nu * m + nz + neta + s2 + nl * nu;
-    // forward: [Abar|B] per edge, K per non-leaf, read old z, new S2 block, d and
-    // eta, write x, u and eta
-    const double f = (n - 1) * nx * m + nl * nu * nx + nz + s2 + nl * nu + neta + (n * nx + nl * nu) + neta;
-    if (bb) *bb = w * b;
-    if (bf) *bf = w * f;
+    double k[4];
+    step_bytes_of(p, prec == SPOCK_FP64 ? 8 : 4, k);
+    if (bb) *bb = k[0] + k[1];
+    if (bf) *bf = k[2] + k[3];
+    return SPOCK_OK;
+}
+
+int32_t spock_kernel_bytes(const spock_problem* p, int32_t prec, double* bytes) {
+    if (!p || !bytes) return fail(SPOCK_E_INVALID, "null argument");
+    step_bytes_of(p, prec == SPOCK_FP64 ? 8 : 4, bytes);
     return SPOCK_OK;
 }
 

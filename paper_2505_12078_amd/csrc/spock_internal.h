@@ -12,12 +12,13 @@
 #include "spock_dev.h"
 
 namespace spk {
+// one CP step: the four launches in order (par: copy holding the iterate,
+// check: residuals of this step into res)
 template <typename real>
-hipError_t launch_step(const ProbDev<real>*, const int2*, int*, int, int, int, int, int, hipStream_t);
+hipError_t launch_step(const ProbDev<real>*, const LaunchCfg&, int par, int check, hipStream_t);
+// one of them: 0 prep, 1 bsweep, 2 fsweep, 3 dual
 template <typename real>
-hipError_t launch_backward(const ProbDev<real>*, const int2*, int*, int, int, int, int, int, hipStream_t);
-template <typename real>
-hipError_t launch_forward(const ProbDev<real>*, const int2*, int*, int, int, int, int, int, hipStream_t);
+hipError_t launch_phase(const ProbDev<real>*, const LaunchCfg&, int phase, int par, int check, hipStream_t);
 template <typename real>
 hipError_t launch_apply_L(const ProbDev<real>*, int, const real*, real*, hipStream_t);
 template <typename real>
@@ -62,8 +63,7 @@ struct DevSet {
     ProbDev<real> h;           // host mirror of the descriptor
     ProbDev<real>* d = nullptr;  // the descriptor in device memory
     int par = 0;               // which copy holds the current iterate
-    int wg = spk::kDefaultWG;  // workgroup size of the sweep kernels
-    int lds_bytes = 0;         // dynamic LDS of a sweep workgroup at that size
+    spk::LaunchCfg cfg{};      // tasks, LDS and tile classes of the four launches
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // check_every steps from parity 0 / 1
     int graph_steps = 0;
 };
@@ -98,7 +98,10 @@ struct spock_problem {
     int* d_path = nullptr;
     int* d_top = nullptr;
     int* d_ticket = nullptr;
-    int2* d_tasks = nullptr;
+    int2* d_tasks = nullptr;   // (0, leaf) per sweep wavefront
+    int4* d_node = nullptr;    // first child, children, y offset, parent per node
+    int2* d_ntasks = nullptr;  // (0, node or -1) per node wavefront
+    int n_ntasks = 0;
     unsigned long long* d_res = nullptr;
     int* d_err = nullptr;
     double* d_stash_z = nullptr;
@@ -142,17 +145,18 @@ struct spock_batch {
     ProbDev<float>* d32 = nullptr;
     int2* tasks = nullptr;
     int n_tasks = 0;
+    int2* ntasks = nullptr;
+    int n_ntasks = 0;
     int* active = nullptr;
     int* ticket = nullptr;
     int* err = nullptr;
     unsigned long long* res = nullptr;
-    int lds64 = 0, lds32 = 0;
-    int wg64 = spk::kDefaultWG, wg32 = spk::kDefaultWG;
+    spk::LaunchCfg cfg64{}, cfg32{};
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // [0] float64, [1] float32
     int graph_steps[2] = {0, 0};
     unsigned long long* h_res = nullptr;  // pinned: 2n residual slots, then n error flags
     std::vector<int> h_active;
-    double bytes_b[2] = {0, 0}, bytes_f[2] = {0, 0};
+    double bytes_k[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // algorithmic bytes per launch, [fp64 / fp32]
 };
 
 // State of one problem inside a batched iteration.
@@ -169,5 +173,14 @@ struct Member {
 template <typename real>
 int32_t batch_tick(spock_batch* b, std::vector<Member>& m, bool stall_exit);
 
-// dynamic LDS bytes of a sweep workgroup of `wg` threads for this problem
-int sweep_lds_bytes(const spock_problem* p, int wg, int real_bytes);
+// Launch configuration of one problem in one precision with node workgroups
+// of `node_wg` threads (tasks and ticket are the problem's own).
+template <typename real>
+spk::LaunchCfg make_cfg(const spock_problem* p, int node_wg);
+// Dynamic LDS bytes of a node workgroup of `node_wg` threads for this problem.
+int node_lds_bytes(const spock_problem* p, int node_wg, int real_bytes);
+// Smallest register tile class that holds a product of `need` rows per lane.
+int tile_class(int need);
+// Algorithmic bytes of the four launches of one step (prep, bsweep, fsweep,
+// dual): every matrix and vector entry the step must read or write, once.
+void step_bytes_of(const spock_problem* p, int real_bytes, double out[4]);

@@ -1,38 +1,41 @@
 // gfx950 kernels of one Chambolle-Pock (CP) step of SPOCK on a scenario tree.
 //
-// One CP step (Sec. 4.1) is two launches over the tree:
+// One CP step (Sec. 4.1), z+ = prox_{alpha f}(z - alpha L* eta) and
+// eta+ = prox_{alpha g*}(eta + alpha L(2 z+ - z)), is four launches:
 //
-//  backward  leaves -> root.  Per node: zbar = z - alpha L* eta for the node's
-//            (x, u) (adjoint of L, Sec. 4.4), the backward recursion of Alg. 2
-//            in reduced form, the S2 projection of the node's (y, tau, s) block
-//            (Sec. 4.3) and, at the root, the prox of s0.  One workgroup starts
-//            at every leaf and walks up; at a node with several children only
-//            the last child to arrive continues (atomic arrival counter), so no
-//            workgroup ever waits and the launch cannot deadlock.
-//
-//  forward   root -> leaves.  Per node: x^j = [Abar^j | B^j] [x^i; d^i] + c^j,
-//            u^j = K^j x^j + d^j (Alg. 2 forward), then every dual block the
-//            node owns: eta+ = prox_{alpha g*}(eta + alpha L(2 z+ - z)) with the
-//            S3 cone projections and Moreau's identity, and on request the
-//            residuals xi1, xi2 of Sec. 5.3.  One workgroup per leaf walks its
-//            root-to-leaf path; the first workgroup to reach a node claims and
-//            computes it, the others wait on its done flag.  A workgroup only
-//            waits on a node claimed by a running workgroup whose own inputs
-//            are already complete, so the wait always ends; a bounded spin
-//            turns an unexpected stall into an error flag instead of a hang.
+//  prep    one wavefront per node, every node at once.  zbar = z - alpha L* eta
+//          on the node's (x, u) (adjoint of L, Sec. 4.4), the S2 projection of
+//          the node's (y, tau, s) block (Sec. 4.3), the prox of s0 at the root,
+//          and the parts of the reduced S1 recursion that do not depend on the
+//          children: h0 = -xbar - K^T ubar (+ P c) and ubar.
+//  bsweep  one wavefront per leaf, leaves -> root: the sequential part of the
+//          backward recursion of Alg. 2.  g = sum of the children's messages,
+//          h = h0 + g_x, d = R~^-1 (ubar - g_u), message [Abar|B]^T h to the
+//          parent.  At a node with several children only the wavefront that
+//          arrives last continues (atomic counter), so nothing ever waits.
+//  fsweep  one wavefront per leaf, root -> leaves: x^j = [Abar^j|B^j][x^i; d^i] + c^j
+//          over the path nodes whose leftmost leaf is this leaf.  The wavefront
+//          waits once, for the node above its first one, which belongs to a
+//          wavefront that took its ticket earlier, so the wait always ends; a
+//          bounded spin turns an unexpected stall into an error flag.
+//  dual    one wavefront per node: u = K x + d, then every dual block the node
+//          owns, eta+ = prox_{alpha g*}(eta + alpha L(2 z+ - z)) with the S3
+//          cone projections and Moreau's identity, and on request the
+//          residuals xi1, xi2 of Sec. 5.3.
 //
 // Reduced S1 recursion (algebraically equal to Alg. 2, using
 // sum_j Abar^jT P^j B^j = -K^iT, which follows from the definition of K in
 // Alg. 1):  with h^j = q^j + P^j c^j and g = sum_{j in ch(i)} [Abar^j|B^j]^T h^j,
 //   q^i = -xbar^i - K^iT ubar^i + g_x,   d^i = R~^i^-1 (ubar^i - g_u),
-// and forward u^i = K^i x^i + d^i, x^j = Abar^j x^i + B^j d^i + c^j.
-// Only [Abar|B] per edge and [K | R~^-1] per non-leaf node are read online.
+// and forward u^i = K^i x^i + d^i, x^j = Abar^j x^i + B^j d^i + c^j.  Only the
+// messages and x pass between tree levels, so the sweeps carry one matrix-vector
+// product per level and everything else runs node-parallel.
 //
-// Every matrix is a contiguous row-major block per node, read once per
-// kernel with coalesced loads straight into registers (no LDS staging): the
-// transposed product (backward) maps consecutive lanes to consecutive columns;
-// the plain product (forward) maps a power-of-two lane segment to a row and
-// reduces it with cross-lane shuffles.  LDS only holds node vectors.
+// Matrix products are "column-lane": out[o] = sum_k A[k][o] v[k], each lane
+// holding its rows of one output column in registers.  The host packs every
+// node matrix in the lane order of its product (one copy per product), so a
+// wavefront reads a tile with contiguous 16-byte-per-lane loads.  LDS holds
+// node vectors only.
 
 #include <hip/hip_runtime.h>
 
@@ -45,7 +48,7 @@ constexpr int kHookWG = 256;  // workgroup size of the per-node hook kernels
 #define SPK_DEV __device__ __forceinline__
 
 // ---------------------------------------------------------------------------
-// workgroup helpers
+// wavefront and workgroup helpers
 // ---------------------------------------------------------------------------
 
 template <typename T>
@@ -90,171 +93,15 @@ SPK_DEV T block_max(T v, T* red) {
     return s;
 }
 
-// out[c] = sum_r A[r*ld + c] * (c < split ? va[r] : vb[r]),  r < R, c < C.
-// A in global memory, vectors and out in LDS.  Threads (g, c): lanes run along
-// the columns of a row, so each load instruction covers a contiguous row
-// segment; G row groups split the rows and are summed through LDS.
-template <int kWG, typename real>
-SPK_DEV void mat_t_vec(const real* __restrict__ A, int R, int C, long long ld, int split,
-                       const real* va, const real* vb, real* out, real* red) {
-    const int t = threadIdx.x;
-    for (int c0 = 0; c0 < C; c0 += kWG) {
-        const int Cc = (C - c0) < kWG ? (C - c0) : kWG;
-        const int G = kWG / Cc;
-        const int g = t / Cc, c = t - g * Cc;
-        real acc = 0;
-        if (g < G) {
-            const real* v = (c0 + c < split) ? va : vb;
-            const real* a = A + c0 + c;
-#pragma unroll 4
-            for (int r = g; r < R; r += G) acc += a[(long long)r * ld] * v[r];
-        }
-        __syncthreads();
-        red[t] = acc;
-        __syncthreads();
-        if (t < Cc) {
-            real s = 0;
-            for (int k = 0; k < G; ++k) s += red[k * Cc + t];
-            out[c0 + t] = s;
-        }
-        __syncthreads();
-    }
+// LDS exchange between lanes of one wavefront: the hardware keeps a
+// wavefront's LDS accesses in order; this keeps the compiler from moving them.
+SPK_DEV void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// out[r] = sum_c A[r*ld + c] * v[c],  r < R, c < C.  A power-of-two segment of
-// W lanes (W <= 64) owns a row: lanes stride the row, then reduce by xor
-// shuffles inside the segment.
-template <int kWG, typename real>
-SPK_DEV void mat_vec(const real* __restrict__ A, int R, int C, long long ld, const real* v,
-                     real* out) {
-    int W = 1;
-    while (W < C && W < 64) W <<= 1;
-    const int t = threadIdx.x;
-    const int nseg = kWG / W;
-    const int seg = t / W, k = t - seg * W;
-    for (int r0 = 0; r0 < R; r0 += nseg) {
-        const int r = r0 + seg;
-        real acc = 0;
-        if (r < R) {
-            const real* a = A + (long long)r * ld;
-#pragma unroll 4
-            for (int c = k; c < C; c += W) acc += a[c] * v[c];
-        }
-        for (int o = W >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, W);
-        if (k == 0 && r < R) out[r] = acc;
-    }
-    __syncthreads();
-}
-
-// Register-prefetched forms of the two products.  The loads of a node's
-// matrices do not depend on the sweep's vectors, so they are issued as soon as
-// the node is known and consumed after the vectors are ready: one memory
-// latency per node instead of one per batch of dependent loads.
-
-// Transposed product, thread (g, c) with G = kWG / C row groups (needs C <= kWG):
-// rows g + i G for i < RB live in registers, any further rows are read directly.
-template <typename real, int RB>
-struct TTile {
-    real a[RB];
-};
-
-template <int kWG, typename real, int RB>
-SPK_DEV void t_load(TTile<real, RB>& T, const real* __restrict__ A, int R, int C, long long ld) {
-    const int t = threadIdx.x, G = kWG / C, g = t / C, c = t - g * C;
-#pragma unroll
-    for (int i = 0; i < RB; ++i) {
-        const int r = g + i * G;
-        T.a[i] = (g < G && r < R) ? A[(long long)r * ld + c] : real(0);
-    }
-}
-
-// out[c] = sum_r A[r][c] (c < split ? va[r] : vb[r]) from a loaded tile.
-template <int kWG, typename real, int RB>
-SPK_DEV void t_apply(const TTile<real, RB>& T, const real* __restrict__ A, int R, int C, long long ld, int split,
-                     const real* va, const real* vb, real* out, real* red) {
-    const int t = threadIdx.x, G = kWG / C, g = t / C, c = t - g * C;
-    real acc = 0;
-    if (g < G) {
-        const real* v = c < split ? va : vb;
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-            const int r = g + i * G;
-            if (r < R) acc += T.a[i] * v[r];
-        }
-        for (int r = g + RB * G; r < R; r += G) acc += A[(long long)r * ld + c] * v[r];
-    }
-    __syncthreads();
-    red[t] = acc;
-    __syncthreads();
-    if (t < C) {
-        real s = 0;
-        for (int k = 0; k < G; ++k) s += red[k * C + t];
-        out[t] = s;
-    }
-    __syncthreads();
-}
-
-// Plain product, a power-of-two segment of W lanes per row: rows seg + i nseg
-// for i < RB and columns k + j W for j < CB live in registers.
-template <typename real, int RB, int CB>
-struct PTile {
-    real a[RB][CB];
-};
-
-SPK_DEV int seg_width(int C) {
-    int W = 1;
-    while (W < C && W < 64) W <<= 1;
-    return W;
-}
-
-template <int kWG, typename real, int RB, int CB>
-SPK_DEV void p_load(PTile<real, RB, CB>& T, const real* __restrict__ A, int R, int C, long long ld) {
-    const int W = seg_width(C), t = threadIdx.x, nseg = kWG / W, seg = t / W, k = t - seg * W;
-#pragma unroll
-    for (int i = 0; i < RB; ++i) {
-        const int r = seg + i * nseg;
-#pragma unroll
-        for (int j = 0; j < CB; ++j) {
-            const int c = k + j * W;
-            T.a[i][j] = (r < R && c < C) ? A[(long long)r * ld + c] : real(0);
-        }
-    }
-}
-
-template <int kWG, typename real, int RB, int CB>
-SPK_DEV void p_apply(const PTile<real, RB, CB>& T, const real* __restrict__ A, int R, int C, long long ld,
-                     const real* v, real* out) {
-    const int W = seg_width(C), t = threadIdx.x, nseg = kWG / W, seg = t / W, k = t - seg * W;
-#pragma unroll
-    for (int i = 0; i < RB; ++i) {
-        if (i * nseg >= R) break;  // uniform over the workgroup
-        const int r = seg + i * nseg;
-        real acc = 0;
-        if (r < R) {
-#pragma unroll
-            for (int j = 0; j < CB; ++j)
-                if (k + j * W < C) acc += T.a[i][j] * v[k + j * W];
-            for (int c = k + CB * W; c < C; c += W) acc += A[(long long)r * ld + c] * v[c];
-        }
-        for (int o = W >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, W);
-        if (k == 0 && r < R) out[r] = acc;
-    }
-    for (int r0 = RB * nseg; r0 < R; r0 += nseg) {
-        const int r = r0 + seg;
-        real acc = 0;
-        if (r < R)
-            for (int c = k; c < C; c += W) acc += A[(long long)r * ld + c] * v[c];
-        for (int o = W >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, W);
-        if (k == 0 && r < R) out[r] = acc;
-    }
-    __syncthreads();
-}
-
-// Register tile sizes (rows per thread kept in registers).
-constexpr int kRBM = 20;  // [Abar|B]^T in the backward sweep
-constexpr int kRBK = 12;  // [K|R~^-1]^T in the backward sweep
-constexpr int kRBP = 16;  // [Abar|B] rows in the forward sweep (two column chunks)
-constexpr int kRBQ = 8;   // K rows in the forward sweep
+SPK_DEV int lane_id() { return (int)(threadIdx.x & 63); }
 
 // Exchange between workgroups of one launch.  A value that another workgroup
 // reads while the launch runs is stored and loaded at device scope: the store
@@ -265,13 +112,25 @@ constexpr int kRBQ = 8;   // K rows in the forward sweep
 // same job, but at device scope they write back or invalidate the whole L2 of
 // the XCD, and that costs tens of microseconds per node when many workgroups
 // have stores in flight.
+// Global-address-space views: accesses through them compile to global (not
+// flat) memory instructions, which only count against the vector memory
+// counter, so waits for them stay precise.
+template <typename T>
+SPK_DEV __attribute__((address_space(1))) T* gm(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+SPK_DEV const __attribute__((address_space(1))) T* gm(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+
 template <typename real>
 SPK_DEV void st_dev(real* p, real v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gm(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename real>
 SPK_DEV real ld_dev(const real* p) {
-    return __hip_atomic_load(const_cast<real*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(gm(const_cast<real*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Every store this wavefront issued has completed (s_waitcnt vmcnt(0)); the
 // workgroup fence keeps the compiler from sinking stores below it.
@@ -297,92 +156,12 @@ SPK_DEV void record_max(unsigned long long* slot, real v) {
     atomicMax(slot, (unsigned long long)__double_as_longlong(d));
 }
 
-// ---------------------------------------------------------------------------
-// node input staging
-// ---------------------------------------------------------------------------
-
-// A node's vector inputs come from several arrays (z, eta, d, messages, ...).
-// They are gathered into LDS in one pass: thread 0 writes a table of
-// (source, length) segments, then every thread issues its share of the loads
-// back to back before storing any of them, so a node costs one memory round
-// trip for its vectors (issued together with its matrix tiles).
-constexpr int kMaxSeg = 16;
-constexpr int kGatherE = 4;  // loads in flight per thread per pass
-
-template <typename real>
-struct SegTable {
-    const real* src[kMaxSeg];
-    int off[kMaxSeg + 1];
-    int n;
-};
-
-template <typename real>
-SPK_DEV void seg_reset(SegTable<real>& T) {
-    T.n = 0;
-    T.off[0] = 0;
-}
-
-template <typename real>
-SPK_DEV void seg_add(SegTable<real>& T, const real* src, int len) {
-    T.src[T.n] = src;
-    T.off[T.n + 1] = T.off[T.n] + len;
-    T.n++;
-}
-
-template <int kWG, typename real>
-SPK_DEV void seg_gather(const SegTable<real>& T, real* st, bool dev = false) {
-    const int nseg = T.n;
-    const int total = T.off[nseg];
-    int off[kMaxSeg + 1];  // segment ends in registers: no dependent LDS reads per element
-#pragma unroll
-    for (int q = 0; q <= kMaxSeg; ++q) off[q] = q <= nseg ? T.off[q] : total;
-    for (int base = 0; base < total; base += kGatherE * kWG) {
-        real v[kGatherE];
-#pragma unroll
-        for (int j = 0; j < kGatherE; ++j) {
-            const int e = base + j * kWG + (int)threadIdx.x;
-            v[j] = 0;
-            if (e < total) {
-                int s = 0;
-#pragma unroll
-                for (int q = 1; q <= kMaxSeg; ++q) s += e >= off[q];
-                const real* src = T.src[s] + (e - T.off[s]);
-                v[j] = dev ? ld_dev(src) : *src;
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < kGatherE; ++j) {
-            const int e = base + j * kWG + (int)threadIdx.x;
-            if (e < total) st[e] = v[j];
-        }
-    }
-}
-
 // Per-problem diagonal data staged once per workgroup.
 template <typename real>
 struct Consts {
     const real *qh, *rh, *qnh, *gx, *gu, *gb, *gxN, *gbN, *lo, *hi, *loN, *hiN;
 };
 
-SPK_DEV int consts_elems(int nx, int nu) { return 10 * nx + 4 * nu; }
-
-template <typename real>
-SPK_DEV void consts_table(const ProbDev<real>* __restrict__ P, SegTable<real>& T) {
-    const int nx = P->nx, nu = P->nu, m = P->m;
-    seg_reset(T);
-    seg_add(T, P->qh, nx);
-    seg_add(T, P->rh, nu);
-    seg_add(T, P->qnh, nx);
-    seg_add(T, P->gx, nx);
-    seg_add(T, P->gu, nu);
-    seg_add(T, P->gb, nx);
-    seg_add(T, P->gxN, nx);
-    seg_add(T, P->gbN, nx);
-    seg_add(T, P->lo, m);
-    seg_add(T, P->hi, m);
-    seg_add(T, P->loN, nx);
-    seg_add(T, P->hiN, nx);
-}
 
 template <typename real>
 SPK_DEV Consts<real> consts_at(const real* c, int nx, int nu) {
@@ -403,277 +182,291 @@ SPK_DEV Consts<real> consts_at(const real* c, int nx, int nu) {
     return C;
 }
 
-// Root-to-leaf path nodes, their child counts and first children (LDS).
-template <int kWG, typename real>
-SPK_DEV void load_path(const ProbDev<real>* __restrict__ P, int leaf, int from, int* s_node, int* s_nch,
-                       int* s_fc) {
-    const int N = P->N;
-    const int* path = P->path + (long long)leaf * (N + 1);
-    for (int q = from + (int)threadIdx.x; q <= N; q += kWG) {
-        const int v = path[q];
-        s_node[q] = v;
-        s_nch[q] = v < P->n_nl ? P->n_ch[v] : 0;
-        s_fc[q] = v < P->n_nl ? P->first_child[v] : 0;
+// ---------------------------------------------------------------------------
+// input staging
+// ---------------------------------------------------------------------------
+
+// A node's vector inputs come from several arrays (z, eta, probabilities, ...).
+// They are copied into LDS with global-to-LDS loads (no registers involved):
+// every wavefront issues all of its copies back to back and waits once, so a
+// node costs one memory round trip for its vectors, overlapped with the loads
+// of its matrix tile.  Slots have fixed positions (uniform values); an empty
+// slot has length 0.
+template <typename real, int NS>
+struct Stage {
+    const real* src[NS];
+    int len[NS];
+    SPK_DEV void set(int q, const real* p, int n) {
+        src[q] = p;
+        len[q] = n;
+    }
+};
+
+// Copy n dwords from global memory to LDS, one wavefront; dst uniform.
+SPK_DEV void lds_copy(const void* src, void* dst, int ndw) {
+    const int lane = lane_id();
+    const unsigned* s = static_cast<const unsigned*>(src);
+    unsigned* d = static_cast<unsigned*>(dst);
+    for (int c = 0; c < ndw; c += 64)
+        if (c + lane < ndw)
+            __builtin_amdgcn_global_load_lds(s + c + lane, (__attribute__((address_space(3))) void*)(d + c), 4, 0, 0);
+}
+
+// Wait for this wavefront's outstanding global loads (global-to-LDS included).
+SPK_DEV void wait_loads() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    wave_sync();
+}
+
+// Copy the slots back to back into st (one wavefront); off[q] receives the
+// start of slot q.  Completion needs wait_loads().
+template <typename real, int NS>
+SPK_DEV void gather(const Stage<real, NS>& S, real* st, int* off) {
+    int o = 0;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        off[q] = o;
+        if (S.len[q] > 0) lds_copy(S.src[q], st + o, S.len[q] * (int)(sizeof(real) / 4));
+        o += S.len[q];
     }
 }
 
-// ---------------------------------------------------------------------------
-// backward sweep
-// ---------------------------------------------------------------------------
-
-template <typename real, int kWG>
-__global__ __launch_bounds__(kWG) void k_backward(const ProbDev<real>* __restrict__ probs,
-                                                  const int2* __restrict__ tasks, int* __restrict__ ticket,
-                                                  int par, int check) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int s_node[kMaxDepth], s_nch[kMaxDepth], s_fc[kMaxDepth];
-    __shared__ SegTable<real> s_seg;
-    __shared__ int s_last;
-    real* sm = reinterpret_cast<real*>(smem_raw);
-    const int2 tk = tasks[blockIdx.x];
-    const ProbDev<real>* __restrict__ P = probs + tk.x;
-    if (*P->active == 0) return;
-    const int nx = P->nx, nu = P->nu, m = P->m, N = P->N, nc = P->nc, ncN = P->ncN, nbox = P->nbox;
-    const int n_nl = P->n_nl;
-    const real alpha = P->alpha;
-    const real* __restrict__ zin = P->z[par];
-    const real* __restrict__ ein = P->eta[par];
-    real* __restrict__ zout = P->z[par ^ 1];
-    const int t = threadIdx.x;
-
-    real* red = sm;
-    real* cst = red + kWG;
-    real* st = cst + consts_elems(nx, nu);
-    real* xb = st + stage_elems(nx, nu, nc, P->max_ch);  // xbar, then h = q + P c
-    real* ub = xb + nx;                                  // ubar
-    real* g = ub + nu;                                   // sum of children messages
-    real* w2 = g + m;                                    // ubar - g_u
-    real* o = w2 + nu;                                   // product outputs
-    real* lam = o + m;                                   // S2 multipliers
-
-    load_path<kWG>(P, tk.y, 0, s_node, s_nch, s_fc);
-    if (t == 0) consts_table(P, s_seg);
+// The 12 diagonal data arrays of a problem, staged by the whole workgroup.
+template <typename real>
+SPK_DEV void stage_consts(const ProbDev<real>* __restrict__ P, real* cst) {
+    const int nx = P->nx, nu = P->nu, m = P->m;
+    Stage<real, 12> S{};
+    S.set(0, P->qh, nx);
+    S.set(1, P->rh, nu);
+    S.set(2, P->qnh, nx);
+    S.set(3, P->gx, nx);
+    S.set(4, P->gu, nu);
+    S.set(5, P->gb, nx);
+    S.set(6, P->gxN, nx);
+    S.set(7, P->gbN, nx);
+    S.set(8, P->lo, m);
+    S.set(9, P->hi, m);
+    S.set(10, P->loN, nx);
+    S.set(11, P->hiN, nx);
+    // wavefront w copies the slots q = w, w + waves, ...
+    const int waves = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6);
+    int o = 0;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        if (q % waves == w) lds_copy(S.src[q], cst + o, S.len[q] * (int)(sizeof(real) / 4));
+        o += S.len[q];
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's copies are in LDS
     __syncthreads();
-    seg_gather<kWG>(s_seg, cst);
-    const Consts<real> C = consts_at<real>(cst, nx, nu);
-    const bool tiles = m <= kWG;  // one column tile: register-prefetched products
-
-    // ---- leaf: q = -xbar, message [Abar|B]^T (q + P c) ----
-    int j = s_node[N];
-    {
-        TTile<real, kRBM> TM;
-        if (tiles) t_load<kWG>(TM, P->M + j * P->M_stride, nx, m, m);
-        const long long lf = j - n_nl;
-        __syncthreads();  // constants gathered, table free
-        if (t == 0) {
-            seg_reset(s_seg);
-            seg_add(s_seg, zin + P->z_x + (long long)j * nx, nx);
-            seg_add(s_seg, ein + P->e_cN + lf * ncN, ncN);
-            seg_add(s_seg, ein + P->e_socN + lf * (nx + 2), nx + 2);
-            if (P->affine) seg_add(s_seg, P->Pc + (long long)j * nx, nx);
-            P->flag[j] = 0;
-        }
-        __syncthreads();
-        seg_gather<kWG>(s_seg, st);
-        __syncthreads();
-        const real* sx = st;
-        const real* sc = sx + nx;
-        const real* ss = sc + ncN;
-        const real* spc = ss + nx + 2;
-        for (int k = t; k < nx; k += kWG) {
-            real lt = C.gxN[k] * sc[k] + C.qnh[k] * ss[k];
-            if (P->has_ballN) lt += C.gbN[k] * sc[nx + k];
-            real h = -(sx[k] - alpha * lt);
-            if (P->affine) h += spc[k];
-            xb[k] = h;
-        }
-        __syncthreads();
-        if (tiles) t_apply<kWG>(TM, P->M + j * P->M_stride, nx, m, m, m, xb, xb, o, red);
-        else mat_t_vec<kWG>(P->M + j * P->M_stride, nx, m, m, m, xb, xb, o, red);
-    }
-
-    // ---- walk up ----
-    for (int lev = N - 1; lev >= 0; --lev) {
-        const int i = s_node[lev];
-        const int k = s_nch[lev], fc = s_fc[lev];
-        if (k > 1) {
-            for (int c = t; c < m; c += kWG) st_dev(P->e + (long long)j * m + c, o[c]);
-            // every wave completes its own message stores before the arrival
-            // is counted (a barrier alone does not wait for them)
-            drain_stores();
-            __syncthreads();
-            if (t == 0) {
-                const int prev =
-                    __hip_atomic_fetch_add(&P->cnt[i], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const int last = (prev == k - 1);
-                if (last) P->cnt[i] = 0;  // the next launch reuses the counter
-                s_last = last;
-            }
-            __syncthreads();
-            if (!s_last) return;
-        }
-        TTile<real, kRBK> TK;
-        TTile<real, kRBM> TM;
-        if (tiles) {
-            t_load<kWG>(TK, P->KR + i * P->KR_stride, nu, m, m);
-            if (i > 0) t_load<kWG>(TM, P->M + i * P->M_stride, nx, m, m);
-        }
-        const bool leafkids = fc >= n_nl;
-        const bool sk = k <= kStageKids;  // per-child inputs staged, else read in place
-        const int kk = sk ? k : 0;
-        const int cs_len = leafkids ? kk * (nx + 2) : kk;
-        const long long yo = P->y_off[i];
-        // staged inputs of node i (offsets into st)
-        const int oX = 0, oU = oX + nx, oEC = oU + nu, oSOC = oEC + nc, oEY = oSOC + kk * (m + 2);
-        const int oES = oEY + (sk ? 2 * k + 1 : 0), oZY = oES + 1, oZT = oZY + (sk ? 2 * k + 1 : 0);
-        const int oZS = oZT + kk, oCS = oZS + kk, oP = oCS + cs_len, oMSG = oP + kk;
-        const int oPC = oMSG + (k > 1 ? kk * m : 0);
-        const real* g_soc = ein + P->e_soc + (long long)(fc - 1) * (m + 2);
-        const real* g_cs = leafkids ? ein + P->e_socN + (long long)(fc - n_nl) * (nx + 2) : ein + P->e_s + fc;
-        if (t == 0) {
-            seg_reset(s_seg);
-            seg_add(s_seg, zin + P->z_x + (long long)i * nx, nx);
-            seg_add(s_seg, zin + P->z_u + (long long)i * nu, nu);
-            seg_add(s_seg, ein + P->e_c + (long long)i * nc, nc);
-            if (sk) {
-                seg_add(s_seg, g_soc, k * (m + 2));
-                seg_add(s_seg, ein + P->e_y + yo, 2 * k + 1);
-            }
-            seg_add(s_seg, ein + P->e_s + i, 1);
-            if (sk) {
-                seg_add(s_seg, zin + P->z_y + yo, 2 * k + 1);
-                seg_add(s_seg, zin + P->z_tau + fc - 1, k);
-                seg_add(s_seg, zin + P->z_s + fc - 1, k);
-                seg_add(s_seg, g_cs, cs_len);
-                seg_add(s_seg, P->prob + fc, k);
-                if (k > 1) seg_add(s_seg, P->e + (long long)fc * m, k * m);
-            }
-            if (P->affine && i > 0) seg_add(s_seg, P->Pc + (long long)i * nx, nx);
-            P->flag[i] = 0;
-        }
-        __syncthreads();
-        seg_gather<kWG>(s_seg, st, k > 1);  // messages: device scope
-        __syncthreads();
-        // per-child inputs: staged copies or the arrays themselves
-        const real* soc = sk ? st + oSOC : g_soc;
-        const real* ey = sk ? st + oEY : ein + P->e_y + yo;
-        const real* zy = sk ? st + oZY : zin + P->z_y + yo;
-        const real* zt = sk ? st + oZT : zin + P->z_tau + fc - 1;
-        const real* zs = sk ? st + oZS : zin + P->z_s + fc - 1;
-        const real* cs = sk ? st + oCS : g_cs;
-        const real* pr = sk ? st + oP : P->prob + fc;
-        const real* msg = sk ? st + oMSG : P->e + (long long)fc * m;
-
-        for (int c = t; c < m; c += kWG) {
-            if (k > 1) {
-                real s = 0;
-                if (sk) {
-                    for (int q = 0; q < k; ++q) s += msg[q * m + c];
-                } else {
-                    for (int q = 0; q < k; ++q) s += ld_dev(msg + q * m + c);
-                }
-                g[c] = s;
-            } else {
-                g[c] = o[c];
-            }
-        }
-        // zbar for (x^i, u^i): L* gathers the constraint rows and the SOC rows of
-        // every child edge (Sec. 4.4)
-        for (int r = t; r < nx; r += kWG) {
-            real s = 0;
-            for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + r];
-            real lt = C.gx[r] * st[oEC + r] + C.qh[r] * s;
-            if (P->has_ball) lt += C.gb[r] * st[oEC + nbox + r];
-            xb[r] = st[oX + r] - alpha * lt;
-        }
-        for (int r = t; r < nu; r += kWG) {
-            real s = 0, gu = 0;
-            for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + nx + r];
-            if (k > 1) {
-                if (sk) {
-                    for (int q = 0; q < k; ++q) gu += msg[q * m + nx + r];
-                } else {
-                    for (int q = 0; q < k; ++q) gu += ld_dev(msg + q * m + nx + r);
-                }
-            } else {
-                gu = o[nx + r];
-            }
-            const real lt = C.gu[r] * st[oEC + nx + r] + C.rh[r] * s;
-            const real u = st[oU + r] - alpha * lt;
-            ub[r] = u;
-            w2[r] = u - gu;
-        }
-        // S2 projection (Sec. 4.3) of node i's block (y^i, tau^[i], s^[i]) after
-        // the z - alpha L* eta shift, on the last wavefront.  Kernel of
-        // G = [E^T, -I, -I] with E = [gamma I; -I; 1^T] (AV@R, Sec. 3.3);
-        // G G^T = (gamma^2 + 3) I + 1 1^T, so with rho = G w the multiplier is
-        // lambda = (rho - (1^T rho / (c + n)) 1) / c, c = gamma^2 + 3
-        // (Sherman-Morrison), and w - G^T lambda is the projection.
-        if ((t >> 6) == (kWG / 64) - 1) {
-            const int lane = t & 63;
-            const real gam = P->gamma[i], cc = gam * gam + real(3);
-            const real es = st[oES];
-            const real yb3 = zy[2 * k] - alpha * (ey[2 * k] - es);
-            auto shifted = [&](int c, real& yb1, real& yb2, real& tb, real& sb) {
-                yb1 = zy[c] - alpha * (ey[c] - pr[c] * es);
-                yb2 = zy[k + c] - alpha * ey[k + c];
-                tb = zt[c] - alpha * real(0.5) * (soc[c * (m + 2) + m] + soc[c * (m + 2) + m + 1]);
-                const real lts = leafkids ? real(0.5) * (cs[c * (nx + 2) + nx] + cs[c * (nx + 2) + nx + 1]) : cs[c];
-                sb = zs[c] - alpha * lts;
-            };
-            real rsum = 0;
-            for (int c = lane; c < k; c += 64) {
-                real yb1, yb2, tb, sb;
-                shifted(c, yb1, yb2, tb, sb);
-                const real rho = gam * yb1 - yb2 + yb3 - tb - sb;
-                lam[c] = rho;
-                rsum += rho;
-            }
-            rsum = wave_sum(rsum);
-            real lsum = 0;
-            for (int c = lane; c < k; c += 64) {
-                real yb1, yb2, tb, sb;
-                shifted(c, yb1, yb2, tb, sb);
-                const real l = (lam[c] - rsum / (cc + real(k))) / cc;
-                lsum += l;
-                zout[P->z_y + yo + c] = yb1 - gam * l;
-                zout[P->z_y + yo + k + c] = yb2 + l;
-                zout[P->z_tau + fc + c - 1] = tb + l;
-                zout[P->z_s + fc + c - 1] = sb + l;
-            }
-            lsum = wave_sum(lsum);
-            if (lane == 0) zout[P->z_y + yo + 2 * k] = yb3 - lsum;
-        }
-        __syncthreads();
-        // [K^T ubar ; R~^-1 (ubar - g_u)] in one pass over [K | R~^-1]
-        if (tiles) t_apply<kWG>(TK, P->KR + i * P->KR_stride, nu, m, m, nx, ub, w2, o, red);
-        else mat_t_vec<kWG>(P->KR + i * P->KR_stride, nu, m, m, nx, ub, w2, o, red);
-        for (int r = t; r < nx; r += kWG) {
-            real h = -xb[r] - o[r] + g[r];
-            if (P->affine && i > 0) h += st[oPC + r];
-            xb[r] = h;
-        }
-        for (int r = t; r < nu; r += kWG) P->d[(long long)i * nu + r] = o[nx + r];
-        if (i == 0) {
-            if (t == 0) {
-                zout[0] = zin[0] - alpha * st[oES] - alpha;  // prox of alpha * s0
-                ticket[0] = 0;                              // forward tickets restart
-                if (check) {
-                    P->res[0] = 0ull;
-                    P->res[1] = 0ull;
-                }
-            }
-            return;
-        }
-        __syncthreads();
-        if (tiles) t_apply<kWG>(TM, P->M + i * P->M_stride, nx, m, m, m, xb, xb, o, red);
-        else mat_t_vec<kWG>(P->M + i * P->M_stride, nx, m, m, m, xb, xb, o, red);
-        j = i;
-    }
 }
 
 // ---------------------------------------------------------------------------
-// forward sweep
+// column-lane products (one wavefront)
+// ---------------------------------------------------------------------------
+
+// out[o] = sum_{k<K} A[k][o] v[k] for o < O <= 128.  Block 1 covers the
+// columns 0..W1-1 (W1 = min(O, 64)) with G1 = 64 / W1 row groups: lane
+// l = g W1 + c keeps rows g, g + G1, ... of column c.  Block 2 covers the
+// columns 64..O-1 the same way with G2 = 64 / (O - 64).  The host stores every
+// such matrix pre-packed in exactly that lane order (tile_pack), so a lane
+// reads its rows with 16-byte loads at fixed offsets and a wavefront's load
+// covers 1 KiB of contiguous memory.  Group partial sums meet in LDS and are
+// added in group order (deterministic).
+struct ColShape {
+    int K, O, W1, G1, W2, G2, rows1, rows2;  // rows per lane, padded to the vector width
+};
+
+template <typename real>
+SPK_DEV ColShape col_shape(int K, int O) {
+    ColShape s;
+    s.K = K;
+    s.O = O;
+    s.W1 = O < 64 ? O : 64;
+    s.G1 = 64 / s.W1;
+    s.W2 = O > 64 ? O - 64 : 0;
+    s.G2 = s.W2 > 0 ? 64 / s.W2 : 1;
+    s.rows1 = tile_rows(K, s.G1, tile_vec<real>());
+    s.rows2 = s.W2 > 0 ? tile_rows(K, s.G2, tile_vec<real>()) : 0;
+    return s;
+}
+
+template <typename real, int R>
+struct ColTile {
+    real a[R];
+    real b[R / 4];
+};
+
+// 16 bytes as tile_vec<real>() values
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <typename real>
+SPK_DEV void unpack16(u32x4 u, real* dst);
+template <>
+SPK_DEV void unpack16<float>(u32x4 u, float* dst) {
+    dst[0] = __uint_as_float(u.x);
+    dst[1] = __uint_as_float(u.y);
+    dst[2] = __uint_as_float(u.z);
+    dst[3] = __uint_as_float(u.w);
+}
+template <>
+SPK_DEV void unpack16<double>(u32x4 u, double* dst) {
+    dst[0] = __hiloint2double((int)u.y, (int)u.x);
+    dst[1] = __hiloint2double((int)u.w, (int)u.z);
+}
+
+// Every lane loads the full register class unconditionally at fixed offsets:
+// rows past the tile's own read whatever follows it (the next node's tile, or
+// the zero padding the host leaves after every tile array), and col_apply
+// masks every row past K.  With no conditional loads the compiler can count
+// the loads in flight, so a later level's prefetch does not force a wait for
+// everything.
+template <typename real, int R>
+SPK_DEV void col_load(ColTile<real, R>& T, const real* __restrict__ tile, const ColShape& s) {
+    constexpr int V = 16 / (int)sizeof(real);
+    const __attribute__((address_space(1))) u32x4* p =
+        (const __attribute__((address_space(1))) u32x4*)tile + lane_id();
+#pragma unroll
+    for (int q = 0; q < R / V; ++q) {
+        const u32x4 u = p[q * 64];
+        unpack16<real>(u, T.a + q * V);
+    }
+    // block 2 (when there is none, the rows after block 1, unused)
+    p += (s.rows1 / V) * 64;
+#pragma unroll
+    for (int q = 0; q < R / 4 / V; ++q) {
+        const u32x4 u = p[q * 64];
+        unpack16<real>(u, T.b + q * V);
+    }
+}
+
+// 16 bytes of LDS as tile_vec<real>() values
+template <typename real>
+SPK_DEV void lds16(const real* p, real* dst) {
+    const u32x4 u = *reinterpret_cast<const u32x4*>(p);
+    unpack16<real>(u, dst);
+}
+
+// v: K entries (LDS, 16-byte aligned), out: O entries (LDS), red: kRed
+// entries of scratch (LDS).  Rows past the tile's own (rows1 / rows2) hold
+// data of whatever follows the tile and are masked; inside them, entries of
+// rows past K and of idle lanes are zero.  kPadded: v is zero from K up to R
+// entries, so the one-group block needs no masks (rows past the tile meet
+// zeros of v; tile data is finite).  The v values a lane needs are read into
+// registers before the products, so the LDS reads issue back to back.
+template <bool kPadded, typename real, int R>
+SPK_DEV void col_apply(const ColTile<real, R>& T, const ColShape& s, const real* v, real* out, real* red) {
+    constexpr int V = 16 / (int)sizeof(real);
+    const int lane = lane_id();
+    const int km = s.K - 1;
+    real acc = 0;
+    if (s.G1 == 1) {
+        // every lane needs v[i]: broadcast reads
+        real x[R];
+        if constexpr (kPadded) {
+#pragma unroll
+            for (int i = 0; i < R; i += V) lds16(v + i, x + i);  // V rows per read
+#pragma unroll
+            for (int i = 0; i < R; ++i) acc += T.a[i] * x[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < R; ++i) x[i] = v[i < km ? i : km];
+#pragma unroll
+            for (int i = 0; i < R; ++i) acc += (i < s.rows1 ? T.a[i] : real(0)) * x[i];
+        }
+    } else {
+        const int g1 = lane / s.W1;
+        real x[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int k = g1 + i * s.G1;
+            x[i] = v[k < km ? k : km];
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) acc += (i < s.rows1 ? T.a[i] : real(0)) * x[i];
+    }
+    real acc2 = 0;
+    if (s.W2 > 0) {
+        const int g2 = lane / s.W2;
+        real x[R / 4];
+#pragma unroll
+        for (int i = 0; i < R / 4; ++i) {
+            const int k = g2 + i * s.G2;
+            x[i] = v[k < km ? k : km];
+        }
+#pragma unroll
+        for (int i = 0; i < R / 4; ++i) acc2 += (i < s.rows2 ? T.b[i] : real(0)) * x[i];
+    }
+    red[lane] = acc;
+    red[64 + lane] = acc2;
+    wave_sync();
+    if (lane < s.W1) {
+        real t = 0;
+        for (int g = 0; g < s.G1; ++g) t += red[g * s.W1 + lane];
+        out[lane] = t;
+    }
+    if (lane < s.W2) {
+        real t = 0;
+        for (int g = 0; g < s.G2; ++g) t += red[64 + g * s.W2 + lane];
+        out[64 + lane] = t;
+    }
+    wave_sync();
+}
+
+// The same product read from the packed tile in global memory (shapes beyond
+// the register class).
+template <typename real>
+SPK_DEV void col_direct(const real* __restrict__ tile, const ColShape& s, const real* v, real* out, real* red) {
+    constexpr int V = 16 / (int)sizeof(real);
+    const int lane = lane_id();
+    auto part = [&](const real* blk, int rows, int W, int G) {
+        const int g = lane / W;
+        real acc = 0;
+#pragma unroll 4
+        for (int i = 0; i < rows; ++i) {
+            const int k = g + i * G;
+            if (k < s.K) acc += blk[((i / V) * 64 + lane) * V + (i % V)] * v[k];
+        }
+        return acc;
+    };
+    red[lane] = part(tile, s.rows1, s.W1, s.G1);
+    red[64 + lane] = s.W2 > 0 ? part(tile + (long long)s.rows1 * 64, s.rows2, s.W2, s.G2) : real(0);
+    wave_sync();
+    if (lane < s.W1) {
+        real t = 0;
+        for (int g = 0; g < s.G1; ++g) t += red[g * s.W1 + lane];
+        out[lane] = t;
+    }
+    if (lane < s.W2) {
+        real t = 0;
+        for (int g = 0; g < s.G2; ++g) t += red[64 + g * s.W2 + lane];
+        out[64 + lane] = t;
+    }
+    wave_sync();
+}
+
+// A tile of class R if the shape fits it, else the product runs from the
+// packed tile in global memory.
+template <typename real, int R>
+struct ColProd {
+    ColTile<real, R> T;
+    ColShape s;
+    const real* tile;
+    bool fit;
+    SPK_DEV void load(const real* t, const ColShape& sh) {
+        tile = t;
+        s = sh;
+        fit = sh.rows1 <= R && sh.rows2 <= R / 4;
+        col_load(T, t, sh);  // unconditional (see col_load); unused when !fit
+    }
+    // kPadded: v is zero from K up to kVecPad entries (see col_apply)
+    template <bool kPadded = false>
+    SPK_DEV void apply(const real* v, real* out, real* red) const {
+        if (fit) col_apply<kPadded>(T, s, v, out, red);
+        else col_direct(tile, s, v, out, red);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// dual blocks
 // ---------------------------------------------------------------------------
 
 // eta+ = prox_{alpha g*}(etabar) for a box row: etabar - clamp(etabar, alpha lo, alpha hi)
@@ -760,7 +553,7 @@ SPK_DEV void fwd_block_c(const ProbDev<real>* __restrict__ P, int v, const real*
         V.dblk[r] = de;
     }
     if (check) {
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         for (int r = lane; r < nx; r += 64) {
             real s = V.C.gx[r] * V.dblk[r];
             if (P->has_ball) s += V.C.gb[r] * V.dblk[nbox + r];
@@ -840,7 +633,7 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, const rea
         if (r <= m) nw2 += eb * eb;
     }
     nw2 = wave_sum(nw2);
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     real cw, ct;
     soc_moreau_coef(nw2, V.blk[m + 1], cw, ct);
     for (int r = lane; r < m + 2; r += 64) {
@@ -851,7 +644,7 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, const rea
         V.dblk[r] = de;
     }
     if (check) {
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         for (int r = lane; r < nx; r += 64) V.lxw[r] += V.C.qh[r] * V.dblk[r];
         for (int r = lane; r < P->nu; r += 64) V.luw[r] += V.C.rh[r] * V.dblk[nx + r];
         if (lane == 0) r1 = fmax(r1, fabs((tv - tn) * ialpha - real(0.5) * (V.dblk[m] + V.dblk[m + 1])));
@@ -901,7 +694,7 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
             V.dblk[r] = de;
         }
         if (check) {
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();
             for (int r = lane; r < nx; r += 64) {
                 real s = V.C.gxN[r] * V.dblk[r];
                 if (P->has_ballN) s += V.C.gbN[r] * V.dblk[nx + r];
@@ -928,7 +721,7 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
             if (r <= nx) nw2 += eb * eb;
         }
         nw2 = wave_sum(nw2);
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         real cw, ct;
         soc_moreau_coef(nw2, V.blk[nx + 1], cw, ct);
         for (int r = lane; r < nx + 2; r += 64) {
@@ -939,220 +732,603 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
             V.dblk[r] = de;
         }
         if (check) {
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();
             for (int r = lane; r < nx; r += 64) V.lxw[r] += V.C.qnh[r] * V.dblk[r];
             if (lane == 0) r1 = fmax(r1, fabs((sv - sn) * ialpha - real(0.5) * (V.dblk[nx] + V.dblk[nx + 1])));
         }
     }
 }
 
-template <typename real, int kWG>
-__global__ __launch_bounds__(kWG) void k_forward(const ProbDev<real>* __restrict__ probs,
-                                                 const int2* __restrict__ tasks, int* __restrict__ ticket,
-                                                 int par, int check) {
+// ---------------------------------------------------------------------------
+// prep: node-parallel part of the backward half-step
+// ---------------------------------------------------------------------------
+
+// One wavefront per node; the workgroup's wavefronts take consecutive entries
+// of the node task table, which never mixes problems inside one workgroup
+// (entries with node -1 pad a problem to a multiple of kMaxNodeWaves).
+template <typename real, int R>
+__global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ probs,
+                                              const int2* __restrict__ ntasks, int* __restrict__ ticket,
+                                              int wave_elems, int par, int check) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int s_node[kMaxDepth], s_nch[kMaxDepth], s_fc[kMaxDepth];
-    __shared__ SegTable<real> s_seg;
-    __shared__ int s_task, s_ok;
     real* sm = reinterpret_cast<real*>(smem_raw);
-    const int t = threadIdx.x, w = t >> 6;
-    // Tickets hand out tasks in start order, so a workgroup only ever waits on
-    // a workgroup that started before it.
-    if (t == 0) s_task = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const int2 tk = tasks[s_task];
+    const int waves = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6), lane = lane_id();
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;  // forward-sweep tickets restart
+    const int2 t0 = ntasks[blockIdx.x * waves];
+    const ProbDev<real>* __restrict__ P = probs + t0.x;
+    if (*P->active == 0) return;  // uniform over the workgroup
+    const int nx = P->nx, nu = P->nu, m = P->m, nc = P->nc, ncN = P->ncN, nbox = P->nbox, n_nl = P->n_nl;
+    real* cst = sm;
+    stage_consts(P, cst);
+    const int v = ntasks[blockIdx.x * waves + w].y;
+    if (v < 0) return;
+    const Consts<real> C = consts_at<real>(cst, nx, nu);
+    const real alpha = P->alpha;
+    const real* __restrict__ zin = P->z[par];
+    const real* __restrict__ ein = P->eta[par];
+    real* __restrict__ zout = P->z[par ^ 1];
+    real* red = cst + consts_elems(nx, nu) + w * wave_elems;
+    real* xb = red + kRed;
+    real* ub = xb + round4(nx);  // 16-byte aligned: the K^T ubar product reads it in vectors
+    real* tk = ub + round4(nu);
+    real* st = red + kRed + node_head_elems(nx, nu, nc, ncN);
+    // vectors are read in 16-byte groups: their padding must hold finite values
+    for (int e = lane; e < kRed + node_head_elems(nx, nu, nc, ncN); e += 64) red[e] = real(0);
+    wave_sync();
+
+    if (v < n_nl) {
+        const int4 ni = P->node[v];
+        const int fc = ni.x, k = ni.y;
+        const long long yo = ni.z;
+        const bool leafkids = fc >= n_nl;
+        const bool sk = k <= kStageKids;  // per-child inputs staged, else read in place
+        const int kk = sk ? k : 0;
+        // K^T ubar: rows r < nu of [K | R~^-1], columns c < nx
+        ColProd<real, R> TK;
+        TK.load(P->T1 + v * P->T1_stride, col_shape<real>(nu, nx));
+        const real* g_soc = ein + P->e_soc + (long long)(fc - 1) * (m + 2);
+        const real* g_cs = leafkids ? ein + P->e_socN + (long long)(fc - n_nl) * (nx + 2) : ein + P->e_s + fc;
+        Stage<real, 12> S{};
+        S.set(0, zin + P->z_x + (long long)v * nx, nx);
+        S.set(1, zin + P->z_u + (long long)v * nu, nu);
+        S.set(2, ein + P->e_c + (long long)v * nc, nc);
+        S.set(3, g_soc, kk * (m + 2));
+        S.set(4, ein + P->e_y + yo, sk ? 2 * k + 1 : 0);
+        S.set(5, ein + P->e_s + v, 1);
+        S.set(6, zin + P->z_y + yo, sk ? 2 * k + 1 : 0);
+        S.set(7, zin + P->z_tau + fc - 1, kk);
+        S.set(8, zin + P->z_s + fc - 1, kk);
+        S.set(9, g_cs, leafkids ? kk * (nx + 2) : kk);
+        S.set(10, P->prob + fc, kk);
+        S.set(11, P->affine ? P->Pc + (long long)v * nx : nullptr, (P->affine && v > 0) ? nx : 0);
+        int off[12];
+        gather(S, st, off);
+        wait_loads();
+        const real* sx = st + off[0];
+        const real* su = st + off[1];
+        const real* ec = st + off[2];
+        const real es = st[off[5]];
+        const real* spc = st + off[11];
+        // per-child inputs: staged copies or the arrays themselves
+        const real* soc = sk ? st + off[3] : g_soc;
+        const real* ey = sk ? st + off[4] : ein + P->e_y + yo;
+        const real* zy = sk ? st + off[6] : zin + P->z_y + yo;
+        const real* zt = sk ? st + off[7] : zin + P->z_tau + fc - 1;
+        const real* zs = sk ? st + off[8] : zin + P->z_s + fc - 1;
+        const real* cs = sk ? st + off[9] : g_cs;
+        const real* pr = sk ? st + off[10] : P->prob + fc;
+
+        // zbar on (x^v, u^v): L* gathers the constraint rows and the SOC rows
+        // of every child edge (Sec. 4.4)
+        for (int r = lane; r < nx; r += 64) {
+            real s = 0;
+            for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + r];
+            real lt = C.gx[r] * ec[r] + C.qh[r] * s;
+            if (P->has_ball) lt += C.gb[r] * ec[nbox + r];
+            xb[r] = sx[r] - alpha * lt;
+        }
+        for (int r = lane; r < nu; r += 64) {
+            real s = 0;
+            for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + nx + r];
+            const real lt = C.gu[r] * ec[nx + r] + C.rh[r] * s;
+            ub[r] = su[r] - alpha * lt;
+        }
+        // S2 projection (Sec. 4.3) of (y^v, tau^[v], s^[v]) after the
+        // z - alpha L* eta shift.  Kernel of G = [E^T, -I, -I] with
+        // E = [gamma I; -I; 1^T] (AV@R, Sec. 3.3); G G^T = (gamma^2 + 3) I + 1 1^T,
+        // so with rho = G w the multiplier is lambda = (rho - (1^T rho / (c + n)) 1) / c,
+        // c = gamma^2 + 3 (Sherman-Morrison), and w - G^T lambda is the projection.
+        {
+            const real gam = P->gamma[v], cc = gam * gam + real(3);
+            const real yb3 = zy[2 * k] - alpha * (ey[2 * k] - es);
+            auto shifted = [&](int c, real& yb1, real& yb2, real& tb, real& sb) {
+                yb1 = zy[c] - alpha * (ey[c] - pr[c] * es);
+                yb2 = zy[k + c] - alpha * ey[k + c];
+                tb = zt[c] - alpha * real(0.5) * (soc[c * (m + 2) + m] + soc[c * (m + 2) + m + 1]);
+                const real lts = leafkids ? real(0.5) * (cs[c * (nx + 2) + nx] + cs[c * (nx + 2) + nx + 1]) : cs[c];
+                sb = zs[c] - alpha * lts;
+            };
+            real rsum = 0;
+            for (int c = lane; c < k; c += 64) {
+                real yb1, yb2, tb, sb;
+                shifted(c, yb1, yb2, tb, sb);
+                rsum += gam * yb1 - yb2 + yb3 - tb - sb;
+            }
+            rsum = wave_sum(rsum);
+            real lsum = 0;
+            for (int c = lane; c < k; c += 64) {
+                real yb1, yb2, tb, sb;
+                shifted(c, yb1, yb2, tb, sb);
+                const real rho = gam * yb1 - yb2 + yb3 - tb - sb;
+                const real l = (rho - rsum / (cc + real(k))) / cc;
+                lsum += l;
+                zout[P->z_y + yo + c] = yb1 - gam * l;
+                zout[P->z_y + yo + k + c] = yb2 + l;
+                zout[P->z_tau + fc + c - 1] = tb + l;
+                zout[P->z_s + fc + c - 1] = sb + l;
+            }
+            lsum = wave_sum(lsum);
+            if (lane == 0) zout[P->z_y + yo + 2 * k] = yb3 - lsum;
+        }
+        wave_sync();
+        // h0 = -xbar - K^T ubar (+ P c)
+        TK.apply(ub, tk, red);
+        for (int r = lane; r < nx; r += 64) {
+            real h = -xb[r] - tk[r];
+            if (P->affine && v > 0) h += spc[r];
+            P->h0[(long long)v * nx + r] = h;
+        }
+        for (int r = lane; r < nu; r += 64) P->ub[(long long)v * nu + r] = ub[r];
+        if (v == 0 && lane == 0) {
+            zout[0] = zin[0] - alpha * es - alpha;  // prox of alpha * s0
+            if (check) {
+                P->res[0] = 0ull;
+                P->res[1] = 0ull;
+            }
+        }
+    } else {
+        // leaf: h0 = -xbar (+ P c) with xbar = x - alpha L* eta on x
+        const long long lf = v - n_nl;
+        Stage<real, 4> S{};
+        S.set(0, zin + P->z_x + (long long)v * nx, nx);
+        S.set(1, ein + P->e_cN + lf * ncN, ncN);
+        S.set(2, ein + P->e_socN + lf * (nx + 2), nx + 2);
+        S.set(3, P->affine ? P->Pc + (long long)v * nx : nullptr, P->affine ? nx : 0);
+        int off[4];
+        gather(S, st, off);
+        wait_loads();
+        const real* sx = st + off[0];
+        const real* sc = st + off[1];
+        const real* ss = st + off[2];
+        const real* spc = st + off[3];
+        for (int r = lane; r < nx; r += 64) {
+            real lt = C.gxN[r] * sc[r] + C.qnh[r] * ss[r];
+            if (P->has_ballN) lt += C.gbN[r] * sc[nx + r];
+            real h = -(sx[r] - alpha * lt);
+            if (P->affine) h += spc[r];
+            P->h0[(long long)v * nx + r] = h;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// bsweep: leaves -> root
+// ---------------------------------------------------------------------------
+
+// base[r] for r = lane + 64 q (q < kVecPL), r clamped to n - 1: every load is
+// issued unconditionally (the consumer ignores r >= n).
+template <typename real>
+SPK_DEV void vec_load(const real* __restrict__ base, int n, real* out) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int q = 0; q < kVecPL; ++q) {
+        const int r = lane + 64 * q;
+        out[q] = gm(base)[r < n ? r : n - 1];
+    }
+}
+
+// Children whose messages the backward sweep reads in one batch of loads.
+constexpr int kMsgFast = 4;
+
+// What one backward level needs from memory: its two tiles and h0, ubar.
+template <typename real, int R>
+struct BLevel {
+    ColProd<real, R> TM;
+    ColProd<real, 16> TR;
+    real h0r[kVecPL], ubr[kVecPL];
+};
+
+template <typename real, int R>
+__global__ __launch_bounds__(64) void k_bsweep(const ProbDev<real>* __restrict__ probs,
+                                               const int2* __restrict__ tasks) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int lane = lane_id();
+    const int2 tk = tasks[blockIdx.x];
     const ProbDev<real>* __restrict__ P = probs + tk.x;
     if (*P->active == 0) return;
-    const int nx = P->nx, nu = P->nu, m = P->m, N = P->N, nc = P->nc, ncN = P->ncN;
-    const int n_nl = P->n_nl;
+    const int N = P->N, nx = P->nx, nu = P->nu, m = P->m, n_nl = P->n_nl;
+    int* s_node = reinterpret_cast<int*>(smem_raw);
+    int* s_nch = s_node + (N + 1);
+    int* s_fc = s_nch + (N + 1);
+    real* red = reinterpret_cast<real*>(smem_raw + sweep_int_bytes(N));
+    real* hv = red + kRed;          // h of the current node (nx)
+    real* gv = hv + sweep_vec(m);   // message (m)
+    real* wv = gv + sweep_vec(m);   // ubar - g_u (nu)
+    real* dv = wv + sweep_vec(nu);  // d (nu)
+    // vectors are read in 16-byte groups: their padding must hold finite values
+    for (int e = lane; e < sweep_elems(nx, nu); e += 64) red[e] = real(0);
+
+    const auto* path = gm(P->path) + (long long)tk.y * (N + 1);
+    for (int q = lane; q <= N; q += 64) {
+        const int v = path[q];
+        const auto* ni = gm(reinterpret_cast<const int*>(P->node + v));  // first child, children
+        s_node[q] = v;
+        s_nch[q] = v < n_nl ? ni[1] : 0;
+        s_fc[q] = ni[0];
+    }
+    wave_sync();
+    const ColShape sM = col_shape<real>(nx, m), sR = col_shape<real>(nu, nu);
+    // every load unconditional (the root reads node 1's [Abar|B] tile unused)
+    auto load_level = [&](BLevel<real, R>& L, int i) {
+        L.TM.load(P->T2M + (i > 0 ? i : 1) * P->T2M_stride, sM);
+        L.TR.load(P->T2R + i * P->T2R_stride, sR);
+        vec_load(P->h0 + (long long)i * nx, nx, L.h0r);
+        vec_load(P->ub + (long long)i * nu, nu, L.ubr);
+    };
+    // Double-buffered levels (the next level's tiles load during this one)
+    // where the registers allow it.
+    constexpr bool kDB = sizeof(real) == 4 || R <= 32;
+    BLevel<real, R> A, B;
+    int j = s_node[N];
+    {   // message of the leaf: [Abar^j|B^j]^T h0^j; the parent's data is
+        // prefetched when the leaf is its only child
+        ColProd<real, R> TM;
+        TM.load(P->T2M + j * P->T2M_stride, sM);
+        for (int r = lane; r < nx; r += 64) hv[r] = gm(P->h0)[(long long)j * nx + r];
+        if constexpr (kDB) load_level(A, s_node[N - 1]);
+        wave_sync();
+        TM.template apply<true>(hv, gv, red);
+    }
+    // one level with the data set `cur`; prefetches the next level into `nxt`
+    // when this wavefront is sure to continue there; false: stop
+    auto level = [&](BLevel<real, R>& cur, BLevel<real, R>& nxt, int lev) -> bool {
+        const int i = s_node[lev], k = s_nch[lev], fc = s_fc[lev];
+        if (k > 1) {
+            for (int c = lane; c < m; c += 64) st_dev(P->e + (long long)j * m + c, gv[c]);
+            // the message stores complete before the arrival is counted
+            drain_stores();
+            int prev = 0;
+            if (lane == 0) prev = __hip_atomic_fetch_add(gm(P->cnt) + i, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            prev = __shfl(prev, 0, 64);
+            if (prev != k - 1) return false;
+            if (lane == 0) gm(P->cnt)[i] = 0;  // the next launch reuses the counter
+        }
+        // the children's messages (up to kMsgFast in registers, issued before
+        // the prefetch so that waiting for them does not wait for it)
+        real mv[kMsgFast][2];
+        if (k > 1 && k <= kMsgFast) {
+#pragma unroll
+            for (int q = 0; q < kMsgFast; ++q) {
+                const real* e = P->e + (long long)(fc + (q < k ? q : k - 1)) * m;
+                mv[q][0] = ld_dev(e + (lane < m ? lane : m - 1));
+                mv[q][1] = ld_dev(e + (64 + lane < m ? 64 + lane : m - 1));
+            }
+        }
+        if constexpr (kDB) {
+            // the next level's data, also where another child may take over
+            // (then it is read in vain)
+            load_level(nxt, s_node[lev > 0 ? lev - 1 : 0]);
+        } else {
+            load_level(cur, i);
+        }
+        if (k > 1) {
+            // summed in child order
+            if (k <= kMsgFast) {
+                real s0 = 0, s1 = 0;
+#pragma unroll
+                for (int q = 0; q < kMsgFast; ++q)
+                    if (q < k) {
+                        s0 += mv[q][0];
+                        s1 += mv[q][1];
+                    }
+                if (lane < m) gv[lane] = s0;
+                if (64 + lane < m) gv[64 + lane] = s1;
+                for (int c = 128 + lane; c < m; c += 64) {
+                    real sum = 0;
+                    for (int q = 0; q < k; ++q) sum += ld_dev(P->e + (long long)(fc + q) * m + c);
+                    gv[c] = sum;
+                }
+            } else {
+                for (int c = lane; c < m; c += 64) {
+                    real sum = 0;
+                    for (int q = 0; q < k; ++q) sum += ld_dev(P->e + (long long)(fc + q) * m + c);
+                    gv[c] = sum;
+                }
+            }
+            wave_sync();
+        }
+        if (lane == 0) gm(P->flag)[i] = 0;  // forward-sweep flags restart
+#pragma unroll
+        for (int q = 0; q < kVecPL; ++q) {
+            const int r = lane + 64 * q;
+            if (r < nx) hv[r] = cur.h0r[q] + gv[r];
+            if (r < nu) wv[r] = cur.ubr[q] - gv[nx + r];
+        }
+        wave_sync();
+        if (i > 0) cur.TM.template apply<true>(hv, gv, red);  // message of i: [Abar^i|B^i]^T h^i
+        cur.TR.template apply<true>(wv, dv, red);             // d^i = R~^-1 (ubar - g_u)
+        for (int r = lane; r < nu; r += 64) gm(P->d)[(long long)i * nu + r] = dv[r];
+        j = i;
+        return i > 0;
+    };
+    if constexpr (kDB) {
+        for (int lev = N - 1; lev >= 0; lev -= 2) {
+            if (!level(A, B, lev)) return;
+            if (lev == 0 || !level(B, A, lev - 1)) return;
+        }
+    } else {
+        for (int lev = N - 1; lev >= 0; --lev)
+            if (!level(A, A, lev)) return;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fsweep: root -> leaves
+// ---------------------------------------------------------------------------
+
+// What one forward level needs from memory: its tile, c^v and d^v.
+template <typename real, int R>
+struct FLevel {
+    ColProd<real, R> TM;
+    real cr[kVecPL], dr[kVecPL];
+};
+
+template <typename real, int R>
+__global__ __launch_bounds__(64) void k_fsweep(const ProbDev<real>* __restrict__ probs,
+                                               const int2* __restrict__ tasks, int n_tasks,
+                                               int* __restrict__ ticket, int par) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int lane = lane_id();
+    // Tickets hand out tasks in start order, so a wavefront only ever waits
+    // on a wavefront that started before it.
+    int task = 0;
+    if (lane == 0) task = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    task = __shfl(task, 0, 64);
+    if (task >= n_tasks) return;
+    const int2 tk = tasks[task];
+    const ProbDev<real>* __restrict__ P = probs + tk.x;
+    if (*P->active == 0) return;
+    const int N = P->N, nx = P->nx, nu = P->nu, m = P->m, n_nl = P->n_nl;
+    real* __restrict__ zout = P->z[par ^ 1];
+    int* s_node = reinterpret_cast<int*>(smem_raw);
+    int* s_nch = s_node + (N + 1);
+    real* red = reinterpret_cast<real*>(smem_raw + sweep_int_bytes(N));
+    real* av = red + kRed;          // [x^anc ; d^anc] (m)
+    real* xv = av + sweep_vec(m);   // x of the current node (nx)
+    for (int e = lane; e < sweep_elems(nx, nu); e += 64) red[e] = real(0);
+
+    // this task computes the path nodes from stage L down to its leaf; the
+    // node above them belongs to the task of its leftmost leaf
+    const int L = gm(P->top_owned)[tk.y];
+    const auto* path = gm(P->path) + (long long)tk.y * (N + 1);
+    for (int q = (L > 0 ? L - 1 : 0) + lane; q <= N; q += 64) {
+        const int v = path[q];
+        s_node[q] = v;
+        s_nch[q] = v < n_nl ? gm(P->n_ch)[v] : 0;
+    }
+    wave_sync();
+    const ColShape sT = col_shape<real>(m, nx);
+    auto publish = [&](int v, int lev) {
+        if (v < n_nl && s_nch[lev] > 1) {
+            // children owned by other tasks read x^v: publish it
+            for (int r = lane; r < nx; r += 64) st_dev(zout + P->z_x + (long long)v * nx + r, xv[r]);
+            drain_stores();
+            if (lane == 0) st_dev(P->flag + v, 2);
+        } else {
+            for (int r = lane; r < nx; r += 64) gm(zout)[P->z_x + (long long)v * nx + r] = xv[r];
+        }
+    };
+    // every load unconditional: without an affine term c is read from x0 and
+    // a leaf reads the last non-leaf d, both unused
+    auto load_level = [&](FLevel<real, R>& F, int v) {
+        F.TM.load(P->T3 + v * P->T3_stride, sT);
+        vec_load(P->affine ? P->c + (long long)v * nx : P->x0, nx, F.cr);
+        vec_load(P->d + (long long)(v < n_nl ? v : n_nl - 1) * nu, nu, F.dr);
+    };
+    // Double-buffered levels (the next level's data loads during this one)
+    // where the registers allow it.
+    constexpr bool kDB = (sizeof(real) == 4 && R <= 64) || R <= 32;
+    FLevel<real, R> A, B;
+    int lev = L;
+    if (L == 0) {
+        // the root's state is the initial state
+        if (N >= 1) load_level(A, s_node[1]);
+        for (int r = lane; r < nx; r += 64) xv[r] = gm(P->x0)[r];
+        wave_sync();
+        publish(0, 0);
+        for (int r = lane; r < nx; r += 64) av[r] = xv[r];
+        for (int r = lane; r < nu; r += 64) av[nx + r] = gm(P->d)[r];
+        lev = 1;
+    } else {
+        // the first owned node's data loads overlap the wait
+        load_level(A, s_node[L]);
+        const int pn = s_node[L - 1];
+        int ok = 1;
+        if (lane == 0 && !wait_done(&P->flag[pn])) {
+            atomicExch(P->err, 1);
+            ok = 0;
+        }
+        ok = __shfl(ok, 0, 64);
+        if (!ok) return;
+        for (int r = lane; r < nx; r += 64) av[r] = ld_dev(zout + P->z_x + (long long)pn * nx + r);
+        for (int r = lane; r < nu; r += 64) av[nx + r] = gm(P->d)[(long long)pn * nu + r];
+    }
+    const int first = lev;  // its data is loaded already
+    wave_sync();
+    // one level with the data set `cur`, the next level's data loading into `nxt`
+    auto level = [&](FLevel<real, R>& cur, FLevel<real, R>& nxt, int lv) {
+        const int v = s_node[lv];
+        if (kDB) load_level(nxt, s_node[lv < N ? lv + 1 : N]);
+        if (!kDB && lv > first) load_level(cur, v);
+        cur.TM.template apply<true>(av, xv, red);  // x^v = [Abar^v | B^v] [x^anc; d^anc]
+        if (P->affine) {
+#pragma unroll
+            for (int q = 0; q < kVecPL; ++q) {
+                const int r = lane + 64 * q;
+                if (r < nx) xv[r] += cur.cr[q];
+            }
+        }
+        wave_sync();
+        publish(v, lv);
+        if (v < n_nl) {
+#pragma unroll
+            for (int q = 0; q < kVecPL; ++q) {
+                const int r = lane + 64 * q;
+                if (r < nx) av[r] = xv[r];
+                if (r < nu) av[nx + r] = cur.dr[q];
+            }
+            wave_sync();
+        }
+    };
+    if constexpr (kDB) {
+        for (; lev <= N; lev += 2) {
+            level(A, B, lev);
+            if (lev + 1 > N) break;
+            level(B, A, lev + 1);
+        }
+    } else {
+        for (; lev <= N; ++lev) level(A, A, lev);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dual: node-parallel forward half-step
+// ---------------------------------------------------------------------------
+
+template <typename real, int R>
+__global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ probs,
+                                              const int2* __restrict__ ntasks, int wave_elems, int par,
+                                              int check) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    real* sm = reinterpret_cast<real*>(smem_raw);
+    const int waves = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6), lane = lane_id();
+    const int2 t0 = ntasks[blockIdx.x * waves];
+    const ProbDev<real>* __restrict__ P = probs + t0.x;
+    if (*P->active == 0) return;
+    const int nx = P->nx, nu = P->nu, m = P->m, nc = P->nc, ncN = P->ncN, n_nl = P->n_nl;
+    real* cst = sm;
+    stage_consts(P, cst);
+    const int v = ntasks[blockIdx.x * waves + w].y;
+    if (v < 0) return;
+    const Consts<real> C = consts_at<real>(cst, nx, nu);
     const real ialpha = real(1) / P->alpha;
     const real* __restrict__ zin = P->z[par];
     const real* __restrict__ ein = P->eta[par];
     real* __restrict__ zout = P->z[par ^ 1];
     real* __restrict__ eout = P->eta[par ^ 1];
-    const int bmax = blk_elems(nx, nu, P->max_ch);
-    constexpr int kWaves = kWG / 64;
+    const int bmax = blk_elems(nx, nu, nc, ncN);
+    real* red = cst + consts_elems(nx, nu) + w * wave_elems;
+    real* un = red + kRed;
+    real* lxw = un + nu;
+    real* luw = lxw + nx;
+    real* blk = luw + nu;
+    real* dblk = blk + bmax;
+    real* st = red + kRed + node_head_elems(nx, nu, nc, ncN);
+    const long long soff = (v == 0) ? 0 : P->z_s + v - 1;
+    real r1 = 0, r2 = 0;  // residual maxima of this lane
 
-    real* red = sm;
-    real* cst = red + kWG;
-    real* st = cst + consts_elems(nx, nu);
-    real* xa = st + stage_elems(nx, nu, nc, P->max_ch);  // [x^anc ; d^anc]
-    real* xn = xa + m;
-    real* un = xn + nx;
-    real* lxw = un + nu;             // kWaves x nx
-    real* luw = lxw + kWaves * nx;   // kWaves x nu
-    real* blk = luw + kWaves * nu;   // kWaves x bmax
-    real* dblk = blk + kWaves * bmax;
-
-    // this task computes the path nodes from stage L down to its leaf; the
-    // node above them belongs to the task of its leftmost leaf
-    const int L = P->top_owned[tk.y];
-    load_path<kWG>(P, tk.y, L > 0 ? L - 1 : 0, s_node, s_nch, s_fc);
-    if (t == 0) consts_table(P, s_seg);
-    __syncthreads();
-    seg_gather<kWG>(s_seg, cst);
-    const Consts<real> C = consts_at<real>(cst, nx, nu);
-    if (t == 0) {
-        int ok = 1;
-        if (L > 0 && !wait_done(&P->flag[s_node[L - 1]])) {
-            atomicExch(P->err, 1);
-            ok = 0;
-        }
-        s_ok = ok;
-    }
-    __syncthreads();
-    if (!s_ok) return;
-    if (L > 0) {
-        const int pn = s_node[L - 1];
-        for (int r = t; r < nx; r += kWG) xa[r] = ld_dev(zout + P->z_x + (long long)pn * nx + r);
-        for (int r = t; r < nu; r += kWG) xa[nx + r] = P->d[(long long)pn * nu + r];
-    }
-
-    real r1 = 0, r2 = 0;  // residual maxima of this thread
-    for (int lev = L; lev <= N; ++lev) {
-        const int v = s_node[lev];
-        const int k = s_nch[lev], fc = s_fc[lev];
-        const bool nonleaf = v < n_nl;
-        PTile<real, kRBP, 2> TM;
-        PTile<real, kRBQ, 1> TK;
-        if (v > 0) p_load<kWG>(TM, P->M + v * P->M_stride, nx, m, m);
-        if (nonleaf) p_load<kWG>(TK, P->KR + v * P->KR_stride, nu, nx, m);
-        // staged inputs of node v (offsets into st)
-        const long long yo = nonleaf ? P->y_off[v] : 0;
-        const long long soff = (v == 0) ? 0 : P->z_s + v - 1;
-        const bool sk = k <= kStageKids;  // per-child inputs staged, else read in place
+    if (v < n_nl) {
+        const int4 ni = P->node[v];
+        const int fc = ni.x, k = ni.y;
+        const long long yo = ni.z;
+        const bool sk = k <= kStageKids;
         const int kk = sk ? k : 0, ky = sk ? 2 * k + 1 : 0;
-        int oD = 0, oXO = 0, oUO = 0, oEC = 0, oSOC = 0, oEY = 0, oES = 0, oYN = 0, oYO = 0, oSN = 0, oSO = 0;
-        int oTN = 0, oTO = 0, oP = 0, oC = 0, oECN = 0, oSOCN = 0;
-        if (nonleaf) {
-            oD = 0; oXO = oD + nu; oUO = oXO + nx; oEC = oUO + nu; oSOC = oEC + nc; oEY = oSOC + kk * (m + 2);
-            oES = oEY + ky; oYN = oES + 1; oYO = oYN + ky; oSN = oYO + ky; oSO = oSN + 1;
-            oTN = oSO + 1; oTO = oTN + kk; oP = oTO + kk; oC = oP + kk;
-        } else {
-            oXO = 0; oECN = oXO + nx; oSOCN = oECN + ncN; oSN = oSOCN + nx + 2; oSO = oSN + 1; oC = oSO + 1;
-        }
-        __syncthreads();  // previous stage data consumed, table free
-        if (t == 0) {
-            seg_reset(s_seg);
-            if (nonleaf) {
-                seg_add(s_seg, P->d + (long long)v * nu, nu);
-                seg_add(s_seg, zin + P->z_x + (long long)v * nx, nx);
-                seg_add(s_seg, zin + P->z_u + (long long)v * nu, nu);
-                seg_add(s_seg, ein + P->e_c + (long long)v * nc, nc);
-                if (sk) {
-                    seg_add(s_seg, ein + P->e_soc + (long long)(fc - 1) * (m + 2), k * (m + 2));
-                    seg_add(s_seg, ein + P->e_y + yo, 2 * k + 1);
-                }
-                seg_add(s_seg, ein + P->e_s + v, 1);
-                if (sk) {
-                    seg_add(s_seg, zout + P->z_y + yo, 2 * k + 1);
-                    seg_add(s_seg, zin + P->z_y + yo, 2 * k + 1);
-                }
-                seg_add(s_seg, zout + soff, 1);
-                seg_add(s_seg, zin + soff, 1);
-                if (sk) {
-                    seg_add(s_seg, zout + P->z_tau + fc - 1, k);
-                    seg_add(s_seg, zin + P->z_tau + fc - 1, k);
-                    seg_add(s_seg, P->prob + fc, k);
-                }
-            } else {
-                seg_add(s_seg, zin + P->z_x + (long long)v * nx, nx);
-                seg_add(s_seg, ein + P->e_cN + (long long)(v - n_nl) * ncN, ncN);
-                seg_add(s_seg, ein + P->e_socN + (long long)(v - n_nl) * (nx + 2), nx + 2);
-                seg_add(s_seg, zout + soff, 1);
-                seg_add(s_seg, zin + soff, 1);
-            }
-            if (P->affine && v > 0) seg_add(s_seg, P->c + (long long)v * nx, nx);
-        }
-        __syncthreads();
-        seg_gather<kWG>(s_seg, st);
-        __syncthreads();
-
-        // ---- state: x^v = [Abar|B] [x^anc; d^anc] + c ----
-        if (v == 0) {
-            for (int r = t; r < nx; r += kWG) xn[r] = P->x0[r];
-            __syncthreads();
-        } else {
-            p_apply<kWG>(TM, P->M + v * P->M_stride, nx, m, m, xa, xn);
-            if (P->affine) {
-                for (int r = t; r < nx; r += kWG) xn[r] += st[oC + r];
-                __syncthreads();
-            }
-        }
-        if (nonleaf && k > 1) {
-            // children owned by other tasks read x^v (and d^v): publish now
-            for (int r = t; r < nx; r += kWG) st_dev(zout + P->z_x + (long long)v * nx + r, xn[r]);
-            drain_stores();
-            __syncthreads();
-            if (t == 0) st_dev(P->flag + v, 2);
-        } else {
-            for (int r = t; r < nx; r += kWG) zout[P->z_x + (long long)v * nx + r] = xn[r];
-        }
-        if (nonleaf) {
-            // ---- input: u^v = K^v x^v + d^v ----
-            p_apply<kWG>(TK, P->KR + v * P->KR_stride, nu, nx, m, xn, un);
-            for (int r = t; r < nu; r += kWG) {
-                const real u = un[r] + st[oD + r];
-                un[r] = u;
-                zout[P->z_u + (long long)v * nu + r] = u;
-            }
+        ColProd<real, R> TK;  // u = K x + d
+        TK.load(P->T4 + v * P->T4_stride, col_shape<real>(nx, nu));
+        Stage<real, 15> S{};
+        S.set(0, zout + P->z_x + (long long)v * nx, nx);
+        S.set(1, zin + P->z_x + (long long)v * nx, nx);
+        S.set(2, zin + P->z_u + (long long)v * nu, nu);
+        S.set(3, P->d + (long long)v * nu, nu);
+        S.set(4, ein + P->e_c + (long long)v * nc, nc);
+        S.set(5, ein + P->e_soc + (long long)(fc - 1) * (m + 2), kk * (m + 2));
+        S.set(6, ein + P->e_y + yo, ky);
+        S.set(7, ein + P->e_s + v, 1);
+        S.set(8, zout + P->z_y + yo, ky);
+        S.set(9, zin + P->z_y + yo, ky);
+        S.set(10, zout + soff, 1);
+        S.set(11, zin + soff, 1);
+        S.set(12, zout + P->z_tau + fc - 1, kk);
+        S.set(13, zin + P->z_tau + fc - 1, kk);
+        S.set(14, P->prob + fc, kk);
+        int off[15];
+        gather(S, st, off);
+        wait_loads();
+        const real* xn = st + off[0];
+        const real* xo = st + off[1];
+        const real* uo = st + off[2];
+        const real* dd = st + off[3];
+        // ---- input: u^v = K^v x^v + d^v ----
+        TK.apply(xn, un, red);
+        for (int r = lane; r < nu; r += 64) {
+            const real u = un[r] + dd[r];
+            un[r] = u;
+            zout[P->z_u + (long long)v * nu + r] = u;
         }
         if (check) {
-            for (int r = t & 63; r < nx; r += 64) lxw[w * nx + r] = 0;
-            for (int r = t & 63; r < nu; r += 64) luw[w * nu + r] = 0;
+            for (int r = lane; r < nx; r += 64) lxw[r] = 0;
+            for (int r = lane; r < nu; r += 64) luw[r] = 0;
         }
-        __syncthreads();
-        // ---- dual blocks, one wavefront each ----
-        const FwdNode<real> V{C, xn, un, st + oXO, st + oUO, blk + w * bmax, dblk + w * bmax,
-                              lxw + w * nx, luw + w * nu};
-        if (nonleaf) {
-            // per-child inputs: staged copies or the arrays themselves
-            const real* soc = sk ? st + oSOC : ein + P->e_soc + (long long)(fc - 1) * (m + 2);
-            const real* ey = sk ? st + oEY : ein + P->e_y + yo;
-            const real* yn = sk ? st + oYN : zout + P->z_y + yo;
-            const real* yv = sk ? st + oYO : zin + P->z_y + yo;
-            const real* tn = sk ? st + oTN : zout + P->z_tau + fc - 1;
-            const real* tv = sk ? st + oTO : zin + P->z_tau + fc - 1;
-            const real* pr = sk ? st + oP : P->prob + fc;
-            for (int b = w; b < k + 2; b += kWaves) {
-                if (b == 0) {
-                    fwd_block_c(P, v, st + oEC, eout, V, check, r2);
-                } else if (b == 1) {
-                    fwd_block_risk(P, v, k, ey, st[oES], yn, yv, st[oSN], st[oSO], pr, eout, check, r1, r2);
-                } else {
-                    const int q = b - 2;
-                    fwd_block_soc(P, fc + q, soc + q * (m + 2), tn[q], tv[q], eout, V, check, r1, r2);
-                }
-            }
-        } else {
-            for (int b = w; b < 2; b += kWaves)
-                fwd_block_leaf(P, v, b, st + oECN, st + oSOCN, st[oSN], st[oSO], eout, V, check, r1, r2);
+        wave_sync();
+        const FwdNode<real> V{C, xn, un, xo, uo, blk, dblk, lxw, luw};
+        const real* soc = sk ? st + off[5] : ein + P->e_soc + (long long)(fc - 1) * (m + 2);
+        const real* ey = sk ? st + off[6] : ein + P->e_y + yo;
+        const real* yn = sk ? st + off[8] : zout + P->z_y + yo;
+        const real* yv = sk ? st + off[9] : zin + P->z_y + yo;
+        const real* tn = sk ? st + off[12] : zout + P->z_tau + fc - 1;
+        const real* tv = sk ? st + off[13] : zin + P->z_tau + fc - 1;
+        const real* pr = sk ? st + off[14] : P->prob + fc;
+        fwd_block_c(P, v, st + off[4], eout, V, check, r2);
+        wave_sync();
+        fwd_block_risk(P, v, k, ey, st[off[7]], yn, yv, st[off[10]], st[off[11]], pr, eout, check, r1, r2);
+        wave_sync();
+        for (int q = 0; q < k; ++q) {
+            fwd_block_soc(P, fc + q, soc + q * (m + 2), tn[q], tv[q], eout, V, check, r1, r2);
+            wave_sync();
         }
         if (check) {
-            __syncthreads();
-            for (int r = t; r < nx; r += kWG) {
-                real s = 0;
-                for (int q = 0; q < kWaves; ++q) s += lxw[q * nx + r];
-                r1 = fmax(r1, fabs((st[oXO + r] - xn[r]) * ialpha - s));
-            }
-            if (nonleaf)
-                for (int r = t; r < nu; r += kWG) {
-                    real s = 0;
-                    for (int q = 0; q < kWaves; ++q) s += luw[q * nu + r];
-                    r1 = fmax(r1, fabs((st[oUO + r] - un[r]) * ialpha - s));
-                }
+            for (int r = lane; r < nx; r += 64) r1 = fmax(r1, fabs((xo[r] - xn[r]) * ialpha - lxw[r]));
+            for (int r = lane; r < nu; r += 64) r1 = fmax(r1, fabs((uo[r] - un[r]) * ialpha - luw[r]));
         }
-        // ---- next stage input [x^v ; d^v] ----
-        if (lev < N) {
-            __syncthreads();
-            for (int r = t; r < nx; r += kWG) xa[r] = xn[r];
-            for (int r = t; r < nu; r += kWG) xa[nx + r] = st[oD + r];
-        }
+    } else {
+        const long long lf = v - n_nl;
+        Stage<real, 6> S{};
+        S.set(0, zout + P->z_x + (long long)v * nx, nx);
+        S.set(1, zin + P->z_x + (long long)v * nx, nx);
+        S.set(2, ein + P->e_cN + lf * ncN, ncN);
+        S.set(3, ein + P->e_socN + lf * (nx + 2), nx + 2);
+        S.set(4, zout + soff, 1);
+        S.set(5, zin + soff, 1);
+        int off[6];
+        gather(S, st, off);
+        wait_loads();
+        if (check)
+            for (int r = lane; r < nx; r += 64) lxw[r] = 0;
+        wave_sync();
+        const real* xn = st + off[0];
+        const real* xo = st + off[1];
+        const FwdNode<real> V{C, xn, un, xo, xo, blk, dblk, lxw, luw};
+        fwd_block_leaf(P, v, 0, st + off[2], st + off[3], st[off[4]], st[off[5]], eout, V, check, r1, r2);
+        wave_sync();
+        fwd_block_leaf(P, v, 1, st + off[2], st + off[3], st[off[4]], st[off[5]], eout, V, check, r1, r2);
+        wave_sync();
+        if (check)
+            for (int r = lane; r < nx; r += 64) r1 = fmax(r1, fabs((xo[r] - xn[r]) * ialpha - lxw[r]));
     }
     if (check) {
-        r1 = block_max<kWG>(r1, red);
-        r2 = block_max<kWG>(r2, red);
-        if (t == 0) {
+        r1 = wave_max(r1);
+        r2 = wave_max(r2);
+        if (lane == 0) {
             record_max(&P->res[0], r1);
             record_max(&P->res[1], r2);
         }
@@ -1327,53 +1503,57 @@ __global__ void k_fill(T* __restrict__ dst, T val, long long n) {
          k += (long long)gridDim.x * blockDim.x)
         dst[k] = val;
 }
-
 // ---------------------------------------------------------------------------
 // launchers (host side)
 // ---------------------------------------------------------------------------
 
-template <typename real, int WG>
-static hipError_t launch_sweep(bool backward, const ProbDev<real>* probs, const int2* tasks, int* ticket,
-                               int n_tasks, int lds_bytes, int par, int check, hipStream_t st) {
-    if (backward)
-        hipLaunchKernelGGL((k_backward<real, WG>), dim3(n_tasks), dim3(WG), lds_bytes, st, probs, tasks, ticket,
-                           par, check);
-    else
-        hipLaunchKernelGGL((k_forward<real, WG>), dim3(n_tasks), dim3(WG), lds_bytes, st, probs, tasks, ticket,
-                           par, check);
+template <typename real, int R>
+static hipError_t launch_phase_r(const ProbDev<real>* probs, const LaunchCfg& c, int phase, int par, int check,
+                                 hipStream_t st) {
+    const int waves = c.node_wg / 64;
+    switch (phase) {
+        case 0:
+            hipLaunchKernelGGL((k_prep<real, R>), dim3(c.n_node_tasks / waves), dim3(c.node_wg), c.node_lds, st,
+                               probs, c.node_tasks, c.ticket, c.wave_elems, par, check);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_bsweep<real, R>), dim3(c.n_leaf_tasks), dim3(64), c.sweep_lds, st, probs,
+                               c.leaf_tasks);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_fsweep<real, R>), dim3(c.n_leaf_tasks), dim3(64), c.sweep_lds, st, probs,
+                               c.leaf_tasks, c.n_leaf_tasks, c.ticket, par);
+            break;
+        default:
+            hipLaunchKernelGGL((k_dual<real, R>), dim3(c.n_node_tasks / waves), dim3(c.node_wg), c.node_lds, st,
+                               probs, c.node_tasks, c.wave_elems, par, check);
+            break;
+    }
     return hipGetLastError();
 }
 
+// One of the four launches of a CP step (0 prep, 1 bsweep, 2 fsweep, 3 dual).
 template <typename real>
-static hipError_t launch_wg(bool backward, const ProbDev<real>* probs, const int2* tasks, int* ticket,
-                            int n_tasks, int lds_bytes, int par, int check, int wg, hipStream_t st) {
-    switch (wg) {
-        case 64: return launch_sweep<real, 64>(backward, probs, tasks, ticket, n_tasks, lds_bytes, par, check, st);
-        case 128: return launch_sweep<real, 128>(backward, probs, tasks, ticket, n_tasks, lds_bytes, par, check, st);
-        case 256: return launch_sweep<real, 256>(backward, probs, tasks, ticket, n_tasks, lds_bytes, par, check, st);
-        case 512: return launch_sweep<real, 512>(backward, probs, tasks, ticket, n_tasks, lds_bytes, par, check, st);
+hipError_t launch_phase(const ProbDev<real>* probs, const LaunchCfg& c, int phase, int par, int check,
+                        hipStream_t st) {
+    if (phase < 0 || phase > 3 || c.n_leaf_tasks <= 0 || c.n_node_tasks <= 0) return hipErrorInvalidValue;
+    if (c.node_wg != 64 && c.node_wg != 128 && c.node_wg != 256 && c.node_wg != 512) return hipErrorInvalidValue;
+    switch (c.cls[phase]) {
+        case 16: return launch_phase_r<real, 16>(probs, c, phase, par, check, st);
+        case 32: return launch_phase_r<real, 32>(probs, c, phase, par, check, st);
+        case 64: return launch_phase_r<real, 64>(probs, c, phase, par, check, st);
+        case 80: return launch_phase_r<real, 80>(probs, c, phase, par, check, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename real>
-hipError_t launch_backward(const ProbDev<real>* probs, const int2* tasks, int* ticket, int n_tasks,
-                           int lds_bytes, int par, int check, int wg, hipStream_t st) {
-    return launch_wg<real>(true, probs, tasks, ticket, n_tasks, lds_bytes, par, check, wg, st);
-}
-
-template <typename real>
-hipError_t launch_forward(const ProbDev<real>* probs, const int2* tasks, int* ticket, int n_tasks,
-                          int lds_bytes, int par, int check, int wg, hipStream_t st) {
-    return launch_wg<real>(false, probs, tasks, ticket, n_tasks, lds_bytes, par, check, wg, st);
-}
-
-template <typename real>
-hipError_t launch_step(const ProbDev<real>* probs, const int2* tasks, int* ticket, int n_tasks, int lds_bytes,
-                       int par, int check, int wg, hipStream_t st) {
-    hipError_t e = launch_backward<real>(probs, tasks, ticket, n_tasks, lds_bytes, par, check, wg, st);
-    if (e != hipSuccess) return e;
-    return launch_forward<real>(probs, tasks, ticket, n_tasks, lds_bytes, par, check, wg, st);
+hipError_t launch_step(const ProbDev<real>* probs, const LaunchCfg& c, int par, int check, hipStream_t st) {
+    for (int phase = 0; phase < 4; ++phase) {
+        const hipError_t e = launch_phase<real>(probs, c, phase, par, check, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename real>
@@ -1413,12 +1593,9 @@ hipError_t launch_fill(T* dst, T val, long long n, hipStream_t st) {
 }
 
 #define SPK_INSTANTIATE(real)                                                                              \
-    template hipError_t launch_step<real>(const ProbDev<real>*, const int2*, int*, int, int, int, int, int,  \
-                                          hipStream_t);                                                    \
-    template hipError_t launch_backward<real>(const ProbDev<real>*, const int2*, int*, int, int, int, int, \
-                                              int, hipStream_t);                                           \
-    template hipError_t launch_forward<real>(const ProbDev<real>*, const int2*, int*, int, int, int, int,  \
-                                             int, hipStream_t);                                            \
+    template hipError_t launch_step<real>(const ProbDev<real>*, const LaunchCfg&, int, int, hipStream_t);   \
+    template hipError_t launch_phase<real>(const ProbDev<real>*, const LaunchCfg&, int, int, int,           \
+                                           hipStream_t);                                                   \
     template hipError_t launch_apply_L<real>(const ProbDev<real>*, int, const real*, real*, hipStream_t);   \
     template hipError_t launch_apply_Lt<real>(const ProbDev<real>*, int, const real*, real*, hipStream_t);  \
     template hipError_t launch_prox_gconj<real>(const ProbDev<real>*, int, const real*, real*, hipStream_t); \

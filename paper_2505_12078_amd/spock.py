@@ -101,6 +101,8 @@ SIGNATURES = {
     "spock_prox_gconj": (C.c_int32, [C.c_void_p, _dp, _dp, C.c_int32]),
     "spock_time_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp]),
     "spock_step_bytes": (C.c_int32, [C.c_void_p, C.c_int32, _dp, _dp]),
+    "spock_time_kernels": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp]),
+    "spock_kernel_bytes": (C.c_int32, [C.c_void_p, C.c_int32, _dp]),
     "spock_run_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
     "spock_set_launch": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
     "spock_get_launch": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
@@ -114,6 +116,8 @@ SIGNATURES = {
     "spock_batch_run_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
     "spock_batch_time_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp]),
     "spock_batch_step_bytes": (C.c_int32, [C.c_void_p, C.c_int32, _dp, _dp]),
+    "spock_batch_time_kernels": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp]),
+    "spock_batch_kernel_bytes": (C.c_int32, [C.c_void_p, C.c_int32, _dp]),
     "spock_server_create": (C.c_int32, [C.c_size_t, C.POINTER(Settings), C.POINTER(C.c_void_p)]),
     "spock_server_add_tree": (C.c_int32, [C.c_void_p, C.POINTER(ProblemDesc), C.POINTER(C.c_int64)]),
     "spock_server_submit": (C.c_int32, [C.c_void_p, C.c_int64, _dp, C.c_uint64]),
@@ -323,6 +327,18 @@ class Problem:
         _check(load().spock_get_launch(self.h, precision, C.byref(v)))
         return v.value
 
+    def time_kernels(self, steps, precision=FP64):
+        """Mean ms per launch (prep, bsweep, fsweep, dual) and per step."""
+        t, k = C.c_double(), (C.c_double * 4)()
+        _check(load().spock_time_kernels(self.h, precision, int(steps), C.byref(t), k))
+        return t.value, list(k)
+
+    def kernel_bytes(self, precision=FP64):
+        """Algorithmic bytes of each launch of one step."""
+        k = (C.c_double * 4)()
+        _check(load().spock_kernel_bytes(self.h, precision, k))
+        return list(k)
+
     def step_bytes(self, precision=FP64):
         b, f = C.c_double(), C.c_double()
         _check(load().spock_step_bytes(self.h, precision, C.byref(b), C.byref(f)))
@@ -377,6 +393,16 @@ class Batch:
         t, b, f = C.c_double(), C.c_double(), C.c_double()
         _check(load().spock_batch_time_steps(self.h, precision, int(steps), C.byref(t), C.byref(b), C.byref(f)))
         return t.value, b.value, f.value
+
+    def time_kernels(self, steps, precision=FP64):
+        t, k = C.c_double(), (C.c_double * 4)()
+        _check(load().spock_batch_time_kernels(self.h, precision, int(steps), C.byref(t), k))
+        return t.value, list(k)
+
+    def kernel_bytes(self, precision=FP64):
+        k = (C.c_double * 4)()
+        _check(load().spock_batch_kernel_bytes(self.h, precision, k))
+        return list(k)
 
     def step_bytes(self, precision=FP64):
         b, f = C.c_double(), C.c_double()
