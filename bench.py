@@ -4,8 +4,10 @@
 Workload: the large scenario tree -- horizon N = 15, branching 2 at stages
 0-9 then 1 (1,024 scenarios, 7,167 nodes), nx = 50, nu = 25, box + ball
 constraints, AV@R_0.95, seeded synthetic data (no dataset is involved).  A
-"step" is one CP iteration T: the backward sweep (L*, S2, Riccati recursion)
-and the forward sweep (dynamics, L, S3 projections) over the whole tree.
+"step" is one CP iteration T over the whole tree: four launches -- prep
+(node-parallel: L*, S2, the children-independent part of the Riccati-style
+recursion), bsweep (leaves -> root recursion), fsweep (root -> leaves
+dynamics) and dual (node-parallel: u = K x + d, L, S3 projections, Moreau).
 
 Reported value: CP iterations per second of the mixed-precision form (float32
 steps on float32 copies of the float64 factors), with the plain float64 rate,
@@ -28,6 +30,31 @@ METRIC = "SPOCK iters/s & time-to-tol (1e-4) vs plain FP64; serve p50/p99 latenc
 WORKLOAD = ("large tree: N=15, branching 2 at stages 0-9 then 1 (1024 scenarios, 7167 nodes), "
             "nx=50, nu=25, box+ball, AV@R_0.95, Dirichlet probabilities")
 HBM_PEAK_GBS = 8000.0
+KERNELS = ("prep", "bsweep", "fsweep", "dual")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def _kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("spock_kernels.hip", "spock_dev.h"):
+        with open(os.path.join(ROOT, "paper_2505_12078_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != _kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
 
 
 def cpu_baseline(steps):
@@ -142,8 +169,8 @@ def serve_bench(S, W, duration_s=10.0, session_rate=20.0, req_per_session=10, ga
 
 def _profile_pass(steps):
     """What a profiler should see: `steps` float32 and float64 CP steps of the
-    large tree (k_backward / k_forward) and one copy of 1 GiB (a plain kernel
-    of known traffic for scaling the memory counters)."""
+    large tree (k_prep / k_bsweep / k_fsweep / k_dual) and one copy of 1 GiB (a
+    plain kernel of known traffic for scaling the memory counters)."""
     import torch
 
     from paper_2505_12078_amd import spock as S
@@ -158,10 +185,10 @@ def _profile_pass(steps):
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    bb32, bf32 = P.step_bytes(S.FP32)
-    bb64, bf64 = P.step_bytes(S.FP64)
-    print(json.dumps({"steps": steps, "copy_bytes": 1 << 30, "bytes_backward_f32": bb32, "bytes_forward_f32": bf32,
-                      "bytes_backward_f64": bb64, "bytes_forward_f64": bf64}))
+    b32 = P.kernel_bytes(S.FP32)
+    b64 = P.kernel_bytes(S.FP64)
+    print(json.dumps({"steps": steps, "copy_bytes": 1 << 30, "source_hash": _kernel_source_hash(),
+                      "bytes_f32": dict(zip(KERNELS, b32)), "bytes_f64": dict(zip(KERNELS, b64))}))
     P.close()
 
 
@@ -220,17 +247,19 @@ def main():
     # per-kernel durations on the library's stream (HIP events around every launch)
     kt = {}
     for name, prec in (("f32", S.FP32), ("f64", S.FP64)):
-        tot, tb, tf = P.time_steps(args.steps, prec)
-        bb, bf = P.step_bytes(prec)
-        kt[name] = dict(ms_step=tot, ms_backward=tb, ms_forward=tf, bytes_backward=bb, bytes_forward=bf)
+        tot, ms_k = P.time_kernels(args.steps, prec)
+        by_k = P.kernel_bytes(prec)
+        kt[name] = {"ms_step_events": round(tot, 5)}
+        for kn, ms, by in zip(KERNELS, ms_k, by_k):
+            kt[name][kn] = {"avg_ms": round(ms, 5), "bytes_per_launch": by,
+                            "GB_s": round(by / (ms * 1e-3) / 1e9, 1), "frac_hbm": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     k = kt["f32"]
-    dom = "forward" if k["ms_forward"] >= k["ms_backward"] else "backward"
-    ms = k["ms_" + dom]
-    by = k["bytes_" + dom]
+    dom = max(KERNELS, key=lambda kn: k[kn]["avg_ms"])
+    ms, by = k[dom]["avg_ms"], k[dom]["bytes_per_launch"]
     achieved = by / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_%s<float>" % dom, "avg_ms": round(ms, 4), "bytes_per_launch": by}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _measured_traffic("k_%s<float>" % dom),
+                "kernel": "k_%s<float>" % dom, "avg_ms": ms, "bytes_per_launch": by}
 
     tol = None
     if not args.no_tol:
