@@ -44,6 +44,7 @@ spk::LaunchCfg batch_cfg(const spock_batch* b, int node_wg) {
     c.leaf_tasks = b->tasks;
     c.n_leaf_tasks = b->n_tasks;
     c.node_tasks = b->ntasks;
+    c.node_info = b->ninfo;
     c.n_node_tasks = b->n_ntasks;
     c.ticket = b->ticket;
     c.node_wg = node_wg;
@@ -199,7 +200,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
     };
     const size_t o64 = take(sizeof(ProbDev<double>) * n), o32 = take(sizeof(ProbDev<float>) * n);
     const size_t ot = take(sizeof(int2) * b->n_tasks), oa = take(sizeof(int) * n), otk = take(sizeof(int) * 4);
-    const size_t ont = take(sizeof(int2) * b->n_ntasks);
+    const size_t ont = take(sizeof(int2) * b->n_ntasks), oni = take(sizeof(int4) * b->n_ntasks);
     const size_t oe = take(sizeof(int) * n), orr = take(sizeof(unsigned long long) * 2 * n);
     b->bytes = off + 256;
     std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
@@ -213,6 +214,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
     b->d32 = (ProbDev<float>*)(base + o32);
     b->tasks = (int2*)(base + ot);
     b->ntasks = (int2*)(base + ont);
+    b->ninfo = (int4*)(base + oni);
     b->active = (int*)(base + oa);
     b->ticket = (int*)(base + otk);
     b->err = (int*)(base + oe);
@@ -228,8 +230,10 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
     std::vector<ProbDev<double>> h64(n);
     std::vector<ProbDev<float>> h32(n);
     std::vector<int2> tasks, ntasks;
+    std::vector<int4> ninfo;
     tasks.reserve(b->n_tasks);
     ntasks.reserve(b->n_ntasks);
+    ninfo.reserve(b->n_ntasks);
     for (int k = 0; k < n; ++k) {
         h64[k] = probs[k]->s64.h;
         h32[k] = probs[k]->s32.h;
@@ -237,7 +241,15 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
         h64[k].err = h32[k].err = b->err + k;
         h64[k].res = h32[k].res = b->res + 2 * k;
         for (int l = 0; l < probs[k]->n_leaf; ++l) tasks.push_back(make_int2(k, l));
-        for (int v = 0; v < probs[k]->n_ntasks; ++v) ntasks.push_back(make_int2(k, v < probs[k]->n ? v : -1));
+        const spock_problem* q = probs[k];
+        for (int v = 0; v < q->n_ntasks; ++v) {
+            ntasks.push_back(make_int2(k, v < q->n ? v : -1));
+            if (v < q->n)
+                ninfo.push_back(make_int4(q->n_ch[v] ? q->first_child[v] : 0, q->n_ch[v], v < q->n_nl ? q->y_off[v] : 0,
+                                          q->parent[v]));
+            else
+                ninfo.push_back(make_int4(0, 0, 0, 0));
+        }
     }
     b->cfg64 = batch_cfg<double>(b, spk::kDefaultWG);
     b->cfg32 = batch_cfg<float>(b, spk::kDefaultWG);
@@ -247,6 +259,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
     if (e == hipSuccess) e = hipMemcpy(b->tasks, tasks.data(), sizeof(int2) * tasks.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->ntasks, ntasks.data(), sizeof(int2) * ntasks.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->ninfo, ninfo.data(), sizeof(int4) * ninfo.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->active, b->h_active.data(), sizeof(int) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(b->ticket, 0, sizeof(int) * 4);
     if (e == hipSuccess) e = hipMemset(b->err, 0, sizeof(int) * n);

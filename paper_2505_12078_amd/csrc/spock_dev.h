@@ -146,6 +146,7 @@ struct LaunchCfg {
     const int2* leaf_tasks;  // (problem, leaf) per sweep wavefront
     int n_leaf_tasks;
     const int2* node_tasks;  // (problem, node or -1) per node wavefront, kMaxNodeWaves-padded per problem
+    const int4* node_info;   // per node task: first child, children, y offset, parent
     int n_node_tasks;
     int* ticket;             // forward-sweep ticket counter
     int node_wg;             // threads per node workgroup (64, 128, 256, 512)

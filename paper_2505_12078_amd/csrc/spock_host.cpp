@@ -192,6 +192,7 @@ static void carve(Arena& a, spock_problem* p) {
     p->d_node = a.take<int4>(p->n);
     p->n_ntasks = (p->n + spk::kMaxNodeWaves - 1) / spk::kMaxNodeWaves * spk::kMaxNodeWaves;
     p->d_ntasks = a.take<int2>(p->n_ntasks);
+    p->d_ninfo = a.take<int4>(p->n_ntasks);
     p->d_res = a.take<unsigned long long>(4);
     p->d_err = a.take<int>(4);
     const long long nv = std::max(p->nz, p->neta);
@@ -823,6 +824,7 @@ spk::LaunchCfg make_cfg(const spock_problem* p, int node_wg) {
     c.leaf_tasks = p->d_tasks;
     c.n_leaf_tasks = p->n_leaf;
     c.node_tasks = p->d_ntasks;
+    c.node_info = p->d_ninfo;
     c.n_node_tasks = p->n_ntasks;
     c.ticket = p->d_ticket;
     c.node_wg = node_wg;
@@ -1014,11 +1016,17 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
             node[v] = make_int4(p->n_ch[v] ? p->first_child[v] : 0, p->n_ch[v], v < p->n_nl ? p->y_off[v] : 0,
                                 p->parent[v]);
         std::vector<int2> ntasks(p->n_ntasks, make_int2(0, -1));
-        for (int v = 0; v < p->n; ++v) ntasks[v] = make_int2(0, v);
+        std::vector<int4> ninfo(p->n_ntasks, make_int4(0, 0, 0, 0));
+        for (int v = 0; v < p->n; ++v) {
+            ntasks[v] = make_int2(0, v);
+            ninfo[v] = node[v];
+        }
         hipError_t e = hipMemcpy(p->d_tree, tree.data(), tree.size() * sizeof(int), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(p->d_node, node.data(), node.size() * sizeof(int4), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(p->d_ntasks, ntasks.data(), ntasks.size() * sizeof(int2), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_ninfo, ninfo.data(), ninfo.size() * sizeof(int4), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(p->d_tasks, tasks.data(), tasks.size() * sizeof(int2), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(p->d_path, path.data(), path.size() * sizeof(int), hipMemcpyHostToDevice);

@@ -101,6 +101,7 @@ struct spock_problem {
     int2* d_tasks = nullptr;   // (0, leaf) per sweep wavefront
     int4* d_node = nullptr;    // first child, children, y offset, parent per node
     int2* d_ntasks = nullptr;  // (0, node or -1) per node wavefront
+    int4* d_ninfo = nullptr;   // first child, children, y offset, parent per node wavefront
     int n_ntasks = 0;
     unsigned long long* d_res = nullptr;
     int* d_err = nullptr;
@@ -146,6 +147,7 @@ struct spock_batch {
     int2* tasks = nullptr;
     int n_tasks = 0;
     int2* ntasks = nullptr;
+    int4* ninfo = nullptr;
     int n_ntasks = 0;
     int* active = nullptr;
     int* ticket = nullptr;

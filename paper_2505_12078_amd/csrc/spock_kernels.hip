@@ -748,19 +748,22 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
 // (entries with node -1 pad a problem to a multiple of kMaxNodeWaves).
 template <typename real, int R>
 __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ probs,
-                                              const int2* __restrict__ ntasks, int* __restrict__ ticket,
-                                              int wave_elems, int par, int check) {
+                                              const int2* __restrict__ ntasks, const int4* __restrict__ ninfo,
+                                              int* __restrict__ ticket, int wave_elems, int par, int check) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real* sm = reinterpret_cast<real*>(smem_raw);
     const int waves = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6), lane = lane_id();
     if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;  // forward-sweep tickets restart
     const int2 t0 = ntasks[blockIdx.x * waves];
+    // this wavefront's node and its first child, children, y offset (loaded
+    // with the task, not after it)
+    const int v = ntasks[blockIdx.x * waves + w].y;
+    const int4 ni = ninfo[blockIdx.x * waves + w];
     const ProbDev<real>* __restrict__ P = probs + t0.x;
     if (*P->active == 0) return;  // uniform over the workgroup
     const int nx = P->nx, nu = P->nu, m = P->m, nc = P->nc, ncN = P->ncN, nbox = P->nbox, n_nl = P->n_nl;
     real* cst = sm;
     stage_consts(P, cst);
-    const int v = ntasks[blockIdx.x * waves + w].y;
     if (v < 0) return;
     const Consts<real> C = consts_at<real>(cst, nx, nu);
     const real alpha = P->alpha;
@@ -777,7 +780,6 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
     wave_sync();
 
     if (v < n_nl) {
-        const int4 ni = P->node[v];
         const int fc = ni.x, k = ni.y;
         const long long yo = ni.z;
         const bool leafkids = fc >= n_nl;
@@ -1207,18 +1209,19 @@ __global__ __launch_bounds__(64) void k_fsweep(const ProbDev<real>* __restrict__
 
 template <typename real, int R>
 __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ probs,
-                                              const int2* __restrict__ ntasks, int wave_elems, int par,
-                                              int check) {
+                                              const int2* __restrict__ ntasks, const int4* __restrict__ ninfo,
+                                              int wave_elems, int par, int check) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real* sm = reinterpret_cast<real*>(smem_raw);
     const int waves = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6), lane = lane_id();
     const int2 t0 = ntasks[blockIdx.x * waves];
+    const int v = ntasks[blockIdx.x * waves + w].y;
+    const int4 ni = ninfo[blockIdx.x * waves + w];
     const ProbDev<real>* __restrict__ P = probs + t0.x;
     if (*P->active == 0) return;
     const int nx = P->nx, nu = P->nu, m = P->m, nc = P->nc, ncN = P->ncN, n_nl = P->n_nl;
     real* cst = sm;
     stage_consts(P, cst);
-    const int v = ntasks[blockIdx.x * waves + w].y;
     if (v < 0) return;
     const Consts<real> C = consts_at<real>(cst, nx, nu);
     const real ialpha = real(1) / P->alpha;
@@ -1238,7 +1241,6 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
     real r1 = 0, r2 = 0;  // residual maxima of this lane
 
     if (v < n_nl) {
-        const int4 ni = P->node[v];
         const int fc = ni.x, k = ni.y;
         const long long yo = ni.z;
         const bool sk = k <= kStageKids;
@@ -1514,7 +1516,7 @@ static hipError_t launch_phase_r(const ProbDev<real>* probs, const LaunchCfg& c,
     switch (phase) {
         case 0:
             hipLaunchKernelGGL((k_prep<real, R>), dim3(c.n_node_tasks / waves), dim3(c.node_wg), c.node_lds, st,
-                               probs, c.node_tasks, c.ticket, c.wave_elems, par, check);
+                               probs, c.node_tasks, c.node_info, c.ticket, c.wave_elems, par, check);
             break;
         case 1:
             hipLaunchKernelGGL((k_bsweep<real, R>), dim3(c.n_leaf_tasks), dim3(64), c.sweep_lds, st, probs,
@@ -1526,7 +1528,7 @@ static hipError_t launch_phase_r(const ProbDev<real>* probs, const LaunchCfg& c,
             break;
         default:
             hipLaunchKernelGGL((k_dual<real, R>), dim3(c.n_node_tasks / waves), dim3(c.node_wg), c.node_lds, st,
-                               probs, c.node_tasks, c.wave_elems, par, check);
+                               probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
             break;
     }
     return hipGetLastError();
