@@ -3,7 +3,7 @@
 // batch holds copies of the members' descriptors whose residual slots, error
 // flags and "active" flags point into batch-owned arrays, two problem-major
 // task tables (one sweep task per leaf and one node task per node of every
-// member) and one forward ticket counter.
+// member).
 // Members that converge are switched off through their active flag, so a
 // captured graph of `check_every` steps is replayed unchanged until every
 // member is done.
@@ -46,7 +46,6 @@ spk::LaunchCfg batch_cfg(const spock_batch* b, int node_wg) {
     c.node_tasks = b->ntasks;
     c.node_info = b->ninfo;
     c.n_node_tasks = b->n_ntasks;
-    c.ticket = b->ticket;
     c.node_wg = node_wg;
     c.node_lds = lds(node_wg);
     return c;
@@ -199,7 +198,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
         return o;
     };
     const size_t o64 = take(sizeof(ProbDev<double>) * n), o32 = take(sizeof(ProbDev<float>) * n);
-    const size_t ot = take(sizeof(int2) * b->n_tasks), oa = take(sizeof(int) * n), otk = take(sizeof(int) * 4);
+    const size_t ot = take(sizeof(int2) * b->n_tasks), oa = take(sizeof(int) * n);
     const size_t ont = take(sizeof(int2) * b->n_ntasks), oni = take(sizeof(int4) * b->n_ntasks);
     const size_t oe = take(sizeof(int) * n), orr = take(sizeof(unsigned long long) * 2 * n);
     b->bytes = off + 256;
@@ -216,7 +215,6 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
     b->ntasks = (int2*)(base + ont);
     b->ninfo = (int4*)(base + oni);
     b->active = (int*)(base + oa);
-    b->ticket = (int*)(base + otk);
     b->err = (int*)(base + oe);
     b->res = (unsigned long long*)(base + orr);
     auto bail = [&](int32_t code, const std::string& msg) {
@@ -261,7 +259,6 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
         e = hipMemcpy(b->ntasks, ntasks.data(), sizeof(int2) * ntasks.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->ninfo, ninfo.data(), sizeof(int4) * ninfo.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->active, b->h_active.data(), sizeof(int) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(b->ticket, 0, sizeof(int) * 4);
     if (e == hipSuccess) e = hipMemset(b->err, 0, sizeof(int) * n);
     if (e == hipSuccess) e = hipMemset(b->res, 0, sizeof(unsigned long long) * 2 * n);
     if (e != hipSuccess) return bail(SPOCK_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));

@@ -33,6 +33,7 @@ struct ProbDev {
     const int* y_off;        // start of y^i inside the y block, per non-leaf node
     const int* path;         // per leaf l: node at each stage 0..N on the root-to-leaf path
     const int* top_owned;    // per leaf l: first stage whose path node has l as leftmost leaf
+                             // (the forward sweep of l stores x from that stage on)
 
     // Offline factors (Alg. 1, reduced online form), each packed in the lane
     // order of the product that reads it (tile_pack):
@@ -84,7 +85,6 @@ struct ProbDev {
     real* h0;                // -xbar - K^T ubar (+ P c): h of node j before its children's messages, nx
     real* ub;                // ubar of non-leaf node i, nu
     int* cnt;                // backward arrival counters, per node
-    int* flag;               // forward claim/done flags, per node
     int* err;                // device wait timeout
     const int* active;       // 0: this problem sits out the launch (batched form)
     unsigned long long* res; // |xi1|_inf, |xi2|_inf as float64 bit patterns
@@ -148,7 +148,6 @@ struct LaunchCfg {
     const int2* node_tasks;  // (problem, node or -1) per node wavefront, kMaxNodeWaves-padded per problem
     const int4* node_info;   // per node task: first child, children, y offset, parent
     int n_node_tasks;
-    int* ticket;             // forward-sweep ticket counter
     int node_wg;             // threads per node workgroup (64, 128, 256, 512)
     int node_lds;            // dynamic LDS bytes of a node workgroup
     int wave_elems;          // LDS elements of one node wavefront
@@ -198,6 +197,34 @@ __host__ __device__ inline int col_need(int K, int O, int V) {
         need = imax(need, 4 * tile_rows(K, G2, V));
     }
     return need;
+}
+
+// Staged sweeps (float): each level's tiles and vectors are copied global ->
+// LDS a level ahead.  A vector slot holds kVecSlot entries (the vector, then
+// copies of its last entry); a tile occupies its own 1 KiB lane groups, with at least
+// one group for block 2 (0 when the shape does not fit class R: that product
+// runs from global memory).
+constexpr int kVecSlot = 64 * kVecPL;
+__host__ __device__ inline int stage_groups(int K, int O, int V, int R) {
+    if (col_need(K, O, V) > R) return 0;
+    const int W1 = O < 64 ? O : 64, G1 = 64 / W1;
+    int g = tile_rows(K, G1, V) / V;
+    if (O > 64) {
+        const int W2 = O - 64, G2 = 64 / W2;
+        g += tile_rows(K, G2, V) / V;
+    } else {
+        g += 1;
+    }
+    return g;
+}
+// LDS elements of a staged sweep wavefront after the vectors: four vector
+// slots and the stage of the larger sweep (bsweep: [Abar|B] and R~^-1 tiles,
+// fsweep: [Abar|B]^T tile), for classes rb (bsweep) and rf (fsweep).
+__host__ __device__ inline int stage_elems(int nx, int nu, int V, int rb, int rf) {
+    const int m = nx + nu;
+    const int gb = stage_groups(nx, m, V, rb) + stage_groups(nu, nu, V, 16);
+    const int gf = stage_groups(m, nx, V, rf);
+    return 4 * kVecSlot + imax(gb, gf) * 64 * V;
 }
 
 }  // namespace spk

@@ -184,10 +184,9 @@ static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
 static void carve(Arena& a, spock_problem* p) {
     p->d_tree = a.take<int>(4LL * p->n + 4);
     p->d_cnt = a.take<int>(p->n);
-    p->d_flag = a.take<int>(p->n);
     p->d_path = a.take<int>((long long)p->n_leaf * (p->N + 1));
     p->d_top = a.take<int>(p->n_leaf);
-    p->d_ticket = a.take<int>(4);  // [0] forward ticket, [1] constant 1 (active flag)
+    p->d_one = a.take<int>(4);  // [0] constant 1: the problem's active flag
     p->d_tasks = a.take<int2>(p->n_leaf);
     p->d_node = a.take<int4>(p->n);
     p->n_ntasks = (p->n + spk::kMaxNodeWaves - 1) / spk::kMaxNodeWaves * spk::kMaxNodeWaves;
@@ -311,8 +310,8 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
 }
 
 // Root-to-leaf path of every leaf, and the first stage of that path whose node
-// has the leaf as its leftmost leaf: the forward task of a leaf computes the
-// path from that stage down, and only waits for the node just above it.
+// has the leaf as its leftmost leaf: the forward task of a leaf computes its
+// whole path and stores the nodes from that stage down.
 static void leaf_paths(const spock_problem* p, std::vector<int>& path, std::vector<int>& top) {
     const int n = p->n, N = p->N;
     std::vector<int> leftmost(n);
@@ -644,10 +643,9 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     h.nz = p->nz;
     h.neta = p->neta;
     h.cnt = p->d_cnt;
-    h.flag = p->d_flag;
     h.path = p->d_path;
     h.top_owned = p->d_top;
-    h.active = p->d_ticket + 1;
+    h.active = p->d_one;
     h.err = p->d_err;
     h.res = p->d_res;
     s.cfg = make_cfg<real>(p, s.cfg.node_wg > 0 ? s.cfg.node_wg : spk::kDefaultWG);
@@ -826,15 +824,16 @@ spk::LaunchCfg make_cfg(const spock_problem* p, int node_wg) {
     c.node_tasks = p->d_ntasks;
     c.node_info = p->d_ninfo;
     c.n_node_tasks = p->n_ntasks;
-    c.ticket = p->d_ticket;
     c.node_wg = node_wg;
     c.node_lds = node_lds_bytes(p, node_wg, (int)sizeof(real));
     c.wave_elems = spk::node_wave_elems(nx, nu, p->nc, p->ncN, p->max_ch);
-    c.sweep_lds = spk::sweep_int_bytes(p->N) + spk::sweep_elems(nx, nu) * (int)sizeof(real);
     c.cls[0] = tile_class(spk::col_need(nu, nx, V));
     c.cls[1] = tile_class(spk::col_need(nx, m, V));
     c.cls[2] = tile_class(spk::col_need(m, nx, V));
     c.cls[3] = tile_class(spk::col_need(nx, nu, V));
+    // float sweeps stage their tiles and vectors in LDS
+    const int staged = sizeof(real) == 4 ? spk::stage_elems(nx, nu, V, c.cls[1], c.cls[2]) : 0;
+    c.sweep_lds = spk::sweep_int_bytes(p->N) + (spk::sweep_elems(nx, nu) + staged) * (int)sizeof(real);
     return c;
 }
 template spk::LaunchCfg make_cfg<double>(const spock_problem*, int);
@@ -1007,10 +1006,10 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
         std::copy(p->first_child.begin(), p->first_child.end(), tree.begin() + p->n);
         std::copy(p->n_ch.begin(), p->n_ch.end(), tree.begin() + 2 * (size_t)p->n);
         std::copy(p->y_off.begin(), p->y_off.end(), tree.begin() + 3 * (size_t)p->n);
-        std::vector<int2> tasks(p->n_leaf);
-        for (int k = 0; k < p->n_leaf; ++k) tasks[k] = make_int2(0, k);
         std::vector<int> path, top;
         leaf_paths(p, path, top);
+        std::vector<int2> tasks(p->n_leaf);
+        for (int k = 0; k < p->n_leaf; ++k) tasks[k] = make_int2(0, k);
         std::vector<int4> node(p->n);
         for (int v = 0; v < p->n; ++v)
             node[v] = make_int4(p->n_ch[v] ? p->first_child[v] : 0, p->n_ch[v], v < p->n_nl ? p->y_off[v] : 0,
@@ -1037,10 +1036,8 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
         }
         // arrival counters, claim flags, the error flag and residual slots start at zero
         e = spk::launch_fill<int>(p->d_cnt, 0, p->n, p->stream);
-        if (e == hipSuccess) e = spk::launch_fill<int>(p->d_flag, 0, p->n, p->stream);
         if (e == hipSuccess) e = spk::launch_fill<int>(p->d_err, 0, 4, p->stream);
-        if (e == hipSuccess) e = spk::launch_fill<int>(p->d_ticket, 0, 1, p->stream);
-        if (e == hipSuccess) e = spk::launch_fill<int>(p->d_ticket + 1, 1, 1, p->stream);
+        if (e == hipSuccess) e = spk::launch_fill<int>(p->d_one, 1, 1, p->stream);
         if (e == hipSuccess) e = spk::launch_fill<unsigned long long>(p->d_res, 0ull, 4, p->stream);
         if (e != hipSuccess) {
             spock_problem_destroy(p);

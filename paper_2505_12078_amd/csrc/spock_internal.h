@@ -94,10 +94,9 @@ struct spock_problem {
     bool owns_stream = false;
     int* d_tree = nullptr;
     int* d_cnt = nullptr;
-    int* d_flag = nullptr;
     int* d_path = nullptr;
     int* d_top = nullptr;
-    int* d_ticket = nullptr;
+    int* d_one = nullptr;      // constant 1 (active flag of the unbatched form)
     int2* d_tasks = nullptr;   // (0, leaf) per sweep wavefront
     int4* d_node = nullptr;    // first child, children, y offset, parent per node
     int2* d_ntasks = nullptr;  // (0, node or -1) per node wavefront
@@ -150,7 +149,6 @@ struct spock_batch {
     int4* ninfo = nullptr;
     int n_ntasks = 0;
     int* active = nullptr;
-    int* ticket = nullptr;
     int* err = nullptr;
     unsigned long long* res = nullptr;
     spk::LaunchCfg cfg64{}, cfg32{};
@@ -176,7 +174,7 @@ template <typename real>
 int32_t batch_tick(spock_batch* b, std::vector<Member>& m, bool stall_exit);
 
 // Launch configuration of one problem in one precision with node workgroups
-// of `node_wg` threads (tasks and ticket are the problem's own).
+// of `node_wg` threads (the tasks are the problem's own).
 template <typename real>
 spk::LaunchCfg make_cfg(const spock_problem* p, int node_wg);
 // Dynamic LDS bytes of a node workgroup of `node_wg` threads for this problem.

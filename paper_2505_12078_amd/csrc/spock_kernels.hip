@@ -14,10 +14,11 @@
 //          parent.  At a node with several children only the wavefront that
 //          arrives last continues (atomic counter), so nothing ever waits.
 //  fsweep  one wavefront per leaf, root -> leaves: x^j = [Abar^j|B^j][x^i; d^i] + c^j
-//          over the path nodes whose leftmost leaf is this leaf.  The wavefront
-//          waits once, for the node above its first one, which belongs to a
-//          wavefront that took its ticket earlier, so the wait always ends; a
-//          bounded spin turns an unexpected stall into an error flag.
+//          along the whole root-to-leaf path.  Paths share their upper nodes:
+//          every wavefront through a node computes the same x^v (same data,
+//          same order), and only the one whose leaf is the node's leftmost
+//          leaf stores it, so no wavefront waits for another (the shared
+//          tiles are read from cache).
 //  dual    one wavefront per node: u = K x + d, then every dual block the node
 //          owns, eta+ = prox_{alpha g*}(eta + alpha L(2 z+ - z)) with the S3
 //          cone projections and Moreau's identity, and on request the
@@ -137,17 +138,6 @@ SPK_DEV real ld_dev(const real* p) {
 SPK_DEV void drain_stores() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_s_waitcnt(0x0F70);
-}
-
-// Wait until a node's forward result is published; false on timeout.
-SPK_DEV bool wait_done(int* flag) {
-    const uint64_t t0 = wall_clock64();
-    unsigned spins = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 2) {
-        __builtin_amdgcn_s_sleep(1);
-        if ((++spins & 1023u) == 0 && wall_clock64() - t0 > 200000000ull) return false;  // ~2 s
-    }
-    return true;
 }
 
 template <typename real>
@@ -287,6 +277,15 @@ SPK_DEV ColShape col_shape(int K, int O) {
     s.G2 = s.W2 > 0 ? 64 / s.W2 : 1;
     s.rows1 = tile_rows(K, s.G1, tile_vec<real>());
     s.rows2 = s.W2 > 0 ? tile_rows(K, s.G2, tile_vec<real>()) : 0;
+    // uniform by construction; say so, so that what derives from it stays scalar
+    s.K = __builtin_amdgcn_readfirstlane(s.K);
+    s.O = __builtin_amdgcn_readfirstlane(s.O);
+    s.W1 = __builtin_amdgcn_readfirstlane(s.W1);
+    s.G1 = __builtin_amdgcn_readfirstlane(s.G1);
+    s.W2 = __builtin_amdgcn_readfirstlane(s.W2);
+    s.G2 = __builtin_amdgcn_readfirstlane(s.G2);
+    s.rows1 = __builtin_amdgcn_readfirstlane(s.rows1);
+    s.rows2 = __builtin_amdgcn_readfirstlane(s.rows2);
     return s;
 }
 
@@ -313,27 +312,27 @@ SPK_DEV void unpack16<double>(u32x4 u, double* dst) {
     dst[1] = __hiloint2double((int)u.w, (int)u.z);
 }
 
-// Every lane loads the full register class unconditionally at fixed offsets:
-// rows past the tile's own read whatever follows it (the next node's tile, or
-// the zero padding the host leaves after every tile array), and col_apply
-// masks every row past K.  With no conditional loads the compiler can count
-// the loads in flight, so a later level's prefetch does not force a wait for
-// everything.
+// Every lane loads the full register class unconditionally: the loads past
+// the tile's own 1 KiB lane groups repeat its last group (the same addresses,
+// so no extra memory traffic), and col_apply masks every row past K.  With no
+// conditional loads the compiler can count the loads in flight, so a later
+// level's prefetch does not force a wait for everything.
 template <typename real, int R>
 SPK_DEV void col_load(ColTile<real, R>& T, const real* __restrict__ tile, const ColShape& s) {
     constexpr int V = 16 / (int)sizeof(real);
     const __attribute__((address_space(1))) u32x4* p =
         (const __attribute__((address_space(1))) u32x4*)tile + lane_id();
+    const int l1 = s.rows1 / V - 1, l2 = s.rows2 > 0 ? s.rows2 / V - 1 : 0;
 #pragma unroll
     for (int q = 0; q < R / V; ++q) {
-        const u32x4 u = p[q * 64];
+        const u32x4 u = p[(q < l1 ? q : l1) * 64];
         unpack16<real>(u, T.a + q * V);
     }
-    // block 2 (when there is none, the rows after block 1, unused)
+    // block 2 (when there is none, the group after block 1, unused)
     p += (s.rows1 / V) * 64;
 #pragma unroll
     for (int q = 0; q < R / 4 / V; ++q) {
-        const u32x4 u = p[q * 64];
+        const u32x4 u = p[(q < l2 ? q : l2) * 64];
         unpack16<real>(u, T.b + q * V);
     }
 }
@@ -346,8 +345,8 @@ SPK_DEV void lds16(const real* p, real* dst) {
 }
 
 // v: K entries (LDS, 16-byte aligned), out: O entries (LDS), red: kRed
-// entries of scratch (LDS).  Rows past the tile's own (rows1 / rows2) hold
-// data of whatever follows the tile and are masked; inside them, entries of
+// entries of scratch (LDS).  Rows past the tile's own (rows1 / rows2) repeat
+// its last lane group (finite data) and are masked; inside them, entries of
 // rows past K and of idle lanes are zero.  kPadded: v is zero from K up to R
 // entries, so the one-group block needs no masks (rows past the tile meet
 // zeros of v; tile data is finite).  The v values a lane needs are read into
@@ -456,6 +455,13 @@ struct ColProd {
         s = sh;
         fit = sh.rows1 <= R && sh.rows2 <= R / 4;
         col_load(T, t, sh);  // unconditional (see col_load); unused when !fit
+    }
+    // staged form: the tile from LDS (st) once its copy has landed
+    SPK_DEV void take(const real* t, const ColShape& sh, const real* st) {
+        tile = t;
+        s = sh;
+        fit = sh.rows1 <= R && sh.rows2 <= R / 4;
+        if (fit) col_take(T, st, sh);
     }
     // kPadded: v is zero from K up to kVecPad entries (see col_apply)
     template <bool kPadded = false>
@@ -749,11 +755,10 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
 template <typename real, int R>
 __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ probs,
                                               const int2* __restrict__ ntasks, const int4* __restrict__ ninfo,
-                                              int* __restrict__ ticket, int wave_elems, int par, int check) {
+                                              int wave_elems, int par, int check) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real* sm = reinterpret_cast<real*>(smem_raw);
     const int waves = (int)(blockDim.x >> 6), w = (int)(threadIdx.x >> 6), lane = lane_id();
-    if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;  // forward-sweep tickets restart
     const int2 t0 = ntasks[blockIdx.x * waves];
     // this wavefront's node and its first child, children, y offset (loaded
     // with the task, not after it)
@@ -1049,7 +1054,6 @@ __global__ __launch_bounds__(64) void k_bsweep(const ProbDev<real>* __restrict__
             }
             wave_sync();
         }
-        if (lane == 0) gm(P->flag)[i] = 0;  // forward-sweep flags restart
 #pragma unroll
         for (int q = 0; q < kVecPL; ++q) {
             const int r = lane + 64 * q;
@@ -1087,49 +1091,28 @@ struct FLevel {
 
 template <typename real, int R>
 __global__ __launch_bounds__(64) void k_fsweep(const ProbDev<real>* __restrict__ probs,
-                                               const int2* __restrict__ tasks, int n_tasks,
-                                               int* __restrict__ ticket, int par) {
+                                               const int2* __restrict__ tasks, int par) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int lane = lane_id();
-    // Tickets hand out tasks in start order, so a wavefront only ever waits
-    // on a wavefront that started before it.
-    int task = 0;
-    if (lane == 0) task = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    task = __shfl(task, 0, 64);
-    if (task >= n_tasks) return;
-    const int2 tk = tasks[task];
+    const int2 tk = tasks[blockIdx.x];
     const ProbDev<real>* __restrict__ P = probs + tk.x;
     if (*P->active == 0) return;
     const int N = P->N, nx = P->nx, nu = P->nu, m = P->m, n_nl = P->n_nl;
     real* __restrict__ zout = P->z[par ^ 1];
     int* s_node = reinterpret_cast<int*>(smem_raw);
-    int* s_nch = s_node + (N + 1);
     real* red = reinterpret_cast<real*>(smem_raw + sweep_int_bytes(N));
     real* av = red + kRed;          // [x^anc ; d^anc] (m)
     real* xv = av + sweep_vec(m);   // x of the current node (nx)
     for (int e = lane; e < sweep_elems(nx, nu); e += 64) red[e] = real(0);
 
-    // this task computes the path nodes from stage L down to its leaf; the
-    // node above them belongs to the task of its leftmost leaf
+    // This task computes its whole root-to-leaf path and stores the nodes it
+    // owns (stages L..N, those whose leftmost leaf it is); every other task
+    // through a node computes the same x^v, bit for bit, and drops it.
     const int L = gm(P->top_owned)[tk.y];
     const auto* path = gm(P->path) + (long long)tk.y * (N + 1);
-    for (int q = (L > 0 ? L - 1 : 0) + lane; q <= N; q += 64) {
-        const int v = path[q];
-        s_node[q] = v;
-        s_nch[q] = v < n_nl ? gm(P->n_ch)[v] : 0;
-    }
+    for (int q = lane; q <= N; q += 64) s_node[q] = path[q];
     wave_sync();
     const ColShape sT = col_shape<real>(m, nx);
-    auto publish = [&](int v, int lev) {
-        if (v < n_nl && s_nch[lev] > 1) {
-            // children owned by other tasks read x^v: publish it
-            for (int r = lane; r < nx; r += 64) st_dev(zout + P->z_x + (long long)v * nx + r, xv[r]);
-            drain_stores();
-            if (lane == 0) st_dev(P->flag + v, 2);
-        } else {
-            for (int r = lane; r < nx; r += 64) gm(zout)[P->z_x + (long long)v * nx + r] = xv[r];
-        }
-    };
     // every load unconditional: without an affine term c is read from x0 and
     // a leaf reads the last non-leaf d, both unused
     auto load_level = [&](FLevel<real, R>& F, int v) {
@@ -1141,57 +1124,34 @@ __global__ __launch_bounds__(64) void k_fsweep(const ProbDev<real>* __restrict__
     // where the registers allow it.
     constexpr bool kDB = (sizeof(real) == 4 && R <= 64) || R <= 32;
     FLevel<real, R> A, B;
-    int lev = L;
-    if (L == 0) {
-        // the root's state is the initial state
-        if (N >= 1) load_level(A, s_node[1]);
-        for (int r = lane; r < nx; r += 64) xv[r] = gm(P->x0)[r];
-        wave_sync();
-        publish(0, 0);
-        for (int r = lane; r < nx; r += 64) av[r] = xv[r];
-        for (int r = lane; r < nu; r += 64) av[nx + r] = gm(P->d)[r];
-        lev = 1;
-    } else {
-        // the first owned node's data loads overlap the wait
-        load_level(A, s_node[L]);
-        const int pn = s_node[L - 1];
-        int ok = 1;
-        if (lane == 0 && !wait_done(&P->flag[pn])) {
-            atomicExch(P->err, 1);
-            ok = 0;
-        }
-        ok = __shfl(ok, 0, 64);
-        if (!ok) return;
-        for (int r = lane; r < nx; r += 64) av[r] = ld_dev(zout + P->z_x + (long long)pn * nx + r);
-        for (int r = lane; r < nu; r += 64) av[nx + r] = gm(P->d)[(long long)pn * nu + r];
+    // the root's state is the initial state
+    for (int r = lane; r < nx; r += 64) {
+        const real x = gm(P->x0)[r];
+        av[r] = x;
+        if (L == 0) gm(zout)[P->z_x + r] = x;
     }
-    const int first = lev;  // its data is loaded already
+    for (int r = lane; r < nu; r += 64) av[nx + r] = gm(P->d)[r];
+    if (N >= 1) load_level(A, s_node[1]);
     wave_sync();
     // one level with the data set `cur`, the next level's data loading into `nxt`
     auto level = [&](FLevel<real, R>& cur, FLevel<real, R>& nxt, int lv) {
         const int v = s_node[lv];
         if (kDB) load_level(nxt, s_node[lv < N ? lv + 1 : N]);
-        if (!kDB && lv > first) load_level(cur, v);
+        if (!kDB && lv > 1) load_level(cur, v);
         cur.TM.template apply<true>(av, xv, red);  // x^v = [Abar^v | B^v] [x^anc; d^anc]
-        if (P->affine) {
 #pragma unroll
-            for (int q = 0; q < kVecPL; ++q) {
-                const int r = lane + 64 * q;
-                if (r < nx) xv[r] += cur.cr[q];
+        for (int q = 0; q < kVecPL; ++q) {
+            const int r = lane + 64 * q;
+            if (r < nx) {
+                const real x = xv[r] + (P->affine ? cur.cr[q] : real(0));
+                av[r] = x;
+                if (lv >= L) gm(zout)[P->z_x + (long long)v * nx + r] = x;
             }
+            if (r < nu) av[nx + r] = cur.dr[q];
         }
         wave_sync();
-        publish(v, lv);
-        if (v < n_nl) {
-#pragma unroll
-            for (int q = 0; q < kVecPL; ++q) {
-                const int r = lane + 64 * q;
-                if (r < nx) av[r] = xv[r];
-                if (r < nu) av[nx + r] = cur.dr[q];
-            }
-            wave_sync();
-        }
     };
+    int lev = 1;
     if constexpr (kDB) {
         for (; lev <= N; lev += 2) {
             level(A, B, lev);
@@ -1201,6 +1161,320 @@ __global__ __launch_bounds__(64) void k_fsweep(const ProbDev<real>* __restrict__
     } else {
         for (; lev <= N; ++lev) level(A, A, lev);
     }
+}
+
+// ---------------------------------------------------------------------------
+// staged sweeps (float): global -> LDS copies a level ahead
+// ---------------------------------------------------------------------------
+//
+// Same recursions as k_bsweep / k_fsweep.  Every tile and vector a level
+// needs is copied to LDS with global-to-LDS loads while the level before it
+// runs, and moved into registers (tiles) only when the level starts, so one
+// tile is ever held in registers and no prefetch waits on register pressure.
+// The copies are written in assembly: the compiler neither counts nor waits
+// for them, and each consumer waits for them explicitly (vm_wait).  No load
+// that the compiler waits for is issued after a copy that is still wanted in
+// flight (its wait would cover the copy too).
+
+// LDS byte address of a pointer into dynamic LDS.
+SPK_DEV unsigned lds_off(const void* p) {
+    return (unsigned)(size_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// A uniform value or address, held in scalar registers.
+SPK_DEV unsigned uni(unsigned x) { return (unsigned)__builtin_amdgcn_readfirstlane((int)x); }
+SPK_DEV const void* uni(const void* p) {
+    const unsigned long long a = (unsigned long long)p;
+    return (const void*)(((unsigned long long)uni((unsigned)(a >> 32)) << 32) | uni((unsigned)a));
+}
+
+// Global-to-LDS loads: lane l reads 16 (dma16) or 4 (dma4) bytes at
+// base + voff (+ k KiB) and writes them at lds + 16 l (+ 4 l) (+ k KiB);
+// base and lds are uniform.  M0 carries lds and is restored.  dma16x4 copies
+// four consecutive 1 KiB lane groups with one address set-up.
+SPK_DEV void dma16(const void* base, unsigned voff, unsigned lds) {
+    unsigned save;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %3\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %1, %2\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(save)
+        : "v"(voff), "s"(uni(base)), "s"(uni(lds))
+        : "memory");
+}
+SPK_DEV void dma16x4(const void* base, unsigned voff, unsigned lds) {
+    unsigned save;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %3\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %1, %2\n\t"
+        "global_load_lds_dwordx4 %1, %2 offset:1024\n\t"
+        "global_load_lds_dwordx4 %1, %2 offset:2048\n\t"
+        "global_load_lds_dwordx4 %1, %2 offset:3072\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(save)
+        : "v"(voff), "s"(uni(base)), "s"(uni(lds))
+        : "memory");
+}
+SPK_DEV void dma4(const void* base, unsigned voff, unsigned lds) {
+    unsigned save;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %3\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dword %1, %2\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(save)
+        : "v"(voff), "s"(uni(base)), "s"(uni(lds))
+        : "memory");
+}
+
+// Wait until at most N of this wavefront's vector memory operations are in
+// flight (they complete in issue order), then order the LDS accesses after it.
+template <int N>
+SPK_DEV void vm_wait() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+    wave_sync();
+}
+// Wait for this wavefront's LDS reads (before a copy overwrites what they read).
+SPK_DEV void lgkm_wait() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    wave_sync();
+}
+
+// The tile's own lane groups to LDS, in the same layout (block 2, or one
+// group after block 1 when there is none, follows block 1).  Nothing is
+// copied when the shape does not fit class R.
+template <typename real, int R>
+SPK_DEV void col_dma(const real* __restrict__ tile, const ColShape& s, real* st) {
+    constexpr int V = 16 / (int)sizeof(real);
+    if (s.rows1 > R || s.rows2 > R / 4) return;
+    const int G = s.rows1 / V + (s.rows2 > 0 ? s.rows2 / V : 1);
+    const unsigned voff = (unsigned)lane_id() * 16;
+    const char* t = reinterpret_cast<const char*>(tile);
+    const unsigned base = lds_off(st);
+    int g = 0;
+    for (; g + 4 <= G; g += 4) dma16x4(t + (long long)g * 1024, voff, base + g * 1024);
+    for (; g < G; ++g) dma16(t + (long long)g * 1024, voff, base + g * 1024);
+}
+
+// A staged tile from LDS into registers (the layout of col_load).
+template <typename real, int R>
+SPK_DEV void col_take(ColTile<real, R>& T, const real* st, const ColShape& s) {
+    constexpr int V = 16 / (int)sizeof(real);
+    const int lane = lane_id();
+    const int g1 = s.rows1 / V, l1 = g1 - 1, l2 = s.rows2 > 0 ? s.rows2 / V - 1 : 0;
+#pragma unroll
+    for (int q = 0; q < R / V; ++q) lds16(st + ((q < l1 ? q : l1) * 64 + lane) * V, T.a + q * V);
+    st += g1 * 64 * V;
+#pragma unroll
+    for (int q = 0; q < R / 4 / V; ++q) lds16(st + ((q < l2 ? q : l2) * 64 + lane) * V, T.b + q * V);
+}
+
+// n >= 1 entries of src into an LDS slot (entries past n up to the next
+// multiple of 256 bytes: copies of the last dword).
+template <typename real>
+SPK_DEV void vec_dma(const real* src, int n, real* dst) {
+    const int lane = lane_id();
+    const unsigned base = lds_off(dst);
+    const int nd = n * (int)(sizeof(real) / 4);
+    for (int q = 0; q * 64 < nd; ++q) {
+        const int e = q * 64 + lane;
+        dma4(src, (unsigned)(e < nd ? e : nd - 1) * 4, base + q * 256);
+    }
+}
+
+template <typename real, int R>
+__global__ __launch_bounds__(64) void k_bsweep_st(const ProbDev<real>* __restrict__ probs,
+                                                  const int2* __restrict__ tasks) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    constexpr int V = tile_vec<real>();
+    const int lane = lane_id();
+    const int2 tk = tasks[blockIdx.x];
+    const ProbDev<real>* __restrict__ P = probs + tk.x;
+    if (*P->active == 0) return;
+    const int N = P->N, nx = P->nx, nu = P->nu, m = P->m;
+    int* s_node = reinterpret_cast<int*>(smem_raw);
+    int* s_nch = s_node + (N + 1);
+    int* s_fc = s_nch + (N + 1);
+    real* red = reinterpret_cast<real*>(smem_raw + sweep_int_bytes(N));
+    real* hv = red + kRed;          // h of the current node (nx)
+    real* gv = hv + sweep_vec(m);   // message (m)
+    real* wv = gv + sweep_vec(m);   // ubar - g_u (nu)
+    real* dv = wv + sweep_vec(nu);  // d (nu)
+    real* vs = red + sweep_elems(nx, nu);
+    real* h0s[2] = {vs, vs + 2 * kVecSlot};  // h0 of the level, two slots
+    real* ubs[2] = {vs + kVecSlot, vs + 3 * kVecSlot};
+    const ColShape sM = col_shape<real>(nx, m), sR = col_shape<real>(nu, nu);
+    real* stM = vs + 4 * kVecSlot;  // staged [Abar|B] tile
+    real* stR = stM + stage_groups(nx, m, V, R) * 64 * V;  // staged R~^-1 tile
+    for (int e = lane; e < sweep_elems(nx, nu); e += 64) red[e] = real(0);
+
+    const auto* path = gm(P->path) + (long long)tk.y * (N + 1);
+    for (int q = lane; q <= N; q += 64) {
+        const int v = path[q];
+        const auto* ni = gm(reinterpret_cast<const int*>(P->node + v));  // first child, children
+        s_node[q] = v;
+        s_nch[q] = v < P->n_nl ? ni[1] : 0;
+        s_fc[q] = ni[0];
+    }
+    wave_sync();
+    ColProd<real, R> TM;
+    ColProd<real, 16> TR;
+    // level data of node i into slot b (the root stages node 1's [Abar|B], unused)
+    auto stage = [&](int i, int b) {
+        col_dma<real, R>(P->T2M + (i > 0 ? i : 1) * P->T2M_stride, sM, stM);
+        col_dma<real, 16>(P->T2R + i * P->T2R_stride, sR, stR);
+        vec_dma(P->h0 + (long long)i * nx, nx, h0s[b]);
+        vec_dma(P->ub + (long long)i * nu, nu, ubs[b]);
+    };
+    int j = s_node[N];
+    // the leaf's message [Abar^j|B^j]^T h0^j (its h0 through slot 1)
+    col_dma<real, R>(P->T2M + j * P->T2M_stride, sM, stM);
+    vec_dma(P->h0 + (long long)j * nx, nx, h0s[1]);
+    vm_wait<0>();
+    TM.take(P->T2M + j * P->T2M_stride, sM, stM);
+    for (int r = lane; r < nx; r += 64) hv[r] = h0s[1][r];
+    lgkm_wait();
+    if (N >= 1) stage(s_node[N - 1], 0);
+    TM.template apply<true>(hv, gv, red);
+    int b = 0;
+    for (int lev = N - 1; lev >= 0; --lev, b ^= 1) {
+        const int i = s_node[lev], k = s_nch[lev], fc = s_fc[lev];
+        real mv[kMsgFast][2];
+        if (k > 1) {
+            for (int c = lane; c < m; c += 64) st_dev(P->e + (long long)j * m + c, gv[c]);
+            // the message stores (and every copy issued so far) complete
+            // before the arrival is counted
+            drain_stores();
+            int prev = 0;
+            if (lane == 0) prev = __hip_atomic_fetch_add(gm(P->cnt) + i, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            prev = __shfl(prev, 0, 64);
+            if (prev != k - 1) return;
+            if (lane == 0) gm(P->cnt)[i] = 0;  // the next launch reuses the counter
+            if (k <= kMsgFast) {
+#pragma unroll
+                for (int q = 0; q < kMsgFast; ++q) {
+                    const real* e = P->e + (long long)(fc + (q < k ? q : k - 1)) * m;
+                    mv[q][0] = ld_dev(e + (lane < m ? lane : m - 1));
+                    mv[q][1] = ld_dev(e + (64 + lane < m ? 64 + lane : m - 1));
+                }
+            }
+        } else if (lev == N - 1) {
+            vm_wait<0>();
+        } else {
+            // only the previous level's d store (at least one) may be younger
+            // than this level's copies
+            vm_wait<1>();
+        }
+        TM.take(P->T2M + (i > 0 ? i : 1) * P->T2M_stride, sM, stM);
+        TR.take(P->T2R + i * P->T2R_stride, sR, stR);
+        lgkm_wait();
+        // the next level's copies: right away on a single-child level, after
+        // the messages arrived otherwise (their wait would cover the copies)
+        if (k == 1 && lev > 0) stage(s_node[lev - 1], b ^ 1);
+        if (k > 1) {
+            // summed in child order
+            if (k <= kMsgFast) {
+                real s0 = 0, s1 = 0;
+#pragma unroll
+                for (int q = 0; q < kMsgFast; ++q)
+                    if (q < k) {
+                        s0 += mv[q][0];
+                        s1 += mv[q][1];
+                    }
+                if (lane < m) gv[lane] = s0;
+                if (64 + lane < m) gv[64 + lane] = s1;
+                for (int c = 128 + lane; c < m; c += 64) {
+                    real sum = 0;
+                    for (int q = 0; q < k; ++q) sum += ld_dev(P->e + (long long)(fc + q) * m + c);
+                    gv[c] = sum;
+                }
+            } else {
+                for (int c = lane; c < m; c += 64) {
+                    real sum = 0;
+                    for (int q = 0; q < k; ++q) sum += ld_dev(P->e + (long long)(fc + q) * m + c);
+                    gv[c] = sum;
+                }
+            }
+            wave_sync();
+            if (lev > 0) stage(s_node[lev - 1], b ^ 1);
+        }
+        for (int r = lane; r < nx; r += 64) hv[r] = h0s[b][r] + gv[r];
+        for (int r = lane; r < nu; r += 64) wv[r] = ubs[b][r] - gv[nx + r];
+        wave_sync();
+        TR.template apply<true>(wv, dv, red);  // d^i = R~^-1 (ubar - g_u)
+        for (int r = lane; r < nu; r += 64) gm(P->d)[(long long)i * nu + r] = dv[r];
+        if (i > 0) TM.template apply<true>(hv, gv, red);  // message of i: [Abar^i|B^i]^T h^i
+        j = i;
+    }
+    vm_wait<0>();  // no copy outlives the wavefront
+}
+
+template <typename real, int R>
+__global__ __launch_bounds__(64) void k_fsweep_st(const ProbDev<real>* __restrict__ probs,
+                                                  const int2* __restrict__ tasks, int par) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int lane = lane_id();
+    const int2 tk = tasks[blockIdx.x];
+    const ProbDev<real>* __restrict__ P = probs + tk.x;
+    if (*P->active == 0) return;
+    const int N = P->N, nx = P->nx, nu = P->nu, m = P->m, n_nl = P->n_nl;
+    real* __restrict__ zout = P->z[par ^ 1];
+    int* s_node = reinterpret_cast<int*>(smem_raw);
+    real* red = reinterpret_cast<real*>(smem_raw + sweep_int_bytes(N));
+    real* av = red + kRed;          // [x^anc ; d^anc] (m)
+    real* xv = av + sweep_vec(m);   // x of the current node (nx)
+    real* vs = red + sweep_elems(nx, nu);
+    real* cs[2] = {vs, vs + 2 * kVecSlot};  // c of the level, two slots
+    real* ds[2] = {vs + kVecSlot, vs + 3 * kVecSlot};  // d of the level
+    real* stT = vs + 4 * kVecSlot;  // staged [Abar|B]^T tile
+    for (int e = lane; e < sweep_elems(nx, nu); e += 64) red[e] = real(0);
+
+    // the whole root-to-leaf path, stores from stage L on (see k_fsweep)
+    const int L = gm(P->top_owned)[tk.y];
+    const auto* path = gm(P->path) + (long long)tk.y * (N + 1);
+    for (int q = lane; q <= N; q += 64) s_node[q] = path[q];
+    const ColShape sT = col_shape<real>(m, nx);
+    ColProd<real, R> TM;
+    // level data of node v into slot b (a leaf stages an unused d)
+    auto stage = [&](int v, int b) {
+        col_dma<real, R>(P->T3 + v * P->T3_stride, sT, stT);
+        if (P->affine) vec_dma(P->c + (long long)v * nx, nx, cs[b]);
+        vec_dma(P->d + (long long)(v < n_nl ? v : n_nl - 1) * nu, nu, ds[b]);
+    };
+    // the root's state is the initial state (read before any copy)
+    for (int r = lane; r < nx; r += 64) {
+        const real x = gm(P->x0)[r];
+        av[r] = x;
+        if (L == 0) gm(zout)[P->z_x + r] = x;
+    }
+    for (int r = lane; r < nu; r += 64) av[nx + r] = gm(P->d)[r];
+    wave_sync();
+    if (N >= 1) stage(s_node[1], 0);
+    for (int lev = 1, b = 0; lev <= N; ++lev, b ^= 1) {
+        const int v = s_node[lev];
+        // this level's copies have landed (the previous level's stores of x,
+        // if any, may still be in flight)
+        if (lev > 1 && lev - 1 >= L) vm_wait<1>();
+        else vm_wait<0>();
+        TM.take(P->T3 + v * P->T3_stride, sT, stT);
+        lgkm_wait();
+        if (lev < N) stage(s_node[lev + 1], b ^ 1);
+        TM.template apply<true>(av, xv, red);  // x^v = [Abar^v | B^v] [x^anc; d^anc]
+        for (int r = lane; r < nx; r += 64) {
+            const real x = xv[r] + (P->affine ? cs[b][r] : real(0));
+            av[r] = x;
+            if (lev >= L) gm(zout)[P->z_x + (long long)v * nx + r] = x;
+        }
+        for (int r = lane; r < nu; r += 64) av[nx + r] = ds[b][r];
+        wave_sync();
+    }
+    vm_wait<0>();  // no copy outlives the wavefront
 }
 
 // ---------------------------------------------------------------------------
@@ -1516,15 +1790,23 @@ static hipError_t launch_phase_r(const ProbDev<real>* probs, const LaunchCfg& c,
     switch (phase) {
         case 0:
             hipLaunchKernelGGL((k_prep<real, R>), dim3(c.n_node_tasks / waves), dim3(c.node_wg), c.node_lds, st,
-                               probs, c.node_tasks, c.node_info, c.ticket, c.wave_elems, par, check);
+                               probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
             break;
         case 1:
-            hipLaunchKernelGGL((k_bsweep<real, R>), dim3(c.n_leaf_tasks), dim3(64), c.sweep_lds, st, probs,
-                               c.leaf_tasks);
+            if constexpr (sizeof(real) == 4)
+                hipLaunchKernelGGL((k_bsweep_st<real, R>), dim3(c.n_leaf_tasks), dim3(64), c.sweep_lds, st, probs,
+                                   c.leaf_tasks);
+            else
+                hipLaunchKernelGGL((k_bsweep<real, R>), dim3(c.n_leaf_tasks), dim3(64), c.sweep_lds, st, probs,
+                                   c.leaf_tasks);
             break;
         case 2:
-            hipLaunchKernelGGL((k_fsweep<real, R>), dim3(c.n_leaf_tasks), dim3(64), c.sweep_lds, st, probs,
-                               c.leaf_tasks, c.n_leaf_tasks, c.ticket, par);
+            if constexpr (sizeof(real) == 4)
+                hipLaunchKernelGGL((k_fsweep_st<real, R>), dim3(c.n_leaf_tasks), dim3(64), c.sweep_lds, st, probs,
+                                   c.leaf_tasks, par);
+            else
+                hipLaunchKernelGGL((k_fsweep<real, R>), dim3(c.n_leaf_tasks), dim3(64), c.sweep_lds, st, probs,
+                                   c.leaf_tasks, par);
             break;
         default:
             hipLaunchKernelGGL((k_dual<real, R>), dim3(c.n_node_tasks / waves), dim3(c.node_wg), c.node_lds, st,
