@@ -192,6 +192,76 @@ def _profile_pass(steps):
     P.close()
 
 
+def summarize_counters(fetch_dir, write_dir, trace_dir, profile_json):
+    """Per-launch HBM traffic of the four kernels from two rocprofv3 counter
+    runs of `bench.py --profile` (FETCH_SIZE, WRITE_SIZE; KiB per dispatch),
+    scaled by what the same counters read for the 1 GiB device copy of that
+    run, next to the algorithmic bytes and the kernel-trace durations.  Writes
+    profiles/traffic.json and prints a markdown table."""
+    import csv
+    import glob
+    import re
+
+    pat = re.compile(r"k_(prep|bsweep|fsweep|dual)(?:_st)?<(float|double), (\d+)>")
+
+    def rows(d, suffix):
+        out = []
+        for f in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+            with open(f) as fh:
+                out.extend(csv.DictReader(fh))
+        return out
+
+    def per_kernel(d, counter):
+        vals, names, copy = {}, {}, 0.0
+        for r in rows(d, "counter_collection.csv"):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+            if "copyBuffer" in r["Kernel_Name"]:
+                copy = max(copy, v)
+                continue
+            m = pat.search(r["Kernel_Name"])
+            if m:
+                key = "k_%s<%s>" % (m.group(1), m.group(2))
+                vals.setdefault(key, []).append(v)
+                names[key] = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        return {k: sum(v) / len(v) for k, v in vals.items()}, names, copy
+
+    fetch, names, copy_f = per_kernel(fetch_dir, "FETCH_SIZE")
+    write, _, copy_w = per_kernel(write_dir, "WRITE_SIZE")
+    with open(profile_json) as fh:
+        prof = json.loads(fh.read().strip().splitlines()[-1])
+    copy_bytes = prof["copy_bytes"]
+    ff, wf = copy_bytes / (copy_f * 1024.0), copy_bytes / (copy_w * 1024.0)
+    avg_us = {}
+    for r in rows(trace_dir, "kernel_stats.csv"):
+        m = pat.search(r["Name"])
+        if m:
+            avg_us["k_%s<%s>" % (m.group(1), m.group(2))] = float(r["AverageNs"]) / 1e3
+    out = {"workload": WORKLOAD, "source_hash": prof["source_hash"],
+           "calibration": {"copy_bytes": copy_bytes, "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
+           "kernels": {}}
+    print("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB (calibrated) | algorithmic MB | ratio | avg us (trace) |")
+    print("|---|---|---|---|---|---|---|")
+    for prec, tag in (("float", "bytes_f32"), ("double", "bytes_f64")):
+        for kn in KERNELS:
+            key = "k_%s<%s>" % (kn, prec)
+            if key not in fetch or key not in write:
+                continue
+            fb, wb = fetch[key] * 1024.0 * ff, write[key] * 1024.0 * wf
+            alg = prof[tag][kn]
+            out["kernels"][key] = {"kernel": names.get(key, key), "fetch_bytes": int(fb), "write_bytes": int(wb),
+                                   "bytes_per_launch": int(fb + wb), "algorithmic_bytes": alg,
+                                   "ratio_to_algorithmic": round((fb + wb) / alg, 3), "avg_us_trace": avg_us.get(key)}
+            print("| %s | %.1f | %.1f | %.1f | %.1f | %.2f | %s |" % (
+                names.get(key, key), fetch[key], write[key], (fb + wb) / 1e6, alg / 1e6, (fb + wb) / alg,
+                "%.1f" % avg_us[key] if key in avg_us else "-"))
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("calibration: fetch x%.4f, write x%.4f (1 GiB copy reads FETCH_SIZE %.0f KiB, WRITE_SIZE %.0f KiB)" % (
+        ff, wf, copy_f, copy_w))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,7 +276,12 @@ def main():
     ap.add_argument("--cpu-baseline-only", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: K steps per precision and a 1 GiB device copy")
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "TRACE_DIR", "PROFILE_JSON"),
+                    help="write profiles/traffic.json from rocprofv3 output of --profile runs (no GPU needed)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.cpu_baseline_only:
         _cpu_baseline_only(args.cpu_steps)
         return

@@ -52,21 +52,47 @@ constexpr int kHookWG = 256;  // workgroup size of the per-node hook kernels
 // wavefront and workgroup helpers
 // ---------------------------------------------------------------------------
 
+// Cross-lane moves inside rows of 16 lanes (DPP): CTRL 0xB1 / 0x4E swap lanes
+// 1 / 2 apart within quads, 0x141 mirrors each half row, 0x140 each row.
+// Every lane of the wavefront must be active.
+template <int CTRL>
+SPK_DEV float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+SPK_DEV double dpp(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Lane l's value (uniform result).
+SPK_DEV float lane_value(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+SPK_DEV double lane_value(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the wavefront in a fixed order, the same value in every lane:
+// quads, half rows and rows by DPP, then the four row sums.  Every lane of the
+// wavefront must be active.
 template <typename T>
 SPK_DEV T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp<0xB1>(v);
+    v += dpp<0x4E>(v);
+    v += dpp<0x141>(v);
+    v += dpp<0x140>(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 template <typename T>
 SPK_DEV T wave_max(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        T w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    return v;
+    v = fmax(v, dpp<0xB1>(v));
+    v = fmax(v, dpp<0x4E>(v));
+    v = fmax(v, dpp<0x141>(v));
+    v = fmax(v, dpp<0x140>(v));
+    return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
 }
 
 // Sum over the workgroup, same value returned to every thread; deterministic.
@@ -123,6 +149,11 @@ SPK_DEV __attribute__((address_space(1))) T* gm(T* p) {
 template <typename T>
 SPK_DEV const __attribute__((address_space(1))) T* gm(const T* p) {
     return (const __attribute__((address_space(1))) T*)p;
+}
+
+template <typename T>
+SPK_DEV const __attribute__((address_space(3))) T* lds(const T* p) {
+    return (const __attribute__((address_space(3))) T*)p;
 }
 
 template <typename real>
@@ -553,7 +584,7 @@ SPK_DEV void fwd_block_c(const ProbDev<real>* __restrict__ P, int v, const real*
     for (int r = lane; r < nc; r += 64) {
         const real eb = V.blk[r];
         const real ep = r < nbox ? moreau_box(eb, alpha, V.C.lo[r], V.C.hi[r]) : eb * cb;
-        eout[off + r] = ep;
+        gm(eout)[off + r] = ep;
         const real de = ec[r] - ep;
         if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
         V.dblk[r] = de;
@@ -570,15 +601,15 @@ SPK_DEV void fwd_block_c(const ProbDev<real>* __restrict__ P, int v, const real*
 }
 
 // eta_y in (K^i)* = R^{2k}_+ x R and eta_s in R_+ (one wavefront), from staged
-// eta_y (ey), eta_s (es), new and old y (yn, yv) and s (sn, sv), probabilities p.
-template <typename real>
-SPK_DEV void fwd_block_risk(const ProbDev<real>* __restrict__ P, int v, int k, const real* ey, real es,
-                            const real* yn, const real* yv, real sn, real sv, const real* p,
+// eta_y (ey), eta_s (es), new and old y (yn, yv) and s (sn, sv), probabilities p;
+// yo: start of y^v in the y block.
+template <typename real, typename PT>
+SPK_DEV void fwd_block_risk(const ProbDev<real>* __restrict__ P, int v, long long yo, int k, PT ey, real es,
+                            PT yn, PT yv, real sn, real sv, PT p,
                             real* __restrict__ eout, int check, real& r1, real& r2) {
     const int lane = threadIdx.x & 63;
     const real alpha = P->alpha, ialpha = real(1) / alpha;
-    const long long yo = P->y_off[v];
-    real bn = 0, bo = 0;  // b^T y with b = (p, 0, 1)
+        real bn = 0, bo = 0;  // b^T y with b = (p, 0, 1)
     for (int c = lane; c < k; c += 64) {
         bn += p[c] * yn[c];
         bo += p[c] * yv[c];
@@ -589,11 +620,11 @@ SPK_DEV void fwd_block_risk(const ProbDev<real>* __restrict__ P, int v, int k, c
     const real ebs = es + alpha * (real(2) * wsn - wso);
     const real eps_ = ebs < 0 ? ebs : real(0);
     const real des = es - eps_;
-    if (lane == 0) eout[P->e_s + v] = eps_;
+    if (lane == 0) gm(eout)[P->e_s + v] = eps_;
     for (int c = lane; c < 2 * k + 1; c += 64) {
         const real eb = ey[c] + alpha * (real(2) * yn[c] - yv[c]);
         const real ep = c < 2 * k ? (eb < 0 ? eb : real(0)) : real(0);
-        eout[P->e_y + yo + c] = ep;
+        gm(eout)[P->e_y + yo + c] = ep;
         if (check) {
             const real de = ey[c] - ep;
             const real dy = yv[c] - yn[c];
@@ -611,8 +642,8 @@ SPK_DEV void fwd_block_risk(const ProbDev<real>* __restrict__ P, int v, int k, c
 // SOC block of the edge into child j of non-leaf node v:
 // (Q^1/2 x^v, R^1/2 u^v, tau^j / 2, tau^j / 2) in SOC + a (one wavefront);
 // es: staged eta_soc of that edge, tn / tv: new / old tau^j.
-template <typename real>
-SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, const real* es, real tn, real tv,
+template <typename real, typename PT>
+SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, real tn, real tv,
                            real* __restrict__ eout, const FwdNode<real>& V, int check, real& r1, real& r2) {
     const int lane = threadIdx.x & 63;
     const int nx = P->nx, m = P->m;
@@ -644,7 +675,7 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, const rea
     soc_moreau_coef(nw2, V.blk[m + 1], cw, ct);
     for (int r = lane; r < m + 2; r += 64) {
         const real ep = r <= m ? V.blk[r] * cw : ct;
-        eout[off + r] = ep;
+        gm(eout)[off + r] = ep;
         const real de = es[r] - ep;
         if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
         V.dblk[r] = de;
@@ -694,7 +725,7 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
         for (int r = lane; r < P->ncN; r += 64) {
             const real eb = V.blk[r];
             const real ep = r < nx ? moreau_box(eb, alpha, V.C.loN[r], V.C.hiN[r]) : eb * cb;
-            eout[off + r] = ep;
+            gm(eout)[off + r] = ep;
             const real de = ec[r] - ep;
             if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
             V.dblk[r] = de;
@@ -732,7 +763,7 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
         soc_moreau_coef(nw2, V.blk[nx + 1], cw, ct);
         for (int r = lane; r < nx + 2; r += 64) {
             const real ep = r <= nx ? V.blk[r] * cw : ct;
-            eout[off + r] = ep;
+            gm(eout)[off + r] = ep;
             const real de = es[r] - ep;
             if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
             V.dblk[r] = de;
@@ -816,15 +847,9 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         const real* ec = st + off[2];
         const real es = st[off[5]];
         const real* spc = st + off[11];
-        // per-child inputs: staged copies or the arrays themselves
-        const real* soc = sk ? st + off[3] : g_soc;
-        const real* ey = sk ? st + off[4] : ein + P->e_y + yo;
-        const real* zy = sk ? st + off[6] : zin + P->z_y + yo;
-        const real* zt = sk ? st + off[7] : zin + P->z_tau + fc - 1;
-        const real* zs = sk ? st + off[8] : zin + P->z_s + fc - 1;
-        const real* cs = sk ? st + off[9] : g_cs;
-        const real* pr = sk ? st + off[10] : P->prob + fc;
-
+        // per-child inputs: the staged copies, or for a wide node the arrays
+        // themselves, each through a pointer of its own address space
+        auto per_child = [&](auto soc, auto ey, auto zy, auto zt, auto zs, auto cs, auto pr) {
         // zbar on (x^v, u^v): L* gathers the constraint rows and the SOC rows
         // of every child edge (Sec. 4.4)
         for (int r = lane; r < nx; r += 64) {
@@ -869,28 +894,35 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
                 const real rho = gam * yb1 - yb2 + yb3 - tb - sb;
                 const real l = (rho - rsum / (cc + real(k))) / cc;
                 lsum += l;
-                zout[P->z_y + yo + c] = yb1 - gam * l;
-                zout[P->z_y + yo + k + c] = yb2 + l;
-                zout[P->z_tau + fc + c - 1] = tb + l;
-                zout[P->z_s + fc + c - 1] = sb + l;
+                gm(zout)[P->z_y + yo + c] = yb1 - gam * l;
+                gm(zout)[P->z_y + yo + k + c] = yb2 + l;
+                gm(zout)[P->z_tau + fc + c - 1] = tb + l;
+                gm(zout)[P->z_s + fc + c - 1] = sb + l;
             }
             lsum = wave_sum(lsum);
-            if (lane == 0) zout[P->z_y + yo + 2 * k] = yb3 - lsum;
+            if (lane == 0) gm(zout)[P->z_y + yo + 2 * k] = yb3 - lsum;
         }
+        };
+        if (sk)
+            per_child(lds(st + off[3]), lds(st + off[4]), lds(st + off[6]), lds(st + off[7]), lds(st + off[8]),
+                      lds(st + off[9]), lds(st + off[10]));
+        else
+            per_child(gm(g_soc), gm(ein + P->e_y + yo), gm(zin + P->z_y + yo), gm(zin + P->z_tau + fc - 1),
+                      gm(zin + P->z_s + fc - 1), gm(g_cs), gm(P->prob + fc));
         wave_sync();
         // h0 = -xbar - K^T ubar (+ P c)
         TK.apply(ub, tk, red);
         for (int r = lane; r < nx; r += 64) {
             real h = -xb[r] - tk[r];
             if (P->affine && v > 0) h += spc[r];
-            P->h0[(long long)v * nx + r] = h;
+            gm(P->h0)[(long long)v * nx + r] = h;
         }
-        for (int r = lane; r < nu; r += 64) P->ub[(long long)v * nu + r] = ub[r];
+        for (int r = lane; r < nu; r += 64) gm(P->ub)[(long long)v * nu + r] = ub[r];
         if (v == 0 && lane == 0) {
-            zout[0] = zin[0] - alpha * es - alpha;  // prox of alpha * s0
+            gm(zout)[0] = zin[0] - alpha * es - alpha;  // prox of alpha * s0
             if (check) {
-                P->res[0] = 0ull;
-                P->res[1] = 0ull;
+                gm(P->res)[0] = 0ull;
+                gm(P->res)[1] = 0ull;
             }
         }
     } else {
@@ -913,7 +945,7 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
             if (P->has_ballN) lt += C.gbN[r] * sc[nx + r];
             real h = -(sx[r] - alpha * lt);
             if (P->affine) h += spc[r];
-            P->h0[(long long)v * nx + r] = h;
+            gm(P->h0)[(long long)v * nx + r] = h;
         }
     }
 }
@@ -1549,7 +1581,7 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
         for (int r = lane; r < nu; r += 64) {
             const real u = un[r] + dd[r];
             un[r] = u;
-            zout[P->z_u + (long long)v * nu + r] = u;
+            gm(zout)[P->z_u + (long long)v * nu + r] = u;
         }
         if (check) {
             for (int r = lane; r < nx; r += 64) lxw[r] = 0;
@@ -1557,21 +1589,26 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
         }
         wave_sync();
         const FwdNode<real> V{C, xn, un, xo, uo, blk, dblk, lxw, luw};
-        const real* soc = sk ? st + off[5] : ein + P->e_soc + (long long)(fc - 1) * (m + 2);
-        const real* ey = sk ? st + off[6] : ein + P->e_y + yo;
-        const real* yn = sk ? st + off[8] : zout + P->z_y + yo;
-        const real* yv = sk ? st + off[9] : zin + P->z_y + yo;
-        const real* tn = sk ? st + off[12] : zout + P->z_tau + fc - 1;
-        const real* tv = sk ? st + off[13] : zin + P->z_tau + fc - 1;
-        const real* pr = sk ? st + off[14] : P->prob + fc;
         fwd_block_c(P, v, st + off[4], eout, V, check, r2);
         wave_sync();
-        fwd_block_risk(P, v, k, ey, st[off[7]], yn, yv, st[off[10]], st[off[11]], pr, eout, check, r1, r2);
-        wave_sync();
-        for (int q = 0; q < k; ++q) {
-            fwd_block_soc(P, fc + q, soc + q * (m + 2), tn[q], tv[q], eout, V, check, r1, r2);
+        // per-child inputs: the staged copies, or for a wide node the arrays
+        // themselves, each through a pointer of its own address space
+        auto per_child = [&](auto soc, auto ey, auto yn, auto yv, auto tn, auto tv, auto pr) {
+            fwd_block_risk(P, v, yo, k, ey, st[off[7]], yn, yv, st[off[10]], st[off[11]], pr, eout, check, r1, r2);
             wave_sync();
-        }
+            for (int q = 0; q < k; ++q) {
+                fwd_block_soc(P, fc + q, soc + q * (m + 2), tn[q], tv[q], eout, V, check, r1, r2);
+                wave_sync();
+            }
+        };
+        if (sk)
+            per_child(lds(st + off[5]), lds(st + off[6]), lds(st + off[8]), lds(st + off[9]), lds(st + off[12]),
+                      lds(st + off[13]), lds(st + off[14]));
+        else
+            per_child(gm(ein + P->e_soc + (long long)(fc - 1) * (m + 2)), gm(ein + P->e_y + yo),
+                      gm(static_cast<const real*>(zout + P->z_y + yo)), gm(zin + P->z_y + yo),
+                      gm(static_cast<const real*>(zout + P->z_tau + fc - 1)), gm(zin + P->z_tau + fc - 1),
+                      gm(P->prob + fc));
         if (check) {
             for (int r = lane; r < nx; r += 64) r1 = fmax(r1, fabs((xo[r] - xn[r]) * ialpha - lxw[r]));
             for (int r = lane; r < nu; r += 64) r1 = fmax(r1, fabs((uo[r] - un[r]) * ialpha - luw[r]));
