@@ -163,6 +163,10 @@ def serve_bench(S, W, duration_s=10.0, session_rate=20.0, req_per_session=10, ga
             "p50_by_shape_s": {k: round(float(np.percentile(v, 50)), 4) for k, v in by_kind.items()},
             "warm_fraction": round(float(np.mean([r["warm"] for r in ok])), 3) if ok else 0.0,
             "mean_iters": round(float(np.mean([r["info"]["iters"] for r in ok])), 1) if ok else 0.0,
+            "median_iters_warm": (round(float(np.median([r["info"]["iters"] for r in ok if r["warm"]])), 1)
+                                  if any(r["warm"] for r in ok) else None),
+            "median_iters_cold": (round(float(np.median([r["info"]["iters"] for r in ok if not r["warm"]])), 1)
+                                  if any(not r["warm"] for r in ok) else None),
             "sessions": len(sessions), "duration_s": duration_s, "drain_s": drain_s,
             "server": {k: int(v) for k, v in st.items()}}
 
@@ -273,6 +277,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="sessions per second (10 requests each)")
+    ap.add_argument("--serve-rate-sustained", type=float, default=0.5,
+                    help="a second, lower session rate the device keeps up with (0: skip)")
     ap.add_argument("--cpu-baseline-only", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: K steps per precision and a 1 GiB device copy")
@@ -353,6 +359,10 @@ def main():
     if not args.no_serve:
         serve = serve_bench(S, W, duration_s=args.serve_seconds, session_rate=args.serve_rate)
         print("serve: %s" % serve, file=sys.stderr, flush=True)
+        if args.serve_rate_sustained > 0:
+            serve["sustained"] = serve_bench(S, W, duration_s=args.serve_seconds,
+                                             session_rate=args.serve_rate_sustained, seed=7)
+            print("serve (sustained rate): %s" % serve["sustained"], file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC, "value": round(v32, 2), "unit": "CP iters/s", "n_gpus": 1, "steps": args.steps,

@@ -1028,9 +1028,18 @@ __global__ __launch_bounds__(64) void k_bsweep(const ProbDev<real>* __restrict__
         wave_sync();
         TM.template apply<true>(hv, gv, red);
     }
+    // d of the node below is computed once the next level has begun (its
+    // R~^-1 tile in the data set `prv`, its ubar - g_u in wv): off the message
+    // chain, while the arrival at the next node is being counted
+    int pend = -1;
+    auto finish_d = [&](BLevel<real, R>& prv) {
+        prv.TR.template apply<true>(wv, dv, red);  // d^pend = R~^-1 (ubar - g_u)
+        for (int r = lane; r < nu; r += 64) gm(P->d)[(long long)pend * nu + r] = dv[r];
+        pend = -1;
+    };
     // one level with the data set `cur`; prefetches the next level into `nxt`
-    // when this wavefront is sure to continue there; false: stop
-    auto level = [&](BLevel<real, R>& cur, BLevel<real, R>& nxt, int lev) -> bool {
+    // (`prv`: the previous level's set); false: another child continues
+    auto level = [&](BLevel<real, R>& cur, BLevel<real, R>& nxt, BLevel<real, R>& prv, int lev) -> bool {
         const int i = s_node[lev], k = s_nch[lev], fc = s_fc[lev];
         if (k > 1) {
             for (int c = lane; c < m; c += 64) st_dev(P->e + (long long)j * m + c, gv[c]);
@@ -1038,9 +1047,12 @@ __global__ __launch_bounds__(64) void k_bsweep(const ProbDev<real>* __restrict__
             drain_stores();
             int prev = 0;
             if (lane == 0) prev = __hip_atomic_fetch_add(gm(P->cnt) + i, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            prev = __shfl(prev, 0, 64);
+            if (pend >= 0) finish_d(prv);
+            prev = __builtin_amdgcn_readfirstlane(prev);
             if (prev != k - 1) return false;
             if (lane == 0) gm(P->cnt)[i] = 0;  // the next launch reuses the counter
+        } else if (pend >= 0) {
+            finish_d(prv);
         }
         // the children's messages (up to kMsgFast in registers, issued before
         // the prefetch so that waiting for them does not wait for it)
@@ -1094,19 +1106,22 @@ __global__ __launch_bounds__(64) void k_bsweep(const ProbDev<real>* __restrict__
         }
         wave_sync();
         if (i > 0) cur.TM.template apply<true>(hv, gv, red);  // message of i: [Abar^i|B^i]^T h^i
-        cur.TR.template apply<true>(wv, dv, red);             // d^i = R~^-1 (ubar - g_u)
-        for (int r = lane; r < nu; r += 64) gm(P->d)[(long long)i * nu + r] = dv[r];
+        pend = i;
         j = i;
-        return i > 0;
+        return true;
     };
     if constexpr (kDB) {
-        for (int lev = N - 1; lev >= 0; lev -= 2) {
-            if (!level(A, B, lev)) return;
-            if (lev == 0 || !level(B, A, lev - 1)) return;
+        int lev = N - 1;
+        for (; lev >= 0; lev -= 2) {
+            if (!level(A, B, B, lev)) return;
+            if (lev == 0) break;
+            if (!level(B, A, A, lev - 1)) return;
         }
+        finish_d(lev == 0 ? A : B);  // the root's
     } else {
         for (int lev = N - 1; lev >= 0; --lev)
-            if (!level(A, A, lev)) return;
+            if (!level(A, A, A, lev)) return;
+        finish_d(A);  // the root's
     }
 }
 
@@ -1374,6 +1389,15 @@ __global__ __launch_bounds__(64) void k_bsweep_st(const ProbDev<real>* __restric
     lgkm_wait();
     if (N >= 1) stage(s_node[N - 1], 0);
     TM.template apply<true>(hv, gv, red);
+    // d of the node below is computed once the next level has begun (its R~^-1
+    // tile stays in registers, its ubar - g_u in wv): off the message chain,
+    // while the arrival at the next node is being counted
+    int pend = -1;
+    auto finish_d = [&]() {
+        TR.template apply<true>(wv, dv, red);  // d^pend = R~^-1 (ubar - g_u)
+        for (int r = lane; r < nu; r += 64) gm(P->d)[(long long)pend * nu + r] = dv[r];
+        pend = -1;
+    };
     int b = 0;
     for (int lev = N - 1; lev >= 0; --lev, b ^= 1) {
         const int i = s_node[lev], k = s_nch[lev], fc = s_fc[lev];
@@ -1385,7 +1409,8 @@ __global__ __launch_bounds__(64) void k_bsweep_st(const ProbDev<real>* __restric
             drain_stores();
             int prev = 0;
             if (lane == 0) prev = __hip_atomic_fetch_add(gm(P->cnt) + i, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            prev = __shfl(prev, 0, 64);
+            if (pend >= 0) finish_d();
+            prev = __builtin_amdgcn_readfirstlane(prev);
             if (prev != k - 1) return;
             if (lane == 0) gm(P->cnt)[i] = 0;  // the next launch reuses the counter
             if (k <= kMsgFast) {
@@ -1399,6 +1424,7 @@ __global__ __launch_bounds__(64) void k_bsweep_st(const ProbDev<real>* __restric
         } else if (lev == N - 1) {
             vm_wait<0>();
         } else {
+            finish_d();
             // only the previous level's d store (at least one) may be younger
             // than this level's copies
             vm_wait<1>();
@@ -1439,11 +1465,11 @@ __global__ __launch_bounds__(64) void k_bsweep_st(const ProbDev<real>* __restric
         for (int r = lane; r < nx; r += 64) hv[r] = h0s[b][r] + gv[r];
         for (int r = lane; r < nu; r += 64) wv[r] = ubs[b][r] - gv[nx + r];
         wave_sync();
-        TR.template apply<true>(wv, dv, red);  // d^i = R~^-1 (ubar - g_u)
-        for (int r = lane; r < nu; r += 64) gm(P->d)[(long long)i * nu + r] = dv[r];
         if (i > 0) TM.template apply<true>(hv, gv, red);  // message of i: [Abar^i|B^i]^T h^i
+        pend = i;
         j = i;
     }
+    finish_d();  // the root's
     vm_wait<0>();  // no copy outlives the wavefront
 }
 
