@@ -31,7 +31,8 @@ struct ProbDev {
     const int* first_child;
     const int* n_ch;
     const int* y_off;        // start of y^i inside the y block, per non-leaf node
-    const int* path;         // per leaf l: node at each stage 0..N on the root-to-leaf path
+    const int4* path;        // per leaf l, stage 0..N of its root-to-leaf path: (node, children,
+                             // first child, 0), children 0 at the leaf
     const int* top_owned;    // per leaf l: first stage whose path node has l as leftmost leaf
                              // (the forward sweep of l stores x from that stage on)
 

@@ -184,7 +184,7 @@ static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
 static void carve(Arena& a, spock_problem* p) {
     p->d_tree = a.take<int>(4LL * p->n + 4);
     p->d_cnt = a.take<int>(p->n);
-    p->d_path = a.take<int>((long long)p->n_leaf * (p->N + 1));
+    p->d_path = a.take<int4>((long long)p->n_leaf * (p->N + 1));
     p->d_top = a.take<int>(p->n_leaf);
     p->d_one = a.take<int>(4);  // [0] constant 1: the problem's active flag
     p->d_tasks = a.take<int2>(p->n_leaf);
@@ -1028,7 +1028,13 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
             e = hipMemcpy(p->d_ninfo, ninfo.data(), ninfo.size() * sizeof(int4), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(p->d_tasks, tasks.data(), tasks.size() * sizeof(int2), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(p->d_path, path.data(), path.size() * sizeof(int), hipMemcpyHostToDevice);
+        std::vector<int4> path4(path.size());
+        for (size_t q = 0; q < path.size(); ++q) {
+            const int v = path[q];
+            path4[q] = make_int4(v, p->n_ch[v], p->n_ch[v] ? p->first_child[v] : 0, 0);
+        }
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_path, path4.data(), path4.size() * sizeof(int4), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(p->d_top, top.data(), top.size() * sizeof(int), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             spock_problem_destroy(p);

@@ -94,7 +94,7 @@ struct spock_problem {
     bool owns_stream = false;
     int* d_tree = nullptr;
     int* d_cnt = nullptr;
-    int* d_path = nullptr;
+    int4* d_path = nullptr;
     int* d_top = nullptr;
     int* d_one = nullptr;      // constant 1 (active flag of the unbatched form)
     int2* d_tasks = nullptr;   // (0, leaf) per sweep wavefront

@@ -997,13 +997,12 @@ __global__ __launch_bounds__(64) void k_bsweep(const ProbDev<real>* __restrict__
     // vectors are read in 16-byte groups: their padding must hold finite values
     for (int e = lane; e < sweep_elems(nx, nu); e += 64) red[e] = real(0);
 
-    const auto* path = gm(P->path) + (long long)tk.y * (N + 1);
+    // (node, children, first child) of every stage of the path, one load each
+    const auto* path = gm(reinterpret_cast<const int*>(P->path + (long long)tk.y * (N + 1)));
     for (int q = lane; q <= N; q += 64) {
-        const int v = path[q];
-        const auto* ni = gm(reinterpret_cast<const int*>(P->node + v));  // first child, children
-        s_node[q] = v;
-        s_nch[q] = v < n_nl ? ni[1] : 0;
-        s_fc[q] = ni[0];
+        s_node[q] = path[4 * q];
+        s_nch[q] = path[4 * q + 1];
+        s_fc[q] = path[4 * q + 2];
     }
     wave_sync();
     const ColShape sM = col_shape<real>(nx, m), sR = col_shape<real>(nu, nu);
@@ -1156,8 +1155,8 @@ __global__ __launch_bounds__(64) void k_fsweep(const ProbDev<real>* __restrict__
     // owns (stages L..N, those whose leftmost leaf it is); every other task
     // through a node computes the same x^v, bit for bit, and drops it.
     const int L = gm(P->top_owned)[tk.y];
-    const auto* path = gm(P->path) + (long long)tk.y * (N + 1);
-    for (int q = lane; q <= N; q += 64) s_node[q] = path[q];
+    const auto* path = gm(reinterpret_cast<const int*>(P->path + (long long)tk.y * (N + 1)));
+    for (int q = lane; q <= N; q += 64) s_node[q] = path[4 * q];
     wave_sync();
     const ColShape sT = col_shape<real>(m, nx);
     // every load unconditional: without an affine term c is read from x0 and
@@ -1361,13 +1360,12 @@ __global__ __launch_bounds__(64) void k_bsweep_st(const ProbDev<real>* __restric
     real* stR = stM + stage_groups(nx, m, V, R) * 64 * V;  // staged R~^-1 tile
     for (int e = lane; e < sweep_elems(nx, nu); e += 64) red[e] = real(0);
 
-    const auto* path = gm(P->path) + (long long)tk.y * (N + 1);
+    // (node, children, first child) of every stage of the path, one load each
+    const auto* path = gm(reinterpret_cast<const int*>(P->path + (long long)tk.y * (N + 1)));
     for (int q = lane; q <= N; q += 64) {
-        const int v = path[q];
-        const auto* ni = gm(reinterpret_cast<const int*>(P->node + v));  // first child, children
-        s_node[q] = v;
-        s_nch[q] = v < P->n_nl ? ni[1] : 0;
-        s_fc[q] = ni[0];
+        s_node[q] = path[4 * q];
+        s_nch[q] = path[4 * q + 1];
+        s_fc[q] = path[4 * q + 2];
     }
     wave_sync();
     ColProd<real, R> TM;
@@ -1495,8 +1493,8 @@ __global__ __launch_bounds__(64) void k_fsweep_st(const ProbDev<real>* __restric
 
     // the whole root-to-leaf path, stores from stage L on (see k_fsweep)
     const int L = gm(P->top_owned)[tk.y];
-    const auto* path = gm(P->path) + (long long)tk.y * (N + 1);
-    for (int q = lane; q <= N; q += 64) s_node[q] = path[q];
+    const auto* path = gm(reinterpret_cast<const int*>(P->path + (long long)tk.y * (N + 1)));
+    for (int q = lane; q <= N; q += 64) s_node[q] = path[4 * q];
     const ColShape sT = col_shape<real>(m, nx);
     ColProd<real, R> TM;
     // level data of node v into slot b (a leaf stages an unused d)
