@@ -49,7 +49,7 @@ extern "C" {
 #define SPOCK_E_INFEASIBLE_X0 (-2)   /* x0 outside the root constraint set */
 #define SPOCK_E_NOT_CONVERGED (-3)   /* max_iters reached; info is filled */
 #define SPOCK_E_DIVERGED (-4)        /* non-finite residual */
-#define SPOCK_E_HIP (-5)             /* HIP runtime failure or device wait timeout */
+#define SPOCK_E_HIP (-5)             /* HIP runtime failure */
 #define SPOCK_E_CAPACITY (-6)        /* a request larger than the whole budget */
 #define SPOCK_E_NOMEM (-7)           /* workspace too small / allocation failed */
 

@@ -1,7 +1,7 @@
 // Batched form: many independent scenario trees advanced by the same four
 // launches per CP step as one tree.  Each member keeps its own workspace; the
-// batch holds copies of the members' descriptors whose residual slots, error
-// flags and "active" flags point into batch-owned arrays, two problem-major
+// batch holds copies of the members' descriptors whose residual slots and
+// "active" flags point into batch-owned arrays, two problem-major
 // task tables (one sweep task per leaf and one node task per node of every
 // member).
 // Members that converge are switched off through their active flag, so a
@@ -94,14 +94,7 @@ int32_t batch_chunk(spock_batch* b, int steps) {
 int32_t read_all(spock_batch* b) {
     HIP_TRY(hipMemcpyAsync(b->h_res, b->res, 2 * b->n * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            b->stream));
-    HIP_TRY(hipMemcpyAsync(b->h_res + 2 * b->n, b->err, b->n * sizeof(int), hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
-    const int* errs = reinterpret_cast<const int*>(b->h_res + 2 * b->n);
-    for (int k = 0; k < b->n; ++k)
-        if (errs[k]) {
-            HIP_TRY(hipMemset(b->err, 0, b->n * sizeof(int)));
-            return fail(SPOCK_E_HIP, "device wait timeout in a batched forward sweep");
-        }
     return SPOCK_OK;
 }
 
@@ -200,7 +193,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
     const size_t o64 = take(sizeof(ProbDev<double>) * n), o32 = take(sizeof(ProbDev<float>) * n);
     const size_t ot = take(sizeof(int2) * b->n_tasks), oa = take(sizeof(int) * n);
     const size_t ont = take(sizeof(int2) * b->n_ntasks), oni = take(sizeof(int4) * b->n_ntasks);
-    const size_t oe = take(sizeof(int) * n), orr = take(sizeof(unsigned long long) * 2 * n);
+    const size_t orr = take(sizeof(unsigned long long) * 2 * n);
     b->bytes = off + 256;
     std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
     hipError_t e = hipMalloc(&b->base, b->bytes);
@@ -215,7 +208,6 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
     b->ntasks = (int2*)(base + ont);
     b->ninfo = (int4*)(base + oni);
     b->active = (int*)(base + oa);
-    b->err = (int*)(base + oe);
     b->res = (unsigned long long*)(base + orr);
     auto bail = [&](int32_t code, const std::string& msg) {
         spock_batch_destroy(b);
@@ -223,7 +215,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
     };
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
         return bail(SPOCK_E_HIP, "batch stream");
-    if (hipHostMalloc((void**)&b->h_res, 3 * n * sizeof(unsigned long long), 0) != hipSuccess)
+    if (hipHostMalloc((void**)&b->h_res, 2 * n * sizeof(unsigned long long), 0) != hipSuccess)
         return bail(SPOCK_E_HIP, "batch pinned buffer");
     std::vector<ProbDev<double>> h64(n);
     std::vector<ProbDev<float>> h32(n);
@@ -236,7 +228,6 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
         h64[k] = probs[k]->s64.h;
         h32[k] = probs[k]->s32.h;
         h64[k].active = h32[k].active = b->active + k;
-        h64[k].err = h32[k].err = b->err + k;
         h64[k].res = h32[k].res = b->res + 2 * k;
         for (int l = 0; l < probs[k]->n_leaf; ++l) tasks.push_back(make_int2(k, l));
         const spock_problem* q = probs[k];
@@ -259,7 +250,6 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
         e = hipMemcpy(b->ntasks, ntasks.data(), sizeof(int2) * ntasks.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->ninfo, ninfo.data(), sizeof(int4) * ninfo.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->active, b->h_active.data(), sizeof(int) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(b->err, 0, sizeof(int) * n);
     if (e == hipSuccess) e = hipMemset(b->res, 0, sizeof(unsigned long long) * 2 * n);
     if (e != hipSuccess) return bail(SPOCK_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
     *out = b;

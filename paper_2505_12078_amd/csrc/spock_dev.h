@@ -86,7 +86,6 @@ struct ProbDev {
     real* h0;                // -xbar - K^T ubar (+ P c): h of node j before its children's messages, nx
     real* ub;                // ubar of non-leaf node i, nu
     int* cnt;                // backward arrival counters, per node
-    int* err;                // device wait timeout
     const int* active;       // 0: this problem sits out the launch (batched form)
     unsigned long long* res; // |xi1|_inf, |xi2|_inf as float64 bit patterns
 };

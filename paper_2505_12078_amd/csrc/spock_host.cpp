@@ -193,7 +193,6 @@ static void carve(Arena& a, spock_problem* p) {
     p->d_ntasks = a.take<int2>(p->n_ntasks);
     p->d_ninfo = a.take<int4>(p->n_ntasks);
     p->d_res = a.take<unsigned long long>(4);
-    p->d_err = a.take<int>(4);
     const long long nv = std::max(p->nz, p->neta);
     p->d_stash_z = a.take<double>(nv);
     p->d_stash_e = a.take<double>(nv);
@@ -646,7 +645,6 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     h.path = p->d_path;
     h.top_owned = p->d_top;
     h.active = p->d_one;
-    h.err = p->d_err;
     h.res = p->d_res;
     s.cfg = make_cfg<real>(p, s.cfg.node_wg > 0 ? s.cfg.node_wg : spk::kDefaultWG);
     hipStream_t st = p->stream;
@@ -733,13 +731,7 @@ static int32_t chunk(spock_problem* p, int steps) {
 
 int32_t read_res(spock_problem* p, double* xi1, double* xi2) {
     HIP_TRY(hipMemcpyAsync(p->h_res, p->d_res, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, p->stream));
-    HIP_TRY(hipMemcpyAsync(p->h_res + 2, p->d_err, sizeof(int), hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
-    if ((int)p->h_res[2] != 0) {
-        int zero = 0;
-        (void)hipMemcpy(p->d_err, &zero, sizeof(int), hipMemcpyHostToDevice);
-        return fail(SPOCK_E_HIP, "device wait timeout in the forward sweep");
-    }
     double a, b;
     std::memcpy(&a, &p->h_res[0], 8);
     std::memcpy(&b, &p->h_res[1], 8);
@@ -1042,7 +1034,6 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
         }
         // arrival counters, claim flags, the error flag and residual slots start at zero
         e = spk::launch_fill<int>(p->d_cnt, 0, p->n, p->stream);
-        if (e == hipSuccess) e = spk::launch_fill<int>(p->d_err, 0, 4, p->stream);
         if (e == hipSuccess) e = spk::launch_fill<int>(p->d_one, 1, 1, p->stream);
         if (e == hipSuccess) e = spk::launch_fill<unsigned long long>(p->d_res, 0ull, 4, p->stream);
         if (e != hipSuccess) {
@@ -1434,13 +1425,6 @@ static int32_t time_steps(spock_problem* p, int steps, double* ms_total, double 
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (ms_total) *ms_total = tot / steps;
     for (int ph = 0; ph < 4; ++ph) ms_k[ph] = t[ph] / steps;
-    int zero = 0;
-    int err = 0;
-    HIP_TRY(hipMemcpy(&err, p->d_err, sizeof(int), hipMemcpyDeviceToHost));
-    if (err) {
-        (void)hipMemcpy(p->d_err, &zero, sizeof(int), hipMemcpyHostToDevice);
-        return fail(SPOCK_E_HIP, "device wait timeout in the forward sweep");
-    }
     return SPOCK_OK;
 }
 }  // extern "C++"

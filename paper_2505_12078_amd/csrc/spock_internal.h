@@ -103,13 +103,12 @@ struct spock_problem {
     int4* d_ninfo = nullptr;   // first child, children, y offset, parent per node wavefront
     int n_ntasks = 0;
     unsigned long long* d_res = nullptr;
-    int* d_err = nullptr;
     double* d_stash_z = nullptr;
     double* d_stash_e = nullptr;
     DevSet<double> s64;
     DevSet<float> s32;
     int cur = SPOCK_FP64;      // precision holding the current iterate
-    unsigned long long* h_res = nullptr;  // pinned readback: res[2], err
+    unsigned long long* h_res = nullptr;  // pinned readback: res[2]
     bool have_ref = false;
     double xi_ref[2] = {0, 0};
     bool solved = false;
@@ -149,12 +148,11 @@ struct spock_batch {
     int4* ninfo = nullptr;
     int n_ntasks = 0;
     int* active = nullptr;
-    int* err = nullptr;
     unsigned long long* res = nullptr;
     spk::LaunchCfg cfg64{}, cfg32{};
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // [0] float64, [1] float32
     int graph_steps[2] = {0, 0};
-    unsigned long long* h_res = nullptr;  // pinned: 2n residual slots, then n error flags
+    unsigned long long* h_res = nullptr;  // pinned: 2n residual slots
     std::vector<int> h_active;
     double bytes_k[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // algorithmic bytes per launch, [fp64 / fp32]
 };
