@@ -131,6 +131,38 @@ def test_T_step_matches_oracle(name, precondition):
             assert xif[0] == pytest.approx(np.abs(x1).max(), rel=1e-3, abs=1e-3 * scale / alpha)
 
 
+def test_large_tree_step_matches_oracle():
+    """The benchmark's own workload and launch configuration: one CP step of
+    the large tree (7,167 nodes, nx = 50, nu = 25: backward products of 64 +
+    16 rows with a second column block, forward products of 80 rows, the
+    LDS-staged float32 sweeps and the float64 register sweeps, node
+    workgroups of 256 threads) against the oracle, every entry, from two
+    seeded random iterates."""
+    prob = W.config_problem(2)
+    D = O.Data(prob)
+    F = O.Offline(D)
+    alpha = O.step_size(D)
+    rng = np.random.default_rng(23)
+    with S.Problem(prob, S.default_settings(alpha=alpha)) as P:
+        P.set_x0(prob["x0"])
+        assert P.sizes["n"] == 7167 and P.sizes["nx"] == 50 and P.sizes["nu"] == 25
+        for trial in range(2):
+            z, e = _random_v(P, rng)
+            zo, eo = O.cp_step(D, F, z, e, alpha)
+            x1, x2 = O.residuals(D, z, e, zo, eo, alpha)
+            scale = max(1.0, np.abs(z).max(), np.abs(e).max(), np.abs(zo).max(), np.abs(eo).max())
+            zg, eg, xi = P.apply_T(z, e)
+            assert _rel(zg, zo, scale) < 1e-10, (trial, _rel(zg, zo, scale))
+            assert _rel(eg, eo, scale) < 1e-10, (trial, _rel(eg, eo, scale))
+            assert xi[0] == pytest.approx(np.abs(x1).max(), rel=1e-9)
+            assert xi[1] == pytest.approx(np.abs(x2).max(), rel=1e-9)
+            zf, ef, _ = P.apply_T(z, e, S.FP32)
+            print("large tree, trial %d: float64 %.2e %.2e, float32 %.2e %.2e" % (
+                trial, _rel(zg, zo, scale), _rel(eg, eo, scale), _rel(zf, zo, scale), _rel(ef, eo, scale)))
+            assert _rel(zf, zo, scale) < 2e-4, (trial, _rel(zf, zo, scale))
+            assert _rel(ef, eo, scale) < 2e-4, (trial, _rel(ef, eo, scale))
+
+
 @pytest.mark.parametrize("name", ["cfg0", "ragged_a", "wide"])
 def test_prox_f_parts(name):
     """With eta = 0 the z part of T is prox_{alpha f}: S1 on (x, u) by Alg. 2,
