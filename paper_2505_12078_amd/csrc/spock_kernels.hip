@@ -130,6 +130,16 @@ SPK_DEV void wave_sync() {
 
 SPK_DEV int lane_id() { return (int)(threadIdx.x & 63); }
 
+// The dispatcher hands workgroups to the 8 XCDs in turn (workgroup w to XCD
+// w mod 8).  The sweeps renumber them so that each XCD takes one contiguous run
+// of the leaf table: neighbouring leaves (one subtree) then share an L2, and the
+// tiles of the nodes above them are fetched from HBM once per XCD rather than
+// by every XCD.  A bijection of [0, g) for any g.
+SPK_DEV int xcd_order(int w, int g) {
+    const int per = g >> 3, rem = g & 7, x = w & 7, j = w >> 3;
+    return x * per + (x < rem ? x : rem) + j;
+}
+
 // Exchange between workgroups of one launch.  A value that another workgroup
 // reads while the launch runs is stored and loaded at device scope: the store
 // is written through to the level of the memory hierarchy that all XCDs share,
@@ -982,7 +992,7 @@ __global__ __launch_bounds__(64) void k_bsweep(const ProbDev<real>* __restrict__
                                                const int2* __restrict__ tasks) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int lane = lane_id();
-    const int2 tk = tasks[blockIdx.x];
+    const int2 tk = tasks[xcd_order(blockIdx.x, gridDim.x)];
     const ProbDev<real>* __restrict__ P = probs + tk.x;
     if (*P->active == 0) return;
     const int N = P->N, nx = P->nx, nu = P->nu, m = P->m, n_nl = P->n_nl;
@@ -1140,7 +1150,7 @@ __global__ __launch_bounds__(64) void k_fsweep(const ProbDev<real>* __restrict__
                                                const int2* __restrict__ tasks, int par) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int lane = lane_id();
-    const int2 tk = tasks[blockIdx.x];
+    const int2 tk = tasks[xcd_order(blockIdx.x, gridDim.x)];
     const ProbDev<real>* __restrict__ P = probs + tk.x;
     if (*P->active == 0) return;
     const int N = P->N, nx = P->nx, nu = P->nu, m = P->m, n_nl = P->n_nl;
@@ -1340,7 +1350,7 @@ __global__ __launch_bounds__(64) void k_bsweep_st(const ProbDev<real>* __restric
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int V = tile_vec<real>();
     const int lane = lane_id();
-    const int2 tk = tasks[blockIdx.x];
+    const int2 tk = tasks[xcd_order(blockIdx.x, gridDim.x)];
     const ProbDev<real>* __restrict__ P = probs + tk.x;
     if (*P->active == 0) return;
     const int N = P->N, nx = P->nx, nu = P->nu, m = P->m;
@@ -1476,7 +1486,7 @@ __global__ __launch_bounds__(64) void k_fsweep_st(const ProbDev<real>* __restric
                                                   const int2* __restrict__ tasks, int par) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int lane = lane_id();
-    const int2 tk = tasks[blockIdx.x];
+    const int2 tk = tasks[xcd_order(blockIdx.x, gridDim.x)];
     const ProbDev<real>* __restrict__ P = probs + tk.x;
     if (*P->active == 0) return;
     const int N = P->N, nx = P->nx, nu = P->nu, m = P->m, n_nl = P->n_nl;
