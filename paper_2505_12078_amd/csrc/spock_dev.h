@@ -26,8 +26,6 @@ struct ProbDev {
     real alpha, ball_r, ballN_r;
 
     // tree (breadth-first numbering, children contiguous)
-    const int4* node;        // per node: first child, number of children, y offset, parent
-    const int* parent;
     const int* first_child;
     const int* n_ch;
     const int* y_off;        // start of y^i inside the y block, per non-leaf node

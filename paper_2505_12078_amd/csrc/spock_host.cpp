@@ -182,13 +182,12 @@ static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
 }
 
 static void carve(Arena& a, spock_problem* p) {
-    p->d_tree = a.take<int>(4LL * p->n + 4);
+    p->d_tree = a.take<int>(3LL * p->n + 4);
     p->d_cnt = a.take<int>(p->n);
     p->d_path = a.take<int4>((long long)p->n_leaf * (p->N + 1));
     p->d_top = a.take<int>(p->n_leaf);
     p->d_one = a.take<int>(4);  // [0] constant 1: the problem's active flag
     p->d_tasks = a.take<int2>(p->n_leaf);
-    p->d_node = a.take<int4>(p->n);
     p->n_ntasks = (p->n + spk::kMaxNodeWaves - 1) / spk::kMaxNodeWaves * spk::kMaxNodeWaves;
     p->d_ntasks = a.take<int2>(p->n_ntasks);
     p->d_ninfo = a.take<int4>(p->n_ntasks);
@@ -632,11 +631,9 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     h.alpha = (real)p->alpha;
     h.ball_r = (real)p->ball_r;
     h.ballN_r = (real)p->ballN_r;
-    h.parent = p->d_tree;
-    h.first_child = p->d_tree + p->n;
-    h.n_ch = p->d_tree + 2 * p->n;
-    h.y_off = p->d_tree + 3 * p->n;
-    h.node = p->d_node;
+    h.first_child = p->d_tree;
+    h.n_ch = p->d_tree + p->n;
+    h.y_off = p->d_tree + 2 * p->n;
     h.z_x = p->z_x; h.z_u = p->z_u; h.z_y = p->z_y; h.z_tau = p->z_tau; h.z_s = p->z_s;
     h.e_y = p->e_y; h.e_s = p->e_s; h.e_c = p->e_c; h.e_soc = p->e_soc; h.e_cN = p->e_cN; h.e_socN = p->e_socN;
     h.nz = p->nz;
@@ -993,27 +990,22 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
         Arena a(p->base);
         carve(a, p);
         // tree arrays and tasks
-        std::vector<int> tree(4 * (size_t)p->n + 4, 0);
-        std::copy(p->parent.begin(), p->parent.end(), tree.begin());
-        std::copy(p->first_child.begin(), p->first_child.end(), tree.begin() + p->n);
-        std::copy(p->n_ch.begin(), p->n_ch.end(), tree.begin() + 2 * (size_t)p->n);
-        std::copy(p->y_off.begin(), p->y_off.end(), tree.begin() + 3 * (size_t)p->n);
+        std::vector<int> tree(3 * (size_t)p->n + 4, 0);
+        std::copy(p->first_child.begin(), p->first_child.end(), tree.begin());
+        std::copy(p->n_ch.begin(), p->n_ch.end(), tree.begin() + p->n);
+        std::copy(p->y_off.begin(), p->y_off.end(), tree.begin() + 2 * (size_t)p->n);
         std::vector<int> path, top;
         leaf_paths(p, path, top);
         std::vector<int2> tasks(p->n_leaf);
         for (int k = 0; k < p->n_leaf; ++k) tasks[k] = make_int2(0, k);
-        std::vector<int4> node(p->n);
-        for (int v = 0; v < p->n; ++v)
-            node[v] = make_int4(p->n_ch[v] ? p->first_child[v] : 0, p->n_ch[v], v < p->n_nl ? p->y_off[v] : 0,
-                                p->parent[v]);
         std::vector<int2> ntasks(p->n_ntasks, make_int2(0, -1));
         std::vector<int4> ninfo(p->n_ntasks, make_int4(0, 0, 0, 0));
         for (int v = 0; v < p->n; ++v) {
             ntasks[v] = make_int2(0, v);
-            ninfo[v] = node[v];
+            ninfo[v] = make_int4(p->n_ch[v] ? p->first_child[v] : 0, p->n_ch[v], v < p->n_nl ? p->y_off[v] : 0,
+                                 p->parent[v]);
         }
         hipError_t e = hipMemcpy(p->d_tree, tree.data(), tree.size() * sizeof(int), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(p->d_node, node.data(), node.size() * sizeof(int4), hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(p->d_ntasks, ntasks.data(), ntasks.size() * sizeof(int2), hipMemcpyHostToDevice);
         if (e == hipSuccess)

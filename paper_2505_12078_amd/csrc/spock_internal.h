@@ -98,7 +98,6 @@ struct spock_problem {
     int* d_top = nullptr;
     int* d_one = nullptr;      // constant 1 (active flag of the unbatched form)
     int2* d_tasks = nullptr;   // (0, leaf) per sweep wavefront
-    int4* d_node = nullptr;    // first child, children, y offset, parent per node
     int2* d_ntasks = nullptr;  // (0, node or -1) per node wavefront
     int4* d_ninfo = nullptr;   // first child, children, y offset, parent per node wavefront
     int n_ntasks = 0;

@@ -108,18 +108,6 @@ SPK_DEV T block_sum(T v, T* red) {
     return s;
 }
 
-template <int kWG, typename T>
-SPK_DEV T block_max(T v, T* red) {
-    v = wave_max(v);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    T s = red[0];
-#pragma unroll
-    for (int k = 1; k < kWG / 64; ++k) s = red[k] > s ? red[k] : s;
-    return s;
-}
-
 // LDS exchange between lanes of one wavefront: the hardware keeps a
 // wavefront's LDS accesses in order; this keeps the compiler from moving them.
 SPK_DEV void wave_sync() {
