@@ -1024,7 +1024,7 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
             spock_problem_destroy(p);
             return fail(SPOCK_E_HIP, std::string("upload: ") + hipGetErrorString(e));
         }
-        // arrival counters, claim flags, the error flag and residual slots start at zero
+        // arrival counters and residual slots start at zero; the active flag at one
         e = spk::launch_fill<int>(p->d_cnt, 0, p->n, p->stream);
         if (e == hipSuccess) e = spk::launch_fill<int>(p->d_one, 1, 1, p->stream);
         if (e == hipSuccess) e = spk::launch_fill<unsigned long long>(p->d_res, 0ull, 4, p->stream);
