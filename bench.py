@@ -13,6 +13,9 @@ Reported value: CP iterations per second of the mixed-precision form (float32
 steps on float32 copies of the float64 factors), with the plain float64 rate,
 time-to-tolerance 1e-4 of both forms, the roofline of the dominant kernel
 (HIP events on the library's stream) and the FP64 oracle on the host cores.
+Beside it: the batched workload (256 uneven trees in the same four launches per
+step, aggregate rates, per-launch roofline, time to 1e-4 of the whole batch)
+and the served form (continuous batching, p50/p99 latency).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -86,6 +89,89 @@ def _cpu_baseline_only(steps):
     print(json.dumps({"value": steps / dt, "unit": "CP iters/s", "cores": 1, "kind": "oracle",
                       "sample": "%d CP steps from zero on the same 7167-node tree, float64 NumPy, "
                                 "one thread; offline factorisation not timed" % steps}))
+
+
+def _batch_member(k):
+    from paper_2505_12078_amd import workloads as W
+    return W.batch_problem(k)
+
+
+def make_batch_inputs(n_problems):
+    """The batched workload's members, drawn in a process pool (each member is
+    seeded by its index, so the pool size does not change them).  Called before
+    anything touches the GPU: the pool forks without exec."""
+    import multiprocessing as mp
+    t = time.perf_counter()
+    workers = max(1, min(16, os.cpu_count() or 1, n_problems))
+    if workers == 1:
+        probs = [_batch_member(k) for k in range(n_problems)]
+    else:
+        with mp.get_context("fork").Pool(workers) as pool:
+            probs = pool.map(_batch_member, range(n_problems), chunksize=1)
+    return probs, time.perf_counter() - t, workers
+
+
+def batch_bench(S, probs, gen_s, workers, steps, warmup, solve=True, max_iters=20000):
+    """Batched form on the batched workload: every member advanced by the same
+    four launches per step (float32 bulk), node workgroup picked by the
+    autotuner on the batch itself; aggregate rates, per-launch roofline and the
+    mixed-precision time to rel_res 1e-4 of the whole batch."""
+    import numpy as np
+    import torch
+
+    from paper_2505_12078_amd import tune
+    st = S.default_settings(eps=1e-4, precision=S.MIXED, check_every=20, max_iters=max_iters)
+    t = time.perf_counter()
+    members = [S.Problem(p, st) for p in probs]
+    for P, p in zip(members, probs):
+        P.set_x0(p["x0"])
+    B = S.Batch(members, st)
+    t_setup = time.perf_counter() - t
+    nodes = int(sum(P.n for P in members))
+    print("batch: %d problems, %d nodes, %d sweep tasks, %.2f GB, setup %.1fs"
+          % (len(members), nodes, B.n_tasks, B.device_bytes / 1e9, t_setup), file=sys.stderr, flush=True)
+    wg, tune_ms = tune.tune_batch(B, S.FP32)
+    B.run_steps(warmup, S.FP32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.run_steps(steps, S.FP32, sync=False)
+    torch.cuda.synchronize()
+    rate = steps / (time.perf_counter() - t0)
+    tot, ms_k = B.time_kernels(steps, S.FP32)
+    by_k = B.kernel_bytes(S.FP32)
+    kern = {"ms_step_events": round(tot, 5)}
+    for kn, ms, by in zip(KERNELS, ms_k, by_k):
+        kern[kn] = {"avg_ms": round(ms, 5), "bytes_per_launch": by, "GB_s": round(by / (ms * 1e-3) / 1e9, 1),
+                    "frac_hbm": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    step_bytes = float(sum(by_k))
+    out = {"workload": "batched: 256 uneven trees, nx 4..32, nu=nx/2, N 5..20, branching 2..4 for 2..5 "
+                       "stages then 1, box+ball, AV@R_0.9, Dirichlet probabilities",
+           "problems": len(members), "nodes": nodes, "batched_steps_per_s": round(rate, 2),
+           "problem_iters_per_s": round(rate * len(members), 1), "node_steps_per_s": round(rate * nodes, 1),
+           "ms_per_step": round(1000.0 / rate, 4), "bytes_per_step": step_bytes,
+           "GB_s": round(step_bytes * rate / 1e9, 1), "frac_hbm": round(step_bytes * rate / 1e9 / HBM_PEAK_GBS, 4),
+           "device_bytes": int(B.device_bytes + sum(P.sizes["device_bytes"] for P in members)),
+           "kernels_f32": kern, "node_workgroup": wg,
+           "tuner_ms_per_step": {str(k): round(v, 4) for k, v in tune_ms.items()},
+           "gen_s": round(gen_s, 2), "gen_workers": workers, "setup_s": round(t_setup, 2)}
+    print("batch: %.1f batched steps/s (%.3f ms), %.1f GB/s" % (rate, 1000.0 / rate, out["GB_s"]),
+          file=sys.stderr, flush=True)
+    if solve:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = B.solve([p["x0"] for p in probs])
+        t_solve = time.perf_counter() - t0
+        it = np.array([i["iters"] for i in infos])
+        ok = sum(i["status"] == S.SPOCK_OK for i in infos)
+        out["time_to_tol"] = {"eps": 1e-4, "seconds": round(t_solve, 3),
+                              "converged": int(ok), "of": len(infos), "max_iters": max_iters,
+                              "iters_median": int(np.median(it)), "iters_max": int(it.max()),
+                              "refined_in_f64": int(sum(bool(i["refined"]) for i in infos))}
+        print("batch time-to-tol: %s" % out["time_to_tol"], file=sys.stderr, flush=True)
+    B.close()
+    for P in members:
+        P.close()
+    return out
 
 
 def serve_bench(S, W, duration_s=10.0, session_rate=20.0, req_per_session=10, gap_mean=0.5,
@@ -279,6 +365,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0, help="sessions per second (10 requests each)")
     ap.add_argument("--serve-rate-sustained", type=float, default=0.5,
                     help="a second, lower session rate the device keeps up with (0: skip)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--batch-problems", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=50)
+    ap.add_argument("--no-batch-solve", action="store_true")
     ap.add_argument("--cpu-baseline-only", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: K steps per precision and a 1 GiB device copy")
@@ -298,6 +388,12 @@ def main():
         print("bench.py measures one GPU only: the CP step of one scenario tree runs on one MI355X "
               "(multi-GPU sharding by subtrees is described in DESIGN.md, not built)", file=sys.stderr)
         sys.exit(2)
+
+    batch_in = None
+    if not args.no_batch:
+        batch_in = make_batch_inputs(args.batch_problems)
+        print("batch inputs: %d problems in %.1fs (%d workers)" % (len(batch_in[0]), batch_in[1], batch_in[2]),
+              file=sys.stderr, flush=True)
 
     import torch
 
@@ -355,6 +451,11 @@ def main():
         tol["speedup_mixed_vs_fp64"] = round(tol["fp64"]["seconds"] / max(tol["mixed"]["seconds"], 1e-9), 3)
 
     P.close()
+    batched = None
+    if batch_in is not None:
+        batched = batch_bench(S, *batch_in, steps=args.batch_steps + (args.batch_steps & 1), warmup=6,
+                              solve=not args.no_batch_solve)
+        batch_in = None
     serve = None
     if not args.no_serve:
         serve = serve_bench(S, W, duration_s=args.serve_seconds, session_rate=args.serve_rate)
@@ -372,7 +473,8 @@ def main():
                    "f64 final check and refinement", "nodes": nodes, "nx": 50, "nu": 25,
                    "setup_s": round(t_setup, 3)},
         "fp64": {"iters_per_s": round(v64, 2), "ms_per_step": round(1000.0 / v64, 4)},
-        "kernels": kt, "roofline": roofline, "time_to_tol": tol, "serve": serve, "cpu_baseline": cpu,
+        "kernels": kt, "roofline": roofline, "time_to_tol": tol, "batched": batched, "serve": serve,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 

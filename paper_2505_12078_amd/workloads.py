@@ -111,6 +111,30 @@ def _stable_gaussian(rng, nx, radius=0.95):
             return radius * G / rho
 
 
+def _draw_dynamics(rng, n, nx, nu):
+    """A^j (scaled to spectral radius 0.95) then B^j for j = 1..n-1, in that
+    order.  The spectral radii are computed for all nodes at once; if any draw
+    would be redrawn, the draws are replayed node by node from the same state,
+    so the result is always that of the node-by-node order."""
+    A = np.zeros((n, nx, nx))
+    B = np.zeros((n, nx, nu))
+    if n <= 1:
+        return A, B
+    state = rng.bit_generator.state
+    for j in range(1, n):
+        A[j] = rng.standard_normal((nx, nx))
+        B[j] = rng.standard_normal((nx, nu))
+    rho = np.max(np.abs(np.linalg.eigvals(A[1:])), axis=1)
+    if np.all(rho >= 1e-3):
+        A[1:] = 0.95 * A[1:] / rho[:, None, None]
+        return A, B
+    rng.bit_generator.state = state
+    for j in range(1, n):
+        A[j] = _stable_gaussian(rng, nx)
+        B[j] = rng.standard_normal((nx, nu))
+    return A, B
+
+
 def _guard_x0(x0, parent, A, x_hi, x_ball, xN_hi, xN_ball, n_nl, margin=0.9):
     """Halve x0 until the zero-input rollout keeps a margin inside every box/ball.
 
@@ -148,11 +172,7 @@ def make_problem(parent, nx, nu, rng, *, prob_kind="uniform", gamma=0.95,
     n = len(parent)
     n_nl = int(np.sum(np.bincount(parent[1:], minlength=n) > 0))
     prob = draw_cond_probs(parent, rng, prob_kind)
-    A = np.zeros((n, nx, nx))
-    B = np.zeros((n, nx, nu))
-    for j in range(1, n):
-        A[j] = _stable_gaussian(rng, nx)
-        B[j] = rng.standard_normal((nx, nu))
+    A, B = _draw_dynamics(rng, n, nx, nu)
     x0 = rng.uniform(-x0_range, x0_range, size=nx)
     c = None
     if affine:

@@ -122,3 +122,48 @@ def test_autotuner_picks_a_candidate(tmp_path):
         assert again == best
         P.set_settings(eps=1e-4)
         assert P.solve(p["x0"])["code"] == S.SPOCK_OK
+
+
+def test_batched_workload_launch_equals_alone_and_oracle():
+    """The batched workload's first 40 members (nx 4..32, up to 14,677 nodes,
+    54,373 in all) in the launch configuration the benchmark's autotuner picks
+    (256-thread node workgroups): after batched steps every member's iterate is
+    bitwise the one its own steps give, in both precisions, and the two
+    smallest members match the oracle's CP steps from zero."""
+    probs = [W.batch_problem(k) for k in range(40)]
+    small = sorted(range(len(probs)), key=lambda k: len(probs[k]["parent"]))[:2]
+    data = {k: O.Data(probs[k]) for k in small}
+    alphas = {k: O.step_size(data[k]) for k in small}
+
+    def handle(k):
+        P = S.Problem(probs[k], S.default_settings(alpha=alphas.get(k, 0.0)))
+        P.set_x0(probs[k]["x0"])
+        return P
+
+    for prec, steps in ((S.FP64, 2), (S.FP32, 4)):
+        alone = []
+        for k in range(len(probs)):
+            with handle(k) as P:
+                P.set_launch(256, prec)
+                P.run_steps(steps, prec)
+                alone.append(P.get_iterate())
+        hs = [handle(k) for k in range(len(probs))]
+        with S.Batch(hs, S.default_settings()) as B:
+            B.set_launch(256, prec)
+            B.run_steps(steps, prec)
+        for k, h in enumerate(hs):
+            z, e = h.get_iterate()
+            h.close()
+            assert np.array_equal(z, alone[k][0]) and np.array_equal(e, alone[k][1]), (prec, k)
+            if k in small:
+                D = data[k]
+                F = O.Offline(D)
+                zo, eo = np.zeros(D.layout.nz), np.zeros(D.layout.neta)
+                for _ in range(steps):
+                    zo, eo = O.cp_step(D, F, zo, eo, alphas[k])
+                scale = max(1.0, np.abs(zo).max(), np.abs(eo).max())
+                tol = 1e-10 if prec == S.FP64 else 2e-4
+                err = max(np.abs(z - zo).max(), np.abs(e - eo).max()) / scale
+                print("member %d (%d nodes) %s: max error / scale %.2e" % (k, len(probs[k]["parent"]),
+                      "f64" if prec == S.FP64 else "f32", err), flush=True)
+                assert err < tol, (prec, k, err)
