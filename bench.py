@@ -35,6 +35,9 @@ WORKLOAD = ("large tree: N=15, branching 2 at stages 0-9 then 1 (1024 scenarios,
 HBM_PEAK_GBS = 8000.0
 KERNELS = ("prep", "bsweep", "fsweep", "dual")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+TRAFFIC_BATCHED_FILE = os.path.join(ROOT, "profiles", "traffic_batched.json")
+BATCH_WORKLOAD = ("batched: 256 uneven trees, nx 4..32, nu=nx/2, N 5..20, branching 2..4 for 2..5 "
+                  "stages then 1, box+ball, AV@R_0.9, Dirichlet probabilities")
 
 
 def _kernel_source_hash():
@@ -46,11 +49,11 @@ def _kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def _measured_traffic(kernel):
+def _measured_traffic(kernel, path=TRAFFIC_FILE):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when the kernel sources changed since it was taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -96,13 +99,15 @@ def _batch_member(k):
     return W.batch_problem(k)
 
 
-def make_batch_inputs(n_problems):
+def make_batch_inputs(n_problems, workers=None):
     """The batched workload's members, drawn in a process pool (each member is
     seeded by its index, so the pool size does not change them).  Called before
-    anything touches the GPU: the pool forks without exec."""
+    anything touches the GPU: the pool forks without exec.  Under a profiler
+    that sets up the GPU before the program starts, draw in-process
+    (workers=1)."""
     import multiprocessing as mp
     t = time.perf_counter()
-    workers = max(1, min(16, os.cpu_count() or 1, n_problems))
+    workers = max(1, min(workers or 16, os.cpu_count() or 1, n_problems))
     if workers == 1:
         probs = [_batch_member(k) for k in range(n_problems)]
     else:
@@ -142,10 +147,10 @@ def batch_bench(S, probs, gen_s, workers, steps, warmup, solve=True, max_iters=2
     kern = {"ms_step_events": round(tot, 5)}
     for kn, ms, by in zip(KERNELS, ms_k, by_k):
         kern[kn] = {"avg_ms": round(ms, 5), "bytes_per_launch": by, "GB_s": round(by / (ms * 1e-3) / 1e9, 1),
-                    "frac_hbm": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                    "frac_hbm": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "traffic": _measured_traffic("k_%s<float>" % kn, TRAFFIC_BATCHED_FILE)}
     step_bytes = float(sum(by_k))
-    out = {"workload": "batched: 256 uneven trees, nx 4..32, nu=nx/2, N 5..20, branching 2..4 for 2..5 "
-                       "stages then 1, box+ball, AV@R_0.9, Dirichlet probabilities",
+    out = {"workload": BATCH_WORKLOAD,
            "problems": len(members), "nodes": nodes, "batched_steps_per_s": round(rate, 2),
            "problem_iters_per_s": round(rate * len(members), 1), "node_steps_per_s": round(rate * nodes, 1),
            "ms_per_step": round(1000.0 / rate, 4), "bytes_per_step": step_bytes,
@@ -282,12 +287,41 @@ def _profile_pass(steps):
     P.close()
 
 
-def summarize_counters(fetch_dir, write_dir, trace_dir, profile_json):
+def _profile_batch_pass(n_problems, steps, node_wg):
+    """What a profiler should see for the batched workload: `steps` float32
+    batched steps of its 256 members at `node_wg` threads per node workgroup
+    (the autotuner's pick on this workload) and one copy of 1 GiB."""
+    probs, _, _ = make_batch_inputs(n_problems, workers=1)
+    import torch
+
+    from paper_2505_12078_amd import spock as S
+    torch.cuda.set_device(0)
+    members = [S.Problem(p, S.default_settings()) for p in probs]
+    for P, p in zip(members, probs):
+        P.set_x0(p["x0"])
+    B = S.Batch(members, S.default_settings())
+    B.set_launch(node_wg, S.FP32)
+    B.run_steps(steps + (steps & 1), S.FP32)
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"steps": steps + (steps & 1), "copy_bytes": 1 << 30, "source_hash": _kernel_source_hash(),
+                      "workload": BATCH_WORKLOAD, "node_workgroup": node_wg,
+                      "bytes_f32": dict(zip(KERNELS, B.kernel_bytes(S.FP32))), "bytes_f64": None}))
+    B.close()
+    for P in members:
+        P.close()
+
+
+def summarize_counters(fetch_dir, write_dir, trace_dir, profile_json, out_path=None):
     """Per-launch HBM traffic of the four kernels from two rocprofv3 counter
     runs of `bench.py --profile` (FETCH_SIZE, WRITE_SIZE; KiB per dispatch),
     scaled by what the same counters read for the 1 GiB device copy of that
     run, next to the algorithmic bytes and the kernel-trace durations.  Writes
-    profiles/traffic.json and prints a markdown table."""
+    profiles/traffic.json (or out_path; the batched workload's counters, from
+    `bench.py --profile-batch`, go to TRAFFIC_BATCHED_FILE) and prints
+    a markdown table."""
     import csv
     import glob
     import re
@@ -328,7 +362,7 @@ def summarize_counters(fetch_dir, write_dir, trace_dir, profile_json):
         m = pat.search(r["Name"])
         if m:
             avg_us["k_%s<%s>" % (m.group(1), m.group(2))] = float(r["AverageNs"]) / 1e3
-    out = {"workload": WORKLOAD, "source_hash": prof["source_hash"],
+    out = {"workload": prof.get("workload", WORKLOAD), "source_hash": prof["source_hash"],
            "calibration": {"copy_bytes": copy_bytes, "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
            "kernels": {}}
     print("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM MB (calibrated) | algorithmic MB | ratio | avg us (trace) |")
@@ -336,7 +370,7 @@ def summarize_counters(fetch_dir, write_dir, trace_dir, profile_json):
     for prec, tag in (("float", "bytes_f32"), ("double", "bytes_f64")):
         for kn in KERNELS:
             key = "k_%s<%s>" % (kn, prec)
-            if key not in fetch or key not in write:
+            if key not in fetch or key not in write or not prof.get(tag):
                 continue
             fb, wb = fetch[key] * 1024.0 * ff, write[key] * 1024.0 * wf
             alg = prof[tag][kn]
@@ -346,7 +380,7 @@ def summarize_counters(fetch_dir, write_dir, trace_dir, profile_json):
             print("| %s | %.1f | %.1f | %.1f | %.1f | %.2f | %s |" % (
                 names.get(key, key), fetch[key], write[key], (fb + wb) / 1e6, alg / 1e6, (fb + wb) / alg,
                 "%.1f" % avg_us[key] if key in avg_us else "-"))
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(out_path or TRAFFIC_FILE, "w") as fh:
         json.dump(out, fh, indent=1)
     print("calibration: fetch x%.4f, write x%.4f (1 GiB copy reads FETCH_SIZE %.0f KiB, WRITE_SIZE %.0f KiB)" % (
         ff, wf, copy_f, copy_w))
@@ -372,11 +406,18 @@ def main():
     ap.add_argument("--cpu-baseline-only", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: K steps per precision and a 1 GiB device copy")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="short run for rocprofv3: K float32 batched steps of the batched workload and a 1 GiB copy")
+    ap.add_argument("--batch-node-wg", type=int, default=256)
+    ap.add_argument("--traffic-out", default=None, help="output of --summarize-counters (default profiles/traffic.json)")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "TRACE_DIR", "PROFILE_JSON"),
                     help="write profiles/traffic.json from rocprofv3 output of --profile runs (no GPU needed)")
     args = ap.parse_args()
     if args.summarize_counters:
-        summarize_counters(*args.summarize_counters)
+        summarize_counters(*args.summarize_counters, out_path=args.traffic_out)
+        return
+    if args.profile_batch:
+        _profile_batch_pass(args.batch_problems, args.steps, args.batch_node_wg)
         return
     if args.cpu_baseline_only:
         _cpu_baseline_only(args.cpu_steps)
