@@ -21,7 +21,8 @@
  *  - Arrays are dense, row-major, float64, in node order.  Nodes are numbered
  *    stage by stage (breadth first): parent[j] < j, children of a node are
  *    consecutive, all non-leaf nodes precede all leaves, every leaf sits at
- *    the last stage N.
+ *    the last stage N, and 1 <= N <= 511 (at most 512 stages); a description
+ *    that breaks any of these is rejected with SPOCK_E_INVALID.
  *  - One problem handle may be used by one host thread at a time.
  *
  * Canonical iterate layout (scaled variables, the space the CP method runs

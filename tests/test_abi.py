@@ -92,3 +92,21 @@ def test_settings_validation(lib):
         S.footprint(W.config_problem(0), S.default_settings(check_every=3))
     with pytest.raises(S.SpockError):
         S.footprint(W.config_problem(0), S.default_settings(eps=0.0))
+
+
+def test_degenerate_and_maximum_trees(lib):
+    rng = np.random.default_rng(21)
+    # a single node (no dynamics, no stage) is not a tree the method solves
+    p = W.config_problem(0)
+    one = dict(p, parent=np.array([-1], dtype=np.int32), prob=np.ones(1), A=p["A"][:1], B=p["B"][:1],
+               gamma=p["gamma"][:0])
+    assert "two nodes" in _bad(one)
+    # nx = 0
+    assert "nx" in _bad(p, nx=0)
+    # the longest horizon: 512 stages (a single scenario) is accepted, 513 are not
+    par, _ = W.tree_from_branching([1] * 511)
+    ok = W.make_problem(par, 2, 1, rng, name="chain511")
+    assert S.footprint(ok) > 0
+    par, _ = W.tree_from_branching([1] * 512)
+    long = W.make_problem(par, 2, 1, rng, name="chain512")
+    assert "horizon" in _bad(long)

@@ -54,6 +54,13 @@ def _cases():
     par, _ = W.tree_from_branching([24, 2])
     cases["very_wide"] = W.make_problem(par, 4, 2, np.random.default_rng(15), prob_kind="dirichlet",
                                         gamma=0.7, x_ball=7.0, name="very_wide")
+    # the longest horizon the library takes (512 stages), as a single scenario
+    # and with eight scenarios branching off near the root
+    par, _ = W.tree_from_branching([1] * 511)
+    cases["deep_chain"] = W.make_problem(par, 2, 1, np.random.default_rng(16), x_ball=6.0, name="deep_chain")
+    par, _ = W.tree_from_branching([2, 2, 2] + [1] * 300)
+    cases["deep_branched"] = W.make_problem(par, 3, 2, np.random.default_rng(17), prob_kind="dirichlet",
+                                            gamma=0.8, x_ball=7.0, name="deep_branched")
     par, _ = W.tree_from_branching([2, 1, 1])
     cases["big_nx"] = W.make_problem(par, 70, 40, np.random.default_rng(14), prob_kind="dirichlet",
                                      x_ball=12.0, name="big_nx")
