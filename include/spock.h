@@ -71,7 +71,7 @@ typedef struct spock_problem_desc {
     int32_t n_nodes;          /* n >= 2 */
     const int32_t* parent;    /* [n], parent[0] = -1 */
     const double* cond_prob;  /* [n], > 0, children of each node sum to 1 */
-    int32_t nx, nu;           /* >= 1 */
+    int32_t nx, nu;           /* >= 1, nx + nu <= 128 */
     const double* A;          /* [n][nx][nx]; entry 0 ignored */
     const double* B;          /* [n][nx][nu]; entry 0 ignored */
     const double* c;          /* [n][nx] or NULL (= 0) */

@@ -299,8 +299,9 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     p->neta = o;
     p->M_stride = ((long long)nx * p->m + 31) / 32 * 32;
     p->KR_stride = ((long long)nu * p->m + 31) / 32 * 32;
-    if (nx > 64 * spk::kVecPL || nu > 64 * spk::kVecPL)
-        return fail(SPOCK_E_INVALID, "nx and nu must not exceed 256");
+    // the column-lane products place at most 128 outputs on a wavefront's
+    // lanes; [Abar|B]^T h has nx + nu of them
+    if (p->m > 128) return fail(SPOCK_E_INVALID, "nx + nu must not exceed 128");
     if (node_lds_bytes(p, 64, 8) > 64 * 1024 ||
         spk::sweep_int_bytes(p->N) + spk::sweep_elems(nx, nu) * 8 > 64 * 1024)
         return fail(SPOCK_E_INVALID, "nx + nu or the branching is too large for one wavefront's LDS");

@@ -103,6 +103,11 @@ def test_degenerate_and_maximum_trees(lib):
     assert "two nodes" in _bad(one)
     # nx = 0
     assert "nx" in _bad(p, nx=0)
+    # the widest state and input: nx + nu = 128 is accepted, 129 is not
+    par, _ = W.tree_from_branching([2, 1])
+    assert S.footprint(W.make_problem(par, 96, 32, rng, name="m128")) > 0
+    assert "128" in _bad(W.make_problem(par, 97, 32, rng, name="m129"))
+    assert "128" in _bad(W.make_problem(par, 150, 10, rng, name="nx150"))
     # the longest horizon: 512 stages (a single scenario) is accepted, 513 are not
     par, _ = W.tree_from_branching([1] * 511)
     ok = W.make_problem(par, 2, 1, rng, name="chain511")

@@ -61,6 +61,10 @@ def _cases():
     par, _ = W.tree_from_branching([2, 2, 2] + [1] * 300)
     cases["deep_branched"] = W.make_problem(par, 3, 2, np.random.default_rng(17), prob_kind="dirichlet",
                                             gamma=0.8, x_ball=7.0, name="deep_branched")
+    # the widest state and input the library takes: nx + nu = 128
+    par, _ = W.tree_from_branching([2, 1])
+    cases["max_m"] = W.make_problem(par, 96, 32, np.random.default_rng(18), prob_kind="dirichlet",
+                                    x_ball=12.0, name="max_m")
     par, _ = W.tree_from_branching([2, 1, 1])
     cases["big_nx"] = W.make_problem(par, 70, 40, np.random.default_rng(14), prob_kind="dirichlet",
                                      x_ball=12.0, name="big_nx")
