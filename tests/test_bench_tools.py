@@ -47,3 +47,16 @@ def test_summarize_counters(tmp_path, monkeypatch):
     p = out["kernels"]["k_prep<double>"]
     assert p["bytes_per_launch"] == 50 * 1024 * 2 + 4 * 1024 and p["avg_us_trace"] is None
     assert "k_dual<float>" not in out["kernels"]
+
+
+def test_batch_inputs_do_not_depend_on_the_pool():
+    # members are seeded by their index: a process pool draws the same ones
+    pooled, _, workers = bench.make_batch_inputs(6, workers=3)
+    alone, _, one = bench.make_batch_inputs(6, workers=1)
+    assert one == 1 and workers >= 1
+    for a, b in zip(pooled, alone):
+        for k, v in a.items():
+            if hasattr(v, "tobytes"):
+                assert v.tobytes() == b[k].tobytes(), k
+            else:
+                assert v == b[k], k
