@@ -427,7 +427,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the CP step of one scenario tree runs on one MI355X "
-              "(multi-GPU sharding by subtrees is described in DESIGN.md, not built)", file=sys.stderr)
+              "(sharding a tree by subtrees across GPUs is designed, not built)", file=sys.stderr)
         sys.exit(2)
 
     batch_in = None
