@@ -628,7 +628,7 @@ def solve(prob, eps=1e-6, max_iters=20000, precondition=True, alpha=None,
 
 
 def nested_cost(prob, x, u):
-    """Value of the nested risk objective (Sec. 3.4) for an unscaled (x, u):
+    """Value of the nested risk objective (Sec. 3.5, with the conditional risk mappings of Sec. 3.4) for an unscaled (x, u):
     leaf values x^T Q_N x, then per non-leaf node the AV@R over its children
     of (stage cost on the edge + child value)."""
     T = Tree(prob["parent"], prob["prob"])

@@ -1,7 +1,7 @@
 """End-to-end pins of the oracle's CP iteration (Sec. 4.1, Sec. 5.3).
 
 The solution of the conic problem is pinned by things the iteration never
-computes: the nested risk objective of Sec. 3.4 evaluated directly on the
+computes: the nested risk objective of Sec. 3.5 evaluated directly on the
 returned trajectory, a textbook Riccati recursion in the risk-neutral special
 case, and an independent nonlinear-programming solve of the same tiny problem.
 """

@@ -278,7 +278,7 @@ def test_L_norm_hand_value(golden):
 
 
 def test_L_rows_match_problem_statement():
-    """L z reproduces the quantities of the epigraph problem (Sec. 3.4): the
+    """L z reproduces the quantities of the epigraph problem (Sec. 3.5): the
     SOC block of an edge encodes the stage cost of the ancestor, the leaf
     block the terminal cost, and the risk row s - b^T y."""
     prob = W.random_ragged_problem(9, N=3, nx=3, nu=2)
@@ -324,3 +324,105 @@ def test_preconditioning_is_a_change_of_variables():
         lhs = D1.A[j] @ (D1.Sx * x[i]) + D1.B[j] @ (D1.Su * u[i])
         np.testing.assert_allclose(lhs, D1.S_of(j) * (D0.A[j] @ x[i] + D0.B[j] @ u[i]), rtol=1e-12)
     assert D1.x0 == pytest.approx(D1.Sx * prob["x0"])
+
+
+# ----------------------------------------------------------------------------
+# residuals xi1, xi2 (Sec. 5.3): the inclusions that define them
+# ----------------------------------------------------------------------------
+#
+# The primal update of T is z+ = prox_{alpha f}(z - alpha L* eta), so
+#     xi1 - L* eta+  lies in  the subdifferential of f at z+,
+# with f = s0 + indicator(S1) + indicator(S2): its s0 entry is 1, its (x, u)
+# part is normal to the affine dynamics set (orthogonal to null(C)), and the
+# (y^i, tau^{ch(i)}, s^{ch(i)}) block of every non-leaf node is normal to the
+# kernel set (orthogonal to null(G_i)); every other entry is 0.
+# The dual update gives
+#     w = xi2 + L z+  lies in  the subdifferential of g* = support function of
+# S3 at eta+, i.e. w is in S3 and eta+ is normal to S3 at w:
+#     proj_S3(w) = w  and  proj_S3(w + eta+) = w.
+
+
+def _xi1_inclusion_error(D, zp, ep, xi1):
+    """Largest violation of xi1 - L* eta+ in df(z+), relative to |xi1|."""
+    T, Y = D.tree, D.layout
+    w = xi1 - O.apply_Lt(D, ep)
+    scale = max(1.0, np.abs(xi1).max())
+    errs = [abs(w[Y.z_s0] - 1.0)]
+    x = np.array([Y.x(zp, i) for i in range(T.n)])
+    u = np.array([Y.u(zp, i) for i in range(T.n_nl)])
+    _, _, C = _dense_S1_projection(D, x, u)
+    wxu = np.concatenate([w[Y.z_x:Y.z_x + T.n * D.nx], w[Y.z_u:Y.z_u + T.n_nl * D.nu]])
+    errs.append(np.abs(scipy.linalg.null_space(C).T @ wxu).max())
+    for i in T.nonleaf:
+        kids = T.ch[i]
+        blk = np.concatenate([Y.y(w, i), [Y.tau(w, j)[0] for j in kids], [Y.s(w, j)[0] for j in kids]])
+        N = scipy.linalg.null_space(O.S2_matrix(D.gamma[i], len(kids)))
+        errs.append(np.abs(N.T @ blk).max())
+    return max(errs) / scale
+
+
+def _xi2_inclusion_error(D, zp, ep, xi2):
+    """Largest violation of xi2 + L z+ in dg*(eta+), relative to |w| + |eta+|."""
+    w = xi2 + O.apply_L(D, zp)
+    scale = max(1.0, np.abs(w).max(), np.abs(ep).max())
+    e_in = np.abs(O.project_S3(D, w) - w).max()
+    e_normal = np.abs(O.project_S3(D, w + ep) - w).max()
+    return max(e_in, e_normal) / scale
+
+
+def _residual_cases():
+    yield "cfg0", W.config_problem(0), True
+    yield "cfg0_noprec", W.config_problem(0), False
+    yield "ragged_affine", W.random_ragged_problem(21, N=3, nx=3, nu=2, affine=True), True
+    yield "ragged_noball", W.random_ragged_problem(22, N=3, nx=2, nu=2, ball=False), False
+    yield "ragged_gamma01", W.random_ragged_problem(23, N=3, nx=3, nu=1, gamma=None), True
+
+
+@pytest.mark.parametrize("case", [c[0] for c in _residual_cases()])
+def test_residuals_satisfy_their_defining_inclusions(case):
+    """Sec. 5.3: xi1 - L* eta+ in df(z+) and xi2 + L z+ in dg*(eta+), from
+    random iterates (not only near a fixed point), so every term of xi1, xi2
+    is exercised, including the 1/alpha factors and the sign of L* d_eta."""
+    name, prob, precond = next(c for c in _residual_cases() if c[0] == case)
+    D = O.Data(prob, precondition=precond)
+    F = O.Offline(D)
+    alpha = O.step_size(D)
+    Y = D.layout
+    for seed in range(3):
+        rng = np.random.default_rng([31, seed])
+        z = rng.standard_normal(Y.nz) * 3
+        eta = rng.standard_normal(Y.neta) * 3
+        zp, ep = O.cp_step(D, F, z, eta, alpha)
+        xi1, xi2 = O.residuals(D, z, eta, zp, ep, alpha)
+        assert _xi1_inclusion_error(D, zp, ep, xi1) < 1e-11
+        assert _xi2_inclusion_error(D, zp, ep, xi2) < 1e-11
+
+
+def test_residual_pins_reject_planted_mistakes():
+    """The inclusion pins above fail for the plausible mistakes in xi1, xi2:
+    the sign of L* d_eta flipped, either 1/alpha dropped, the sign of L dz
+    flipped, and the roles of the new and old iterate swapped."""
+    for name, prob, precond in _residual_cases():
+        D = O.Data(prob, precondition=precond)
+        F = O.Offline(D)
+        alpha = O.step_size(D)
+        Y = D.layout
+        rng = np.random.default_rng([32, len(name)])
+        z = rng.standard_normal(Y.nz) * 3
+        eta = rng.standard_normal(Y.neta) * 3
+        zp, ep = O.cp_step(D, F, z, eta, alpha)
+        dz, de = z - zp, eta - ep
+        bad1 = {
+            "L* sign": dz / alpha + O.apply_Lt(D, de),
+            "1/alpha dropped": dz - O.apply_Lt(D, de),
+            "old/new swapped": -dz / alpha + O.apply_Lt(D, de),
+        }
+        bad2 = {
+            "L sign": de / alpha + O.apply_L(D, dz),
+            "1/alpha dropped": de - O.apply_L(D, dz),
+            "old/new swapped": -de / alpha + O.apply_L(D, dz),
+        }
+        for label, xi1 in bad1.items():
+            assert _xi1_inclusion_error(D, zp, ep, xi1) > 1e-3, (name, label)
+        for label, xi2 in bad2.items():
+            assert _xi2_inclusion_error(D, zp, ep, xi2) > 1e-3, (name, label)
