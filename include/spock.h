@@ -109,6 +109,8 @@ typedef struct spock_info {
     int64_t iters_fp32;     /* of which in float32 */
     double rel_res, xi1_inf, xi2_inf;
     double s0;              /* objective value s^0 (= V* at convergence) */
+    double t_setup_s;       /* wall time spock_problem_create took for this handle
+                               (validation, scaling, Alg. 1, exact ||L||, upload) */
     double t_solve_s;       /* wall time of the solve call */
     int32_t status;         /* the same code the call returned */
     int32_t precision_used; /* precision of the final accepted step */
@@ -189,6 +191,26 @@ int32_t spock_set_x0(spock_problem* p, const double* x0);
 int32_t spock_apply_T(spock_problem* p, const double* z, const double* eta, double* z_out,
                       double* eta_out, int32_t precision, double* xi);
 int32_t spock_apply_L(spock_problem* p, const double* z, double* eta_out, int32_t precision);
+
+/*
+ * The two parts of prox_{alpha f} (Sec. 4.5) on their own, host arrays, scaled
+ * space, float64 or float32 kernels as precision says.
+ *  spock_project_S1: Euclidean projection of (xbar, ubar) onto the dynamics
+ *    set S1 of Sec. 4.3 with x^0 fixed to the handle's initial state
+ *    (spock_set_x0), computed by the online sweep of Alg. 2 (Sec. 5.1).
+ *    xbar [n][nx] (row 0 is ignored: x^0 is fixed), ubar [n_nl][nu];
+ *    x_out [n][nx], u_out [n_nl][nu].
+ *  spock_project_S2: orthogonal projection of every non-leaf node's block
+ *    (y^i, tau^[i], s^[i]) onto the kernel of [E^T -I -I] of Sec. 4.3 (the
+ *    AV@R kernel set, with E of Sec. 3.3).  y in the canonical y layout (per
+ *    non-leaf node 2 n_ch + 1 entries), tau and s per node 1..n-1; the outputs
+ *    have the same shapes.
+ * Errors: SPOCK_E_INVALID (null pointer, bad precision), SPOCK_E_HIP.
+ */
+int32_t spock_project_S1(spock_problem* p, const double* xbar, const double* ubar, double* x_out, double* u_out,
+                         int32_t precision);
+int32_t spock_project_S2(spock_problem* p, const double* y, const double* tau, const double* s, double* y_out,
+                         double* tau_out, double* s_out, int32_t precision);
 int32_t spock_apply_Lt(spock_problem* p, const double* eta, double* z_out, int32_t precision);
 int32_t spock_prox_gconj(spock_problem* p, const double* w, double* eta_out, int32_t precision);
 

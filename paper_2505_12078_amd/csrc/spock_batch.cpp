@@ -117,7 +117,7 @@ int32_t batch_tick(spock_batch* b, std::vector<Member>& m, bool stall_exit) {
             if (sizeof(real) == 4) x.iters32 += ce;
             std::memcpy(&x.x1, &b->h_res[2 * k], 8);
             std::memcpy(&x.x2, &b->h_res[2 * k + 1], 8);
-            x.rel = std::max(x.x1, x.x2) / std::max(1.0, std::max(p->xi_ref[0], p->xi_ref[1]));
+            x.rel = rel_of(x.x1, x.x2, std::max(1.0, std::max(p->xi_ref[0], p->xi_ref[1])));
             if (!std::isfinite(x.rel)) {
                 x.status = SPOCK_E_DIVERGED;
                 x.live = false;
@@ -381,7 +381,10 @@ int32_t spock_batch_solve(spock_batch* b, const double* const* x0s, const int32_
         infos[k].refined = m[k].refined;
     }
     const double t = now_s() - t0;
-    for (int k = 0; k < n; ++k) infos[k].t_solve_s = t;
+    for (int k = 0; k < n; ++k) {
+        infos[k].t_solve_s = t;
+        infos[k].t_setup_s = b->probs[k]->t_setup;
+    }
     return SPOCK_OK;
 }
 

@@ -940,6 +940,7 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
     int32_t r = check_settings(s);
     if (r) return r;
     spock_problem* p = nullptr;
+    const double t_create = now_s();
     try {
         p = new spock_problem();
         p->set = *s;
@@ -1039,6 +1040,7 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
             spock_problem_destroy(p);
             return r;
         }
+        p->t_setup = now_s() - t_create;
         *out = p;
         return SPOCK_OK;
     } catch (const std::bad_alloc&) {
@@ -1116,7 +1118,7 @@ static int32_t iterate(spock_problem* p, long long budget, long long* taken, dou
         *taken += ce;
         r = read_res(p, x1, x2);
         if (r) return r;
-        *rel = std::max(*x1, *x2) / scale;
+        *rel = rel_of(*x1, *x2, scale);
         if (!std::isfinite(*rel)) return fail(SPOCK_E_DIVERGED, "non-finite residual");
         if (*rel <= p->set.eps) return SPOCK_OK;
         if (stall_exit) {
@@ -1174,7 +1176,7 @@ int32_t spock_solve(spock_problem* p, const double* x0, int32_t warm, spock_info
             p->s64.par = 0;
         } else {
             it = 1;
-            rel = std::max(x1, x2) / std::max(1.0, std::max(x1, x2));
+            rel = rel_of(x1, x2, std::max(1.0, std::max(x1, x2)));
         }
     }
     const long long budget = p->set.max_iters;
@@ -1201,7 +1203,7 @@ int32_t spock_solve(spock_problem* p, const double* x0, int32_t warm, spock_info
             if (!r2) r2 = read_res(p, &x1, &x2);
             if (r2) return r2;
             it += 1;
-            rel = std::max(x1, x2) / std::max(1.0, std::max(p->xi_ref[0], p->xi_ref[1]));
+            rel = rel_of(x1, x2, std::max(1.0, std::max(p->xi_ref[0], p->xi_ref[1])));
             if (rel <= p->set.eps) {
                 r = SPOCK_OK;
             } else if (it < budget) {
@@ -1234,6 +1236,7 @@ int32_t spock_solve(spock_problem* p, const double* x0, int32_t warm, spock_info
     inf.status = r;
     inf.precision_used = used;
     inf.refined = refined;
+    inf.t_setup_s = p->t_setup;
     inf.t_solve_s = now_s() - t0;
     if (info) *info = inf;
     if (r == SPOCK_E_NOT_CONVERGED) return fail(r, "max_iters reached before the tolerance");
@@ -1335,6 +1338,58 @@ int32_t spock_apply_T(spock_problem* p, const double* z, const double* eta, doub
     if (r) return r;
     if (z_out) std::copy(zz.begin(), zz.end(), z_out);
     if (eta_out) std::copy(ee.begin(), ee.end(), eta_out);
+    return SPOCK_OK;
+}
+
+// The z part of T with eta = 0 is prox_{alpha f}(z) (zbar = z): its (x, u)
+// block is the S1 projection (Alg. 2) and its (y, tau, s) block the S2
+// projection of every non-leaf node, computed by the step's own kernels.
+static int32_t prox_f_only(spock_problem* p, std::vector<double>& z, int32_t prec) {
+    std::vector<double> eta(p->neta, 0.0), zo(p->nz, 0.0);
+    int32_t r = spock_apply_T(p, z.data(), eta.data(), zo.data(), nullptr, prec, nullptr);
+    if (r) return r;
+    z.swap(zo);
+    return SPOCK_OK;
+}
+
+int32_t spock_project_S1(spock_problem* p, const double* xbar, const double* ubar, double* x_out, double* u_out,
+                         int32_t prec) {
+    if (!p || !xbar || !ubar || !x_out || !u_out) return fail(SPOCK_E_INVALID, "null argument");
+    int32_t r = check_prec(prec);
+    if (r) return r;
+    try {
+        std::vector<double> z(p->nz, 0.0);
+        std::copy(xbar, xbar + (size_t)p->n * p->nx, z.begin() + p->z_x);
+        std::copy(ubar, ubar + (size_t)p->n_nl * p->nu, z.begin() + p->z_u);
+        r = prox_f_only(p, z, prec);
+        if (r) return r;
+        std::copy(z.begin() + p->z_x, z.begin() + p->z_x + (size_t)p->n * p->nx, x_out);
+        std::copy(z.begin() + p->z_u, z.begin() + p->z_u + (size_t)p->n_nl * p->nu, u_out);
+    } catch (const std::bad_alloc&) {
+        return fail(SPOCK_E_NOMEM, "host allocation failed");
+    }
+    return SPOCK_OK;
+}
+
+int32_t spock_project_S2(spock_problem* p, const double* y, const double* tau, const double* s, double* y_out,
+                         double* tau_out, double* s_out, int32_t prec) {
+    if (!p || !y || !tau || !s || !y_out || !tau_out || !s_out) return fail(SPOCK_E_INVALID, "null argument");
+    int32_t r = check_prec(prec);
+    if (r) return r;
+    try {
+        const size_t e = (size_t)p->n - 1;
+        std::vector<double> z(p->nz, 0.0);
+        std::copy(y, y + p->ny, z.begin() + p->z_y);
+        std::copy(tau, tau + e, z.begin() + p->z_tau);
+        std::copy(s, s + e, z.begin() + p->z_s);
+        r = prox_f_only(p, z, prec);
+        if (r) return r;
+        std::copy(z.begin() + p->z_y, z.begin() + p->z_y + p->ny, y_out);
+        std::copy(z.begin() + p->z_tau, z.begin() + p->z_tau + e, tau_out);
+        std::copy(z.begin() + p->z_s, z.begin() + p->z_s + e, s_out);
+    } catch (const std::bad_alloc&) {
+        return fail(SPOCK_E_NOMEM, "host allocation failed");
+    }
     return SPOCK_OK;
 }
 

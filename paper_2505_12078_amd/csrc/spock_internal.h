@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <string>
@@ -111,6 +112,7 @@ struct spock_problem {
     bool have_ref = false;
     double xi_ref[2] = {0, 0};
     bool solved = false;
+    double t_setup = 0;        // seconds spock_problem_create took
 };
 
 template <typename real>
@@ -128,6 +130,12 @@ int32_t move_iterate(spock_problem* p, int to);
 int32_t zero_iterate(spock_problem* p);
 int32_t set_x0_device(spock_problem* p, const double* x0, bool check_feasible);
 double now_s();
+// rel_res of Sec. 5.3 from the two residual maxima: NaN when either is NaN
+// (std::max would return the other operand and hide it).
+inline double rel_of(double x1, double x2, double scale) {
+    if (x1 != x1 || x2 != x2) return NAN;
+    return std::max(x1, x2) / scale;
+}
 int32_t normalize_parity(spock_problem* p);
 int32_t ensure_ref(spock_problem* p, bool warm, long long* taken, double* x1, double* x2);
 

@@ -86,13 +86,20 @@ SPK_DEV T wave_sum(T v) {
     return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
+// Maximum that keeps a NaN from either side (fmax would drop it), so that a
+// non-finite iterate gives a non-finite residual and stops the solve.
+template <typename T>
+SPK_DEV T nmax(T a, T b) {
+    return (b > a || b != b) ? b : a;
+}
+
 template <typename T>
 SPK_DEV T wave_max(T v) {
-    v = fmax(v, dpp<0xB1>(v));
-    v = fmax(v, dpp<0x4E>(v));
-    v = fmax(v, dpp<0x141>(v));
-    v = fmax(v, dpp<0x140>(v));
-    return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
+    v = nmax(v, dpp<0xB1>(v));
+    v = nmax(v, dpp<0x4E>(v));
+    v = nmax(v, dpp<0x141>(v));
+    v = nmax(v, dpp<0x140>(v));
+    return nmax(nmax(lane_value(v, 0), lane_value(v, 16)), nmax(lane_value(v, 32), lane_value(v, 48)));
 }
 
 // Sum over the workgroup, same value returned to every thread; deterministic.
@@ -169,9 +176,12 @@ SPK_DEV void drain_stores() {
     __builtin_amdgcn_s_waitcnt(0x0F70);
 }
 
+// v >= 0 or NaN: the float64 bit patterns of non-negative values order as the
+// values, and a NaN with a clear sign bit orders above +inf, so the slot keeps
+// a NaN once any wavefront records one.
 template <typename real>
 SPK_DEV void record_max(unsigned long long* slot, real v) {
-    const double d = (double)v;
+    const double d = v != v ? __longlong_as_double(0x7FF8000000000000LL) : (double)v;
     atomicMax(slot, (unsigned long long)__double_as_longlong(d));
 }
 
@@ -584,7 +594,7 @@ SPK_DEV void fwd_block_c(const ProbDev<real>* __restrict__ P, int v, const real*
         const real ep = r < nbox ? moreau_box(eb, alpha, V.C.lo[r], V.C.hi[r]) : eb * cb;
         gm(eout)[off + r] = ep;
         const real de = ec[r] - ep;
-        if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
+        if (check) r2 = nmax(r2, fabs(de * ialpha - V.dblk[r]));
         V.dblk[r] = de;
     }
     if (check) {
@@ -626,14 +636,14 @@ SPK_DEV void fwd_block_risk(const ProbDev<real>* __restrict__ P, int v, long lon
         if (check) {
             const real de = ey[c] - ep;
             const real dy = yv[c] - yn[c];
-            r2 = fmax(r2, fabs(de * ialpha - dy));
+            r2 = nmax(r2, fabs(de * ialpha - dy));
             const real bc = c < k ? p[c] : (c == 2 * k ? real(1) : real(0));
-            r1 = fmax(r1, fabs(dy * ialpha - (de - bc * des)));
+            r1 = nmax(r1, fabs(dy * ialpha - (de - bc * des)));
         }
     }
     if (check && lane == 0) {
-        r2 = fmax(r2, fabs(des * ialpha - (wso - wsn)));
-        r1 = fmax(r1, fabs((sv - sn) * ialpha - des));
+        r2 = nmax(r2, fabs(des * ialpha - (wso - wsn)));
+        r1 = nmax(r1, fabs((sv - sn) * ialpha - des));
     }
 }
 
@@ -675,14 +685,14 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
         const real ep = r <= m ? V.blk[r] * cw : ct;
         gm(eout)[off + r] = ep;
         const real de = es[r] - ep;
-        if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
+        if (check) r2 = nmax(r2, fabs(de * ialpha - V.dblk[r]));
         V.dblk[r] = de;
     }
     if (check) {
         wave_sync();
         for (int r = lane; r < nx; r += 64) V.lxw[r] += V.C.qh[r] * V.dblk[r];
         for (int r = lane; r < P->nu; r += 64) V.luw[r] += V.C.rh[r] * V.dblk[nx + r];
-        if (lane == 0) r1 = fmax(r1, fabs((tv - tn) * ialpha - real(0.5) * (V.dblk[m] + V.dblk[m + 1])));
+        if (lane == 0) r1 = nmax(r1, fabs((tv - tn) * ialpha - real(0.5) * (V.dblk[m] + V.dblk[m + 1])));
     }
 }
 
@@ -725,7 +735,7 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
             const real ep = r < nx ? moreau_box(eb, alpha, V.C.loN[r], V.C.hiN[r]) : eb * cb;
             gm(eout)[off + r] = ep;
             const real de = ec[r] - ep;
-            if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
+            if (check) r2 = nmax(r2, fabs(de * ialpha - V.dblk[r]));
             V.dblk[r] = de;
         }
         if (check) {
@@ -763,13 +773,13 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
             const real ep = r <= nx ? V.blk[r] * cw : ct;
             gm(eout)[off + r] = ep;
             const real de = es[r] - ep;
-            if (check) r2 = fmax(r2, fabs(de * ialpha - V.dblk[r]));
+            if (check) r2 = nmax(r2, fabs(de * ialpha - V.dblk[r]));
             V.dblk[r] = de;
         }
         if (check) {
             wave_sync();
             for (int r = lane; r < nx; r += 64) V.lxw[r] += V.C.qnh[r] * V.dblk[r];
-            if (lane == 0) r1 = fmax(r1, fabs((sv - sn) * ialpha - real(0.5) * (V.dblk[nx] + V.dblk[nx + 1])));
+            if (lane == 0) r1 = nmax(r1, fabs((sv - sn) * ialpha - real(0.5) * (V.dblk[nx] + V.dblk[nx + 1])));
         }
     }
 }
@@ -1632,8 +1642,8 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
                       gm(static_cast<const real*>(zout + P->z_tau + fc - 1)), gm(zin + P->z_tau + fc - 1),
                       gm(P->prob + fc));
         if (check) {
-            for (int r = lane; r < nx; r += 64) r1 = fmax(r1, fabs((xo[r] - xn[r]) * ialpha - lxw[r]));
-            for (int r = lane; r < nu; r += 64) r1 = fmax(r1, fabs((uo[r] - un[r]) * ialpha - luw[r]));
+            for (int r = lane; r < nx; r += 64) r1 = nmax(r1, fabs((xo[r] - xn[r]) * ialpha - lxw[r]));
+            for (int r = lane; r < nu; r += 64) r1 = nmax(r1, fabs((uo[r] - un[r]) * ialpha - luw[r]));
         }
     } else {
         const long long lf = v - n_nl;
@@ -1658,7 +1668,7 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
         fwd_block_leaf(P, v, 1, st + off[2], st + off[3], st[off[4]], st[off[5]], eout, V, check, r1, r2);
         wave_sync();
         if (check)
-            for (int r = lane; r < nx; r += 64) r1 = fmax(r1, fabs((xo[r] - xn[r]) * ialpha - lxw[r]));
+            for (int r = lane; r < nx; r += 64) r1 = nmax(r1, fabs((xo[r] - xn[r]) * ialpha - lxw[r]));
     }
     if (check) {
         r1 = wave_max(r1);

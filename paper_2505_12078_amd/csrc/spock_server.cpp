@@ -147,6 +147,7 @@ void finish(spock_server* s, Flight& f, int32_t status, double t) {
         }
         r.info.s0 = s0;
         r.info.precision_used = T.p->cur;
+        r.info.t_setup_s = T.p->t_setup;
         T.has_iterate = true;
         T.p->solved = true;
     }
@@ -172,23 +173,31 @@ std::vector<SrvReq> admit(spock_server* s, std::vector<int64_t>& to_create, std:
         }
         if (!T.p) {
             if (used + T.footprint > s->budget) {
-                // evict idle resident trees, least recently used first
+                // evict idle resident trees, least recently used first; the
+                // victims are chosen first and evicted only if the tree then
+                // fits, so a request that cannot start destroys nothing
                 std::vector<SrvTree*> idle;
                 for (auto& kv : s->trees)
                     if (kv.second.p && !kv.second.busy &&
                         std::find(to_evict.begin(), to_evict.end(), kv.first) == to_evict.end())
                         idle.push_back(&kv.second);
                 std::sort(idle.begin(), idle.end(), [](SrvTree* a, SrvTree* b) { return a->last_used < b->last_used; });
+                std::vector<SrvTree*> victims;
+                size_t freed = 0;
                 for (SrvTree* v : idle) {
-                    if (used + T.footprint <= s->budget) break;
+                    if (used - freed + T.footprint <= s->budget) break;
+                    victims.push_back(v);
+                    freed += v->footprint;
+                }
+                if (used - freed + T.footprint > s->budget) {
+                    ++it;
+                    continue;
+                }
+                for (SrvTree* v : victims) {
                     to_evict.push_back(v->id);
                     v->busy = true;  // nobody touches it until it is gone
-                    used -= v->footprint;
                 }
-            }
-            if (used + T.footprint > s->budget) {
-                ++it;
-                continue;
+                used -= freed;
             }
             used += T.footprint;
             to_create.push_back(T.id);
@@ -224,7 +233,7 @@ int32_t start_flight(spock_server* s, SrvReq& rq) {
     if (taken) {
         f.m.x1 = a1;
         f.m.x2 = a2;
-        f.m.rel = std::max(a1, a2) / std::max(1.0, std::max(a1, a2));
+        f.m.rel = rel_of(a1, a2, std::max(1.0, std::max(a1, a2)));
     }
     f.m.live = f.m.iters < s->set.max_iters;
     f.phase = prec == SPOCK_FP64 ? 1 : 0;
@@ -305,7 +314,7 @@ int32_t tick(spock_server* s) {
             f.m.iters += 1;
             f.m.x1 = a1;
             f.m.x2 = a2;
-            f.m.rel = std::max(a1, a2) / std::max(1.0, std::max(p->xi_ref[0], p->xi_ref[1]));
+            f.m.rel = rel_of(a1, a2, std::max(1.0, std::max(p->xi_ref[0], p->xi_ref[1])));
             if (f.m.rel <= s->set.eps) {
                 f.m.status = SPOCK_OK;
             } else if (f.m.iters < s->set.max_iters) {

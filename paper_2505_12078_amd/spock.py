@@ -44,7 +44,7 @@ class Settings(C.Structure):
 class Info(C.Structure):
     _fields_ = [("iters", C.c_int64), ("iters_fp32", C.c_int64), ("rel_res", C.c_double),
                 ("xi1_inf", C.c_double), ("xi2_inf", C.c_double), ("s0", C.c_double),
-                ("t_solve_s", C.c_double), ("status", C.c_int32), ("precision_used", C.c_int32),
+                ("t_setup_s", C.c_double), ("t_solve_s", C.c_double), ("status", C.c_int32), ("precision_used", C.c_int32),
                 ("refined", C.c_int32)]
 
     def as_dict(self):
@@ -97,6 +97,8 @@ SIGNATURES = {
     "spock_set_x0": (C.c_int32, [C.c_void_p, _dp]),
     "spock_apply_T": (C.c_int32, [C.c_void_p, _dp, _dp, _dp, _dp, C.c_int32, _dp]),
     "spock_apply_L": (C.c_int32, [C.c_void_p, _dp, _dp, C.c_int32]),
+    "spock_project_S1": (C.c_int32, [C.c_void_p, _dp, _dp, _dp, _dp, C.c_int32]),
+    "spock_project_S2": (C.c_int32, [C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int32]),
     "spock_apply_Lt": (C.c_int32, [C.c_void_p, _dp, _dp, C.c_int32]),
     "spock_prox_gconj": (C.c_int32, [C.c_void_p, _dp, _dp, C.c_int32]),
     "spock_time_steps": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, _dp, _dp, _dp]),
@@ -292,6 +294,24 @@ class Problem:
         zo, eo, xi = np.zeros(self.nz), np.zeros(self.neta), np.zeros(2)
         _check(load().spock_apply_T(self.h, _ptr(z), _ptr(eta), _ptr(zo), _ptr(eo), precision, _ptr(xi)))
         return zo, eo, xi
+
+    def project_S1(self, xbar, ubar, precision=FP64):
+        xbar = np.ascontiguousarray(xbar, dtype=np.float64).reshape(self.n, self.nx)
+        ubar = np.ascontiguousarray(ubar, dtype=np.float64).reshape(self.n_nl, self.nu)
+        x, u = np.zeros((self.n, self.nx)), np.zeros((self.n_nl, self.nu))
+        _check(load().spock_project_S1(self.h, _ptr(xbar), _ptr(ubar), _ptr(x), _ptr(u), precision))
+        return x, u
+
+    def project_S2(self, y, tau, s, precision=FP64):
+        y, tau, s = (np.ascontiguousarray(a, dtype=np.float64) for a in (y, tau, s))
+        if tau.size != self.n - 1 or s.size != self.n - 1:
+            raise ValueError("tau and s have one entry per node 1..n-1")
+        if y.size != self.nz - 1 - self.n * self.nx - self.n_nl * self.nu - 2 * (self.n - 1):
+            raise ValueError("y must hold 2 n_ch(i) + 1 entries per non-leaf node i")
+        yo, to, so = np.zeros_like(y), np.zeros_like(tau), np.zeros_like(s)
+        _check(load().spock_project_S2(self.h, _ptr(y), _ptr(tau), _ptr(s), _ptr(yo), _ptr(to), _ptr(so),
+                                       precision))
+        return yo, to, so
 
     def apply_L(self, z, precision=FP64):
         z = np.ascontiguousarray(z, dtype=np.float64)

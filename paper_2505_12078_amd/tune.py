@@ -1,12 +1,13 @@
-"""Autotuner for the sweep kernels' workgroup size.
+"""Autotuner for the launch shape of the node-parallel kernels.
 
-A CP step's two launches run one workgroup per leaf task; the workgroup size
-trades threads per node (latency of one node's matrix products, number of
-barriers) against workgroups resident per CU.  The best size depends on nx,
-nu, the branching profile and the precision, so it is measured: every
-candidate runs a few steps on the actual problem (or batch) and the fastest
-is kept, with a JSON cache keyed by GPU architecture, precision, nx, nu and
-the tree profile.
+Two of a CP step's four launches (prep and dual) run one wavefront per tree
+node, 1-8 nodes per workgroup (64-512 threads).  The workgroup size trades
+the per-problem constants staged once per workgroup against workgroups
+resident per CU (LDS and registers); the sweeps always run one wavefront per
+workgroup.  The best size depends on nx, nu, the branching profile and the
+precision, so it is measured: every candidate runs a few steps on the actual
+problem (or batch) and the fastest is kept, with a JSON cache keyed by GPU
+architecture, precision, nx, nu and the tree profile.
 """
 from __future__ import annotations
 

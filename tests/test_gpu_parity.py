@@ -300,3 +300,80 @@ def test_run_to_run_bitwise_deterministic():
             P.solve(prob["x0"])
             out.append(P.get_iterate())
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("name", ["cfg0", "cfg1", "ragged_a", "ragged_affine", "wide", "very_wide", "big_nx",
+                                  "deep_branched"])
+def test_project_S1_S2_hooks_match_oracle(name):
+    """spock_project_S1 (Alg. 2 through the sweep kernels) against the oracle's
+    Alg. 2 with P, and spock_project_S2 against the oracle's dense
+    w - G^T (G G^T)^-1 G w, node by node, float64 at 1e-12 of the input scale
+    and float32 at 2e-4."""
+    prob, D, alpha, P = _pair(name)
+    F = O.Offline(D)
+    T, Y = D.tree, D.layout
+    rng = np.random.default_rng(31)
+    with P:
+        xbar = rng.standard_normal((T.n, D.nx)) * 3
+        ubar = rng.standard_normal((T.n_nl, D.nu)) * 3
+        xo, uo = O.project_S1(D, F, xbar, ubar)
+        scale = max(3.0, np.abs(xo).max(), np.abs(uo).max())
+        xg, ug = P.project_S1(xbar, ubar)
+        assert _rel(xg, xo, scale) < 1e-12 and _rel(ug, uo, scale) < 1e-12, (_rel(xg, xo, scale),
+                                                                              _rel(ug, uo, scale))
+        xf, uf = P.project_S1(xbar, ubar, S.FP32)
+        assert _rel(xf, xo, scale) < 2e-4 and _rel(uf, uo, scale) < 2e-4
+        ny = Y.yoff[-1]
+        y = rng.standard_normal(ny) * 3
+        tau = rng.standard_normal(T.n - 1) * 3
+        s = rng.standard_normal(T.n - 1) * 3
+        yg, tg, sg = P.project_S2(y, tau, s)
+        yf, tf, sf = P.project_S2(y, tau, s, S.FP32)
+        for i in T.nonleaf:
+            kids = T.ch[i]
+            w = np.concatenate([y[Y.yoff[i]:Y.yoff[i + 1]], tau[np.asarray(kids) - 1], s[np.asarray(kids) - 1]])
+            pw = O.project_S2_block(w, D.gamma[i], len(kids))
+            m = 2 * len(kids) + 1
+            got = np.concatenate([yg[Y.yoff[i]:Y.yoff[i + 1]], tg[np.asarray(kids) - 1], sg[np.asarray(kids) - 1]])
+            gotf = np.concatenate([yf[Y.yoff[i]:Y.yoff[i + 1]], tf[np.asarray(kids) - 1], sf[np.asarray(kids) - 1]])
+            assert got.size == pw.size and m + 2 * len(kids) == pw.size
+            assert _rel(got, pw, 3.0) < 1e-12, (i, _rel(got, pw, 3.0))
+            assert _rel(gotf, pw, 3.0) < 2e-4
+
+
+@pytest.mark.parametrize("precision", [S.FP64, S.FP32])
+def test_nonfinite_iterate_gives_nonfinite_residual(precision):
+    """A NaN anywhere in the iterate reaches the residual maxima of Sec. 5.3
+    (a plain max would drop it and report a converged solve)."""
+    prob, D, alpha, P = _pair("ragged_a")
+    rng = np.random.default_rng(41)
+    with P:
+        for where in ("z_x", "eta"):
+            z, e = _random_v(P, rng)
+            if where == "z_x":
+                z[1 + 3 * D.nx + 1] = np.nan
+            else:
+                e[P.neta // 2] = np.nan
+            _, _, xi = P.apply_T(z, e, precision)
+            assert not np.all(np.isfinite(xi)), (where, xi)
+
+
+@pytest.mark.parametrize("precision", [S.FP64, S.MIXED])
+def test_nonfinite_iterate_solve_reports_diverged(precision):
+    prob = CASES["ragged_a"]
+    with S.Problem(prob, S.default_settings(eps=1e-4, precision=precision)) as P:
+        r = P.solve(prob["x0"])
+        assert r["code"] == S.SPOCK_OK
+        z, e = P.get_iterate()
+        z[5] = np.nan
+        P.set_iterate(z, e)
+        r = P.solve(prob["x0"], warm_start=True)
+        assert r["code"] == S.SPOCK_E_DIVERGED, r
+        assert not np.isfinite(r["rel_res"])
+
+
+def test_setup_time_reported():
+    prob = CASES["cfg1"]
+    with S.Problem(prob, S.default_settings(max_iters=40)) as P:
+        r = P.solve(prob["x0"])
+        assert 0 < r["t_setup_s"] < 60 and r["t_solve_s"] > 0

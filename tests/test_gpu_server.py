@@ -90,3 +90,35 @@ def test_infeasible_request_reports_and_others_continue():
         res = {r["req_id"]: r for r in srv.poll()}
     assert res[1]["status"] == S.SPOCK_E_INFEASIBLE_X0
     assert res[2]["status"] == S.SPOCK_OK and res[3]["status"] == S.SPOCK_OK
+
+
+def test_request_that_cannot_fit_evicts_nothing():
+    """A tree that does not fit next to a busy one waits; the idle resident
+    tree it would have displaced stays resident and warm (its next request
+    warm-starts and equals the same sequence solved alone)."""
+    a, b, c = W.config_problem(0), W.config_problem(1), W.batch_problem(11)
+    fa, fb, fc = (S.footprint(p) for p in (a, b, c))
+    budget = fa + fb + (64 << 10)
+    assert fc <= budget and fb + fc > budget  # c fits alone, never next to b
+    settings = S.default_settings(eps=1e-4, max_iters=20000)
+    with S.Server(hbm_budget=budget, settings=settings) as srv:
+        ia, ib, ic = srv.add_tree(a), srv.add_tree(b), srv.add_tree(c)
+        srv.submit(ia, a["x0"], 0)
+        srv.wait_idle(600)
+        first = srv.poll()
+        assert len(first) == 1 and first[0]["warm"] == 0
+        srv.submit(ib, b["x0"], 1)   # b is set up and runs for a while
+        srv.submit(ic, c["x0"], 2)   # c cannot fit while b is busy
+        srv.submit(ia, a["x0"] * 0.9, 3)
+        srv.wait_idle(600)
+        res = {r["req_id"]: r for r in srv.poll()}
+        st = srv.stats()
+    assert sorted(res) == [1, 2, 3]
+    assert res[3]["warm"] == 1, res[3]
+    assert res[2]["status"] in (S.SPOCK_OK, S.SPOCK_E_NOT_CONVERGED)
+    assert st["resident_bytes"] <= budget
+    with S.Problem(a, settings) as P:
+        r0 = P.solve(a["x0"])
+        r1 = P.solve(a["x0"] * 0.9, warm_start=True)
+    assert first[0]["info"]["iters"] == r0["iters"] and first[0]["info"]["s0"] == r0["s0"]
+    assert res[3]["info"]["iters"] == r1["iters"] and res[3]["info"]["s0"] == r1["s0"]
