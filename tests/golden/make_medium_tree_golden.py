@@ -7,7 +7,7 @@ solved by plain CP iterations (Sec. 4.1) from zero to the relative residual
 few iteration counts K on that trajectory, s0 and every 97th entry of z and
 eta (with the indices), so a GPU run of exactly K steps from zero can be
 compared entry by entry; and at the stopping iteration the iteration count,
-rel_res and V* = s0.
+rel_res, V* = s0 and the nested risk objective of the unscaled (x, u) there.
 
 Only `oracle/` does arithmetic here; `paper_2505_12078_amd.workloads` only
 draws the seeded inputs.  Run from the repository root:
@@ -69,6 +69,9 @@ def main(out=os.path.join(ROOT, "tests", "golden", "medium_tree_cp.json")):
             print("step %d rel_res %.3e (%.0f s)" % (k, rel, time.time() - t0), flush=True)
         if rel <= EPS or k >= 200000:
             break
+    x = np.array([Y.x(z, i) for i in range(D.tree.n)])
+    u = np.array([Y.u(z, i) for i in range(D.tree.n_nl)])
+    xs, us = D.unscale(x, u)
     doc = {
         "_about": "FP64 oracle trajectory of plain CP from zero on the medium tree "
                   "(config_problem(1)); written by tests/golden/make_medium_tree_golden.py, "
@@ -76,7 +79,9 @@ def main(out=os.path.join(ROOT, "tests", "golden", "medium_tree_cp.json")):
         "cite": "CP operator T (Sec. 4.1), residuals and relative residual (Sec. 5.3)",
         "alpha": a, "L_norm": float(O.L_norm(D)), "xi_ref": ref, "eps": EPS,
         "nz": int(Y.nz), "neta": int(Y.neta),
-        "stop": {"iters": k, "rel_res": rel, "xi1": r1, "xi2": r2, "s0": float(z[0])},
+        "stop": {"iters": k, "rel_res": rel, "xi1": r1, "xi2": r2, "s0": float(z[0]),
+                 "nested_cost": O.nested_cost(prob, xs, us),
+                 "dynamics_violation": O.dynamics_violation(prob, xs, us)},
         "snapshots": snaps,
         "final": snapshot(k, z, eta),
         "oracle_seconds": time.time() - t0,

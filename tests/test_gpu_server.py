@@ -44,6 +44,22 @@ def test_mix_equals_alone(precision, eps):
         st = srv.stats()
     assert len(res) == 12 and st["completed"] == 12 and st["evicted"] == 0
     assert sum(r["status"] == S.SPOCK_OK for r in res) >= 9
+    # the tiny tree's served results against the oracle's V* at each x0 (plain
+    # CP to rel_res 1e-10, tests/golden/tiny_tree_vstar.json); an iterate at
+    # rel_res eps lies within 10 eps of V* (the oracle's own: 3.3e-4 at 1e-4)
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tiny_tree_vstar.json")) as f:
+        vstar = [g["vstar"] for g in json.load(f)["tiny"]]
+    tiny = [r for r in res if r["tree_id"] == ids[0]]
+    for i, r in enumerate(tiny):
+        assert r["status"] == S.SPOCK_OK
+        print("served tiny tree request %d: s0 %.10g, oracle V* %.10g, rel diff %.2e" % (
+            i, r["info"]["s0"], vstar[i], abs(r["info"]["s0"] - vstar[i]) / max(1.0, abs(vstar[i]))))
+        assert abs(r["info"]["s0"] - vstar[i]) <= 10 * eps * max(1.0, abs(vstar[i]))
+    for r in res:
+        print("tree %d request %d: status %d iters %d rel_res %.3e" % (r["tree_id"], r["req_id"], r["status"],
+                                                                       r["info"]["iters"], r["info"]["rel_res"]))
     for t, p in enumerate(trees):
         mine = [r for r in res if r["tree_id"] == ids[t]]
         with S.Problem(p, S.default_settings(eps=eps, max_iters=80000, precision=precision)) as P:
