@@ -54,6 +54,10 @@ extern "C" {
 #define SPOCK_E_CAPACITY (-6)        /* a request larger than the whole budget */
 #define SPOCK_E_NOMEM (-7)           /* workspace too small / allocation failed */
 
+/* outer method */
+#define SPOCK_CP 0         /* plain Chambolle-Pock iterations v <- T(v) (Sec. 4.1) */
+#define SPOCK_SUPERMANN 1  /* SuperMann over T with Anderson directions (Sec. 5.2) */
+
 /* precision of the iteration */
 #define SPOCK_FP64 0   /* every step in float64 */
 #define SPOCK_MIXED 1  /* float32 steps; float64 final check and refinement */
@@ -97,12 +101,19 @@ typedef struct spock_settings {
     int32_t precondition;  /* 1 = diagonal scaling of Sec. 5.4 (default), 0 = off */
     int32_t check_every;   /* steps between residual checks, even (default 20) */
     int32_t use_graph;     /* 1 = replay check_every steps as one hipGraph (default) */
+    int32_t method;        /* SPOCK_CP (default) or SPOCK_SUPERMANN; fixed at create time.
+                              SuperMann runs float64 iterations (precision SPOCK_FP64), checks
+                              the residuals at every iteration, and is available to
+                              spock_solve only (not to the batched and served forms) */
+    int32_t aa_memory;     /* Anderson memory m of SuperMann, 1..8 (default 3) */
 } spock_settings;
 
 /*
  * Per-solve report.  rel_res = max(|xi1|_inf, |xi2|_inf) / max(1, |xi1_ref|_inf,
  * |xi2_ref|_inf) with the residuals xi1, xi2 of Sec. 5.3 and the reference
- * residuals of the first CP step from zero (kept with the handle).
+ * residuals of the first CP step from zero (kept with the handle).  With
+ * SPOCK_SUPERMANN, iters counts SuperMann iterations and the residuals are
+ * those of the CP step from the returned iterate.
  */
 typedef struct spock_info {
     int64_t iters;          /* CP steps taken in this solve */
@@ -115,6 +126,8 @@ typedef struct spock_info {
     int32_t status;         /* the same code the call returned */
     int32_t precision_used; /* precision of the final accepted step */
     int32_t refined;        /* 1 if float64 steps had to follow float32 ones */
+    int64_t n_T;            /* applications of T (plain CP: iters) */
+    int64_t n_K0, n_K1, n_K2;  /* SuperMann: educated, safeguarded and generalized-KM steps */
 } spock_info;
 
 typedef struct spock_sizes {

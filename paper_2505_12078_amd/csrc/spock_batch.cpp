@@ -162,6 +162,7 @@ extern "C" {
 int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_settings* s, spock_batch** out) {
     if (!out || !probs || n < 1 || !s) return fail(SPOCK_E_INVALID, "bad batch arguments");
     *out = nullptr;
+    if (s->method != SPOCK_CP) return fail(SPOCK_E_INVALID, "the batched form runs plain CP iterations");
     if (s->check_every < 2 || (s->check_every & 1) || !(s->eps > 0) || s->max_iters < 1 ||
         s->precision < SPOCK_FP64 || s->precision > SPOCK_FP32)
         return fail(SPOCK_E_INVALID, "bad batch settings");

@@ -225,4 +225,23 @@ __host__ __device__ inline int stage_elems(int nx, int nu, int V, int rb, int rf
     return 4 * kVecSlot + imax(gb, gf) * 64 * V;
 }
 
+// Vector algebra of the SuperMann iteration (float64, iterate-sized vectors).
+// out = sum_i c[i] in[i] entrywise; an input may be the output itself.
+constexpr int kMaxCombo = 17;  // 2 m + 1 inputs for the Anderson direction, m <= 8
+struct VecCombo {
+    const double* in[kMaxCombo];
+    double c[kMaxCombo];
+    int n_in;
+};
+// A batch of dot products sum_k a[j][k] b[j][k], k < n[j], reduced in a fixed
+// order (kDotBlocks block partials, then one wavefront).
+constexpr int kMaxDots = 20;  // 2 m + 2 for the Anderson update, m <= 8
+constexpr int kDotBlocks = 512;
+struct DotSet {
+    const double* a[kMaxDots];
+    const double* b[kMaxDots];
+    long long n[kMaxDots];
+    int count;
+};
+
 }  // namespace spk

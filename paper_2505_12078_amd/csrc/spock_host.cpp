@@ -170,9 +170,11 @@ static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
     h.prob = a.take<real>(n);
     h.gamma = a.take<real>(nl);
     h.x0 = a.take<real>(nx);
+    // z and eta of one copy are one vector [z | zero pad | eta] (the
+    // SuperMann iteration combines whole iterates)
     for (int k = 0; k < 2; ++k) {
-        h.z[k] = a.take<real>(p->nz);
-        h.eta[k] = a.take<real>(p->neta);
+        h.z[k] = a.take<real>(p->nzp + p->neta);
+        h.eta[k] = h.z[k] + p->nzp;
     }
     h.d = a.take<real>((long long)nl * nu);
     h.e = a.take<real>((long long)n * m);
@@ -197,6 +199,26 @@ static void carve(Arena& a, spock_problem* p) {
     p->d_stash_e = a.take<double>(nv);
     carve_set(a, p, p->s64);
     carve_set(a, p, p->s32);
+    if (p->set.method == SPOCK_SUPERMANN) {
+        // float64 vectors of the SuperMann iteration, each [z | pad | eta]
+        SmWork& w = p->sm;
+        const long long nv = p->nzp + p->neta;
+        for (auto& r : w.R) r = a.take<double>(nv);
+        w.PSI = a.take<double>(nv);
+        w.VT = a.take<double>(nv);
+        w.TVT = a.take<double>(nv);
+        w.RT = a.take<double>(nv);
+        for (int j = 0; j < p->set.aa_memory; ++j) {
+            w.Y[j] = a.take<double>(nv);
+            w.S[j] = a.take<double>(nv);
+        }
+        w.LR = a.take<double>(p->neta);
+        w.LPSI = a.take<double>(p->neta);
+        w.LRT = a.take<double>(p->neta);
+        w.partial = a.take<double>((long long)spk::kMaxDots * spk::kDotBlocks);
+        w.dots = a.take<double>(spk::kMaxDots);
+        w.d_trial = a.take<ProbDev<double>>(1);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -289,6 +311,7 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     p->z_tau = o; o += n - 1;
     p->z_s = o; o += n - 1;
     p->nz = o;
+    p->nzp = (o + 63) & ~63LL;
     o = 0;
     p->e_y = o; o += p->ny;
     p->e_s = o; o += nl;
@@ -665,12 +688,32 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     HIP_TRY(put<real>(h.hiN, p->hiN, st));
     HIP_TRY(put<real>(h.prob, p->prob, st));
     HIP_TRY(put<real>(h.gamma, p->gamma, st));
-    for (int k = 0; k < 2; ++k) {
-        HIP_TRY(spk::launch_fill<real>(h.z[k], real(0), p->nz, st));
-        HIP_TRY(spk::launch_fill<real>(h.eta[k], real(0), p->neta, st));
-    }
+    for (int k = 0; k < 2; ++k) HIP_TRY(spk::launch_fill<real>(h.z[k], real(0), p->nzp + p->neta, st));
     HIP_TRY(hipMemcpyAsync(s.d, &h, sizeof(h), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return SPOCK_OK;
+}
+
+// The SuperMann vectors start at zero (their z-to-eta pads stay zero), and the
+// trial descriptor is the float64 one reading VT and writing TVT.
+static int32_t upload_supermann(spock_problem* p) {
+    SmWork& w = p->sm;
+    const long long nv = p->nzp + p->neta;
+    hipStream_t st = p->stream;
+    for (double* v : {w.R[0], w.R[1], w.PSI, w.VT, w.TVT, w.RT}) HIP_TRY(spk::launch_fill<double>(v, 0.0, nv, st));
+    for (int j = 0; j < p->set.aa_memory; ++j) {
+        HIP_TRY(spk::launch_fill<double>(w.Y[j], 0.0, nv, st));
+        HIP_TRY(spk::launch_fill<double>(w.S[j], 0.0, nv, st));
+    }
+    ProbDev<double> h = p->s64.h;
+    h.z[0] = w.VT;
+    h.eta[0] = w.VT + p->nzp;
+    h.z[1] = w.TVT;
+    h.eta[1] = w.TVT + p->nzp;
+    HIP_TRY(hipMemcpyAsync(w.d_trial, &h, sizeof(h), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hipHostMalloc((void**)&w.h_dots, (spk::kMaxDots + 4) * sizeof(double), 0) != hipSuccess)
+        return fail(SPOCK_E_HIP, "hipHostMalloc failed");
     return SPOCK_OK;
 }
 
@@ -907,6 +950,8 @@ int32_t spock_default_settings(spock_settings* s) {
     s->precondition = 1;
     s->check_every = 20;
     s->use_graph = 1;
+    s->method = SPOCK_CP;
+    s->aa_memory = 3;
     return SPOCK_OK;
 }
 
@@ -917,6 +962,11 @@ static int32_t check_settings(const spock_settings* s) {
     if (s->max_iters < 1) return fail(SPOCK_E_INVALID, "max_iters must be >= 1");
     if (s->precision < SPOCK_FP64 || s->precision > SPOCK_FP32) return fail(SPOCK_E_INVALID, "bad precision");
     if (s->check_every < 2 || (s->check_every & 1)) return fail(SPOCK_E_INVALID, "check_every must be even and >= 2");
+    if (s->method != SPOCK_CP && s->method != SPOCK_SUPERMANN) return fail(SPOCK_E_INVALID, "bad method");
+    if (s->method == SPOCK_SUPERMANN) {
+        if (s->aa_memory < 1 || s->aa_memory > 8) return fail(SPOCK_E_INVALID, "aa_memory must be in 1..8");
+        if (s->precision != SPOCK_FP64) return fail(SPOCK_E_INVALID, "SuperMann runs float64 iterations only");
+    }
     return SPOCK_OK;
 }
 
@@ -925,6 +975,7 @@ int32_t spock_problem_footprint(const spock_problem_desc* desc, const spock_sett
     int32_t r = check_settings(s);
     if (r) return r;
     spock_problem tmp;
+    tmp.set = *s;
     r = validate_and_layout(desc, &tmp);
     if (r) return r;
     Arena a(nullptr);
@@ -961,6 +1012,10 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
         carve(dry, p);
         p->bytes = dry.off + 256;
         std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
+        if (hipGetDevice(&p->device) != hipSuccess) {
+            delete p;
+            return fail(SPOCK_E_HIP, "hipGetDevice failed");
+        }
         if (ws) {
             if (ws_bytes < p->bytes) {
                 delete p;
@@ -1036,6 +1091,7 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
         }
         r = upload_set<double>(p, p->s64, M, KR, cs, Pc);
         if (!r) r = upload_set<float>(p, p->s32, M, KR, cs, Pc);
+        if (!r && p->set.method == SPOCK_SUPERMANN) r = upload_supermann(p);
         if (r) {
             spock_problem_destroy(p);
             return r;
@@ -1059,6 +1115,7 @@ int32_t spock_problem_destroy(spock_problem* p) {
     for (auto* s : {&p->s64.graph[0], &p->s64.graph[1], &p->s32.graph[0], &p->s32.graph[1]})
         if (*s) (void)hipGraphExecDestroy(*s);
     if (p->h_res) (void)hipHostFree(p->h_res);
+    if (p->sm.h_dots) (void)hipHostFree(p->sm.h_dots);
     if (p->owns && p->base) (void)hipFree(p->base);
     if (p->owns_stream && p->stream) (void)hipStreamDestroy(p->stream);
     delete p;
@@ -1091,6 +1148,9 @@ int32_t spock_set_settings(spock_problem* p, const spock_settings* s) {
     if (s->alpha != p->set.alpha && s->alpha > 0 && s->alpha != p->alpha)
         return fail(SPOCK_E_INVALID, "alpha is fixed at create time");
     if (s->precondition != p->set.precondition) return fail(SPOCK_E_INVALID, "precondition is fixed at create time");
+    if (s->method != p->set.method) return fail(SPOCK_E_INVALID, "method is fixed at create time");
+    if (s->method == SPOCK_SUPERMANN && s->aa_memory != p->set.aa_memory)
+        return fail(SPOCK_E_INVALID, "aa_memory is fixed at create time");
     p->set = *s;
     return SPOCK_OK;
 }
@@ -1139,12 +1199,55 @@ static int32_t iterate(spock_problem* p, long long budget, long long* taken, dou
 }  // extern "C++"
 
 
+// SuperMann solve (Sec. 5.2): float64 iterate in copy 0 with its CP step
+// taken, reference residuals of the first CP step from zero, then the
+// accelerated iteration.
+static int32_t supermann_solve(spock_problem* p, int32_t warm, spock_info* info, double t0) {
+    spock_info inf{};
+    int32_t r = SPOCK_OK;
+    if (!warm) {
+        r = zero_iterate(p);
+        if (r) return r;
+    } else {
+        r = move_iterate(p, SPOCK_FP64);
+        if (!r) r = normalize_parity(p);
+        if (r) return r;
+    }
+    if (!p->have_ref || !warm) {
+        long long taken = 0;
+        double x1, x2;
+        r = ensure_ref(p, warm != 0, &taken, &x1, &x2);
+        if (r) return r;
+        // a cold start keeps the reference step: copy 1 holds T(0)
+        if (!taken) r = step<double>(p, 1);
+    } else {
+        r = step<double>(p, 1);
+    }
+    if (r) return r;
+    p->s64.par = 0;  // the SuperMann loop reads v in copy 0 and T(v) in copy 1
+    r = supermann_iterate(p, p->set.max_iters, &inf);
+    if (r != SPOCK_OK && r != SPOCK_E_NOT_CONVERGED && r != SPOCK_E_DIVERGED) return r;
+    p->solved = true;
+    double s0 = 0;
+    HIP_TRY(hipMemcpyAsync(&s0, p->s64.h.z[0], 8, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    inf.s0 = s0;
+    inf.precision_used = SPOCK_FP64;
+    inf.t_setup_s = p->t_setup;
+    inf.t_solve_s = now_s() - t0;
+    if (info) *info = inf;
+    if (r == SPOCK_E_NOT_CONVERGED) return fail(r, "max_iters reached before the tolerance");
+    if (r == SPOCK_E_DIVERGED) return fail(r, "non-finite residual");
+    return SPOCK_OK;
+}
+
 int32_t spock_solve(spock_problem* p, const double* x0, int32_t warm, spock_info* info) {
     if (!p) return fail(SPOCK_E_INVALID, "null handle");
     const double t0 = now_s();
     spock_info inf{};
     int32_t r = set_x0_device(p, x0, true);
     if (r) return r;
+    if (p->set.method == SPOCK_SUPERMANN) return supermann_solve(p, warm, info, t0);
     long long it = 0, it32 = 0;
     double rel = INFINITY, x1 = INFINITY, x2 = INFINITY;
     const int prec = p->set.precision;
@@ -1219,6 +1322,7 @@ int32_t spock_solve(spock_problem* p, const double* x0, int32_t warm, spock_info
     p->solved = true;
     inf.iters = it;
     inf.iters_fp32 = it32;
+    inf.n_T = it;
     inf.rel_res = rel;
     inf.xi1_inf = x1;
     inf.xi2_inf = x2;

@@ -30,6 +30,8 @@ template <typename D, typename S>
 hipError_t launch_convert(D*, const S*, long long, hipStream_t);
 template <typename T>
 hipError_t launch_fill(T*, T, long long, hipStream_t);
+hipError_t launch_combo(double* out, const VecCombo& cb, long long n, hipStream_t);
+hipError_t launch_dots(const DotSet& ds, double* partial, double* out, hipStream_t);
 }  // namespace spk
 
 
@@ -69,11 +71,31 @@ struct DevSet {
     int graph_steps = 0;
 };
 
+// Device vectors of the SuperMann iteration (float64, [z | pad | eta] each
+// unless noted), carved from the handle's workspace when the method is
+// SuperMann.
+struct SmWork {
+    double* R[2] = {nullptr, nullptr};  // residual v - T(v): current and previous
+    double* PSI = nullptr;              // Anderson direction
+    double* VT = nullptr;               // line-search trial v + tau psi
+    double* TVT = nullptr;              // T(trial)
+    double* RT = nullptr;               // trial residual
+    double* Y[8] = {};                  // residual differences (ring of aa_memory)
+    double* S[8] = {};                  // iterate differences (ring)
+    double* LR = nullptr;               // L r_z, L psi_z, L rt_z (eta-sized)
+    double* LPSI = nullptr;
+    double* LRT = nullptr;
+    double* partial = nullptr;          // dot-product block partials
+    double* dots = nullptr;             // dot-product results
+    ProbDev<double>* d_trial = nullptr; // float64 descriptor reading VT, writing TVT
+    double* h_dots = nullptr;           // pinned readback of dots and residual slots
+};
+
 struct spock_problem {
     // sizes
     int n = 0, n_nl = 0, n_leaf = 0, N = 0, nx = 0, nu = 0, m = 0, nc = 0, ncN = 0, max_ch = 0;
     int has_ball = 0, has_ballN = 0, affine = 0;
-    long long ny = 0, nz = 0, neta = 0;
+    long long ny = 0, nz = 0, neta = 0, nzp = 0;  // nzp: nz rounded up to 64 entries
     long long z_x, z_u, z_y, z_tau, z_s, e_y, e_s, e_c, e_soc, e_cN, e_socN;
     long long M_stride = 0, KR_stride = 0;
     std::vector<int> parent, first_child, n_ch, y_off;
@@ -113,6 +135,8 @@ struct spock_problem {
     double xi_ref[2] = {0, 0};
     bool solved = false;
     double t_setup = 0;        // seconds spock_problem_create took
+    int device = 0;            // HIP device current at create
+    SmWork sm;                 // SuperMann vectors (method SPOCK_SUPERMANN)
 };
 
 template <typename real>
@@ -138,6 +162,9 @@ inline double rel_of(double x1, double x2, double scale) {
 }
 int32_t normalize_parity(spock_problem* p);
 int32_t ensure_ref(spock_problem* p, bool warm, long long* taken, double* x1, double* x2);
+// SuperMann iteration (spock_supermann.cpp) from the float64 iterate in copy
+// 0, whose CP step (copy 1, residual slots) has been taken; fills info.
+int32_t supermann_iterate(spock_problem* p, long long budget, spock_info* info);
 
 // Batched form (spock_batch.cpp).
 struct spock_batch {

@@ -1849,6 +1849,46 @@ __global__ void k_fill(T* __restrict__ dst, T val, long long n) {
         dst[k] = val;
 }
 // ---------------------------------------------------------------------------
+// vector algebra of the SuperMann iteration (float64)
+// ---------------------------------------------------------------------------
+
+// out = sum_i c_i in_i, inputs summed in index order; every entry is read
+// before it is written, so out may be one of the inputs.
+__global__ __launch_bounds__(256) void k_combo(double* out, VecCombo cb, long long n) {
+    for (long long k = blockIdx.x * 256LL + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
+        double s = 0.0;
+        for (int i = 0; i < cb.n_in; ++i) s += cb.c[i] * cb.in[i][k];
+        out[k] = s;
+    }
+}
+
+// Block partial sums of every dot product of the set; each block strides
+// over the whole vector with a fixed assignment, so the result does not
+// depend on timing.
+__global__ __launch_bounds__(256) void k_dots(DotSet ds, double* partial) {
+    __shared__ double red[4];
+    for (int j = 0; j < ds.count; ++j) {
+        const double* a = ds.a[j];
+        const double* b = ds.b[j];
+        double s = 0.0;
+        for (long long k = blockIdx.x * 256LL + threadIdx.x; k < ds.n[j]; k += (long long)gridDim.x * 256)
+            s += a[k] * b[k];
+        s = block_sum<256>(s, red);
+        if (threadIdx.x == 0) partial[j * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// One wavefront adds the block partials of each dot product in a fixed order.
+__global__ __launch_bounds__(64) void k_dots_final(const double* partial, int blocks, int count, double* out) {
+    for (int j = 0; j < count; ++j) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < blocks; b += 64) s += partial[j * blocks + b];
+        s = wave_sum(s);
+        if (threadIdx.x == 0) out[j] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers (host side)
 // ---------------------------------------------------------------------------
 
@@ -1942,6 +1982,23 @@ hipError_t launch_fill(T* dst, T val, long long n, hipStream_t st) {
     long long blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, st, dst, val, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_combo(double* out, const VecCombo& cb, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (cb.n_in < 1 || cb.n_in > kMaxCombo) return hipErrorInvalidValue;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_combo, dim3((unsigned)blocks), dim3(256), 0, st, out, cb, n);
+    return hipGetLastError();
+}
+
+// out[j] = <a_j, b_j> for the set; partial holds kMaxDots * kDotBlocks doubles.
+hipError_t launch_dots(const DotSet& ds, double* partial, double* out, hipStream_t st) {
+    if (ds.count < 1 || ds.count > kMaxDots) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dots, dim3(kDotBlocks), dim3(256), 0, st, ds, partial);
+    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(64), 0, st, (const double*)partial, kDotBlocks, ds.count, out);
     return hipGetLastError();
 }
 

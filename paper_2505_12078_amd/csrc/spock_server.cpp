@@ -455,6 +455,7 @@ extern "C" {
 
 int32_t spock_server_create(size_t budget, const spock_settings* set, spock_server** out) {
     if (!out || !set || budget == 0) return fail(SPOCK_E_INVALID, "bad server arguments");
+    if (set->method != SPOCK_CP) return fail(SPOCK_E_INVALID, "the served form runs plain CP iterations");
     if (set->check_every < 2 || (set->check_every & 1) || !(set->eps > 0) || set->max_iters < 1)
         return fail(SPOCK_E_INVALID, "bad server settings");
     spock_server* s = new spock_server();

@@ -22,6 +22,7 @@ SPOCK_E_HIP = -5
 SPOCK_E_CAPACITY = -6
 SPOCK_E_NOMEM = -7
 FP64, MIXED, FP32 = 0, 1, 2
+CP, SUPERMANN = 0, 1
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -38,14 +39,15 @@ class ProblemDesc(C.Structure):
 class Settings(C.Structure):
     _fields_ = [("alpha", C.c_double), ("eps", C.c_double), ("max_iters", C.c_int64),
                 ("precision", C.c_int32), ("precondition", C.c_int32), ("check_every", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("method", C.c_int32), ("aa_memory", C.c_int32)]
 
 
 class Info(C.Structure):
     _fields_ = [("iters", C.c_int64), ("iters_fp32", C.c_int64), ("rel_res", C.c_double),
                 ("xi1_inf", C.c_double), ("xi2_inf", C.c_double), ("s0", C.c_double),
                 ("t_setup_s", C.c_double), ("t_solve_s", C.c_double), ("status", C.c_int32), ("precision_used", C.c_int32),
-                ("refined", C.c_int32)]
+                ("refined", C.c_int32), ("n_T", C.c_int64), ("n_K0", C.c_int64), ("n_K1", C.c_int64),
+                ("n_K2", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -115,3 +115,13 @@ def test_degenerate_and_maximum_trees(lib):
     par, _ = W.tree_from_branching([1] * 512)
     long = W.make_problem(par, 2, 1, rng, name="chain512")
     assert "horizon" in _bad(long)
+
+
+def test_supermann_settings_are_validated(lib):
+    p = W.config_problem(0)
+    assert S.footprint(p, S.default_settings(method=S.SUPERMANN)) > S.footprint(p, S.default_settings())
+    for bad in (dict(method=S.SUPERMANN, precision=S.MIXED), dict(method=S.SUPERMANN, aa_memory=0),
+                dict(method=S.SUPERMANN, aa_memory=9), dict(method=7)):
+        with pytest.raises(S.SpockError) as e:
+            S.footprint(p, S.default_settings(**bad))
+        assert e.value.code == S.SPOCK_E_INVALID

@@ -1,0 +1,120 @@
+"""The SPOCK outer method on the GPU: SuperMann over T with Anderson
+directions (Sec. 5.2), float64, every vector operation in the library's
+kernels.  Its trajectory is not compared step by step with the oracle's (an
+acceptance test can go either way under rounding); the solutions are: the
+optimal value against the oracle's V*, the nested risk objective and the
+dynamics of the returned (x, u), at the tolerance of the solve."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import spock_oracle as O
+from oracle import supermann_oracle as SM
+from paper_2505_12078_amd import spock as S
+from paper_2505_12078_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need an MI355X; none is visible")
+    S.load()
+
+
+def _golden(name):
+    with open(os.path.join(HERE, "golden", name)) as f:
+        return json.load(f)
+
+
+def _sm(**kw):
+    return S.default_settings(method=S.SUPERMANN, **kw)
+
+
+def test_tiny_tree_supermann_matches_oracle():
+    eps = 1e-6
+    prob = W.config_problem(0)
+    vs = _golden("tiny_tree_vstar.json")["tiny"][0]["vstar"]
+    ref = SM.solve(prob, eps=eps, max_iters=20000)
+    with S.Problem(prob, _sm(eps=eps, max_iters=20000)) as P:
+        r = P.solve(prob["x0"])
+        x, u, s0 = P.solution()
+    print("tiny tree SuperMann: GPU %d it (%d T: K0 %d K1 %d K2 %d) s0 %.10g | oracle %d it (%s) s0 %.10g | V* %.10g"
+          % (r["iters"], r["n_T"], r["n_K0"], r["n_K1"], r["n_K2"], s0, ref["iters"], ref["counts"], ref["s0"], vs))
+    assert r["code"] == S.SPOCK_OK and r["rel_res"] <= eps
+    assert abs(s0 - vs) <= 10 * eps * max(1.0, abs(vs))
+    assert abs(s0 - ref["s0"]) <= 10 * eps * max(1.0, abs(vs))
+    assert O.nested_cost(prob, x, u) == pytest.approx(s0, rel=10 * eps)
+    assert O.dynamics_violation(prob, x, u) < 1e-10
+    # plain CP takes 3,641 applications of T to the same tolerance on the GPU
+    assert r["n_T"] < 3641
+    assert r["n_K0"] + r["n_K1"] + r["n_K2"] == r["iters"]
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_ragged_tree_supermann_invariants(seed):
+    eps = 1e-6
+    prob = W.random_ragged_problem(seed, N=4, nx=3, nu=2, max_children=3)
+    with S.Problem(prob, _sm(eps=eps, max_iters=50000)) as P:
+        r = P.solve(prob["x0"])
+        x, u, s0 = P.solution()
+    with S.Problem(prob, S.default_settings(eps=eps, max_iters=200000)) as P:
+        rp = P.solve(prob["x0"])
+    print("ragged %d: SuperMann %d it, %d T, s0 %.10g; plain CP %d T, s0 %.10g" % (
+        seed, r["iters"], r["n_T"], s0, rp["n_T"], rp["s0"]))
+    assert r["code"] == S.SPOCK_OK
+    assert O.nested_cost(prob, x, u) == pytest.approx(s0, rel=10 * eps)
+    assert O.dynamics_violation(prob, x, u) < 1e-10
+    if rp["code"] == S.SPOCK_OK:
+        assert abs(s0 - rp["s0"]) <= 10 * eps * max(1.0, abs(s0))
+
+
+def test_medium_tree_supermann_reaches_1e6():
+    """The medium tree at rel_res 1e-6 (plain CP: not within 3e5 steps)."""
+    eps = 1e-6
+    prob = W.config_problem(1)
+    with S.Problem(prob, _sm(eps=eps, max_iters=100000)) as P:
+        r = P.solve(prob["x0"])
+        x, u, s0 = P.solution()
+    print("medium tree SuperMann: %d it, %d T (K0 %d K1 %d K2 %d), %.2f s, rel_res %.3e, s0 %.12g" % (
+        r["iters"], r["n_T"], r["n_K0"], r["n_K1"], r["n_K2"], r["t_solve_s"], r["rel_res"], s0))
+    assert r["code"] == S.SPOCK_OK and r["rel_res"] <= eps
+    assert O.nested_cost(prob, x, u) == pytest.approx(s0, rel=10 * eps)
+    assert O.dynamics_violation(prob, x, u) < 1e-9
+    g = _golden("medium_tree_cp.json")["stop"]   # plain CP at 1e-4: within 10 x 1e-4 of V*
+    assert abs(s0 - g["s0"]) <= 10 * 1e-4 * abs(s0)
+    path = os.path.join(HERE, "golden", "medium_tree_supermann.json")
+    if os.path.exists(path):
+        gs = _golden("medium_tree_supermann.json")
+        print("  oracle SuperMann: %d it, %s, V* %.12g" % (gs["iters"], gs["counts"], gs["vstar"]))
+        assert abs(s0 - gs["vstar"]) <= 10 * eps * abs(gs["vstar"])
+
+
+def test_supermann_warm_start_and_nan():
+    prob = W.config_problem(0)
+    with S.Problem(prob, _sm(eps=1e-6)) as P:
+        a = P.solve(prob["x0"])
+        b = P.solve(prob["x0"], warm_start=True)
+        assert a["code"] == S.SPOCK_OK and b["code"] == S.SPOCK_OK
+        assert b["iters"] <= 1 and b["s0"] == pytest.approx(a["s0"], rel=1e-9)
+        z, e = P.get_iterate()
+        z[3] = np.nan
+        P.set_iterate(z, e)
+        c = P.solve(prob["x0"], warm_start=True)
+        assert c["code"] == S.SPOCK_E_DIVERGED
+
+
+def test_supermann_not_offered_to_batched_and_served_forms():
+    prob = W.config_problem(0)
+    with S.Problem(prob) as P:
+        with pytest.raises(S.SpockError) as e:
+            S.Batch([P], _sm())
+        assert e.value.code == S.SPOCK_E_INVALID
+    with pytest.raises(S.SpockError) as e:
+        S.Server(1 << 30, _sm())
+    assert e.value.code == S.SPOCK_E_INVALID
