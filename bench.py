@@ -63,16 +63,41 @@ def _measured_traffic(kernel, path=TRAFFIC_FILE):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(steps):
-    """The FP64 oracle (one thread) for `steps` CP steps of the same workload."""
+def _host_threads():
+    """Threads the host gives this job: the OMP setting when there is one
+    (the GPU machine sets it to its CPU share), else the visible CPUs."""
+    try:
+        return max(1, int(os.environ.get("OMP_NUM_THREADS", "")))
+    except ValueError:
+        return max(1, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count() or 1)
+
+
+def _cpu_run(steps, threads):
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
-        env[k] = "1"
+        env[k] = str(threads)
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-steps", str(steps)]
     r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=900)
     if r.returncode != 0:
         return {"error": r.stderr[-400:]}
     return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(steps):
+    """The FP64 oracle for `steps` CP steps of the same workload, with the BLAS
+    and OpenMP thread count set to every host thread the job has and to one."""
+    threads = _host_threads()
+    allc = _cpu_run(steps, threads)
+    one = _cpu_run(steps, 1) if threads > 1 else dict(allc)
+    if "error" in allc:
+        return allc
+    out = dict(allc)
+    out["cores"] = threads
+    out["sample"] = ("%d CP steps from zero on the same 7167-node tree, float64 NumPy, BLAS/OpenMP threads = %d "
+                     "(os.cpu_count() = %s); offline factorisation not timed" % (steps, threads, os.cpu_count()))
+    out["os_cpu_count"] = os.cpu_count()
+    out["one_thread"] = {"value": one.get("value"), "unit": "CP iters/s", "cores": 1}
+    return out
 
 
 def _cpu_baseline_only(steps):
@@ -89,9 +114,8 @@ def _cpu_baseline_only(steps):
     for _ in range(steps):
         z, e = O.cp_step(D, F, z, e, a)
     dt = time.perf_counter() - t0
-    print(json.dumps({"value": steps / dt, "unit": "CP iters/s", "cores": 1, "kind": "oracle",
-                      "sample": "%d CP steps from zero on the same 7167-node tree, float64 NumPy, "
-                                "one thread; offline factorisation not timed" % steps}))
+    print(json.dumps({"value": steps / dt, "unit": "CP iters/s", "kind": "oracle",
+                      "threads_env": os.environ.get("OMP_NUM_THREADS")}))
 
 
 def _batch_member(k):
@@ -116,7 +140,7 @@ def make_batch_inputs(n_problems, workers=None):
     return probs, time.perf_counter() - t, workers
 
 
-def batch_bench(S, probs, gen_s, workers, steps, warmup, solve=True, max_iters=20000):
+def batch_bench(S, probs, gen_s, workers, steps, warmup, solve=True, max_iters=20000, n_compare=64):
     """Batched form on the batched workload: every member advanced by the same
     four launches per step (float32 bulk), node workgroup picked by the
     autotuner on the batch itself; aggregate rates, per-launch roofline and the
@@ -173,19 +197,76 @@ def batch_bench(S, probs, gen_s, workers, steps, warmup, solve=True, max_iters=2
                               "iters_median": int(np.median(it)), "iters_max": int(it.max()),
                               "refined_in_f64": int(sum(bool(i["refined"]) for i in infos))}
         print("batch time-to-tol: %s" % out["time_to_tol"], file=sys.stderr, flush=True)
+        # mixed against plain float64 time-to-tolerance on the same members
+        sub = members[:n_compare]
+        cmp = {}
+        for name, prec in (("mixed", S.MIXED), ("fp64", S.FP64)):
+            Bs = S.Batch(sub, S.default_settings(eps=1e-4, precision=prec, check_every=20, max_iters=max_iters))
+            Bs.set_launch(wg, S.FP32)
+            Bs.set_launch(wg, S.FP64)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos = Bs.solve([p["x0"] for p in probs[:n_compare]])
+            dt = time.perf_counter() - t0
+            Bs.close()
+            cmp[name] = {"seconds": round(dt, 3), "converged": int(sum(i["status"] == S.SPOCK_OK for i in infos)),
+                         "iters_median": int(np.median([i["iters"] for i in infos])),
+                         "s0": [i["s0"] for i in infos], "ok": [i["status"] == S.SPOCK_OK for i in infos]}
+        s_m, s_d = np.array(cmp["mixed"].pop("s0")), np.array(cmp["fp64"].pop("s0"))
+        both = np.array(cmp["mixed"].pop("ok")) & np.array(cmp["fp64"].pop("ok"))
+        cmp["members"] = n_compare
+        cmp["converged_both"] = int(both.sum())
+        cmp["max_rel_s0_diff_converged"] = (float(np.max(np.abs(s_m - s_d)[both] / np.maximum(1.0, np.abs(s_d[both]))))
+                                            if both.any() else None)
+        cmp["speedup_mixed_vs_fp64"] = round(cmp["fp64"]["seconds"] / max(cmp["mixed"]["seconds"], 1e-9), 3)
+        out["time_to_tol_mixed_vs_fp64"] = cmp
+        print("batch mixed vs fp64 (%d members): %s" % (n_compare, cmp), file=sys.stderr, flush=True)
     B.close()
     for P in members:
         P.close()
     return out
 
 
+def small_trees_bench(S, W):
+    """Plain float64 CP on the tiny tree (15 nodes) and the medium tree (229
+    nodes): steps per second, microseconds per step and per stage level (a
+    step walks the N stages twice, backward and forward), and the time to the
+    tolerance the configurations state (tiny: rel_res 1e-6; medium: 1e-4,
+    which plain CP reaches in about 1.1e4 steps -- 1e-6 takes more than 3e5)."""
+    import torch
+    out = {}
+    for cfg, eps, name in ((0, 1e-6, "tiny"), (1, 1e-4, "medium")):
+        prob = W.config_problem(cfg)
+        with S.Problem(prob, S.default_settings(eps=eps, max_iters=400000)) as P:
+            P.set_x0(prob["x0"])
+            P.run_steps(200, S.FP64)
+            torch.cuda.synchronize()
+            steps = 4000
+            t0 = time.perf_counter()
+            P.run_steps(steps, S.FP64, sync=False)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            r = P.solve(prob["x0"])
+            N = P.sizes["N"]
+            out[name] = {"nodes": P.n, "N": N, "nx": P.nx, "nu": P.nu, "steps_per_s": round(1.0 / dt, 1),
+                         "us_per_step": round(dt * 1e6, 2), "us_per_stage_level": round(dt * 1e6 / (2 * N), 2),
+                         "time_to_tol": {"eps": eps, "seconds": round(r["t_solve_s"], 4), "iters": r["iters"],
+                                         "converged": r["code"] == S.SPOCK_OK, "s0": r["s0"]}}
+        print("%s tree: %s" % (name, out[name]), file=sys.stderr, flush=True)
+    return out
+
+
 def serve_bench(S, W, duration_s=10.0, session_rate=20.0, req_per_session=10, gap_mean=0.5,
-                drain_s=40.0, budget=200 << 30, seed=4):
+                drain_s=40.0, budget=200 << 30, seed=4, precision=None):
     """Poisson sessions (rate session_rate/s), each one tree drawn uniformly from
     {medium tree, large tree, a batched-workload tree} issuing req_per_session
     requests with exponential gaps (mean gap_mean s); request k+1 shifts x0 by
     N(0, 0.1) and re-applies the feasibility guard; warm starts from the
-    resident iterate; eps 1e-4, mixed precision.  Latency = submit -> result."""
+    resident iterate; eps 1e-4, mixed precision unless `precision` says
+    otherwise; admission within `budget` bytes of HBM.  Latency = submit ->
+    result.  Requests still open when the drain window ends are censored
+    there: their latency is at least (window end - submit), and the
+    all-request percentiles use that lower bound."""
     import threading
     import numpy as np
     rng = np.random.default_rng(seed)
@@ -211,7 +292,8 @@ def serve_bench(S, W, duration_s=10.0, session_rate=20.0, req_per_session=10, ga
                             prob["x_hi"], prob["x_ball"], prob["xN_hi"], prob["xN_ball"], n_nl)
             x0s.append(x)
         sessions.append((kind, prob, times, x0s))
-    settings = S.default_settings(eps=1e-4, precision=S.MIXED, max_iters=200000, check_every=20)
+    settings = S.default_settings(eps=1e-4, precision=S.MIXED if precision is None else precision,
+                                  max_iters=200000, check_every=20)
     srv = S.Server(budget, settings)
     ids = [srv.add_tree(sess[1]) for sess in sessions]
     events = sorted((tm, si, k) for si, sess in enumerate(sessions) for k, tm in enumerate(sess[2]))
@@ -227,30 +309,42 @@ def serve_bench(S, W, duration_s=10.0, session_rate=20.0, req_per_session=10, ga
     th = threading.Thread(target=poller)
     th.start()
     t0 = time.perf_counter()
+    t_sub = {}
     for tm, si, k in events:
         dt = tm - (time.perf_counter() - t0)
         if dt > 0:
             time.sleep(dt)
+        t_sub[si * 1000 + k] = S.now()
         srv.submit(ids[si], sessions[si][3][k], si * 1000 + k)
     t_end = time.perf_counter() + drain_s
     while time.perf_counter() < t_end and len(results) < len(events):
         time.sleep(0.05)
     stop.set()
     th.join()
+    t_cut = S.now()
     st = srv.stats()
     srv.close()
     ok = [r for r in results if r["status"] == 0]
-    lat = np.array([r["t_done"] - r["t_submit"] for r in ok]) if ok else np.array([np.nan])
+    done = {r["req_id"]: r["t_done"] - r["t_submit"] for r in results}
+    # every request: finished ones with their latency, open ones censored at the cut
+    lat_all = np.array([done.get(q, t_cut - t) for q, t in t_sub.items()])
+    lat_ok = np.array([r["t_done"] - r["t_submit"] for r in ok]) if ok else np.array([np.nan])
     span = (max(r["t_done"] for r in results) - min(r["t_submit"] for r in results)) if results else float("nan")
     by_kind = {}
-    for r in ok:
-        kind = sessions[r["req_id"] // 1000][0]
-        by_kind.setdefault(kind, []).append(r["t_done"] - r["t_submit"])
+    for q, t in t_sub.items():
+        kind = sessions[q // 1000][0]
+        by_kind.setdefault(kind, []).append(done.get(q, t_cut - t))
     return {"offered_req_per_s": round(len(events) / duration_s, 2), "requests": len(events),
+            "precision": "fp64" if precision == S.FP64 else "mixed", "budget_bytes": int(budget),
             "completed_ok": len(ok), "completed": len(results),
+            "completed_fraction": round(len(results) / max(1, len(events)), 4),
             "solves_per_s": round(len(ok) / span, 2) if results else 0.0,
-            "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
-            "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+            "p50_latency_s": round(float(np.percentile(lat_all, 50)), 4),
+            "p99_latency_s": round(float(np.percentile(lat_all, 99)), 4),
+            "latency_note": "over every request; open requests censored at the end of the drain window "
+                            "(lower bounds)" if len(results) < len(events) else "over every request",
+            "p50_latency_completed_s": round(float(np.percentile(lat_ok, 50)), 4),
+            "p99_latency_completed_s": round(float(np.percentile(lat_ok, 99)), 4),
             "p50_by_shape_s": {k: round(float(np.percentile(v, 50)), 4) for k, v in by_kind.items()},
             "warm_fraction": round(float(np.mean([r["warm"] for r in ok])), 3) if ok else 0.0,
             "mean_iters": round(float(np.mean([r["info"]["iters"] for r in ok])), 1) if ok else 0.0,
@@ -399,7 +493,13 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0, help="sessions per second (10 requests each)")
     ap.add_argument("--serve-rate-sustained", type=float, default=0.5,
                     help="a second, lower session rate the device keeps up with (0: skip)")
+    ap.add_argument("--serve-drain", type=float, default=20.0,
+                    help="seconds the saturated serving runs wait for open requests after the last arrival")
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0,
+                    help="HBM budget of the capped serving run (0: skip)")
+    ap.add_argument("--serve-capped-seconds", type=float, default=5.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-small", action="store_true", help="skip the tiny and medium trees")
     ap.add_argument("--batch-problems", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--no-batch-solve", action="store_true")
@@ -492,6 +592,7 @@ def main():
         tol["speedup_mixed_vs_fp64"] = round(tol["fp64"]["seconds"] / max(tol["mixed"]["seconds"], 1e-9), 3)
 
     P.close()
+    small = None if args.no_small else small_trees_bench(S, W)
     batched = None
     if batch_in is not None:
         batched = batch_bench(S, *batch_in, steps=args.batch_steps + (args.batch_steps & 1), warmup=6,
@@ -499,12 +600,24 @@ def main():
         batch_in = None
     serve = None
     if not args.no_serve:
-        serve = serve_bench(S, W, duration_s=args.serve_seconds, session_rate=args.serve_rate)
+        serve = serve_bench(S, W, duration_s=args.serve_seconds, session_rate=args.serve_rate,
+                            drain_s=args.serve_drain)
         print("serve: %s" % serve, file=sys.stderr, flush=True)
         if args.serve_rate_sustained > 0:
             serve["sustained"] = serve_bench(S, W, duration_s=args.serve_seconds,
                                              session_rate=args.serve_rate_sustained, seed=7)
             print("serve (sustained rate): %s" % serve["sustained"], file=sys.stderr, flush=True)
+            # the same request stream served by plain float64 iterations
+            serve["sustained_fp64"] = serve_bench(S, W, duration_s=args.serve_seconds,
+                                                  session_rate=args.serve_rate_sustained, seed=7,
+                                                  precision=S.FP64)
+            print("serve (sustained rate, fp64): %s" % serve["sustained_fp64"], file=sys.stderr, flush=True)
+        if args.serve_budget_gb > 0:
+            # admission under a capped HBM budget: trees are evicted and set up again
+            serve["capped"] = serve_bench(S, W, duration_s=args.serve_capped_seconds, session_rate=args.serve_rate,
+                                          drain_s=args.serve_drain, budget=int(args.serve_budget_gb * (1 << 30)),
+                                          seed=9)
+            print("serve (capped budget): %s" % serve["capped"], file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC, "value": round(v32, 2), "unit": "CP iters/s", "n_gpus": 1, "steps": args.steps,
@@ -514,7 +627,8 @@ def main():
                    "f64 final check and refinement", "nodes": nodes, "nx": 50, "nu": 25,
                    "setup_s": round(t_setup, 3)},
         "fp64": {"iters_per_s": round(v64, 2), "ms_per_step": round(1000.0 / v64, 4)},
-        "kernels": kt, "roofline": roofline, "time_to_tol": tol, "batched": batched, "serve": serve,
+        "kernels": kt, "roofline": roofline, "time_to_tol": tol, "small_trees": small, "batched": batched,
+        "serve": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
