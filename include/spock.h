@@ -228,6 +228,33 @@ int32_t spock_apply_Lt(spock_problem* p, const double* eta, double* z_out, int32
 int32_t spock_prox_gconj(spock_problem* p, const double* w, double* eta_out, int32_t precision);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one CP step
+ * T, as spock_apply_T computes it, on caller DEVICE iterates, with every
+ * scratch buffer of the step's kernels (the step's descriptor, d, the backward
+ * messages, h0, ubar, the arrival counters, the residual slots) in a static
+ * device array of the library of SPOCK_NOALLOC_SCRATCH_BYTES per GPU, which
+ * each GPU the library runs on holds until the process ends.  The call makes
+ * no device or host allocation.
+ *  z, eta: device arrays [nz], [neta] (canonical layout, scaled space) of
+ *    float64 for precision SPOCK_FP64 or float32 for SPOCK_FP32; read only.
+ *  z_out, eta_out: device arrays of the same type and sizes, distinct from
+ *    the inputs and from each other; every entry is written.
+ *  xi (host, nullable, [2]) receives |xi1|_inf and |xi2|_inf of the step.
+ * The kernels run on the handle's stream with the handle's device current,
+ * and the call waits for them.  Scratch need, 256-byte aligned regions:
+ * descriptor + w (n_nl nu + n (nx + nu) + n nx + n_nl nu) + 4 n + 16 bytes,
+ * w = 8 or 4; a problem that needs more fails with SPOCK_E_CAPACITY.  Every
+ * call on one GPU shares that GPU's array and leaves its contents behind:
+ * calls that overlap on one GPU (other streams or threads) race.
+ * Errors: SPOCK_E_INVALID (null or aliased pointer, bad precision, another
+ * device current), SPOCK_E_CAPACITY, SPOCK_E_HIP.
+ */
+#define SPOCK_NOALLOC_SCRATCH_BYTES (16u << 20)
+int32_t spock_apply_T_noalloc(spock_problem* p, const void* z, const void* eta, void* z_out, void* eta_out,
+                              int32_t precision, double* xi);
+
+/*
  * Timing hook: run `steps` CP steps from the current device iterate in the
  * given precision (no residual checks, no readback) and report mean device
  * durations measured with HIP events on the handle's stream around every

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libspock_mi355x.so")
-SOURCES = ["spock_kernels.hip", "spock_host.cpp", "spock_batch.cpp", "spock_server.cpp",
+SOURCES = ["spock_kernels.hip", "spock_host.cpp", "spock_batch.cpp", "spock_server.cpp", "spock_noalloc.cpp",
            "spock_supermann.cpp"]
 ARCH = "gfx950"
 

@@ -99,6 +99,8 @@ SIGNATURES = {
     "spock_set_x0": (C.c_int32, [C.c_void_p, _dp]),
     "spock_apply_T": (C.c_int32, [C.c_void_p, _dp, _dp, _dp, _dp, C.c_int32, _dp]),
     "spock_apply_L": (C.c_int32, [C.c_void_p, _dp, _dp, C.c_int32]),
+    "spock_apply_T_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_int32, _dp]),
     "spock_project_S1": (C.c_int32, [C.c_void_p, _dp, _dp, _dp, _dp, C.c_int32]),
     "spock_project_S2": (C.c_int32, [C.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int32]),
     "spock_apply_Lt": (C.c_int32, [C.c_void_p, _dp, _dp, C.c_int32]),
@@ -314,6 +316,14 @@ class Problem:
         _check(load().spock_project_S2(self.h, _ptr(y), _ptr(tau), _ptr(s), _ptr(yo), _ptr(to), _ptr(so),
                                        precision))
         return yo, to, so
+
+    def apply_T_noalloc(self, z_dev, eta_dev, z_out_dev, eta_out_dev, precision=FP64):
+        """One CP step on device buffers given as integer addresses (e.g. a
+        torch tensor's data_ptr()); scratch in the library's static array."""
+        xi = np.zeros(2)
+        _check(load().spock_apply_T_noalloc(self.h, C.c_void_p(z_dev), C.c_void_p(eta_dev), C.c_void_p(z_out_dev),
+                                            C.c_void_p(eta_out_dev), precision, _ptr(xi)))
+        return xi
 
     def apply_L(self, z, precision=FP64):
         z = np.ascontiguousarray(z, dtype=np.float64)
