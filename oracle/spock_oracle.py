@@ -223,6 +223,19 @@ class Data:
         self.x0 = Sx * np.asarray(prob["x0"], float)
         self.layout = Layout(T, nx, nu, self.nc, self.ncN)
 
+        # linear cost terms (Prop. 1, Sec. 4.2): q^j, r^j on the edge into j
+        # (acting on x^anc(j), u^anc(j)), qN^j at leaf j; in the new variables
+        # q~ = S^-1 q, and the translation a of Prop. 1 follows from the factor
+        # Q~^1/2 that L uses (Qh, Rh, QNh)
+        def lin(key, cols):
+            v = prob.get(key)
+            return np.zeros((n, cols)) if v is None else np.asarray(v, float).reshape(n, cols)
+
+        self.q_lin = lin("q", nx) / Sx[None, :]
+        self.r_lin = lin("r", nu) / Su[None, :]
+        self.qN_lin = lin("qN", nx) / SxN[None, :]
+        self.has_lin = any(prob.get(k) is not None for k in ("q", "r", "qN"))
+
     def unscale(self, x, u):
         T = self.tree
         xs = np.array([x[j] / self.S_of(j) for j in range(T.n)])
@@ -482,6 +495,35 @@ def soc_shift(m):
     return a
 
 
+def soc_shift_lin(Qh, q):
+    """Translation a of Prop. 1 (Sec. 4.2) with Q ≻ 0 (S = I, z' = 0):
+    (-1/2 Q~^-1/2 q~, -1/8 |q~|^2_{Q~^-1} + 1/2, -1/8 |q~|^2_{Q~^-1} - 1/2),
+    where Q~^1/2 is the factor Qh of the cost block of L (Qh^T Qh = Q~), so
+    Q~^-1/2 q~ = Qh^-T q~ and |q~|^2_{Q~^-1} = |Qh^-T q~|^2."""
+    w = np.linalg.solve(Qh.T, q)
+    c = -0.125 * float(w @ w)
+    return np.concatenate([-0.5 * w, [c + 0.5, c - 0.5]])
+
+
+def edge_shift(D, j):
+    """a of the SOC block of the edge into node j: the cost on (x, u) of the
+    parent with Q~ = blkdiag(Q~, R~) and q~ = (q~^j, r~^j)."""
+    if not D.has_lin:
+        return soc_shift(D.nx + D.nu + 2)
+    nx, nu = D.nx, D.nu
+    F = np.zeros((nx + nu, nx + nu))
+    F[:nx, :nx] = D.Qh
+    F[nx:, nx:] = D.Rh
+    return soc_shift_lin(F, np.concatenate([D.q_lin[j], D.r_lin[j]]))
+
+
+def leaf_shift(D, j):
+    """a of the SOC block of leaf j (terminal cost Q_N, qN^j)."""
+    if not D.has_lin:
+        return soc_shift(D.nx + 2)
+    return soc_shift_lin(D.QNh, D.qN_lin[j])
+
+
 def project_S3(D, eta):
     T, Y = D.tree, D.layout
     nb = D.nbox
@@ -498,7 +540,7 @@ def project_S3(D, eta):
         Y.ec(out, i)[:] = pc
     for j in range(1, T.n):
         v = Y.esoc(eta, j)
-        a = soc_shift(v.size)
+        a = edge_shift(D, j)
         Y.esoc(out, j)[:] = a + proj_soc(v - a)
     for j in T.leaves:
         c = Y.ecN(eta, j)
@@ -507,7 +549,7 @@ def project_S3(D, eta):
             pc = np.concatenate([pc, proj_ball(c[D.nx:], D.ballN_r)])
         Y.ecN(out, j)[:] = pc
         v = Y.esocN(eta, j)
-        a = soc_shift(v.size)
+        a = leaf_shift(D, j)
         Y.esocN(out, j)[:] = a + proj_soc(v - a)
     return out
 
@@ -629,18 +671,22 @@ def solve(prob, eps=1e-6, max_iters=20000, precondition=True, alpha=None,
 
 def nested_cost(prob, x, u):
     """Value of the nested risk objective (Sec. 3.5, with the conditional risk mappings of Sec. 3.4) for an unscaled (x, u):
-    leaf values x^T Q_N x, then per non-leaf node the AV@R over its children
-    of (stage cost on the edge + child value)."""
+    leaf values x^T Q_N x (+ qN^T x), then per non-leaf node the AV@R over its
+    children of (stage cost on the edge, with its linear terms, + child value)."""
     T = Tree(prob["parent"], prob["prob"])
     Q, R, QN = (np.asarray(prob[k], float) for k in ("Q", "R", "QN"))
+    n, nx, nu = T.n, int(prob["nx"]), int(prob["nu"])
+    q = np.zeros((n, nx)) if prob.get("q") is None else np.asarray(prob["q"], float)
+    r = np.zeros((n, nu)) if prob.get("r") is None else np.asarray(prob["r"], float)
+    qN = np.zeros((n, nx)) if prob.get("qN") is None else np.asarray(prob["qN"], float)
     val = np.zeros(T.n)
     for j in T.leaves:
-        val[j] = np.sum(QN * x[j] ** 2)
+        val[j] = np.sum(QN * x[j] ** 2) + qN[j] @ x[j]
     for t in range(T.N - 1, -1, -1):
         for i in T.nodes(t):
             kids = T.ch[i]
             stage = np.sum(Q * x[i] ** 2) + np.sum(R * u[i] ** 2)
-            Z = np.array([stage + val[j] for j in kids])
+            Z = np.array([stage + q[j] @ x[i] + r[j] @ u[i] + val[j] for j in kids])
             val[i] = avar_ambiguity_form(Z, T.p[kids], float(prob["gamma"][i]))
     return float(val[0])
 

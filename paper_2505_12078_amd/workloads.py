@@ -18,6 +18,9 @@ A problem is a plain dict of NumPy arrays (the "problem description"):
     c        float64[n,nx] or None
     Q, R     float64[nx], float64[nu]   diagonal of the edge stage cost
     QN       float64[nx]   diagonal of the leaf cost
+    q, r, qN float64[n,nx], [n,nu], [n,nx] (optional) linear cost terms:
+                           q^j, r^j on x, u of the parent in the edge into j,
+                           qN^j at leaf j
     x_lo, x_hi, u_lo, u_hi, xN_lo, xN_hi   box bounds
     x_ball, xN_ball        Euclidean-ball radius on x (<= 0: none)
     gamma    float64[n_nl] AV@R parameter per non-leaf node
@@ -165,9 +168,11 @@ def _guard_x0(x0, parent, A, x_hi, x_ball, xN_hi, xN_ball, n_nl, margin=0.9):
 
 def make_problem(parent, nx, nu, rng, *, prob_kind="uniform", gamma=0.95,
                  x_box=5.0, u_box=1.0, x_ball=0.0, q=1.0, r=0.1, qn=1.0,
-                 affine=False, x0_range=2.0, name="custom"):
+                 affine=False, linear=False, x0_range=2.0, name="custom"):
     """Draw a full problem on the given tree (draw order: probabilities, then
-    A^i and B^i for i = 1..n-1, then x0, then the optional affine terms)."""
+    A^i and B^i for i = 1..n-1, then x0, then the optional affine terms, then
+    the optional linear cost terms q^j, r^j of the edge into j and qN^j of
+    leaf j, each N(0, 0.25))."""
     parent = np.asarray(parent, dtype=np.int32)
     n = len(parent)
     n_nl = int(np.sum(np.bincount(parent[1:], minlength=n) > 0))
@@ -183,7 +188,15 @@ def make_problem(parent, nx, nu, rng, *, prob_kind="uniform", gamma=0.95,
     x0 = _guard_x0(x0, parent, A, x_hi, x_ball, x_hi, x_ball, n_nl)
     if np.isscalar(gamma):
         gamma = np.full(n_nl, float(gamma))
+    lin = {}
+    if linear:
+        lin["q"] = 0.5 * rng.standard_normal((n, nx))
+        lin["r"] = 0.5 * rng.standard_normal((n, nu))
+        lin["qN"] = 0.5 * rng.standard_normal((n, nx))
+        for v in lin.values():
+            v[0] = 0.0  # node 0 owns no edge and is not a leaf
     return dict(
+        **lin,
         name=name, parent=parent, prob=prob, nx=int(nx), nu=int(nu), A=A, B=B, c=c,
         Q=np.full(nx, float(q)), R=np.full(nu, float(r)), QN=np.full(nx, float(qn)),
         x_lo=-x_hi.copy(), x_hi=x_hi.copy(), u_lo=-u_hi.copy(), u_hi=u_hi.copy(),
@@ -243,7 +256,7 @@ def batch_problem(k, seed=3):
 
 
 def random_ragged_problem(seed, N=4, nx=3, nu=2, max_children=3, ball=True,
-                          affine=False, gamma=None):
+                          affine=False, gamma=None, linear=False):
     """Irregular tree (each non-leaf has 1..max_children children), for tests."""
     rng = np.random.default_rng(np.random.SeedSequence([977, int(seed)]))
     counts = []
@@ -258,7 +271,7 @@ def random_ragged_problem(seed, N=4, nx=3, nu=2, max_children=3, ball=True,
     if gamma is None:
         gamma = rng.uniform(0.05, 1.0, size=n_nl)
     return make_problem(parent, nx, nu, rng, prob_kind="dirichlet", gamma=gamma,
-                        x_ball=(6.0 if ball else 0.0), affine=affine,
+                        x_ball=(6.0 if ball else 0.0), affine=affine, linear=linear,
                         name="ragged%d" % seed)
 
 
@@ -272,3 +285,85 @@ def problem_sizes(p):
     for j in range(1, n):
         stage[j] = stage[parent[j]] + 1
     return dict(n=n, n_nl=n_nl, n_leaf=n - n_nl, N=int(stage.max()), max_children=int(n_ch.max()))
+
+
+# ----------------------------------------------------------------------------
+# the networked-control case study (delay process on a scenario tree)
+# ----------------------------------------------------------------------------
+
+
+def delay_tree(branching, phi0=0.1, theta=1.0):
+    """Scenario tree of the sensor-to-controller delay fraction phi of the
+    networked-control case study: the children of a node are equiprobable,
+    and a child's phi is the quantile of Beta(theta phi, theta (1 - phi)) (its
+    parent's phi) at the centre of the child's equal-length interval of
+    [0, 1].  Returns (parent, prob, phi).  phi is kept inside
+    [1e-12, 1 - 1e-12] so that the next Beta stays defined (quantiles of a
+    Beta with a tiny first parameter underflow to 0)."""
+    from scipy.stats import beta as _beta
+    parent, _ = tree_from_branching(branching)
+    n = len(parent)
+    kids = children_lists(parent)
+    prob = np.zeros(n)
+    prob[0] = 1.0
+    phi = np.zeros(n)
+    phi[0] = phi0
+    for i in range(n):
+        k = len(kids[i])
+        if not k:
+            continue
+        centres = (np.arange(k) + 0.5) / k
+        q = _beta.ppf(centres, theta * phi[i], theta * (1.0 - phi[i]))
+        phi[kids[i]] = np.clip(q, 1e-12, 1.0 - 1e-12)
+        prob[kids[i]] = 1.0 / k
+    return parent, prob, phi
+
+
+def delay_problem(branching, nx=100, nu=50, T=5.0, phi0=0.1, theta=1.0, gamma=0.95, seed=0, name=None):
+    """The networked-control case study: a plant dx/dt = A_c x + B_c u with
+    A_c = I + diag(a), a_i ~ N(0, 0.01), B_c = 0.1 * ones(nx, nu), sampled with
+    period T; the input u_k acts after the delay sigma = phi T of its sample,
+    so over one period the previous input acts for sigma and the new one for
+    T - sigma (zero-order hold).  The state is augmented with the previous
+    input, xt = (x, u_prev) in R^(nx + nu), and the edge into node j uses the
+    delay of node j:
+        A^j = [[e^(A_c T), G1(sigma_j)], [0, 0]],  B^j = [[G0(sigma_j)], [I]],
+        G0(s) = int_0^(T - s) e^(A_c r) dr B_c,  G1(s) = int_(T - s)^T e^(A_c r) dr B_c
+    (closed forms, A_c being diagonal).  Costs Q = 1e-6 I, R = 0.1 I,
+    Q_N = diag(1 (nx), 1e-6 (nu)); |x|_inf <= 3 on the plant state (the
+    previous-input part is free), |u|_inf <= 0.9; AV@R_gamma; initial plant
+    state 2, previous input 0."""
+    parent, prob, phi = delay_tree(branching, phi0, theta)
+    n = len(parent)
+    rng = np.random.default_rng(np.random.SeedSequence([1385, int(seed)]))
+    lam = 1.0 + rng.normal(0.0, 0.1, size=nx)          # diagonal of A_c (variance 0.01)
+    Bc = 0.1 * np.ones((nx, nu))
+    m = nx + nu
+    A = np.zeros((n, m, m))
+    B = np.zeros((n, m, nu))
+    eT = np.exp(lam * T)
+    for j in range(1, n):
+        s = phi[j] * T
+        g0 = (np.exp(lam * (T - s)) - 1.0) / lam          # int_0^(T-s) e^(lam r) dr
+        g1 = (eT - np.exp(lam * (T - s))) / lam           # int_(T-s)^T e^(lam r) dr
+        A[j, :nx, :nx] = np.diag(eT)
+        A[j, :nx, nx:] = g1[:, None] * Bc
+        B[j, :nx, :] = g0[:, None] * Bc
+        B[j, nx:, :] = np.eye(nu)
+    n_nl = int(np.sum(np.bincount(parent[1:], minlength=n) > 0))
+    x_hi = np.concatenate([np.full(nx, 3.0), np.full(nu, np.inf)])
+    u_hi = np.full(nu, 0.9)
+    x0 = np.concatenate([np.full(nx, 2.0), np.zeros(nu)])
+    return dict(
+        name=name or "delay_%s_nx%d_nu%d" % ("x".join(str(b) for b in branching[:3]), nx, nu),
+        parent=parent, prob=prob, nx=m, nu=int(nu), A=A, B=B, c=None,
+        Q=np.full(m, 1e-6), R=np.full(nu, 0.1), QN=np.concatenate([np.ones(nx), np.full(nu, 1e-6)]),
+        x_lo=-x_hi.copy(), x_hi=x_hi.copy(), u_lo=-u_hi.copy(), u_hi=u_hi.copy(),
+        xN_lo=-x_hi.copy(), xN_hi=x_hi.copy(), x_ball=0.0, xN_ball=0.0,
+        gamma=np.full(n_nl, float(gamma)), x0=x0, phi=phi)
+
+
+def delay_branching(n, N=48, wide_first=True):
+    """The two tree shapes of the case study with n^2 scenarios each:
+    [n^2, 1, ..., 1] (wide_first) or [n, n, 1, ..., 1], horizon N."""
+    return [n * n] + [1] * (N - 1) if wide_first else [n, n] + [1] * (N - 2)

@@ -50,6 +50,9 @@ def _epigraph_nlp(p):
     nx, nu, n, nl = p["nx"], p["nu"], T.n, T.n_nl
     A, B = p["A"], p["B"]
     Q, R, QN = p["Q"], p["R"], p["QN"]
+    ql = np.zeros((n, nx)) if p.get("q") is None else p["q"]
+    rl = np.zeros((n, nu)) if p.get("r") is None else p["r"]
+    qNl = np.zeros((n, nx)) if p.get("qN") is None else p["qN"]
     nvar = nl * nu + nl + (n - 1)
 
     def split(v):
@@ -68,7 +71,7 @@ def _epigraph_nlp(p):
         x = rollout(u)
         val = np.zeros(n)
         for j in T.leaves:
-            val[j] = np.sum(QN * x[j] ** 2)
+            val[j] = np.sum(QN * x[j] ** 2) + qNl[j] @ x[j]
         for i in reversed(T.nonleaf):
             kids = T.ch[i]
             val[i] = t[i] + np.dot(T.p[kids], w[np.array(kids) - 1]) / p["gamma"][i]
@@ -80,7 +83,7 @@ def _epigraph_nlp(p):
         for i in T.nonleaf:
             st = np.sum(Q * x[i] ** 2) + np.sum(R * u[i] ** 2)
             for j in T.ch[i]:
-                out.append(w[j - 1] - (st + val[j] - t[i]))
+                out.append(w[j - 1] - (st + ql[j] @ x[i] + rl[j] @ u[i] + val[j] - t[i]))
         return np.array(out)
 
     def cons_box(v):
@@ -182,3 +185,34 @@ def test_golden_medium_tree_invariants():
     D = O.Data(W.config_problem(1))
     assert g["alpha"] == pytest.approx(O.step_size(D), rel=1e-14)
     assert [s["iters"] for s in g["snapshots"]] == sorted(s["iters"] for s in g["snapshots"])
+
+
+def test_linear_cost_terms_nested_objective():
+    """Linear stage and terminal cost terms (Prop. 1 with q != 0) on a ragged
+    tree: the solve's s0 equals the nested risk objective evaluated directly
+    with the linear terms on the returned trajectory, which satisfies the
+    dynamics; dropping the linear terms from the data changes the optimum."""
+    p = W.random_ragged_problem(4, N=3, nx=2, nu=1, linear=True)
+    r = O.solve(p, eps=1e-6, max_iters=40000)
+    assert r["status"] == "converged"
+    assert O.nested_cost(p, r["x"], r["u"]) == pytest.approx(r["s0"], rel=1e-5)
+    assert O.dynamics_violation(p, r["x"], r["u"]) < 1e-10
+    p0 = {k: v for k, v in p.items() if k not in ("q", "r", "qN")}
+    r0 = O.solve(p0, eps=1e-6, max_iters=40000)
+    assert abs(r0["s0"] - r["s0"]) > 1e-3
+
+
+def test_linear_cost_terms_match_independent_nlp_solve():
+    """The tiny tree with linear terms against the SLSQP epigraph solve with
+    the same terms added to its stage and leaf costs."""
+    p = W.config_problem(0)
+    rng = np.random.default_rng(77)
+    n = len(p["parent"])
+    p["q"] = 0.5 * rng.standard_normal((n, 2))
+    p["r"] = 0.5 * rng.standard_normal((n, 1))
+    p["qN"] = 0.5 * rng.standard_normal((n, 2))
+    r = O.solve(p, eps=1e-7, max_iters=60000)
+    assert r["status"] == "converged"
+    res = _epigraph_nlp(p)
+    assert res.success, res.message
+    assert res.fun == pytest.approx(r["s0"], rel=1e-5)

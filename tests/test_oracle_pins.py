@@ -70,6 +70,36 @@ def test_prop1_soc_encoding():
         assert inside == (ell <= tau)
 
 
+def test_prop1_soc_encoding_with_linear_term():
+    """Prop. 1 with a linear term (Q > 0, S = I): z^T Q z + q^T z <= tau exactly
+    when (Q^1/2 z, tau/2, tau/2) - a lies in the SOC, a = (-Q^-1/2 q / 2,
+    -|q|^2_{Q^-1}/8 + 1/2, -|q|^2_{Q^-1}/8 - 1/2); dense Q, and a planted
+    sign mistake in a fails it."""
+    rng = np.random.default_rng(6)
+    M = rng.standard_normal((4, 4))
+    Q = M @ M.T + 0.2 * np.eye(4)
+    w_, V_ = np.linalg.eigh(Q)
+    F = (V_ * np.sqrt(w_)) @ V_.T
+    q = rng.standard_normal(4)
+    a = O.soc_shift_lin(F, q)
+    bad = a.copy()
+    bad[:4] *= -1
+    agree = disagree = 0
+    for _ in range(600):
+        z = rng.standard_normal(4)
+        ell = float(z @ Q @ z + q @ z)
+        tau = ell + rng.choice([-1, 1]) * rng.uniform(1e-3, 2)
+        v = np.concatenate([F @ z, [tau / 2, tau / 2]])
+        inside = np.linalg.norm((v - a)[:-1]) <= (v - a)[-1]
+        assert inside == (ell <= tau)
+        wrong = np.linalg.norm((v - bad)[:-1]) <= (v - bad)[-1]
+        agree += wrong == (ell <= tau)
+        disagree += wrong != (ell <= tau)
+    assert disagree > 0
+    # q = 0 gives back the translation of the quadratic-only encoding
+    np.testing.assert_array_equal(O.soc_shift_lin(F, np.zeros(4)), O.soc_shift(6))
+
+
 def test_soc_hand_values(golden):
     for case in golden["soc_projection"]:
         np.testing.assert_allclose(O.proj_soc(np.array(case["v"], float)), case["proj"], atol=1e-15)
@@ -426,3 +456,26 @@ def test_residual_pins_reject_planted_mistakes():
             assert _xi1_inclusion_error(D, zp, ep, xi1) > 1e-3, (name, label)
         for label, xi2 in bad2.items():
             assert _xi2_inclusion_error(D, zp, ep, xi2) > 1e-3, (name, label)
+
+
+def test_delay_instance_is_ill_conditioned_for_float64():
+    """The networked-control case study's instance (dynamics growing about
+    150-fold per stage) defeats float64: on a 3-stage delay tree the oracle's
+    Alg. 2 and the dense KKT solve of the same S1 projection differ by O(1)
+    relative to the iterate scale, while a random problem of the same shapes
+    (nx = 150, nu = 50) agrees to rounding.  So the GPU's CP steps on this
+    instance are compared with nothing finer than that (its operators L, L*
+    and prox are compared at rounding)."""
+    for prob, lo, hi in ((W.delay_problem([4, 1, 1], nx=100, nu=50), 1e-2, np.inf),
+                         (W.make_problem(W.tree_from_branching([4, 1, 1])[0], 150, 50, np.random.default_rng(21),
+                                         x_ball=15.0), 0.0, 1e-11)):
+        D = O.Data(prob)
+        F = O.Offline(D)
+        rng = np.random.default_rng(17)
+        xbar = rng.standard_normal((D.tree.n, D.nx)) * 2
+        ubar = rng.standard_normal((D.tree.n_nl, D.nu)) * 2
+        x1, u1 = O.project_S1(D, F, xbar, ubar)
+        x2, u2, _ = _dense_S1_projection(D, xbar, ubar)
+        scale = max(np.abs(x1).max(), np.abs(u1).max())
+        err = max(np.abs(x1 - x2).max(), np.abs(u1 - u2).max()) / scale
+        assert lo <= err <= hi, err
