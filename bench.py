@@ -227,6 +227,17 @@ def batch_bench(S, probs, gen_s, workers, steps, warmup, solve=True, max_iters=2
     return out
 
 
+def supermann_time_to_tol(S, prob, eps, max_iters=40000):
+    """The SPOCK outer method (SuperMann with Anderson directions, float64)
+    from zero to rel_res eps: wall time, SuperMann iterations, applications of
+    T and the K0 / K1 / K2 step counts."""
+    with S.Problem(prob, S.default_settings(eps=eps, max_iters=max_iters, method=S.SUPERMANN)) as Q:
+        r = Q.solve(prob["x0"])
+    return {"seconds": round(r["t_solve_s"], 4), "iters": r["iters"], "T_applications": r["n_T"],
+            "K0": r["n_K0"], "K1": r["n_K1"], "K2": r["n_K2"], "rel_res": r["rel_res"],
+            "converged": r["code"] == S.SPOCK_OK, "s0": r["s0"]}
+
+
 def small_trees_bench(S, W):
     """Plain float64 CP on the tiny tree (15 nodes) and the medium tree (229
     nodes): steps per second, microseconds per step and per stage level (a
@@ -252,7 +263,44 @@ def small_trees_bench(S, W):
                          "us_per_step": round(dt * 1e6, 2), "us_per_stage_level": round(dt * 1e6 / (2 * N), 2),
                          "time_to_tol": {"eps": eps, "seconds": round(r["t_solve_s"], 4), "iters": r["iters"],
                                          "converged": r["code"] == S.SPOCK_OK, "s0": r["s0"]}}
+        out[name]["time_to_tol_supermann"] = supermann_time_to_tol(S, prob, eps, max_iters=100000)
         print("%s tree: %s" % (name, out[name]), file=sys.stderr, flush=True)
+    return out
+
+
+def delay_bench(S, W, ns=(2, 4, 8), steps=40):
+    """The networked-control case study's parallelization question: CP step
+    time of the delay tree (N = 48, plant nx = 100 plus the previous input,
+    nu = 50: products of 150 and 200 outputs) with n^2 scenarios as
+    [n^2, 1, ..., 1] and as [n, n, 1, ..., 1], float64 and float32, with the
+    algorithmic bytes per step.  (The instance as stated is infeasible, so only
+    step rates are measured.)"""
+    import numpy as np
+    import torch
+    out = []
+    for n in ns:
+        for wide in (True, False):
+            br = W.delay_branching(n, wide_first=wide)
+            prob = W.delay_problem(br)
+            t = time.perf_counter()
+            with S.Problem(prob, S.default_settings()) as P:
+                t_setup = time.perf_counter() - t
+                P.set_x0(prob["x0"])
+                row = {"n": n, "shape": "[n^2,1,...]" if wide else "[n,n,1,...]", "nodes": P.n,
+                       "scenarios": n * n, "setup_s": round(t_setup, 2)}
+                for name, prec in (("f64", S.FP64), ("f32", S.FP32)):
+                    P.set_iterate(np.zeros(P.nz), np.zeros(P.neta))
+                    P.run_steps(4, prec)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    P.run_steps(steps, prec, sync=False)
+                    torch.cuda.synchronize()
+                    dt = (time.perf_counter() - t0) / steps
+                    by = float(sum(P.kernel_bytes(prec)))
+                    row[name] = {"ms_per_step": round(dt * 1e3, 4), "steps_per_s": round(1.0 / dt, 1),
+                                 "GB_s": round(by / dt / 1e9, 1)}
+            out.append(row)
+            print("delay tree: %s" % row, file=sys.stderr, flush=True)
     return out
 
 
@@ -500,6 +548,7 @@ def main():
     ap.add_argument("--serve-capped-seconds", type=float, default=5.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-small", action="store_true", help="skip the tiny and medium trees")
+    ap.add_argument("--no-delay", action="store_true", help="skip the networked-control delay trees")
     ap.add_argument("--batch-problems", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--no-batch-solve", action="store_true")
@@ -590,9 +639,12 @@ def main():
                          "refined_in_f64": bool(r["refined"])}
             print("time-to-tol %s: %s" % (name, tol[name]), file=sys.stderr, flush=True)
         tol["speedup_mixed_vs_fp64"] = round(tol["fp64"]["seconds"] / max(tol["mixed"]["seconds"], 1e-9), 3)
+        tol["supermann_fp64"] = supermann_time_to_tol(S, prob, 1e-4)
+        print("time-to-tol supermann fp64: %s" % tol["supermann_fp64"], file=sys.stderr, flush=True)
 
     P.close()
     small = None if args.no_small else small_trees_bench(S, W)
+    delay = None if args.no_delay else delay_bench(S, W)
     batched = None
     if batch_in is not None:
         batched = batch_bench(S, *batch_in, steps=args.batch_steps + (args.batch_steps & 1), warmup=6,
@@ -627,7 +679,8 @@ def main():
                    "f64 final check and refinement", "nodes": nodes, "nx": 50, "nu": 25,
                    "setup_s": round(t_setup, 3)},
         "fp64": {"iters_per_s": round(v64, 2), "ms_per_step": round(1000.0 / v64, 4)},
-        "kernels": kt, "roofline": roofline, "time_to_tol": tol, "small_trees": small, "batched": batched,
+        "kernels": kt, "roofline": roofline, "time_to_tol": tol, "small_trees": small, "delay_trees": delay,
+        "batched": batched,
         "serve": serve,
         "cpu_baseline": cpu,
     }

@@ -65,8 +65,10 @@ extern "C" {
 
 /*
  * Problem data (Sec. 3.1-3.4).  x^j = A^j x^i + B^j u^i + c^j for j with
- * parent i; stage cost of the edge into j: x^iT Q x^i + u^iT R u^i; leaf
- * cost x^jT QN x^j; constraints lo <= (x, u) <= hi and ||x|| <= x_ball at
+ * parent i; stage cost of the edge into j: x^iT Q^j x^i + u^iT R^j u^i
+ * (+ q^jT x^i + r^jT u^i); leaf cost x^jT QN^j x^j (+ qN^jT x^j); the cost
+ * diagonals are shared (Q_diag, R_diag, QN_diag) or given per edge / leaf
+ * (Q_edge, R_edge, QN_leaf); constraints lo <= (x, u) <= hi and ||x|| <= x_ball at
  * non-leaf nodes, xN_lo <= x <= xN_hi and ||x|| <= xN_ball at leaves;
  * AV@R_gamma[i] over the children of non-leaf node i with the conditional
  * probabilities cond_prob (AV@R_1 = expectation, AV@R_0 = max).
@@ -75,13 +77,13 @@ typedef struct spock_problem_desc {
     int32_t n_nodes;          /* n >= 2 */
     const int32_t* parent;    /* [n], parent[0] = -1 */
     const double* cond_prob;  /* [n], > 0, children of each node sum to 1 */
-    int32_t nx, nu;           /* >= 1, nx + nu <= 128 */
+    int32_t nx, nu;           /* 1 <= nx, nu <= 256 */
     const double* A;          /* [n][nx][nx]; entry 0 ignored */
     const double* B;          /* [n][nx][nu]; entry 0 ignored */
     const double* c;          /* [n][nx] or NULL (= 0) */
-    const double* Q_diag;     /* [nx] > 0, shared by all edges */
-    const double* R_diag;     /* [nu] > 0 */
-    const double* QN_diag;    /* [nx] > 0, shared by all leaves */
+    const double* Q_diag;     /* [nx] > 0, shared by all edges (or see Q_edge) */
+    const double* R_diag;     /* [nu] > 0 (or see R_edge) */
+    const double* QN_diag;    /* [nx] > 0, shared by all leaves (or see QN_leaf) */
     const double* x_lo;       /* [nx], non-leaf state box (may be +-inf) */
     const double* x_hi;
     const double* u_lo;       /* [nu] */
@@ -91,6 +93,21 @@ typedef struct spock_problem_desc {
     double x_ball;            /* radius at non-leaf nodes; <= 0: no ball */
     double xN_ball;           /* radius at leaves; <= 0: no ball */
     const double* gamma;      /* [n_nl] in [0, 1] */
+    /* Optional linear cost terms (Prop. 1 with q != 0, Sec. 4.2), each NULL
+     * for zero: the edge into node j adds q[j]^T x^i + r[j]^T u^i (i its
+     * parent), leaf j adds qN[j]^T x^j.  Row-major [n][nx], [n][nu], [n][nx];
+     * row 0 (and qN's non-leaf rows) ignored. */
+    const double* q;
+    const double* r;
+    const double* qN;
+    /* Optional per-edge stage costs and per-leaf terminal costs (the paper's
+     * Q^j, R^j of each event and Q_N^j of each scenario, Sec. 3.1): diagonals
+     * [n][nx], [n][nu] (row j: the edge into node j; row 0 ignored) and
+     * [n][nx] (leaf rows).  A non-NULL array replaces Q_diag, R_diag or
+     * QN_diag, which may then be NULL; every used entry must be > 0. */
+    const double* Q_edge;
+    const double* R_edge;
+    const double* QN_leaf;
 } spock_problem_desc;
 
 typedef struct spock_settings {

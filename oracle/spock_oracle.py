@@ -149,19 +149,26 @@ class Data:
         self.tree = T = Tree(prob["parent"], prob["prob"])
         nx, nu = int(prob["nx"]), int(prob["nu"])
         self.nx, self.nu = nx, nu
-        Q = np.diag(np.asarray(prob["Q"], float))
-        R = np.diag(np.asarray(prob["R"], float))
-        QN = np.diag(np.asarray(prob["QN"], float))
+        # stage costs Q^j, R^j of the edge into j and terminal costs Q_N^j of
+        # leaf j (Sec. 3.1): one shared diagonal, or one row per node
+        Qa, Ra, QNa = (np.asarray(prob[k], float) for k in ("Q", "R", "QN"))
+        n = T.n
+
+        def per_node(a):
+            return [np.diag(a[j] if a.ndim == 2 else a) for j in range(n)]
+
+        Qs, Rs, QNs = per_node(Qa), per_node(Ra), per_node(QNa)
         ball = float(prob["x_ball"]) > 0
         ballN = float(prob["xN_ball"]) > 0
         self.has_ball, self.has_ballN = ball, ballN
 
-        # Sec. 5.4 scalings
+        # Sec. 5.4 scalings: the largest square root over the edges (leaves)
         if precondition:
             chat = np.sqrt(max(len(T.ch[i]) for i in T.nonleaf))
-            Sx = chat * np.maximum(1.0, np.sqrt(np.diag(Q)))
-            Su = chat * np.maximum(1.0, np.sqrt(np.diag(R)))
-            SxN = np.maximum(1.0, np.sqrt(np.diag(QN)))
+            edges = range(1, n)
+            Sx = chat * np.maximum(1.0, np.sqrt(np.max([np.diag(Qs[j]) for j in edges], axis=0)))
+            Su = chat * np.maximum(1.0, np.sqrt(np.max([np.diag(Rs[j]) for j in edges], axis=0)))
+            SxN = np.maximum(1.0, np.sqrt(np.max([np.diag(QNs[j]) for j in T.leaves], axis=0)))
         else:
             Sx, Su, SxN = np.ones(nx), np.ones(nu), np.ones(nx)
         self.Sx, self.Su, self.SxN = Sx, Su, SxN
@@ -184,10 +191,11 @@ class Data:
             self.A[j] = (Sj[:, None] * A[j]) / Sx[None, :]
             self.B[j] = (Sj[:, None] * B[j]) / Su[None, :]
             self.c[j] = Sj * c[j]
-        # cost square roots in the new variables: ||Q^1/2 x||^2 = x^T Q x
-        self.Qh = _sym_sqrt(Q) / Sx[None, :]
-        self.Rh = _sym_sqrt(R) / Su[None, :]
-        self.QNh = _sym_sqrt(QN) / SxN[None, :]
+        # cost square roots in the new variables: ||Q^1/2 x||^2 = x^T Q x, per
+        # edge j (Qh_e[j], Rh_e[j]) and per leaf (QNh_l[j])
+        self.Qh_e = [_sym_sqrt(Qs[j]) / Sx[None, :] for j in range(n)]
+        self.Rh_e = [_sym_sqrt(Rs[j]) / Su[None, :] for j in range(n)]
+        self.QNh_l = [_sym_sqrt(QNs[j]) / SxN[None, :] for j in range(n)]
 
         # non-leaf constraint Gamma_x x + Gamma_u u in C = box(x) x box(u) [x ball(x)]
         Ix, Iu = np.eye(nx), np.eye(nu)
@@ -324,11 +332,11 @@ def apply_L(D, z):
     for j in range(1, T.n):
         i = T.anc[j]
         t = Y.tau(z, j)[0]
-        Y.esoc(eta, j)[:] = np.concatenate([D.Qh @ Y.x(z, i), D.Rh @ Y.u(z, i), [0.5 * t, 0.5 * t]])
+        Y.esoc(eta, j)[:] = np.concatenate([D.Qh_e[j] @ Y.x(z, i), D.Rh_e[j] @ Y.u(z, i), [0.5 * t, 0.5 * t]])
     for j in T.leaves:
         Y.ecN(eta, j)[:] = D.GN @ Y.x(z, j)
         sj = Y.s(z, j)[0]
-        Y.esocN(eta, j)[:] = np.concatenate([D.QNh @ Y.x(z, j), [0.5 * sj, 0.5 * sj]])
+        Y.esocN(eta, j)[:] = np.concatenate([D.QNh_l[j] @ Y.x(z, j), [0.5 * sj, 0.5 * sj]])
     return eta
 
 
@@ -348,13 +356,13 @@ def apply_Lt(D, eta):
     for j in range(1, T.n):
         i = T.anc[j]
         w = Y.esoc(eta, j)
-        Y.x(z, i)[:] += D.Qh.T @ w[:nx]
-        Y.u(z, i)[:] += D.Rh.T @ w[nx:nx + nu]
+        Y.x(z, i)[:] += D.Qh_e[j].T @ w[:nx]
+        Y.u(z, i)[:] += D.Rh_e[j].T @ w[nx:nx + nu]
         Y.tau(z, j)[:] += 0.5 * (w[nx + nu] + w[nx + nu + 1])
     for j in T.leaves:
         Y.x(z, j)[:] += D.GN.T @ Y.ecN(eta, j)
         w = Y.esocN(eta, j)
-        Y.x(z, j)[:] += D.QNh.T @ w[:nx]
+        Y.x(z, j)[:] += D.QNh_l[j].T @ w[:nx]
         Y.s(z, j)[:] += 0.5 * (w[nx] + w[nx + 1])
     return z
 
@@ -368,9 +376,9 @@ def L_norm(D):
     norms = []
     for i in T.nonleaf:
         rows = [np.hstack([D.Gx, D.Gu])]
-        for _ in T.ch[i]:
-            rows.append(np.hstack([D.Qh, np.zeros((D.nx, D.nu))]))
-            rows.append(np.hstack([np.zeros((D.nu, D.nx)), D.Rh]))
+        for j in T.ch[i]:
+            rows.append(np.hstack([D.Qh_e[j], np.zeros((D.nx, D.nu))]))
+            rows.append(np.hstack([np.zeros((D.nu, D.nx)), D.Rh_e[j]]))
         norms.append(np.linalg.norm(np.vstack(rows), 2))
         b = b_vector(D, i)
         m = b.size
@@ -380,7 +388,7 @@ def L_norm(D):
         blk[m, m] = 1.0
         norms.append(np.linalg.norm(blk, 2))
     for j in T.leaves:
-        norms.append(np.linalg.norm(np.vstack([D.GN, D.QNh]), 2))
+        norms.append(np.linalg.norm(np.vstack([D.GN, D.QNh_l[j]]), 2))
     norms.append(np.sqrt(0.5))  # tau^j and leaf s^j: (1/2, 1/2)
     return float(max(norms))
 
@@ -512,8 +520,8 @@ def edge_shift(D, j):
         return soc_shift(D.nx + D.nu + 2)
     nx, nu = D.nx, D.nu
     F = np.zeros((nx + nu, nx + nu))
-    F[:nx, :nx] = D.Qh
-    F[nx:, nx:] = D.Rh
+    F[:nx, :nx] = D.Qh_e[j]
+    F[nx:, nx:] = D.Rh_e[j]
     return soc_shift_lin(F, np.concatenate([D.q_lin[j], D.r_lin[j]]))
 
 
@@ -521,7 +529,7 @@ def leaf_shift(D, j):
     """a of the SOC block of leaf j (terminal cost Q_N, qN^j)."""
     if not D.has_lin:
         return soc_shift(D.nx + 2)
-    return soc_shift_lin(D.QNh, D.qN_lin[j])
+    return soc_shift_lin(D.QNh_l[j], D.qN_lin[j])
 
 
 def project_S3(D, eta):
@@ -674,19 +682,21 @@ def nested_cost(prob, x, u):
     leaf values x^T Q_N x (+ qN^T x), then per non-leaf node the AV@R over its
     children of (stage cost on the edge, with its linear terms, + child value)."""
     T = Tree(prob["parent"], prob["prob"])
-    Q, R, QN = (np.asarray(prob[k], float) for k in ("Q", "R", "QN"))
     n, nx, nu = T.n, int(prob["nx"]), int(prob["nu"])
+    # cost diagonals per node (the edge into j, or leaf j): shared or per row
+    Q, R, QN = (np.broadcast_to(np.asarray(prob[k], float), (n, d)) for k, d in (("Q", nx), ("R", nu),
+                                                                                 ("QN", nx)))
     q = np.zeros((n, nx)) if prob.get("q") is None else np.asarray(prob["q"], float)
     r = np.zeros((n, nu)) if prob.get("r") is None else np.asarray(prob["r"], float)
     qN = np.zeros((n, nx)) if prob.get("qN") is None else np.asarray(prob["qN"], float)
     val = np.zeros(T.n)
     for j in T.leaves:
-        val[j] = np.sum(QN * x[j] ** 2) + qN[j] @ x[j]
+        val[j] = np.sum(QN[j] * x[j] ** 2) + qN[j] @ x[j]
     for t in range(T.N - 1, -1, -1):
         for i in T.nodes(t):
             kids = T.ch[i]
-            stage = np.sum(Q * x[i] ** 2) + np.sum(R * u[i] ** 2)
-            Z = np.array([stage + q[j] @ x[i] + r[j] @ u[i] + val[j] for j in kids])
+            Z = np.array([np.sum(Q[j] * x[i] ** 2) + np.sum(R[j] * u[i] ** 2) + q[j] @ x[i] + r[j] @ u[i] + val[j]
+                          for j in kids])
             val[i] = avar_ambiguity_form(Z, T.p[kids], float(prob["gamma"][i]))
     return float(val[0])
 
@@ -708,19 +718,22 @@ def risk_neutral_lq(prob):
     when every AV@R parameter is 1 (AV@R_1 = E) and no constraint is active.
     Returns (V*, x, u) with V* = x0^T P0 x0."""
     T = Tree(prob["parent"], prob["prob"])
-    Q, R, QN = (np.diag(np.asarray(prob[k], float)) for k in ("Q", "R", "QN"))
+    nx, nu = int(prob["nx"]), int(prob["nu"])
+    Qd, Rd, QNd = (np.broadcast_to(np.asarray(prob[k], float), (T.n, d)) for k, d in (("Q", nx), ("R", nu),
+                                                                                      ("QN", nx)))
     A, B = np.asarray(prob["A"]), np.asarray(prob["B"])
     Ph = [None] * T.n
     Kf = [None] * T.n
     for j in T.leaves:
-        Ph[j] = QN
+        Ph[j] = np.diag(QNd[j])
     for t in range(T.N - 1, -1, -1):
         for i in T.nodes(t):
             kids = T.ch[i]
             p = T.p[kids]
-            Huu = R + sum(pk * B[j].T @ Ph[j] @ B[j] for pk, j in zip(p, kids))
+            # the stage cost of the edge into child j weighs with p_j
+            Huu = sum(pk * (np.diag(Rd[j]) + B[j].T @ Ph[j] @ B[j]) for pk, j in zip(p, kids))
             Hux = sum(pk * B[j].T @ Ph[j] @ A[j] for pk, j in zip(p, kids))
-            Hxx = Q + sum(pk * A[j].T @ Ph[j] @ A[j] for pk, j in zip(p, kids))
+            Hxx = sum(pk * (np.diag(Qd[j]) + A[j].T @ Ph[j] @ A[j]) for pk, j in zip(p, kids))
             Kf[i] = -np.linalg.solve(Huu, Hux)
             Ph[i] = Hxx + Hux.T @ Kf[i]
     x = np.zeros((T.n, A.shape[1]))

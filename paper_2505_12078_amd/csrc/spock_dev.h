@@ -69,6 +69,17 @@ struct ProbDev {
     const real* hiN;
     const real* prob;        // conditional probability per node
     const real* gamma;       // AV@R parameter per non-leaf node
+    // translations a of Prop. 1 with linear cost terms: per edge j (m + 2,
+    // at (j - 1) (m + 2)) and per leaf (nx + 2); null without linear terms,
+    // then a = (0, ..., 0, 1/2, -1/2)
+    const real* sa;
+    const real* saN;
+    // per-edge cost square roots (Q^j^1/2 S_x^-1 at j nx, R^j^1/2 S_u^-1 at
+    // j nu, edge j = 1..n-1) and per-leaf terminal ones (at (j - n_nl) nx);
+    // null when every edge shares qh, rh and every leaf qnh
+    const real* qh_e;
+    const real* rh_e;
+    const real* qnh_l;
     const real* x0;          // scaled initial state
 
     // iterates, two copies each; a step reads copy `par` and writes `par ^ 1`
@@ -154,7 +165,7 @@ struct LaunchCfg {
 };
 
 // Packed tiles of the column-lane products out[o] = sum_k A[k][o] v[k]
-// (K rows, O <= 128 columns).  Block 1 holds columns 0..min(O,64)-1 with
+// (K rows, O columns; the register forms below take O <= 128).  Block 1 holds columns 0..min(O,64)-1 with
 // G1 = 64 / min(O,64) row groups, block 2 the columns from 64 on with
 // G2 = 64 / (O - 64).  Lane l = g W + c of a block holds rows g, g + G, ... of
 // column c; rows per lane are padded to the 16-byte vector width V, and the
@@ -162,14 +173,14 @@ struct LaunchCfg {
 template <typename real>
 __host__ __device__ constexpr int tile_vec() { return 16 / (int)sizeof(real); }
 __host__ __device__ inline int tile_rows(int K, int G, int V) { return ((K + G - 1) / G + V - 1) / V * V; }
+// Wider products (O > 128) continue the same way: block b holds the columns
+// 64 b .. min(O, 64 (b + 1)) - 1, every block but the last with one row group.
+__host__ __device__ inline int tile_blocks(int O) { return (O + 63) / 64; }
+__host__ __device__ inline int tile_block_width(int O, int b) { return O - 64 * b < 64 ? O - 64 * b : 64; }
 __host__ __device__ inline long long tile_elems(int K, int O, int V) {
     if (O < 1) return 0;
-    const int W1 = O < 64 ? O : 64, G1 = 64 / W1;
-    long long e = (long long)tile_rows(K, G1, V) * 64;
-    if (O > 64) {
-        const int W2 = O - 64, G2 = 64 / W2;
-        e += (long long)tile_rows(K, G2, V) * 64;
-    }
+    long long e = 0;
+    for (int b = 0; b < tile_blocks(O); ++b) e += (long long)tile_rows(K, 64 / tile_block_width(O, b), V) * 64;
     return e;
 }
 

@@ -169,6 +169,11 @@ static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
     h.hiN = a.take<real>(nx);
     h.prob = a.take<real>(n);
     h.gamma = a.take<real>(nl);
+    h.sa = p->has_lin ? a.take<real>((long long)(n - 1) * (m + 2)) : nullptr;
+    h.saN = p->has_lin ? a.take<real>((long long)p->n_leaf * (nx + 2)) : nullptr;
+    h.qh_e = p->edge_cost ? a.take<real>((long long)n * nx) : nullptr;
+    h.rh_e = p->edge_cost ? a.take<real>((long long)n * nu) : nullptr;
+    h.qnh_l = p->leaf_cost ? a.take<real>((long long)p->n_leaf * nx) : nullptr;
     h.x0 = a.take<real>(nx);
     // z and eta of one copy are one vector [z | zero pad | eta] (the
     // SuperMann iteration combines whole iterates)
@@ -231,12 +236,24 @@ static bool finite_all(const double* v, long long n) {
     return true;
 }
 
+// Cost diagonals of the edge into node j (shared or per edge) and of leaf j.
+static double Qd(const spock_problem_desc* d, int j, int k) {
+    return d->Q_edge ? d->Q_edge[(size_t)j * d->nx + k] : d->Q_diag[k];
+}
+static double Rd(const spock_problem_desc* d, int j, int k) {
+    return d->R_edge ? d->R_edge[(size_t)j * d->nu + k] : d->R_diag[k];
+}
+static double QNd(const spock_problem_desc* d, int j, int k) {
+    return d->QN_leaf ? d->QN_leaf[(size_t)j * d->nx + k] : d->QN_diag[k];
+}
+
 static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p) {
     if (!d) return fail(SPOCK_E_INVALID, "null problem description");
     const int n = d->n_nodes;
     if (n < 2) return fail(SPOCK_E_INVALID, "a tree needs at least two nodes");
     if (d->nx < 1 || d->nu < 1) return fail(SPOCK_E_INVALID, "nx and nu must be >= 1");
-    if (!d->parent || !d->cond_prob || !d->A || !d->B || !d->Q_diag || !d->R_diag || !d->QN_diag ||
+    if (!d->parent || !d->cond_prob || !d->A || !d->B || !(d->Q_diag || d->Q_edge) || !(d->R_diag || d->R_edge) ||
+        !(d->QN_diag || d->QN_leaf) ||
         !d->x_lo || !d->x_hi || !d->u_lo || !d->u_hi || !d->xN_lo || !d->xN_hi || !d->gamma)
         return fail(SPOCK_E_INVALID, "missing array in the problem description");
     if (d->parent[0] != -1) return fail(SPOCK_E_INVALID, "parent[0] must be -1");
@@ -279,13 +296,31 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     const int nx = d->nx, nu = d->nu;
     if (!finite_all(d->A + (size_t)nx * nx, (long long)(n - 1) * nx * nx) ||
         !finite_all(d->B + (size_t)nx * nu, (long long)(n - 1) * nx * nu) ||
-        (d->c && !finite_all(d->c + nx, (long long)(n - 1) * nx)) || !finite_all(d->Q_diag, nx) ||
-        !finite_all(d->R_diag, nu) || !finite_all(d->QN_diag, nx) || !finite_all(d->gamma, nl))
+        (d->c && !finite_all(d->c + nx, (long long)(n - 1) * nx)) || !finite_all(d->gamma, nl))
         return fail(SPOCK_E_INVALID, "non-finite problem data");
-    for (int k = 0; k < nx; ++k)
-        if (!(d->Q_diag[k] > 0) || !(d->QN_diag[k] > 0)) return fail(SPOCK_E_INVALID, "Q, QN must be > 0");
-    for (int k = 0; k < nu; ++k)
-        if (!(d->R_diag[k] > 0)) return fail(SPOCK_E_INVALID, "R must be > 0");
+    // cost diagonals: every edge's Q, R and every leaf's QN positive and finite
+    for (int j = 1; j < n; ++j) {
+        for (int k = 0; k < nx; ++k) {
+            const double v = Qd(d, j, k);
+            if (!(v > 0) || !std::isfinite(v)) return fail(SPOCK_E_INVALID, "Q must be finite and > 0");
+            if (j >= nl) {
+                const double w = QNd(d, j, k);
+                if (!(w > 0) || !std::isfinite(w)) return fail(SPOCK_E_INVALID, "QN must be finite and > 0");
+            }
+        }
+        for (int k = 0; k < nu; ++k) {
+            const double v = Rd(d, j, k);
+            if (!(v > 0) || !std::isfinite(v)) return fail(SPOCK_E_INVALID, "R must be finite and > 0");
+        }
+    }
+    // linear cost terms: edge rows 1..n-1, leaf rows of qN
+    if ((d->q && !finite_all(d->q + nx, (long long)(n - 1) * nx)) ||
+        (d->r && !finite_all(d->r + nu, (long long)(n - 1) * nu)) ||
+        (d->qN && !finite_all(d->qN + (size_t)nl * nx, (long long)(n - nl) * nx)))
+        return fail(SPOCK_E_INVALID, "non-finite linear cost terms");
+    p->has_lin = (d->q || d->r || d->qN) ? 1 : 0;
+    p->edge_cost = (d->Q_edge || d->R_edge) ? 1 : 0;
+    p->leaf_cost = d->QN_leaf ? 1 : 0;
     for (int k = 0; k < nx; ++k)
         if (!(d->x_lo[k] <= d->x_hi[k]) || !(d->xN_lo[k] <= d->xN_hi[k]) || std::isnan(d->x_lo[k]) ||
             std::isnan(d->xN_lo[k]))
@@ -322,9 +357,8 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     p->neta = o;
     p->M_stride = ((long long)nx * p->m + 31) / 32 * 32;
     p->KR_stride = ((long long)nu * p->m + 31) / 32 * 32;
-    // the column-lane products place at most 128 outputs on a wavefront's
-    // lanes; [Abar|B]^T h has nx + nu of them
-    if (p->m > 128) return fail(SPOCK_E_INVALID, "nx + nu must not exceed 128");
+    // the sweeps keep a vector of nx and of nu entries as 4 entries per lane
+    if (p->nx > 256 || p->nu > 256) return fail(SPOCK_E_INVALID, "nx and nu must not exceed 256");
     if (node_lds_bytes(p, 64, 8) > 64 * 1024 ||
         spk::sweep_int_bytes(p->N) + spk::sweep_elems(nx, nu) * 8 > 64 * 1024)
         return fail(SPOCK_E_INVALID, "nx + nu or the branching is too large for one wavefront's LDS");
@@ -362,21 +396,51 @@ static void scale_data(const spock_problem_desc* d, int precondition, spock_prob
     p->Su.assign(nu, 1.0);
     p->SxN.assign(nx, 1.0);
     if (precondition) {
+        // Sec. 5.4: the largest square root over the edges (leaves for S_N)
         const double chat = std::sqrt((double)p->max_ch);
         for (int k = 0; k < nx; ++k) {
-            p->Sx[k] = chat * std::max(1.0, std::sqrt(d->Q_diag[k]));
-            p->SxN[k] = std::max(1.0, std::sqrt(d->QN_diag[k]));
+            double mq = 0, mqN = 0;
+            for (int j = 1; j < p->n; ++j) {
+                mq = std::max(mq, Qd(d, j, k));
+                if (j >= p->n_nl) mqN = std::max(mqN, QNd(d, j, k));
+            }
+            p->Sx[k] = chat * std::max(1.0, std::sqrt(mq));
+            p->SxN[k] = std::max(1.0, std::sqrt(mqN));
         }
-        for (int k = 0; k < nu; ++k) p->Su[k] = chat * std::max(1.0, std::sqrt(d->R_diag[k]));
+        for (int k = 0; k < nu; ++k) {
+            double mr = 0;
+            for (int j = 1; j < p->n; ++j) mr = std::max(mr, Rd(d, j, k));
+            p->Su[k] = chat * std::max(1.0, std::sqrt(mr));
+        }
     }
+    // shared square roots (those of edge 1 / the first leaf when they differ
+    // per edge; the kernels then read the per-edge ones)
+    const int j1 = 1, l1 = p->n_nl;
     p->qh.resize(nx);
     p->rh.resize(nu);
     p->qnh.resize(nx);
     for (int k = 0; k < nx; ++k) {
-        p->qh[k] = std::sqrt(d->Q_diag[k]) / p->Sx[k];
-        p->qnh[k] = std::sqrt(d->QN_diag[k]) / p->SxN[k];
+        p->qh[k] = std::sqrt(Qd(d, j1, k)) / p->Sx[k];
+        p->qnh[k] = std::sqrt(QNd(d, l1, k)) / p->SxN[k];
     }
-    for (int k = 0; k < nu; ++k) p->rh[k] = std::sqrt(d->R_diag[k]) / p->Su[k];
+    for (int k = 0; k < nu; ++k) p->rh[k] = std::sqrt(Rd(d, j1, k)) / p->Su[k];
+    p->qh_e.clear();
+    p->rh_e.clear();
+    p->qnh_l.clear();
+    if (p->edge_cost) {
+        p->qh_e.assign((size_t)p->n * nx, 0.0);
+        p->rh_e.assign((size_t)p->n * nu, 0.0);
+        for (int j = 1; j < p->n; ++j) {
+            for (int k = 0; k < nx; ++k) p->qh_e[(size_t)j * nx + k] = std::sqrt(Qd(d, j, k)) / p->Sx[k];
+            for (int k = 0; k < nu; ++k) p->rh_e[(size_t)j * nu + k] = std::sqrt(Rd(d, j, k)) / p->Su[k];
+        }
+    }
+    if (p->leaf_cost) {
+        p->qnh_l.assign((size_t)p->n_leaf * nx, 0.0);
+        for (int l = 0; l < p->n_leaf; ++l)
+            for (int k = 0; k < nx; ++k)
+                p->qnh_l[(size_t)l * nx + k] = std::sqrt(QNd(d, p->n_nl + l, k)) / p->SxN[k];
+    }
     // constraint rows Gamma S^-1 have orthogonal columns; their 2-norm is the
     // largest column norm
     double a = 1.0, aN = 1.0;
@@ -427,21 +491,76 @@ static void scale_data(const spock_problem_desc* d, int precondition, spock_prob
     p->x_hi.assign(d->x_hi, d->x_hi + nx);
     p->x_ball = d->x_ball;
 
+    // Prop. 1 with a linear term: a = (-Q^-1/2 q / 2, c + 1/2, c - 1/2),
+    // c = -|q|^2_{Q^-1} / 8; the change of variables of Sec. 5.4 leaves a
+    // unchanged (Q~^-1/2 q~ = Q^-1/2 q for diagonal Q and S)
+    p->sa.clear();
+    p->saN.clear();
+    if (p->has_lin) {
+        const int m = p->m;
+        p->sa.assign((size_t)(p->n - 1) * (m + 2), 0.0);
+        for (int j = 1; j < p->n; ++j) {
+            double* a = p->sa.data() + (size_t)(j - 1) * (m + 2);
+            double c = 0;
+            for (int k = 0; k < nx; ++k) {
+                const double w = d->q ? d->q[(size_t)j * nx + k] / std::sqrt(Qd(d, j, k)) : 0.0;
+                a[k] = -0.5 * w;
+                c += w * w;
+            }
+            for (int k = 0; k < nu; ++k) {
+                const double w = d->r ? d->r[(size_t)j * nu + k] / std::sqrt(Rd(d, j, k)) : 0.0;
+                a[nx + k] = -0.5 * w;
+                c += w * w;
+            }
+            a[m] = -0.125 * c + 0.5;
+            a[m + 1] = -0.125 * c - 0.5;
+        }
+        p->saN.assign((size_t)p->n_leaf * (nx + 2), 0.0);
+        for (int l = 0; l < p->n_leaf; ++l) {
+            const int j = p->n_nl + l;
+            double* a = p->saN.data() + (size_t)l * (nx + 2);
+            double c = 0;
+            for (int k = 0; k < nx; ++k) {
+                const double w = d->qN ? d->qN[(size_t)j * nx + k] / std::sqrt(QNd(d, j, k)) : 0.0;
+                a[k] = -0.5 * w;
+                c += w * w;
+            }
+            a[nx] = -0.125 * c + 0.5;
+            a[nx + 1] = -0.125 * c - 0.5;
+        }
+    }
+
     // ||L||: largest block norm of L composed with a permutation
     double L2 = 0.5;  // tau^j and leaf s^j rows (1/2, 1/2)
     for (int i = 0; i < p->n_nl; ++i) {
-        const double k = p->n_ch[i];
-        for (int r = 0; r < nx; ++r)
-            L2 = std::max(L2, p->gx[r] * p->gx[r] + p->gb[r] * p->gb[r] + k * p->qh[r] * p->qh[r]);
-        for (int r = 0; r < nu; ++r) L2 = std::max(L2, p->gu[r] * p->gu[r] + k * p->rh[r] * p->rh[r]);
+        // (x^i, u^i) block: constraint rows and every child edge's cost rows
+        for (int r = 0; r < nx; ++r) {
+            double sq = 0;
+            for (int c = 0; c < p->n_ch[i]; ++c) {
+                const double h = p->edge_cost ? p->qh_e[(size_t)(p->first_child[i] + c) * nx + r] : p->qh[r];
+                sq += h * h;
+            }
+            L2 = std::max(L2, p->gx[r] * p->gx[r] + p->gb[r] * p->gb[r] + sq);
+        }
+        for (int r = 0; r < nu; ++r) {
+            double sq = 0;
+            for (int c = 0; c < p->n_ch[i]; ++c) {
+                const double h = p->edge_cost ? p->rh_e[(size_t)(p->first_child[i] + c) * nu + r] : p->rh[r];
+                sq += h * h;
+            }
+            L2 = std::max(L2, p->gu[r] * p->gu[r] + sq);
+        }
         double b2 = 1.0;
         for (int c = 0; c < p->n_ch[i]; ++c) b2 += p->prob[p->first_child[i] + c] * p->prob[p->first_child[i] + c];
         const double beta = std::sqrt(b2);
         const double sig = 0.5 * (beta + std::sqrt(b2 + 4.0));  // [[I, 0], [-b^T, 1]]
         L2 = std::max(L2, sig * sig);
     }
-    for (int r = 0; r < nx; ++r)
-        L2 = std::max(L2, p->gxN[r] * p->gxN[r] + p->gbN[r] * p->gbN[r] + p->qnh[r] * p->qnh[r]);
+    for (int l = 0; l < (p->leaf_cost ? p->n_leaf : 1); ++l)
+        for (int r = 0; r < nx; ++r) {
+            const double h = p->leaf_cost ? p->qnh_l[(size_t)l * nx + r] : p->qnh[r];
+            L2 = std::max(L2, p->gxN[r] * p->gxN[r] + p->gbN[r] * p->gbN[r] + h * h);
+        }
     p->Lnorm = std::sqrt(L2);
 }
 
@@ -579,9 +698,8 @@ static void tile_pack(real* out, int K, int O, F at) {
             }
         return (size_t)rows * 64;
     };
-    const int W1 = O < 64 ? O : 64;
-    const size_t e1 = block(out, W1, 0);
-    if (O > 64) block(out + e1, O - 64, 64);
+    size_t off = 0;
+    for (int b = 0; b < spk::tile_blocks(O); ++b) off += block(out + off, spk::tile_block_width(O, b), 64 * b);
 }
 
 // The five packed tile arrays of one precision from the float64 factors.
@@ -688,6 +806,15 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     HIP_TRY(put<real>(h.hiN, p->hiN, st));
     HIP_TRY(put<real>(h.prob, p->prob, st));
     HIP_TRY(put<real>(h.gamma, p->gamma, st));
+    if (p->has_lin) {
+        HIP_TRY(put<real>(h.sa, p->sa, st));
+        HIP_TRY(put<real>(h.saN, p->saN, st));
+    }
+    if (p->edge_cost) {
+        HIP_TRY(put<real>(h.qh_e, p->qh_e, st));
+        HIP_TRY(put<real>(h.rh_e, p->rh_e, st));
+    }
+    if (p->leaf_cost) HIP_TRY(put<real>(h.qnh_l, p->qnh_l, st));
     for (int k = 0; k < 2; ++k) HIP_TRY(spk::launch_fill<real>(h.z[k], real(0), p->nzp + p->neta, st));
     HIP_TRY(hipMemcpyAsync(s.d, &h, sizeof(h), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -842,7 +969,9 @@ int node_lds_bytes(const spock_problem* p, int node_wg, int real_bytes) {
 int tile_class(int need) {
     for (int c : spk::kTileClasses)
         if (need <= c) return c;
-    return spk::kTileClasses[3];
+    // no class holds it: the product runs from the packed tile in global
+    // memory, and the smallest class keeps the unused register tile small
+    return spk::kTileClasses[0];
 }
 
 template <typename real>

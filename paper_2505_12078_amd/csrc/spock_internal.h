@@ -102,6 +102,15 @@ struct spock_problem {
     // scaled problem data
     std::vector<double> Sx, Su, SxN;
     std::vector<double> qh, rh, qnh, gx, gu, gb, gxN, gbN, lo, hi, loN, hiN, prob, gamma;
+    // translations a of Prop. 1 with linear cost terms (has_lin): per edge
+    // j = 1..n-1 (m + 2 each) and per leaf (nx + 2 each)
+    int has_lin = 0;
+    std::vector<double> sa, saN;
+    // per-edge / per-leaf cost square roots in the scaled space (qh_e [n][nx],
+    // rh_e [n][nu] by edge, qnh_l [n_leaf][nx] by leaf), used when the
+    // description gives per-edge costs (edge_cost) or per-leaf ones (leaf_cost)
+    int edge_cost = 0, leaf_cost = 0;
+    std::vector<double> qh_e, rh_e, qnh_l;
     double ball_r = 0, ballN_r = 0, con_scale = 1, con_scaleN = 1;
     double Lnorm = 0, alpha = 0;
     // unscaled root constraint for the x0 check

@@ -293,7 +293,7 @@ SPK_DEV void stage_consts(const ProbDev<real>* __restrict__ P, real* cst) {
 // column-lane products (one wavefront)
 // ---------------------------------------------------------------------------
 
-// out[o] = sum_{k<K} A[k][o] v[k] for o < O <= 128.  Block 1 covers the
+// out[o] = sum_{k<K} A[k][o] v[k] for o < O.  Block 1 covers the
 // columns 0..W1-1 (W1 = min(O, 64)) with G1 = 64 / W1 row groups: lane
 // l = g W1 + c keeps rows g, g + G1, ... of column c.  Block 2 covers the
 // columns 64..O-1 the same way with G2 = 64 / (O - 64).  The host stores every
@@ -301,6 +301,8 @@ SPK_DEV void stage_consts(const ProbDev<real>* __restrict__ P, real* cst) {
 // reads its rows with 16-byte loads at fixed offsets and a wavefront's load
 // covers 1 KiB of contiguous memory.  Group partial sums meet in LDS and are
 // added in group order (deterministic).
+// Wider products (O > 128, more blocks of 64 columns) run from global memory
+// (col_direct); W2, G2 and rows2 then describe the full second block.
 struct ColShape {
     int K, O, W1, G1, W2, G2, rows1, rows2;  // rows per lane, padded to the vector width
 };
@@ -312,7 +314,7 @@ SPK_DEV ColShape col_shape(int K, int O) {
     s.O = O;
     s.W1 = O < 64 ? O : 64;
     s.G1 = 64 / s.W1;
-    s.W2 = O > 64 ? O - 64 : 0;
+    s.W2 = O > 64 ? (O - 64 < 64 ? O - 64 : 64) : 0;
     s.G2 = s.W2 > 0 ? 64 / s.W2 : 1;
     s.rows1 = tile_rows(K, s.G1, tile_vec<real>());
     s.rows2 = s.W2 > 0 ? tile_rows(K, s.G2, tile_vec<real>()) : 0;
@@ -450,7 +452,8 @@ SPK_DEV void col_apply(const ColTile<real, R>& T, const ColShape& s, const real*
 }
 
 // The same product read from the packed tile in global memory (shapes beyond
-// the register class).
+// the register class, and products of any width: one 64-column block after
+// the other, block b at columns 64 b ..).
 template <typename real>
 SPK_DEV void col_direct(const real* __restrict__ tile, const ColShape& s, const real* v, real* out, real* red) {
     constexpr int V = 16 / (int)sizeof(real);
@@ -465,20 +468,20 @@ SPK_DEV void col_direct(const real* __restrict__ tile, const ColShape& s, const 
         }
         return acc;
     };
-    red[lane] = part(tile, s.rows1, s.W1, s.G1);
-    red[64 + lane] = s.W2 > 0 ? part(tile + (long long)s.rows1 * 64, s.rows2, s.W2, s.G2) : real(0);
-    wave_sync();
-    if (lane < s.W1) {
-        real t = 0;
-        for (int g = 0; g < s.G1; ++g) t += red[g * s.W1 + lane];
-        out[lane] = t;
+    const int nb = tile_blocks(s.O);
+    const real* blk = tile;
+    for (int b = 0; b < nb; ++b) {
+        const int W = tile_block_width(s.O, b), G = 64 / W, rows = tile_rows(s.K, G, V);
+        red[lane] = part(blk, rows, W, G);
+        wave_sync();
+        if (lane < W) {
+            real t = 0;
+            for (int g = 0; g < G; ++g) t += red[g * W + lane];
+            out[64 * b + lane] = t;
+        }
+        wave_sync();
+        blk += (long long)rows * 64;
     }
-    if (lane < s.W2) {
-        real t = 0;
-        for (int g = 0; g < s.G2; ++g) t += red[64 + g * s.W2 + lane];
-        out[64 + lane] = t;
-    }
-    wave_sync();
 }
 
 // A tile of class R if the shape fits it, else the product runs from the
@@ -492,14 +495,14 @@ struct ColProd {
     SPK_DEV void load(const real* t, const ColShape& sh) {
         tile = t;
         s = sh;
-        fit = sh.rows1 <= R && sh.rows2 <= R / 4;
+        fit = sh.O <= 128 && sh.rows1 <= R && sh.rows2 <= R / 4;
         col_load(T, t, sh);  // unconditional (see col_load); unused when !fit
     }
     // staged form: the tile from LDS (st) once its copy has landed
     SPK_DEV void take(const real* t, const ColShape& sh, const real* st) {
         tile = t;
         s = sh;
-        fit = sh.rows1 <= R && sh.rows2 <= R / 4;
+        fit = sh.O <= 128 && sh.rows1 <= R && sh.rows2 <= R / 4;
         if (fit) col_take(T, st, sh);
     }
     // kPadded: v is zero from K up to kVecPad entries (see col_apply)
@@ -540,6 +543,14 @@ SPK_DEV void soc_moreau_coef(real nw2, real vt, real& cw, real& ct) {
         cw = real(1) - a / nw;
         ct = vt - a;
     }
+}
+
+// Entry r of the translation a of Prop. 1 for an SOC block of length len:
+// the stored per-block vector with linear cost terms, else (0, .., 1/2, -1/2).
+template <typename real>
+SPK_DEV real soc_shift_at(const real* a, int r, int len) {
+    if (a) return a[r];
+    return r == len - 2 ? real(0.5) : (r == len - 1 ? real(-0.5) : real(0));
 }
 
 // What the dual-block updates of one node read (LDS) and where they write.
@@ -657,22 +668,27 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
     const int nx = P->nx, m = P->m;
     const real alpha = P->alpha, ialpha = real(1) / alpha;
     const long long off = P->e_soc + (long long)(j - 1) * (m + 2);
+    const real* aj = P->sa ? P->sa + (long long)(j - 1) * (m + 2) : nullptr;
+    // the edge's cost square roots: its own, or the shared ones staged in LDS
+    const real* qe = P->qh_e ? P->qh_e + (long long)j * nx : nullptr;
+    const real* re = P->rh_e ? P->rh_e + (long long)j * P->nu : nullptr;
+    auto qh = [&](int r) { return qe ? gm(qe)[r] : V.C.qh[r]; };
+    auto rh = [&](int r) { return re ? gm(re)[r] : V.C.rh[r]; };
     real nw2 = 0;
     for (int r = lane; r < m + 2; r += 64) {
         real wn, wo;
         if (r < nx) {
-            wn = V.C.qh[r] * V.xn[r];
-            wo = V.C.qh[r] * V.xo[r];
+            wn = qh(r) * V.xn[r];
+            wo = qh(r) * V.xo[r];
         } else if (r < m) {
-            wn = V.C.rh[r - nx] * V.un[r - nx];
-            wo = V.C.rh[r - nx] * V.uo[r - nx];
+            wn = rh(r - nx) * V.un[r - nx];
+            wo = rh(r - nx) * V.uo[r - nx];
         } else {
             wn = real(0.5) * tn;
             wo = real(0.5) * tv;
         }
         real eb = es[r] + alpha * (real(2) * wn - wo);
-        if (r == m) eb -= real(0.5) * alpha;  // v = etabar - alpha a
-        if (r == m + 1) eb += real(0.5) * alpha;
+        eb -= alpha * soc_shift_at(aj, r, m + 2);  // v = etabar - alpha a
         V.blk[r] = eb;
         V.dblk[r] = wo - wn;
         if (r <= m) nw2 += eb * eb;
@@ -690,8 +706,8 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
     }
     if (check) {
         wave_sync();
-        for (int r = lane; r < nx; r += 64) V.lxw[r] += V.C.qh[r] * V.dblk[r];
-        for (int r = lane; r < P->nu; r += 64) V.luw[r] += V.C.rh[r] * V.dblk[nx + r];
+        for (int r = lane; r < nx; r += 64) V.lxw[r] += qh(r) * V.dblk[r];
+        for (int r = lane; r < P->nu; r += 64) V.luw[r] += rh(r) * V.dblk[nx + r];
         if (lane == 0) r1 = nmax(r1, fabs((tv - tn) * ialpha - real(0.5) * (V.dblk[m] + V.dblk[m + 1])));
     }
 }
@@ -748,19 +764,21 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
         }
     } else {
         const long long off = P->e_socN + lf * (nx + 2);
+        const real* aj = P->saN ? P->saN + lf * (nx + 2) : nullptr;
+        const real* qe = P->qnh_l ? P->qnh_l + lf * nx : nullptr;
+        auto qnh = [&](int r) { return qe ? gm(qe)[r] : V.C.qnh[r]; };
         real nw2 = 0;
         for (int r = lane; r < nx + 2; r += 64) {
             real wn, wo;
             if (r < nx) {
-                wn = V.C.qnh[r] * V.xn[r];
-                wo = V.C.qnh[r] * V.xo[r];
+                wn = qnh(r) * V.xn[r];
+                wo = qnh(r) * V.xo[r];
             } else {
                 wn = real(0.5) * sn;
                 wo = real(0.5) * sv;
             }
             real eb = es[r] + alpha * (real(2) * wn - wo);
-            if (r == nx) eb -= real(0.5) * alpha;
-            if (r == nx + 1) eb += real(0.5) * alpha;
+            eb -= alpha * soc_shift_at(aj, r, nx + 2);
             V.blk[r] = eb;
             V.dblk[r] = wo - wn;
             if (r <= nx) nw2 += eb * eb;
@@ -778,7 +796,7 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
         }
         if (check) {
             wave_sync();
-            for (int r = lane; r < nx; r += 64) V.lxw[r] += V.C.qnh[r] * V.dblk[r];
+            for (int r = lane; r < nx; r += 64) V.lxw[r] += qnh(r) * V.dblk[r];
             if (lane == 0) r1 = nmax(r1, fabs((sv - sn) * ialpha - real(0.5) * (V.dblk[nx] + V.dblk[nx + 1])));
         }
     }
@@ -862,15 +880,26 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         // of every child edge (Sec. 4.4)
         for (int r = lane; r < nx; r += 64) {
             real s = 0;
-            for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + r];
-            real lt = C.gx[r] * ec[r] + C.qh[r] * s;
+            if (P->qh_e) {  // each child edge's own Q^1/2
+                for (int q = 0; q < k; ++q) s += gm(P->qh_e)[(long long)(fc + q) * nx + r] * soc[q * (m + 2) + r];
+            } else {
+                for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + r];
+                s *= C.qh[r];
+            }
+            real lt = C.gx[r] * ec[r] + s;
             if (P->has_ball) lt += C.gb[r] * ec[nbox + r];
             xb[r] = sx[r] - alpha * lt;
         }
         for (int r = lane; r < nu; r += 64) {
             real s = 0;
-            for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + nx + r];
-            const real lt = C.gu[r] * ec[nx + r] + C.rh[r] * s;
+            if (P->rh_e) {
+                for (int q = 0; q < k; ++q)
+                    s += gm(P->rh_e)[(long long)(fc + q) * nu + r] * soc[q * (m + 2) + nx + r];
+            } else {
+                for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + nx + r];
+                s *= C.rh[r];
+            }
+            const real lt = C.gu[r] * ec[nx + r] + s;
             ub[r] = su[r] - alpha * lt;
         }
         // S2 projection (Sec. 4.3) of (y^v, tau^[v], s^[v]) after the
@@ -949,7 +978,7 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         const real* ss = st + off[2];
         const real* spc = st + off[3];
         for (int r = lane; r < nx; r += 64) {
-            real lt = C.gxN[r] * sc[r] + C.qnh[r] * ss[r];
+            real lt = C.gxN[r] * sc[r] + (P->qnh_l ? gm(P->qnh_l)[lf * nx + r] : C.qnh[r]) * ss[r];
             if (P->has_ballN) lt += C.gbN[r] * sc[nx + r];
             real h = -(sx[r] - alpha * lt);
             if (P->affine) h += spc[r];
@@ -1302,11 +1331,11 @@ SPK_DEV void lgkm_wait() {
 
 // The tile's own lane groups to LDS, in the same layout (block 2, or one
 // group after block 1 when there is none, follows block 1).  Nothing is
-// copied when the shape does not fit class R.
+// copied when the shape does not fit class R (or has more than two blocks).
 template <typename real, int R>
 SPK_DEV void col_dma(const real* __restrict__ tile, const ColShape& s, real* st) {
     constexpr int V = 16 / (int)sizeof(real);
-    if (s.rows1 > R || s.rows2 > R / 4) return;
+    if (s.O > 128 || s.rows1 > R || s.rows2 > R / 4) return;
     const int G = s.rows1 / V + (s.rows2 > 0 ? s.rows2 / V : 1);
     const unsigned voff = (unsigned)lane_id() * 16;
     const char* t = reinterpret_cast<const char*>(tile);
@@ -1715,7 +1744,9 @@ __global__ __launch_bounds__(kHookWG) void k_apply_L(const ProbDev<real>* __rest
             const real tau = z[P->z_tau + j - 1];
             real* o = eta + P->e_soc + (long long)(j - 1) * (m + 2);
             for (int r = t; r < m + 2; r += kHookWG)
-                o[r] = r < nx ? P->qh[r] * x[r] : (r < m ? P->rh[r - nx] * u[r - nx] : real(0.5) * tau);
+                o[r] = r < nx ? (P->qh_e ? P->qh_e[(long long)j * nx + r] : P->qh[r]) * x[r]
+                              : (r < m ? (P->rh_e ? P->rh_e[(long long)j * nu + r - nx] : P->rh[r - nx]) * u[r - nx]
+                                       : real(0.5) * tau);
         }
     } else {
         const long long lf = v - P->n_nl;
@@ -1723,7 +1754,8 @@ __global__ __launch_bounds__(kHookWG) void k_apply_L(const ProbDev<real>* __rest
             eta[P->e_cN + lf * P->ncN + r] = r < nx ? P->gxN[r] * x[r] : P->gbN[r - nx] * x[r - nx];
         const real s = z[P->z_s + v - 1];
         for (int r = t; r < nx + 2; r += kHookWG)
-            eta[P->e_socN + lf * (nx + 2) + r] = r < nx ? P->qnh[r] * x[r] : real(0.5) * s;
+            eta[P->e_socN + lf * (nx + 2) + r] =
+                r < nx ? (P->qnh_l ? P->qnh_l[lf * nx + r] : P->qnh[r]) * x[r] : real(0.5) * s;
     }
 }
 
@@ -1739,15 +1771,19 @@ __global__ __launch_bounds__(kHookWG) void k_apply_Lt(const ProbDev<real>* __res
         const real* ec = eta + P->e_c + (long long)v * P->nc;
         for (int r = t; r < nx; r += kHookWG) {
             real s = 0;
-            for (int q = 0; q < k; ++q) s += eta[P->e_soc + (long long)(fc + q - 1) * (m + 2) + r];
-            real w = P->gx[r] * ec[r] + P->qh[r] * s;
+            for (int q = 0; q < k; ++q)
+                s += (P->qh_e ? P->qh_e[(long long)(fc + q) * nx + r] : P->qh[r]) *
+                     eta[P->e_soc + (long long)(fc + q - 1) * (m + 2) + r];
+            real w = P->gx[r] * ec[r] + s;
             if (P->has_ball) w += P->gb[r] * ec[nbox + r];
             x[r] = w;
         }
         for (int r = t; r < nu; r += kHookWG) {
             real s = 0;
-            for (int q = 0; q < k; ++q) s += eta[P->e_soc + (long long)(fc + q - 1) * (m + 2) + nx + r];
-            z[P->z_u + (long long)v * nu + r] = P->gu[r] * ec[nx + r] + P->rh[r] * s;
+            for (int q = 0; q < k; ++q)
+                s += (P->rh_e ? P->rh_e[(long long)(fc + q) * nu + r] : P->rh[r]) *
+                     eta[P->e_soc + (long long)(fc + q - 1) * (m + 2) + nx + r];
+            z[P->z_u + (long long)v * nu + r] = P->gu[r] * ec[nx + r] + s;
         }
         const long long yo = P->y_off[v];
         const real es = eta[P->e_s + v];
@@ -1769,7 +1805,7 @@ __global__ __launch_bounds__(kHookWG) void k_apply_Lt(const ProbDev<real>* __res
         const real* ecN = eta + P->e_cN + lf * P->ncN;
         const real* esN = eta + P->e_socN + lf * (nx + 2);
         for (int r = t; r < nx; r += kHookWG) {
-            real w = P->gxN[r] * ecN[r] + P->qnh[r] * esN[r];
+            real w = P->gxN[r] * ecN[r] + (P->qnh_l ? P->qnh_l[lf * nx + r] : P->qnh[r]) * esN[r];
             if (P->has_ballN) w += P->gbN[r] * ecN[nx + r];
             x[r] = w;
         }
@@ -1785,20 +1821,19 @@ __global__ __launch_bounds__(kHookWG) void k_prox_gconj(const ProbDev<real>* __r
     const int v = blockIdx.x, t = threadIdx.x;
     const int nx = P->nx, m = P->m, nbox = P->nbox;
     const real alpha = P->alpha;
-    auto soc = [&](long long off, int len) {
+    // v = w - alpha a, eta = v - proj_SOC(v) (a: the block's translation)
+    auto soc = [&](long long off, int len, const real* a) {
         real nw2 = 0;
         for (int r = t; r < len - 1; r += kHookWG) {
-            real e = w[off + r];
-            if (r == len - 2) e -= real(0.5) * alpha;
+            const real e = w[off + r] - alpha * soc_shift_at(a, r, len);
             nw2 += e * e;
         }
         nw2 = block_sum<kHookWG>(nw2, red);
-        const real vt = w[off + len - 1] + real(0.5) * alpha;
+        const real vt = w[off + len - 1] - alpha * soc_shift_at(a, len - 1, len);
         real cw, ct;
         soc_moreau_coef(nw2, vt, cw, ct);
         for (int r = t; r < len; r += kHookWG) {
-            real e = w[off + r];
-            if (r == len - 2) e -= real(0.5) * alpha;
+            const real e = w[off + r] - alpha * soc_shift_at(a, r, len);
             eta[off + r] = r < len - 1 ? e * cw : ct;
         }
     };
@@ -1826,11 +1861,13 @@ __global__ __launch_bounds__(kHookWG) void k_prox_gconj(const ProbDev<real>* __r
             eta[P->e_s + v] = e < 0 ? e : real(0);
         }
         ballbox(P->e_c + (long long)v * P->nc, nbox, P->nc, P->lo, P->hi, P->ball_r);
-        for (int q = 0; q < k; ++q) soc(P->e_soc + (long long)(fc + q - 1) * (m + 2), m + 2);
+        for (int q = 0; q < k; ++q)
+            soc(P->e_soc + (long long)(fc + q - 1) * (m + 2), m + 2,
+                P->sa ? P->sa + (long long)(fc + q - 1) * (m + 2) : nullptr);
     } else {
         const long long lf = v - P->n_nl;
         ballbox(P->e_cN + lf * P->ncN, nx, P->ncN, P->loN, P->hiN, P->ballN_r);
-        soc(P->e_socN + lf * (nx + 2), nx + 2);
+        soc(P->e_socN + lf * (nx + 2), nx + 2, P->saN ? P->saN + lf * (nx + 2) : nullptr);
     }
 }
 

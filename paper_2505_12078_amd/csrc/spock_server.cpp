@@ -33,7 +33,7 @@ struct SrvTree {
     int64_t id = 0;
     int n = 0, nx = 0, nu = 0, n_nl = 0;
     std::vector<int32_t> parent;
-    std::vector<double> prob, A, B, c, Q, R, QN, xlo, xhi, ulo, uhi, xNlo, xNhi, gamma;
+    std::vector<double> prob, A, B, c, Q, R, QN, xlo, xhi, ulo, uhi, xNlo, xNhi, gamma, q, r, qN, Qe, Re, QNl;
     double x_ball = 0, xN_ball = 0;
     size_t footprint = 0;
     spock_problem* p = nullptr;  // resident when non-null
@@ -51,9 +51,12 @@ struct SrvTree {
         d.A = A.data();
         d.B = B.data();
         d.c = c.empty() ? nullptr : c.data();
-        d.Q_diag = Q.data();
-        d.R_diag = R.data();
-        d.QN_diag = QN.data();
+        d.Q_diag = Q.empty() ? nullptr : Q.data();
+        d.R_diag = R.empty() ? nullptr : R.data();
+        d.QN_diag = QN.empty() ? nullptr : QN.data();
+        d.Q_edge = Qe.empty() ? nullptr : Qe.data();
+        d.R_edge = Re.empty() ? nullptr : Re.data();
+        d.QN_leaf = QNl.empty() ? nullptr : QNl.data();
         d.x_lo = xlo.data();
         d.x_hi = xhi.data();
         d.u_lo = ulo.data();
@@ -63,6 +66,9 @@ struct SrvTree {
         d.x_ball = x_ball;
         d.xN_ball = xN_ball;
         d.gamma = gamma.data();
+        d.q = q.empty() ? nullptr : q.data();
+        d.r = r.empty() ? nullptr : r.data();
+        d.qN = qN.empty() ? nullptr : qN.data();
         return d;
     }
 };
@@ -485,9 +491,15 @@ int32_t spock_server_add_tree(spock_server* s, const spock_problem_desc* d, int6
     T.A.assign(d->A, d->A + n * nx * nx);
     T.B.assign(d->B, d->B + n * nx * nu);
     if (d->c) T.c.assign(d->c, d->c + n * nx);
-    T.Q.assign(d->Q_diag, d->Q_diag + nx);
-    T.R.assign(d->R_diag, d->R_diag + nu);
-    T.QN.assign(d->QN_diag, d->QN_diag + nx);
+    if (d->q) T.q.assign(d->q, d->q + n * nx);
+    if (d->r) T.r.assign(d->r, d->r + n * nu);
+    if (d->qN) T.qN.assign(d->qN, d->qN + n * nx);
+    if (d->Q_diag) T.Q.assign(d->Q_diag, d->Q_diag + nx);
+    if (d->R_diag) T.R.assign(d->R_diag, d->R_diag + nu);
+    if (d->QN_diag) T.QN.assign(d->QN_diag, d->QN_diag + nx);
+    if (d->Q_edge) T.Qe.assign(d->Q_edge, d->Q_edge + n * nx);
+    if (d->R_edge) T.Re.assign(d->R_edge, d->R_edge + n * nu);
+    if (d->QN_leaf) T.QNl.assign(d->QN_leaf, d->QN_leaf + n * nx);
     T.xlo.assign(d->x_lo, d->x_lo + nx);
     T.xhi.assign(d->x_hi, d->x_hi + nx);
     T.ulo.assign(d->u_lo, d->u_lo + nu);

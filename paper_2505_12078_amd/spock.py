@@ -33,7 +33,8 @@ class ProblemDesc(C.Structure):
                 ("nu", C.c_int32), ("A", _dp), ("B", _dp), ("c", _dp), ("Q_diag", _dp), ("R_diag", _dp),
                 ("QN_diag", _dp), ("x_lo", _dp), ("x_hi", _dp), ("u_lo", _dp), ("u_hi", _dp),
                 ("xN_lo", _dp), ("xN_hi", _dp), ("x_ball", C.c_double), ("xN_ball", C.c_double),
-                ("gamma", _dp)]
+                ("gamma", _dp), ("q", _dp), ("r", _dp), ("qN", _dp), ("Q_edge", _dp), ("R_edge", _dp),
+                ("QN_leaf", _dp)]
 
 
 class Settings(C.Structure):
@@ -200,6 +201,9 @@ class _Desc:
             "Q": f("Q"), "R": f("R"), "QN": f("QN"), "x_lo": f("x_lo"), "x_hi": f("x_hi"),
             "u_lo": f("u_lo"), "u_hi": f("u_hi"), "xN_lo": f("xN_lo"), "xN_hi": f("xN_hi"),
             "gamma": f("gamma"),
+            "q": None if prob.get("q") is None else f("q"),
+            "r": None if prob.get("r") is None else f("r"),
+            "qN": None if prob.get("qN") is None else f("qN"),
         }
         k = self.keep
         self.desc = ProblemDesc(
@@ -208,7 +212,12 @@ class _Desc:
             Q_diag=_ptr(k["Q"]), R_diag=_ptr(k["R"]), QN_diag=_ptr(k["QN"]), x_lo=_ptr(k["x_lo"]),
             x_hi=_ptr(k["x_hi"]), u_lo=_ptr(k["u_lo"]), u_hi=_ptr(k["u_hi"]), xN_lo=_ptr(k["xN_lo"]),
             xN_hi=_ptr(k["xN_hi"]), x_ball=float(prob["x_ball"]), xN_ball=float(prob["xN_ball"]),
-            gamma=_ptr(k["gamma"]))
+            gamma=_ptr(k["gamma"]), q=_ptr(k["q"]), r=_ptr(k["r"]), qN=_ptr(k["qN"]))
+        # cost diagonals given per edge / per leaf (one row per node)
+        for key, shared, per in (("Q", "Q_diag", "Q_edge"), ("R", "R_diag", "R_edge"), ("QN", "QN_diag", "QN_leaf")):
+            if k[key].ndim == 2:
+                setattr(self.desc, shared, None)
+                setattr(self.desc, per, _ptr(k[key]))
 
 
 def footprint(prob, settings=None):

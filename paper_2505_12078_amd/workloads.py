@@ -17,7 +17,8 @@ A problem is a plain dict of NumPy arrays (the "problem description"):
     B        float64[n,nx,nu]  (entry 0 unused)
     c        float64[n,nx] or None
     Q, R     float64[nx], float64[nu]   diagonal of the edge stage cost
-    QN       float64[nx]   diagonal of the leaf cost
+             (or [n,nx], [n,nu]: row j for the edge into node j)
+    QN       float64[nx]   diagonal of the leaf cost (or [n,nx]: leaf rows)
     q, r, qN float64[n,nx], [n,nu], [n,nx] (optional) linear cost terms:
                            q^j, r^j on x, u of the parent in the edge into j,
                            qN^j at leaf j
@@ -168,11 +169,12 @@ def _guard_x0(x0, parent, A, x_hi, x_ball, xN_hi, xN_ball, n_nl, margin=0.9):
 
 def make_problem(parent, nx, nu, rng, *, prob_kind="uniform", gamma=0.95,
                  x_box=5.0, u_box=1.0, x_ball=0.0, q=1.0, r=0.1, qn=1.0,
-                 affine=False, linear=False, x0_range=2.0, name="custom"):
+                 affine=False, linear=False, edge_costs=False, x0_range=2.0, name="custom"):
     """Draw a full problem on the given tree (draw order: probabilities, then
     A^i and B^i for i = 1..n-1, then x0, then the optional affine terms, then
     the optional linear cost terms q^j, r^j of the edge into j and qN^j of
-    leaf j, each N(0, 0.25))."""
+    leaf j, each N(0, 0.25)), then the optional per-edge and per-leaf cost
+    diagonals Q^j = q u, R^j = r u, Q_N^j = qn u with u ~ U[0.5, 2] entrywise)."""
     parent = np.asarray(parent, dtype=np.int32)
     n = len(parent)
     n_nl = int(np.sum(np.bincount(parent[1:], minlength=n) > 0))
@@ -195,10 +197,15 @@ def make_problem(parent, nx, nu, rng, *, prob_kind="uniform", gamma=0.95,
         lin["qN"] = 0.5 * rng.standard_normal((n, nx))
         for v in lin.values():
             v[0] = 0.0  # node 0 owns no edge and is not a leaf
+    Qc, Rc, QNc = np.full(nx, float(q)), np.full(nu, float(r)), np.full(nx, float(qn))
+    if edge_costs:
+        Qc = float(q) * rng.uniform(0.5, 2.0, size=(n, nx))
+        Rc = float(r) * rng.uniform(0.5, 2.0, size=(n, nu))
+        QNc = float(qn) * rng.uniform(0.5, 2.0, size=(n, nx))
     return dict(
         **lin,
         name=name, parent=parent, prob=prob, nx=int(nx), nu=int(nu), A=A, B=B, c=c,
-        Q=np.full(nx, float(q)), R=np.full(nu, float(r)), QN=np.full(nx, float(qn)),
+        Q=Qc, R=Rc, QN=QNc,
         x_lo=-x_hi.copy(), x_hi=x_hi.copy(), u_lo=-u_hi.copy(), u_hi=u_hi.copy(),
         xN_lo=-x_hi.copy(), xN_hi=x_hi.copy(),
         x_ball=float(x_ball), xN_ball=float(x_ball),
@@ -256,7 +263,7 @@ def batch_problem(k, seed=3):
 
 
 def random_ragged_problem(seed, N=4, nx=3, nu=2, max_children=3, ball=True,
-                          affine=False, gamma=None, linear=False):
+                          affine=False, gamma=None, linear=False, edge_costs=False):
     """Irregular tree (each non-leaf has 1..max_children children), for tests."""
     rng = np.random.default_rng(np.random.SeedSequence([977, int(seed)]))
     counts = []
@@ -271,7 +278,7 @@ def random_ragged_problem(seed, N=4, nx=3, nu=2, max_children=3, ball=True,
     if gamma is None:
         gamma = rng.uniform(0.05, 1.0, size=n_nl)
     return make_problem(parent, nx, nu, rng, prob_kind="dirichlet", gamma=gamma,
-                        x_ball=(6.0 if ball else 0.0), affine=affine, linear=linear,
+                        x_ball=(6.0 if ball else 0.0), affine=affine, linear=linear, edge_costs=edge_costs,
                         name="ragged%d" % seed)
 
 

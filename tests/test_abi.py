@@ -103,11 +103,12 @@ def test_degenerate_and_maximum_trees(lib):
     assert "two nodes" in _bad(one)
     # nx = 0
     assert "nx" in _bad(p, nx=0)
-    # the widest state and input: nx + nu = 128 is accepted, 129 is not
+    # the widest state and input: 256 each is accepted, 257 is not
     par, _ = W.tree_from_branching([2, 1])
     assert S.footprint(W.make_problem(par, 96, 32, rng, name="m128")) > 0
-    assert "128" in _bad(W.make_problem(par, 97, 32, rng, name="m129"))
-    assert "128" in _bad(W.make_problem(par, 150, 10, rng, name="nx150"))
+    assert S.footprint(W.make_problem(par, 150, 50, rng, name="m200")) > 0
+    assert "256" in _bad(W.make_problem(par, 257, 32, rng, name="nx257"))
+    assert "256" in _bad(W.make_problem(par, 20, 257, rng, name="nu257"))
     # the longest horizon: 512 stages (a single scenario) is accepted, 513 are not
     par, _ = W.tree_from_branching([1] * 511)
     ok = W.make_problem(par, 2, 1, rng, name="chain511")
@@ -125,3 +126,4 @@ def test_supermann_settings_are_validated(lib):
         with pytest.raises(S.SpockError) as e:
             S.footprint(p, S.default_settings(**bad))
         assert e.value.code == S.SPOCK_E_INVALID
+

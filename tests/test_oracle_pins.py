@@ -277,10 +277,11 @@ def _dense_L(D):
     return M
 
 
-@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("seed", range(6))
 def test_L_adjoint_and_norm(seed):
-    prob = W.random_ragged_problem(seed, N=3, nx=3, nu=2, ball=(seed % 2 == 0))
-    D = O.Data(prob, precondition=(seed < 2))
+    # seeds 4, 5: per-edge stage costs and per-leaf terminal costs
+    prob = W.random_ragged_problem(seed, N=3, nx=3, nu=2, ball=(seed % 2 == 0), edge_costs=(seed >= 4))
+    D = O.Data(prob, precondition=(seed < 2 or seed == 4))
     Y = D.layout
     rng = np.random.default_rng(seed)
     z, e = rng.standard_normal(Y.nz), rng.standard_normal(Y.neta)
