@@ -429,6 +429,22 @@ def _profile_pass(steps):
     P.close()
 
 
+def _profile_supermann_pass(iters):
+    """What a profiler should see for the SuperMann outer method: `iters`
+    float64 SuperMann iterations on the large tree (CP step kernels, k_combo,
+    k_dots / k_dots_final, k_apply_L)."""
+    import torch
+
+    from paper_2505_12078_amd import spock as S
+    from paper_2505_12078_amd import workloads as W
+    torch.cuda.set_device(0)
+    prob = W.config_problem(2)
+    with S.Problem(prob, S.default_settings(eps=1e-12, max_iters=iters, method=S.SUPERMANN)) as P:
+        r = P.solve(prob["x0"])
+    print(json.dumps({"iters": r["iters"], "T": r["n_T"], "K0": r["n_K0"], "K1": r["n_K1"], "K2": r["n_K2"],
+                      "seconds": r["t_solve_s"]}))
+
+
 def _profile_batch_pass(n_problems, steps, node_wg):
     """What a profiler should see for the batched workload: `steps` float32
     batched steps of its 256 members at `node_wg` threads per node workgroup
@@ -557,6 +573,8 @@ def main():
                     help="short run for rocprofv3: K steps per precision and a 1 GiB device copy")
     ap.add_argument("--profile-batch", action="store_true",
                     help="short run for rocprofv3: K float32 batched steps of the batched workload and a 1 GiB copy")
+    ap.add_argument("--profile-supermann", action="store_true",
+                    help="short run for rocprofv3: K float64 SuperMann iterations on the large tree")
     ap.add_argument("--batch-node-wg", type=int, default=256)
     ap.add_argument("--traffic-out", default=None, help="output of --summarize-counters (default profiles/traffic.json)")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "TRACE_DIR", "PROFILE_JSON"),
@@ -567,6 +585,9 @@ def main():
         return
     if args.profile_batch:
         _profile_batch_pass(args.batch_problems, args.steps, args.batch_node_wg)
+        return
+    if args.profile_supermann:
+        _profile_supermann_pass(args.steps)
         return
     if args.cpu_baseline_only:
         _cpu_baseline_only(args.cpu_steps)
