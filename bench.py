@@ -100,6 +100,31 @@ def cpu_baseline(steps):
     return out
 
 
+def cpu_baseline_case_study(case_study, instances=3, steps=2):
+    """CPU baseline of the case-study leg: the oracle's seconds per CP step on
+    the first accepted instances (a bounded sample, float64 NumPy as it
+    stands), and that times the GPU's iteration count, the oracle's estimated
+    time to the same tolerance."""
+    import numpy as np
+
+    from oracle import spock_oracle as O
+    from paper_2505_12078_amd import workloads as W
+    est = []
+    for r in [r for r in case_study["rows"] if "seconds" in r][:instances]:
+        prob = W.benchmark_problem(r["k"], nu_max=128)
+        D = O.Data(prob)
+        F = O.Offline(D)
+        alpha = O.step_size(D)
+        z, e = np.zeros(D.layout.nz), np.zeros(D.layout.neta)
+        t = time.perf_counter()
+        for _ in range(steps):
+            z, e = O.cp_step(D, F, z, e, alpha)
+        sec = (time.perf_counter() - t) / steps
+        est.append({"k": r["k"], "oracle_s_per_step": round(sec, 4), "oracle_est_seconds": round(sec * r["iters"], 1),
+                    "gpu_seconds": r["seconds"], "ratio": round(sec * r["iters"] / max(r["seconds"], 1e-9), 1)})
+    return est
+
+
 def _cpu_baseline_only(steps):
     import numpy as np
 
@@ -301,6 +326,43 @@ def delay_bench(S, W, ns=(2, 4, 8), steps=40):
                                  "GB_s": round(by / dt / 1e9, 1)}
             out.append(row)
             print("delay tree: %s" % row, file=sys.stderr, flush=True)
+    return out
+
+
+def case_study_bench(S, W, instances=10, eps=1e-3, max_iters=20000):
+    """The benchmark case study's random problems (dense event-dependent Q, R;
+    n_u capped at 128 so that nx = 2 n_u fits the library): for instances
+    0..K-1, setup time, device footprint, and the time, iterations and
+    outcome of a mixed-precision solve from zero to rel_res eps (the paper
+    recommends float for tolerances around 1e-3).  Its CPU baseline is
+    cpu_baseline_case_study."""
+    import numpy as np
+    import torch
+    rows = []
+    for k in range(instances):
+        prob = W.benchmark_problem(k, nu_max=128)
+        row = {"k": k, "name": prob["name"], "n_v": int(prob["n_v"]), "nodes": len(prob["parent"]),
+               "nx": int(prob["nx"]), "nu": int(prob["nu"])}
+        try:
+            row["footprint_bytes"] = S.footprint(prob, S.default_settings(precision=S.MIXED))
+            t = time.perf_counter()
+            with S.Problem(prob, S.default_settings(eps=eps, precision=S.MIXED, max_iters=max_iters)) as P:
+                row["setup_s"] = round(time.perf_counter() - t, 3)
+                r = P.solve(prob["x0"])
+                torch.cuda.synchronize()
+                row.update(seconds=round(r["t_solve_s"], 4), iters=r["iters"], rel_res=r["rel_res"],
+                           converged=r["code"] == S.SPOCK_OK, s0=r["s0"])
+        except S.SpockError as e:
+            row["error"] = str(e)
+        rows.append(row)
+        print("case study instance: %s" % row, file=sys.stderr, flush=True)
+    done = [r for r in rows if "seconds" in r]
+    out = {"eps": eps, "precision": "mixed", "max_iters": max_iters, "instances": len(rows),
+           "accepted": len(done), "converged": sum(1 for r in done if r["converged"]),
+           "median_seconds": float(np.median([r["seconds"] for r in done])) if done else None,
+           "max_seconds": max((r["seconds"] for r in done), default=None),
+           "median_footprint_MB": float(np.median([r["footprint_bytes"] for r in done]) / 2 ** 20) if done else None,
+           "rows": rows}
     return out
 
 
@@ -565,6 +627,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-small", action="store_true", help="skip the tiny and medium trees")
     ap.add_argument("--no-delay", action="store_true", help="skip the networked-control delay trees")
+    ap.add_argument("--case-study", type=int, default=0,
+                    help="instances of the benchmark case study's random problems to solve (0: skip)")
+    ap.add_argument("--case-study-only", action="store_true", help="run only the case-study leg (one JSON line)")
     ap.add_argument("--batch-problems", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--no-batch-solve", action="store_true")
@@ -599,6 +664,17 @@ def main():
         print("bench.py measures one GPU only: the CP step of one scenario tree runs on one MI355X "
               "(sharding a tree by subtrees across GPUs is designed, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.case_study_only:
+        import torch
+
+        from paper_2505_12078_amd import spock as S
+        from paper_2505_12078_amd import workloads as W
+        torch.cuda.set_device(0)
+        cs = case_study_bench(S, W, instances=args.case_study)
+        if not args.no_cpu:
+            cs["cpu_baseline"] = cpu_baseline_case_study(cs)
+        print(json.dumps({"case_study": cs}))
+        return
 
     batch_in = None
     if not args.no_batch:
@@ -666,6 +742,7 @@ def main():
     P.close()
     small = None if args.no_small else small_trees_bench(S, W)
     delay = None if args.no_delay else delay_bench(S, W)
+    case_study = case_study_bench(S, W, instances=args.case_study) if args.case_study > 0 else None
     batched = None
     if batch_in is not None:
         batched = batch_bench(S, *batch_in, steps=args.batch_steps + (args.batch_steps & 1), warmup=6,
@@ -692,6 +769,8 @@ def main():
                                           seed=9)
             print("serve (capped budget): %s" % serve["capped"], file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
+    if case_study is not None and not args.no_cpu:
+        case_study["cpu_baseline"] = cpu_baseline_case_study(case_study)
     out = {
         "metric": METRIC, "value": round(v32, 2), "unit": "CP iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1000.0 / v32, 4), "higher_is_better": True,
@@ -701,6 +780,7 @@ def main():
                    "setup_s": round(t_setup, 3)},
         "fp64": {"iters_per_s": round(v64, 2), "ms_per_step": round(1000.0 / v64, 4)},
         "kernels": kt, "roofline": roofline, "time_to_tol": tol, "small_trees": small, "delay_trees": delay,
+        "case_study": case_study,
         "batched": batched,
         "serve": serve,
         "cpu_baseline": cpu,

@@ -108,6 +108,14 @@ typedef struct spock_problem_desc {
     const double* Q_edge;
     const double* R_edge;
     const double* QN_leaf;
+    /* Optional dense per-edge / per-leaf cost matrices (symmetric positive
+     * definite; Prop. 1 with S = I): [n][nx][nx], [n][nu][nu] (matrix j: the
+     * edge into node j; matrix 0 ignored) and [n][nx][nx] (leaf matrices).  A
+     * non-NULL array replaces the corresponding diagonal form.  The SOC block
+     * of an edge then carries Q^1/2 x (the symmetric square root). */
+    const double* Q_dense;
+    const double* R_dense;
+    const double* QN_dense;
 } spock_problem_desc;
 
 typedef struct spock_settings {
@@ -260,7 +268,7 @@ int32_t spock_prox_gconj(spock_problem* p, const double* w, double* eta_out, int
  *  xi (host, nullable, [2]) receives |xi1|_inf and |xi2|_inf of the step.
  * The kernels run on the handle's stream with the handle's device current,
  * and the call waits for them.  Scratch need, 256-byte aligned regions:
- * descriptor + w (n_nl nu + n (nx + nu) + n nx + n_nl nu) + 4 n + 16 bytes,
+ * descriptor + w (n_nl nu + n (nx + nu) + n nx + n_nl nu) + 4 n + 512 bytes,
  * w = 8 or 4; a problem that needs more fails with SPOCK_E_CAPACITY.  Every
  * call on one GPU shares that GPU's array and leaves its contents behind:
  * calls that overlap on one GPU (other streams or threads) race.

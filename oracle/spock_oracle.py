@@ -133,6 +133,16 @@ def avar_conic_data(p, gamma):
 # ----------------------------------------------------------------------------
 
 
+def cost_matrices(prob, key, n):
+    """The cost matrix of every node for prob[key] (Sec. 3.1): one shared
+    diagonal [d], one diagonal per node [n][d], or one dense matrix per node
+    [n][d][d] (row / matrix j: the edge into node j, or leaf j)."""
+    a = np.asarray(prob[key], float)
+    if a.ndim == 3:
+        return [a[j] for j in range(n)]
+    return [np.diag(a[j] if a.ndim == 2 else a) for j in range(n)]
+
+
 def _sym_sqrt(M):
     w, V = np.linalg.eigh(M)
     return (V * np.sqrt(np.maximum(w, 0.0))) @ V.T
@@ -151,13 +161,8 @@ class Data:
         self.nx, self.nu = nx, nu
         # stage costs Q^j, R^j of the edge into j and terminal costs Q_N^j of
         # leaf j (Sec. 3.1): one shared diagonal, or one row per node
-        Qa, Ra, QNa = (np.asarray(prob[k], float) for k in ("Q", "R", "QN"))
         n = T.n
-
-        def per_node(a):
-            return [np.diag(a[j] if a.ndim == 2 else a) for j in range(n)]
-
-        Qs, Rs, QNs = per_node(Qa), per_node(Ra), per_node(QNa)
+        Qs, Rs, QNs = (cost_matrices(prob, k, n) for k in ("Q", "R", "QN"))
         ball = float(prob["x_ball"]) > 0
         ballN = float(prob["xN_ball"]) > 0
         self.has_ball, self.has_ballN = ball, ballN
@@ -683,19 +688,18 @@ def nested_cost(prob, x, u):
     children of (stage cost on the edge, with its linear terms, + child value)."""
     T = Tree(prob["parent"], prob["prob"])
     n, nx, nu = T.n, int(prob["nx"]), int(prob["nu"])
-    # cost diagonals per node (the edge into j, or leaf j): shared or per row
-    Q, R, QN = (np.broadcast_to(np.asarray(prob[k], float), (n, d)) for k, d in (("Q", nx), ("R", nu),
-                                                                                 ("QN", nx)))
+    # cost matrices per node (the edge into j, or leaf j)
+    Q, R, QN = (cost_matrices(prob, k, n) for k in ("Q", "R", "QN"))
     q = np.zeros((n, nx)) if prob.get("q") is None else np.asarray(prob["q"], float)
     r = np.zeros((n, nu)) if prob.get("r") is None else np.asarray(prob["r"], float)
     qN = np.zeros((n, nx)) if prob.get("qN") is None else np.asarray(prob["qN"], float)
     val = np.zeros(T.n)
     for j in T.leaves:
-        val[j] = np.sum(QN[j] * x[j] ** 2) + qN[j] @ x[j]
+        val[j] = x[j] @ QN[j] @ x[j] + qN[j] @ x[j]
     for t in range(T.N - 1, -1, -1):
         for i in T.nodes(t):
             kids = T.ch[i]
-            Z = np.array([np.sum(Q[j] * x[i] ** 2) + np.sum(R[j] * u[i] ** 2) + q[j] @ x[i] + r[j] @ u[i] + val[j]
+            Z = np.array([x[i] @ Q[j] @ x[i] + u[i] @ R[j] @ u[i] + q[j] @ x[i] + r[j] @ u[i] + val[j]
                           for j in kids])
             val[i] = avar_ambiguity_form(Z, T.p[kids], float(prob["gamma"][i]))
     return float(val[0])
@@ -719,21 +723,20 @@ def risk_neutral_lq(prob):
     Returns (V*, x, u) with V* = x0^T P0 x0."""
     T = Tree(prob["parent"], prob["prob"])
     nx, nu = int(prob["nx"]), int(prob["nu"])
-    Qd, Rd, QNd = (np.broadcast_to(np.asarray(prob[k], float), (T.n, d)) for k, d in (("Q", nx), ("R", nu),
-                                                                                      ("QN", nx)))
+    Qd, Rd, QNd = (cost_matrices(prob, k, T.n) for k in ("Q", "R", "QN"))
     A, B = np.asarray(prob["A"]), np.asarray(prob["B"])
     Ph = [None] * T.n
     Kf = [None] * T.n
     for j in T.leaves:
-        Ph[j] = np.diag(QNd[j])
+        Ph[j] = QNd[j]
     for t in range(T.N - 1, -1, -1):
         for i in T.nodes(t):
             kids = T.ch[i]
             p = T.p[kids]
             # the stage cost of the edge into child j weighs with p_j
-            Huu = sum(pk * (np.diag(Rd[j]) + B[j].T @ Ph[j] @ B[j]) for pk, j in zip(p, kids))
+            Huu = sum(pk * (Rd[j] + B[j].T @ Ph[j] @ B[j]) for pk, j in zip(p, kids))
             Hux = sum(pk * B[j].T @ Ph[j] @ A[j] for pk, j in zip(p, kids))
-            Hxx = sum(pk * (np.diag(Qd[j]) + A[j].T @ Ph[j] @ A[j]) for pk, j in zip(p, kids))
+            Hxx = sum(pk * (Qd[j] + A[j].T @ Ph[j] @ A[j]) for pk, j in zip(p, kids))
             Kf[i] = -np.linalg.solve(Huu, Hux)
             Ph[i] = Hxx + Hux.T @ Kf[i]
     x = np.zeros((T.n, A.shape[1]))

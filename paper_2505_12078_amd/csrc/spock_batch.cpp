@@ -92,7 +92,7 @@ int32_t batch_chunk(spock_batch* b, int steps) {
 }
 
 int32_t read_all(spock_batch* b) {
-    HIP_TRY(hipMemcpyAsync(b->h_res, b->res, 2 * b->n * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+    HIP_TRY(hipMemcpyAsync(b->h_res, b->res, 2 * spk::kResSlots * b->n * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return SPOCK_OK;
@@ -115,8 +115,7 @@ int32_t batch_tick(spock_batch* b, std::vector<Member>& m, bool stall_exit) {
             spock_problem* p = b->probs[k];
             x.iters += ce;
             if (sizeof(real) == 4) x.iters32 += ce;
-            std::memcpy(&x.x1, &b->h_res[2 * k], 8);
-            std::memcpy(&x.x2, &b->h_res[2 * k + 1], 8);
+            res_reduce(b->h_res + 2 * spk::kResSlots * k, &x.x1, &x.x2);
             x.rel = rel_of(x.x1, x.x2, std::max(1.0, std::max(p->xi_ref[0], p->xi_ref[1])));
             if (!std::isfinite(x.rel)) {
                 x.status = SPOCK_E_DIVERGED;
@@ -194,7 +193,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
     const size_t o64 = take(sizeof(ProbDev<double>) * n), o32 = take(sizeof(ProbDev<float>) * n);
     const size_t ot = take(sizeof(int2) * b->n_tasks), oa = take(sizeof(int) * n);
     const size_t ont = take(sizeof(int2) * b->n_ntasks), oni = take(sizeof(int4) * b->n_ntasks);
-    const size_t orr = take(sizeof(unsigned long long) * 2 * n);
+    const size_t orr = take(sizeof(unsigned long long) * 2 * spk::kResSlots * n);
     b->bytes = off + 256;
     std::lock_guard<std::recursive_mutex> lock(hip_setup_mutex());
     hipError_t e = hipMalloc(&b->base, b->bytes);
@@ -216,7 +215,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
     };
     if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
         return bail(SPOCK_E_HIP, "batch stream");
-    if (hipHostMalloc((void**)&b->h_res, 2 * n * sizeof(unsigned long long), 0) != hipSuccess)
+    if (hipHostMalloc((void**)&b->h_res, 2 * spk::kResSlots * n * sizeof(unsigned long long), 0) != hipSuccess)
         return bail(SPOCK_E_HIP, "batch pinned buffer");
     std::vector<ProbDev<double>> h64(n);
     std::vector<ProbDev<float>> h32(n);
@@ -229,7 +228,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
         h64[k] = probs[k]->s64.h;
         h32[k] = probs[k]->s32.h;
         h64[k].active = h32[k].active = b->active + k;
-        h64[k].res = h32[k].res = b->res + 2 * k;
+        h64[k].res = h32[k].res = b->res + 2 * spk::kResSlots * k;
         for (int l = 0; l < probs[k]->n_leaf; ++l) tasks.push_back(make_int2(k, l));
         const spock_problem* q = probs[k];
         for (int v = 0; v < q->n_ntasks; ++v) {
@@ -251,7 +250,7 @@ int32_t spock_batch_create(spock_problem* const* probs, int32_t n, const spock_s
         e = hipMemcpy(b->ntasks, ntasks.data(), sizeof(int2) * ntasks.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->ninfo, ninfo.data(), sizeof(int4) * ninfo.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->active, b->h_active.data(), sizeof(int) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(b->res, 0, sizeof(unsigned long long) * 2 * n);
+    if (e == hipSuccess) e = hipMemset(b->res, 0, sizeof(unsigned long long) * 2 * spk::kResSlots * n);
     if (e != hipSuccess) return bail(SPOCK_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
     *out = b;
     return SPOCK_OK;

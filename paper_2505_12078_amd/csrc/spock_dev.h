@@ -23,6 +23,7 @@ struct ProbDev {
     int nx, nu, m;           // m = nx + nu
     int nc, ncN, nbox;       // constraint rows at non-leaf / leaf nodes, nbox = nx + nu
     int has_ball, has_ballN, affine, max_ch;
+    int stage_kids;          // nodes with at most this many children stage their per-child inputs in LDS
     real alpha, ball_r, ballN_r;
 
     // tree (breadth-first numbering, children contiguous)
@@ -80,6 +81,13 @@ struct ProbDev {
     const real* qh_e;
     const real* rh_e;
     const real* qnh_l;
+    // dense costs (null unless the costs are dense): the symmetric square
+    // roots H = Q^j^1/2 (nx x nx at j nx^2), R^j^1/2 (nu x nu at j nu^2) per
+    // edge and Q_N^j^1/2 per leaf (at (j - n_nl) nx^2); the cost rows of L are
+    // then H (qh o x) (qh, rh, qnh hold S^-1) and those of L* qh o (H w)
+    const real* Hq_e;
+    const real* Hr_e;
+    const real* HqN_l;
     const real* x0;          // scaled initial state
 
     // iterates, two copies each; a step reads copy `par` and writes `par ^ 1`
@@ -96,11 +104,18 @@ struct ProbDev {
     real* ub;                // ubar of non-leaf node i, nu
     int* cnt;                // backward arrival counters, per node
     const int* active;       // 0: this problem sits out the launch (batched form)
-    unsigned long long* res; // |xi1|_inf, |xi2|_inf as float64 bit patterns
+    unsigned long long* res; // kResSlots pairs (|xi1|_inf, |xi2|_inf) as float64 bit patterns:
+                             // a node wavefront records into the pair of its workgroup
+                             // (mod kResSlots); the residuals are the maxima over the pairs
 };
 
-// Children whose per-child inputs are staged in LDS; a wider node reads them
-// from global memory directly (same contiguous layout).
+// Residual slot pairs per problem: spreading the atomic maxima of thousands of
+// node wavefronts over many addresses keeps them from serializing on one.
+constexpr int kResSlots = 32;
+
+// Children whose per-child inputs are staged in LDS (at most; fewer when a
+// node's blocks are wide, so that a wavefront's LDS stays within 64 KiB); a
+// wider node reads them from global memory directly (same contiguous layout).
 constexpr int kStageKids = 16;
 // LDS scratch of one wavefront for cross-lane partial sums.
 constexpr int kRed = 128;

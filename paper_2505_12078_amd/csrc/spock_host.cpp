@@ -14,6 +14,8 @@
 #include <string>
 #include <thread>
 #include <vector>
+#include <unordered_map>
+#include <map>
 
 #include "../../include/spock.h"
 #include "spock_dev.h"
@@ -102,6 +104,64 @@ static void chol_inverse(int n, const double* L, double* inv) {
         }
 }
 
+// Eigen-decomposition A = V diag(w) V^T of a symmetric n x n matrix by cyclic
+// Jacobi rotations (V's columns are the eigenvectors).
+static void sym_eig(int n, const double* A, std::vector<double>& w, std::vector<double>& V) {
+    std::vector<double> a(A, A + (size_t)n * n);
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0, tot = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double v = a[(size_t)i * n + j] * a[(size_t)i * n + j];
+                tot += v;
+                if (i != j) off += v;
+            }
+        if (off <= 1e-32 * tot) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = a[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                const double app = a[(size_t)p * n + p], aqq = a[(size_t)q * n + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {  // columns p, q
+                    const double akp = a[(size_t)k * n + p], akq = a[(size_t)k * n + q];
+                    a[(size_t)k * n + p] = c * akp - sn * akq;
+                    a[(size_t)k * n + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // rows p, q
+                    const double apk = a[(size_t)p * n + k], aqk = a[(size_t)q * n + k];
+                    a[(size_t)p * n + k] = c * apk - sn * aqk;
+                    a[(size_t)q * n + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = c * vkp - sn * vkq;
+                    V[(size_t)k * n + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = a[(size_t)i * n + i];
+}
+
+// V diag(f(w)) V^T
+template <typename Fn>
+static std::vector<double> eig_fn(int n, const std::vector<double>& w, const std::vector<double>& V, Fn f) {
+    std::vector<double> out((size_t)n * n, 0.0);
+    for (int k = 0; k < n; ++k) {
+        const double fk = f(w[k]);
+        for (int i = 0; i < n; ++i) {
+            const double vik = V[(size_t)i * n + k] * fk;
+            for (int j = 0; j < n; ++j) out[(size_t)i * n + j] += vik * V[(size_t)j * n + k];
+        }
+    }
+    return out;
+}
+
 template <typename F>
 static void parallel_for(int n, F f) {
     unsigned hw = std::thread::hardware_concurrency();
@@ -174,6 +234,9 @@ static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
     h.qh_e = p->edge_cost ? a.take<real>((long long)n * nx) : nullptr;
     h.rh_e = p->edge_cost ? a.take<real>((long long)n * nu) : nullptr;
     h.qnh_l = p->leaf_cost ? a.take<real>((long long)p->n_leaf * nx) : nullptr;
+    h.Hq_e = p->dense_edge ? a.take<real>((long long)n * nx * nx) : nullptr;
+    h.Hr_e = p->dense_edge ? a.take<real>((long long)n * nu * nu) : nullptr;
+    h.HqN_l = p->dense_leaf ? a.take<real>((long long)p->n_leaf * nx * nx) : nullptr;
     h.x0 = a.take<real>(nx);
     // z and eta of one copy are one vector [z | zero pad | eta] (the
     // SuperMann iteration combines whole iterates)
@@ -198,7 +261,7 @@ static void carve(Arena& a, spock_problem* p) {
     p->n_ntasks = (p->n + spk::kMaxNodeWaves - 1) / spk::kMaxNodeWaves * spk::kMaxNodeWaves;
     p->d_ntasks = a.take<int2>(p->n_ntasks);
     p->d_ninfo = a.take<int4>(p->n_ntasks);
-    p->d_res = a.take<unsigned long long>(4);
+    p->d_res = a.take<unsigned long long>(2 * spk::kResSlots);
     const long long nv = std::max(p->nz, p->neta);
     p->d_stash_z = a.take<double>(nv);
     p->d_stash_e = a.take<double>(nv);
@@ -238,13 +301,27 @@ static bool finite_all(const double* v, long long n) {
 
 // Cost diagonals of the edge into node j (shared or per edge) and of leaf j.
 static double Qd(const spock_problem_desc* d, int j, int k) {
+    if (d->Q_dense) return d->Q_dense[((size_t)j * d->nx + k) * d->nx + k];
     return d->Q_edge ? d->Q_edge[(size_t)j * d->nx + k] : d->Q_diag[k];
 }
 static double Rd(const spock_problem_desc* d, int j, int k) {
+    if (d->R_dense) return d->R_dense[((size_t)j * d->nu + k) * d->nu + k];
     return d->R_edge ? d->R_edge[(size_t)j * d->nu + k] : d->R_diag[k];
 }
 static double QNd(const spock_problem_desc* d, int j, int k) {
+    if (d->QN_dense) return d->QN_dense[((size_t)j * d->nx + k) * d->nx + k];
     return d->QN_leaf ? d->QN_leaf[(size_t)j * d->nx + k] : d->QN_diag[k];
+}
+// The full cost matrix of edge / leaf j (dense, or the diagonal form).
+static std::vector<double> cost_mat(const double* dense, int j, int dim, double (*diag)(const spock_problem_desc*, int, int),
+                                    const spock_problem_desc* d) {
+    std::vector<double> M((size_t)dim * dim, 0.0);
+    if (dense) {
+        std::copy(dense + (size_t)j * dim * dim, dense + (size_t)(j + 1) * dim * dim, M.begin());
+    } else {
+        for (int k = 0; k < dim; ++k) M[(size_t)k * dim + k] = diag(d, j, k);
+    }
+    return M;
 }
 
 static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p) {
@@ -252,8 +329,8 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     const int n = d->n_nodes;
     if (n < 2) return fail(SPOCK_E_INVALID, "a tree needs at least two nodes");
     if (d->nx < 1 || d->nu < 1) return fail(SPOCK_E_INVALID, "nx and nu must be >= 1");
-    if (!d->parent || !d->cond_prob || !d->A || !d->B || !(d->Q_diag || d->Q_edge) || !(d->R_diag || d->R_edge) ||
-        !(d->QN_diag || d->QN_leaf) ||
+    if (!d->parent || !d->cond_prob || !d->A || !d->B || !(d->Q_diag || d->Q_edge || d->Q_dense) ||
+        !(d->R_diag || d->R_edge || d->R_dense) || !(d->QN_diag || d->QN_leaf || d->QN_dense) ||
         !d->x_lo || !d->x_hi || !d->u_lo || !d->u_hi || !d->xN_lo || !d->xN_hi || !d->gamma)
         return fail(SPOCK_E_INVALID, "missing array in the problem description");
     if (d->parent[0] != -1) return fail(SPOCK_E_INVALID, "parent[0] must be -1");
@@ -319,8 +396,27 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
         (d->qN && !finite_all(d->qN + (size_t)nl * nx, (long long)(n - nl) * nx)))
         return fail(SPOCK_E_INVALID, "non-finite linear cost terms");
     p->has_lin = (d->q || d->r || d->qN) ? 1 : 0;
-    p->edge_cost = (d->Q_edge || d->R_edge) ? 1 : 0;
-    p->leaf_cost = d->QN_leaf ? 1 : 0;
+    // dense costs: finite and symmetric (definiteness is checked with their
+    // eigenvalues when the square roots are taken)
+    auto dense_ok = [&](const double* M, int dim, int j0, int j1) {
+        if (!M) return true;
+        for (int j = j0; j < j1; ++j) {
+            const double* A = M + (size_t)j * dim * dim;
+            if (!finite_all(A, (long long)dim * dim)) return false;
+            for (int a = 0; a < dim; ++a)
+                for (int b = 0; b < a; ++b)
+                    if (std::fabs(A[a * dim + b] - A[b * dim + a]) > 1e-12 * (std::fabs(A[a * dim + b]) + 1e-300) &&
+                        A[a * dim + b] != A[b * dim + a])
+                        return false;
+        }
+        return true;
+    };
+    if (!dense_ok(d->Q_dense, nx, 1, n) || !dense_ok(d->R_dense, nu, 1, n) || !dense_ok(d->QN_dense, nx, nl, n))
+        return fail(SPOCK_E_INVALID, "dense cost matrices must be finite and symmetric");
+    p->dense_edge = (d->Q_dense || d->R_dense) ? 1 : 0;
+    p->dense_leaf = d->QN_dense ? 1 : 0;
+    p->edge_cost = (!p->dense_edge && (d->Q_edge || d->R_edge)) ? 1 : 0;
+    p->leaf_cost = (!p->dense_leaf && d->QN_leaf) ? 1 : 0;
     for (int k = 0; k < nx; ++k)
         if (!(d->x_lo[k] <= d->x_hi[k]) || !(d->xN_lo[k] <= d->xN_hi[k]) || std::isnan(d->x_lo[k]) ||
             std::isnan(d->xN_lo[k]))
@@ -359,6 +455,10 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     p->KR_stride = ((long long)nu * p->m + 31) / 32 * 32;
     // the sweeps keep a vector of nx and of nu entries as 4 entries per lane
     if (p->nx > 256 || p->nu > 256) return fail(SPOCK_E_INVALID, "nx and nu must not exceed 256");
+    // stage the per-child inputs of as many children as one wavefront's LDS
+    // holds (up to kStageKids); wider nodes read theirs in place
+    p->stage_kids = spk::kStageKids;
+    while (p->stage_kids > 0 && node_lds_bytes(p, 64, 8) > 64 * 1024) --p->stage_kids;
     if (node_lds_bytes(p, 64, 8) > 64 * 1024 ||
         spk::sweep_int_bytes(p->N) + spk::sweep_elems(nx, nu) * 8 > 64 * 1024)
         return fail(SPOCK_E_INVALID, "nx + nu or the branching is too large for one wavefront's LDS");
@@ -390,7 +490,100 @@ static void leaf_paths(const spock_problem* p, std::vector<int>& path, std::vect
 // scaling (Sec. 5.4) and exact ||L|| (Sec. 4.4)
 // ---------------------------------------------------------------------------
 
-static void scale_data(const spock_problem_desc* d, int precondition, spock_problem* p) {
+// FNV-1a hash of n doubles' bytes
+static uint64_t mat_hash(const std::vector<double>& a) {
+    uint64_t h = 1469598103934665603ull;
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(a.data());
+    for (size_t i = 0; i < a.size() * sizeof(double); ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+
+// Distinct matrices among items 0..count-1 (mat(i) returns item i's matrix):
+// id[i] indexes rep, which holds one item per distinct matrix.
+template <typename Mat>
+static void distinct_mats(int count, Mat mat, std::vector<int>& id, std::vector<int>& rep) {
+    std::unordered_map<uint64_t, std::vector<int>> seen;  // hash -> distinct ids
+    id.assign(count, -1);
+    rep.clear();
+    for (int i = 0; i < count; ++i) {
+        const std::vector<double> a = mat(i);
+        std::vector<int>& bucket = seen[mat_hash(a)];
+        for (int u : bucket)
+            if (mat(rep[u]) == a) {
+                id[i] = u;
+                break;
+            }
+        if (id[i] < 0) {
+            id[i] = (int)rep.size();
+            bucket.push_back(id[i]);
+            rep.push_back(i);
+        }
+    }
+}
+
+// Dense costs: the symmetric square root H = V diag(w^1/2) V^T of every
+// distinct matrix, and V diag(w^-1/2) V^T b for linear terms b (Prop. 1 with a
+// dense Q: the translation takes Q^-1/2 q).  Fails unless positive definite.
+struct DenseRoots {
+    int dim = 0;
+    std::vector<int> id, rep;
+    std::vector<std::vector<double>> w, V, H;
+    template <typename Mat>
+    bool build(int count, int dim_, Mat mat) {
+        dim = dim_;
+        distinct_mats(count, mat, id, rep);
+        const int u = (int)rep.size();
+        w.assign(u, {});
+        V.assign(u, {});
+        H.assign(u, {});
+        std::vector<int> ok(u, 1);
+        parallel_for(u, [&](int k) {
+            const std::vector<double> a = mat(rep[k]);
+            sym_eig(dim, a.data(), w[k], V[k]);
+            double top = 0;
+            for (double e : w[k]) top = std::max(top, std::fabs(e));
+            for (double e : w[k])
+                if (!(e > 1e-14 * top)) ok[k] = 0;
+            H[k] = eig_fn(dim, w[k], V[k], [](double e) { return std::sqrt(std::max(e, 0.0)); });
+        });
+        for (int k = 0; k < u; ++k)
+            if (!ok[k]) return false;
+        return true;
+    }
+    // Q^-1/2 b of item i
+    void inv_root_apply(int i, const double* b, double* out) const {
+        const int k = id[i];
+        std::vector<double> t(dim, 0.0);
+        for (int e = 0; e < dim; ++e) {
+            double s = 0;
+            for (int r = 0; r < dim; ++r) s += V[k][(size_t)r * dim + e] * b[r];
+            t[e] = s / std::sqrt(w[k][e]);
+        }
+        for (int r = 0; r < dim; ++r) {
+            double s = 0;
+            for (int e = 0; e < dim; ++e) s += V[k][(size_t)r * dim + e] * t[e];
+            out[r] = s;
+        }
+    }
+};
+
+// Largest eigenvalue of diag(g2) + D (sum of the listed matrices) D, D = diag(dsc)
+static double dense_block_norm2(int dim, const std::vector<const std::vector<double>*>& mats,
+                                const std::vector<double>& g2, const std::vector<double>& dsc) {
+    std::vector<double> M((size_t)dim * dim, 0.0);
+    for (const std::vector<double>* a : mats)
+        for (size_t e = 0; e < M.size(); ++e) M[e] += (*a)[e];
+    for (int r = 0; r < dim; ++r)
+        for (int c = 0; c < dim; ++c) M[(size_t)r * dim + c] *= dsc[r] * dsc[c];
+    for (int r = 0; r < dim; ++r) M[(size_t)r * dim + r] += g2[r];
+    std::vector<double> w, V;
+    sym_eig(dim, M.data(), w, V);
+    double top = 0;
+    for (double e : w) top = std::max(top, e);
+    return top;
+}
+
+static int32_t scale_data(const spock_problem_desc* d, int precondition, spock_problem* p) {
     const int nx = p->nx, nu = p->nu;
     p->Sx.assign(nx, 1.0);
     p->Su.assign(nu, 1.0);
@@ -424,6 +617,38 @@ static void scale_data(const spock_problem_desc* d, int precondition, spock_prob
         p->qnh[k] = std::sqrt(QNd(d, l1, k)) / p->SxN[k];
     }
     for (int k = 0; k < nu; ++k) p->rh[k] = std::sqrt(Rd(d, j1, k)) / p->Su[k];
+    // dense costs: qh, rh, qnh hold S^-1 and the square roots are per edge / leaf
+    DenseRoots dq, dr, dqN;
+    const int n = p->n, nl = p->n_nl;
+    p->Hq_e.clear();
+    p->Hr_e.clear();
+    p->HqN_l.clear();
+    if (p->dense_edge) {
+        for (int k = 0; k < nx; ++k) p->qh[k] = 1.0 / p->Sx[k];
+        for (int k = 0; k < nu; ++k) p->rh[k] = 1.0 / p->Su[k];
+        // item i is edge i + 1
+        if (!dq.build(n - 1, nx, [&](int i) { return cost_mat(d->Q_dense, i + 1, nx, Qd, d); }) ||
+            !dr.build(n - 1, nu, [&](int i) { return cost_mat(d->R_dense, i + 1, nu, Rd, d); }))
+            return fail(SPOCK_E_INVALID, "dense Q and R must be positive definite");
+        p->Hq_e.assign((size_t)n * nx * nx, 0.0);
+        p->Hr_e.assign((size_t)n * nu * nu, 0.0);
+        for (int j = 1; j < n; ++j) {
+            const std::vector<double>& hq = dq.H[dq.id[j - 1]];
+            const std::vector<double>& hr = dr.H[dr.id[j - 1]];
+            std::copy(hq.begin(), hq.end(), p->Hq_e.begin() + (size_t)j * nx * nx);
+            std::copy(hr.begin(), hr.end(), p->Hr_e.begin() + (size_t)j * nu * nu);
+        }
+    }
+    if (p->dense_leaf) {
+        for (int k = 0; k < nx; ++k) p->qnh[k] = 1.0 / p->SxN[k];
+        if (!dqN.build(p->n_leaf, nx, [&](int l) { return cost_mat(d->QN_dense, nl + l, nx, QNd, d); }))
+            return fail(SPOCK_E_INVALID, "dense QN must be positive definite");
+        p->HqN_l.assign((size_t)p->n_leaf * nx * nx, 0.0);
+        for (int l = 0; l < p->n_leaf; ++l) {
+            const std::vector<double>& h = dqN.H[dqN.id[l]];
+            std::copy(h.begin(), h.end(), p->HqN_l.begin() + (size_t)l * nx * nx);
+        }
+    }
     p->qh_e.clear();
     p->rh_e.clear();
     p->qnh_l.clear();
@@ -502,15 +727,20 @@ static void scale_data(const spock_problem_desc* d, int precondition, spock_prob
         for (int j = 1; j < p->n; ++j) {
             double* a = p->sa.data() + (size_t)(j - 1) * (m + 2);
             double c = 0;
+            std::vector<double> wq(nx, 0.0), wr(nu, 0.0);
+            if (d->q && p->dense_edge) dq.inv_root_apply(j - 1, d->q + (size_t)j * nx, wq.data());
+            else if (d->q)
+                for (int k = 0; k < nx; ++k) wq[k] = d->q[(size_t)j * nx + k] / std::sqrt(Qd(d, j, k));
+            if (d->r && p->dense_edge) dr.inv_root_apply(j - 1, d->r + (size_t)j * nu, wr.data());
+            else if (d->r)
+                for (int k = 0; k < nu; ++k) wr[k] = d->r[(size_t)j * nu + k] / std::sqrt(Rd(d, j, k));
             for (int k = 0; k < nx; ++k) {
-                const double w = d->q ? d->q[(size_t)j * nx + k] / std::sqrt(Qd(d, j, k)) : 0.0;
-                a[k] = -0.5 * w;
-                c += w * w;
+                a[k] = -0.5 * wq[k];
+                c += wq[k] * wq[k];
             }
             for (int k = 0; k < nu; ++k) {
-                const double w = d->r ? d->r[(size_t)j * nu + k] / std::sqrt(Rd(d, j, k)) : 0.0;
-                a[nx + k] = -0.5 * w;
-                c += w * w;
+                a[nx + k] = -0.5 * wr[k];
+                c += wr[k] * wr[k];
             }
             a[m] = -0.125 * c + 0.5;
             a[m + 1] = -0.125 * c - 0.5;
@@ -520,10 +750,13 @@ static void scale_data(const spock_problem_desc* d, int precondition, spock_prob
             const int j = p->n_nl + l;
             double* a = p->saN.data() + (size_t)l * (nx + 2);
             double c = 0;
+            std::vector<double> wq(nx, 0.0);
+            if (d->qN && p->dense_leaf) dqN.inv_root_apply(l, d->qN + (size_t)j * nx, wq.data());
+            else if (d->qN)
+                for (int k = 0; k < nx; ++k) wq[k] = d->qN[(size_t)j * nx + k] / std::sqrt(QNd(d, j, k));
             for (int k = 0; k < nx; ++k) {
-                const double w = d->qN ? d->qN[(size_t)j * nx + k] / std::sqrt(QNd(d, j, k)) : 0.0;
-                a[k] = -0.5 * w;
-                c += w * w;
+                a[k] = -0.5 * wq[k];
+                c += wq[k] * wq[k];
             }
             a[nx] = -0.125 * c + 0.5;
             a[nx + 1] = -0.125 * c - 0.5;
@@ -532,9 +765,48 @@ static void scale_data(const spock_problem_desc* d, int precondition, spock_prob
 
     // ||L||: largest block norm of L composed with a permutation
     double L2 = 0.5;  // tau^j and leaf s^j rows (1/2, 1/2)
+    if (p->dense_edge) {
+        // (x^i, u^i) block with dense cost rows: the largest eigenvalue of
+        // diag(gx^2 + gb^2) + S^-1 (sum over the child edges of Q^j) S^-1,
+        // once per distinct list of children's matrices (likewise for u)
+        std::vector<double> gx2(nx), gu2(nu), qd = p->qh, rd = p->rh;
+        for (int k = 0; k < nx; ++k) gx2[k] = p->gx[k] * p->gx[k] + p->gb[k] * p->gb[k];
+        for (int k = 0; k < nu; ++k) gu2[k] = p->gu[k] * p->gu[k];
+        std::vector<std::vector<double>> Qm(dq.rep.size()), Rm(dr.rep.size());
+        for (size_t u = 0; u < dq.rep.size(); ++u) Qm[u] = cost_mat(d->Q_dense, dq.rep[u] + 1, nx, Qd, d);
+        for (size_t u = 0; u < dr.rep.size(); ++u) Rm[u] = cost_mat(d->R_dense, dr.rep[u] + 1, nu, Rd, d);
+        std::map<std::vector<int>, int> keys;
+        std::vector<std::vector<int>> klist;
+        for (int i = 0; i < nl; ++i) {
+            std::vector<int> key;
+            for (int c = 0; c < p->n_ch[i]; ++c) key.push_back(dq.id[p->first_child[i] + c - 1]);
+            key.push_back(-1);
+            for (int c = 0; c < p->n_ch[i]; ++c) key.push_back(dr.id[p->first_child[i] + c - 1]);
+            if (keys.emplace(key, (int)klist.size()).second) klist.push_back(key);
+        }
+        std::vector<double> top(klist.size(), 0.0);
+        parallel_for((int)klist.size(), [&](int t) {
+            std::vector<const std::vector<double>*> mq, mr;
+            size_t e = 0;
+            for (; klist[t][e] >= 0; ++e) mq.push_back(&Qm[klist[t][e]]);
+            for (++e; e < klist[t].size(); ++e) mr.push_back(&Rm[klist[t][e]]);
+            top[t] = std::max(dense_block_norm2(nx, mq, gx2, qd), dense_block_norm2(nu, mr, gu2, rd));
+        });
+        for (double t : top) L2 = std::max(L2, t);
+    }
+    if (p->dense_leaf) {
+        std::vector<double> g2(nx), qd = p->qnh;
+        for (int k = 0; k < nx; ++k) g2[k] = p->gxN[k] * p->gxN[k] + p->gbN[k] * p->gbN[k];
+        std::vector<double> top(dqN.rep.size(), 0.0);
+        parallel_for((int)dqN.rep.size(), [&](int u) {
+            const std::vector<double> QN = cost_mat(d->QN_dense, nl + dqN.rep[u], nx, QNd, d);
+            top[u] = dense_block_norm2(nx, {&QN}, g2, qd);
+        });
+        for (double t : top) L2 = std::max(L2, t);
+    }
     for (int i = 0; i < p->n_nl; ++i) {
         // (x^i, u^i) block: constraint rows and every child edge's cost rows
-        for (int r = 0; r < nx; ++r) {
+        for (int r = 0; r < (p->dense_edge ? 0 : nx); ++r) {
             double sq = 0;
             for (int c = 0; c < p->n_ch[i]; ++c) {
                 const double h = p->edge_cost ? p->qh_e[(size_t)(p->first_child[i] + c) * nx + r] : p->qh[r];
@@ -542,7 +814,7 @@ static void scale_data(const spock_problem_desc* d, int precondition, spock_prob
             }
             L2 = std::max(L2, p->gx[r] * p->gx[r] + p->gb[r] * p->gb[r] + sq);
         }
-        for (int r = 0; r < nu; ++r) {
+        for (int r = 0; r < (p->dense_edge ? 0 : nu); ++r) {
             double sq = 0;
             for (int c = 0; c < p->n_ch[i]; ++c) {
                 const double h = p->edge_cost ? p->rh_e[(size_t)(p->first_child[i] + c) * nu + r] : p->rh[r];
@@ -556,12 +828,13 @@ static void scale_data(const spock_problem_desc* d, int precondition, spock_prob
         const double sig = 0.5 * (beta + std::sqrt(b2 + 4.0));  // [[I, 0], [-b^T, 1]]
         L2 = std::max(L2, sig * sig);
     }
-    for (int l = 0; l < (p->leaf_cost ? p->n_leaf : 1); ++l)
+    for (int l = 0; l < (p->dense_leaf ? 0 : p->leaf_cost ? p->n_leaf : 1); ++l)
         for (int r = 0; r < nx; ++r) {
             const double h = p->leaf_cost ? p->qnh_l[(size_t)l * nx + r] : p->qnh[r];
             L2 = std::max(L2, p->gxN[r] * p->gxN[r] + p->gbN[r] * p->gbN[r] + h * h);
         }
     p->Lnorm = std::sqrt(L2);
+    return SPOCK_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -770,6 +1043,7 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     h.has_ballN = p->has_ballN;
     h.affine = p->affine;
     h.max_ch = p->max_ch;
+    h.stage_kids = p->stage_kids;
     h.alpha = (real)p->alpha;
     h.ball_r = (real)p->ball_r;
     h.ballN_r = (real)p->ballN_r;
@@ -815,6 +1089,11 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
         HIP_TRY(put<real>(h.rh_e, p->rh_e, st));
     }
     if (p->leaf_cost) HIP_TRY(put<real>(h.qnh_l, p->qnh_l, st));
+    if (p->dense_edge) {
+        HIP_TRY(put<real>(h.Hq_e, p->Hq_e, st));
+        HIP_TRY(put<real>(h.Hr_e, p->Hr_e, st));
+    }
+    if (p->dense_leaf) HIP_TRY(put<real>(h.HqN_l, p->HqN_l, st));
     for (int k = 0; k < 2; ++k) HIP_TRY(spk::launch_fill<real>(h.z[k], real(0), p->nzp + p->neta, st));
     HIP_TRY(hipMemcpyAsync(s.d, &h, sizeof(h), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -839,7 +1118,7 @@ static int32_t upload_supermann(spock_problem* p) {
     h.eta[1] = w.TVT + p->nzp;
     HIP_TRY(hipMemcpyAsync(w.d_trial, &h, sizeof(h), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (hipHostMalloc((void**)&w.h_dots, (spk::kMaxDots + 4) * sizeof(double), 0) != hipSuccess)
+    if (hipHostMalloc((void**)&w.h_dots, (spk::kMaxDots + 2 * spk::kResSlots) * sizeof(double), 0) != hipSuccess)
         return fail(SPOCK_E_HIP, "hipHostMalloc failed");
     return SPOCK_OK;
 }
@@ -898,13 +1177,10 @@ static int32_t chunk(spock_problem* p, int steps) {
 }
 
 int32_t read_res(spock_problem* p, double* xi1, double* xi2) {
-    HIP_TRY(hipMemcpyAsync(p->h_res, p->d_res, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->h_res, p->d_res, 2 * spk::kResSlots * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
-    double a, b;
-    std::memcpy(&a, &p->h_res[0], 8);
-    std::memcpy(&b, &p->h_res[1], 8);
-    *xi1 = a;
-    *xi2 = b;
+    res_reduce(p->h_res, xi1, xi2);
     return SPOCK_OK;
 }
 
@@ -962,7 +1238,8 @@ double now_s() {
 
 int node_lds_bytes(const spock_problem* p, int node_wg, int real_bytes) {
     const int waves = node_wg / 64;
-    return (spk::consts_elems(p->nx, p->nu) + waves * spk::node_wave_elems(p->nx, p->nu, p->nc, p->ncN, p->max_ch)) *
+    return (spk::consts_elems(p->nx, p->nu) +
+            waves * spk::node_wave_elems(p->nx, p->nu, p->nc, p->ncN, std::min(p->max_ch, p->stage_kids))) *
            real_bytes;
 }
 
@@ -988,7 +1265,7 @@ spk::LaunchCfg make_cfg(const spock_problem* p, int node_wg) {
     c.n_node_tasks = p->n_ntasks;
     c.node_wg = node_wg;
     c.node_lds = node_lds_bytes(p, node_wg, (int)sizeof(real));
-    c.wave_elems = spk::node_wave_elems(nx, nu, p->nc, p->ncN, p->max_ch);
+    c.wave_elems = spk::node_wave_elems(nx, nu, p->nc, p->ncN, std::min(p->max_ch, p->stage_kids));
     c.cls[0] = tile_class(spk::col_need(nu, nx, V));
     c.cls[1] = tile_class(spk::col_need(nx, m, V));
     c.cls[2] = tile_class(spk::col_need(m, nx, V));
@@ -1129,7 +1406,11 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
             delete p;
             return r;
         }
-        scale_data(desc, s->precondition, p);
+        r = scale_data(desc, s->precondition, p);
+        if (r) {
+            delete p;
+            return r;
+        }
         p->alpha = s->alpha > 0 ? s->alpha : 0.99 / p->Lnorm;
         std::vector<double> M, KR, cs, Pc;
         r = offline_factor(desc, p, M, KR, cs, Pc);
@@ -1169,7 +1450,7 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
             }
             p->owns_stream = true;
         }
-        if (hipHostMalloc((void**)&p->h_res, 4 * sizeof(unsigned long long), 0) != hipSuccess) {
+        if (hipHostMalloc((void**)&p->h_res, 2 * spk::kResSlots * sizeof(unsigned long long), 0) != hipSuccess) {
             spock_problem_destroy(p);
             return fail(SPOCK_E_HIP, "hipHostMalloc failed");
         }
@@ -1213,7 +1494,7 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
         // arrival counters and residual slots start at zero; the active flag at one
         e = spk::launch_fill<int>(p->d_cnt, 0, p->n, p->stream);
         if (e == hipSuccess) e = spk::launch_fill<int>(p->d_one, 1, 1, p->stream);
-        if (e == hipSuccess) e = spk::launch_fill<unsigned long long>(p->d_res, 0ull, 4, p->stream);
+        if (e == hipSuccess) e = spk::launch_fill<unsigned long long>(p->d_res, 0ull, 2 * spk::kResSlots, p->stream);
         if (e != hipSuccess) {
             spock_problem_destroy(p);
             return fail(SPOCK_E_HIP, std::string("init: ") + hipGetErrorString(e));

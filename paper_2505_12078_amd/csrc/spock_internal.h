@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -94,6 +95,7 @@ struct SmWork {
 struct spock_problem {
     // sizes
     int n = 0, n_nl = 0, n_leaf = 0, N = 0, nx = 0, nu = 0, m = 0, nc = 0, ncN = 0, max_ch = 0;
+    int stage_kids = 16;  // children whose per-child inputs the node kernels stage in LDS
     int has_ball = 0, has_ballN = 0, affine = 0;
     long long ny = 0, nz = 0, neta = 0, nzp = 0;  // nzp: nz rounded up to 64 entries
     long long z_x, z_u, z_y, z_tau, z_s, e_y, e_s, e_c, e_soc, e_cN, e_socN;
@@ -111,6 +113,12 @@ struct spock_problem {
     // description gives per-edge costs (edge_cost) or per-leaf ones (leaf_cost)
     int edge_cost = 0, leaf_cost = 0;
     std::vector<double> qh_e, rh_e, qnh_l;
+    // dense costs (dense_edge: Q and R per edge, dense_leaf: QN per leaf):
+    // the symmetric square roots Hq_e [n][nx][nx], Hr_e [n][nu][nu] by edge and
+    // HqN_l [n_leaf][nx][nx] by leaf; qh, rh (qnh) then hold S_x^-1, S_u^-1
+    // (S_xN^-1), so that the cost rows are H (qh o x)
+    int dense_edge = 0, dense_leaf = 0;
+    std::vector<double> Hq_e, Hr_e, HqN_l;
     double ball_r = 0, ballN_r = 0, con_scale = 1, con_scaleN = 1;
     double Lnorm = 0, alpha = 0;
     // unscaled root constraint for the x0 check
@@ -163,6 +171,18 @@ int32_t move_iterate(spock_problem* p, int to);
 int32_t zero_iterate(spock_problem* p);
 int32_t set_x0_device(spock_problem* p, const double* x0, bool check_feasible);
 double now_s();
+// The residual maxima from kResSlots pairs of float64 bit patterns (the
+// unsigned order of non-negative doubles, with a NaN above +inf).
+inline void res_reduce(const unsigned long long* h, double* x1, double* x2) {
+    unsigned long long a = 0, b = 0;
+    for (int s = 0; s < spk::kResSlots; ++s) {
+        a = std::max(a, h[2 * s]);
+        b = std::max(b, h[2 * s + 1]);
+    }
+    std::memcpy(x1, &a, 8);
+    std::memcpy(x2, &b, 8);
+}
+
 // rel_res of Sec. 5.3 from the two residual maxima: NaN when either is NaN
 // (std::max would return the other operand and hide it).
 inline double rel_of(double x1, double x2, double scale) {

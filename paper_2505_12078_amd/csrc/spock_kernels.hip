@@ -161,6 +161,28 @@ SPK_DEV const __attribute__((address_space(3))) T* lds(const T* p) {
     return (const __attribute__((address_space(3))) T*)p;
 }
 
+// sum_c H[c][r] x(c) for a symmetric n x n H in global memory: with r the
+// lane's row, consecutive lanes read consecutive addresses of row c of H
+template <typename real, typename X>
+SPK_DEV real sym_col_dot(const real* H, int n, int r, X x) {
+    real s = 0;
+    for (int c = 0; c < n; ++c) s += gm(H)[(long long)c * n + r] * x(c);
+    return s;
+}
+
+// the same for two vectors in one pass over H
+template <typename real, typename X, typename Y>
+SPK_DEV void sym_col_dot2(const real* H, int n, int r, X x, Y y, real& sx, real& sy) {
+    real a = 0, b = 0;
+    for (int c = 0; c < n; ++c) {
+        const real h = gm(H)[(long long)c * n + r];
+        a += h * x(c);
+        b += h * y(c);
+    }
+    sx = a;
+    sy = b;
+}
+
 template <typename real>
 SPK_DEV void st_dev(real* p, real v) {
     __hip_atomic_store(gm(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -674,10 +696,29 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
     const real* re = P->rh_e ? P->rh_e + (long long)j * P->nu : nullptr;
     auto qh = [&](int r) { return qe ? gm(qe)[r] : V.C.qh[r]; };
     auto rh = [&](int r) { return re ? gm(re)[r] : V.C.rh[r]; };
+    // dense costs: the cost rows H (S^-1 x) of the new and old iterate, first
+    // into blk / dblk
+    const real* Hq = P->Hq_e ? P->Hq_e + (long long)j * nx * nx : nullptr;
+    const real* Hr = P->Hr_e ? P->Hr_e + (long long)j * P->nu * P->nu : nullptr;
+    if (Hq) {
+        wave_sync();
+        for (int r = lane; r < nx; r += 64)
+            sym_col_dot2(
+                Hq, nx, r, [&](int c) { return V.C.qh[c] * V.xn[c]; }, [&](int c) { return V.C.qh[c] * V.xo[c]; },
+                V.blk[r], V.dblk[r]);
+        for (int r = lane; r < P->nu; r += 64)
+            sym_col_dot2(
+                Hr, P->nu, r, [&](int c) { return V.C.rh[c] * V.un[c]; },
+                [&](int c) { return V.C.rh[c] * V.uo[c]; }, V.blk[nx + r], V.dblk[nx + r]);
+        wave_sync();
+    }
     real nw2 = 0;
     for (int r = lane; r < m + 2; r += 64) {
         real wn, wo;
-        if (r < nx) {
+        if (Hq && r < m) {
+            wn = V.blk[r];
+            wo = V.dblk[r];
+        } else if (r < nx) {
             wn = qh(r) * V.xn[r];
             wo = qh(r) * V.xo[r];
         } else if (r < m) {
@@ -706,8 +747,15 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
     }
     if (check) {
         wave_sync();
-        for (int r = lane; r < nx; r += 64) V.lxw[r] += qh(r) * V.dblk[r];
-        for (int r = lane; r < P->nu; r += 64) V.luw[r] += rh(r) * V.dblk[nx + r];
+        if (Hq) {
+            for (int r = lane; r < nx; r += 64)
+                V.lxw[r] += V.C.qh[r] * sym_col_dot(Hq, nx, r, [&](int c) { return V.dblk[c]; });
+            for (int r = lane; r < P->nu; r += 64)
+                V.luw[r] += V.C.rh[r] * sym_col_dot(Hr, P->nu, r, [&](int c) { return V.dblk[nx + c]; });
+        } else {
+            for (int r = lane; r < nx; r += 64) V.lxw[r] += qh(r) * V.dblk[r];
+            for (int r = lane; r < P->nu; r += 64) V.luw[r] += rh(r) * V.dblk[nx + r];
+        }
         if (lane == 0) r1 = nmax(r1, fabs((tv - tn) * ialpha - real(0.5) * (V.dblk[m] + V.dblk[m + 1])));
     }
 }
@@ -767,10 +815,20 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
         const real* aj = P->saN ? P->saN + lf * (nx + 2) : nullptr;
         const real* qe = P->qnh_l ? P->qnh_l + lf * nx : nullptr;
         auto qnh = [&](int r) { return qe ? gm(qe)[r] : V.C.qnh[r]; };
+        const real* Hq = P->HqN_l ? P->HqN_l + lf * nx * nx : nullptr;
+        if (Hq) {
+            for (int r = lane; r < nx; r += 64)
+                sym_col_dot2(
+                    Hq, nx, r, [&](int c) { return V.C.qnh[c] * V.xn[c]; },
+                    [&](int c) { return V.C.qnh[c] * V.xo[c]; }, V.blk[r], V.dblk[r]);
+        }
         real nw2 = 0;
         for (int r = lane; r < nx + 2; r += 64) {
             real wn, wo;
-            if (r < nx) {
+            if (Hq && r < nx) {
+                wn = V.blk[r];
+                wo = V.dblk[r];
+            } else if (r < nx) {
                 wn = qnh(r) * V.xn[r];
                 wo = qnh(r) * V.xo[r];
             } else {
@@ -796,7 +854,9 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
         }
         if (check) {
             wave_sync();
-            for (int r = lane; r < nx; r += 64) V.lxw[r] += qnh(r) * V.dblk[r];
+            for (int r = lane; r < nx; r += 64)
+                V.lxw[r] += Hq ? V.C.qnh[r] * sym_col_dot(Hq, nx, r, [&](int c) { return V.dblk[c]; })
+                               : qnh(r) * V.dblk[r];
             if (lane == 0) r1 = nmax(r1, fabs((sv - sn) * ialpha - real(0.5) * (V.dblk[nx] + V.dblk[nx + 1])));
         }
     }
@@ -845,7 +905,7 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         const int fc = ni.x, k = ni.y;
         const long long yo = ni.z;
         const bool leafkids = fc >= n_nl;
-        const bool sk = k <= kStageKids;  // per-child inputs staged, else read in place
+        const bool sk = k <= P->stage_kids;  // per-child inputs staged, else read in place
         const int kk = sk ? k : 0;
         // K^T ubar: rows r < nu of [K | R~^-1], columns c < nx
         ColProd<real, R> TK;
@@ -880,7 +940,12 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         // of every child edge (Sec. 4.4)
         for (int r = lane; r < nx; r += 64) {
             real s = 0;
-            if (P->qh_e) {  // each child edge's own Q^1/2
+            if (P->Hq_e) {  // dense: S^-1 sum over child edges of H^j eta^j
+                for (int q = 0; q < k; ++q)
+                    s += sym_col_dot(P->Hq_e + (long long)(fc + q) * nx * nx, nx, r,
+                                     [&](int c) { return soc[q * (m + 2) + c]; });
+                s *= C.qh[r];
+            } else if (P->qh_e) {  // each child edge's own Q^1/2
                 for (int q = 0; q < k; ++q) s += gm(P->qh_e)[(long long)(fc + q) * nx + r] * soc[q * (m + 2) + r];
             } else {
                 for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + r];
@@ -892,7 +957,12 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         }
         for (int r = lane; r < nu; r += 64) {
             real s = 0;
-            if (P->rh_e) {
+            if (P->Hr_e) {
+                for (int q = 0; q < k; ++q)
+                    s += sym_col_dot(P->Hr_e + (long long)(fc + q) * nu * nu, nu, r,
+                                     [&](int c) { return soc[q * (m + 2) + nx + c]; });
+                s *= C.rh[r];
+            } else if (P->rh_e) {
                 for (int q = 0; q < k; ++q)
                     s += gm(P->rh_e)[(long long)(fc + q) * nu + r] * soc[q * (m + 2) + nx + r];
             } else {
@@ -955,13 +1025,9 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
             gm(P->h0)[(long long)v * nx + r] = h;
         }
         for (int r = lane; r < nu; r += 64) gm(P->ub)[(long long)v * nu + r] = ub[r];
-        if (v == 0 && lane == 0) {
-            gm(zout)[0] = zin[0] - alpha * es - alpha;  // prox of alpha * s0
-            if (check) {
-                gm(P->res)[0] = 0ull;
-                gm(P->res)[1] = 0ull;
-            }
-        }
+        if (v == 0 && lane == 0) gm(zout)[0] = zin[0] - alpha * es - alpha;  // prox of alpha * s0
+        if (v == 0 && check)
+            for (int e = lane; e < 2 * kResSlots; e += 64) gm(P->res)[e] = 0ull;
     } else {
         // leaf: h0 = -xbar (+ P c) with xbar = x - alpha L* eta on x
         const long long lf = v - n_nl;
@@ -978,7 +1044,10 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         const real* ss = st + off[2];
         const real* spc = st + off[3];
         for (int r = lane; r < nx; r += 64) {
-            real lt = C.gxN[r] * sc[r] + (P->qnh_l ? gm(P->qnh_l)[lf * nx + r] : C.qnh[r]) * ss[r];
+            const real cost = P->HqN_l ? C.qnh[r] * sym_col_dot(P->HqN_l + lf * nx * nx, nx, r,
+                                                                 [&](int c) { return ss[c]; })
+                                       : (P->qnh_l ? gm(P->qnh_l)[lf * nx + r] : C.qnh[r]) * ss[r];
+            real lt = C.gxN[r] * sc[r] + cost;
             if (P->has_ballN) lt += C.gbN[r] * sc[nx + r];
             real h = -(sx[r] - alpha * lt);
             if (P->affine) h += spc[r];
@@ -1610,7 +1679,7 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
     if (v < n_nl) {
         const int fc = ni.x, k = ni.y;
         const long long yo = ni.z;
-        const bool sk = k <= kStageKids;
+        const bool sk = k <= P->stage_kids;
         const int kk = sk ? k : 0, ky = sk ? 2 * k + 1 : 0;
         ColProd<real, R> TK;  // u = K x + d
         TK.load(P->T4 + v * P->T4_stride, col_shape<real>(nx, nu));
@@ -1703,8 +1772,9 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
         r1 = wave_max(r1);
         r2 = wave_max(r2);
         if (lane == 0) {
-            record_max(&P->res[0], r1);
-            record_max(&P->res[1], r2);
+            const int slot = (int)(blockIdx.x % kResSlots);
+            record_max(&P->res[2 * slot], r1);
+            record_max(&P->res[2 * slot + 1], r2);
         }
     }
 }
@@ -1743,19 +1813,37 @@ __global__ __launch_bounds__(kHookWG) void k_apply_L(const ProbDev<real>* __rest
             const int j = fc + q;
             const real tau = z[P->z_tau + j - 1];
             real* o = eta + P->e_soc + (long long)(j - 1) * (m + 2);
-            for (int r = t; r < m + 2; r += kHookWG)
+            for (int r = t; r < m + 2; r += kHookWG) {
+                if (P->Hq_e && r < m) {
+                    real a = 0;
+                    if (r < nx)
+                        for (int c = 0; c < nx; ++c) a += P->Hq_e[((long long)j * nx + r) * nx + c] * P->qh[c] * x[c];
+                    else
+                        for (int c = 0; c < nu; ++c)
+                            a += P->Hr_e[((long long)j * nu + r - nx) * nu + c] * P->rh[c] * u[c];
+                    o[r] = a;
+                    continue;
+                }
                 o[r] = r < nx ? (P->qh_e ? P->qh_e[(long long)j * nx + r] : P->qh[r]) * x[r]
                               : (r < m ? (P->rh_e ? P->rh_e[(long long)j * nu + r - nx] : P->rh[r - nx]) * u[r - nx]
                                        : real(0.5) * tau);
+            }
         }
     } else {
         const long long lf = v - P->n_nl;
         for (int r = t; r < P->ncN; r += kHookWG)
             eta[P->e_cN + lf * P->ncN + r] = r < nx ? P->gxN[r] * x[r] : P->gbN[r - nx] * x[r - nx];
         const real s = z[P->z_s + v - 1];
-        for (int r = t; r < nx + 2; r += kHookWG)
-            eta[P->e_socN + lf * (nx + 2) + r] =
-                r < nx ? (P->qnh_l ? P->qnh_l[lf * nx + r] : P->qnh[r]) * x[r] : real(0.5) * s;
+        for (int r = t; r < nx + 2; r += kHookWG) {
+            real w;
+            if (P->HqN_l && r < nx) {
+                w = 0;
+                for (int c = 0; c < nx; ++c) w += P->HqN_l[(lf * nx + r) * nx + c] * P->qnh[c] * x[c];
+            } else {
+                w = r < nx ? (P->qnh_l ? P->qnh_l[lf * nx + r] : P->qnh[r]) * x[r] : real(0.5) * s;
+            }
+            eta[P->e_socN + lf * (nx + 2) + r] = w;
+        }
     }
 }
 
@@ -1771,18 +1859,32 @@ __global__ __launch_bounds__(kHookWG) void k_apply_Lt(const ProbDev<real>* __res
         const real* ec = eta + P->e_c + (long long)v * P->nc;
         for (int r = t; r < nx; r += kHookWG) {
             real s = 0;
-            for (int q = 0; q < k; ++q)
-                s += (P->qh_e ? P->qh_e[(long long)(fc + q) * nx + r] : P->qh[r]) *
-                     eta[P->e_soc + (long long)(fc + q - 1) * (m + 2) + r];
+            for (int q = 0; q < k; ++q) {
+                const real* o = eta + P->e_soc + (long long)(fc + q - 1) * (m + 2);
+                if (P->Hq_e) {
+                    real a = 0;
+                    for (int c = 0; c < nx; ++c) a += P->Hq_e[((long long)(fc + q) * nx + r) * nx + c] * o[c];
+                    s += P->qh[r] * a;
+                } else {
+                    s += (P->qh_e ? P->qh_e[(long long)(fc + q) * nx + r] : P->qh[r]) * o[r];
+                }
+            }
             real w = P->gx[r] * ec[r] + s;
             if (P->has_ball) w += P->gb[r] * ec[nbox + r];
             x[r] = w;
         }
         for (int r = t; r < nu; r += kHookWG) {
             real s = 0;
-            for (int q = 0; q < k; ++q)
-                s += (P->rh_e ? P->rh_e[(long long)(fc + q) * nu + r] : P->rh[r]) *
-                     eta[P->e_soc + (long long)(fc + q - 1) * (m + 2) + nx + r];
+            for (int q = 0; q < k; ++q) {
+                const real* o = eta + P->e_soc + (long long)(fc + q - 1) * (m + 2) + nx;
+                if (P->Hr_e) {
+                    real a = 0;
+                    for (int c = 0; c < nu; ++c) a += P->Hr_e[((long long)(fc + q) * nu + r) * nu + c] * o[c];
+                    s += P->rh[r] * a;
+                } else {
+                    s += (P->rh_e ? P->rh_e[(long long)(fc + q) * nu + r] : P->rh[r]) * o[r];
+                }
+            }
             z[P->z_u + (long long)v * nu + r] = P->gu[r] * ec[nx + r] + s;
         }
         const long long yo = P->y_off[v];
@@ -1805,7 +1907,15 @@ __global__ __launch_bounds__(kHookWG) void k_apply_Lt(const ProbDev<real>* __res
         const real* ecN = eta + P->e_cN + lf * P->ncN;
         const real* esN = eta + P->e_socN + lf * (nx + 2);
         for (int r = t; r < nx; r += kHookWG) {
-            real w = P->gxN[r] * ecN[r] + (P->qnh_l ? P->qnh_l[lf * nx + r] : P->qnh[r]) * esN[r];
+            real cost;
+            if (P->HqN_l) {
+                cost = 0;
+                for (int c = 0; c < nx; ++c) cost += P->HqN_l[(lf * nx + r) * nx + c] * esN[c];
+                cost *= P->qnh[r];
+            } else {
+                cost = (P->qnh_l ? P->qnh_l[lf * nx + r] : P->qnh[r]) * esN[r];
+            }
+            real w = P->gxN[r] * ecN[r] + cost;
             if (P->has_ballN) w += P->gbN[r] * ecN[nx + r];
             x[r] = w;
         }

@@ -65,7 +65,7 @@ Plan plan_of(const spock_problem* p, size_t w, size_t desc_bytes) {
     q.cnt = o;
     o = align256(o + (size_t)p->n * sizeof(int));
     q.res = o;
-    o = align256(o + 2 * sizeof(unsigned long long));
+    o = align256(o + 2 * spk::kResSlots * sizeof(unsigned long long));
     q.total = o;
     return q;
 }
@@ -102,14 +102,12 @@ int32_t step_noalloc(spock_problem* p, const void* z, const void* eta, void* z_o
     // slots start at zero (fill kernels, not memsets, so a capture replays them)
     HIP_TRY(hipMemcpyAsync(d_desc, &h, sizeof(h), hipMemcpyHostToDevice, p->stream));
     HIP_TRY(spk::launch_fill<int>(h.cnt, 0, p->n, p->stream));
-    HIP_TRY(spk::launch_fill<unsigned long long>(h.res, 0ull, 2, p->stream));
+    HIP_TRY(spk::launch_fill<unsigned long long>(h.res, 0ull, 2 * spk::kResSlots, p->stream));
     HIP_TRY(spk::launch_step<real>(d_desc, s.cfg, 0, 1, p->stream));
-    HIP_TRY(hipMemcpyAsync(p->h_res, h.res, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->h_res, h.res, 2 * spk::kResSlots * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
-    if (xi) {
-        std::memcpy(&xi[0], &p->h_res[0], 8);
-        std::memcpy(&xi[1], &p->h_res[1], 8);
-    }
+    if (xi) res_reduce(p->h_res, &xi[0], &xi[1]);
     return SPOCK_OK;
 }
 

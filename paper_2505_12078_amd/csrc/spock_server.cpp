@@ -33,7 +33,7 @@ struct SrvTree {
     int64_t id = 0;
     int n = 0, nx = 0, nu = 0, n_nl = 0;
     std::vector<int32_t> parent;
-    std::vector<double> prob, A, B, c, Q, R, QN, xlo, xhi, ulo, uhi, xNlo, xNhi, gamma, q, r, qN, Qe, Re, QNl;
+    std::vector<double> prob, A, B, c, Q, R, QN, xlo, xhi, ulo, uhi, xNlo, xNhi, gamma, q, r, qN, Qe, Re, QNl, Qd, Rd, QNd;
     double x_ball = 0, xN_ball = 0;
     size_t footprint = 0;
     spock_problem* p = nullptr;  // resident when non-null
@@ -57,6 +57,9 @@ struct SrvTree {
         d.Q_edge = Qe.empty() ? nullptr : Qe.data();
         d.R_edge = Re.empty() ? nullptr : Re.data();
         d.QN_leaf = QNl.empty() ? nullptr : QNl.data();
+        d.Q_dense = Qd.empty() ? nullptr : Qd.data();
+        d.R_dense = Rd.empty() ? nullptr : Rd.data();
+        d.QN_dense = QNd.empty() ? nullptr : QNd.data();
         d.x_lo = xlo.data();
         d.x_hi = xhi.data();
         d.u_lo = ulo.data();
@@ -500,6 +503,9 @@ int32_t spock_server_add_tree(spock_server* s, const spock_problem_desc* d, int6
     if (d->Q_edge) T.Qe.assign(d->Q_edge, d->Q_edge + n * nx);
     if (d->R_edge) T.Re.assign(d->R_edge, d->R_edge + n * nu);
     if (d->QN_leaf) T.QNl.assign(d->QN_leaf, d->QN_leaf + n * nx);
+    if (d->Q_dense) T.Qd.assign(d->Q_dense, d->Q_dense + n * nx * nx);
+    if (d->R_dense) T.Rd.assign(d->R_dense, d->R_dense + n * nu * nu);
+    if (d->QN_dense) T.QNd.assign(d->QN_dense, d->QN_dense + n * nx * nx);
     T.xlo.assign(d->x_lo, d->x_lo + nx);
     T.xhi.assign(d->x_hi, d->x_hi + nx);
     T.ulo.assign(d->u_lo, d->u_lo + nu);

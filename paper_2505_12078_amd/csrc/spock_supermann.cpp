@@ -122,10 +122,10 @@ int32_t supermann_iterate(spock_problem* p, long long budget, spock_info* info) 
         add(w.LR, w.R[cur] + nzp, ne);
         HIP_TRY(spk::launch_dots(ds, w.partial, w.dots, st));
         HIP_TRY(hipMemcpyAsync(w.h_dots, w.dots, ds.count * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(w.h_dots + spk::kMaxDots, p->d_res, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(w.h_dots + spk::kMaxDots, p->d_res, 2 * spk::kResSlots * sizeof(double),
+                               hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        std::memcpy(&x1, &w.h_dots[spk::kMaxDots], 8);
-        std::memcpy(&x2, &w.h_dots[spk::kMaxDots + 1], 8);
+        res_reduce(reinterpret_cast<const unsigned long long*>(w.h_dots + spk::kMaxDots), &x1, &x2);
         rel = rel_of(x1, x2, scale);
         if (k == 0) nT = 1;  // the step of v_0 was taken by the caller
         if (!std::isfinite(rel)) {

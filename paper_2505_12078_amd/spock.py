@@ -34,7 +34,7 @@ class ProblemDesc(C.Structure):
                 ("QN_diag", _dp), ("x_lo", _dp), ("x_hi", _dp), ("u_lo", _dp), ("u_hi", _dp),
                 ("xN_lo", _dp), ("xN_hi", _dp), ("x_ball", C.c_double), ("xN_ball", C.c_double),
                 ("gamma", _dp), ("q", _dp), ("r", _dp), ("qN", _dp), ("Q_edge", _dp), ("R_edge", _dp),
-                ("QN_leaf", _dp)]
+                ("QN_leaf", _dp), ("Q_dense", _dp), ("R_dense", _dp), ("QN_dense", _dp)]
 
 
 class Settings(C.Structure):
@@ -213,11 +213,16 @@ class _Desc:
             x_hi=_ptr(k["x_hi"]), u_lo=_ptr(k["u_lo"]), u_hi=_ptr(k["u_hi"]), xN_lo=_ptr(k["xN_lo"]),
             xN_hi=_ptr(k["xN_hi"]), x_ball=float(prob["x_ball"]), xN_ball=float(prob["xN_ball"]),
             gamma=_ptr(k["gamma"]), q=_ptr(k["q"]), r=_ptr(k["r"]), qN=_ptr(k["qN"]))
-        # cost diagonals given per edge / per leaf (one row per node)
-        for key, shared, per in (("Q", "Q_diag", "Q_edge"), ("R", "R_diag", "R_edge"), ("QN", "QN_diag", "QN_leaf")):
+        # cost diagonals given per edge / per leaf (one row per node), or
+        # dense matrices per edge / per leaf (one matrix per node)
+        for key, shared, per, dense in (("Q", "Q_diag", "Q_edge", "Q_dense"), ("R", "R_diag", "R_edge", "R_dense"),
+                                        ("QN", "QN_diag", "QN_leaf", "QN_dense")):
             if k[key].ndim == 2:
                 setattr(self.desc, shared, None)
                 setattr(self.desc, per, _ptr(k[key]))
+            elif k[key].ndim == 3:
+                setattr(self.desc, shared, None)
+                setattr(self.desc, dense, _ptr(k[key]))
 
 
 def footprint(prob, settings=None):

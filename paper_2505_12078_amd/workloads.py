@@ -169,12 +169,14 @@ def _guard_x0(x0, parent, A, x_hi, x_ball, xN_hi, xN_ball, n_nl, margin=0.9):
 
 def make_problem(parent, nx, nu, rng, *, prob_kind="uniform", gamma=0.95,
                  x_box=5.0, u_box=1.0, x_ball=0.0, q=1.0, r=0.1, qn=1.0,
-                 affine=False, linear=False, edge_costs=False, x0_range=2.0, name="custom"):
+                 affine=False, linear=False, edge_costs=False, dense_costs=False, x0_range=2.0, name="custom"):
     """Draw a full problem on the given tree (draw order: probabilities, then
     A^i and B^i for i = 1..n-1, then x0, then the optional affine terms, then
     the optional linear cost terms q^j, r^j of the edge into j and qN^j of
     leaf j, each N(0, 0.25)), then the optional per-edge and per-leaf cost
-    diagonals Q^j = q u, R^j = r u, Q_N^j = qn u with u ~ U[0.5, 2] entrywise)."""
+    diagonals Q^j = q u, R^j = r u, Q_N^j = qn u with u ~ U[0.5, 2] entrywise),
+    then the optional dense per-edge and per-leaf costs
+    Q^j = q (I / 2 + W W^T / (2 nx)) with W ~ N(0, 1) entrywise (R^j, Q_N^j alike)."""
     parent = np.asarray(parent, dtype=np.int32)
     n = len(parent)
     n_nl = int(np.sum(np.bincount(parent[1:], minlength=n) > 0))
@@ -202,6 +204,11 @@ def make_problem(parent, nx, nu, rng, *, prob_kind="uniform", gamma=0.95,
         Qc = float(q) * rng.uniform(0.5, 2.0, size=(n, nx))
         Rc = float(r) * rng.uniform(0.5, 2.0, size=(n, nu))
         QNc = float(qn) * rng.uniform(0.5, 2.0, size=(n, nx))
+    if dense_costs:
+        def spd(scale, d):
+            W = rng.standard_normal((n, d, d))
+            return float(scale) * (0.5 * np.eye(d)[None] + np.einsum("nij,nkj->nik", W, W) / (2.0 * d))
+        Qc, Rc, QNc = spd(q, nx), spd(r, nu), spd(qn, nx)
     return dict(
         **lin,
         name=name, parent=parent, prob=prob, nx=int(nx), nu=int(nu), A=A, B=B, c=c,
@@ -263,7 +270,7 @@ def batch_problem(k, seed=3):
 
 
 def random_ragged_problem(seed, N=4, nx=3, nu=2, max_children=3, ball=True,
-                          affine=False, gamma=None, linear=False, edge_costs=False):
+                          affine=False, gamma=None, linear=False, edge_costs=False, dense_costs=False):
     """Irregular tree (each non-leaf has 1..max_children children), for tests."""
     rng = np.random.default_rng(np.random.SeedSequence([977, int(seed)]))
     counts = []
@@ -279,7 +286,7 @@ def random_ragged_problem(seed, N=4, nx=3, nu=2, max_children=3, ball=True,
         gamma = rng.uniform(0.05, 1.0, size=n_nl)
     return make_problem(parent, nx, nu, rng, prob_kind="dirichlet", gamma=gamma,
                         x_ball=(6.0 if ball else 0.0), affine=affine, linear=linear, edge_costs=edge_costs,
-                        name="ragged%d" % seed)
+                        dense_costs=dense_costs, name="ragged%d" % seed)
 
 
 def problem_sizes(p):
@@ -292,6 +299,92 @@ def problem_sizes(p):
     for j in range(1, n):
         stage[j] = stage[parent[j]] + 1
     return dict(n=n, n_nl=n_nl, n_leaf=n - n_nl, N=int(stage.max()), max_children=int(n_ch.max()))
+
+
+
+
+# ----------------------------------------------------------------------------
+# the benchmark case study (random problems of many sizes)
+# ----------------------------------------------------------------------------
+
+
+def _benchmark_sizes(rng, nu_max):
+    """N ~ U{5..15}, then (n_b, n_w, n_u) uniform on the set with
+    1 <= n_b <= 3, 2 <= n_w <= 10, 10 <= n_u <= nu_max and
+    1e3 <= n_v <= 1e5 (n_v = nx |nodes(0, N)| + nu |nodes(0, N-1)|, nx = 2 nu),
+    by rejection."""
+    N = int(rng.integers(5, 16))
+    while True:
+        nb = int(rng.integers(1, 4))
+        nw = int(rng.integers(2, 11))
+        nu = int(rng.integers(10, nu_max + 1))
+        nx = 2 * nu
+        widths = [nw ** min(t, nb) for t in range(N + 1)]
+        nv = nx * sum(widths) + nu * sum(widths[:-1])
+        if 1e3 <= nv <= 1e5:
+            return N, nb, nw, nu, nx, nv
+
+
+def benchmark_problem(k, nu_max=300, seed=1268):
+    """Instance k of the benchmark case study's random problems: horizon N,
+    a tree that branches into n_w events at each of its first n_b stages
+    (children of a branching node take events 1..n_w in order with base
+    probabilities pi ~ U(simplex); past stage n_b each node has one child,
+    which keeps its parent's event), nx = 2 nu; per event w:
+    A(w) = I + A^w, B(w) = B + B^w (A^w, B^w entries ~ N(0, 0.01), B ~ N(0, 1)),
+    Q(w) = (Q0 + Q^w)(Q0 + Q^w)^T, R(w) = (R0 + R^w)(R0 + R^w)^T
+    (Q0 = diag(U[0, 0.1]), R0 = diag(U[0, 100]), Q^w, R^w entries ~ N(0, 0.01)),
+    Q_N = Q0; boxes |x| <= xbar ~ U[1, 2], |u| <= ubar ~ U[0, 0.1]; AV@R_gamma
+    with gamma ~ U[0, 1]; x0_i ~ U[-xbar_i / 2, xbar_i / 2].  The edge into
+    node j carries its event's matrices.  nu_max caps n_u (the library takes
+    nx = 2 nu <= 256)."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), int(k)]))
+    N, nb, nw, nu, nx, nv = _benchmark_sizes(rng, nu_max)
+    parent, stage = tree_from_branching([nw] * min(nb, N) + [1] * (N - min(nb, N)))
+    n = len(parent)
+    kids = children_lists(parent)
+    pi = rng.dirichlet(np.ones(nw))
+    event = np.zeros(n, dtype=np.int64)
+    prob = np.zeros(n)
+    prob[0] = 1.0
+    for i in range(n):
+        if len(kids[i]) == nw and nw > 1:
+            for w, j in enumerate(kids[i]):
+                event[j] = w
+                prob[j] = pi[w]
+        elif kids[i]:
+            event[kids[i][0]] = event[i]
+            prob[kids[i][0]] = 1.0
+    sd = np.sqrt(0.01)
+    B = rng.standard_normal((nx, nu))
+    Aw = [np.eye(nx) + sd * rng.standard_normal((nx, nx)) for _ in range(nw)]
+    Bw = [B + sd * rng.standard_normal((nx, nu)) for _ in range(nw)]
+    q0 = rng.uniform(0.0, 0.1, size=nx)
+    r0 = rng.uniform(0.0, 100.0, size=nu)
+    Qw, Rw = [], []
+    for _ in range(nw):
+        M = np.diag(q0) + sd * rng.standard_normal((nx, nx))
+        Qw.append(M @ M.T)
+        M = np.diag(r0) + sd * rng.standard_normal((nu, nu))
+        Rw.append(M @ M.T)
+    xbar = rng.uniform(1.0, 2.0, size=nx)
+    ubar = rng.uniform(0.0, 0.1, size=nu)
+    gamma = float(rng.uniform(0.0, 1.0))
+    x0 = rng.uniform(-0.5 * xbar, 0.5 * xbar)
+    A = np.zeros((n, nx, nx))
+    Bn = np.zeros((n, nx, nu))
+    Q = np.zeros((n, nx, nx))
+    R = np.zeros((n, nu, nu))
+    for j in range(1, n):
+        A[j], Bn[j], Q[j], R[j] = Aw[event[j]], Bw[event[j]], Qw[event[j]], Rw[event[j]]
+    Q[0], R[0] = Qw[0], Rw[0]
+    QN = np.broadcast_to(np.diag(q0), (n, nx, nx)).copy()
+    n_nl = int(np.sum(np.bincount(parent[1:], minlength=n) > 0))
+    return dict(
+        name="bench%d_N%d_nb%d_nw%d_nu%d" % (k, N, nb, nw, nu), parent=parent, prob=prob, nx=nx, nu=nu,
+        A=A, B=Bn, c=None, Q=Q, R=R, QN=QN, x_lo=-xbar, x_hi=xbar.copy(), u_lo=-ubar, u_hi=ubar.copy(),
+        xN_lo=-xbar, xN_hi=xbar.copy(), x_ball=0.0, xN_ball=0.0, gamma=np.full(n_nl, gamma), x0=x0,
+        n_v=nv, events=event)
 
 
 # ----------------------------------------------------------------------------

@@ -127,3 +127,23 @@ def test_supermann_settings_are_validated(lib):
             S.footprint(p, S.default_settings(**bad))
         assert e.value.code == S.SPOCK_E_INVALID
 
+
+
+def test_dense_costs_are_validated(lib):
+    """Dense per-edge / per-leaf cost matrices: the footprint counts one
+    square root per edge and leaf; a non-symmetric or non-finite matrix is
+    rejected (definiteness is checked when the square roots are taken)."""
+    p = W.random_ragged_problem(5, N=3, nx=3, nu=2, dense_costs=True)
+    shared = dict(p, Q=np.diagonal(p["Q"][1]).copy(), R=np.diagonal(p["R"][1]).copy(),
+                  QN=np.diagonal(p["QN"][-1]).copy())
+    n, nx, nu = len(p["parent"]), 3, 2
+    assert S.footprint(p) >= S.footprint(shared) + 8 * n * (nx * nx + nu * nu)
+    Q = p["Q"].copy()
+    Q[2, 0, 1] += 0.5  # not symmetric
+    assert "symmetric" in _bad(p, Q=Q)
+    R = p["R"].copy()
+    R[3, 1, 1] = np.inf
+    _bad(p, R=R)
+    b = W.benchmark_problem(1, nu_max=128)
+    assert b["nx"] == 2 * b["nu"] <= 256 and b["Q"].shape == (len(b["parent"]), b["nx"], b["nx"])
+    assert S.footprint(b) > 0

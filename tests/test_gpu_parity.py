@@ -89,6 +89,17 @@ def _cases():
     cases["edge_costs"] = W.random_ragged_problem(6, N=3, nx=2, nu=1, edge_costs=True)
     cases["edge_costs_lin"] = W.random_ragged_problem(9, N=4, nx=10, nu=4, max_children=4, linear=True,
                                                       edge_costs=True)
+    # dense per-edge stage costs and per-leaf terminal costs (symmetric
+    # square roots in L and L*): small, with linear terms, more than one row
+    # per lane (nx = 100), and an instance of the benchmark case study's random
+    # problems (nx = 84, nu = 42: event-dependent dense Q(w), R(w), Q_N = Q_0)
+    cases["dense"] = W.random_ragged_problem(5, N=3, nx=3, nu=2, dense_costs=True)
+    cases["dense_lin"] = W.random_ragged_problem(10, N=4, nx=12, nu=6, max_children=4, linear=True,
+                                                 dense_costs=True)
+    par, _ = W.tree_from_branching([2, 2, 1])
+    cases["dense_m150"] = W.make_problem(par, 100, 50, np.random.default_rng(22), prob_kind="dirichlet",
+                                         x_ball=15.0, dense_costs=True, linear=True, name="dense_m150")
+    cases["bench1"] = W.benchmark_problem(1, nu_max=128)
     return cases
 
 
@@ -136,11 +147,15 @@ def test_L_Lt_prox_match_oracle(name, precondition):
     with P:
         z = rng.standard_normal(P.nz) * 2
         e = rng.standard_normal(P.neta) * 2
-        assert _rel(P.apply_L(z), O.apply_L(D, z), 2) < 1e-12
-        assert _rel(P.apply_Lt(e), O.apply_Lt(D, e), 2) < 1e-12
+        # relative to the larger of the input and output scales: dense cost
+        # rows sum nx products of entries up to |Q^1/2| |x|
+        Lz, Lte = O.apply_L(D, z), O.apply_Lt(D, e)
+        sL, sLt = max(2.0, np.abs(Lz).max()), max(2.0, np.abs(Lte).max())
+        assert _rel(P.apply_L(z), Lz, sL) < 1e-12
+        assert _rel(P.apply_Lt(e), Lte, sLt) < 1e-12
         assert _rel(P.prox_gconj(e), O.prox_gconj(D, e, alpha), 2) < 1e-12
         # float32 kernels
-        assert _rel(P.apply_L(z, S.FP32), O.apply_L(D, z), 2) < 1e-5
+        assert _rel(P.apply_L(z, S.FP32), Lz, sL) < 1e-5
         assert _rel(P.prox_gconj(e, S.FP32), O.prox_gconj(D, e, alpha), 2) < 1e-5
 
 
@@ -218,7 +233,8 @@ def test_prox_f_parts(name):
 
 
 @pytest.mark.parametrize("name,steps", [("cfg0", 200), ("cfg1", 60), ("ragged_affine", 100), ("m150", 40),
-                                        ("m200", 20), ("linear_big", 60), ("edge_costs_lin", 60)])
+                                        ("m200", 20), ("linear_big", 60), ("edge_costs_lin", 60),
+                                        ("dense_lin", 60), ("bench1", 40)])
 def test_trajectory_matches_oracle(name, steps):
     """K plain CP steps from zero: T is firmly nonexpansive, so differences
     cannot amplify along the trajectory."""
@@ -407,6 +423,21 @@ def test_infeasible_x0_and_not_converged():
         assert r["code"] == S.SPOCK_E_NOT_CONVERGED and r["iters"] >= 10
 
 
+def test_dense_cost_not_positive_definite_is_rejected():
+    """A symmetric dense Q^j with a negative eigenvalue fails at setup with
+    SPOCK_E_INVALID (Prop. 1 takes Q > 0); a positive definite one is taken."""
+    prob = dict(CASES["dense"])
+    Q = prob["Q"].copy()
+    w, V = np.linalg.eigh(Q[2])
+    Q[2] = (V * np.concatenate([[-0.5], w[1:]])) @ V.T
+    Q[2] = 0.5 * (Q[2] + Q[2].T)
+    with pytest.raises(S.SpockError) as e:
+        S.Problem(dict(prob, Q=Q))
+    assert e.value.code == S.SPOCK_E_INVALID and "positive definite" in str(e.value)
+    with S.Problem(prob) as P:
+        assert P.n == len(prob["parent"])
+
+
 def test_torch_workspace_and_stream():
     """Device memory and the stream can come from PyTorch."""
     import torch
@@ -509,12 +540,13 @@ def test_setup_time_reported():
         assert 0 < r["t_setup_s"] < 60 and r["t_solve_s"] > 0
 
 
-def test_linear_cost_solution_matches_oracle():
-    """A ragged tree with linear stage and terminal cost terms solved in
-    float64 to rel_res 1e-6 against the oracle's solve and the nested risk
-    objective with the linear terms."""
+@pytest.mark.parametrize("name", ["linear", "dense"])
+def test_linear_cost_solution_matches_oracle(name):
+    """A ragged tree with linear stage and terminal cost terms (and one with
+    dense per-edge costs) solved in float64 to rel_res 1e-6 against the
+    oracle's solve and the nested risk objective with the same costs."""
     eps = 1e-6
-    prob = CASES["linear"]
+    prob = CASES[name]
     ref = O.solve(prob, eps=eps, max_iters=60000)
     with S.Problem(prob, S.default_settings(alpha=ref["alpha"], eps=eps, max_iters=200000, check_every=2)) as P:
         r = P.solve(prob["x0"])
@@ -524,7 +556,7 @@ def test_linear_cost_solution_matches_oracle():
         P.set_iterate(np.zeros(P.nz), np.zeros(P.neta))
         P.run_steps(K)
         zg, eg = P.get_iterate()
-    print("linear costs: GPU %d it s0 %.10g | oracle %d it s0 %.10g" % (r["iters"], s0, ref["iters"], ref["s0"]))
+    print("%s: GPU %d it s0 %.10g | oracle %d it s0 %.10g" % (name, r["iters"], s0, ref["iters"], ref["s0"]))
     assert r["code"] == S.SPOCK_OK and ref["status"] == "converged"
     assert abs(s0 - ref["s0"]) <= 10 * eps * max(1.0, abs(ref["s0"]))
     assert O.nested_cost(prob, x, u) == pytest.approx(s0, rel=10 * eps)

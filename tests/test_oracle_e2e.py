@@ -245,3 +245,33 @@ def test_per_edge_costs_nested_objective():
     assert O.dynamics_violation(p, r["x"], r["u"]) < 1e-10
     shared = dict(p, Q=p["Q"][1], R=p["R"][1], QN=p["QN"][-1])
     assert abs(O.nested_cost(shared, r["x"], r["u"]) - r["s0"]) > 1e-4
+
+
+def test_dense_costs_risk_neutral_special_case():
+    """Dense per-edge stage costs and per-leaf terminal costs with gamma = 1
+    and loose bounds: the probability-weighted Riccati recursion with each
+    edge's own dense matrices gives the unique (x, u) and V*."""
+    p = W.random_ragged_problem(6, N=3, nx=2, nu=1, ball=False, dense_costs=True)
+    p["gamma"] = np.ones_like(p["gamma"])
+    for k in ("x_lo", "x_hi", "u_lo", "u_hi", "xN_lo", "xN_hi"):
+        p[k] = p[k] * 1e3
+    V, x, u = O.risk_neutral_lq(p)
+    r = O.solve(p, eps=1e-8, max_iters=60000)
+    assert r["status"] == "converged"
+    assert r["s0"] == pytest.approx(V, rel=1e-7)
+    np.testing.assert_allclose(r["x"], x, atol=1e-6)
+    np.testing.assert_allclose(r["u"], u, atol=1e-6)
+
+
+def test_dense_costs_with_linear_terms_nested_objective():
+    """Dense costs, linear terms, AV@R risk and active bounds: s0 equals the
+    nested objective evaluated with the dense matrices; keeping only their
+    diagonals gives another optimum."""
+    p = W.random_ragged_problem(6, N=3, nx=2, nu=1, dense_costs=True, linear=True)
+    r = O.solve(p, eps=1e-6, max_iters=60000)
+    assert r["status"] == "converged"
+    assert O.nested_cost(p, r["x"], r["u"]) == pytest.approx(r["s0"], rel=1e-5)
+    assert O.dynamics_violation(p, r["x"], r["u"]) < 1e-10
+    diag = dict(p, Q=np.diagonal(p["Q"], axis1=1, axis2=2).copy(), R=np.diagonal(p["R"], axis1=1, axis2=2).copy(),
+                QN=np.diagonal(p["QN"], axis1=1, axis2=2).copy())
+    assert abs(O.nested_cost(diag, r["x"], r["u"]) - r["s0"]) > 1e-4

@@ -277,11 +277,13 @@ def _dense_L(D):
     return M
 
 
-@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("seed", range(8))
 def test_L_adjoint_and_norm(seed):
-    # seeds 4, 5: per-edge stage costs and per-leaf terminal costs
-    prob = W.random_ragged_problem(seed, N=3, nx=3, nu=2, ball=(seed % 2 == 0), edge_costs=(seed >= 4))
-    D = O.Data(prob, precondition=(seed < 2 or seed == 4))
+    # seeds 4, 5: per-edge stage costs and per-leaf terminal costs; 6, 7:
+    # dense ones
+    prob = W.random_ragged_problem(seed, N=3, nx=3, nu=2, ball=(seed % 2 == 0), edge_costs=(seed in (4, 5)),
+                                   dense_costs=(seed >= 6))
+    D = O.Data(prob, precondition=(seed < 2 or seed in (4, 6)))
     Y = D.layout
     rng = np.random.default_rng(seed)
     z, e = rng.standard_normal(Y.nz), rng.standard_normal(Y.neta)
@@ -339,6 +341,29 @@ def test_L_rows_match_problem_statement():
         assert Y.es(eta, i)[0] == pytest.approx(expect, rel=1e-12)
         np.testing.assert_allclose(Y.ec(eta, i)[:D.nx] * D.con_scale, xs[i], rtol=1e-12, atol=1e-12)
         np.testing.assert_allclose(Y.ec(eta, i)[D.nx:D.nx + D.nu] * D.con_scale, us[i], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("precond", [False, True])
+def test_L_rows_with_dense_costs(precond):
+    """Dense per-edge and per-leaf costs (Sec. 3.1): the squared cost rows of
+    each SOC block of L z equal x^T Q^j x + u^T R^j u of the ancestor with the
+    edge's own matrices (and x^T Q_N^j x at leaf j), in the original
+    variables."""
+    prob = W.random_ragged_problem(3, N=3, nx=3, nu=2, dense_costs=True)
+    D = O.Data(prob, precondition=precond)
+    Y, T = D.layout, D.tree
+    z = np.random.default_rng(2).standard_normal(Y.nz)
+    eta = O.apply_L(D, z)
+    x, u = np.array([Y.x(z, i) for i in range(T.n)]), np.array([Y.u(z, i) for i in range(T.n_nl)])
+    xs, us = D.unscale(x, u)
+    for j in range(1, T.n):
+        i = T.anc[j]
+        w = Y.esoc(eta, j)
+        cost = xs[i] @ prob["Q"][j] @ xs[i] + us[i] @ prob["R"][j] @ us[i]
+        assert np.sum(w[:-2] ** 2) == pytest.approx(cost, rel=1e-12)
+    for j in T.leaves:
+        w = Y.esocN(eta, j)
+        assert np.sum(w[:-2] ** 2) == pytest.approx(xs[j] @ prob["QN"][j] @ xs[j], rel=1e-12)
 
 
 def test_preconditioning_is_a_change_of_variables():
