@@ -546,7 +546,7 @@ def summarize_counters(fetch_dir, write_dir, trace_dir, profile_json, out_path=N
     import glob
     import re
 
-    pat = re.compile(r"k_(prep|bsweep|fsweep|dual)(?:_st)?<(float|double), (\d+)>")
+    pat = re.compile(r"k_(prep|bsweep|fsweep|dual)(?:_st)?<(float|double), (\d+)(?:, (?:true|false))?>")
 
     def rows(d, suffix):
         out = []
@@ -630,6 +630,8 @@ def main():
     ap.add_argument("--case-study", type=int, default=0,
                     help="instances of the benchmark case study's random problems to solve (0: skip)")
     ap.add_argument("--case-study-only", action="store_true", help="run only the case-study leg (one JSON line)")
+    ap.add_argument("--case-study-iters", type=int, default=20000, help="iteration cap per case-study solve")
+    ap.add_argument("--case-study-eps", type=float, default=1e-3)
     ap.add_argument("--batch-problems", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--no-batch-solve", action="store_true")
@@ -670,7 +672,8 @@ def main():
         from paper_2505_12078_amd import spock as S
         from paper_2505_12078_amd import workloads as W
         torch.cuda.set_device(0)
-        cs = case_study_bench(S, W, instances=args.case_study)
+        cs = case_study_bench(S, W, instances=args.case_study, eps=args.case_study_eps,
+                              max_iters=args.case_study_iters)
         if not args.no_cpu:
             cs["cpu_baseline"] = cpu_baseline_case_study(cs)
         print(json.dumps({"case_study": cs}))
@@ -742,7 +745,8 @@ def main():
     P.close()
     small = None if args.no_small else small_trees_bench(S, W)
     delay = None if args.no_delay else delay_bench(S, W)
-    case_study = case_study_bench(S, W, instances=args.case_study) if args.case_study > 0 else None
+    case_study = (case_study_bench(S, W, instances=args.case_study, eps=args.case_study_eps,
+                                   max_iters=args.case_study_iters) if args.case_study > 0 else None)
     batched = None
     if batch_in is not None:
         batched = batch_bench(S, *batch_in, steps=args.batch_steps + (args.batch_steps & 1), warmup=6,

@@ -37,6 +37,7 @@ spk::LaunchCfg batch_cfg(const spock_batch* b, int node_wg) {
         c.wave_elems = std::max(c.wave_elems, m.wave_elems);
         c.sweep_lds = std::max(c.sweep_lds, m.sweep_lds);
         for (int q = 0; q < 4; ++q) c.cls[q] = std::max(c.cls[q], m.cls[q]);
+        c.dense = std::max(c.dense, m.dense);
         cst = std::max(cst, spk::consts_elems(p->nx, p->nu));
     }
     auto lds = [&](int wg) { return (cst + (wg / 64) * c.wave_elems) * (int)sizeof(real); };

@@ -177,6 +177,7 @@ struct LaunchCfg {
     int wave_elems;          // LDS elements of one node wavefront
     int sweep_lds;           // dynamic LDS bytes of a sweep wavefront
     int cls[4];              // register tile class of prep, bsweep, fsweep, dual
+    int dense;               // some problem has dense costs (node kernels built with their products)
 };
 
 // Packed tiles of the column-lane products out[o] = sum_k A[k][o] v[k]
@@ -208,7 +209,11 @@ __host__ __device__ constexpr long long tile_pad_elems() { return (long long)kTi
 
 // Register tile classes of the column-lane products (rows per lane); a
 // product that does not fit its class runs from global memory instead.
+// kWideClass: the launch's product fits no class; its kernels keep a minimal
+// register tile and read every product from global memory with several row
+// groups in flight.
 constexpr int kTileClasses[4] = {16, 32, 64, 80};
+constexpr int kWideClass = 8;
 
 // Register rows a column-lane product needs: block 1 rows, and block 2 rows
 // times 4 (block 2 has a quarter of the class).

@@ -1247,8 +1247,8 @@ int tile_class(int need) {
     for (int c : spk::kTileClasses)
         if (need <= c) return c;
     // no class holds it: the product runs from the packed tile in global
-    // memory, and the smallest class keeps the unused register tile small
-    return spk::kTileClasses[0];
+    // memory, in kernels built for that (a minimal register tile)
+    return spk::kWideClass;
 }
 
 template <typename real>
@@ -1270,6 +1270,7 @@ spk::LaunchCfg make_cfg(const spock_problem* p, int node_wg) {
     c.cls[1] = tile_class(spk::col_need(nx, m, V));
     c.cls[2] = tile_class(spk::col_need(m, nx, V));
     c.cls[3] = tile_class(spk::col_need(nx, nu, V));
+    c.dense = (p->dense_edge || p->dense_leaf) ? 1 : 0;
     // float sweeps stage their tiles and vectors in LDS
     const int staged = sizeof(real) == 4 ? spk::stage_elems(nx, nu, V, c.cls[1], c.cls[2]) : 0;
     c.sweep_lds = spk::sweep_int_bytes(p->N) + (spk::sweep_elems(nx, nu) + staged) * (int)sizeof(real);

@@ -163,9 +163,12 @@ SPK_DEV const __attribute__((address_space(3))) T* lds(const T* p) {
 
 // sum_c H[c][r] x(c) for a symmetric n x n H in global memory: with r the
 // lane's row, consecutive lanes read consecutive addresses of row c of H
+// (used only by the node kernels built for dense costs, so the loads in
+// flight cost the other kernels no registers)
 template <typename real, typename X>
 SPK_DEV real sym_col_dot(const real* H, int n, int r, X x) {
     real s = 0;
+#pragma unroll 16
     for (int c = 0; c < n; ++c) s += gm(H)[(long long)c * n + r] * x(c);
     return s;
 }
@@ -174,6 +177,7 @@ SPK_DEV real sym_col_dot(const real* H, int n, int r, X x) {
 template <typename real, typename X, typename Y>
 SPK_DEV void sym_col_dot2(const real* H, int n, int r, X x, Y y, real& sx, real& sy) {
     real a = 0, b = 0;
+#pragma unroll 16
     for (int c = 0; c < n; ++c) {
         const real h = gm(H)[(long long)c * n + r];
         a += h * x(c);
@@ -475,18 +479,42 @@ SPK_DEV void col_apply(const ColTile<real, R>& T, const ColShape& s, const real*
 
 // The same product read from the packed tile in global memory (shapes beyond
 // the register class, and products of any width: one 64-column block after
-// the other, block b at columns 64 b ..).
-template <typename real>
+// the other, block b at columns 64 b ..).  kWide (the launches of problems whose
+// products fit no register class): a lane keeps kU 16-byte row groups of its
+// column in flight; otherwise one row at a time, four in flight, so that the
+// fallback adds few registers to kernels that rarely take it.  Both sum a
+// lane's rows in row order.
+template <bool kWide, typename real>
 SPK_DEV void col_direct(const real* __restrict__ tile, const ColShape& s, const real* v, real* out, real* red) {
     constexpr int V = 16 / (int)sizeof(real);
     const int lane = lane_id();
     auto part = [&](const real* blk, int rows, int W, int G) {
         const int g = lane / W;
         real acc = 0;
+        if constexpr (kWide) {
+            constexpr int kU = 16;
+            const int nv = rows / V;  // rows are a multiple of V
+            const __attribute__((address_space(1))) u32x4* p =
+                (const __attribute__((address_space(1))) u32x4*)blk + lane;
+            for (int q0 = 0; q0 < nv; q0 += kU) {
+                real buf[kU * V];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int q = q0 + u < nv ? q0 + u : nv - 1;  // stays inside the block
+                    unpack16<real>(p[(long long)q * 64], buf + u * V);
+                }
+#pragma unroll
+                for (int e = 0; e < kU * V; ++e) {
+                    const int i = q0 * V + e, k = g + i * G;
+                    if (i < rows && k < s.K) acc += buf[e] * v[k];
+                }
+            }
+        } else {
 #pragma unroll 4
-        for (int i = 0; i < rows; ++i) {
-            const int k = g + i * G;
-            if (k < s.K) acc += blk[((i / V) * 64 + lane) * V + (i % V)] * v[k];
+            for (int i = 0; i < rows; ++i) {
+                const int k = g + i * G;
+                if (k < s.K) acc += blk[((i / V) * 64 + lane) * V + (i % V)] * v[k];
+            }
         }
         return acc;
     };
@@ -531,7 +559,7 @@ struct ColProd {
     template <bool kPadded = false>
     SPK_DEV void apply(const real* v, real* out, real* red) const {
         if (fit) col_apply<kPadded>(T, s, v, out, red);
-        else col_direct(tile, s, v, out, red);
+        else col_direct<R == kWideClass>(tile, s, v, out, red);
     }
 };
 
@@ -683,7 +711,7 @@ SPK_DEV void fwd_block_risk(const ProbDev<real>* __restrict__ P, int v, long lon
 // SOC block of the edge into child j of non-leaf node v:
 // (Q^1/2 x^v, R^1/2 u^v, tau^j / 2, tau^j / 2) in SOC + a (one wavefront);
 // es: staged eta_soc of that edge, tn / tv: new / old tau^j.
-template <typename real, typename PT>
+template <typename real, bool kDense, typename PT>
 SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, real tn, real tv,
                            real* __restrict__ eout, const FwdNode<real>& V, int check, real& r1, real& r2) {
     const int lane = threadIdx.x & 63;
@@ -698,8 +726,8 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
     auto rh = [&](int r) { return re ? gm(re)[r] : V.C.rh[r]; };
     // dense costs: the cost rows H (S^-1 x) of the new and old iterate, first
     // into blk / dblk
-    const real* Hq = P->Hq_e ? P->Hq_e + (long long)j * nx * nx : nullptr;
-    const real* Hr = P->Hr_e ? P->Hr_e + (long long)j * P->nu * P->nu : nullptr;
+    const real* Hq = kDense && P->Hq_e ? P->Hq_e + (long long)j * nx * nx : nullptr;
+    const real* Hr = kDense && P->Hr_e ? P->Hr_e + (long long)j * P->nu * P->nu : nullptr;
     if (Hq) {
         wave_sync();
         for (int r = lane; r < nx; r += 64)
@@ -762,7 +790,7 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
 
 // Leaf v: eta_cN (box x ball) for which = 0, eta_socN (Q_N^1/2 x, s/2, s/2) for
 // which = 1 (one wavefront each); ec / es: the staged blocks.
-template <typename real>
+template <typename real, bool kDense>
 SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int which, const real* ec,
                             const real* es, real sn, real sv, real* __restrict__ eout, const FwdNode<real>& V,
                             int check, real& r1, real& r2) {
@@ -815,7 +843,7 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
         const real* aj = P->saN ? P->saN + lf * (nx + 2) : nullptr;
         const real* qe = P->qnh_l ? P->qnh_l + lf * nx : nullptr;
         auto qnh = [&](int r) { return qe ? gm(qe)[r] : V.C.qnh[r]; };
-        const real* Hq = P->HqN_l ? P->HqN_l + lf * nx * nx : nullptr;
+        const real* Hq = kDense && P->HqN_l ? P->HqN_l + lf * nx * nx : nullptr;
         if (Hq) {
             for (int r = lane; r < nx; r += 64)
                 sym_col_dot2(
@@ -869,7 +897,7 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
 // One wavefront per node; the workgroup's wavefronts take consecutive entries
 // of the node task table, which never mixes problems inside one workgroup
 // (entries with node -1 pad a problem to a multiple of kMaxNodeWaves).
-template <typename real, int R>
+template <typename real, int R, bool kDense>
 __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ probs,
                                               const int2* __restrict__ ntasks, const int4* __restrict__ ninfo,
                                               int wave_elems, int par, int check) {
@@ -905,7 +933,7 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         const int fc = ni.x, k = ni.y;
         const long long yo = ni.z;
         const bool leafkids = fc >= n_nl;
-        const bool sk = k <= P->stage_kids;  // per-child inputs staged, else read in place
+        const bool sk = k <= kStageKids && k <= P->stage_kids;  // per-child inputs staged, else read in place
         const int kk = sk ? k : 0;
         // K^T ubar: rows r < nu of [K | R~^-1], columns c < nx
         ColProd<real, R> TK;
@@ -940,7 +968,7 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         // of every child edge (Sec. 4.4)
         for (int r = lane; r < nx; r += 64) {
             real s = 0;
-            if (P->Hq_e) {  // dense: S^-1 sum over child edges of H^j eta^j
+            if (kDense && P->Hq_e) {  // dense: S^-1 sum over child edges of H^j eta^j
                 for (int q = 0; q < k; ++q)
                     s += sym_col_dot(P->Hq_e + (long long)(fc + q) * nx * nx, nx, r,
                                      [&](int c) { return soc[q * (m + 2) + c]; });
@@ -957,7 +985,7 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         }
         for (int r = lane; r < nu; r += 64) {
             real s = 0;
-            if (P->Hr_e) {
+            if (kDense && P->Hr_e) {
                 for (int q = 0; q < k; ++q)
                     s += sym_col_dot(P->Hr_e + (long long)(fc + q) * nu * nu, nu, r,
                                      [&](int c) { return soc[q * (m + 2) + nx + c]; });
@@ -1044,7 +1072,7 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         const real* ss = st + off[2];
         const real* spc = st + off[3];
         for (int r = lane; r < nx; r += 64) {
-            const real cost = P->HqN_l ? C.qnh[r] * sym_col_dot(P->HqN_l + lf * nx * nx, nx, r,
+            const real cost = kDense && P->HqN_l ? C.qnh[r] * sym_col_dot(P->HqN_l + lf * nx * nx, nx, r,
                                                                  [&](int c) { return ss[c]; })
                                        : (P->qnh_l ? gm(P->qnh_l)[lf * nx + r] : C.qnh[r]) * ss[r];
             real lt = C.gxN[r] * sc[r] + cost;
@@ -1079,7 +1107,7 @@ constexpr int kMsgFast = 4;
 template <typename real, int R>
 struct BLevel {
     ColProd<real, R> TM;
-    ColProd<real, 16> TR;
+    ColProd<real, R == kWideClass ? kWideClass : 16> TR;
     real h0r[kVecPL], ubr[kVecPL];
 };
 
@@ -1475,7 +1503,7 @@ __global__ __launch_bounds__(64) void k_bsweep_st(const ProbDev<real>* __restric
     }
     wave_sync();
     ColProd<real, R> TM;
-    ColProd<real, 16> TR;
+    ColProd<real, R == kWideClass ? kWideClass : 16> TR;
     // level data of node i into slot b (the root stages node 1's [Abar|B], unused)
     auto stage = [&](int i, int b) {
         col_dma<real, R>(P->T2M + (i > 0 ? i : 1) * P->T2M_stride, sM, stM);
@@ -1643,7 +1671,7 @@ __global__ __launch_bounds__(64) void k_fsweep_st(const ProbDev<real>* __restric
 // dual: node-parallel forward half-step
 // ---------------------------------------------------------------------------
 
-template <typename real, int R>
+template <typename real, int R, bool kDense>
 __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ probs,
                                               const int2* __restrict__ ntasks, const int4* __restrict__ ninfo,
                                               int wave_elems, int par, int check) {
@@ -1679,7 +1707,7 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
     if (v < n_nl) {
         const int fc = ni.x, k = ni.y;
         const long long yo = ni.z;
-        const bool sk = k <= P->stage_kids;
+        const bool sk = k <= kStageKids && k <= P->stage_kids;
         const int kk = sk ? k : 0, ky = sk ? 2 * k + 1 : 0;
         ColProd<real, R> TK;  // u = K x + d
         TK.load(P->T4 + v * P->T4_stride, col_shape<real>(nx, nu));
@@ -1727,7 +1755,7 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
             fwd_block_risk(P, v, yo, k, ey, st[off[7]], yn, yv, st[off[10]], st[off[11]], pr, eout, check, r1, r2);
             wave_sync();
             for (int q = 0; q < k; ++q) {
-                fwd_block_soc(P, fc + q, soc + q * (m + 2), tn[q], tv[q], eout, V, check, r1, r2);
+                fwd_block_soc<real, kDense>(P, fc + q, soc + q * (m + 2), tn[q], tv[q], eout, V, check, r1, r2);
                 wave_sync();
             }
         };
@@ -1761,9 +1789,9 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
         const real* xn = st + off[0];
         const real* xo = st + off[1];
         const FwdNode<real> V{C, xn, un, xo, xo, blk, dblk, lxw, luw};
-        fwd_block_leaf(P, v, 0, st + off[2], st + off[3], st[off[4]], st[off[5]], eout, V, check, r1, r2);
+        fwd_block_leaf<real, kDense>(P, v, 0, st + off[2], st + off[3], st[off[4]], st[off[5]], eout, V, check, r1, r2);
         wave_sync();
-        fwd_block_leaf(P, v, 1, st + off[2], st + off[3], st[off[4]], st[off[5]], eout, V, check, r1, r2);
+        fwd_block_leaf<real, kDense>(P, v, 1, st + off[2], st + off[3], st[off[4]], st[off[5]], eout, V, check, r1, r2);
         wave_sync();
         if (check)
             for (int r = lane; r < nx; r += 64) r1 = nmax(r1, fabs((xo[r] - xn[r]) * ialpha - lxw[r]));
@@ -2012,27 +2040,38 @@ __global__ __launch_bounds__(256) void k_combo(double* out, VecCombo cb, long lo
 // Block partial sums of every dot product of the set; each block strides
 // over the whole vector with a fixed assignment, so the result does not
 // depend on timing.
+// All products of the set advance together over the entries, so a vector
+// that several of them read is fetched from memory once (the repeats hit the
+// cache); each sum still runs over the thread's entries in order.
 __global__ __launch_bounds__(256) void k_dots(DotSet ds, double* partial) {
     __shared__ double red[4];
-    for (int j = 0; j < ds.count; ++j) {
-        const double* a = ds.a[j];
-        const double* b = ds.b[j];
-        double s = 0.0;
-        for (long long k = blockIdx.x * 256LL + threadIdx.x; k < ds.n[j]; k += (long long)gridDim.x * 256)
-            s += a[k] * b[k];
-        s = block_sum<256>(s, red);
-        if (threadIdx.x == 0) partial[j * gridDim.x + blockIdx.x] = s;
+    double s[kMaxDots];
+    long long nmax = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxDots; ++j) {
+        s[j] = 0.0;
+        if (j < ds.count && ds.n[j] > nmax) nmax = ds.n[j];
+    }
+    for (long long k = blockIdx.x * 256LL + threadIdx.x; k < nmax; k += (long long)gridDim.x * 256) {
+#pragma unroll
+        for (int j = 0; j < kMaxDots; ++j)
+            if (j < ds.count && k < ds.n[j]) s[j] += ds.a[j][k] * ds.b[j][k];
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxDots; ++j) {
+        if (j >= ds.count) break;
+        const double t = block_sum<256>(s[j], red);
+        if (threadIdx.x == 0) partial[j * gridDim.x + blockIdx.x] = t;
     }
 }
 
-// One wavefront adds the block partials of each dot product in a fixed order.
-__global__ __launch_bounds__(64) void k_dots_final(const double* partial, int blocks, int count, double* out) {
-    for (int j = 0; j < count; ++j) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < blocks; b += 64) s += partial[j * blocks + b];
-        s = wave_sum(s);
-        if (threadIdx.x == 0) out[j] = s;
-    }
+// Wavefront j adds the block partials of dot product j in a fixed order.
+__global__ __launch_bounds__(64) void k_dots_final(const double* partial, int blocks, double* out) {
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < blocks; b += 64) s += partial[j * blocks + b];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) out[j] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -2045,8 +2084,12 @@ static hipError_t launch_phase_r(const ProbDev<real>* probs, const LaunchCfg& c,
     const int waves = c.node_wg / 64;
     switch (phase) {
         case 0:
-            hipLaunchKernelGGL((k_prep<real, R>), dim3(c.n_node_tasks / waves), dim3(c.node_wg), c.node_lds, st,
-                               probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
+            if (c.dense)
+                hipLaunchKernelGGL((k_prep<real, R, true>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
+                                   c.node_lds, st, probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
+            else
+                hipLaunchKernelGGL((k_prep<real, R, false>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
+                                   c.node_lds, st, probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
             break;
         case 1:
             if constexpr (sizeof(real) == 4)
@@ -2065,8 +2108,12 @@ static hipError_t launch_phase_r(const ProbDev<real>* probs, const LaunchCfg& c,
                                    c.leaf_tasks, par);
             break;
         default:
-            hipLaunchKernelGGL((k_dual<real, R>), dim3(c.n_node_tasks / waves), dim3(c.node_wg), c.node_lds, st,
-                               probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
+            if (c.dense)
+                hipLaunchKernelGGL((k_dual<real, R, true>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
+                                   c.node_lds, st, probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
+            else
+                hipLaunchKernelGGL((k_dual<real, R, false>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
+                                   c.node_lds, st, probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
             break;
     }
     return hipGetLastError();
@@ -2079,6 +2126,7 @@ hipError_t launch_phase(const ProbDev<real>* probs, const LaunchCfg& c, int phas
     if (phase < 0 || phase > 3 || c.n_leaf_tasks <= 0 || c.n_node_tasks <= 0) return hipErrorInvalidValue;
     if (c.node_wg != 64 && c.node_wg != 128 && c.node_wg != 256 && c.node_wg != 512) return hipErrorInvalidValue;
     switch (c.cls[phase]) {
+        case kWideClass: return launch_phase_r<real, kWideClass>(probs, c, phase, par, check, st);
         case 16: return launch_phase_r<real, 16>(probs, c, phase, par, check, st);
         case 32: return launch_phase_r<real, 32>(probs, c, phase, par, check, st);
         case 64: return launch_phase_r<real, 64>(probs, c, phase, par, check, st);
@@ -2145,7 +2193,7 @@ hipError_t launch_combo(double* out, const VecCombo& cb, long long n, hipStream_
 hipError_t launch_dots(const DotSet& ds, double* partial, double* out, hipStream_t st) {
     if (ds.count < 1 || ds.count > kMaxDots) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_dots, dim3(kDotBlocks), dim3(256), 0, st, ds, partial);
-    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(64), 0, st, (const double*)partial, kDotBlocks, ds.count, out);
+    hipLaunchKernelGGL(k_dots_final, dim3(ds.count), dim3(64), 0, st, (const double*)partial, kDotBlocks, out);
     return hipGetLastError();
 }
 
