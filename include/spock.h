@@ -116,6 +116,22 @@ typedef struct spock_problem_desc {
     const double* Q_dense;
     const double* R_dense;
     const double* QN_dense;
+    /* Optional general constraints (Sec. 3.1, the set C a box): at every
+     * non-leaf node Gamma_x x + Gamma_u u in [con_lo, con_hi], Gamma the
+     * n_con x (nx + nu) row-major matrix [Gamma_x | Gamma_u]; at every leaf
+     * Gamma_N x in [conN_lo, conN_hi], GammaN n_conN x nx.  Bounds may be
+     * infinite (one-sided rows), never NaN, and lo <= hi.  A non-NULL Gamma
+     * replaces x_lo, x_hi, u_lo, u_hi and x_ball at non-leaf nodes (the root
+     * x0 is then not checked against them); a non-NULL GammaN replaces xN_lo,
+     * xN_hi and xN_ball.  1 <= n_con, n_conN <= 512. */
+    int32_t n_con;
+    const double* Gamma;
+    const double* con_lo;
+    const double* con_hi;
+    int32_t n_conN;
+    const double* GammaN;
+    const double* conN_lo;
+    const double* conN_hi;
 } spock_problem_desc;
 
 typedef struct spock_settings {

@@ -202,31 +202,52 @@ class Data:
         self.Rh_e = [_sym_sqrt(Rs[j]) / Su[None, :] for j in range(n)]
         self.QNh_l = [_sym_sqrt(QNs[j]) / SxN[None, :] for j in range(n)]
 
-        # non-leaf constraint Gamma_x x + Gamma_u u in C = box(x) x box(u) [x ball(x)]
+        # non-leaf constraint Gamma_x x + Gamma_u u in C (Sec. 3.1): C a box
+        # [c_lo, c_hi] for general Gamma (prob["Gamma_x"], prob["Gamma_u"]),
+        # else box(x) x box(u) [x ball(x)]
         Ix, Iu = np.eye(nx), np.eye(nu)
-        Gx = [Ix, np.zeros((nu, nx))]
-        Gu = [np.zeros((nx, nu)), Iu]
-        lo = [np.asarray(prob["x_lo"], float), np.asarray(prob["u_lo"], float)]
-        hi = [np.asarray(prob["x_hi"], float), np.asarray(prob["u_hi"], float)]
-        if ball:
-            Gx.append(Ix)
-            Gu.append(np.zeros((nx, nu)))
-        Gx = np.vstack(Gx) / Sx[None, :]
-        Gu = np.vstack(Gu) / Su[None, :]
+        self.general = prob.get("Gamma_x") is not None
+        if self.general:
+            ball = False
+            Gx = np.asarray(prob["Gamma_x"], float)
+            Gu = np.asarray(prob["Gamma_u"], float)
+            lo, hi = [np.asarray(prob["c_lo"], float)], [np.asarray(prob["c_hi"], float)]
+        else:
+            Gx = [Ix, np.zeros((nu, nx))]
+            Gu = [np.zeros((nx, nu)), Iu]
+            lo = [np.asarray(prob["x_lo"], float), np.asarray(prob["u_lo"], float)]
+            hi = [np.asarray(prob["x_hi"], float), np.asarray(prob["u_hi"], float)]
+            if ball:
+                Gx.append(Ix)
+                Gu.append(np.zeros((nx, nu)))
+            Gx, Gu = np.vstack(Gx), np.vstack(Gu)
+        self.has_ball = ball
+        Gx = Gx / Sx[None, :]
+        Gu = Gu / Su[None, :]
         a = max(1.0, np.linalg.norm(np.hstack([Gx, Gu]), 2)) if precondition else 1.0
         self.Gx, self.Gu = Gx / a, Gu / a
         self.box_lo = np.concatenate(lo) / a
         self.box_hi = np.concatenate(hi) / a
-        self.nbox = nx + nu
+        self.nbox = self.box_lo.size
         self.ball_r = float(prob["x_ball"]) / a if ball else 0.0
         self.con_scale = a
-        # leaf constraint Gamma_N x in C_N = box(x) [x ball(x)]
-        GN = [Ix] + ([Ix] if ballN else [])
-        GN = np.vstack(GN) / SxN[None, :]
+        # leaf constraint Gamma_N x in C_N: a box [cN_lo, cN_hi] for general
+        # Gamma_N (prob["Gamma_N"]), else box(x) [x ball(x)]
+        self.generalN = prob.get("Gamma_N") is not None
+        if self.generalN:
+            ballN = False
+            GN = np.asarray(prob["Gamma_N"], float)
+            loN, hiN = np.asarray(prob["cN_lo"], float), np.asarray(prob["cN_hi"], float)
+        else:
+            GN = np.vstack([Ix] + ([Ix] if ballN else []))
+            loN, hiN = np.asarray(prob["xN_lo"], float), np.asarray(prob["xN_hi"], float)
+        self.has_ballN = ballN
+        GN = GN / SxN[None, :]
         aN = max(1.0, np.linalg.norm(GN, 2)) if precondition else 1.0
         self.GN = GN / aN
-        self.boxN_lo = np.asarray(prob["xN_lo"], float) / aN
-        self.boxN_hi = np.asarray(prob["xN_hi"], float) / aN
+        self.boxN_lo = loN / aN
+        self.boxN_hi = hiN / aN
+        self.nboxN = self.boxN_lo.size
         self.ballN_r = float(prob["xN_ball"]) / aN if ballN else 0.0
         self.con_scaleN = aN
         self.nc = self.Gx.shape[0]
@@ -557,9 +578,9 @@ def project_S3(D, eta):
         Y.esoc(out, j)[:] = a + proj_soc(v - a)
     for j in T.leaves:
         c = Y.ecN(eta, j)
-        pc = np.clip(c[:D.nx], D.boxN_lo, D.boxN_hi)
+        pc = np.clip(c[:D.nboxN], D.boxN_lo, D.boxN_hi)
         if D.has_ballN:
-            pc = np.concatenate([pc, proj_ball(c[D.nx:], D.ballN_r)])
+            pc = np.concatenate([pc, proj_ball(c[D.nboxN:], D.ballN_r)])
         Y.ecN(out, j)[:] = pc
         v = Y.esocN(eta, j)
         a = leaf_shift(D, j)

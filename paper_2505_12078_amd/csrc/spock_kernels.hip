@@ -2039,29 +2039,18 @@ __global__ __launch_bounds__(256) void k_combo(double* out, VecCombo cb, long lo
 
 // Block partial sums of every dot product of the set; each block strides
 // over the whole vector with a fixed assignment, so the result does not
-// depend on timing.
-// All products of the set advance together over the entries, so a vector
-// that several of them read is fetched from memory once (the repeats hit the
-// cache); each sum still runs over the thread's entries in order.
+// depend on timing.  (One pass per product: a fused pass over all products
+// of a set, which reads a shared vector once, measured slower.)
 __global__ __launch_bounds__(256) void k_dots(DotSet ds, double* partial) {
     __shared__ double red[4];
-    double s[kMaxDots];
-    long long nmax = 0;
-#pragma unroll
-    for (int j = 0; j < kMaxDots; ++j) {
-        s[j] = 0.0;
-        if (j < ds.count && ds.n[j] > nmax) nmax = ds.n[j];
-    }
-    for (long long k = blockIdx.x * 256LL + threadIdx.x; k < nmax; k += (long long)gridDim.x * 256) {
-#pragma unroll
-        for (int j = 0; j < kMaxDots; ++j)
-            if (j < ds.count && k < ds.n[j]) s[j] += ds.a[j][k] * ds.b[j][k];
-    }
-#pragma unroll
-    for (int j = 0; j < kMaxDots; ++j) {
-        if (j >= ds.count) break;
-        const double t = block_sum<256>(s[j], red);
-        if (threadIdx.x == 0) partial[j * gridDim.x + blockIdx.x] = t;
+    for (int j = 0; j < ds.count; ++j) {
+        const double* a = ds.a[j];
+        const double* b = ds.b[j];
+        double s = 0.0;
+        for (long long k = blockIdx.x * 256LL + threadIdx.x; k < ds.n[j]; k += (long long)gridDim.x * 256)
+            s += a[k] * b[k];
+        s = block_sum<256>(s, red);
+        if (threadIdx.x == 0) partial[j * gridDim.x + blockIdx.x] = s;
     }
 }
 

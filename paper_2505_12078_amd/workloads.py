@@ -169,14 +169,21 @@ def _guard_x0(x0, parent, A, x_hi, x_ball, xN_hi, xN_ball, n_nl, margin=0.9):
 
 def make_problem(parent, nx, nu, rng, *, prob_kind="uniform", gamma=0.95,
                  x_box=5.0, u_box=1.0, x_ball=0.0, q=1.0, r=0.1, qn=1.0,
-                 affine=False, linear=False, edge_costs=False, dense_costs=False, x0_range=2.0, name="custom"):
+                 affine=False, linear=False, edge_costs=False, dense_costs=False, general_con=False,
+                 x0_range=2.0, name="custom"):
     """Draw a full problem on the given tree (draw order: probabilities, then
     A^i and B^i for i = 1..n-1, then x0, then the optional affine terms, then
     the optional linear cost terms q^j, r^j of the edge into j and qN^j of
     leaf j, each N(0, 0.25)), then the optional per-edge and per-leaf cost
     diagonals Q^j = q u, R^j = r u, Q_N^j = qn u with u ~ U[0.5, 2] entrywise),
     then the optional dense per-edge and per-leaf costs
-    Q^j = q (I / 2 + W W^T / (2 nx)) with W ~ N(0, 1) entrywise (R^j, Q_N^j alike)."""
+    Q^j = q (I / 2 + W W^T / (2 nx)) with W ~ N(0, 1) entrywise (R^j, Q_N^j alike),
+    then the optional general constraints: the box rows of x and u plus
+    max(1, nx / 2) coupling rows W_x x + W_u u (entries N(0, 1/nx), N(0, 1/nu))
+    at non-leaf nodes and the box rows of x plus as many rows W_N x at leaves,
+    each coupling row bounded by +-(1.5 c + 0.5), c its largest magnitude along
+    the zero-input rollout from x0 (so the instance stays strictly feasible);
+    no ball then."""
     parent = np.asarray(parent, dtype=np.int32)
     n = len(parent)
     n_nl = int(np.sum(np.bincount(parent[1:], minlength=n) > 0))
@@ -209,8 +216,26 @@ def make_problem(parent, nx, nu, rng, *, prob_kind="uniform", gamma=0.95,
             W = rng.standard_normal((n, d, d))
             return float(scale) * (0.5 * np.eye(d)[None] + np.einsum("nij,nkj->nik", W, W) / (2.0 * d))
         Qc, Rc, QNc = spd(q, nx), spd(r, nu), spd(qn, nx)
+    gen = {}
+    if general_con:
+        ncx = max(1, nx // 2)
+        Wx = rng.standard_normal((ncx, nx)) / np.sqrt(nx)
+        Wu = rng.standard_normal((ncx, nu)) / np.sqrt(nu)
+        WN = rng.standard_normal((ncx, nx)) / np.sqrt(nx)
+        xs = np.zeros((n, nx))
+        xs[0] = x0
+        for j in range(1, n):
+            xs[j] = A[j] @ xs[int(parent[j])] + (c[j] if c is not None else 0.0)
+        cb = 1.5 * np.abs(xs[:n_nl] @ Wx.T).max(axis=0) + 0.5
+        cbN = 1.5 * np.abs(xs[n_nl:] @ WN.T).max(axis=0) + 0.5
+        gen = dict(Gamma_x=np.vstack([np.eye(nx), np.zeros((nu, nx)), Wx]),
+                   Gamma_u=np.vstack([np.zeros((nx, nu)), np.eye(nu), Wu]),
+                   c_lo=np.concatenate([-x_hi, -u_hi, -cb]), c_hi=np.concatenate([x_hi, u_hi, cb]),
+                   Gamma_N=np.vstack([np.eye(nx), WN]),
+                   cN_lo=np.concatenate([-x_hi, -cbN]), cN_hi=np.concatenate([x_hi, cbN]))
+        x_ball = 0.0
     return dict(
-        **lin,
+        **lin, **gen,
         name=name, parent=parent, prob=prob, nx=int(nx), nu=int(nu), A=A, B=B, c=c,
         Q=Qc, R=Rc, QN=QNc,
         x_lo=-x_hi.copy(), x_hi=x_hi.copy(), u_lo=-u_hi.copy(), u_hi=u_hi.copy(),
@@ -270,7 +295,8 @@ def batch_problem(k, seed=3):
 
 
 def random_ragged_problem(seed, N=4, nx=3, nu=2, max_children=3, ball=True,
-                          affine=False, gamma=None, linear=False, edge_costs=False, dense_costs=False):
+                          affine=False, gamma=None, linear=False, edge_costs=False, dense_costs=False,
+                          general_con=False):
     """Irregular tree (each non-leaf has 1..max_children children), for tests."""
     rng = np.random.default_rng(np.random.SeedSequence([977, int(seed)]))
     counts = []
@@ -286,7 +312,7 @@ def random_ragged_problem(seed, N=4, nx=3, nu=2, max_children=3, ball=True,
         gamma = rng.uniform(0.05, 1.0, size=n_nl)
     return make_problem(parent, nx, nu, rng, prob_kind="dirichlet", gamma=gamma,
                         x_ball=(6.0 if ball else 0.0), affine=affine, linear=linear, edge_costs=edge_costs,
-                        dense_costs=dense_costs, name="ragged%d" % seed)
+                        dense_costs=dense_costs, general_con=general_con, name="ragged%d" % seed)
 
 
 def problem_sizes(p):

@@ -277,13 +277,13 @@ def _dense_L(D):
     return M
 
 
-@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("seed", range(10))
 def test_L_adjoint_and_norm(seed):
     # seeds 4, 5: per-edge stage costs and per-leaf terminal costs; 6, 7:
-    # dense ones
+    # dense ones; 8, 9: general constraint matrices (with dense costs in 9)
     prob = W.random_ragged_problem(seed, N=3, nx=3, nu=2, ball=(seed % 2 == 0), edge_costs=(seed in (4, 5)),
-                                   dense_costs=(seed >= 6))
-    D = O.Data(prob, precondition=(seed < 2 or seed in (4, 6)))
+                                   dense_costs=(seed in (6, 7, 9)), general_con=(seed >= 8))
+    D = O.Data(prob, precondition=(seed < 2 or seed in (4, 6, 8)))
     Y = D.layout
     rng = np.random.default_rng(seed)
     z, e = rng.standard_normal(Y.nz), rng.standard_normal(Y.neta)
@@ -505,3 +505,52 @@ def test_delay_instance_is_ill_conditioned_for_float64():
         scale = max(np.abs(x1).max(), np.abs(u1).max())
         err = max(np.abs(x1 - x2).max(), np.abs(u1 - u2).max()) / scale
         assert lo <= err <= hi, err
+
+
+def test_general_constraints_reduce_to_the_box():
+    """Sec. 3.1 with Gamma_x = [I; 0], Gamma_u = [0; I] and C the box of x and
+    u (Gamma_N = I at the leaves) is the box-constrained problem: the same
+    scaled data, the same L and the same CP iterates."""
+    p = W.random_ragged_problem(5, N=2, nx=3, nu=2, ball=False)
+    nx, nu = 3, 2
+    g = dict(p, Gamma_x=np.vstack([np.eye(nx), np.zeros((nu, nx))]),
+             Gamma_u=np.vstack([np.zeros((nx, nu)), np.eye(nu)]),
+             c_lo=np.concatenate([p["x_lo"], p["u_lo"]]), c_hi=np.concatenate([p["x_hi"], p["u_hi"]]),
+             Gamma_N=np.eye(nx), cN_lo=p["xN_lo"].copy(), cN_hi=p["xN_hi"].copy())
+    for precond in (False, True):
+        Db, Dg = O.Data(p, precondition=precond), O.Data(g, precondition=precond)
+        np.testing.assert_array_equal(Db.Gx, Dg.Gx)
+        np.testing.assert_array_equal(Db.box_hi, Dg.box_hi)
+        np.testing.assert_array_equal(Db.GN, Dg.GN)
+        assert O.L_norm(Db) == O.L_norm(Dg)
+    rb = O.solve(p, eps=1e-6, max_iters=40000)
+    rg = O.solve(g, eps=1e-6, max_iters=40000)
+    assert rb["iters"] == rg["iters"]
+    np.testing.assert_array_equal(rb["z"], rg["z"])
+
+
+def test_general_constraints_hold_at_the_solution():
+    """General constraint rows (box rows plus coupling rows W_x x + W_u u at
+    non-leaf nodes, W_N x at leaves): the solution satisfies every row within
+    the tolerance's reach, its s0 is the nested objective, and the coupling
+    rows shape it (scaled-down bounds change the optimum)."""
+    p = W.random_ragged_problem(3, N=2, nx=3, nu=2, general_con=True)
+    r = O.solve(p, eps=1e-6, max_iters=60000)
+    assert r["status"] == "converged"
+    x, u = r["x"], r["u"]
+    T = O.Tree(p["parent"], p["prob"])
+    for i in T.nonleaf:
+        row = p["Gamma_x"] @ x[i] + p["Gamma_u"] @ u[i]
+        assert np.all(row >= p["c_lo"] - 1e-4) and np.all(row <= p["c_hi"] + 1e-4)
+    for j in T.leaves:
+        row = p["Gamma_N"] @ x[j]
+        assert np.all(row >= p["cN_lo"] - 1e-4) and np.all(row <= p["cN_hi"] + 1e-4)
+    assert O.nested_cost(p, x, u) == pytest.approx(r["s0"], rel=1e-5)
+    assert O.dynamics_violation(p, x, u) < 1e-10
+    nx, nu = 3, 2
+    tight = dict(p, c_lo=p["c_lo"].copy(), c_hi=p["c_hi"].copy())
+    tight["c_lo"][nx + nu:] *= 0.05
+    tight["c_hi"][nx + nu:] *= 0.05
+    rt = O.solve(tight, eps=1e-6, max_iters=60000)
+    assert rt["status"] == "converged"
+    assert abs(rt["s0"] - r["s0"]) > 1e-3
