@@ -21,7 +21,9 @@ struct ProbDev {
     // sizes
     int n, n_nl, N;          // nodes, non-leaf nodes, horizon
     int nx, nu, m;           // m = nx + nu
-    int nc, ncN, nbox;       // constraint rows at non-leaf / leaf nodes, nbox = nx + nu
+    int nc, ncN, nbox;       // constraint rows at non-leaf / leaf nodes; box rows among the nc (nx + nu,
+                             // or nc with general constraints; the rest are ball rows)
+    int nboxN;               // box rows among the ncN (nx, or ncN with general leaf constraints)
     int has_ball, has_ballN, affine, max_ch;
     int stage_kids;          // nodes with at most this many children stage their per-child inputs in LDS
     real alpha, ball_r, ballN_r;
@@ -88,6 +90,14 @@ struct ProbDev {
     const real* Hq_e;
     const real* Hr_e;
     const real* HqN_l;
+    // general constraints (null unless given): Gamma S^-1 / a row-major
+    // (nc x m, Gt, read by L*) and transposed (m x nc, GtT, read by L); at the
+    // leaves Gamma_N S_N^-1 / a_N (ncN x nx, GNt) and transposed (GNtT).  The
+    // box bounds lo, hi (loN, hiN) then hold nc (ncN) rows.
+    const real* Gt;
+    const real* GtT;
+    const real* GNt;
+    const real* GNtT;
     const real* x0;          // scaled initial state
 
     // iterates, two copies each; a step reads copy `par` and writes `par ^ 1`

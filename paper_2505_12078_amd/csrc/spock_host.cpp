@@ -223,10 +223,10 @@ static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
     h.gb = a.take<real>(nx);
     h.gxN = a.take<real>(nx);
     h.gbN = a.take<real>(nx);
-    h.lo = a.take<real>(m);
-    h.hi = a.take<real>(m);
-    h.loN = a.take<real>(nx);
-    h.hiN = a.take<real>(nx);
+    h.lo = a.take<real>(std::max(m, p->nbox));
+    h.hi = a.take<real>(std::max(m, p->nbox));
+    h.loN = a.take<real>(std::max(nx, p->nboxN));
+    h.hiN = a.take<real>(std::max(nx, p->nboxN));
     h.prob = a.take<real>(n);
     h.gamma = a.take<real>(nl);
     h.sa = p->has_lin ? a.take<real>((long long)(n - 1) * (m + 2)) : nullptr;
@@ -237,6 +237,10 @@ static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
     h.Hq_e = p->dense_edge ? a.take<real>((long long)n * nx * nx) : nullptr;
     h.Hr_e = p->dense_edge ? a.take<real>((long long)n * nu * nu) : nullptr;
     h.HqN_l = p->dense_leaf ? a.take<real>((long long)p->n_leaf * nx * nx) : nullptr;
+    h.Gt = p->gen ? a.take<real>((long long)p->nbox * m) : nullptr;
+    h.GtT = p->gen ? a.take<real>((long long)p->nbox * m) : nullptr;
+    h.GNt = p->genN ? a.take<real>((long long)p->nboxN * nx) : nullptr;
+    h.GNtT = p->genN ? a.take<real>((long long)p->nboxN * nx) : nullptr;
     h.x0 = a.take<real>(nx);
     // z and eta of one copy are one vector [z | zero pad | eta] (the
     // SuperMann iteration combines whole iterates)
@@ -331,7 +335,9 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     if (d->nx < 1 || d->nu < 1) return fail(SPOCK_E_INVALID, "nx and nu must be >= 1");
     if (!d->parent || !d->cond_prob || !d->A || !d->B || !(d->Q_diag || d->Q_edge || d->Q_dense) ||
         !(d->R_diag || d->R_edge || d->R_dense) || !(d->QN_diag || d->QN_leaf || d->QN_dense) ||
-        !d->x_lo || !d->x_hi || !d->u_lo || !d->u_hi || !d->xN_lo || !d->xN_hi || !d->gamma)
+        (!d->Gamma && (!d->x_lo || !d->x_hi || !d->u_lo || !d->u_hi)) ||
+        (!d->GammaN && (!d->xN_lo || !d->xN_hi)) || !d->gamma ||
+        (d->Gamma && (!d->con_lo || !d->con_hi)) || (d->GammaN && (!d->conN_lo || !d->conN_hi)))
         return fail(SPOCK_E_INVALID, "missing array in the problem description");
     if (d->parent[0] != -1) return fail(SPOCK_E_INVALID, "parent[0] must be -1");
     p->n = n;
@@ -417,21 +423,39 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     p->dense_leaf = d->QN_dense ? 1 : 0;
     p->edge_cost = (!p->dense_edge && (d->Q_edge || d->R_edge)) ? 1 : 0;
     p->leaf_cost = (!p->dense_leaf && d->QN_leaf) ? 1 : 0;
-    for (int k = 0; k < nx; ++k)
-        if (!(d->x_lo[k] <= d->x_hi[k]) || !(d->xN_lo[k] <= d->xN_hi[k]) || std::isnan(d->x_lo[k]) ||
-            std::isnan(d->xN_lo[k]))
+    // general constraints: finite rows, bounds lo <= hi (infinite allowed)
+    p->gen = d->Gamma ? 1 : 0;
+    p->genN = d->GammaN ? 1 : 0;
+    auto rows_ok = [&](const double* G, int rows, int cols, const double* lo, const double* hi) {
+        if (!finite_all(G, (long long)rows * cols)) return false;
+        for (int r = 0; r < rows; ++r)
+            if (!(lo[r] <= hi[r])) return false;  // also rejects NaN
+        return true;
+    };
+    if (p->gen && (d->n_con < 1 || d->n_con > 512 || !rows_ok(d->Gamma, d->n_con, p->m, d->con_lo, d->con_hi)))
+        return fail(SPOCK_E_INVALID, "general constraints: 1 <= n_con <= 512, finite Gamma, con_lo <= con_hi");
+    if (p->genN && (d->n_conN < 1 || d->n_conN > 512 || !rows_ok(d->GammaN, d->n_conN, nx, d->conN_lo, d->conN_hi)))
+        return fail(SPOCK_E_INVALID, "general leaf constraints: 1 <= n_conN <= 512, finite GammaN, conN_lo <= conN_hi");
+    for (int k = 0; k < nx; ++k) {
+        if (!p->gen && (!(d->x_lo[k] <= d->x_hi[k]) || std::isnan(d->x_lo[k])))
             return fail(SPOCK_E_INVALID, "state bounds must satisfy lo <= hi");
+        if (!p->genN && (!(d->xN_lo[k] <= d->xN_hi[k]) || std::isnan(d->xN_lo[k])))
+            return fail(SPOCK_E_INVALID, "state bounds must satisfy lo <= hi");
+    }
     for (int k = 0; k < nu; ++k)
-        if (!(d->u_lo[k] <= d->u_hi[k])) return fail(SPOCK_E_INVALID, "input bounds must satisfy lo <= hi");
+        if (!p->gen && !(d->u_lo[k] <= d->u_hi[k]))
+            return fail(SPOCK_E_INVALID, "input bounds must satisfy lo <= hi");
     for (int i = 0; i < nl; ++i)
         if (!(d->gamma[i] >= 0 && d->gamma[i] <= 1)) return fail(SPOCK_E_INVALID, "gamma must lie in [0, 1]");
     if (std::isnan(d->x_ball) || std::isnan(d->xN_ball)) return fail(SPOCK_E_INVALID, "NaN ball radius");
 
-    p->has_ball = d->x_ball > 0;
-    p->has_ballN = d->xN_ball > 0;
+    p->has_ball = !p->gen && d->x_ball > 0;
+    p->has_ballN = !p->genN && d->xN_ball > 0;
     p->affine = d->c != nullptr;
-    p->nc = p->m + (p->has_ball ? nx : 0);
-    p->ncN = nx + (p->has_ballN ? nx : 0);
+    p->nbox = p->gen ? d->n_con : p->m;
+    p->nboxN = p->genN ? d->n_conN : nx;
+    p->nc = p->nbox + (p->has_ball ? nx : 0);
+    p->ncN = p->nboxN + (p->has_ballN ? nx : 0);
     p->y_off.assign(nl + 1, 0);
     for (int i = 0; i < nl; ++i) p->y_off[i + 1] = p->y_off[i] + 2 * p->n_ch[i] + 1;
     p->ny = p->y_off[nl];
@@ -666,17 +690,73 @@ static int32_t scale_data(const spock_problem_desc* d, int precondition, spock_p
             for (int k = 0; k < nx; ++k)
                 p->qnh_l[(size_t)l * nx + k] = std::sqrt(QNd(d, p->n_nl + l, k)) / p->SxN[k];
     }
-    // constraint rows Gamma S^-1 have orthogonal columns; their 2-norm is the
-    // largest column norm
+    // constraint rows Gamma S^-1 / a with a = max(1, ||Gamma S^-1||_2): the box
+    // and ball rows have orthogonal columns (the 2-norm is the largest column
+    // norm); general rows take the largest eigenvalue of their Gram matrix
     double a = 1.0, aN = 1.0;
-    if (precondition) {
+    auto two_norm = [&](const std::vector<double>& G, int rows, int cols) {
+        const int k = std::min(rows, cols);
+        std::vector<double> M((size_t)k * k, 0.0);
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) {
+                double v = 0;
+                if (rows <= cols)
+                    for (int c = 0; c < cols; ++c) v += G[(size_t)i * cols + c] * G[(size_t)j * cols + c];
+                else
+                    for (int r = 0; r < rows; ++r) v += G[(size_t)r * cols + i] * G[(size_t)r * cols + j];
+                M[(size_t)i * k + j] = v;
+            }
+        std::vector<double> w, V;
+        sym_eig(k, M.data(), w, V);
+        double top = 0;
+        for (double e : w) top = std::max(top, e);
+        return std::sqrt(top);
+    };
+    std::vector<double> Gs, GNs;  // Gamma S^-1, Gamma_N S_N^-1
+    if (p->gen) {
+        const int nc = p->nbox, m = p->m;
+        Gs.resize((size_t)nc * m);
+        for (int r = 0; r < nc; ++r)
+            for (int c = 0; c < m; ++c)
+                Gs[(size_t)r * m + c] = d->Gamma[(size_t)r * m + c] / (c < nx ? p->Sx[c] : p->Su[c - nx]);
+        if (precondition) a = std::max(1.0, two_norm(Gs, nc, m));
+    }
+    if (p->genN) {
+        const int nc = p->nboxN;
+        GNs.resize((size_t)nc * nx);
+        for (int r = 0; r < nc; ++r)
+            for (int c = 0; c < nx; ++c) GNs[(size_t)r * nx + c] = d->GammaN[(size_t)r * nx + c] / p->SxN[c];
+        if (precondition) aN = std::max(1.0, two_norm(GNs, nc, nx));
+    }
+    if (precondition && !p->gen) {
         double mx = 0;
         for (int k = 0; k < nx; ++k) mx = std::max(mx, (1.0 + p->has_ball) / (p->Sx[k] * p->Sx[k]));
         for (int k = 0; k < nu; ++k) mx = std::max(mx, 1.0 / (p->Su[k] * p->Su[k]));
         a = std::max(1.0, std::sqrt(mx));
+    }
+    if (precondition && !p->genN) {
         double mxN = 0;
         for (int k = 0; k < nx; ++k) mxN = std::max(mxN, (1.0 + p->has_ballN) / (p->SxN[k] * p->SxN[k]));
         aN = std::max(1.0, std::sqrt(mxN));
+    }
+    p->Gt.clear();
+    p->GtT.clear();
+    p->GNt.clear();
+    p->GNtT.clear();
+    if (p->gen) {
+        const int nc = p->nbox, m = p->m;
+        p->Gt.resize((size_t)nc * m);
+        p->GtT.resize((size_t)m * nc);
+        for (int r = 0; r < nc; ++r)
+            for (int c = 0; c < m; ++c) p->Gt[(size_t)r * m + c] = p->GtT[(size_t)c * nc + r] = Gs[(size_t)r * m + c] / a;
+    }
+    if (p->genN) {
+        const int nc = p->nboxN;
+        p->GNt.resize((size_t)nc * nx);
+        p->GNtT.resize((size_t)nx * nc);
+        for (int r = 0; r < nc; ++r)
+            for (int c = 0; c < nx; ++c)
+                p->GNt[(size_t)r * nx + c] = p->GNtT[(size_t)c * nc + r] = GNs[(size_t)r * nx + c] / aN;
     }
     p->con_scale = a;
     p->con_scaleN = aN;
@@ -692,29 +772,45 @@ static int32_t scale_data(const spock_problem_desc* d, int precondition, spock_p
         p->gbN[k] = p->has_ballN ? 1.0 / (aN * p->SxN[k]) : 0.0;
     }
     for (int k = 0; k < nu; ++k) p->gu[k] = 1.0 / (a * p->Su[k]);
-    p->lo.resize(p->m);
-    p->hi.resize(p->m);
-    for (int k = 0; k < nx; ++k) {
-        p->lo[k] = d->x_lo[k] / a;
-        p->hi[k] = d->x_hi[k] / a;
+    // box bounds of the nbox (nboxN) box rows; at least m (nx) entries, as
+    // the node kernels stage that many (zeros past the rows)
+    p->lo.assign(std::max(p->m, p->nbox), 0.0);
+    p->hi.assign(std::max(p->m, p->nbox), 0.0);
+    if (p->gen) {
+        for (int r = 0; r < p->nbox; ++r) {
+            p->lo[r] = d->con_lo[r] / a;
+            p->hi[r] = d->con_hi[r] / a;
+        }
+    } else {
+        for (int k = 0; k < nx; ++k) {
+            p->lo[k] = d->x_lo[k] / a;
+            p->hi[k] = d->x_hi[k] / a;
+        }
+        for (int k = 0; k < nu; ++k) {
+            p->lo[nx + k] = d->u_lo[k] / a;
+            p->hi[nx + k] = d->u_hi[k] / a;
+        }
     }
-    for (int k = 0; k < nu; ++k) {
-        p->lo[nx + k] = d->u_lo[k] / a;
-        p->hi[nx + k] = d->u_hi[k] / a;
-    }
-    p->loN.resize(nx);
-    p->hiN.resize(nx);
-    for (int k = 0; k < nx; ++k) {
-        p->loN[k] = d->xN_lo[k] / aN;
-        p->hiN[k] = d->xN_hi[k] / aN;
+    p->loN.assign(std::max(nx, p->nboxN), 0.0);
+    p->hiN.assign(std::max(nx, p->nboxN), 0.0);
+    for (int r = 0; r < p->nboxN; ++r) {
+        p->loN[r] = (p->genN ? d->conN_lo[r] : d->xN_lo[r]) / aN;
+        p->hiN[r] = (p->genN ? d->conN_hi[r] : d->xN_hi[r]) / aN;
     }
     p->ball_r = p->has_ball ? d->x_ball / a : 0.0;
     p->ballN_r = p->has_ballN ? d->xN_ball / aN : 0.0;
     p->prob.assign(d->cond_prob, d->cond_prob + p->n);
     p->gamma.assign(d->gamma, d->gamma + p->n_nl);
-    p->x_lo.assign(d->x_lo, d->x_lo + nx);
-    p->x_hi.assign(d->x_hi, d->x_hi + nx);
-    p->x_ball = d->x_ball;
+    // the root's box and ball for the x0 check (none with general rows)
+    if (p->gen) {
+        p->x_lo.assign(nx, -INFINITY);
+        p->x_hi.assign(nx, INFINITY);
+        p->x_ball = 0;
+    } else {
+        p->x_lo.assign(d->x_lo, d->x_lo + nx);
+        p->x_hi.assign(d->x_hi, d->x_hi + nx);
+        p->x_ball = d->x_ball;
+    }
 
     // Prop. 1 with a linear term: a = (-Q^-1/2 q / 2, c + 1/2, c - 1/2),
     // c = -|q|^2_{Q^-1} / 8; the change of variables of Sec. 5.4 leaves a
@@ -765,7 +861,84 @@ static int32_t scale_data(const spock_problem_desc* d, int precondition, spock_p
 
     // ||L||: largest block norm of L composed with a permutation
     double L2 = 0.5;  // tau^j and leaf s^j rows (1/2, 1/2)
-    if (p->dense_edge) {
+    if (p->gen || p->genN) {
+        // general constraint rows couple x and u: the (x^i, u^i) block is
+        // lambda_max(Gt^T Gt + blockdiag(C_x, C_u)), C the sum over the child
+        // edges of the cost rows' Gram matrices (S^-1 Q^j S^-1 dense, or the
+        // squared diagonals); the leaf block lambda_max(GNt^T GNt + C_N).
+        // Once per distinct C.
+        auto gram = [&](const std::vector<double>& G, int rows, int cols) {
+            std::vector<double> M((size_t)cols * cols, 0.0);
+            for (int r = 0; r < rows; ++r)
+                for (int i = 0; i < cols; ++i) {
+                    const double gi = G[(size_t)r * cols + i];
+                    if (gi == 0.0) continue;
+                    for (int j = 0; j < cols; ++j) M[(size_t)i * cols + j] += gi * G[(size_t)r * cols + j];
+                }
+            return M;
+        };
+        auto top_of = [&](int dim, const std::vector<double>& base, std::vector<std::vector<double>>& Cs) {
+            std::vector<double> top(Cs.size(), 0.0);
+            parallel_for((int)Cs.size(), [&](int t) {
+                std::vector<double> M = base;
+                for (size_t e = 0; e < M.size(); ++e) M[e] += Cs[t][e];
+                std::vector<double> w, V;
+                sym_eig(dim, M.data(), w, V);
+                for (double x : w) top[t] = std::max(top[t], x);
+            });
+            double best = 0;
+            for (double x : top) best = std::max(best, x);
+            return best;
+        };
+        // the cost rows' Gram matrix of edge (leaf) j into C at offset off:
+        // S^-1 Q^j S^-1 with dense costs (sc = S^-1), else the squared
+        // diagonal (per-row square roots, or the shared ones)
+        auto add_cost = [&](std::vector<double>& C, int mm, int off, int dim, bool dense_mode, const double* dense,
+                            int j, double (*diag)(const spock_problem_desc*, int, int), const std::vector<double>& sc,
+                            const std::vector<double>* per, int per_row) {
+            if (dense_mode) {
+                const std::vector<double> Qm = cost_mat(dense, j, dim, diag, d);
+                for (int a2 = 0; a2 < dim; ++a2)
+                    for (int b2 = 0; b2 < dim; ++b2)
+                        C[(size_t)(off + a2) * mm + off + b2] += Qm[(size_t)a2 * dim + b2] * sc[a2] * sc[b2];
+            } else {
+                for (int a2 = 0; a2 < dim; ++a2) {
+                    const double h = per ? (*per)[(size_t)per_row * dim + a2] : sc[a2];
+                    C[(size_t)(off + a2) * mm + off + a2] += h * h;
+                }
+            }
+        };
+        if (p->gen) {
+            const int m = p->m;
+            const std::vector<double> base = gram(p->Gt, p->nbox, m);
+            std::map<std::vector<double>, int> seen;
+            std::vector<std::vector<double>> Cs;
+            for (int i = 0; i < nl; ++i) {
+                std::vector<double> C((size_t)m * m, 0.0);
+                for (int c = 0; c < p->n_ch[i]; ++c) {
+                    const int j = p->first_child[i] + c;
+                    add_cost(C, m, 0, nx, p->dense_edge, d->Q_dense, j, Qd, p->qh, p->edge_cost ? &p->qh_e : nullptr, j);
+                    add_cost(C, m, nx, nu, p->dense_edge, d->R_dense, j, Rd, p->rh, p->edge_cost ? &p->rh_e : nullptr,
+                             j);
+                }
+                if (seen.emplace(C, (int)Cs.size()).second) Cs.push_back(C);
+            }
+            L2 = std::max(L2, top_of(m, base, Cs));
+        }
+        if (p->genN) {
+            const std::vector<double> base = gram(p->GNt, p->nboxN, nx);
+            std::map<std::vector<double>, int> seen;
+            std::vector<std::vector<double>> Cs;
+            for (int l = 0; l < p->n_leaf; ++l) {
+                std::vector<double> C((size_t)nx * nx, 0.0);
+                add_cost(C, nx, 0, nx, p->dense_leaf, d->QN_dense, nl + l, QNd, p->qnh,
+                         p->leaf_cost ? &p->qnh_l : nullptr, l);
+                if (seen.emplace(C, (int)Cs.size()).second) Cs.push_back(C);
+            }
+            L2 = std::max(L2, top_of(nx, base, Cs));
+        }
+    }
+    if (p->dense_edge && !p->gen) {
         // (x^i, u^i) block with dense cost rows: the largest eigenvalue of
         // diag(gx^2 + gb^2) + S^-1 (sum over the child edges of Q^j) S^-1,
         // once per distinct list of children's matrices (likewise for u)
@@ -794,7 +967,7 @@ static int32_t scale_data(const spock_problem_desc* d, int precondition, spock_p
         });
         for (double t : top) L2 = std::max(L2, t);
     }
-    if (p->dense_leaf) {
+    if (p->dense_leaf && !p->genN) {
         std::vector<double> g2(nx), qd = p->qnh;
         for (int k = 0; k < nx; ++k) g2[k] = p->gxN[k] * p->gxN[k] + p->gbN[k] * p->gbN[k];
         std::vector<double> top(dqN.rep.size(), 0.0);
@@ -806,7 +979,7 @@ static int32_t scale_data(const spock_problem_desc* d, int precondition, spock_p
     }
     for (int i = 0; i < p->n_nl; ++i) {
         // (x^i, u^i) block: constraint rows and every child edge's cost rows
-        for (int r = 0; r < (p->dense_edge ? 0 : nx); ++r) {
+        for (int r = 0; r < ((p->dense_edge || p->gen) ? 0 : nx); ++r) {
             double sq = 0;
             for (int c = 0; c < p->n_ch[i]; ++c) {
                 const double h = p->edge_cost ? p->qh_e[(size_t)(p->first_child[i] + c) * nx + r] : p->qh[r];
@@ -814,7 +987,7 @@ static int32_t scale_data(const spock_problem_desc* d, int precondition, spock_p
             }
             L2 = std::max(L2, p->gx[r] * p->gx[r] + p->gb[r] * p->gb[r] + sq);
         }
-        for (int r = 0; r < (p->dense_edge ? 0 : nu); ++r) {
+        for (int r = 0; r < ((p->dense_edge || p->gen) ? 0 : nu); ++r) {
             double sq = 0;
             for (int c = 0; c < p->n_ch[i]; ++c) {
                 const double h = p->edge_cost ? p->rh_e[(size_t)(p->first_child[i] + c) * nu + r] : p->rh[r];
@@ -828,7 +1001,7 @@ static int32_t scale_data(const spock_problem_desc* d, int precondition, spock_p
         const double sig = 0.5 * (beta + std::sqrt(b2 + 4.0));  // [[I, 0], [-b^T, 1]]
         L2 = std::max(L2, sig * sig);
     }
-    for (int l = 0; l < (p->dense_leaf ? 0 : p->leaf_cost ? p->n_leaf : 1); ++l)
+    for (int l = 0; l < ((p->dense_leaf || p->genN) ? 0 : p->leaf_cost ? p->n_leaf : 1); ++l)
         for (int r = 0; r < nx; ++r) {
             const double h = p->leaf_cost ? p->qnh_l[(size_t)l * nx + r] : p->qnh[r];
             L2 = std::max(L2, p->gxN[r] * p->gxN[r] + p->gbN[r] * p->gbN[r] + h * h);
@@ -1038,7 +1211,8 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     h.m = p->m;
     h.nc = p->nc;
     h.ncN = p->ncN;
-    h.nbox = p->m;
+    h.nbox = p->nbox;
+    h.nboxN = p->nboxN;
     h.has_ball = p->has_ball;
     h.has_ballN = p->has_ballN;
     h.affine = p->affine;
@@ -1094,6 +1268,14 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
         HIP_TRY(put<real>(h.Hr_e, p->Hr_e, st));
     }
     if (p->dense_leaf) HIP_TRY(put<real>(h.HqN_l, p->HqN_l, st));
+    if (p->gen) {
+        HIP_TRY(put<real>(h.Gt, p->Gt, st));
+        HIP_TRY(put<real>(h.GtT, p->GtT, st));
+    }
+    if (p->genN) {
+        HIP_TRY(put<real>(h.GNt, p->GNt, st));
+        HIP_TRY(put<real>(h.GNtT, p->GNtT, st));
+    }
     for (int k = 0; k < 2; ++k) HIP_TRY(spk::launch_fill<real>(h.z[k], real(0), p->nzp + p->neta, st));
     HIP_TRY(hipMemcpyAsync(s.d, &h, sizeof(h), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1270,7 +1452,7 @@ spk::LaunchCfg make_cfg(const spock_problem* p, int node_wg) {
     c.cls[1] = tile_class(spk::col_need(nx, m, V));
     c.cls[2] = tile_class(spk::col_need(m, nx, V));
     c.cls[3] = tile_class(spk::col_need(nx, nu, V));
-    c.dense = (p->dense_edge || p->dense_leaf) ? 1 : 0;
+    c.dense = (p->dense_edge || p->dense_leaf || p->gen || p->genN) ? 1 : 0;
     // float sweeps stage their tiles and vectors in LDS
     const int staged = sizeof(real) == 4 ? spk::stage_elems(nx, nu, V, c.cls[1], c.cls[2]) : 0;
     c.sweep_lds = spk::sweep_int_bytes(p->N) + (spk::sweep_elems(nx, nu) + staged) * (int)sizeof(real);

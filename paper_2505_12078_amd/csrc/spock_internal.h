@@ -119,6 +119,11 @@ struct spock_problem {
     // (S_xN^-1), so that the cost rows are H (qh o x)
     int dense_edge = 0, dense_leaf = 0;
     std::vector<double> Hq_e, Hr_e, HqN_l;
+    // general constraints (gen: non-leaf rows Gamma, genN: leaf rows Gamma_N)
+    // in the scaled space: Gt [nc][m] and GtT [m][nc], GNt [ncN][nx] and GNtT
+    int gen = 0, genN = 0;
+    int nbox = 0, nboxN = 0;
+    std::vector<double> Gt, GtT, GNt, GNtT;
     double ball_r = 0, ballN_r = 0, con_scale = 1, con_scaleN = 1;
     double Lnorm = 0, alpha = 0;
     // unscaled root constraint for the x0 check

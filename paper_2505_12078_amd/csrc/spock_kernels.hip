@@ -617,14 +617,57 @@ struct FwdNode {
     real* luw;       //                                    on u
 };
 
-// eta_c of non-leaf node v: C^i = box x ball (one wavefront).  ec: staged eta_c.
+// General constraint rows G [x; u] in a box (one wavefront): G S^-1 / a as
+// Gt (rows) and GtT (columns), ncol = nx + nu columns, or ncol = nx at a leaf
+// (u unused); the box bounds in global memory.  lxw, luw gather G^T of the
+// dual change for the residual.
 template <typename real>
+SPK_DEV void fwd_block_gen(const real* Gt, const real* GtT, int nr, int nx, int ncol, const real* lo,
+                           const real* hi, long long off, const real* ec, const real* xn, const real* xo,
+                           const real* un, const real* uo, real alpha, real* dblk, real* lxw, real* luw,
+                           real* __restrict__ eout, int check, real& r2) {
+    const int lane = threadIdx.x & 63;
+    const real ialpha = real(1) / alpha;
+    for (int r = lane; r < nr; r += 64) {
+        real wn = 0, wo = 0;
+#pragma unroll 4
+        for (int c = 0; c < ncol; ++c) {
+            const real g = gm(GtT)[(long long)c * nr + r];
+            wn += g * (c < nx ? xn[c] : un[c - nx]);
+            wo += g * (c < nx ? xo[c] : uo[c - nx]);
+        }
+        const real eb = ec[r] + alpha * (real(2) * wn - wo);
+        const real ep = moreau_box(eb, alpha, gm(lo)[r], gm(hi)[r]);
+        gm(eout)[off + r] = ep;
+        const real de = ec[r] - ep;
+        if (check) r2 = nmax(r2, fabs(de * ialpha - (wo - wn)));
+        dblk[r] = de;
+    }
+    if (check) {
+        wave_sync();
+        for (int c = lane; c < ncol; c += 64) {
+            real s = 0;
+#pragma unroll 4
+            for (int r = 0; r < nr; ++r) s += gm(Gt)[(long long)r * ncol + c] * dblk[r];
+            if (c < nx) lxw[c] += s;
+            else luw[c - nx] += s;
+        }
+    }
+}
+
+// eta_c of non-leaf node v: C^i = box x ball (one wavefront).  ec: staged eta_c.
+template <typename real, bool kDense>
 SPK_DEV void fwd_block_c(const ProbDev<real>* __restrict__ P, int v, const real* ec, real* __restrict__ eout,
                          const FwdNode<real>& V, int check, real& r2) {
     const int lane = threadIdx.x & 63;
     const int nx = P->nx, nbox = P->nbox, nc = P->nc;
     const real alpha = P->alpha, ialpha = real(1) / alpha;
     const long long off = P->e_c + (long long)v * nc;
+    if (kDense && P->Gt) {
+        fwd_block_gen(P->Gt, P->GtT, nc, nx, P->m, P->lo, P->hi, off, ec, V.xn, V.xo, V.un, V.uo, alpha, V.dblk,
+                      V.lxw, V.luw, eout, check, r2);
+        return;
+    }
     real nb2 = 0;
     for (int r = lane; r < nc; r += 64) {
         real wn, wo;
@@ -800,6 +843,11 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
     const long long lf = v - P->n_nl;
     if (which == 0) {
         const long long off = P->e_cN + lf * P->ncN;
+        if (kDense && P->GNt) {
+            fwd_block_gen(P->GNt, P->GNtT, P->ncN, nx, nx, P->loN, P->hiN, off, ec, V.xn, V.xo, V.xn, V.xo,
+                          alpha, V.dblk, V.lxw, V.lxw, eout, check, r2);
+            return;
+        }
         real nb2 = 0;
         for (int r = lane; r < P->ncN; r += 64) {
             real wn, wo;
@@ -979,8 +1027,14 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
                 for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + r];
                 s *= C.qh[r];
             }
-            real lt = C.gx[r] * ec[r] + s;
-            if (P->has_ball) lt += C.gb[r] * ec[nbox + r];
+            real lt;
+            if (kDense && P->Gt) {  // general rows: (G^T eta_c) on x
+                lt = s;
+                for (int q = 0; q < nc; ++q) lt += gm(P->Gt)[(long long)q * m + r] * ec[q];
+            } else {
+                lt = C.gx[r] * ec[r] + s;
+                if (P->has_ball) lt += C.gb[r] * ec[nbox + r];
+            }
             xb[r] = sx[r] - alpha * lt;
         }
         for (int r = lane; r < nu; r += 64) {
@@ -997,7 +1051,13 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
                 for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + nx + r];
                 s *= C.rh[r];
             }
-            const real lt = C.gu[r] * ec[nx + r] + s;
+            real lt;
+            if (kDense && P->Gt) {
+                lt = s;
+                for (int q = 0; q < nc; ++q) lt += gm(P->Gt)[(long long)q * m + nx + r] * ec[q];
+            } else {
+                lt = C.gu[r] * ec[nx + r] + s;
+            }
             ub[r] = su[r] - alpha * lt;
         }
         // S2 projection (Sec. 4.3) of (y^v, tau^[v], s^[v]) after the
@@ -1075,8 +1135,14 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
             const real cost = kDense && P->HqN_l ? C.qnh[r] * sym_col_dot(P->HqN_l + lf * nx * nx, nx, r,
                                                                  [&](int c) { return ss[c]; })
                                        : (P->qnh_l ? gm(P->qnh_l)[lf * nx + r] : C.qnh[r]) * ss[r];
-            real lt = C.gxN[r] * sc[r] + cost;
-            if (P->has_ballN) lt += C.gbN[r] * sc[nx + r];
+            real lt;
+            if (kDense && P->GNt) {
+                lt = cost;
+                for (int q = 0; q < ncN; ++q) lt += gm(P->GNt)[(long long)q * nx + r] * sc[q];
+            } else {
+                lt = C.gxN[r] * sc[r] + cost;
+                if (P->has_ballN) lt += C.gbN[r] * sc[nx + r];
+            }
             real h = -(sx[r] - alpha * lt);
             if (P->affine) h += spc[r];
             gm(P->h0)[(long long)v * nx + r] = h;
@@ -1747,7 +1813,7 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
         }
         wave_sync();
         const FwdNode<real> V{C, xn, un, xo, uo, blk, dblk, lxw, luw};
-        fwd_block_c(P, v, st + off[4], eout, V, check, r2);
+        fwd_block_c<real, kDense>(P, v, st + off[4], eout, V, check, r2);
         wave_sync();
         // per-child inputs: the staged copies, or for a wide node the arrays
         // themselves, each through a pointer of its own address space
@@ -1823,9 +1889,16 @@ __global__ __launch_bounds__(kHookWG) void k_apply_L(const ProbDev<real>* __rest
         const real* u = z + P->z_u + (long long)v * nu;
         for (int r = t; r < P->nc; r += kHookWG) {
             real w;
-            if (r < nx) w = P->gx[r] * x[r];
-            else if (r < nbox) w = P->gu[r - nx] * u[r - nx];
-            else w = P->gb[r - nbox] * x[r - nbox];
+            if (P->Gt) {
+                w = 0;
+                for (int c = 0; c < m; ++c) w += P->Gt[(long long)r * m + c] * (c < nx ? x[c] : u[c - nx]);
+            } else if (r < nx) {
+                w = P->gx[r] * x[r];
+            } else if (r < nbox) {
+                w = P->gu[r - nx] * u[r - nx];
+            } else {
+                w = P->gb[r - nbox] * x[r - nbox];
+            }
             eta[P->e_c + (long long)v * P->nc + r] = w;
         }
         const int k = P->n_ch[v], fc = P->first_child[v];
@@ -1859,8 +1932,16 @@ __global__ __launch_bounds__(kHookWG) void k_apply_L(const ProbDev<real>* __rest
         }
     } else {
         const long long lf = v - P->n_nl;
-        for (int r = t; r < P->ncN; r += kHookWG)
-            eta[P->e_cN + lf * P->ncN + r] = r < nx ? P->gxN[r] * x[r] : P->gbN[r - nx] * x[r - nx];
+        for (int r = t; r < P->ncN; r += kHookWG) {
+            real w;
+            if (P->GNt) {
+                w = 0;
+                for (int c = 0; c < nx; ++c) w += P->GNt[(long long)r * nx + c] * x[c];
+            } else {
+                w = r < nx ? P->gxN[r] * x[r] : P->gbN[r - nx] * x[r - nx];
+            }
+            eta[P->e_cN + lf * P->ncN + r] = w;
+        }
         const real s = z[P->z_s + v - 1];
         for (int r = t; r < nx + 2; r += kHookWG) {
             real w;
@@ -1897,8 +1978,13 @@ __global__ __launch_bounds__(kHookWG) void k_apply_Lt(const ProbDev<real>* __res
                     s += (P->qh_e ? P->qh_e[(long long)(fc + q) * nx + r] : P->qh[r]) * o[r];
                 }
             }
-            real w = P->gx[r] * ec[r] + s;
-            if (P->has_ball) w += P->gb[r] * ec[nbox + r];
+            real w = s;
+            if (P->Gt) {
+                for (int q = 0; q < P->nc; ++q) w += P->Gt[(long long)q * m + r] * ec[q];
+            } else {
+                w += P->gx[r] * ec[r];
+                if (P->has_ball) w += P->gb[r] * ec[nbox + r];
+            }
             x[r] = w;
         }
         for (int r = t; r < nu; r += kHookWG) {
@@ -1913,7 +1999,13 @@ __global__ __launch_bounds__(kHookWG) void k_apply_Lt(const ProbDev<real>* __res
                     s += (P->rh_e ? P->rh_e[(long long)(fc + q) * nu + r] : P->rh[r]) * o[r];
                 }
             }
-            z[P->z_u + (long long)v * nu + r] = P->gu[r] * ec[nx + r] + s;
+            real w = s;
+            if (P->Gt) {
+                for (int q = 0; q < P->nc; ++q) w += P->Gt[(long long)q * m + nx + r] * ec[q];
+            } else {
+                w += P->gu[r] * ec[nx + r];
+            }
+            z[P->z_u + (long long)v * nu + r] = w;
         }
         const long long yo = P->y_off[v];
         const real es = eta[P->e_s + v];
@@ -1943,8 +2035,13 @@ __global__ __launch_bounds__(kHookWG) void k_apply_Lt(const ProbDev<real>* __res
             } else {
                 cost = (P->qnh_l ? P->qnh_l[lf * nx + r] : P->qnh[r]) * esN[r];
             }
-            real w = P->gxN[r] * ecN[r] + cost;
-            if (P->has_ballN) w += P->gbN[r] * ecN[nx + r];
+            real w = cost;
+            if (P->GNt) {
+                for (int q = 0; q < P->ncN; ++q) w += P->GNt[(long long)q * nx + r] * ecN[q];
+            } else {
+                w += P->gxN[r] * ecN[r];
+                if (P->has_ballN) w += P->gbN[r] * ecN[nx + r];
+            }
             x[r] = w;
         }
         if (t == 0) z[P->z_s + v - 1] = real(0.5) * (esN[nx] + esN[nx + 1]);
@@ -2004,7 +2101,7 @@ __global__ __launch_bounds__(kHookWG) void k_prox_gconj(const ProbDev<real>* __r
                 P->sa ? P->sa + (long long)(fc + q - 1) * (m + 2) : nullptr);
     } else {
         const long long lf = v - P->n_nl;
-        ballbox(P->e_cN + lf * P->ncN, nx, P->ncN, P->loN, P->hiN, P->ballN_r);
+        ballbox(P->e_cN + lf * P->ncN, P->nboxN, P->ncN, P->loN, P->hiN, P->ballN_r);
         soc(P->e_socN + lf * (nx + 2), nx + 2, P->saN ? P->saN + lf * (nx + 2) : nullptr);
     }
 }

@@ -33,7 +33,7 @@ struct SrvTree {
     int64_t id = 0;
     int n = 0, nx = 0, nu = 0, n_nl = 0;
     std::vector<int32_t> parent;
-    std::vector<double> prob, A, B, c, Q, R, QN, xlo, xhi, ulo, uhi, xNlo, xNhi, gamma, q, r, qN, Qe, Re, QNl, Qd, Rd, QNd;
+    std::vector<double> prob, A, B, c, Q, R, QN, xlo, xhi, ulo, uhi, xNlo, xNhi, gamma, q, r, qN, Qe, Re, QNl, Qd, Rd, QNd, G, glo, ghi, GN, gNlo, gNhi;
     double x_ball = 0, xN_ball = 0;
     size_t footprint = 0;
     spock_problem* p = nullptr;  // resident when non-null
@@ -60,12 +60,20 @@ struct SrvTree {
         d.Q_dense = Qd.empty() ? nullptr : Qd.data();
         d.R_dense = Rd.empty() ? nullptr : Rd.data();
         d.QN_dense = QNd.empty() ? nullptr : QNd.data();
-        d.x_lo = xlo.data();
-        d.x_hi = xhi.data();
-        d.u_lo = ulo.data();
-        d.u_hi = uhi.data();
-        d.xN_lo = xNlo.data();
-        d.xN_hi = xNhi.data();
+        d.n_con = (int32_t)glo.size();
+        d.Gamma = G.empty() ? nullptr : G.data();
+        d.con_lo = glo.empty() ? nullptr : glo.data();
+        d.con_hi = ghi.empty() ? nullptr : ghi.data();
+        d.n_conN = (int32_t)gNlo.size();
+        d.GammaN = GN.empty() ? nullptr : GN.data();
+        d.conN_lo = gNlo.empty() ? nullptr : gNlo.data();
+        d.conN_hi = gNhi.empty() ? nullptr : gNhi.data();
+        d.x_lo = xlo.empty() ? nullptr : xlo.data();
+        d.x_hi = xhi.empty() ? nullptr : xhi.data();
+        d.u_lo = ulo.empty() ? nullptr : ulo.data();
+        d.u_hi = uhi.empty() ? nullptr : uhi.data();
+        d.xN_lo = xNlo.empty() ? nullptr : xNlo.data();
+        d.xN_hi = xNhi.empty() ? nullptr : xNhi.data();
         d.x_ball = x_ball;
         d.xN_ball = xN_ball;
         d.gamma = gamma.data();
@@ -506,12 +514,25 @@ int32_t spock_server_add_tree(spock_server* s, const spock_problem_desc* d, int6
     if (d->Q_dense) T.Qd.assign(d->Q_dense, d->Q_dense + n * nx * nx);
     if (d->R_dense) T.Rd.assign(d->R_dense, d->R_dense + n * nu * nu);
     if (d->QN_dense) T.QNd.assign(d->QN_dense, d->QN_dense + n * nx * nx);
-    T.xlo.assign(d->x_lo, d->x_lo + nx);
-    T.xhi.assign(d->x_hi, d->x_hi + nx);
-    T.ulo.assign(d->u_lo, d->u_lo + nu);
-    T.uhi.assign(d->u_hi, d->u_hi + nu);
-    T.xNlo.assign(d->xN_lo, d->xN_lo + nx);
-    T.xNhi.assign(d->xN_hi, d->xN_hi + nx);
+    if (d->Gamma) {
+        const size_t nr = (size_t)d->n_con;
+        T.G.assign(d->Gamma, d->Gamma + nr * (nx + nu));
+        T.glo.assign(d->con_lo, d->con_lo + nr);
+        T.ghi.assign(d->con_hi, d->con_hi + nr);
+    }
+    if (d->GammaN) {
+        const size_t nr = (size_t)d->n_conN;
+        T.GN.assign(d->GammaN, d->GammaN + nr * nx);
+        T.gNlo.assign(d->conN_lo, d->conN_lo + nr);
+        T.gNhi.assign(d->conN_hi, d->conN_hi + nr);
+    }
+    // the box of the non-leaf (leaf) nodes may be absent when general rows replace it
+    if (d->x_lo) T.xlo.assign(d->x_lo, d->x_lo + nx);
+    if (d->x_hi) T.xhi.assign(d->x_hi, d->x_hi + nx);
+    if (d->u_lo) T.ulo.assign(d->u_lo, d->u_lo + nu);
+    if (d->u_hi) T.uhi.assign(d->u_hi, d->u_hi + nu);
+    if (d->xN_lo) T.xNlo.assign(d->xN_lo, d->xN_lo + nx);
+    if (d->xN_hi) T.xNhi.assign(d->xN_hi, d->xN_hi + nx);
     T.x_ball = d->x_ball;
     T.xN_ball = d->xN_ball;
     T.footprint = fp;

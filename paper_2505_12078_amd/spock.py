@@ -34,7 +34,9 @@ class ProblemDesc(C.Structure):
                 ("QN_diag", _dp), ("x_lo", _dp), ("x_hi", _dp), ("u_lo", _dp), ("u_hi", _dp),
                 ("xN_lo", _dp), ("xN_hi", _dp), ("x_ball", C.c_double), ("xN_ball", C.c_double),
                 ("gamma", _dp), ("q", _dp), ("r", _dp), ("qN", _dp), ("Q_edge", _dp), ("R_edge", _dp),
-                ("QN_leaf", _dp), ("Q_dense", _dp), ("R_dense", _dp), ("QN_dense", _dp)]
+                ("QN_leaf", _dp), ("Q_dense", _dp), ("R_dense", _dp), ("QN_dense", _dp),
+                ("n_con", C.c_int32), ("Gamma", _dp), ("con_lo", _dp), ("con_hi", _dp),
+                ("n_conN", C.c_int32), ("GammaN", _dp), ("conN_lo", _dp), ("conN_hi", _dp)]
 
 
 class Settings(C.Structure):
@@ -223,6 +225,18 @@ class _Desc:
             elif k[key].ndim == 3:
                 setattr(self.desc, shared, None)
                 setattr(self.desc, dense, _ptr(k[key]))
+        # general constraint rows (Gamma = [Gamma_x | Gamma_u]) and leaf rows
+        if prob.get("Gamma_x") is not None:
+            k["Gamma"] = np.ascontiguousarray(np.hstack([prob["Gamma_x"], prob["Gamma_u"]]), dtype=np.float64)
+            k["con_lo"], k["con_hi"] = f("c_lo"), f("c_hi")
+            self.desc.n_con = k["Gamma"].shape[0]
+            self.desc.Gamma, self.desc.con_lo, self.desc.con_hi = _ptr(k["Gamma"]), _ptr(k["con_lo"]), _ptr(k["con_hi"])
+        if prob.get("Gamma_N") is not None:
+            k["GammaN"] = f("Gamma_N")
+            k["conN_lo"], k["conN_hi"] = f("cN_lo"), f("cN_hi")
+            self.desc.n_conN = k["GammaN"].shape[0]
+            self.desc.GammaN = _ptr(k["GammaN"])
+            self.desc.conN_lo, self.desc.conN_hi = _ptr(k["conN_lo"]), _ptr(k["conN_hi"])
 
 
 def footprint(prob, settings=None):

@@ -147,3 +147,29 @@ def test_dense_costs_are_validated(lib):
     b = W.benchmark_problem(1, nu_max=128)
     assert b["nx"] == 2 * b["nu"] <= 256 and b["Q"].shape == (len(b["parent"]), b["nx"], b["nx"])
     assert S.footprint(b) > 0
+
+
+def test_general_constraints_are_validated(lib):
+    """General constraint rows: accepted with finite rows and lo <= hi
+    (infinite bounds allowed), the footprint holds the rows and their
+    transpose; NaN or crossed bounds, a non-finite row and more than 512 rows
+    are rejected."""
+    p = W.random_ragged_problem(3, N=3, nx=3, nu=2, general_con=True)
+    box = {k: v for k, v in p.items() if k not in ("Gamma_x", "Gamma_u", "c_lo", "c_hi", "Gamma_N", "cN_lo", "cN_hi")}
+    nc, ncN, m = p["Gamma_x"].shape[0], p["Gamma_N"].shape[0], 5
+    assert S.footprint(p) > S.footprint(box)
+    one_sided = dict(p, c_hi=p["c_hi"].copy())
+    one_sided["c_hi"][-1] = np.inf
+    assert S.footprint(one_sided) > 0
+    lo = p["c_lo"].copy()
+    lo[0] = p["c_hi"][0] + 1
+    assert "con_lo" in _bad(p, c_lo=lo)
+    lo = p["c_lo"].copy()
+    lo[1] = np.nan
+    _bad(p, c_lo=lo)
+    G = p["Gamma_x"].copy()
+    G[2, 1] = np.inf
+    _bad(p, Gamma_x=G)
+    big = dict(p, Gamma_x=np.zeros((513, 3)), Gamma_u=np.zeros((513, 2)), c_lo=-np.ones(513), c_hi=np.ones(513))
+    assert "512" in _bad(big)
+    assert nc == m + 1 and ncN == 3 + 1

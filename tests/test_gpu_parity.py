@@ -100,6 +100,16 @@ def _cases():
     cases["dense_m150"] = W.make_problem(par, 100, 50, np.random.default_rng(22), prob_kind="dirichlet",
                                          x_ball=15.0, dense_costs=True, linear=True, name="dense_m150")
     cases["bench1"] = W.benchmark_problem(1, nu_max=128)
+    # general constraint rows (box rows plus coupling rows W_x x + W_u u at
+    # non-leaf nodes, W_N x at leaves): small, with dense costs and linear
+    # terms, and with 135 rows and 100 columns (more than one row and column
+    # per lane)
+    cases["general"] = W.random_ragged_problem(7, N=3, nx=3, nu=2, general_con=True)
+    cases["general_dense"] = W.random_ragged_problem(11, N=3, nx=6, nu=3, max_children=3, general_con=True,
+                                                     dense_costs=True, linear=True)
+    par, _ = W.tree_from_branching([2, 2, 1])
+    cases["general_big"] = W.make_problem(par, 70, 30, np.random.default_rng(23), prob_kind="dirichlet",
+                                          general_con=True, name="general_big")
     return cases
 
 
@@ -234,7 +244,8 @@ def test_prox_f_parts(name):
 
 @pytest.mark.parametrize("name,steps", [("cfg0", 200), ("cfg1", 60), ("ragged_affine", 100), ("m150", 40),
                                         ("m200", 20), ("linear_big", 60), ("edge_costs_lin", 60),
-                                        ("dense_lin", 60), ("bench1", 40)])
+                                        ("dense_lin", 60), ("bench1", 40), ("general", 100),
+                                        ("general_dense", 60), ("general_big", 30)])
 def test_trajectory_matches_oracle(name, steps):
     """K plain CP steps from zero: T is firmly nonexpansive, so differences
     cannot amplify along the trajectory."""
@@ -540,11 +551,12 @@ def test_setup_time_reported():
         assert 0 < r["t_setup_s"] < 60 and r["t_solve_s"] > 0
 
 
-@pytest.mark.parametrize("name", ["linear", "dense"])
+@pytest.mark.parametrize("name", ["linear", "dense", "general"])
 def test_linear_cost_solution_matches_oracle(name):
-    """A ragged tree with linear stage and terminal cost terms (and one with
-    dense per-edge costs) solved in float64 to rel_res 1e-6 against the
-    oracle's solve and the nested risk objective with the same costs."""
+    """A ragged tree with linear stage and terminal cost terms (and ones with
+    dense per-edge costs, and with general constraint rows) solved in float64
+    to rel_res 1e-6 against the oracle's solve and the nested risk objective
+    with the same costs."""
     eps = 1e-6
     prob = CASES[name]
     ref = O.solve(prob, eps=eps, max_iters=60000)
