@@ -480,7 +480,7 @@ SPK_DEV void col_apply(const ColTile<real, R>& T, const ColShape& s, const real*
 // The same product read from the packed tile in global memory (shapes beyond
 // the register class, and products of any width: one 64-column block after
 // the other, block b at columns 64 b ..).  kWide (the launches of problems whose
-// products fit no register class): a lane keeps kU 16-byte row groups of its
+// products fit no register class): a lane keeps kU = 16 16-byte row groups of its
 // column in flight; otherwise one row at a time, four in flight, so that the
 // fallback adds few registers to kernels that rarely take it.  Both sum a
 // lane's rows in row order.
@@ -1249,6 +1249,9 @@ __global__ __launch_bounds__(64) void k_bsweep(const ProbDev<real>* __restrict__
             if (pend >= 0) finish_d(prv);
             prev = __builtin_amdgcn_readfirstlane(prev);
             if (prev != k - 1) return false;
+            // the siblings' message loads below stay after the arrival count
+            // (an ordering the compiler must keep; no cache action at wavefront scope)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (lane == 0) gm(P->cnt)[i] = 0;  // the next launch reuses the counter
         } else if (pend >= 0) {
             finish_d(prv);
@@ -1610,6 +1613,9 @@ __global__ __launch_bounds__(64) void k_bsweep_st(const ProbDev<real>* __restric
             if (pend >= 0) finish_d();
             prev = __builtin_amdgcn_readfirstlane(prev);
             if (prev != k - 1) return;
+            // the siblings' message loads below stay after the arrival count
+            // (an ordering the compiler must keep; no cache action at wavefront scope)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (lane == 0) gm(P->cnt)[i] = 0;  // the next launch reuses the counter
             if (k <= kMsgFast) {
 #pragma unroll

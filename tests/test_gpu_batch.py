@@ -167,3 +167,45 @@ def test_batched_workload_launch_equals_alone_and_oracle():
                 print("member %d (%d nodes) %s: max error / scale %.2e" % (k, len(probs[k]["parent"]),
                       "f64" if prec == S.FP64 else "f32", err), flush=True)
                 assert err < tol, (prec, k, err)
+
+
+def test_batch_with_dense_and_general_members():
+    """A batch that mixes plain members with one carrying dense costs and one
+    carrying general constraint rows runs the node kernels built with those
+    products for every member: after float64 and float32 steps each member's
+    iterate matches its own steps (the same operations in the same order; the
+    other kernel build may fuse differently, so to rounding), and the general
+    member matches the oracle."""
+    probs = [W.config_problem(0), W.random_ragged_problem(5, N=3, nx=3, nu=2, dense_costs=True),
+             W.random_ragged_problem(7, N=3, nx=3, nu=2, general_con=True), W.batch_problem(1)]
+    D = O.Data(probs[2])
+    alpha = O.step_size(D)
+
+    def handle(k):
+        P = S.Problem(probs[k], S.default_settings(alpha=alpha if k == 2 else 0.0))
+        P.set_x0(probs[k]["x0"])
+        return P
+
+    for prec, steps, tol in ((S.FP64, 4, 1e-12), (S.FP32, 4, 1e-5)):
+        alone = []
+        for k in range(len(probs)):
+            with handle(k) as P:
+                P.run_steps(steps, prec)
+                alone.append(P.get_iterate())
+        hs = [handle(k) for k in range(len(probs))]
+        with S.Batch(hs, S.default_settings()) as B:
+            B.run_steps(steps, prec)
+        for k, h in enumerate(hs):
+            z, e = h.get_iterate()
+            h.close()
+            scale = max(1.0, np.abs(alone[k][0]).max(), np.abs(alone[k][1]).max())
+            err = max(np.abs(z - alone[k][0]).max(), np.abs(e - alone[k][1]).max()) / scale
+            assert err <= tol, (prec, k, err)
+        F = O.Offline(D)
+        zo, eo = np.zeros(D.layout.nz), np.zeros(D.layout.neta)
+        for _ in range(steps):
+            zo, eo = O.cp_step(D, F, zo, eo, alpha)
+        z2 = alone[2]
+        scale = max(1.0, np.abs(zo).max(), np.abs(eo).max())
+        err = max(np.abs(z2[0] - zo).max(), np.abs(z2[1] - eo).max()) / scale
+        assert err < (1e-10 if prec == S.FP64 else 2e-4), (prec, err)
