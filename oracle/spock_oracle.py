@@ -128,6 +128,39 @@ def avar_conic_data(p, gamma):
     return b, E
 
 
+def conic_risk_value(Z, E, F, b, cone):
+    """rho(Z) = max{mu^T Z : b - E mu - F nu in K} (Sec. 3.3) for a polyhedral
+    K given entrywise (cone[r] = 0: R_+, 1: {0}), by an LP (scipy HiGHS)."""
+    from scipy.optimize import linprog
+    E = np.asarray(E, float)
+    ny, k = E.shape
+    F = np.zeros((ny, 0)) if F is None else np.asarray(F, float)
+    nnu = F.shape[1]
+    cone = np.asarray(cone)
+    A = np.hstack([E, F])  # b - A [mu; nu] in K: A v <= b (R_+ rows), A v = b ({0} rows)
+    ineq, eq = cone == 0, cone == 1
+    c = -np.concatenate([np.asarray(Z, float), np.zeros(nnu)])
+    res = linprog(c, A_ub=A[ineq] if ineq.any() else None, b_ub=np.asarray(b)[ineq] if ineq.any() else None,
+                  A_eq=A[eq] if eq.any() else None, b_eq=np.asarray(b)[eq] if eq.any() else None,
+                  bounds=[(None, None)] * (k + nnu), method="highs")
+    assert res.status == 0, res.message
+    return float(-res.fun)
+
+
+def node_risk(prob, i, p_kids):
+    """The conic data (E, F, b, cone) of the risk at non-leaf node i: the
+    node's own from prob["risk"][i] when given (general coherent risk,
+    Sec. 3.3, polyhedral K), else AV@R_gamma^i."""
+    r = prob.get("risk")
+    if r is not None:
+        E, F, b, cone = r[i]
+        return (np.asarray(E, float), None if F is None else np.asarray(F, float), np.asarray(b, float),
+                np.asarray(cone, int))
+    b, E = avar_conic_data(p_kids, float(prob["gamma"][i]))
+    k = len(p_kids)
+    return E, None, b, np.concatenate([np.zeros(2 * k, int), [1]])
+
+
 # ----------------------------------------------------------------------------
 # problem data in the iterated (preconditioned) space (Sec. 5.4)
 # ----------------------------------------------------------------------------
@@ -254,8 +287,11 @@ class Data:
         self.ncN = self.GN.shape[0]
 
         self.gamma = np.asarray(prob["gamma"], float)
+        # the risk of every non-leaf node as conic data (E, F, b, K)
+        self.risk = [node_risk(prob, i, T.p[T.ch[i]]) for i in range(T.n_nl)]
+        self.general_risk = prob.get("risk") is not None
         self.x0 = Sx * np.asarray(prob["x0"], float)
-        self.layout = Layout(T, nx, nu, self.nc, self.ncN)
+        self.layout = Layout(T, nx, nu, self.nc, self.ncN, [len(r[2]) for r in self.risk])
 
         # linear cost terms (Prop. 1, Sec. 4.2): q^j, r^j on the edge into j
         # (acting on x^anc(j), u^anc(j)), qN^j at leaf j; in the new variables
@@ -288,10 +324,11 @@ class Layout:
     eta_c[non-leaf], eta_soc[edge j = 1..n-1], eta_cN[leaf], eta_socN[leaf]),
     each block in node order (Sec. 4.3 and Sec. 4.4)."""
 
-    def __init__(self, T, nx, nu, nc, ncN):
+    def __init__(self, T, nx, nu, nc, ncN, ylen=None):
         self.T, self.nx, self.nu, self.nc, self.ncN = T, nx, nu, nc, ncN
         n, n_nl, n_l = T.n, T.n_nl, T.n_leaf
-        self.ylen = [2 * len(T.ch[i]) + 1 for i in range(n_nl)]
+        # y^i has one entry per row of the node's conic data (2 n_ch + 1 for AV@R)
+        self.ylen = list(ylen) if ylen is not None else [2 * len(T.ch[i]) + 1 for i in range(n_nl)]
         self.yoff = np.concatenate([[0], np.cumsum(self.ylen)]).astype(int)
         ny = int(self.yoff[-1])
         o = 0
@@ -343,9 +380,9 @@ class Layout:
 
 
 def b_vector(D, i):
-    """b^i = (p^{ch(i)}, 0, 1) of AV@R at node i (conditional probabilities)."""
-    p = D.tree.p[D.tree.ch[i]]
-    return np.concatenate([p, np.zeros(p.size), [1.0]])
+    """b^i of the risk's conic data at node i: (p^{ch(i)}, 0, 1) for AV@R
+    (conditional probabilities), else the given b^i."""
+    return D.risk[i][2]
 
 
 def apply_L(D, z):
@@ -488,15 +525,20 @@ def project_S1(D, F, xbar, ubar):
 # ----------------------------------------------------------------------------
 
 
-def S2_matrix(gamma, nch):
-    """G with G (y, tau^[i], s^[i]) = E^T y - tau - s."""
-    _, E = avar_conic_data(np.full(nch, 1.0 / nch), gamma)
-    return np.hstack([E.T, -np.eye(nch), -np.eye(nch)])
+def S2_matrix(gamma, nch, E=None, F=None):
+    """G with G (y, tau^[i], s^[i]) = (E^T y - tau - s, F^T y) (the kernel of
+    Sec. 4.3); AV@R_gamma's E when E is not given (no F)."""
+    if E is None:
+        _, E = avar_conic_data(np.full(nch, 1.0 / nch), gamma)
+    G = np.hstack([E.T, -np.eye(nch), -np.eye(nch)])
+    if F is not None and F.shape[1] > 0:
+        G = np.vstack([G, np.hstack([F.T, np.zeros((F.shape[1], 2 * nch))])])
+    return G
 
 
-def project_S2_block(w, gamma, nch):
+def project_S2_block(w, gamma, nch, E=None, F=None):
     """Orthogonal projection of w onto ker G: w - G^T (G G^T)^-1 G w."""
-    G = S2_matrix(gamma, nch)
+    G = S2_matrix(gamma, nch, E, F)
     return w - G.T @ np.linalg.solve(G @ G.T, G @ w)
 
 
@@ -565,7 +607,8 @@ def project_S3(D, eta):
     for i in T.nonleaf:
         k = len(T.ch[i])
         v = Y.ey(eta, i)
-        Y.ey(out, i)[:] = np.concatenate([np.maximum(v[:2 * k], 0.0), v[2 * k:]])  # (K^i)* = R^{2k}_+ x R
+        # (K^i)*: R_+ where K^i is R_+, R where K^i is {0} (AV@R: R^{2k}_+ x R)
+        Y.ey(out, i)[:] = np.where(D.risk[i][3] == 0, np.maximum(v, 0.0), v)
         Y.es(out, i)[:] = np.maximum(Y.es(eta, i), 0.0)
         c = Y.ec(eta, i)
         pc = np.clip(c[:nb], D.box_lo, D.box_hi)
@@ -616,8 +659,9 @@ def prox_f(D, F, zbar, alpha):
         w = np.concatenate([Y.y(zbar, i),
                             [Y.tau(zbar, j)[0] for j in kids],
                             [Y.s(zbar, j)[0] for j in kids]])
-        pw = project_S2_block(w, D.gamma[i], len(kids))
-        m = 2 * len(kids) + 1
+        E, Fm, _, _ = D.risk[i]
+        pw = project_S2_block(w, D.gamma[i], len(kids), E, Fm)
+        m = Y.ylen[i]
         Y.y(z, i)[:] = pw[:m]
         for k, j in enumerate(kids):
             Y.tau(z, j)[:] = pw[m + k]
@@ -722,7 +766,11 @@ def nested_cost(prob, x, u):
             kids = T.ch[i]
             Z = np.array([x[i] @ Q[j] @ x[i] + u[i] @ R[j] @ u[i] + q[j] @ x[i] + r[j] @ u[i] + val[j]
                           for j in kids])
-            val[i] = avar_ambiguity_form(Z, T.p[kids], float(prob["gamma"][i]))
+            if prob.get("risk") is not None:
+                E, F, b, cone = node_risk(prob, i, T.p[kids])
+                val[i] = conic_risk_value(Z, E, F, b, cone)
+            else:
+                val[i] = avar_ambiguity_form(Z, T.p[kids], float(prob["gamma"][i]))
     return float(val[0])
 
 

@@ -245,6 +245,38 @@ def make_problem(parent, nx, nu, rng, *, prob_kind="uniform", gamma=0.95,
     )
 
 
+def spectral_risk(prob, weight=0.5, gammas=(0.2, 0.9)):
+    """The problem with every non-leaf node's risk replaced by the spectral
+    risk weight AV@R_g1 + (1 - weight) AV@R_g2 of its children's costs, as
+    general conic data (E, F, b, cone) per node: mu = weight mu1 + (1 - weight)
+    mu2 (k rows in {0}), b_l - E_l mu_l in K_l for the two AV@R blocks
+    (E_l = [g_l I; -I; 1^T], b_l = (p, 0, 1), K_l = R_+^{2k} x {0}), with
+    nu = (mu1, mu2); cone code 0: R_+, 1: {0}."""
+    parent = np.asarray(prob["parent"])
+    n = len(parent)
+    kids = children_lists(parent)
+    p_all = np.asarray(prob["prob"], float)
+    risk = []
+    for i in range(n):
+        k = len(kids[i])
+        if k == 0:
+            break
+        p = p_all[kids[i]]
+        blocks_E, blocks_F, blocks_b, cones = [np.eye(k)], [np.hstack([-weight * np.eye(k),
+                                                                      -(1.0 - weight) * np.eye(k)])], \
+            [np.zeros(k)], [np.ones(k, int)]
+        for l, g in enumerate(gammas):
+            El = np.vstack([g * np.eye(k), -np.eye(k), np.ones((1, k))])
+            Fl = np.zeros((2 * k + 1, 2 * k))
+            Fl[:, l * k:(l + 1) * k] = El
+            blocks_E.append(np.zeros((2 * k + 1, k)))
+            blocks_F.append(Fl)
+            blocks_b.append(np.concatenate([p, np.zeros(k), [1.0]]))
+            cones.append(np.concatenate([np.zeros(2 * k, int), [1]]))
+        risk.append((np.vstack(blocks_E), np.vstack(blocks_F), np.concatenate(blocks_b), np.concatenate(cones)))
+    return dict(prob, risk=risk, name=prob.get("name", "custom") + "_spectral")
+
+
 def seeded_rng(config_id, instance_id=0):
     return np.random.default_rng(np.random.SeedSequence([int(config_id), int(instance_id)]))
 

@@ -554,3 +554,91 @@ def test_general_constraints_hold_at_the_solution():
     rt = O.solve(tight, eps=1e-6, max_iters=60000)
     assert rt["status"] == "converged"
     assert abs(rt["s0"] - r["s0"]) > 1e-3
+
+
+# ----------------------------------------------------------------------------
+# general coherent risks (Sec. 3.3, conic form with a polyhedral cone)
+# ----------------------------------------------------------------------------
+
+def test_spectral_risk_conic_value_matches_closed_form():
+    """The conic data of w AV@R_g1 + (1 - w) AV@R_g2 evaluate (by the LP of
+    Sec. 3.3's representation) to the weighted sum of AV@R's min form."""
+    rng = np.random.default_rng(41)
+    p = W.spectral_risk(W.random_ragged_problem(4, N=2, nx=2, nu=1), weight=0.3, gammas=(0.1, 0.7))
+    T = O.Tree(p["parent"], p["prob"])
+    for i in T.nonleaf:
+        pk = T.p[T.ch[i]]
+        for _ in range(5):
+            Z = rng.standard_normal(len(pk)) * 3
+            E, F, b, cone = p["risk"][i]
+            ref = 0.3 * O.avar_min_form(Z, pk, 0.1) + 0.7 * O.avar_min_form(Z, pk, 0.7)
+            assert O.conic_risk_value(Z, E, F, b, cone) == pytest.approx(ref, abs=1e-9)
+
+
+def test_general_risk_S2_vs_null_space():
+    """S2 with an F block: the projection equals N N^T w with N an orthonormal
+    basis of ker [E^T -I -I; F^T 0 0] (scipy null_space)."""
+    from scipy.linalg import null_space
+    p = W.spectral_risk(W.random_ragged_problem(4, N=2, nx=2, nu=1))
+    rng = np.random.default_rng(3)
+    for (E, F, b, cone) in p["risk"]:
+        k = E.shape[1]
+        G = O.S2_matrix(0.0, k, E, F)
+        N = null_space(G)
+        w = rng.standard_normal(G.shape[1])
+        np.testing.assert_allclose(O.project_S2_block(w, 0.0, k, E, F), N @ (N.T @ w), atol=1e-12)
+
+
+def test_avar_as_general_risk_is_the_avar_path():
+    """AV@R_gamma given as general conic data (E, F = none, b, K = R_+^{2k} x
+    {0}) is the AV@R problem: the same L, ||L|| and CP iterates."""
+    p = W.random_ragged_problem(5, N=2, nx=3, nu=2)
+    T = O.Tree(p["parent"], p["prob"])
+    risk = []
+    for i in T.nonleaf:
+        b, E = O.avar_conic_data(T.p[T.ch[i]], float(p["gamma"][i]))
+        k = len(T.ch[i])
+        risk.append((E, None, b, np.concatenate([np.zeros(2 * k, int), [1]])))
+    g = dict(p, risk=risk)
+    assert O.L_norm(O.Data(p)) == O.L_norm(O.Data(g))
+    rp, rg = O.solve(p, eps=1e-6, max_iters=40000), O.solve(g, eps=1e-6, max_iters=40000)
+    assert rp["iters"] == rg["iters"]
+    np.testing.assert_array_equal(rp["z"], rg["z"])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_general_risk_L_adjoint_and_norm(seed):
+    prob = W.spectral_risk(W.random_ragged_problem(seed, N=3, nx=3, nu=2), weight=0.4)
+    D = O.Data(prob, precondition=(seed == 0))
+    Y = D.layout
+    rng = np.random.default_rng(seed)
+    z, e = rng.standard_normal(Y.nz), rng.standard_normal(Y.neta)
+    assert abs(O.apply_L(D, z) @ e - z @ O.apply_Lt(D, e)) < 1e-12 * max(1, abs(z @ O.apply_Lt(D, e)))
+    assert O.L_norm(D) == pytest.approx(np.linalg.norm(_dense_L(D), 2), rel=1e-10)
+
+
+def test_spectral_risk_solution_is_the_nested_objective():
+    """A ragged tree with a spectral risk at every node: s0 equals the nested
+    objective with the closed form w AV@R_g1 + (1 - w) AV@R_g2, and differs
+    from either AV@R alone."""
+    base = W.random_ragged_problem(4, N=2, nx=3, nu=2, ball=False)
+    p = W.spectral_risk(base, weight=0.5, gammas=(0.2, 0.9))
+    r = O.solve(p, eps=1e-7, max_iters=60000)
+    assert r["status"] == "converged"
+    T = O.Tree(p["parent"], p["prob"])
+    x, u = r["x"], r["u"]
+    n = T.n
+    Q, R, QN = (O.cost_matrices(p, k, n) for k in ("Q", "R", "QN"))
+    val = np.zeros(n)
+    for j in T.leaves:
+        val[j] = x[j] @ QN[j] @ x[j]
+    for t in range(T.N - 1, -1, -1):
+        for i in T.nodes(t):
+            kids = T.ch[i]
+            Z = np.array([x[i] @ Q[j] @ x[i] + u[i] @ R[j] @ u[i] + val[j] for j in kids])
+            val[i] = 0.5 * O.avar_min_form(Z, T.p[kids], 0.2) + 0.5 * O.avar_min_form(Z, T.p[kids], 0.9)
+    assert val[0] == pytest.approx(r["s0"], rel=1e-5)
+    assert O.dynamics_violation(p, x, u) < 1e-10
+    for g in (0.2, 0.9):
+        rg = O.solve(dict(base, gamma=np.full_like(base["gamma"], g)), eps=1e-6, max_iters=60000)
+        assert abs(rg["s0"] - r["s0"]) > 1e-3
