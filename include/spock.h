@@ -132,6 +132,20 @@ typedef struct spock_problem_desc {
     const double* GammaN;
     const double* conN_lo;
     const double* conN_hi;
+    /* Optional general coherent risks (Sec. 3.3, the cone K polyhedral): the
+     * risk at non-leaf node i (k_i children) is max{mu^T Z : b - E mu - F nu
+     * in K} over the children's costs Z, with y^i of risk_ny[i] entries (the
+     * rows of E, F, b) and nu of risk_nnu[i] (the columns of F).  Concatenated
+     * in node order: risk_E (ny x k_i, row-major), risk_F (ny x nnu), risk_b
+     * (ny), risk_cone (ny codes: 0 for R_+, 1 for {0}).  A non-NULL risk_ny
+     * replaces AV@R (gamma is then not read); 1 <= ny <= 128,
+     * k_i + nnu <= 64, and [E^T -I -I; F^T 0 0] must have full row rank. */
+    const int32_t* risk_ny;
+    const int32_t* risk_nnu;
+    const double* risk_E;
+    const double* risk_F;
+    const double* risk_b;
+    const int32_t* risk_cone;
 } spock_problem_desc;
 
 typedef struct spock_settings {
@@ -255,10 +269,11 @@ int32_t spock_apply_L(spock_problem* p, const double* z, double* eta_out, int32_
  *    xbar [n][nx] (row 0 is ignored: x^0 is fixed), ubar [n_nl][nu];
  *    x_out [n][nx], u_out [n_nl][nu].
  *  spock_project_S2: orthogonal projection of every non-leaf node's block
- *    (y^i, tau^[i], s^[i]) onto the kernel of [E^T -I -I] of Sec. 4.3 (the
- *    AV@R kernel set, with E of Sec. 3.3).  y in the canonical y layout (per
- *    non-leaf node 2 n_ch + 1 entries), tau and s per node 1..n-1; the outputs
- *    have the same shapes.
+ *    (y^i, tau^[i], s^[i]) onto the kernel of [E^T -I -I; F^T 0 0] of
+ *    Sec. 4.3 (E of AV@R, Sec. 3.3, and no F unless general risks are given).
+ *    y in the canonical y layout (per non-leaf node 2 n_ch + 1 entries for
+ *    AV@R, risk_ny[i] for a general risk), tau and s per node 1..n-1; the
+ *    outputs have the same shapes.
  * Errors: SPOCK_E_INVALID (null pointer, bad precision), SPOCK_E_HIP.
  */
 int32_t spock_project_S1(spock_problem* p, const double* xbar, const double* ubar, double* x_out, double* u_out,

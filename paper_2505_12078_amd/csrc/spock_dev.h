@@ -98,6 +98,14 @@ struct ProbDev {
     const real* GtT;
     const real* GNt;
     const real* GNtT;
+    // general coherent risks (null unless given): per non-leaf node i, y^i has
+    // rny[i] entries and nu rnnu[i]; at rdata + roff[i]: E (ny x k, row-major),
+    // F (ny x nnu), b (ny), cone codes (ny: 0 for R_+, 1 for {0}), and
+    // M = (G G^T)^-1 ((k + nnu) x (k + nnu)) of G = [E^T -I -I; F^T 0 0]
+    const long long* roff;
+    const int* rny;
+    const int* rnnu;
+    const real* rdata;
     const real* x0;          // scaled initial state
 
     // iterates, two copies each; a step reads copy `par` and writes `par ^ 1`

@@ -241,6 +241,7 @@ static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
     h.GtT = p->gen ? a.take<real>((long long)p->nbox * m) : nullptr;
     h.GNt = p->genN ? a.take<real>((long long)p->nboxN * nx) : nullptr;
     h.GNtT = p->genN ? a.take<real>((long long)p->nboxN * nx) : nullptr;
+    h.rdata = p->grisk ? a.take<real>((long long)p->rdata.size()) : nullptr;
     h.x0 = a.take<real>(nx);
     // z and eta of one copy are one vector [z | zero pad | eta] (the
     // SuperMann iteration combines whole iterates)
@@ -257,6 +258,8 @@ static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
 
 static void carve(Arena& a, spock_problem* p) {
     p->d_tree = a.take<int>(3LL * p->n + 4);
+    p->d_roff = p->grisk ? a.take<long long>(p->n_nl) : nullptr;
+    p->d_rint = p->grisk ? a.take<int>(2LL * p->n_nl) : nullptr;
     p->d_cnt = a.take<int>(p->n);
     p->d_path = a.take<int4>((long long)p->n_leaf * (p->N + 1));
     p->d_top = a.take<int>(p->n_leaf);
@@ -336,7 +339,8 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     if (!d->parent || !d->cond_prob || !d->A || !d->B || !(d->Q_diag || d->Q_edge || d->Q_dense) ||
         !(d->R_diag || d->R_edge || d->R_dense) || !(d->QN_diag || d->QN_leaf || d->QN_dense) ||
         (!d->Gamma && (!d->x_lo || !d->x_hi || !d->u_lo || !d->u_hi)) ||
-        (!d->GammaN && (!d->xN_lo || !d->xN_hi)) || !d->gamma ||
+        (!d->GammaN && (!d->xN_lo || !d->xN_hi)) || (!d->gamma && !d->risk_ny) ||
+        (d->risk_ny && (!d->risk_nnu || !d->risk_E || !d->risk_b || !d->risk_cone)) ||
         (d->Gamma && (!d->con_lo || !d->con_hi)) || (d->GammaN && (!d->conN_lo || !d->conN_hi)))
         return fail(SPOCK_E_INVALID, "missing array in the problem description");
     if (d->parent[0] != -1) return fail(SPOCK_E_INVALID, "parent[0] must be -1");
@@ -379,7 +383,7 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     const int nx = d->nx, nu = d->nu;
     if (!finite_all(d->A + (size_t)nx * nx, (long long)(n - 1) * nx * nx) ||
         !finite_all(d->B + (size_t)nx * nu, (long long)(n - 1) * nx * nu) ||
-        (d->c && !finite_all(d->c + nx, (long long)(n - 1) * nx)) || !finite_all(d->gamma, nl))
+        (d->c && !finite_all(d->c + nx, (long long)(n - 1) * nx)) || (d->gamma && !finite_all(d->gamma, nl)))
         return fail(SPOCK_E_INVALID, "non-finite problem data");
     // cost diagonals: every edge's Q, R and every leaf's QN positive and finite
     for (int j = 1; j < n; ++j) {
@@ -445,8 +449,65 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     for (int k = 0; k < nu; ++k)
         if (!p->gen && !(d->u_lo[k] <= d->u_hi[k]))
             return fail(SPOCK_E_INVALID, "input bounds must satisfy lo <= hi");
-    for (int i = 0; i < nl; ++i)
+    p->grisk = d->risk_ny ? 1 : 0;
+    for (int i = 0; i < nl && !p->grisk; ++i)
         if (!(d->gamma[i] >= 0 && d->gamma[i] <= 1)) return fail(SPOCK_E_INVALID, "gamma must lie in [0, 1]");
+    if (p->grisk) {
+        // general coherent risks: sizes, finite data, cone codes, and the
+        // inverse Gram matrix of G = [E^T -I -I; F^T 0 0] per node (Sec. 4.3)
+        p->rny.assign(nl, 0);
+        p->rnnu.assign(nl, 0);
+        p->roff.assign(nl, 0);
+        long long ie = 0, iF = 0, ib = 0, tot = 0;
+        for (int i = 0; i < nl; ++i) {
+            const int ny = d->risk_ny[i], nnu = d->risk_nnu[i], k = p->n_ch[i];
+            if (ny < 1 || ny > 128 || nnu < 0 || k + nnu > 64)
+                return fail(SPOCK_E_INVALID, "general risks: 1 <= ny <= 128 and k + nnu <= 64 per node");
+            p->rny[i] = ny;
+            p->rnnu[i] = nnu;
+            p->roff[i] = tot;
+            tot += (long long)ny * k + (long long)ny * nnu + 2LL * ny + (long long)(k + nnu) * (k + nnu);
+        }
+        p->rdata.assign(tot, 0.0);
+        for (int i = 0; i < nl; ++i) {
+            const int ny = p->rny[i], nnu = p->rnnu[i], k = p->n_ch[i], g = k + nnu;
+            double* blk = p->rdata.data() + p->roff[i];
+            double* E = blk;
+            double* F = E + (size_t)ny * k;
+            double* b = F + (size_t)ny * nnu;
+            double* cone = b + ny;
+            double* M = cone + ny;
+            if (!finite_all(d->risk_E + ie, (long long)ny * k) || (nnu > 0 && (!d->risk_F || !finite_all(d->risk_F + iF, (long long)ny * nnu))) ||
+                !finite_all(d->risk_b + ib, ny))
+                return fail(SPOCK_E_INVALID, "general risks: non-finite E, F or b");
+            std::copy(d->risk_E + ie, d->risk_E + ie + (long long)ny * k, E);
+            if (nnu > 0) std::copy(d->risk_F + iF, d->risk_F + iF + (long long)ny * nnu, F);
+            std::copy(d->risk_b + ib, d->risk_b + ib + ny, b);
+            for (int r = 0; r < ny; ++r) {
+                const int code = d->risk_cone[ib + r];
+                if (code != 0 && code != 1) return fail(SPOCK_E_INVALID, "general risks: cone codes are 0 or 1");
+                cone[r] = code;
+            }
+            // G G^T = [E^T E + 2 I, E^T F; F^T E, F^T F]; invert through Cholesky
+            std::vector<double> GG((size_t)g * g, 0.0);
+            for (int a = 0; a < g; ++a)
+                for (int c = 0; c < g; ++c) {
+                    double v = 0;
+                    for (int r = 0; r < ny; ++r) {
+                        const double ga = a < k ? E[(size_t)r * k + a] : F[(size_t)r * nnu + a - k];
+                        const double gc = c < k ? E[(size_t)r * k + c] : F[(size_t)r * nnu + c - k];
+                        v += ga * gc;
+                    }
+                    if (a == c && a < k) v += 2.0;
+                    GG[(size_t)a * g + c] = v;
+                }
+            if (!cholesky(g, GG.data())) return fail(SPOCK_E_INVALID, "general risks: G must have full row rank");
+            chol_inverse(g, GG.data(), M);
+            ie += (long long)ny * k;
+            iF += (long long)ny * nnu;
+            ib += ny;
+        }
+    }
     if (std::isnan(d->x_ball) || std::isnan(d->xN_ball)) return fail(SPOCK_E_INVALID, "NaN ball radius");
 
     p->has_ball = !p->gen && d->x_ball > 0;
@@ -457,7 +518,7 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     p->nc = p->nbox + (p->has_ball ? nx : 0);
     p->ncN = p->nboxN + (p->has_ballN ? nx : 0);
     p->y_off.assign(nl + 1, 0);
-    for (int i = 0; i < nl; ++i) p->y_off[i + 1] = p->y_off[i] + 2 * p->n_ch[i] + 1;
+    for (int i = 0; i < nl; ++i) p->y_off[i + 1] = p->y_off[i] + (p->grisk ? p->rny[i] : 2 * p->n_ch[i] + 1);
     p->ny = p->y_off[nl];
     long long o = 1;
     p->z_x = o; o += (long long)n * nx;
@@ -481,7 +542,8 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
     if (p->nx > 256 || p->nu > 256) return fail(SPOCK_E_INVALID, "nx and nu must not exceed 256");
     // stage the per-child inputs of as many children as one wavefront's LDS
     // holds (up to kStageKids); wider nodes read theirs in place
-    p->stage_kids = spk::kStageKids;
+    // (general risks: none staged, their y blocks have other lengths)
+    p->stage_kids = p->grisk ? 0 : spk::kStageKids;
     while (p->stage_kids > 0 && node_lds_bytes(p, 64, 8) > 64 * 1024) --p->stage_kids;
     if (node_lds_bytes(p, 64, 8) > 64 * 1024 ||
         spk::sweep_int_bytes(p->N) + spk::sweep_elems(nx, nu) * 8 > 64 * 1024)
@@ -800,7 +862,8 @@ static int32_t scale_data(const spock_problem_desc* d, int precondition, spock_p
     p->ball_r = p->has_ball ? d->x_ball / a : 0.0;
     p->ballN_r = p->has_ballN ? d->xN_ball / aN : 0.0;
     p->prob.assign(d->cond_prob, d->cond_prob + p->n);
-    p->gamma.assign(d->gamma, d->gamma + p->n_nl);
+    if (p->grisk) p->gamma.assign(p->n_nl, 0.0);  // not read
+    else p->gamma.assign(d->gamma, d->gamma + p->n_nl);
     // the root's box and ball for the x0 check (none with general rows)
     if (p->gen) {
         p->x_lo.assign(nx, -INFINITY);
@@ -995,8 +1058,14 @@ static int32_t scale_data(const spock_problem_desc* d, int precondition, spock_p
             }
             L2 = std::max(L2, p->gu[r] * p->gu[r] + sq);
         }
-        double b2 = 1.0;
-        for (int c = 0; c < p->n_ch[i]; ++c) b2 += p->prob[p->first_child[i] + c] * p->prob[p->first_child[i] + c];
+        double b2 = 0.0;  // ||b^i||^2: (p, 0, 1) for AV@R, else the given b^i
+        if (p->grisk) {
+            const double* b = p->rdata.data() + p->roff[i] + (size_t)p->rny[i] * (p->n_ch[i] + p->rnnu[i]);
+            for (int r = 0; r < p->rny[i]; ++r) b2 += b[r] * b[r];
+        } else {
+            b2 = 1.0;
+            for (int c = 0; c < p->n_ch[i]; ++c) b2 += p->prob[p->first_child[i] + c] * p->prob[p->first_child[i] + c];
+        }
         const double beta = std::sqrt(b2);
         const double sig = 0.5 * (beta + std::sqrt(b2 + 4.0));  // [[I, 0], [-b^T, 1]]
         L2 = std::max(L2, sig * sig);
@@ -1222,6 +1291,9 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     h.ball_r = (real)p->ball_r;
     h.ballN_r = (real)p->ballN_r;
     h.first_child = p->d_tree;
+    h.roff = p->d_roff;
+    h.rny = p->d_rint;
+    h.rnnu = p->d_rint ? p->d_rint + p->n_nl : nullptr;
     h.n_ch = p->d_tree + p->n;
     h.y_off = p->d_tree + 2 * p->n;
     h.z_x = p->z_x; h.z_u = p->z_u; h.z_y = p->z_y; h.z_tau = p->z_tau; h.z_s = p->z_s;
@@ -1276,6 +1348,7 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
         HIP_TRY(put<real>(h.GNt, p->GNt, st));
         HIP_TRY(put<real>(h.GNtT, p->GNtT, st));
     }
+    if (p->grisk) HIP_TRY(put<real>(h.rdata, p->rdata, st));
     for (int k = 0; k < 2; ++k) HIP_TRY(spk::launch_fill<real>(h.z[k], real(0), p->nzp + p->neta, st));
     HIP_TRY(hipMemcpyAsync(s.d, &h, sizeof(h), hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1452,7 +1525,7 @@ spk::LaunchCfg make_cfg(const spock_problem* p, int node_wg) {
     c.cls[1] = tile_class(spk::col_need(nx, m, V));
     c.cls[2] = tile_class(spk::col_need(m, nx, V));
     c.cls[3] = tile_class(spk::col_need(nx, nu, V));
-    c.dense = (p->dense_edge || p->dense_leaf || p->gen || p->genN) ? 1 : 0;
+    c.dense = (p->dense_edge || p->dense_leaf || p->gen || p->genN || p->grisk) ? 1 : 0;
     // float sweeps stage their tiles and vectors in LDS
     const int staged = sizeof(real) == 4 ? spk::stage_elems(nx, nu, V, c.cls[1], c.cls[2]) : 0;
     c.sweep_lds = spk::sweep_int_bytes(p->N) + (spk::sweep_elems(nx, nu) + staged) * (int)sizeof(real);
@@ -1656,6 +1729,13 @@ int32_t spock_problem_create(const spock_problem_desc* desc, const spock_setting
                                  p->parent[v]);
         }
         hipError_t e = hipMemcpy(p->d_tree, tree.data(), tree.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess && p->grisk) {
+            std::vector<int> rint(p->rny);
+            rint.insert(rint.end(), p->rnnu.begin(), p->rnnu.end());
+            e = hipMemcpy(p->d_rint, rint.data(), rint.size() * sizeof(int), hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(p->d_roff, p->roff.data(), p->roff.size() * sizeof(long long), hipMemcpyHostToDevice);
+        }
         if (e == hipSuccess)
             e = hipMemcpy(p->d_ntasks, ntasks.data(), ntasks.size() * sizeof(int2), hipMemcpyHostToDevice);
         if (e == hipSuccess)

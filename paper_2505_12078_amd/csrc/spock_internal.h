@@ -124,6 +124,13 @@ struct spock_problem {
     int gen = 0, genN = 0;
     int nbox = 0, nboxN = 0;
     std::vector<double> Gt, GtT, GNt, GNtT;
+    // general coherent risks (grisk): per non-leaf node its y length rny, F
+    // columns rnnu and a packed block at roff of rdata: E (ny x k), F
+    // (ny x nnu), b (ny), cone codes (ny, 0 or 1), M = (G G^T)^-1 ((k + nnu)^2)
+    int grisk = 0;
+    std::vector<int> rny, rnnu;
+    std::vector<long long> roff;
+    std::vector<double> rdata;
     double ball_r = 0, ballN_r = 0, con_scale = 1, con_scaleN = 1;
     double Lnorm = 0, alpha = 0;
     // unscaled root constraint for the x0 check
@@ -138,6 +145,8 @@ struct spock_problem {
     hipStream_t stream = nullptr;
     bool owns_stream = false;
     int* d_tree = nullptr;
+    long long* d_roff = nullptr;  // general risks: per-node block offsets
+    int* d_rint = nullptr;        //                y lengths, then F columns
     int* d_cnt = nullptr;
     int4* d_path = nullptr;
     int* d_top = nullptr;

@@ -751,6 +751,67 @@ SPK_DEV void fwd_block_risk(const ProbDev<real>* __restrict__ P, int v, long lon
     }
 }
 
+// The conic data of a general coherent risk at non-leaf node v (Sec. 3.3, K
+// polyhedral): y^v has ny entries, nu^v has nnu; the node's packed block holds
+// E (ny x k, row-major), F (ny x nnu), b (ny), the cone codes of K's rows (ny;
+// 0: R_+, 1: {0}) and M = (G G^T)^-1 ((k + nnu)^2) of G = [E^T -I -I; F^T 0 0].
+template <typename real>
+struct RiskData {
+    int ny, nnu;
+    const real *E, *F, *b, *cone, *M;
+};
+template <typename real>
+SPK_DEV RiskData<real> risk_data(const ProbDev<real>* __restrict__ P, int v, int k) {
+    RiskData<real> d;
+    d.ny = P->rny[v];
+    d.nnu = P->rnnu[v];
+    d.E = P->rdata + P->roff[v];
+    d.F = d.E + (long long)d.ny * k;
+    d.b = d.F + (long long)d.ny * d.nnu;
+    d.cone = d.b + d.ny;
+    d.M = d.cone + d.ny;
+    return d;
+}
+
+// fwd_block_risk for a general coherent risk: eta_y in (K^v)* row by row (R_+
+// where K^v is R_+, R where it is {0}) and eta_s in R_+, with the node's b.
+template <typename real, typename PT>
+SPK_DEV void fwd_block_risk_gen(const ProbDev<real>* __restrict__ P, int v, long long yo, int k, PT ey, real es,
+                                PT yn, PT yv, real sn, real sv, real* __restrict__ eout, int check, real& r1,
+                                real& r2) {
+    const int lane = threadIdx.x & 63;
+    const real alpha = P->alpha, ialpha = real(1) / alpha;
+    const RiskData<real> D = risk_data(P, v, k);
+    real bn = 0, bo = 0;
+    for (int c = lane; c < D.ny; c += 64) {
+        const real bc = gm(D.b)[c];
+        bn += bc * yn[c];
+        bo += bc * yv[c];
+    }
+    bn = wave_sum(bn);
+    bo = wave_sum(bo);
+    const real wsn = sn - bn, wso = sv - bo;
+    const real ebs = es + alpha * (real(2) * wsn - wso);
+    const real eps_ = ebs < 0 ? ebs : real(0);
+    const real des = es - eps_;
+    if (lane == 0) gm(eout)[P->e_s + v] = eps_;
+    for (int c = lane; c < D.ny; c += 64) {
+        const real eb = ey[c] + alpha * (real(2) * yn[c] - yv[c]);
+        const real ep = gm(D.cone)[c] == real(0) ? (eb < 0 ? eb : real(0)) : real(0);
+        gm(eout)[P->e_y + yo + c] = ep;
+        if (check) {
+            const real de = ey[c] - ep;
+            const real dy = yv[c] - yn[c];
+            r2 = nmax(r2, fabs(de * ialpha - dy));
+            r1 = nmax(r1, fabs(dy * ialpha - (de - gm(D.b)[c] * des)));
+        }
+    }
+    if (check && lane == 0) {
+        r2 = nmax(r2, fabs(des * ialpha - (wso - wsn)));
+        r1 = nmax(r1, fabs((sv - sn) * ialpha - des));
+    }
+}
+
 // SOC block of the edge into child j of non-leaf node v:
 // (Q^1/2 x^v, R^1/2 u^v, tau^j / 2, tau^j / 2) in SOC + a (one wavefront);
 // es: staged eta_soc of that edge, tn / tv: new / old tau^j.
@@ -1061,7 +1122,57 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
             ub[r] = su[r] - alpha * lt;
         }
         // S2 projection (Sec. 4.3) of (y^v, tau^[v], s^[v]) after the
-        // z - alpha L* eta shift.  Kernel of G = [E^T, -I, -I] with
+        // z - alpha L* eta shift, general coherent risk: G w = (E^T y - tau - s,
+        // F^T y) with one row per lane (k + nnu <= 64), lambda = M G w, and
+        // w - G^T lambda = (y - E lambda_E - F lambda_F, tau + lambda_E, s + lambda_E).
+        // Rows of y sit on lanes r and r + 64 (ny <= 128); every sum over rows
+        // or multipliers runs in index order with the other side broadcast.
+        if (kDense && P->rdata) {
+            const RiskData<real> D = risk_data(P, v, k);
+            const int g = k + D.nnu;
+            real ybh[2];
+            for (int h = 0; h < 2; ++h) {
+                const int r = lane + 64 * h;
+                ybh[h] = r < D.ny ? zy[r] - alpha * (ey[r] - gm(D.b)[r] * es) : real(0);
+            }
+            real tb = 0, sb = 0;
+            if (lane < k) {
+                tb = zt[lane] - alpha * real(0.5) * (soc[lane * (m + 2) + m] + soc[lane * (m + 2) + m + 1]);
+                const real lts = leafkids ? real(0.5) * (cs[lane * (nx + 2) + nx] + cs[lane * (nx + 2) + nx + 1])
+                                          : cs[lane];
+                sb = zs[lane] - alpha * lts;
+            }
+            real rho = 0;
+            for (int r = 0; r < D.ny; ++r) {
+                const real yr = lane_value(r < 64 ? ybh[0] : ybh[1], r & 63);
+                if (lane < k) rho += gm(D.E)[(long long)r * k + lane] * yr;
+                else if (lane < g) rho += gm(D.F)[(long long)r * D.nnu + lane - k] * yr;
+            }
+            if (lane < k) rho -= tb + sb;
+            real lam = 0;
+            for (int d = 0; d < g; ++d) {
+                const real rd = lane_value(rho, d);
+                if (lane < g) lam += gm(D.M)[(long long)d * g + lane] * rd;  // M is symmetric
+            }
+            if (lane < k) {
+                gm(zout)[P->z_tau + fc + lane - 1] = tb + lam;
+                gm(zout)[P->z_s + fc + lane - 1] = sb + lam;
+            }
+            real acc[2] = {ybh[0], ybh[1]};
+            for (int c = 0; c < g; ++c) {
+                const real lc = lane_value(lam, c);
+                for (int h = 0; h < 2; ++h) {
+                    const int r = lane + 64 * h;
+                    if (r < D.ny)
+                        acc[h] -= (c < k ? gm(D.E)[(long long)r * k + c] : gm(D.F)[(long long)r * D.nnu + c - k]) * lc;
+                }
+            }
+            for (int h = 0; h < 2; ++h) {
+                const int r = lane + 64 * h;
+                if (r < D.ny) gm(zout)[P->z_y + yo + r] = acc[h];
+            }
+        } else
+        // AV@R: the kernel of G = [E^T, -I, -I] with
         // E = [gamma I; -I; 1^T] (AV@R, Sec. 3.3); G G^T = (gamma^2 + 3) I + 1 1^T,
         // so with rho = G w the multiplier is lambda = (rho - (1^T rho / (c + n)) 1) / c,
         // c = gamma^2 + 3 (Sherman-Morrison), and w - G^T lambda is the projection.
@@ -1824,7 +1935,12 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
         // per-child inputs: the staged copies, or for a wide node the arrays
         // themselves, each through a pointer of its own address space
         auto per_child = [&](auto soc, auto ey, auto yn, auto yv, auto tn, auto tv, auto pr) {
-            fwd_block_risk(P, v, yo, k, ey, st[off[7]], yn, yv, st[off[10]], st[off[11]], pr, eout, check, r1, r2);
+            if (kDense && P->rdata)
+                fwd_block_risk_gen(P, v, yo, k, ey, st[off[7]], yn, yv, st[off[10]], st[off[11]], eout, check, r1,
+                                   r2);
+            else
+                fwd_block_risk(P, v, yo, k, ey, st[off[7]], yn, yv, st[off[10]], st[off[11]], pr, eout, check, r1,
+                               r2);
             wave_sync();
             for (int q = 0; q < k; ++q) {
                 fwd_block_soc<real, kDense>(P, fc + q, soc + q * (m + 2), tn[q], tv[q], eout, V, check, r1, r2);
@@ -1910,12 +2026,20 @@ __global__ __launch_bounds__(kHookWG) void k_apply_L(const ProbDev<real>* __rest
         const int k = P->n_ch[v], fc = P->first_child[v];
         const long long yo = P->y_off[v];
         const real* y = z + P->z_y + yo;
+        // b^T y with b = (p, 0, 1) for AV@R, else the node's own b
+        const real* bg = P->rdata ? risk_data(P, v, k).b : nullptr;
+        const int ny = bg ? P->rny[v] : 2 * k + 1;
         real b = 0;
-        for (int c = t; c < k; c += kHookWG) b += P->prob[fc + c] * y[c];
-        b = block_sum<kHookWG>(b, red) + y[2 * k];
+        if (bg) {
+            for (int c = t; c < ny; c += kHookWG) b += bg[c] * y[c];
+            b = block_sum<kHookWG>(b, red);
+        } else {
+            for (int c = t; c < k; c += kHookWG) b += P->prob[fc + c] * y[c];
+            b = block_sum<kHookWG>(b, red) + y[2 * k];
+        }
         const real s = (v == 0) ? z[0] : z[P->z_s + v - 1];
         if (t == 0) eta[P->e_s + v] = s - b;
-        for (int c = t; c < 2 * k + 1; c += kHookWG) eta[P->e_y + yo + c] = y[c];
+        for (int c = t; c < ny; c += kHookWG) eta[P->e_y + yo + c] = y[c];
         for (int q = 0; q < k; ++q) {
             const int j = fc + q;
             const real tau = z[P->z_tau + j - 1];
@@ -2015,8 +2139,10 @@ __global__ __launch_bounds__(kHookWG) void k_apply_Lt(const ProbDev<real>* __res
         }
         const long long yo = P->y_off[v];
         const real es = eta[P->e_s + v];
-        for (int c = t; c < 2 * k + 1; c += kHookWG) {
-            const real bc = c < k ? P->prob[fc + c] : (c == 2 * k ? real(1) : real(0));
+        const real* bg = P->rdata ? risk_data(P, v, k).b : nullptr;
+        const int ny = bg ? P->rny[v] : 2 * k + 1;
+        for (int c = t; c < ny; c += kHookWG) {
+            const real bc = bg ? bg[c] : c < k ? P->prob[fc + c] : (c == 2 * k ? real(1) : real(0));
             z[P->z_y + yo + c] = eta[P->e_y + yo + c] - bc * es;
         }
         if (t == 0) {
@@ -2093,9 +2219,13 @@ __global__ __launch_bounds__(kHookWG) void k_prox_gconj(const ProbDev<real>* __r
     if (v < P->n_nl) {
         const int k = P->n_ch[v], fc = P->first_child[v];
         const long long yo = P->y_off[v];
-        for (int c = t; c < 2 * k + 1; c += kHookWG) {
+        // rows where K is R_+ keep min(e, 0), rows where K is {0} (dual R) give 0
+        const real* cg = P->rdata ? risk_data(P, v, k).cone : nullptr;
+        const int ny = cg ? P->rny[v] : 2 * k + 1;
+        for (int c = t; c < ny; c += kHookWG) {
             const real e = w[P->e_y + yo + c];
-            eta[P->e_y + yo + c] = c < 2 * k ? (e < 0 ? e : real(0)) : real(0);
+            const bool pos = cg ? cg[c] == real(0) : c < 2 * k;
+            eta[P->e_y + yo + c] = pos ? (e < 0 ? e : real(0)) : real(0);
         }
         if (t == 0) {
             const real e = w[P->e_s + v];

@@ -34,6 +34,8 @@ struct SrvTree {
     int n = 0, nx = 0, nu = 0, n_nl = 0;
     std::vector<int32_t> parent;
     std::vector<double> prob, A, B, c, Q, R, QN, xlo, xhi, ulo, uhi, xNlo, xNhi, gamma, q, r, qN, Qe, Re, QNl, Qd, Rd, QNd, G, glo, ghi, GN, gNlo, gNhi;
+    std::vector<double> rE, rF, rb;  // general coherent risks (empty: AV@R)
+    std::vector<int32_t> rny, rnnu, rcone;
     double x_ball = 0, xN_ball = 0;
     size_t footprint = 0;
     spock_problem* p = nullptr;  // resident when non-null
@@ -76,7 +78,13 @@ struct SrvTree {
         d.xN_hi = xNhi.empty() ? nullptr : xNhi.data();
         d.x_ball = x_ball;
         d.xN_ball = xN_ball;
-        d.gamma = gamma.data();
+        d.gamma = gamma.empty() ? nullptr : gamma.data();
+        d.risk_ny = rny.empty() ? nullptr : rny.data();
+        d.risk_nnu = rnnu.empty() ? nullptr : rnnu.data();
+        d.risk_E = rE.empty() ? nullptr : rE.data();
+        d.risk_F = rF.empty() ? nullptr : rF.data();
+        d.risk_b = rb.empty() ? nullptr : rb.data();
+        d.risk_cone = rcone.empty() ? nullptr : rcone.data();
         d.q = q.empty() ? nullptr : q.data();
         d.r = r.empty() ? nullptr : r.data();
         d.qN = qN.empty() ? nullptr : qN.data();
@@ -540,7 +548,23 @@ int32_t spock_server_add_tree(spock_server* s, const spock_problem_desc* d, int6
     std::vector<char> nonleaf(n, 0);
     for (size_t j = 1; j < n; ++j) nonleaf[d->parent[j]] = 1;
     T.n_nl = (int)std::count(nonleaf.begin(), nonleaf.end(), 1);
-    T.gamma.assign(d->gamma, d->gamma + T.n_nl);
+    if (d->gamma) T.gamma.assign(d->gamma, d->gamma + T.n_nl);
+    if (d->risk_ny) {  // sizes from the validated layout: children per non-leaf node
+        std::vector<long long> kids(T.n_nl, 0);
+        for (size_t j = 1; j < n; ++j) kids[d->parent[j]]++;
+        long long tE = 0, tF = 0, tb = 0;
+        for (int i = 0; i < T.n_nl; ++i) {
+            tE += (long long)d->risk_ny[i] * kids[i];
+            tF += (long long)d->risk_ny[i] * d->risk_nnu[i];
+            tb += d->risk_ny[i];
+        }
+        T.rny.assign(d->risk_ny, d->risk_ny + T.n_nl);
+        T.rnnu.assign(d->risk_nnu, d->risk_nnu + T.n_nl);
+        T.rE.assign(d->risk_E, d->risk_E + tE);
+        if (tF > 0) T.rF.assign(d->risk_F, d->risk_F + tF);
+        T.rb.assign(d->risk_b, d->risk_b + tb);
+        T.rcone.assign(d->risk_cone, d->risk_cone + tb);
+    }
     std::lock_guard<std::mutex> g(s->mu);
     T.id = s->next_tree++;
     *tree_id = T.id;

@@ -36,7 +36,9 @@ class ProblemDesc(C.Structure):
                 ("gamma", _dp), ("q", _dp), ("r", _dp), ("qN", _dp), ("Q_edge", _dp), ("R_edge", _dp),
                 ("QN_leaf", _dp), ("Q_dense", _dp), ("R_dense", _dp), ("QN_dense", _dp),
                 ("n_con", C.c_int32), ("Gamma", _dp), ("con_lo", _dp), ("con_hi", _dp),
-                ("n_conN", C.c_int32), ("GammaN", _dp), ("conN_lo", _dp), ("conN_hi", _dp)]
+                ("n_conN", C.c_int32), ("GammaN", _dp), ("conN_lo", _dp), ("conN_hi", _dp),
+                ("risk_ny", _ip), ("risk_nnu", _ip), ("risk_E", _dp), ("risk_F", _dp), ("risk_b", _dp),
+                ("risk_cone", _ip)]
 
 
 class Settings(C.Structure):
@@ -237,6 +239,23 @@ class _Desc:
             self.desc.n_conN = k["GammaN"].shape[0]
             self.desc.GammaN = _ptr(k["GammaN"])
             self.desc.conN_lo, self.desc.conN_hi = _ptr(k["conN_lo"]), _ptr(k["conN_hi"])
+        # general coherent risks: per non-leaf node (E, F, b, cone codes),
+        # concatenated in node order
+        if prob.get("risk") is not None:
+            risk = prob["risk"]
+            cat = lambda parts, dt: np.ascontiguousarray(np.concatenate([np.ravel(a) for a in parts]) if parts
+                                                         else np.zeros(0), dtype=dt)
+            k["risk_ny"] = np.ascontiguousarray([len(r[2]) for r in risk], dtype=np.int32)
+            k["risk_nnu"] = np.ascontiguousarray([0 if r[1] is None else np.shape(r[1])[1] for r in risk],
+                                                 dtype=np.int32)
+            k["risk_E"] = cat([r[0] for r in risk], np.float64)
+            k["risk_F"] = cat([r[1] for r in risk if r[1] is not None], np.float64)
+            k["risk_b"] = cat([r[2] for r in risk], np.float64)
+            k["risk_cone"] = cat([r[3] for r in risk], np.int32)
+            self.desc.risk_ny, self.desc.risk_nnu = _ptr(k["risk_ny"], np.int32), _ptr(k["risk_nnu"], np.int32)
+            self.desc.risk_E, self.desc.risk_b = _ptr(k["risk_E"]), _ptr(k["risk_b"])
+            self.desc.risk_F = _ptr(k["risk_F"]) if k["risk_F"].size else None
+            self.desc.risk_cone = _ptr(k["risk_cone"], np.int32)
 
 
 def footprint(prob, settings=None):
@@ -339,7 +358,7 @@ class Problem:
         if tau.size != self.n - 1 or s.size != self.n - 1:
             raise ValueError("tau and s have one entry per node 1..n-1")
         if y.size != self.nz - 1 - self.n * self.nx - self.n_nl * self.nu - 2 * (self.n - 1):
-            raise ValueError("y must hold 2 n_ch(i) + 1 entries per non-leaf node i")
+            raise ValueError("y must hold one entry per row of every non-leaf node's risk (2 n_ch(i) + 1 for AV@R)")
         yo, to, so = np.zeros_like(y), np.zeros_like(tau), np.zeros_like(s)
         _check(load().spock_project_S2(self.h, _ptr(y), _ptr(tau), _ptr(s), _ptr(yo), _ptr(to), _ptr(so),
                                        precision))

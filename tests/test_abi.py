@@ -173,3 +173,38 @@ def test_general_constraints_are_validated(lib):
     big = dict(p, Gamma_x=np.zeros((513, 3)), Gamma_u=np.zeros((513, 2)), c_lo=-np.ones(513), c_hi=np.ones(513))
     assert "512" in _bad(big)
     assert nc == m + 1 and ncN == 3 + 1
+
+
+def test_general_risks_are_validated(lib):
+    """General coherent risks (conic data per non-leaf node): accepted for the
+    spectral risk, the footprint holds the data; rejected for a cone code
+    other than 0 and 1, a non-finite entry of E, F or b, more than 128 rows
+    of y or 64 rows of G, and a G without full row rank."""
+    base = W.random_ragged_problem(3, N=3, nx=3, nu=2)
+    p = W.spectral_risk(base)
+    assert S.footprint(p) > S.footprint(base)
+
+    def with_node0(**kw):
+        E, F, b, cone = p["risk"][0]
+        parts = dict(E=E, F=F, b=b, cone=cone)
+        parts.update(kw)
+        return dict(p, risk=[(parts["E"], parts["F"], parts["b"], parts["cone"])] + list(p["risk"][1:]))
+
+    E, F, b, cone = p["risk"][0]
+    c = cone.copy()
+    c[0] = 2
+    assert "cone" in _bad(with_node0(cone=c))
+    e = E.copy()
+    e[0, 0] = np.nan
+    assert "non-finite" in _bad(with_node0(E=e))
+    f = F.copy()
+    f[1, 1] = np.inf
+    _bad(with_node0(F=f))
+    k = E.shape[1]
+    assert "128" in _bad(with_node0(E=np.ones((129, k)), F=np.zeros((129, 0)), b=np.ones(129),
+                                    cone=np.zeros(129, int)))
+    assert "64" in _bad(with_node0(F=np.ones((E.shape[0], 64))))
+    # two equal columns of F: F^T y has a repeated row, G loses rank
+    f = F.copy()
+    f[:, 1] = f[:, 0]
+    assert "rank" in _bad(with_node0(F=f))

@@ -110,7 +110,36 @@ def _cases():
     par, _ = W.tree_from_branching([2, 2, 1])
     cases["general_big"] = W.make_problem(par, 70, 30, np.random.default_rng(23), prob_kind="dirichlet",
                                           general_con=True, name="general_big")
+    # general coherent risks (conic data E, F, b, K per node): the spectral
+    # risk w AV@R_g1 + (1 - w) AV@R_g2 (y of 5k + 2 rows, F of 2k columns); a
+    # root with 20 children (102 rows of y: two rows per lane, 60 rows of G);
+    # one with general constraint rows, dense costs and linear terms; and
+    # AV@R itself given as general data
+    cases["spectral"] = W.spectral_risk(W.random_ragged_problem(4, N=3, nx=3, nu=2), weight=0.4)
+    par, _ = W.tree_from_branching([20, 2, 1])
+    cases["spectral_wide"] = W.spectral_risk(W.make_problem(par, 8, 4, np.random.default_rng(24),
+                                                            prob_kind="dirichlet", name="spectral_wide"),
+                                             weight=0.7, gammas=(0.1, 0.6))
+    cases["spectral_mixed"] = W.spectral_risk(W.random_ragged_problem(11, N=3, nx=6, nu=3, max_children=3,
+                                                                      general_con=True, dense_costs=True,
+                                                                      linear=True))
+    cases["avar_general"] = _avar_as_general(W.random_ragged_problem(5, N=3, nx=3, nu=2))
     return cases
+
+
+def _avar_as_general(prob):
+    """AV@R_gamma at every node written out as general conic data (Sec. 3.3):
+    E = [gamma I; -I; 1^T], no F, b = (p, 0, 1), K = R_+^{2k} x {0}."""
+    parent = np.asarray(prob["parent"])
+    p = np.asarray(prob["prob"], float)
+    risk = []
+    for i in range(int(parent.max()) + 1):
+        kids = np.flatnonzero(parent == i)
+        k, g = kids.size, float(prob["gamma"][i])
+        E = np.vstack([g * np.eye(k), -np.eye(k), np.ones((1, k))])
+        risk.append((E, None, np.concatenate([p[kids], np.zeros(k), [1.0]]),
+                     np.concatenate([np.zeros(2 * k, int), [1]])))
+    return dict(prob, risk=risk)
 
 
 CASES = _cases()
@@ -245,7 +274,8 @@ def test_prox_f_parts(name):
 @pytest.mark.parametrize("name,steps", [("cfg0", 200), ("cfg1", 60), ("ragged_affine", 100), ("m150", 40),
                                         ("m200", 20), ("linear_big", 60), ("edge_costs_lin", 60),
                                         ("dense_lin", 60), ("bench1", 40), ("general", 100),
-                                        ("general_dense", 60), ("general_big", 30)])
+                                        ("general_dense", 60), ("general_big", 30), ("spectral", 100),
+                                        ("spectral_wide", 40), ("spectral_mixed", 60), ("avar_general", 60)])
 def test_trajectory_matches_oracle(name, steps):
     """K plain CP steps from zero: T is firmly nonexpansive, so differences
     cannot amplify along the trajectory."""
@@ -475,7 +505,7 @@ def test_run_to_run_bitwise_deterministic():
 
 
 @pytest.mark.parametrize("name", ["cfg0", "cfg1", "ragged_a", "ragged_affine", "wide", "very_wide", "big_nx",
-                                  "deep_branched", "m200"])
+                                  "deep_branched", "m200", "spectral", "spectral_wide", "avar_general"])
 def test_project_S1_S2_hooks_match_oracle(name):
     """spock_project_S1 (Alg. 2 through the sweep kernels) against the oracle's
     Alg. 2 with P, and spock_project_S2 against the oracle's dense
@@ -504,8 +534,9 @@ def test_project_S1_S2_hooks_match_oracle(name):
         for i in T.nonleaf:
             kids = T.ch[i]
             w = np.concatenate([y[Y.yoff[i]:Y.yoff[i + 1]], tau[np.asarray(kids) - 1], s[np.asarray(kids) - 1]])
-            pw = O.project_S2_block(w, D.gamma[i], len(kids))
-            m = 2 * len(kids) + 1
+            E, Fm = D.risk[i][0], D.risk[i][1]  # AV@R's E when the node has no general risk
+            pw = O.project_S2_block(w, D.gamma[i], len(kids), E, Fm)
+            m = Y.ylen[i]
             got = np.concatenate([yg[Y.yoff[i]:Y.yoff[i + 1]], tg[np.asarray(kids) - 1], sg[np.asarray(kids) - 1]])
             gotf = np.concatenate([yf[Y.yoff[i]:Y.yoff[i + 1]], tf[np.asarray(kids) - 1], sf[np.asarray(kids) - 1]])
             assert got.size == pw.size and m + 2 * len(kids) == pw.size
@@ -551,7 +582,7 @@ def test_setup_time_reported():
         assert 0 < r["t_setup_s"] < 60 and r["t_solve_s"] > 0
 
 
-@pytest.mark.parametrize("name", ["linear", "dense", "general"])
+@pytest.mark.parametrize("name", ["linear", "dense", "general", "spectral"])
 def test_linear_cost_solution_matches_oracle(name):
     """A ragged tree with linear stage and terminal cost terms (and ones with
     dense per-edge costs, and with general constraint rows) solved in float64
@@ -577,3 +608,21 @@ def test_linear_cost_solution_matches_oracle(name):
     # iterates at the oracle's stopping iteration do
     scale = max(1.0, np.abs(ref["z"]).max(), np.abs(ref["eta"]).max())
     assert _rel(zg, ref["z"], scale) <= K * 1e-12 and _rel(eg, ref["eta"], scale) <= K * 1e-12
+
+
+def test_avar_as_general_risk_matches_avar_path():
+    """AV@R given as general conic data runs the general-risk code (the node
+    kernels built with the general products, the S2 multiplier through
+    (G G^T)^-1 instead of the closed form): its iterates after 60 CP steps
+    equal those of the AV@R path to rounding, in float64 and float32."""
+    prob = CASES["avar_general"]
+    base = {k: v for k, v in prob.items() if k != "risk"}
+    for prec, tol in ((S.FP64, 1e-12), (S.FP32, 1e-5)):
+        out = []
+        for p in (base, prob):
+            with S.Problem(p) as P:
+                P.set_x0(p["x0"])
+                P.run_steps(60, prec)
+                out.append(P.get_iterate())
+        scale = max(1.0, np.abs(out[0][0]).max(), np.abs(out[0][1]).max())
+        assert _rel(out[1][0], out[0][0], scale) < tol and _rel(out[1][1], out[0][1], scale) < tol
