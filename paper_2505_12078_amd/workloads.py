@@ -277,6 +277,52 @@ def spectral_risk(prob, weight=0.5, gammas=(0.2, 0.9)):
     return dict(prob, risk=risk, name=prob.get("name", "custom") + "_spectral")
 
 
+def soft_state_bounds(prob, idx, x_max, weight=1.0):
+    """The problem with the hard upper bounds of the state components idx at
+    non-leaf nodes replaced by the quadratic penalty weight *
+    ||max(0, x_idx - x_max)||^2 in the stage cost (the soft constraints that
+    follow Prop. 2 of Sec. 4.2), written with the paper's relaxation: one slack
+    input theta per component (u' = (u, theta), no effect on the dynamics,
+    cost weight * theta^T theta on every edge) and the constraint rows
+    theta >= 0, x_idx - theta <= x_max, as general rows Gamma_x x + Gamma_u u'
+    in a box.  The box of x (other components, and the lower bounds of idx)
+    and of u stay as rows; leaves keep their hard bounds.  No ball on x."""
+    if float(prob.get("x_ball", 0.0)) > 0 or prob.get("Gamma_x") is not None:
+        raise ValueError("soft_state_bounds takes a problem with box constraints only")
+    idx = np.asarray(idx, dtype=int)
+    x_max = np.broadcast_to(np.asarray(x_max, float), idx.shape)
+    nx, nu, ns = int(prob["nx"]), int(prob["nu"]), idx.size
+    n = len(prob["parent"])
+    nu2 = nu + ns
+    B = np.concatenate([np.asarray(prob["B"], float), np.zeros((n, nx, ns))], axis=2)
+    R = np.asarray(prob["R"], float)
+    w = float(weight)
+    if R.ndim == 1:
+        R2 = np.concatenate([R, np.full(ns, w)])
+    elif R.ndim == 2:
+        R2 = np.concatenate([R, np.full((n, ns), w)], axis=1)
+    else:
+        R2 = np.zeros((n, nu2, nu2))
+        R2[:, :nu, :nu] = R
+        R2[:, nu:, nu:] = w * np.eye(ns)
+    hard_hi = np.asarray(prob["x_hi"], float).copy()
+    hard_hi[idx] = np.inf
+    Ex = np.zeros((ns, nx))
+    Ex[np.arange(ns), idx] = 1.0
+    Gx = np.vstack([np.eye(nx), np.zeros((nu, nx)), np.zeros((ns, nx)), Ex])
+    Gu = np.vstack([np.zeros((nx, nu2)), np.hstack([np.eye(nu), np.zeros((nu, ns))]),
+                    np.hstack([np.zeros((ns, nu)), np.eye(ns)]), np.hstack([np.zeros((ns, nu)), -np.eye(ns)])])
+    c_lo = np.concatenate([prob["x_lo"], prob["u_lo"], np.zeros(ns), np.full(ns, -np.inf)])
+    c_hi = np.concatenate([hard_hi, prob["u_hi"], np.full(ns, np.inf), x_max])
+    out = dict(prob, nu=nu2, B=B, R=R2, Gamma_x=Gx, Gamma_u=Gu, c_lo=c_lo, c_hi=c_hi,
+               Gamma_N=np.eye(nx), cN_lo=np.asarray(prob["xN_lo"], float), cN_hi=np.asarray(prob["xN_hi"], float),
+               u_lo=np.concatenate([prob["u_lo"], np.zeros(ns)]), u_hi=np.concatenate([prob["u_hi"], np.full(ns, np.inf)]),
+               name=prob.get("name", "custom") + "_soft")
+    if prob.get("r") is not None:
+        out["r"] = np.concatenate([np.asarray(prob["r"], float), np.zeros((n, ns))], axis=1)
+    return out
+
+
 def seeded_rng(config_id, instance_id=0):
     return np.random.default_rng(np.random.SeedSequence([int(config_id), int(instance_id)]))
 

@@ -642,3 +642,42 @@ def test_spectral_risk_solution_is_the_nested_objective():
     for g in (0.2, 0.9):
         rg = O.solve(dict(base, gamma=np.full_like(base["gamma"], g)), eps=1e-6, max_iters=60000)
         assert abs(rg["s0"] - r["s0"]) > 1e-3
+
+
+def test_soft_state_bounds_solution_is_the_penalised_objective():
+    """Soft state bounds by the relaxation after Prop. 2 (slack inputs theta,
+    rows theta >= 0 and x - theta <= x_max): the solve's s0 equals the nested
+    objective of the original problem with w ||max(0, x_S - x_max)||^2 added
+    to every stage cost (AV@R by its closed min form), the slacks equal
+    max(0, x_S - x_max), and the bound is violated where the hard bound would
+    have held it."""
+    base = W.random_ragged_problem(7, N=2, nx=3, nu=2, ball=False)
+    rb = O.solve(base, eps=1e-7, max_iters=60000)
+    T = O.Tree(base["parent"], base["prob"])
+    nl = T.n_nl
+    S_idx = np.array([0])
+    x_max = 0.5 * rb["x"][1:nl, 0].max()  # half the largest x_0 the hard problem reaches after the root
+    assert x_max > 0.1
+    w = 3.0
+    p = W.soft_state_bounds(base, S_idx, x_max, weight=w)
+    r = O.solve(p, eps=1e-7, max_iters=80000)
+    assert r["status"] == "converged"
+    x, u = r["x"], r["u"]
+    nu = base["nu"]
+    theta = u[:nl, nu:]
+    pen = np.maximum(0.0, x[:nl, S_idx] - x_max)
+    assert np.abs(theta - pen).max() <= 1e-3 * max(1.0, np.abs(x).max())
+    assert pen.max() > 1e-2  # the soft bound is active and violated
+    Q, R, QN = (O.cost_matrices(base, k, T.n) for k in ("Q", "R", "QN"))
+    val = np.zeros(T.n)
+    for j in T.leaves:
+        val[j] = x[j] @ QN[j] @ x[j]
+    for t in range(T.N - 1, -1, -1):
+        for i in T.nodes(t):
+            kids = T.ch[i]
+            ui = u[i, :nu]
+            extra = w * float(np.sum(np.maximum(0.0, x[i, S_idx] - x_max) ** 2))
+            Z = np.array([x[i] @ Q[j] @ x[i] + ui @ R[j] @ ui + extra + val[j] for j in kids])
+            val[i] = O.avar_min_form(Z, T.p[kids], float(base["gamma"][i]))
+    assert val[0] == pytest.approx(r["s0"], rel=1e-5)
+    assert abs(r["s0"] - rb["s0"]) > 1e-3 * abs(rb["s0"])
