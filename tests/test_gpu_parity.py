@@ -124,6 +124,9 @@ def _cases():
                                                                       general_con=True, dense_costs=True,
                                                                       linear=True))
     cases["avar_general"] = _avar_as_general(W.random_ragged_problem(5, N=3, nx=3, nu=2))
+    # soft upper bound on x_0 at non-leaf nodes (slack inputs and general rows)
+    cases["soft"] = W.soft_state_bounds(W.random_ragged_problem(7, N=2, nx=3, nu=2, ball=False), [0], 0.7,
+                                        weight=3.0)
     return cases
 
 
@@ -275,7 +278,8 @@ def test_prox_f_parts(name):
                                         ("m200", 20), ("linear_big", 60), ("edge_costs_lin", 60),
                                         ("dense_lin", 60), ("bench1", 40), ("general", 100),
                                         ("general_dense", 60), ("general_big", 30), ("spectral", 100),
-                                        ("spectral_wide", 40), ("spectral_mixed", 60), ("avar_general", 60)])
+                                        ("spectral_wide", 40), ("spectral_mixed", 60), ("avar_general", 60),
+                                        ("soft", 100)])
 def test_trajectory_matches_oracle(name, steps):
     """K plain CP steps from zero: T is firmly nonexpansive, so differences
     cannot amplify along the trajectory."""
@@ -582,7 +586,7 @@ def test_setup_time_reported():
         assert 0 < r["t_setup_s"] < 60 and r["t_solve_s"] > 0
 
 
-@pytest.mark.parametrize("name", ["linear", "dense", "general", "spectral"])
+@pytest.mark.parametrize("name", ["linear", "dense", "general", "spectral", "soft"])
 def test_linear_cost_solution_matches_oracle(name):
     """A ragged tree with linear stage and terminal cost terms (and ones with
     dense per-edge costs, and with general constraint rows) solved in float64
@@ -626,3 +630,19 @@ def test_avar_as_general_risk_matches_avar_path():
                 out.append(P.get_iterate())
         scale = max(1.0, np.abs(out[0][0]).max(), np.abs(out[0][1]).max())
         assert _rel(out[1][0], out[0][0], scale) < tol and _rel(out[1][1], out[0][1], scale) < tol
+
+
+def test_soft_state_bounds_slacks():
+    """Soft state bounds (slack inputs theta with rows theta >= 0 and
+    x_0 - theta <= 0.7): the float64 solve's slacks equal max(0, x_0 - 0.7)
+    at every non-leaf node, and the bound is exceeded somewhere."""
+    prob = CASES["soft"]
+    nu0 = prob["nu"] - 1
+    with S.Problem(prob, S.default_settings(eps=1e-7, max_iters=200000, check_every=2)) as P:
+        r = P.solve(prob["x0"])
+        x, u, s0 = P.solution()
+    assert r["code"] == S.SPOCK_OK
+    nl = u.shape[0]
+    pen = np.maximum(0.0, x[:nl, 0] - 0.7)
+    assert np.abs(u[:, nu0] - pen).max() <= 1e-3 * max(1.0, np.abs(x).max())
+    assert pen.max() > 1e-2
