@@ -305,6 +305,29 @@ class Data:
         self.r_lin = lin("r", nu) / Su[None, :]
         self.qN_lin = lin("qN", nx) / SxN[None, :]
         self.has_lin = any(prob.get(k) is not None for k in ("q", "r", "qN"))
+        # Prop. 1 with a singular cost matrix: the part of the linear term in
+        # ker Q (z' of the proposition) enters the two tau rows of the SOC
+        # block, (tau - q_ker^T z) / 2 each; the part in range Q makes the
+        # translation.  Per edge j on (x, u) of the parent, per leaf on x.
+        def split(F, q):
+            # range(F^T F) = range(F^T); q_range its orthogonal projection
+            U, sv, _ = np.linalg.svd(F.T)
+            r = int(np.sum(sv > 1e-12 * max(1.0, sv.max() if sv.size else 0.0)))
+            Ur = U[:, :r]
+            q_rng = Ur @ (Ur.T @ q)
+            return q_rng, q - q_rng
+        self.c_edge = np.zeros((n, nx + nu))
+        self.cN_leaf = np.zeros((n, nx))
+        self.q_rng = np.zeros((n, nx + nu))
+        self.qN_rng = np.zeros((n, nx))
+        if self.has_lin:
+            for j in range(1, n):
+                F = np.zeros((nx + nu, nx + nu))
+                F[:nx, :nx], F[nx:, nx:] = self.Qh_e[j], self.Rh_e[j]
+                self.q_rng[j], self.c_edge[j] = split(F, np.concatenate([self.q_lin[j], self.r_lin[j]]))
+            for j in T.leaves:
+                self.qN_rng[j], self.cN_leaf[j] = split(self.QNh_l[j], self.qN_lin[j])
+        self.coupled = bool(np.any(self.c_edge != 0) or np.any(self.cN_leaf != 0))
 
     def unscale(self, x, u):
         T = self.tree
@@ -394,11 +417,12 @@ def apply_L(D, z):
         Y.ec(eta, i)[:] = D.Gx @ Y.x(z, i) + D.Gu @ Y.u(z, i)
     for j in range(1, T.n):
         i = T.anc[j]
-        t = Y.tau(z, j)[0]
+        # tau rows (tau - q_ker^T (x, u)) / 2 (Prop. 1; q_ker = 0 unless Q is singular)
+        t = Y.tau(z, j)[0] - D.c_edge[j] @ np.concatenate([Y.x(z, i), Y.u(z, i)])
         Y.esoc(eta, j)[:] = np.concatenate([D.Qh_e[j] @ Y.x(z, i), D.Rh_e[j] @ Y.u(z, i), [0.5 * t, 0.5 * t]])
     for j in T.leaves:
         Y.ecN(eta, j)[:] = D.GN @ Y.x(z, j)
-        sj = Y.s(z, j)[0]
+        sj = Y.s(z, j)[0] - D.cN_leaf[j] @ Y.x(z, j)
         Y.esocN(eta, j)[:] = np.concatenate([D.QNh_l[j] @ Y.x(z, j), [0.5 * sj, 0.5 * sj]])
     return eta
 
@@ -419,14 +443,16 @@ def apply_Lt(D, eta):
     for j in range(1, T.n):
         i = T.anc[j]
         w = Y.esoc(eta, j)
-        Y.x(z, i)[:] += D.Qh_e[j].T @ w[:nx]
-        Y.u(z, i)[:] += D.Rh_e[j].T @ w[nx:nx + nu]
-        Y.tau(z, j)[:] += 0.5 * (w[nx + nu] + w[nx + nu + 1])
+        h = 0.5 * (w[nx + nu] + w[nx + nu + 1])
+        Y.x(z, i)[:] += D.Qh_e[j].T @ w[:nx] - h * D.c_edge[j][:nx]
+        Y.u(z, i)[:] += D.Rh_e[j].T @ w[nx:nx + nu] - h * D.c_edge[j][nx:]
+        Y.tau(z, j)[:] += h
     for j in T.leaves:
         Y.x(z, j)[:] += D.GN.T @ Y.ecN(eta, j)
         w = Y.esocN(eta, j)
-        Y.x(z, j)[:] += D.QNh_l[j].T @ w[:nx]
-        Y.s(z, j)[:] += 0.5 * (w[nx] + w[nx + 1])
+        h = 0.5 * (w[nx] + w[nx + 1])
+        Y.x(z, j)[:] += D.QNh_l[j].T @ w[:nx] - h * D.cN_leaf[j]
+        Y.s(z, j)[:] += h
     return z
 
 
@@ -442,7 +468,17 @@ def L_norm(D):
         for j in T.ch[i]:
             rows.append(np.hstack([D.Qh_e[j], np.zeros((D.nx, D.nu))]))
             rows.append(np.hstack([np.zeros((D.nu, D.nx)), D.Rh_e[j]]))
-        norms.append(np.linalg.norm(np.vstack(rows), 2))
+        if D.coupled:
+            # the tau rows couple (x^i, u^i) with every tau^j of the children:
+            # one block over (x^i, u^i, tau^ch(i))
+            k = len(T.ch[i])
+            blk = [np.hstack([r, np.zeros((r.shape[0], k))]) for r in rows]
+            for q, j in enumerate(T.ch[i]):
+                tr = np.concatenate([-0.5 * D.c_edge[j], 0.5 * np.eye(k)[q]])
+                blk += [tr[None, :], tr[None, :]]
+            norms.append(np.linalg.norm(np.vstack(blk), 2))
+        else:
+            norms.append(np.linalg.norm(np.vstack(rows), 2))
         b = b_vector(D, i)
         m = b.size
         blk = np.zeros((m + 1, m + 1))
@@ -451,7 +487,13 @@ def L_norm(D):
         blk[m, m] = 1.0
         norms.append(np.linalg.norm(blk, 2))
     for j in T.leaves:
-        norms.append(np.linalg.norm(np.vstack([D.GN, D.QNh_l[j]]), 2))
+        if D.coupled:  # (x^j, s^j) with the leaf's s rows (s - qN_ker^T x) / 2
+            tr = np.concatenate([-0.5 * D.cN_leaf[j], [0.5]])
+            blk = np.vstack([np.hstack([D.GN, np.zeros((D.GN.shape[0], 1))]),
+                             np.hstack([D.QNh_l[j], np.zeros((D.nx, 1))]), tr, tr])
+            norms.append(np.linalg.norm(blk, 2))
+        else:
+            norms.append(np.linalg.norm(np.vstack([D.GN, D.QNh_l[j]]), 2))
     norms.append(np.sqrt(0.5))  # tau^j and leaf s^j: (1/2, 1/2)
     return float(max(norms))
 
@@ -572,11 +614,14 @@ def soc_shift(m):
 
 
 def soc_shift_lin(Qh, q):
-    """Translation a of Prop. 1 (Sec. 4.2) with Q ≻ 0 (S = I, z' = 0):
+    """Translation a of Prop. 1 (Sec. 4.2):
     (-1/2 Q~^-1/2 q~, -1/8 |q~|^2_{Q~^-1} + 1/2, -1/8 |q~|^2_{Q~^-1} - 1/2),
     where Q~^1/2 is the factor Qh of the cost block of L (Qh^T Qh = Q~), so
-    Q~^-1/2 q~ = Qh^-T q~ and |q~|^2_{Q~^-1} = |Qh^-T q~|^2."""
-    w = np.linalg.solve(Qh.T, q)
+    Q~^-1/2 q~ = Qh^-T q~ and |q~|^2_{Q~^-1} = |Qh^-T q~|^2.  For a singular
+    Q~, q is its part in range Q~ (the rest enters L's tau rows) and Qh^-T
+    is the pseudo-inverse (Qh^T w = q has the solution of least norm, which
+    lies in range Qh)."""
+    w = np.linalg.lstsq(Qh.T, q, rcond=None)[0]
     c = -0.125 * float(w @ w)
     return np.concatenate([-0.5 * w, [c + 0.5, c - 0.5]])
 
@@ -590,14 +635,14 @@ def edge_shift(D, j):
     F = np.zeros((nx + nu, nx + nu))
     F[:nx, :nx] = D.Qh_e[j]
     F[nx:, nx:] = D.Rh_e[j]
-    return soc_shift_lin(F, np.concatenate([D.q_lin[j], D.r_lin[j]]))
+    return soc_shift_lin(F, D.q_rng[j])
 
 
 def leaf_shift(D, j):
     """a of the SOC block of leaf j (terminal cost Q_N, qN^j)."""
     if not D.has_lin:
         return soc_shift(D.nx + 2)
-    return soc_shift_lin(D.QNh_l[j], D.qN_lin[j])
+    return soc_shift_lin(D.QNh_l[j], D.qN_rng[j])
 
 
 def project_S3(D, eta):

@@ -323,6 +323,52 @@ def soft_state_bounds(prob, idx, x_max, weight=1.0):
     return out
 
 
+def l1_input_penalty(prob, lam0):
+    """The problem with lam0 * ||u||_1 added to every stage cost (Prop. 2 of
+    Sec. 4.2, on the inputs), written as the proposition does: slack inputs
+    lambda (one per input) and theta, u' = (u, lambda, theta), no effect on
+    the dynamics and no quadratic cost (R' = blkdiag(R, 0)), the linear cost
+    lam0 * theta on every edge, and the rows -lambda <= u <= lambda,
+    sum(lambda) <= theta as general rows next to the box rows of x and u.
+    Leaves keep their hard bounds.  No ball on x."""
+    if float(prob.get("x_ball", 0.0)) > 0 or prob.get("Gamma_x") is not None:
+        raise ValueError("l1_input_penalty takes a problem with box constraints only")
+    nx, nu = int(prob["nx"]), int(prob["nu"])
+    n = len(prob["parent"])
+    ns = nu + 1
+    nu2 = nu + ns
+    B = np.concatenate([np.asarray(prob["B"], float), np.zeros((n, nx, ns))], axis=2)
+    R = np.asarray(prob["R"], float)
+    if R.ndim == 1:
+        R2 = np.concatenate([R, np.zeros(ns)])
+    elif R.ndim == 2:
+        R2 = np.concatenate([R, np.zeros((n, ns))], axis=1)
+    else:
+        raise ValueError("l1_input_penalty takes diagonal input costs")
+    r = np.zeros((n, nu)) if prob.get("r") is None else np.asarray(prob["r"], float)
+    r2 = np.concatenate([r, np.zeros((n, nu)), np.full((n, 1), float(lam0))], axis=1)
+    r2[0] = 0.0  # node 0 owns no edge
+    I, Z = np.eye(nu), np.zeros((nu, nu))
+    Gx = np.vstack([np.eye(nx), np.zeros((nu, nx)), np.zeros((2 * nu + 1, nx))])
+    Gu = np.vstack([np.hstack([np.zeros((nx, nu)), np.zeros((nx, ns))]),
+                    np.hstack([I, Z, np.zeros((nu, 1))]),
+                    np.hstack([I, -I, np.zeros((nu, 1))]),      # u - lambda <= 0
+                    np.hstack([-I, -I, np.zeros((nu, 1))]),     # -u - lambda <= 0
+                    np.concatenate([np.zeros(nu), np.ones(nu), [-1.0]])[None, :]])  # sum lambda - theta <= 0
+    c_lo = np.concatenate([prob["x_lo"], prob["u_lo"], np.full(2 * nu + 1, -np.inf)])
+    c_hi = np.concatenate([prob["x_hi"], prob["u_hi"], np.zeros(2 * nu + 1)])
+    out = dict(prob, nu=nu2, B=B, R=R2, r=r2, Gamma_x=Gx, Gamma_u=Gu, c_lo=c_lo, c_hi=c_hi,
+               Gamma_N=np.eye(nx), cN_lo=np.asarray(prob["xN_lo"], float), cN_hi=np.asarray(prob["xN_hi"], float),
+               u_lo=np.concatenate([prob["u_lo"], np.full(ns, -np.inf)]),
+               u_hi=np.concatenate([prob["u_hi"], np.full(ns, np.inf)]),
+               name=prob.get("name", "custom") + "_l1")
+    if out.get("q") is None:
+        out["q"] = np.zeros((n, nx))
+    if out.get("qN") is None:
+        out["qN"] = np.zeros((n, nx))
+    return out
+
+
 def seeded_rng(config_id, instance_id=0):
     return np.random.default_rng(np.random.SeedSequence([int(config_id), int(instance_id)]))
 

@@ -681,3 +681,88 @@ def test_soft_state_bounds_solution_is_the_penalised_objective():
             val[i] = O.avar_min_form(Z, T.p[kids], float(base["gamma"][i]))
     assert val[0] == pytest.approx(r["s0"], rel=1e-5)
     assert abs(r["s0"] - rb["s0"]) > 1e-3 * abs(rb["s0"])
+
+
+def _l1_problem():
+    base = W.random_ragged_problem(7, N=2, nx=3, nu=2, ball=False)
+    return base, W.l1_input_penalty(base, 2.0)
+
+
+@pytest.mark.parametrize("precondition", [False, True])
+def test_prop1_singular_cost_in_L(precondition):
+    """Prop. 1 with a singular cost matrix (R with zero entries; the linear
+    term partly in ker R, which enters L's two tau rows as (tau - q_ker^T z)/2,
+    the rest in the translation a): for every edge, the stage cost
+    x^T Q x + u^T R u + q^T x + r^T u <= tau in the original variables exactly
+    when that edge's SOC block of L z minus a lies in the SOC; with the sign of
+    the coupling flipped the equivalence fails."""
+    p = W.random_ragged_problem(3, N=2, nx=2, nu=3, ball=False, linear=True)
+    p["R"] = np.array([0.7, 0.0, 0.0])
+    D = O.Data(p, precondition=precondition)
+    assert D.coupled and np.abs(D.c_edge[1:, :2]).max() == 0.0  # no coupling on x: Q > 0
+    T, Y = D.tree, D.layout
+    rng = np.random.default_rng(8)
+    Q, R = O.cost_matrices(p, "Q", T.n), O.cost_matrices(p, "R", T.n)
+    disagree = 0
+    for trial in range(300):
+        j = int(rng.integers(1, T.n))
+        i = T.anc[j]
+        z = rng.standard_normal(Y.nz)
+        x, u = Y.x(z, i) / D.Sx, Y.u(z, i) / D.Su
+        ell = float(x @ Q[j] @ x + u @ R[j] @ u + p["q"][j] @ x + p["r"][j] @ u)
+        Y.tau(z, j)[:] = ell + rng.choice([-1, 1]) * rng.uniform(1e-3, 2)
+        v = Y.esoc(O.apply_L(D, z), j) - O.edge_shift(D, j)
+        inside = np.linalg.norm(v[:-1]) <= v[-1]
+        assert inside == (ell <= Y.tau(z, j)[0]), trial
+        D.c_edge *= -1
+        w = Y.esoc(O.apply_L(D, z), j) - O.edge_shift(D, j)
+        D.c_edge *= -1
+        disagree += (np.linalg.norm(w[:-1]) <= w[-1]) != (ell <= Y.tau(z, j)[0])
+    assert disagree > 0
+
+
+@pytest.mark.parametrize("precondition", [False, True])
+def test_l1_penalty_L_adjoint_and_norm(precondition):
+    """With the tau rows coupled to the inputs (the l1 penalty's theta), L*
+    is the adjoint of L and ||L|| equals the largest singular value of L
+    built column by column."""
+    _, p = _l1_problem()
+    D = O.Data(p, precondition=precondition)
+    assert D.coupled
+    Y = D.layout
+    rng = np.random.default_rng(11)
+    z, e = rng.standard_normal(Y.nz), rng.standard_normal(Y.neta)
+    assert abs(O.apply_L(D, z) @ e - z @ O.apply_Lt(D, e)) < 1e-12 * max(1, abs(z @ O.apply_Lt(D, e)))
+    assert O.L_norm(D) == pytest.approx(np.linalg.norm(_dense_L(D), 2), rel=1e-10)
+
+
+def test_l1_penalty_solution_is_the_penalised_objective():
+    """Prop. 2 on the inputs: the solve's s0 equals the nested objective of
+    the original problem with 2 ||u||_1 added to every stage cost (AV@R by its
+    closed min form), theta >= ||u||_1 everywhere with equality at the root
+    (a node whose subtree the risks above it weigh with zero may keep slack),
+    and the penalty drives input components to zero that the unpenalised
+    solution uses."""
+    base, p = _l1_problem()
+    rb = O.solve(base, eps=1e-8, max_iters=80000)
+    r = O.solve(p, eps=1e-8, max_iters=200000)
+    assert r["status"] == "converged"
+    T = O.Tree(base["parent"], base["prob"])
+    nl, nu = T.n_nl, base["nu"]
+    x, u = r["x"], r["u"][:, :nu]
+    theta = r["u"][:, 2 * nu]
+    l1 = np.abs(u).sum(axis=1)
+    assert (theta - l1).min() > -1e-6 and abs(theta[0] - l1[0]) < 1e-5
+    assert (np.abs(u) < 1e-5).sum() > (np.abs(rb["u"]) < 1e-5).sum()
+    Q, R, QN = (O.cost_matrices(base, k, T.n) for k in ("Q", "R", "QN"))
+    val = np.zeros(T.n)
+    for j in T.leaves:
+        val[j] = x[j] @ QN[j] @ x[j]
+    for t in range(T.N - 1, -1, -1):
+        for i in T.nodes(t):
+            kids = T.ch[i]
+            Z = np.array([x[i] @ Q[j] @ x[i] + u[i] @ R[j] @ u[i] + 2.0 * np.abs(u[i]).sum() + val[j]
+                          for j in kids])
+            val[i] = O.avar_min_form(Z, T.p[kids], float(base["gamma"][i]))
+    assert val[0] == pytest.approx(r["s0"], rel=1e-5)
+    assert r["s0"] > rb["s0"] + 1e-3
