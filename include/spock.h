@@ -82,7 +82,7 @@ typedef struct spock_problem_desc {
     const double* B;          /* [n][nx][nu]; entry 0 ignored */
     const double* c;          /* [n][nx] or NULL (= 0) */
     const double* Q_diag;     /* [nx] > 0, shared by all edges (or see Q_edge) */
-    const double* R_diag;     /* [nu] > 0 (or see R_edge) */
+    const double* R_diag;     /* [nu] >= 0 (or see R_edge; zero entries: see r) */
     const double* QN_diag;    /* [nx] > 0, shared by all leaves (or see QN_leaf) */
     const double* x_lo;       /* [nx], non-leaf state box (may be +-inf) */
     const double* x_hi;
@@ -96,7 +96,11 @@ typedef struct spock_problem_desc {
     /* Optional linear cost terms (Prop. 1 with q != 0, Sec. 4.2), each NULL
      * for zero: the edge into node j adds q[j]^T x^i + r[j]^T u^i (i its
      * parent), leaf j adds qN[j]^T x^j.  Row-major [n][nx], [n][nu], [n][nx];
-     * row 0 (and qN's non-leaf rows) ignored. */
+     * row 0 (and qN's non-leaf rows) ignored.  Where a diagonal R has a zero
+     * entry (an input without quadratic cost, e.g. the slacks of Prop. 2's l1
+     * penalty), r's entry lies in ker R and enters the edge's two tau rows of
+     * L as -(r_k u_k) / 2 each (Prop. 1 with Q singular) instead of the
+     * translation. */
     const double* q;
     const double* r;
     const double* qN;
@@ -104,7 +108,8 @@ typedef struct spock_problem_desc {
      * Q^j, R^j of each event and Q_N^j of each scenario, Sec. 3.1): diagonals
      * [n][nx], [n][nu] (row j: the edge into node j; row 0 ignored) and
      * [n][nx] (leaf rows).  A non-NULL array replaces Q_diag, R_diag or
-     * QN_diag, which may then be NULL; every used entry must be > 0. */
+     * QN_diag, which may then be NULL; every used entry must be > 0 (R's:
+     * >= 0). */
     const double* Q_edge;
     const double* R_edge;
     const double* QN_leaf;

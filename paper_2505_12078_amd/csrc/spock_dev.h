@@ -77,6 +77,7 @@ struct ProbDev {
     // then a = (0, ..., 0, 1/2, -1/2)
     const real* sa;
     const real* saN;
+    const real* ck;  // tau-row coupling of the inputs per edge [n][nu] (null unless R is singular)
     // per-edge cost square roots (Q^j^1/2 S_x^-1 at j nx, R^j^1/2 S_u^-1 at
     // j nu, edge j = 1..n-1) and per-leaf terminal ones (at (j - n_nl) nx);
     // null when every edge shares qh, rh and every leaf qnh

@@ -231,6 +231,7 @@ static void carve_set(Arena& a, spock_problem* p, DevSet<real>& s) {
     h.gamma = a.take<real>(nl);
     h.sa = p->has_lin ? a.take<real>((long long)(n - 1) * (m + 2)) : nullptr;
     h.saN = p->has_lin ? a.take<real>((long long)p->n_leaf * (nx + 2)) : nullptr;
+    h.ck = p->coupled ? a.take<real>((long long)n * nu) : nullptr;
     h.qh_e = p->edge_cost ? a.take<real>((long long)n * nx) : nullptr;
     h.rh_e = p->edge_cost ? a.take<real>((long long)n * nu) : nullptr;
     h.qnh_l = p->leaf_cost ? a.take<real>((long long)p->n_leaf * nx) : nullptr;
@@ -396,8 +397,10 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
             }
         }
         for (int k = 0; k < nu; ++k) {
+            // diagonal R may have zero entries (inputs without quadratic cost)
             const double v = Rd(d, j, k);
-            if (!(v > 0) || !std::isfinite(v)) return fail(SPOCK_E_INVALID, "R must be finite and > 0");
+            if (!(d->R_dense ? v > 0 : v >= 0) || !std::isfinite(v))
+                return fail(SPOCK_E_INVALID, "R must be finite and > 0 (diagonal R: >= 0)");
         }
     }
     // linear cost terms: edge rows 1..n-1, leaf rows of qN
@@ -406,6 +409,12 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
         (d->qN && !finite_all(d->qN + (size_t)nl * nx, (long long)(n - nl) * nx)))
         return fail(SPOCK_E_INVALID, "non-finite linear cost terms");
     p->has_lin = (d->q || d->r || d->qN) ? 1 : 0;
+    // Prop. 1 with R singular: a linear term on an input without quadratic cost
+    p->coupled = 0;
+    if (d->r && !d->R_dense)
+        for (int j = 1; j < n && !p->coupled; ++j)
+            for (int k = 0; k < nu; ++k)
+                if (Rd(d, j, k) == 0.0 && d->r[(size_t)j * nu + k] != 0.0) p->coupled = 1;
     // dense costs: finite and symmetric (definiteness is checked with their
     // eigenvalues when the square roots are taken)
     auto dense_ok = [&](const double* M, int dim, int j0, int j1) {
@@ -880,6 +889,7 @@ static int32_t scale_data(const spock_problem_desc* d, int precondition, spock_p
     // unchanged (Q~^-1/2 q~ = Q^-1/2 q for diagonal Q and S)
     p->sa.clear();
     p->saN.clear();
+    p->ck.assign(p->coupled ? (size_t)p->n * nu : 0, 0.0);
     if (p->has_lin) {
         const int m = p->m;
         p->sa.assign((size_t)(p->n - 1) * (m + 2), 0.0);
@@ -892,7 +902,13 @@ static int32_t scale_data(const spock_problem_desc* d, int precondition, spock_p
                 for (int k = 0; k < nx; ++k) wq[k] = d->q[(size_t)j * nx + k] / std::sqrt(Qd(d, j, k));
             if (d->r && p->dense_edge) dr.inv_root_apply(j - 1, d->r + (size_t)j * nu, wr.data());
             else if (d->r)
-                for (int k = 0; k < nu; ++k) wr[k] = d->r[(size_t)j * nu + k] / std::sqrt(Rd(d, j, k));
+                for (int k = 0; k < nu; ++k) {
+                    // an input without quadratic cost: its linear term lies in
+                    // ker R and goes to the tau rows (Prop. 1's z'), not into a
+                    const double rk = d->r[(size_t)j * nu + k], Rk = Rd(d, j, k);
+                    if (Rk > 0) wr[k] = rk / std::sqrt(Rk);
+                    else if (p->coupled) p->ck[(size_t)j * nu + k] = rk / p->Su[k];
+                }
             for (int k = 0; k < nx; ++k) {
                 a[k] = -0.5 * wq[k];
                 c += wq[k] * wq[k];
@@ -1075,6 +1091,65 @@ static int32_t scale_data(const spock_problem_desc* d, int precondition, spock_p
             const double h = p->leaf_cost ? p->qnh_l[(size_t)l * nx + r] : p->qnh[r];
             L2 = std::max(L2, p->gxN[r] * p->gxN[r] + p->gbN[r] * p->gbN[r] + h * h);
         }
+    if (p->coupled) {
+        // Prop. 1 with R singular: each child edge's two tau rows carry
+        // (tau^j - c_j^T u^i) / 2, which couples (x^i, u^i) with the
+        // children's tau.  The block over (x^i, u^i, tau^ch(i)) is
+        // [[Gc + C + sum_j c_j c_j^T / 2, -c_j / 2], [-c_j^T / 2, I / 2]]:
+        // Gc the constraint rows' Gram matrix, C the cost rows' (dense Q or
+        // diagonal).  Once per distinct block.
+        const int m = p->m;
+        std::vector<double> base((size_t)m * m, 0.0);
+        if (p->gen) {
+            for (int r = 0; r < p->nbox; ++r)
+                for (int a2 = 0; a2 < m; ++a2) {
+                    const double ga = p->Gt[(size_t)r * m + a2];
+                    if (ga != 0.0)
+                        for (int b2 = 0; b2 < m; ++b2) base[(size_t)a2 * m + b2] += ga * p->Gt[(size_t)r * m + b2];
+                }
+        } else {
+            for (int k = 0; k < nx; ++k) base[(size_t)k * m + k] = p->gx[k] * p->gx[k] + p->gb[k] * p->gb[k];
+            for (int k = 0; k < nu; ++k) base[(size_t)(nx + k) * m + nx + k] = p->gu[k] * p->gu[k];
+        }
+        std::map<std::vector<double>, int> seen;
+        std::vector<std::pair<int, std::vector<double>>> blocks;
+        for (int i = 0; i < nl; ++i) {
+            const int k = p->n_ch[i], dim = m + k;
+            std::vector<double> M((size_t)dim * dim, 0.0);
+            for (int a2 = 0; a2 < m; ++a2)
+                for (int b2 = 0; b2 < m; ++b2) M[(size_t)a2 * dim + b2] = base[(size_t)a2 * m + b2];
+            for (int q = 0; q < k; ++q) {
+                const int j = p->first_child[i] + q;
+                if (d->Q_dense) {
+                    const std::vector<double> Qm = cost_mat(d->Q_dense, j, nx, Qd, d);
+                    for (int a2 = 0; a2 < nx; ++a2)
+                        for (int b2 = 0; b2 < nx; ++b2)
+                            M[(size_t)a2 * dim + b2] += Qm[(size_t)a2 * nx + b2] * p->qh[a2] * p->qh[b2];
+                } else {
+                    for (int a2 = 0; a2 < nx; ++a2) {
+                        const double h = p->edge_cost ? p->qh_e[(size_t)j * nx + a2] : p->qh[a2];
+                        M[(size_t)a2 * dim + a2] += h * h;
+                    }
+                }
+                const double* c = p->ck.data() + (size_t)j * nu;
+                for (int a2 = 0; a2 < nu; ++a2) {
+                    const double h = p->edge_cost ? p->rh_e[(size_t)j * nu + a2] : p->rh[a2];
+                    M[(size_t)(nx + a2) * dim + nx + a2] += h * h;
+                    for (int b2 = 0; b2 < nu; ++b2) M[(size_t)(nx + a2) * dim + nx + b2] += 0.5 * c[a2] * c[b2];
+                    M[(size_t)(nx + a2) * dim + m + q] = M[(size_t)(m + q) * dim + nx + a2] = -0.5 * c[a2];
+                }
+                M[(size_t)(m + q) * dim + m + q] = 0.5;
+            }
+            if (seen.emplace(M, (int)blocks.size()).second) blocks.emplace_back(dim, M);
+        }
+        std::vector<double> top(blocks.size(), 0.0);
+        parallel_for((int)blocks.size(), [&](int t) {
+            std::vector<double> w, V;
+            sym_eig(blocks[t].first, blocks[t].second.data(), w, V);
+            for (double x : w) top[t] = std::max(top[t], x);
+        });
+        for (double t : top) L2 = std::max(L2, t);
+    }
     p->Lnorm = std::sqrt(L2);
     return SPOCK_OK;
 }
@@ -1328,6 +1403,7 @@ static int32_t upload_set(spock_problem* p, DevSet<real>& s, const std::vector<d
     HIP_TRY(put<real>(h.gamma, p->gamma, st));
     if (p->has_lin) {
         HIP_TRY(put<real>(h.sa, p->sa, st));
+        if (p->coupled) HIP_TRY(put<real>(h.ck, p->ck, st));
         HIP_TRY(put<real>(h.saN, p->saN, st));
     }
     if (p->edge_cost) {
@@ -1525,7 +1601,7 @@ spk::LaunchCfg make_cfg(const spock_problem* p, int node_wg) {
     c.cls[1] = tile_class(spk::col_need(nx, m, V));
     c.cls[2] = tile_class(spk::col_need(m, nx, V));
     c.cls[3] = tile_class(spk::col_need(nx, nu, V));
-    c.dense = (p->dense_edge || p->dense_leaf || p->gen || p->genN || p->grisk) ? 1 : 0;
+    c.dense = (p->dense_edge || p->dense_leaf || p->gen || p->genN || p->grisk || p->coupled) ? 1 : 0;
     // float sweeps stage their tiles and vectors in LDS
     const int staged = sizeof(real) == 4 ? spk::stage_elems(nx, nu, V, c.cls[1], c.cls[2]) : 0;
     c.sweep_lds = spk::sweep_int_bytes(p->N) + (spk::sweep_elems(nx, nu) + staged) * (int)sizeof(real);

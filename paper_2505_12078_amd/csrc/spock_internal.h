@@ -108,6 +108,12 @@ struct spock_problem {
     // j = 1..n-1 (m + 2 each) and per leaf (nx + 2 each)
     int has_lin = 0;
     std::vector<double> sa, saN;
+    // Prop. 1 with a singular R (diagonal R with zero entries): the linear
+    // term r_k of an input without quadratic cost enters the edge's two tau
+    // rows of L as -(c^T u) / 2 each; ck [n][nu] by edge, in the scaled
+    // inputs (r_k / Su_k on those inputs, 0 elsewhere)
+    int coupled = 0;
+    std::vector<double> ck;
     // per-edge / per-leaf cost square roots in the scaled space (qh_e [n][nx],
     // rh_e [n][nu] by edge, qnh_l [n_leaf][nx] by leaf), used when the
     // description gives per-edge costs (edge_cost) or per-leaf ones (leaf_cost)

@@ -844,6 +844,17 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
                 [&](int c) { return V.C.rh[c] * V.uo[c]; }, V.blk[nx + r], V.dblk[nx + r]);
         wave_sync();
     }
+    // Prop. 1 with R singular: the tau rows are (tau - c_j^T u) / 2
+    real cun = 0, cuo = 0;
+    if (kDense && P->ck) {
+        const real* cj = P->ck + (long long)j * P->nu;
+        for (int r = lane; r < P->nu; r += 64) {
+            cun += gm(cj)[r] * V.un[r];
+            cuo += gm(cj)[r] * V.uo[r];
+        }
+        cun = wave_sum(cun);
+        cuo = wave_sum(cuo);
+    }
     real nw2 = 0;
     for (int r = lane; r < m + 2; r += 64) {
         real wn, wo;
@@ -857,8 +868,8 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
             wn = rh(r - nx) * V.un[r - nx];
             wo = rh(r - nx) * V.uo[r - nx];
         } else {
-            wn = real(0.5) * tn;
-            wo = real(0.5) * tv;
+            wn = real(0.5) * (tn - cun);
+            wo = real(0.5) * (tv - cuo);
         }
         real eb = es[r] + alpha * (real(2) * wn - wo);
         eb -= alpha * soc_shift_at(aj, r, m + 2);  // v = etabar - alpha a
@@ -887,6 +898,10 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
         } else {
             for (int r = lane; r < nx; r += 64) V.lxw[r] += qh(r) * V.dblk[r];
             for (int r = lane; r < P->nu; r += 64) V.luw[r] += rh(r) * V.dblk[nx + r];
+        }
+        if (kDense && P->ck) {
+            const real h = real(0.5) * (V.dblk[m] + V.dblk[m + 1]);
+            for (int r = lane; r < P->nu; r += 64) V.luw[r] -= gm(P->ck)[(long long)j * P->nu + r] * h;
         }
         if (lane == 0) r1 = nmax(r1, fabs((tv - tn) * ialpha - real(0.5) * (V.dblk[m] + V.dblk[m + 1])));
     }
@@ -1112,6 +1127,10 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
                 for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + nx + r];
                 s *= C.rh[r];
             }
+            if (kDense && P->ck)  // each child edge's tau rows: -(c_j^T u) / 2 twice
+                for (int q = 0; q < k; ++q)
+                    s -= real(0.5) * gm(P->ck)[(long long)(fc + q) * nu + r] *
+                         (soc[q * (m + 2) + m] + soc[q * (m + 2) + m + 1]);
             real lt;
             if (kDense && P->Gt) {
                 lt = s;
@@ -2042,7 +2061,12 @@ __global__ __launch_bounds__(kHookWG) void k_apply_L(const ProbDev<real>* __rest
         for (int c = t; c < ny; c += kHookWG) eta[P->e_y + yo + c] = y[c];
         for (int q = 0; q < k; ++q) {
             const int j = fc + q;
-            const real tau = z[P->z_tau + j - 1];
+            real tau = z[P->z_tau + j - 1];
+            if (P->ck) {  // tau rows (tau - c_j^T u) / 2 (Prop. 1 with R singular)
+                real cu = 0;
+                for (int c = t; c < nu; c += kHookWG) cu += P->ck[(long long)j * nu + c] * u[c];
+                tau -= block_sum<kHookWG>(cu, red);
+            }
             real* o = eta + P->e_soc + (long long)(j - 1) * (m + 2);
             for (int r = t; r < m + 2; r += kHookWG) {
                 if (P->Hq_e && r < m) {
@@ -2128,6 +2152,7 @@ __global__ __launch_bounds__(kHookWG) void k_apply_Lt(const ProbDev<real>* __res
                 } else {
                     s += (P->rh_e ? P->rh_e[(long long)(fc + q) * nu + r] : P->rh[r]) * o[r];
                 }
+                if (P->ck) s -= real(0.5) * P->ck[(long long)(fc + q) * nu + r] * (o[m - nx] + o[m - nx + 1]);
             }
             real w = s;
             if (P->Gt) {

@@ -208,3 +208,17 @@ def test_general_risks_are_validated(lib):
     f = F.copy()
     f[:, 1] = f[:, 0]
     assert "rank" in _bad(with_node0(F=f))
+
+
+def test_inputs_without_quadratic_cost_are_accepted(lib):
+    """Diagonal R may have zero entries (Prop. 1 with R singular): the l1
+    input penalty's slack inputs are accepted, and their linear term adds
+    the per-edge coupling rows to the footprint; a negative entry and a
+    zero eigenvalue of a dense R are still rejected."""
+    base = W.random_ragged_problem(7, N=2, nx=3, nu=2, ball=False)
+    p = W.l1_input_penalty(base, 2.0)
+    no_lin = dict(p, r=np.zeros_like(p["r"]))
+    assert S.footprint(p) > S.footprint(no_lin) > 0
+    R = p["R"].copy()
+    R[-1] = -1e-3
+    assert "R must" in _bad(p, R=R)

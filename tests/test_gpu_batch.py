@@ -170,14 +170,15 @@ def test_batched_workload_launch_equals_alone_and_oracle():
 
 
 def test_batch_with_dense_and_general_members():
-    """A batch that mixes plain members with one carrying dense costs and one
-    carrying general constraint rows runs the node kernels built with those
-    products for every member: after float64 and float32 steps each member's
-    iterate matches its own steps (the same operations in the same order; the
-    other kernel build may fuse differently, so to rounding), and the general
-    member matches the oracle."""
+    """A batch that mixes plain members with one carrying dense costs, one
+    carrying general constraint rows and one with an l1 input penalty runs
+    the node kernels built with those products for every member: after
+    float64 and float32 steps each member's iterate matches its own steps (the
+    same operations in the same order; the other kernel build may fuse
+    differently, so to rounding), and the general member matches the oracle."""
     probs = [W.config_problem(0), W.random_ragged_problem(5, N=3, nx=3, nu=2, dense_costs=True),
-             W.random_ragged_problem(7, N=3, nx=3, nu=2, general_con=True), W.batch_problem(1)]
+             W.random_ragged_problem(7, N=3, nx=3, nu=2, general_con=True), W.batch_problem(1),
+             W.l1_input_penalty(W.random_ragged_problem(7, N=2, nx=3, nu=2, ball=False), 2.0)]
     D = O.Data(probs[2])
     alpha = O.step_size(D)
 

@@ -125,6 +125,12 @@ def _cases():
                                                                       linear=True))
     cases["avar_general"] = _avar_as_general(W.random_ragged_problem(5, N=3, nx=3, nu=2))
     # soft upper bound on x_0 at non-leaf nodes (slack inputs and general rows)
+    # Prop. 2's l1 input penalty: slack inputs without quadratic cost whose
+    # linear term enters the tau rows of L (Prop. 1 with R singular); small,
+    # and with per-edge diagonal costs and linear terms on the original inputs
+    cases["l1"] = W.l1_input_penalty(W.random_ragged_problem(7, N=2, nx=3, nu=2, ball=False), 2.0)
+    cases["l1_edge"] = W.l1_input_penalty(W.random_ragged_problem(12, N=3, nx=4, nu=3, edge_costs=True, linear=True,
+                                                                  ball=False), 0.5)
     cases["soft"] = W.soft_state_bounds(W.random_ragged_problem(7, N=2, nx=3, nu=2, ball=False), [0], 0.7,
                                         weight=3.0)
     return cases
@@ -279,7 +285,7 @@ def test_prox_f_parts(name):
                                         ("dense_lin", 60), ("bench1", 40), ("general", 100),
                                         ("general_dense", 60), ("general_big", 30), ("spectral", 100),
                                         ("spectral_wide", 40), ("spectral_mixed", 60), ("avar_general", 60),
-                                        ("soft", 100)])
+                                        ("soft", 100), ("l1", 100), ("l1_edge", 60)])
 def test_trajectory_matches_oracle(name, steps):
     """K plain CP steps from zero: T is firmly nonexpansive, so differences
     cannot amplify along the trajectory."""
@@ -586,7 +592,7 @@ def test_setup_time_reported():
         assert 0 < r["t_setup_s"] < 60 and r["t_solve_s"] > 0
 
 
-@pytest.mark.parametrize("name", ["linear", "dense", "general", "spectral", "soft"])
+@pytest.mark.parametrize("name", ["linear", "dense", "general", "spectral", "soft", "l1"])
 def test_linear_cost_solution_matches_oracle(name):
     """A ragged tree with linear stage and terminal cost terms (and ones with
     dense per-edge costs, and with general constraint rows) solved in float64
