@@ -128,10 +128,45 @@ def avar_conic_data(p, gamma):
     return b, E
 
 
+def soc_blocks(cone):
+    """The second-order cone blocks of a cone given row by row: code 2 opens
+    a block {(t, w): ||w|| <= t} at its head row t, code 3 continues it with
+    the rows of w.  Returns (head, tail length) pairs."""
+    cone = np.asarray(cone)
+    out = []
+    r = 0
+    while r < cone.size:
+        if cone[r] == 2:
+            L = 0
+            while r + 1 + L < cone.size and cone[r + 1 + L] == 3:
+                L += 1
+            out.append((r, L))
+            r += 1 + L
+        else:
+            r += 1
+    return out
+
+
+def project_dual_cone(v, cone):
+    """Projection onto K* for K given row by row (Sec. 3.3): R_+ rows
+    (code 0) are self-dual, {0} rows (code 1) have dual R, and a second-order
+    cone block (codes 2, 3...) is self-dual."""
+    cone = np.asarray(cone)
+    out = np.where(cone == 0, np.maximum(v, 0.0), v)
+    for h, L in soc_blocks(cone):
+        blk = np.concatenate([v[h + 1:h + 1 + L], [v[h]]])  # (w, t): scalar last
+        pb = proj_soc(blk)
+        out[h] = pb[-1]
+        out[h + 1:h + 1 + L] = pb[:-1]
+    return out
+
+
 def conic_risk_value(Z, E, F, b, cone):
     """rho(Z) = max{mu^T Z : b - E mu - F nu in K} (Sec. 3.3) for a polyhedral
     K given entrywise (cone[r] = 0: R_+, 1: {0}), by an LP (scipy HiGHS)."""
     from scipy.optimize import linprog
+    if np.any(np.asarray(cone) >= 2):
+        raise NotImplementedError("conic_risk_value evaluates polyhedral cones only")
     E = np.asarray(E, float)
     ny, k = E.shape
     F = np.zeros((ny, 0)) if F is None else np.asarray(F, float)
@@ -652,8 +687,9 @@ def project_S3(D, eta):
     for i in T.nonleaf:
         k = len(T.ch[i])
         v = Y.ey(eta, i)
-        # (K^i)*: R_+ where K^i is R_+, R where K^i is {0} (AV@R: R^{2k}_+ x R)
-        Y.ey(out, i)[:] = np.where(D.risk[i][3] == 0, np.maximum(v, 0.0), v)
+        # (K^i)*: R_+ where K^i is R_+, R where K^i is {0} (AV@R: R^{2k}_+ x R),
+        # a second-order cone where K^i has one
+        Y.ey(out, i)[:] = project_dual_cone(v, D.risk[i][3])
         Y.es(out, i)[:] = np.maximum(Y.es(eta, i), 0.0)
         c = Y.ec(eta, i)
         pc = np.clip(c[:nb], D.box_lo, D.box_hi)

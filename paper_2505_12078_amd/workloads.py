@@ -277,6 +277,31 @@ def spectral_risk(prob, weight=0.5, gammas=(0.2, 0.9)):
     return dict(prob, risk=risk, name=prob.get("name", "custom") + "_spectral")
 
 
+def l2_ball_risk(prob, r_frac=0.5):
+    """The problem with every non-leaf node's risk replaced by the worst
+    expectation over the probability vectors within Euclidean distance
+    r = r_frac * min(p) of the node's conditional probabilities p, as
+    conic data with a second-order cone (Sec. 3.3): mu >= 0 (k rows, R_+),
+    1^T mu = 1 (one row, {0}) and (r, mu - p) in SOC_{k+1} (a head row,
+    code 2, and k tail rows, code 3); no nu.  With r <= min(p) the ball lies
+    in the simplex and the risk is p^T Z + r ||Z - mean(Z) 1||."""
+    parent = np.asarray(prob["parent"])
+    kids = children_lists(parent)
+    p_all = np.asarray(prob["prob"], float)
+    risk = []
+    for i in range(len(parent)):
+        k = len(kids[i])
+        if k == 0:
+            break
+        p = p_all[kids[i]]
+        r = float(r_frac) * float(p.min())
+        E = np.vstack([-np.eye(k), np.ones((1, k)), np.zeros((1, k)), -np.eye(k)])
+        b = np.concatenate([np.zeros(k), [1.0], [r], -p])
+        cone = np.concatenate([np.zeros(k, int), [1, 2], np.full(k, 3)])
+        risk.append((E, None, b, cone))
+    return dict(prob, risk=risk, name=prob.get("name", "custom") + "_l2ball")
+
+
 def soft_state_bounds(prob, idx, x_max, weight=1.0):
     """The problem with the hard upper bounds of the state components idx at
     non-leaf nodes replaced by the quadratic penalty weight *

@@ -766,3 +766,83 @@ def test_l1_penalty_solution_is_the_penalised_objective():
             val[i] = O.avar_min_form(Z, T.p[kids], float(base["gamma"][i]))
     assert val[0] == pytest.approx(r["s0"], rel=1e-5)
     assert r["s0"] > rb["s0"] + 1e-3
+
+
+def test_l2_ball_risk_data_certified():
+    """The l2-ball ambiguity risk as conic data with a second-order cone:
+    mu* = p + r d / ||d|| (d = Z - mean(Z) 1) is primal feasible (b - E mu*
+    in K), y* = (0, mean(Z), ||d||, -d) is dual feasible (E^T y* = Z, y* in
+    K*), and both reach p^T Z + r ||d||: by weak duality that is the risk."""
+    p0 = W.l2_ball_risk(W.random_ragged_problem(4, N=2, nx=2, nu=1), r_frac=0.6)
+    T = O.Tree(p0["parent"], p0["prob"])
+    rng = np.random.default_rng(12)
+    for i in T.nonleaf:
+        E, F, b, cone = p0["risk"][i]
+        p = T.p[T.ch[i]]
+        k = p.size
+        r = b[k + 1]
+        Z = rng.standard_normal(k) * 3
+        d = Z - Z.mean()
+        mu = p + r * d / np.linalg.norm(d)
+        w = b - E @ mu
+        assert np.all(w[:k] >= -1e-14) and abs(w[k]) < 1e-14
+        assert np.linalg.norm(w[k + 2:]) <= w[k + 1] + 1e-12
+        y = np.concatenate([np.zeros(k), [Z.mean()], [np.linalg.norm(d)], -d])
+        np.testing.assert_allclose(E.T @ y, Z, atol=1e-12)
+        assert np.linalg.norm(y[k + 2:]) <= y[k + 1] + 1e-12
+        val = p @ Z + r * np.linalg.norm(d)
+        assert mu @ Z == pytest.approx(val, rel=1e-12) and y @ b == pytest.approx(val, rel=1e-12)
+
+
+def test_dual_cone_projection_moreau():
+    """The S3 projection onto K* with R_+, {0} and second-order cone rows:
+    P(v) in K*, v - P(v) in the polar cone -K (R_+ rows: <= 0, {0}-rows'
+    dual R: 0, SOC: -SOC) and <P(v), v - P(v)> = 0, which characterises the
+    projection (Moreau); the three SOC cases (inside, inside the polar,
+    neither) all occur."""
+    cone = np.array([0, 0, 1, 2, 3, 3, 3, 0, 2, 3])
+    rng = np.random.default_rng(13)
+    seen = set()
+    for _ in range(300):
+        v = rng.standard_normal(cone.size) * 2
+        P = O.project_dual_cone(v, cone)
+        q = v - P
+        for h, L in O.soc_blocks(cone):
+            t, w = P[h], P[h + 1:h + 1 + L]
+            assert np.linalg.norm(w) <= t + 1e-12
+            assert np.linalg.norm(q[h + 1:h + 1 + L]) <= -q[h] + 1e-12
+            nw = np.linalg.norm(v[h + 1:h + 1 + L])
+            seen.add(0 if nw <= v[h] else 1 if nw <= -v[h] else 2)
+        assert np.all(P[cone == 0] >= 0) and np.all(q[cone == 0] <= 1e-15)
+        assert np.all(q[cone == 1] == 0)
+        assert abs(P @ q) < 1e-12 * max(1.0, np.abs(v).max() ** 2)
+    assert seen == {0, 1, 2}
+    assert O.soc_blocks(cone) == [(3, 3), (8, 1)]
+
+
+def test_l2_ball_risk_solution_is_the_nested_objective():
+    """A ragged tree with the l2-ball risk at every node: s0 equals the
+    nested objective with the risk in closed form p^T Z + r ||Z - mean(Z)||,
+    and lies above the risk-neutral value."""
+    base = W.random_ragged_problem(4, N=2, nx=3, nu=2, ball=False)
+    p = W.l2_ball_risk(base, r_frac=0.6)
+    r = O.solve(p, eps=1e-7, max_iters=60000)
+    assert r["status"] == "converged"
+    T = O.Tree(p["parent"], p["prob"])
+    x, u = r["x"], r["u"]
+    Q, R, QN = (O.cost_matrices(p, k, T.n) for k in ("Q", "R", "QN"))
+    val = np.zeros(T.n)
+    neutral = np.zeros(T.n)
+    for j in T.leaves:
+        val[j] = neutral[j] = x[j] @ QN[j] @ x[j]
+    for t in range(T.N - 1, -1, -1):
+        for i in T.nodes(t):
+            kids = T.ch[i]
+            pk = T.p[kids]
+            stage = np.array([x[i] @ Q[j] @ x[i] + u[i] @ R[j] @ u[i] for j in kids])
+            Z = stage + val[kids]
+            rad = 0.6 * pk.min()
+            val[i] = pk @ Z + rad * np.linalg.norm(Z - Z.mean())
+            neutral[i] = pk @ (stage + neutral[kids])
+    assert val[0] == pytest.approx(r["s0"], rel=1e-5)
+    assert r["s0"] > neutral[0] + 1e-6
