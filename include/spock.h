@@ -137,12 +137,15 @@ typedef struct spock_problem_desc {
     const double* GammaN;
     const double* conN_lo;
     const double* conN_hi;
-    /* Optional general coherent risks (Sec. 3.3, the cone K polyhedral): the
-     * risk at non-leaf node i (k_i children) is max{mu^T Z : b - E mu - F nu
-     * in K} over the children's costs Z, with y^i of risk_ny[i] entries (the
+    /* Optional general coherent risks (Sec. 3.3; K a product of R_+, {0}
+     * and second-order cones, given row by row): the risk at non-leaf node i
+     * (k_i children) is max{mu^T Z : b - E mu - F nu in K} over the
+     * children's costs Z, with y^i of risk_ny[i] entries (the
      * rows of E, F, b) and nu of risk_nnu[i] (the columns of F).  Concatenated
      * in node order: risk_E (ny x k_i, row-major), risk_F (ny x nnu), risk_b
-     * (ny), risk_cone (ny codes: 0 for R_+, 1 for {0}).  A non-NULL risk_ny
+     * (ny), risk_cone (ny codes: 0 for R_+, 1 for {0}, 2 for the head row t
+     * of a second-order cone block {(t, w): ||w|| <= t} and 3 for each of
+     * its rows of w, which follow the head).  A non-NULL risk_ny
      * replaces AV@R (gamma is then not read); 1 <= ny <= 128,
      * k_i + nnu <= 64, and [E^T -I -I; F^T 0 0] must have full row rank. */
     const int32_t* risk_ny;

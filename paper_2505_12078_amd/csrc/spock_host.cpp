@@ -492,10 +492,18 @@ static int32_t validate_and_layout(const spock_problem_desc* d, spock_problem* p
             std::copy(d->risk_E + ie, d->risk_E + ie + (long long)ny * k, E);
             if (nnu > 0) std::copy(d->risk_F + iF, d->risk_F + iF + (long long)ny * nnu, F);
             std::copy(d->risk_b + ib, d->risk_b + ib + ny, b);
+            // cone codes: 0 R_+, 1 {0}, 2 the head row t of a second-order cone
+            // block {(t, w): ||w|| <= t}, 3 its rows of w; stored for the
+            // kernels as 0, 1, 2 and, for a block's w rows, -1 - (head row)
+            int head = -1;
             for (int r = 0; r < ny; ++r) {
                 const int code = d->risk_cone[ib + r];
-                if (code != 0 && code != 1) return fail(SPOCK_E_INVALID, "general risks: cone codes are 0 or 1");
-                cone[r] = code;
+                if (code < 0 || code > 3) return fail(SPOCK_E_INVALID, "general risks: cone codes are 0, 1, 2 or 3");
+                if (code == 3 && head < 0)
+                    return fail(SPOCK_E_INVALID, "general risks: cone code 3 must follow a 2 or a 3");
+                if (code == 2) head = r;
+                else if (code != 3) head = -1;
+                cone[r] = code == 3 ? -1.0 - head : (double)code;
             }
             // G G^T = [E^T E + 2 I, E^T F; F^T E, F^T F]; invert through Cholesky
             std::vector<double> GG((size_t)g * g, 0.0);

@@ -795,12 +795,51 @@ SPK_DEV void fwd_block_risk_gen(const ProbDev<real>* __restrict__ P, int v, long
     const real eps_ = ebs < 0 ? ebs : real(0);
     const real des = es - eps_;
     if (lane == 0) gm(eout)[P->e_s + v] = eps_;
-    for (int c = lane; c < D.ny; c += 64) {
-        const real eb = ey[c] + alpha * (real(2) * yn[c] - yv[c]);
-        const real ep = gm(D.cone)[c] == real(0) ? (eb < 0 ? eb : real(0)) : real(0);
-        gm(eout)[P->e_y + yo + c] = ep;
+    // eta_y+ = ebar - P_{K*}(ebar) on the rows of y (lanes r and r + 64):
+    // R_+ rows min(ebar, 0), {0} rows 0, and each second-order cone block
+    // (head row code 2, its w rows coded -1 - head) ebar minus its projection
+    // onto the (self-dual) cone
+    real eb[2], cd[2], ep[2];
+    for (int h = 0; h < 2; ++h) {
+        const int c = lane + 64 * h;
+        eb[h] = c < D.ny ? ey[c] + alpha * (real(2) * yn[c] - yv[c]) : real(0);
+        cd[h] = c < D.ny ? gm(D.cone)[c] : real(1);
+        ep[h] = cd[h] == real(0) ? (eb[h] < 0 ? eb[h] : real(0)) : real(0);
+    }
+    for (int half = 0; half < 2; ++half) {
+        unsigned long long heads = __ballot(cd[half] == real(2));
+        while (heads) {
+            const int hr = 64 * half + __ffsll((long long)heads) - 1;
+            heads &= heads - 1;
+            const real tag = real(-1 - hr);
+            real w2 = 0;
+            for (int h = 0; h < 2; ++h)
+                if (cd[h] == tag) w2 += eb[h] * eb[h];
+            w2 = wave_sum(w2);
+            const real t = lane_value(half ? eb[1] : eb[0], hr & 63), nw = sqrt(w2);
+            real ct, cw;  // projection: head ct, w rows cw * w
+            if (nw <= t) {
+                ct = t;
+                cw = real(1);
+            } else if (nw <= -t) {
+                ct = real(0);
+                cw = real(0);
+            } else {
+                ct = real(0.5) * (t + nw);
+                cw = ct / nw;
+            }
+            for (int h = 0; h < 2; ++h) {
+                if (lane + 64 * h == hr) ep[h] = eb[h] - ct;
+                else if (cd[h] == tag) ep[h] = eb[h] - cw * eb[h];
+            }
+        }
+    }
+    for (int h = 0; h < 2; ++h) {
+        const int c = lane + 64 * h;
+        if (c >= D.ny) continue;
+        gm(eout)[P->e_y + yo + c] = ep[h];
         if (check) {
-            const real de = ey[c] - ep;
+            const real de = ey[c] - ep[h];
             const real dy = yv[c] - yn[c];
             r2 = nmax(r2, fabs(de * ialpha - dy));
             r1 = nmax(r1, fabs(dy * ialpha - (de - gm(D.b)[c] * des)));
@@ -2251,6 +2290,23 @@ __global__ __launch_bounds__(kHookWG) void k_prox_gconj(const ProbDev<real>* __r
             const real e = w[P->e_y + yo + c];
             const bool pos = cg ? cg[c] == real(0) : c < 2 * k;
             eta[P->e_y + yo + c] = pos ? (e < 0 ? e : real(0)) : real(0);
+        }
+        // second-order cone blocks of a general risk: e minus its projection
+        // onto the cone (head row code 2, its w rows coded -1 - head)
+        for (int hr = 0; cg && hr < ny; ++hr) {
+            if (cg[hr] != real(2)) continue;
+            const real tag = real(-1 - hr);
+            real w2 = 0;
+            for (int c = t; c < ny; c += kHookWG)
+                if (cg[c] == tag) w2 += w[P->e_y + yo + c] * w[P->e_y + yo + c];
+            const real nw = sqrt(block_sum<kHookWG>(w2, red)), th = w[P->e_y + yo + hr];
+            const real ct = nw <= th ? th : (nw <= -th ? real(0) : real(0.5) * (th + nw));
+            const real cw = nw <= th ? real(1) : (nw <= -th ? real(0) : ct / nw);
+            for (int c = t; c < ny; c += kHookWG) {
+                const real e = w[P->e_y + yo + c];
+                if (c == hr) eta[P->e_y + yo + c] = e - ct;
+                else if (cg[c] == tag) eta[P->e_y + yo + c] = e - cw * e;
+            }
         }
         if (t == 0) {
             const real e = w[P->e_s + v];

@@ -178,7 +178,7 @@ def test_general_constraints_are_validated(lib):
 def test_general_risks_are_validated(lib):
     """General coherent risks (conic data per non-leaf node): accepted for the
     spectral risk, the footprint holds the data; rejected for a cone code
-    other than 0 and 1, a non-finite entry of E, F or b, more than 128 rows
+    outside 0..3, a non-finite entry of E, F or b, more than 128 rows
     of y or 64 rows of G, and a G without full row rank."""
     base = W.random_ragged_problem(3, N=3, nx=3, nu=2)
     p = W.spectral_risk(base)
@@ -192,7 +192,7 @@ def test_general_risks_are_validated(lib):
 
     E, F, b, cone = p["risk"][0]
     c = cone.copy()
-    c[0] = 2
+    c[0] = 5
     assert "cone" in _bad(with_node0(cone=c))
     e = E.copy()
     e[0, 0] = np.nan
@@ -222,3 +222,17 @@ def test_inputs_without_quadratic_cost_are_accepted(lib):
     R = p["R"].copy()
     R[-1] = -1e-3
     assert "R must" in _bad(p, R=R)
+
+
+def test_second_order_cone_risk_codes_are_validated(lib):
+    """Cone code 3 (a row of a second-order cone block) must follow a 2 or a
+    3; codes outside 0..3 are rejected; the l2-ball risk is accepted."""
+    p = W.l2_ball_risk(W.random_ragged_problem(3, N=3, nx=3, nu=2))
+    assert S.footprint(p) > 0
+    E, F, b, cone = p["risk"][0]
+    c = cone.copy()
+    c[0] = 3  # a w row with no head before it
+    assert "follow" in _bad(p, risk=[(E, F, b, c)] + list(p["risk"][1:]))
+    c = cone.copy()
+    c[-1] = 4
+    assert "0, 1, 2 or 3" in _bad(p, risk=[(E, F, b, c)] + list(p["risk"][1:]))

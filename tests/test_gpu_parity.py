@@ -124,6 +124,13 @@ def _cases():
                                                                       general_con=True, dense_costs=True,
                                                                       linear=True))
     cases["avar_general"] = _avar_as_general(W.random_ragged_problem(5, N=3, nx=3, nu=2))
+    # the l2-ball ambiguity risk (a second-order cone block in K): small, and
+    # a root with 63 children whose cone block's head row sits on the second
+    # row of its lane (y of 128 rows)
+    cases["l2ball"] = W.l2_ball_risk(W.random_ragged_problem(4, N=3, nx=3, nu=2), r_frac=0.6)
+    par, _ = W.tree_from_branching([63, 1])
+    cases["l2ball_63"] = W.l2_ball_risk(W.make_problem(par, 4, 2, np.random.default_rng(25), prob_kind="dirichlet",
+                                                       name="l2ball_63"), r_frac=0.8)
     # soft upper bound on x_0 at non-leaf nodes (slack inputs and general rows)
     # Prop. 2's l1 input penalty: slack inputs without quadratic cost whose
     # linear term enters the tau rows of L (Prop. 1 with R singular); small,
@@ -285,7 +292,8 @@ def test_prox_f_parts(name):
                                         ("dense_lin", 60), ("bench1", 40), ("general", 100),
                                         ("general_dense", 60), ("general_big", 30), ("spectral", 100),
                                         ("spectral_wide", 40), ("spectral_mixed", 60), ("avar_general", 60),
-                                        ("soft", 100), ("l1", 100), ("l1_edge", 60)])
+                                        ("soft", 100), ("l1", 100), ("l1_edge", 60), ("l2ball", 100),
+                                        ("l2ball_63", 40)])
 def test_trajectory_matches_oracle(name, steps):
     """K plain CP steps from zero: T is firmly nonexpansive, so differences
     cannot amplify along the trajectory."""
@@ -515,7 +523,8 @@ def test_run_to_run_bitwise_deterministic():
 
 
 @pytest.mark.parametrize("name", ["cfg0", "cfg1", "ragged_a", "ragged_affine", "wide", "very_wide", "big_nx",
-                                  "deep_branched", "m200", "spectral", "spectral_wide", "avar_general"])
+                                  "deep_branched", "m200", "spectral", "spectral_wide", "avar_general", "l2ball",
+                                  "l2ball_63"])
 def test_project_S1_S2_hooks_match_oracle(name):
     """spock_project_S1 (Alg. 2 through the sweep kernels) against the oracle's
     Alg. 2 with P, and spock_project_S2 against the oracle's dense
@@ -652,3 +661,24 @@ def test_soft_state_bounds_slacks():
     pen = np.maximum(0.0, x[:nl, 0] - 0.7)
     assert np.abs(u[:, nu0] - pen).max() <= 1e-3 * max(1.0, np.abs(x).max())
     assert pen.max() > 1e-2
+
+
+def test_l2_ball_risk_solution_matches_oracle():
+    """The l2-ball risk (a second-order cone in K) solved in float64 to
+    rel_res 1e-6: the optimal value against the oracle's solve, and the
+    iterates at the oracle's stopping iteration against its trajectory."""
+    eps = 1e-6
+    prob = CASES["l2ball"]
+    ref = O.solve(prob, eps=eps, max_iters=60000)
+    with S.Problem(prob, S.default_settings(alpha=ref["alpha"], eps=eps, max_iters=200000, check_every=2)) as P:
+        r = P.solve(prob["x0"])
+        _, _, s0 = P.solution()
+        K = ref["iters"]
+        P.set_iterate(np.zeros(P.nz), np.zeros(P.neta))
+        P.run_steps(K)
+        zg, eg = P.get_iterate()
+    print("l2ball: GPU %d it s0 %.10g | oracle %d it s0 %.10g" % (r["iters"], s0, ref["iters"], ref["s0"]))
+    assert r["code"] == S.SPOCK_OK and ref["status"] == "converged"
+    assert abs(s0 - ref["s0"]) <= 10 * eps * max(1.0, abs(ref["s0"]))
+    scale = max(1.0, np.abs(ref["z"]).max(), np.abs(ref["eta"]).max())
+    assert _rel(zg, ref["z"], scale) <= K * 1e-12 and _rel(eg, ref["eta"], scale) <= K * 1e-12

@@ -138,3 +138,36 @@ def test_request_that_cannot_fit_evicts_nothing():
         r1 = P.solve(a["x0"] * 0.9, warm_start=True)
     assert first[0]["info"]["iters"] == r0["iters"] and first[0]["info"]["s0"] == r0["s0"]
     assert res[3]["info"]["iters"] == r1["iters"] and res[3]["info"]["s0"] == r1["s0"]
+
+
+def test_general_problems_served_equal_alone():
+    """Trees with the general parts of the formulation (a spectral risk given
+    as conic data, an l1 input penalty, dense costs, general constraint rows)
+    served together: every request converges and its optimal value equals
+    the same request sequence solved alone, at the tolerance of the solve."""
+    eps = 1e-4
+    trees = [W.spectral_risk(W.random_ragged_problem(4, N=3, nx=3, nu=2), weight=0.4),
+             W.l1_input_penalty(W.random_ragged_problem(7, N=2, nx=3, nu=2, ball=False), 2.0),
+             W.random_ragged_problem(5, N=3, nx=3, nu=2, dense_costs=True),
+             W.random_ragged_problem(7, N=3, nx=3, nu=2, general_con=True)]
+    settings = S.default_settings(eps=eps, max_iters=80000)
+    with S.Server(hbm_budget=8 << 30, settings=settings) as srv:
+        ids = [srv.add_tree(p) for p in trees]
+        req = 0
+        for i in range(2):
+            for tid, p in zip(ids, trees):
+                srv.submit(tid, _sequence(p, 2)[i], req)
+                req += 1
+        srv.wait_idle(600)
+        res = sorted(srv.poll(), key=lambda r: r["req_id"])
+    assert len(res) == 8 and all(r["status"] == S.SPOCK_OK for r in res)
+    for t, p in enumerate(trees):
+        mine = [r for r in res if r["tree_id"] == ids[t]]
+        with S.Problem(p, settings) as P:
+            for i, x0 in enumerate(_sequence(p, 2)):
+                a = P.solve(x0, warm_start=i > 0)
+                s_srv = mine[i]["info"]["s0"]
+                print("tree %d request %d: served s0 %.10g (%d it), alone %.10g (%d it)" % (
+                    t, i, s_srv, mine[i]["info"]["iters"], a["s0"], a["iters"]))
+                assert a["code"] == S.SPOCK_OK
+                assert abs(s_srv - a["s0"]) <= 10 * eps * max(1.0, abs(a["s0"]))
