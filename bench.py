@@ -293,6 +293,38 @@ def small_trees_bench(S, W):
     return out
 
 
+def generality_bench(S, W, prob, steps=200):
+    """The large tree with the general parts of the formulation in place of
+    AV@R and the box-and-ball constraints: a spectral risk and the l2-ball
+    ambiguity risk at every non-leaf node (conic data, Sec. 3.3), and the l1
+    input penalty of Prop. 2 (slack inputs and general rows; no ball).  Each
+    runs the node kernels built with the general products; per variant the
+    setup time and the float32 and float64 milliseconds per CP step."""
+    import torch
+    variants = {"avar": prob, "spectral": W.spectral_risk(prob, weight=0.5, gammas=(0.2, 0.95)),
+                "l2_ball": W.l2_ball_risk(prob, r_frac=0.5),
+                "l1_penalty": W.l1_input_penalty(dict(prob, x_ball=0.0, xN_ball=0.0), 0.1)}
+    out = {}
+    for name, p in variants.items():
+        t0 = time.perf_counter()
+        with S.Problem(p) as P:
+            setup = time.perf_counter() - t0
+            P.set_x0(p["x0"])
+            row = {"setup_s": round(setup, 3), "nu": P.nu,
+                   "y_entries": int(P.nz - 1 - P.n * P.nx - P.n_nl * P.nu - 2 * (P.n - 1)),
+                   "device_MB": round(P.sizes["device_bytes"] / 1e6, 1)}
+            for prec, key in ((S.FP32, "f32"), (S.FP64, "f64")):
+                P.run_steps(20, prec)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                P.run_steps(steps, prec, sync=False)
+                torch.cuda.synchronize()
+                row[key + "_ms_per_step"] = round((time.perf_counter() - t0) / steps * 1e3, 4)
+        out[name] = row
+        print("generality %s: %s" % (name, row), file=sys.stderr, flush=True)
+    return out
+
+
 def delay_bench(S, W, ns=(2, 4), steps=40):
     """The networked-control case study's parallelization question: CP step
     time of the delay tree's shapes (N = 48, n^2 equiprobable scenarios as
@@ -632,6 +664,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-small", action="store_true", help="skip the tiny and medium trees")
     ap.add_argument("--no-delay", action="store_true", help="skip the networked-control delay trees")
+    ap.add_argument("--no-general", action="store_true",
+                    help="skip the large tree with general risks and the l1 penalty")
     ap.add_argument("--case-study", type=int, default=6,
                     help="instances of the benchmark case study's random problems to solve (0: skip)")
     ap.add_argument("--case-study-only", action="store_true", help="run only the case-study leg (one JSON line)")
@@ -748,6 +782,7 @@ def main():
         print("time-to-tol supermann fp64: %s" % tol["supermann_fp64"], file=sys.stderr, flush=True)
 
     P.close()
+    general = None if args.no_general else generality_bench(S, W, prob)
     small = None if args.no_small else small_trees_bench(S, W)
     delay = None if args.no_delay else delay_bench(S, W)
     case_study = (case_study_bench(S, W, instances=args.case_study, eps=args.case_study_eps,
@@ -788,7 +823,7 @@ def main():
                    "f64 final check and refinement", "nodes": nodes, "nx": 50, "nu": 25,
                    "setup_s": round(t_setup, 3)},
         "fp64": {"iters_per_s": round(v64, 2), "ms_per_step": round(1000.0 / v64, 4)},
-        "kernels": kt, "roofline": roofline, "time_to_tol": tol, "small_trees": small, "delay_trees": delay,
+        "kernels": kt, "roofline": roofline, "time_to_tol": tol, "small_trees": small, "generality": general, "delay_trees": delay,
         "case_study": case_study,
         "batched": batched,
         "serve": serve,
