@@ -2351,6 +2351,32 @@ __global__ __launch_bounds__(256) void k_combo(double* out, VecCombo cb, long lo
     }
 }
 
+// The same for 16-byte aligned vectors and a fixed number of inputs (the
+// common one to three): two entries per lane and pass, every input's load
+// issued before the sums (in input order, as above); an odd last entry is
+// taken by the first lane.
+template <int NIN>
+__global__ __launch_bounds__(256) void k_combo2(double* out, VecCombo cb, long long n) {
+    const long long n2 = n >> 1;
+    for (long long k = blockIdx.x * 256LL + threadIdx.x; k < n2; k += (long long)gridDim.x * 256) {
+        double2 v[NIN];
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) v[i] = reinterpret_cast<const double2*>(cb.in[i])[k];
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+            sx += cb.c[i] * v[i].x;
+            sy += cb.c[i] * v[i].y;
+        }
+        reinterpret_cast<double2*>(out)[k] = make_double2(sx, sy);
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < NIN; ++i) s += cb.c[i] * cb.in[i][n - 1];
+        out[n - 1] = s;
+    }
+}
+
 // Block partial sums of every dot product of the set; each block strides
 // over the whole vector with a fixed assignment, so the result does not
 // depend on timing.  (One pass per product: a fused pass over all products
@@ -2363,6 +2389,36 @@ __global__ __launch_bounds__(256) void k_dots(DotSet ds, double* partial) {
         double s = 0.0;
         for (long long k = blockIdx.x * 256LL + threadIdx.x; k < ds.n[j]; k += (long long)gridDim.x * 256)
             s += a[k] * b[k];
+        s = block_sum<256>(s, red);
+        if (threadIdx.x == 0) partial[j * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// The same for 16-byte aligned vectors: two entries per lane and load, two
+// loads of each vector in flight, partial sums in a fixed assignment.
+__global__ __launch_bounds__(256) void k_dots2(DotSet ds, double* partial) {
+    __shared__ double red[4];
+    const long long st = (long long)gridDim.x * 256;
+    for (int j = 0; j < ds.count; ++j) {
+        const double2* a = reinterpret_cast<const double2*>(ds.a[j]);
+        const double2* b = reinterpret_cast<const double2*>(ds.b[j]);
+        const long long n2 = ds.n[j] >> 1;
+        double s0 = 0.0, s1 = 0.0;
+        long long k = blockIdx.x * 256LL + threadIdx.x;
+        for (; k + st < n2; k += 2 * st) {
+            const double2 x0 = a[k], y0 = b[k], x1 = a[k + st], y1 = b[k + st];
+            s0 += x0.x * y0.x;
+            s0 += x0.y * y0.y;
+            s1 += x1.x * y1.x;
+            s1 += x1.y * y1.y;
+        }
+        if (k < n2) {
+            const double2 x0 = a[k], y0 = b[k];
+            s0 += x0.x * y0.x;
+            s0 += x0.y * y0.y;
+        }
+        double s = s0 + s1;
+        if ((ds.n[j] & 1) && blockIdx.x == 0 && threadIdx.x == 0) s += ds.a[j][ds.n[j] - 1] * ds.b[j][ds.n[j] - 1];
         s = block_sum<256>(s, red);
         if (threadIdx.x == 0) partial[j * gridDim.x + blockIdx.x] = s;
     }
@@ -2486,16 +2542,29 @@ hipError_t launch_fill(T* dst, T val, long long n, hipStream_t st) {
 hipError_t launch_combo(double* out, const VecCombo& cb, long long n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (cb.n_in < 1 || cb.n_in > kMaxCombo) return hipErrorInvalidValue;
-    long long blocks = (n + 255) / 256;
+    bool aligned = (reinterpret_cast<uintptr_t>(out) & 15) == 0 && cb.n_in <= 3;
+    for (int i = 0; i < cb.n_in; ++i) aligned = aligned && (reinterpret_cast<uintptr_t>(cb.in[i]) & 15) == 0;
+    long long blocks = ((aligned ? (n + 1) / 2 : n) + 255) / 256;
     if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(k_combo, dim3((unsigned)blocks), dim3(256), 0, st, out, cb, n);
+    const dim3 g((unsigned)blocks), b(256);
+    if (!aligned) hipLaunchKernelGGL(k_combo, g, b, 0, st, out, cb, n);
+    else if (cb.n_in == 1) hipLaunchKernelGGL(k_combo2<1>, g, b, 0, st, out, cb, n);
+    else if (cb.n_in == 2) hipLaunchKernelGGL(k_combo2<2>, g, b, 0, st, out, cb, n);
+    else hipLaunchKernelGGL(k_combo2<3>, g, b, 0, st, out, cb, n);
     return hipGetLastError();
 }
 
 // out[j] = <a_j, b_j> for the set; partial holds kMaxDots * kDotBlocks doubles.
 hipError_t launch_dots(const DotSet& ds, double* partial, double* out, hipStream_t st) {
     if (ds.count < 1 || ds.count > kMaxDots) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_dots, dim3(kDotBlocks), dim3(256), 0, st, ds, partial);
+    bool aligned = true;
+    for (int j = 0; j < ds.count; ++j)
+        aligned = aligned && (reinterpret_cast<uintptr_t>(ds.a[j]) & 15) == 0 &&
+                  (reinterpret_cast<uintptr_t>(ds.b[j]) & 15) == 0;
+    if (aligned)
+        hipLaunchKernelGGL(k_dots2, dim3(kDotBlocks), dim3(256), 0, st, ds, partial);
+    else
+        hipLaunchKernelGGL(k_dots, dim3(kDotBlocks), dim3(256), 0, st, ds, partial);
     hipLaunchKernelGGL(k_dots_final, dim3(ds.count), dim3(64), 0, st, (const double*)partial, kDotBlocks, out);
     return hipGetLastError();
 }
