@@ -846,3 +846,29 @@ def test_l2_ball_risk_solution_is_the_nested_objective():
             neutral[i] = pk @ (stage + neutral[kids])
     assert val[0] == pytest.approx(r["s0"], rel=1e-5)
     assert r["s0"] > neutral[0] + 1e-6
+
+
+def test_prop1_singular_terminal_cost_in_L():
+    """Prop. 1 with a singular terminal cost (Q_N with a zero entry, qN partly
+    in its kernel; the oracle only): for every leaf, x^T Q_N x + qN^T x <= s
+    exactly when the leaf's SOC block of L z minus a lies in the SOC; the L
+    adjoint identity and ||L|| by dense SVD hold with the leaf coupling."""
+    p = W.random_ragged_problem(3, N=2, nx=3, nu=2, ball=False, linear=True)
+    p["QN"] = np.array([1.5, 0.0, 0.8])
+    for precondition in (False, True):
+        D = O.Data(p, precondition=precondition)
+        assert D.coupled and np.abs(D.cN_leaf[D.tree.leaves][:, [0, 2]]).max() == 0.0
+        T, Y = D.tree, D.layout
+        QN = O.cost_matrices(p, "QN", T.n)
+        rng = np.random.default_rng(9)
+        for _ in range(200):
+            j = int(rng.choice(T.leaves))
+            z = rng.standard_normal(Y.nz)
+            x = Y.x(z, j) / D.SxN
+            ell = float(x @ QN[j] @ x + p["qN"][j] @ x)
+            Y.s(z, j)[:] = ell + rng.choice([-1, 1]) * rng.uniform(1e-3, 2)
+            v = Y.esocN(O.apply_L(D, z), j) - O.leaf_shift(D, j)
+            assert (np.linalg.norm(v[:-1]) <= v[-1]) == (ell <= Y.s(z, j)[0])
+        z, e = rng.standard_normal(Y.nz), rng.standard_normal(Y.neta)
+        assert abs(O.apply_L(D, z) @ e - z @ O.apply_Lt(D, e)) < 1e-12 * max(1, abs(z @ O.apply_Lt(D, e)))
+        assert O.L_norm(D) == pytest.approx(np.linalg.norm(_dense_L(D), 2), rel=1e-10)
