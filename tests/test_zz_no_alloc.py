@@ -56,6 +56,14 @@ def test_noalloc_step_equals_apply_T_twice_second_smaller(precision):
     _compare(W.config_problem(0), 6, precision)   # 15 nodes, nx = 2, nu = 1
 
 
+@pytest.mark.parametrize("precision", [S.FP64, S.FP32])
+def test_noalloc_step_with_general_formulation(precision):
+    """The same with the node kernels built for the general formulation: a
+    spectral risk given as conic data, then an l1 input penalty (smaller)."""
+    _compare(W.spectral_risk(W.random_ragged_problem(4, N=3, nx=3, nu=2), weight=0.4), 7, precision)
+    _compare(W.l1_input_penalty(W.random_ragged_problem(7, N=2, nx=3, nu=2, ball=False), 2.0), 8, precision)
+
+
 def test_noalloc_rejects_aliasing_and_bad_precision():
     import torch
     prob = W.config_problem(0)
