@@ -583,7 +583,7 @@ def summarize_counters(fetch_dir, write_dir, trace_dir, profile_json, out_path=N
     import glob
     import re
 
-    pat = re.compile(r"k_(prep|bsweep|fsweep|dual)(?:_st)?<(float|double), (\d+)(?:, (?:true|false))?>")
+    pat = re.compile(r"k_(prep|bsweep|fsweep|dual)(?:_st)?<(float|double), (\d+)(?:, (?:true|false|[012]))?>")
 
     def rows(d, suffix):
         out = []

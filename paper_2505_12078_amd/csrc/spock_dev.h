@@ -196,7 +196,7 @@ struct LaunchCfg {
     int wave_elems;          // LDS elements of one node wavefront
     int sweep_lds;           // dynamic LDS bytes of a sweep wavefront
     int cls[4];              // register tile class of prep, bsweep, fsweep, dual
-    int dense;               // some problem has dense costs (node kernels built with their products)
+    int dense;               // node kernel build: 0 plain, 1 dense costs, 2 the general formulation (max over problems)
 };
 
 // Packed tiles of the column-lane products out[o] = sum_k A[k][o] v[k]

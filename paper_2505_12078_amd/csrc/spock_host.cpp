@@ -1609,7 +1609,10 @@ spk::LaunchCfg make_cfg(const spock_problem* p, int node_wg) {
     c.cls[1] = tile_class(spk::col_need(nx, m, V));
     c.cls[2] = tile_class(spk::col_need(m, nx, V));
     c.cls[3] = tile_class(spk::col_need(nx, nu, V));
-    c.dense = (p->dense_edge || p->dense_leaf || p->gen || p->genN || p->grisk || p->coupled) ? 1 : 0;
+    // node kernel build: 2 with the general formulation's products (general
+    // rows, general risks, tau-row coupling; dense costs included), 1 with the
+    // dense-cost products only, 0 with neither
+    c.dense = (p->gen || p->genN || p->grisk || p->coupled) ? 2 : (p->dense_edge || p->dense_leaf) ? 1 : 0;
     // float sweeps stage their tiles and vectors in LDS
     const int staged = sizeof(real) == 4 ? spk::stage_elems(nx, nu, V, c.cls[1], c.cls[2]) : 0;
     c.sweep_lds = spk::sweep_int_bytes(p->N) + (spk::sweep_elems(nx, nu) + staged) * (int)sizeof(real);

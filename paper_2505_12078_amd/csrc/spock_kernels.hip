@@ -656,14 +656,14 @@ SPK_DEV void fwd_block_gen(const real* Gt, const real* GtT, int nr, int nx, int 
 }
 
 // eta_c of non-leaf node v: C^i = box x ball (one wavefront).  ec: staged eta_c.
-template <typename real, bool kDense>
+template <typename real, int kMode>
 SPK_DEV void fwd_block_c(const ProbDev<real>* __restrict__ P, int v, const real* ec, real* __restrict__ eout,
                          const FwdNode<real>& V, int check, real& r2) {
     const int lane = threadIdx.x & 63;
     const int nx = P->nx, nbox = P->nbox, nc = P->nc;
     const real alpha = P->alpha, ialpha = real(1) / alpha;
     const long long off = P->e_c + (long long)v * nc;
-    if (kDense && P->Gt) {
+    if (kMode == 2 && P->Gt) {
         fwd_block_gen(P->Gt, P->GtT, nc, nx, P->m, P->lo, P->hi, off, ec, V.xn, V.xo, V.un, V.uo, alpha, V.dblk,
                       V.lxw, V.luw, eout, check, r2);
         return;
@@ -854,7 +854,7 @@ SPK_DEV void fwd_block_risk_gen(const ProbDev<real>* __restrict__ P, int v, long
 // SOC block of the edge into child j of non-leaf node v:
 // (Q^1/2 x^v, R^1/2 u^v, tau^j / 2, tau^j / 2) in SOC + a (one wavefront);
 // es: staged eta_soc of that edge, tn / tv: new / old tau^j.
-template <typename real, bool kDense, typename PT>
+template <typename real, int kMode, typename PT>
 SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, real tn, real tv,
                            real* __restrict__ eout, const FwdNode<real>& V, int check, real& r1, real& r2) {
     const int lane = threadIdx.x & 63;
@@ -869,8 +869,8 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
     auto rh = [&](int r) { return re ? gm(re)[r] : V.C.rh[r]; };
     // dense costs: the cost rows H (S^-1 x) of the new and old iterate, first
     // into blk / dblk
-    const real* Hq = kDense && P->Hq_e ? P->Hq_e + (long long)j * nx * nx : nullptr;
-    const real* Hr = kDense && P->Hr_e ? P->Hr_e + (long long)j * P->nu * P->nu : nullptr;
+    const real* Hq = kMode >= 1 && P->Hq_e ? P->Hq_e + (long long)j * nx * nx : nullptr;
+    const real* Hr = kMode >= 1 && P->Hr_e ? P->Hr_e + (long long)j * P->nu * P->nu : nullptr;
     if (Hq) {
         wave_sync();
         for (int r = lane; r < nx; r += 64)
@@ -885,7 +885,7 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
     }
     // Prop. 1 with R singular: the tau rows are (tau - c_j^T u) / 2
     real cun = 0, cuo = 0;
-    if (kDense && P->ck) {
+    if (kMode == 2 && P->ck) {
         const real* cj = P->ck + (long long)j * P->nu;
         for (int r = lane; r < P->nu; r += 64) {
             cun += gm(cj)[r] * V.un[r];
@@ -938,7 +938,7 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
             for (int r = lane; r < nx; r += 64) V.lxw[r] += qh(r) * V.dblk[r];
             for (int r = lane; r < P->nu; r += 64) V.luw[r] += rh(r) * V.dblk[nx + r];
         }
-        if (kDense && P->ck) {
+        if (kMode == 2 && P->ck) {
             const real h = real(0.5) * (V.dblk[m] + V.dblk[m + 1]);
             for (int r = lane; r < P->nu; r += 64) V.luw[r] -= gm(P->ck)[(long long)j * P->nu + r] * h;
         }
@@ -948,7 +948,7 @@ SPK_DEV void fwd_block_soc(const ProbDev<real>* __restrict__ P, int j, PT es, re
 
 // Leaf v: eta_cN (box x ball) for which = 0, eta_socN (Q_N^1/2 x, s/2, s/2) for
 // which = 1 (one wavefront each); ec / es: the staged blocks.
-template <typename real, bool kDense>
+template <typename real, int kMode>
 SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int which, const real* ec,
                             const real* es, real sn, real sv, real* __restrict__ eout, const FwdNode<real>& V,
                             int check, real& r1, real& r2) {
@@ -958,7 +958,7 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
     const long long lf = v - P->n_nl;
     if (which == 0) {
         const long long off = P->e_cN + lf * P->ncN;
-        if (kDense && P->GNt) {
+        if (kMode == 2 && P->GNt) {
             fwd_block_gen(P->GNt, P->GNtT, P->ncN, nx, nx, P->loN, P->hiN, off, ec, V.xn, V.xo, V.xn, V.xo,
                           alpha, V.dblk, V.lxw, V.lxw, eout, check, r2);
             return;
@@ -1006,7 +1006,7 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
         const real* aj = P->saN ? P->saN + lf * (nx + 2) : nullptr;
         const real* qe = P->qnh_l ? P->qnh_l + lf * nx : nullptr;
         auto qnh = [&](int r) { return qe ? gm(qe)[r] : V.C.qnh[r]; };
-        const real* Hq = kDense && P->HqN_l ? P->HqN_l + lf * nx * nx : nullptr;
+        const real* Hq = kMode >= 1 && P->HqN_l ? P->HqN_l + lf * nx * nx : nullptr;
         if (Hq) {
             for (int r = lane; r < nx; r += 64)
                 sym_col_dot2(
@@ -1060,7 +1060,7 @@ SPK_DEV void fwd_block_leaf(const ProbDev<real>* __restrict__ P, int v, int whic
 // One wavefront per node; the workgroup's wavefronts take consecutive entries
 // of the node task table, which never mixes problems inside one workgroup
 // (entries with node -1 pad a problem to a multiple of kMaxNodeWaves).
-template <typename real, int R, bool kDense>
+template <typename real, int R, int kMode>
 __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ probs,
                                               const int2* __restrict__ ntasks, const int4* __restrict__ ninfo,
                                               int wave_elems, int par, int check) {
@@ -1131,7 +1131,7 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         // of every child edge (Sec. 4.4)
         for (int r = lane; r < nx; r += 64) {
             real s = 0;
-            if (kDense && P->Hq_e) {  // dense: S^-1 sum over child edges of H^j eta^j
+            if (kMode >= 1 && P->Hq_e) {  // dense: S^-1 sum over child edges of H^j eta^j
                 for (int q = 0; q < k; ++q)
                     s += sym_col_dot(P->Hq_e + (long long)(fc + q) * nx * nx, nx, r,
                                      [&](int c) { return soc[q * (m + 2) + c]; });
@@ -1143,7 +1143,7 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
                 s *= C.qh[r];
             }
             real lt;
-            if (kDense && P->Gt) {  // general rows: (G^T eta_c) on x
+            if (kMode == 2 && P->Gt) {  // general rows: (G^T eta_c) on x
                 lt = s;
                 for (int q = 0; q < nc; ++q) lt += gm(P->Gt)[(long long)q * m + r] * ec[q];
             } else {
@@ -1154,7 +1154,7 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         }
         for (int r = lane; r < nu; r += 64) {
             real s = 0;
-            if (kDense && P->Hr_e) {
+            if (kMode >= 1 && P->Hr_e) {
                 for (int q = 0; q < k; ++q)
                     s += sym_col_dot(P->Hr_e + (long long)(fc + q) * nu * nu, nu, r,
                                      [&](int c) { return soc[q * (m + 2) + nx + c]; });
@@ -1166,12 +1166,12 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
                 for (int q = 0; q < k; ++q) s += soc[q * (m + 2) + nx + r];
                 s *= C.rh[r];
             }
-            if (kDense && P->ck)  // each child edge's tau rows: -(c_j^T u) / 2 twice
+            if (kMode == 2 && P->ck)  // each child edge's tau rows: -(c_j^T u) / 2 twice
                 for (int q = 0; q < k; ++q)
                     s -= real(0.5) * gm(P->ck)[(long long)(fc + q) * nu + r] *
                          (soc[q * (m + 2) + m] + soc[q * (m + 2) + m + 1]);
             real lt;
-            if (kDense && P->Gt) {
+            if (kMode == 2 && P->Gt) {
                 lt = s;
                 for (int q = 0; q < nc; ++q) lt += gm(P->Gt)[(long long)q * m + nx + r] * ec[q];
             } else {
@@ -1185,7 +1185,7 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         // w - G^T lambda = (y - E lambda_E - F lambda_F, tau + lambda_E, s + lambda_E).
         // Rows of y sit on lanes r and r + 64 (ny <= 128); every sum over rows
         // or multipliers runs in index order with the other side broadcast.
-        if (kDense && P->rdata) {
+        if (kMode == 2 && P->rdata) {
             const RiskData<real> D = risk_data(P, v, k);
             const int g = k + D.nnu;
             real ybh[2];
@@ -1301,11 +1301,11 @@ __global__ __launch_bounds__(512) void k_prep(const ProbDev<real>* __restrict__ 
         const real* ss = st + off[2];
         const real* spc = st + off[3];
         for (int r = lane; r < nx; r += 64) {
-            const real cost = kDense && P->HqN_l ? C.qnh[r] * sym_col_dot(P->HqN_l + lf * nx * nx, nx, r,
+            const real cost = kMode >= 1 && P->HqN_l ? C.qnh[r] * sym_col_dot(P->HqN_l + lf * nx * nx, nx, r,
                                                                  [&](int c) { return ss[c]; })
                                        : (P->qnh_l ? gm(P->qnh_l)[lf * nx + r] : C.qnh[r]) * ss[r];
             real lt;
-            if (kDense && P->GNt) {
+            if (kMode == 2 && P->GNt) {
                 lt = cost;
                 for (int q = 0; q < ncN; ++q) lt += gm(P->GNt)[(long long)q * nx + r] * sc[q];
             } else {
@@ -1912,7 +1912,7 @@ __global__ __launch_bounds__(64) void k_fsweep_st(const ProbDev<real>* __restric
 // dual: node-parallel forward half-step
 // ---------------------------------------------------------------------------
 
-template <typename real, int R, bool kDense>
+template <typename real, int R, int kMode>
 __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ probs,
                                               const int2* __restrict__ ntasks, const int4* __restrict__ ninfo,
                                               int wave_elems, int par, int check) {
@@ -1988,12 +1988,12 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
         }
         wave_sync();
         const FwdNode<real> V{C, xn, un, xo, uo, blk, dblk, lxw, luw};
-        fwd_block_c<real, kDense>(P, v, st + off[4], eout, V, check, r2);
+        fwd_block_c<real, kMode>(P, v, st + off[4], eout, V, check, r2);
         wave_sync();
         // per-child inputs: the staged copies, or for a wide node the arrays
         // themselves, each through a pointer of its own address space
         auto per_child = [&](auto soc, auto ey, auto yn, auto yv, auto tn, auto tv, auto pr) {
-            if (kDense && P->rdata)
+            if (kMode == 2 && P->rdata)
                 fwd_block_risk_gen(P, v, yo, k, ey, st[off[7]], yn, yv, st[off[10]], st[off[11]], eout, check, r1,
                                    r2);
             else
@@ -2001,7 +2001,7 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
                                r2);
             wave_sync();
             for (int q = 0; q < k; ++q) {
-                fwd_block_soc<real, kDense>(P, fc + q, soc + q * (m + 2), tn[q], tv[q], eout, V, check, r1, r2);
+                fwd_block_soc<real, kMode>(P, fc + q, soc + q * (m + 2), tn[q], tv[q], eout, V, check, r1, r2);
                 wave_sync();
             }
         };
@@ -2035,9 +2035,9 @@ __global__ __launch_bounds__(512) void k_dual(const ProbDev<real>* __restrict__ 
         const real* xn = st + off[0];
         const real* xo = st + off[1];
         const FwdNode<real> V{C, xn, un, xo, xo, blk, dblk, lxw, luw};
-        fwd_block_leaf<real, kDense>(P, v, 0, st + off[2], st + off[3], st[off[4]], st[off[5]], eout, V, check, r1, r2);
+        fwd_block_leaf<real, kMode>(P, v, 0, st + off[2], st + off[3], st[off[4]], st[off[5]], eout, V, check, r1, r2);
         wave_sync();
-        fwd_block_leaf<real, kDense>(P, v, 1, st + off[2], st + off[3], st[off[4]], st[off[5]], eout, V, check, r1, r2);
+        fwd_block_leaf<real, kMode>(P, v, 1, st + off[2], st + off[3], st[off[4]], st[off[5]], eout, V, check, r1, r2);
         wave_sync();
         if (check)
             for (int r = lane; r < nx; r += 64) r1 = nmax(r1, fabs((xo[r] - xn[r]) * ialpha - lxw[r]));
@@ -2443,11 +2443,14 @@ static hipError_t launch_phase_r(const ProbDev<real>* probs, const LaunchCfg& c,
     const int waves = c.node_wg / 64;
     switch (phase) {
         case 0:
-            if (c.dense)
-                hipLaunchKernelGGL((k_prep<real, R, true>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
+            if (c.dense == 2)
+                hipLaunchKernelGGL((k_prep<real, R, 2>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
+                                   c.node_lds, st, probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
+            else if (c.dense == 1)
+                hipLaunchKernelGGL((k_prep<real, R, 1>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
                                    c.node_lds, st, probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
             else
-                hipLaunchKernelGGL((k_prep<real, R, false>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
+                hipLaunchKernelGGL((k_prep<real, R, 0>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
                                    c.node_lds, st, probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
             break;
         case 1:
@@ -2467,11 +2470,14 @@ static hipError_t launch_phase_r(const ProbDev<real>* probs, const LaunchCfg& c,
                                    c.leaf_tasks, par);
             break;
         default:
-            if (c.dense)
-                hipLaunchKernelGGL((k_dual<real, R, true>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
+            if (c.dense == 2)
+                hipLaunchKernelGGL((k_dual<real, R, 2>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
+                                   c.node_lds, st, probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
+            else if (c.dense == 1)
+                hipLaunchKernelGGL((k_dual<real, R, 1>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
                                    c.node_lds, st, probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
             else
-                hipLaunchKernelGGL((k_dual<real, R, false>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
+                hipLaunchKernelGGL((k_dual<real, R, 0>), dim3(c.n_node_tasks / waves), dim3(c.node_wg),
                                    c.node_lds, st, probs, c.node_tasks, c.node_info, c.wave_elems, par, check);
             break;
     }
